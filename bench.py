@@ -1,0 +1,179 @@
+"""Benchmark: V-cycles/s, smoother HBM bandwidth and time to relative residual
+1e-10 for the Poisson-control KKT system at 2049^2 vertices (level 11) on one
+MI355X.
+
+One step = one complete solve from x = 0: right-hand side f = (M y_D; 0), then
+multigrid iterates until ||f - A x||_2 <= 1e-10 ||f||_2.  The printed JSON line
+carries the throughput, the roofline of the dominant kernel (the finest-level
+smoothing sweep, timed with HIP events on the launch stream) and the FP64 CPU
+oracle timed on a bounded sample on the host cores.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
+METRIC = "V-cycles/s and HBM GB/s at 2049^2 Poisson control; time to rel. residual 1e-10"
+
+
+def log(msg: str) -> None:
+    print(msg, file=sys.stderr, flush=True)
+
+
+def words_per_cycle(level: int, coarse: int, nu1: int, nu2: int, sweep_words: float = 8.0) -> float:
+    """Algorithmic words of one V-cycle: per level visit nu1+nu2 sweeps of
+    `sweep_words` per vertex, restriction (read r: 2 words, write f_c: 0.5),
+    prolongation + residual (read x_c 0.5, x 2, f 2; write x 2, r 2), plus the
+    finest-level residual at the start of the cycle (read f, x; write r)."""
+    total = 0.0
+    for l in range(coarse + 1, level + 1):
+        V = ((1 << l) + 1) ** 2
+        total += V * ((nu1 + nu2) * sweep_words + 2.5 + 8.5)
+    V = ((1 << level) + 1) ** 2
+    total += 6 * V
+    return total
+
+
+def cpu_baseline(level: int, alpha: float, seed: int, smoother: str, cycles: int):
+    import numpy as np
+
+    import oracle
+    import workloads
+
+    h = oracle.Hierarchy(level, alpha, coarse=1)
+    f = h.rhs(workloads.desired_state(level, seed))
+    x = np.zeros(h.ndof())
+    t0 = time.perf_counter()
+    for _ in range(cycles):
+        h.cycle(f, x, smoother=smoother, order="col7")
+    dt = time.perf_counter() - t0
+    return {"value": cycles / dt, "unit": "V-cycles/s", "cores": 1, "kind": "oracle",
+            "sample": f"{cycles} V(2,2) {smoother.upper()} cycles (7-colour order) of the 2049^2 workload, "
+                      f"alpha={alpha:g}, from x=0, setup excluded; single-threaded FP64 C"}
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--level", type=int, default=11)
+    ap.add_argument("--alpha", type=float, default=1e-4)
+    ap.add_argument("--smoother", default="lsgs")
+    ap.add_argument("--precision", default="fp64")
+    ap.add_argument("--tol", type=float, default=1e-10)
+    ap.add_argument("--seed", type=int, default=2)
+    ap.add_argument("--cpu-cycles", type=int, default=2)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--variants", action="store_true", help="also time the other smoother/precision/alpha variants")
+    args = ap.parse_args()
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py: this solver runs on one GPU; --gpus must be 1 (multi-GPU sharding is design only)",
+              file=sys.stderr)
+        return 2
+
+    import numpy as np
+    import torch
+
+    import paper_1502_03917_amd as mg
+    import workloads
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+    yd = torch.from_numpy(workloads.desired_state(args.level, args.seed)).cuda()
+
+    def run(smoother, precision, alpha, steps, warmup, timing=False):
+        s = mg.Solver(args.level, alpha, smoother=smoother, precision=precision)
+        inner = s.opts().inner_cycles
+        x = torch.zeros(s.vec_len(), dtype=torch.float64, device="cuda")
+        for _ in range(warmup):
+            x.zero_()
+            f = s.rhs(yd)
+            s.solve(f, x, tol=args.tol)
+        torch.cuda.synchronize()
+        if timing:
+            s.timing_enable(True)
+        cycles = 0
+        rel = None
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            x.zero_()
+            f = s.rhs(yd)
+            _, it, rel, st = s.solve(f, x, tol=args.tol)
+            cycles += it * (inner if precision == "fp32_ir" else 1)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        out = {"cycles_per_solve": cycles / steps, "ms_per_solve": 1e3 * dt / steps, "relres": rel,
+               "vcycles_per_s": cycles / dt}
+        if timing:
+            ms, n = s.timing_read()
+            s.timing_enable(False)
+            out["sweep_ms"] = ms / max(n, 1)
+            out["sweeps_timed"] = n
+        s.close()
+        return out
+
+    log(f"bench: level {args.level}, alpha {args.alpha:g}, {args.smoother}/{args.precision}, "
+        f"{args.warmup} warmup + {args.steps} timed solves to {args.tol:g}")
+    main_run = run(args.smoother, args.precision, args.alpha, args.steps, args.warmup, timing=True)
+    V = ((1 << args.level) + 1) ** 2
+    wbytes = 4 if args.precision == "fp32_ir" else 8
+    sweep_bytes = 8 * V * wbytes  # read and write x and r, both fields
+    achieved = sweep_bytes / (main_run["sweep_ms"] * 1e-3) / 1e9
+    cyc_bytes = words_per_cycle(args.level, 1, 2, 2) * wbytes
+    if args.precision == "fp32_ir":
+        cyc_bytes += V * 2 * (8 + 8 + 8 + 4 + 8)  # FP64 residual (f, x -> r), scaled cast, FP64 update
+    result = {
+        "metric": METRIC,
+        "value": main_run["vcycles_per_s"],
+        "unit": "V-cycles/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": main_run["ms_per_solve"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if args.precision == "fp64" else "f32+f64",
+        "data": "synthetic",
+        "config": {"workload": f"Poisson control KKT, {(1 << args.level) + 1}^2 vertices, alpha={args.alpha:g}, "
+                               f"y_D = 8 seeded sine modes (seed {args.seed}), x0 = 0, tol {args.tol:g}",
+                   "level": args.level, "unknowns": 2 * V, "smoother": args.smoother, "cycle": "V(2,2)",
+                   "precision": args.precision, "coarse_level": 1},
+        "time_to_tol_ms": main_run["ms_per_solve"],
+        "cycles_per_solve": main_run["cycles_per_solve"],
+        "final_relres": main_run["relres"],
+        "unknown_updates_per_s": main_run["vcycles_per_s"] * sum(4 * 2 * ((1 << l) + 1) ** 2 for l in range(2, args.level + 1)),
+        "cycle_algorithmic_GBps": main_run["vcycles_per_s"] * cyc_bytes / 1e9,
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": "finest-level smoothing sweep", "sweep_ms": main_run["sweep_ms"],
+                     "algorithmic_bytes_per_sweep": sweep_bytes},
+    }
+    if args.variants:
+        var = {}
+        for sm in ("ne", "lsgs"):
+            for pr in ("fp64", "fp32_ir"):
+                for al in (1e-8, 1e-4, 1.0):
+                    key = f"{sm}/{pr}/alpha={al:g}"
+                    log(f"bench: variant {key}")
+                    var[key] = run(sm, pr, al, 2, 1)
+        result["variants"] = var
+    if not args.no_cpu_baseline:
+        log(f"bench: CPU oracle baseline ({args.cpu_cycles} cycles)")
+        result["cpu_baseline"] = cpu_baseline(args.level, args.alpha, args.seed, args.smoother, args.cpu_cycles)
+    print(json.dumps(result), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -1,0 +1,159 @@
+/*
+ * mgkkt.h -- C ABI of the MI355X (gfx950) all-at-once multigrid solver for the
+ * discretised Poisson-control KKT system of Takacs, "Efficient smoothers for
+ * all-at-once multigrid methods for Poisson and Stokes control problems"
+ * (arXiv 1502.03917), section 1 eq. mp2:
+ *
+ *      [ M_k          K_k     ] [ y_k      ]   [ M_k y_D ]
+ *      [ K_k   -alpha^-1 M_k  ] [ lambda_k ] = [    0    ]
+ *
+ * on the unit square, P1 (Courant) elements on the uniform mesh with n = 2^k
+ * cells per side, every square split along its (i,j)-(i+1,j+1) diagonal,
+ * K_k = stiffness matrix of -Laplace(y) + y with natural boundary conditions.
+ *
+ * Conventions shared by every entry point:
+ *  - Vectors are contiguous FP64 arrays in DEVICE memory of the context's GPU.
+ *    A level-l vector has 2 (2^l+1)^2 entries, field-major [ y | lambda ];
+ *    vertex (i,j) (x = i h, y = j h) has index j (2^l+1) + i within a field.
+ *  - Caller-owned buffers are never freed, retained or resized by the library.
+ *    The context owns its level workspace (allocated in mg_setup).
+ *  - `stream` is a hipStream_t (NULL = default stream).  Work is enqueued in
+ *    stream order; only mg_solve and the norm outputs synchronise the stream.
+ *  - One context must not be used from two host threads or two streams at the
+ *    same time; distinct contexts are independent.
+ *  - Every entry point returns an mg_status (0 = success).  Argument checks run
+ *    before any HIP call, so invalid arguments never touch the GPU.
+ *    No exception crosses the ABI and the library never aborts.
+ */
+#ifndef MGKKT_H
+#define MGKKT_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct mg_ctx mg_ctx;
+
+/* problems: section 1, Poisson control (eq. mp2) and Stokes control (eq. mp3) */
+enum mg_problem { MG_POISSON = 0, MG_STOKES = 1 };
+
+/* smoothers of section 2:
+ *  MG_NE    normal-equation smoother x += tau L^-1 A^T L^-1 (f - A x) (Alg. 1)
+ *  MG_LSGS  least-squares Gauss-Seidel x += trig(N)^-1 A^T L^-1 (f - A x),
+ *           N = A^T L^-1 A (Alg. 2), unknowns visited in 7 colours
+ *           c(i,j) = (i + 2 j) mod 7; a vertex's y and lambda are updated
+ *           together from one residual snapshot (their N entry is zero)
+ *  MG_SLSGS symmetric LSGS: one LSGS sweep, then one in reversed order (eq. mcNhat)
+ *  MG_CGS   collective point Gauss-Seidel: 2x2 solve per vertex, 7 colours */
+enum mg_smoother { MG_NE = 0, MG_LSGS = 1, MG_SLSGS = 2, MG_CGS = 3 };
+
+/* arithmetic of the cycles: FP64 throughout, or FP32 cycles used as the
+ * preconditioner of FP64 iterative refinement (outer residual, update and the
+ * coarsest-level LU stay FP64) */
+enum mg_precision { MG_FP64 = 0, MG_FP32_IR = 1 };
+
+typedef enum mg_status {
+  MG_OK = 0,
+  MG_EINVAL = -1,      /* invalid argument (checked before any HIP call)     */
+  MG_EHIP = -2,        /* a HIP runtime call failed; see mg_last_error        */
+  MG_ENOMEM = -3,      /* device allocation failed                            */
+  MG_ENOTCONV = -4,    /* max_cycles reached; x holds the last iterate        */
+  MG_ENAN = -5,        /* non-finite residual norm                            */
+  MG_EDIVERGE = -6,    /* residual grew above 1e3 times its initial value     */
+  MG_EUNSUPPORTED = -7 /* valid but not provided by this build                */
+} mg_status;
+
+typedef struct {
+  int smoother;     /* mg_smoother; default MG_LSGS                                  */
+  int nu1, nu2;     /* pre-/post-smoothing steps; default 2, 2 (section 3)           */
+  int gamma;        /* recursive coarse iterates: 1 = V-cycle (default), 2 = W-cycle */
+  double tau;       /* NE damping; <= 0 selects 0.4 (Poisson) / 0.35 (Stokes), section 3 */
+  int coarse_level; /* k0: level solved exactly by FP64 LU; 1..3, default 1           */
+  int precision;    /* mg_precision; default MG_FP64                                */
+  int max_cycles;   /* cap of mg_solve; default 200                                  */
+  int inner_cycles; /* FP32 cycles per refinement step (MG_FP32_IR); default 1       */
+} mg_opts;
+
+/* defaults for a problem (see the field comments) */
+mg_opts mg_default_opts(int problem);
+
+/* Build a solver context for level `level` (n = 2^level cells per side),
+ * regularisation `alpha` (> 0, finite) and problem MG_POISSON.  opts may be
+ * NULL (defaults).  Requires coarse_level+1 <= level <= 12.  Computes the
+ * per-level stencil tables, the FP64 LU factors of the coarsest matrix and
+ * allocates the level hierarchy on the current HIP device.
+ * Errors: MG_EINVAL, MG_EUNSUPPORTED (problem), MG_ENOMEM, MG_EHIP. */
+int mg_setup(int level, double alpha, int problem, const mg_opts *opts, mg_ctx **out);
+
+/* Release the context and its device memory (NULL is allowed). */
+void mg_destroy(mg_ctx *ctx);
+
+/* Number of unknowns on the finest level, 2 (2^level+1)^2 (0 for NULL). */
+size_t mg_vec_len(const mg_ctx *ctx);
+/* Number of unknowns on level l (0 if l is outside [coarse_level, level]). */
+size_t mg_level_len(const mg_ctx *ctx, int level);
+
+/* Read / replace the options (the level and alpha are fixed at setup). */
+int mg_get_opts(const mg_ctx *ctx, mg_opts *out);
+int mg_set_opts(mg_ctx *ctx, const mg_opts *opts);
+
+/* f = (M_k y_D; 0): yd holds the nodal values of the desired state (V
+ * entries), f the fine-level right-hand side (2V entries), eq. mp2. */
+int mg_rhs(mg_ctx *ctx, const double *yd, double *f, void *stream);
+
+/* y = A_l x on level l (section 1, eq. mp2). */
+int mg_apply(mg_ctx *ctx, int level, const double *x, double *y, void *stream);
+
+/* r = f - A_l x on level l; if norm_out is not NULL the Euclidean norm of r
+ * is written there (this synchronises the stream). */
+int mg_residual(mg_ctx *ctx, int level, const double *f, const double *x, double *r, double *norm_out,
+                void *stream);
+
+/* `steps` smoothing steps of the context's smoother on level l, in place on
+ * (x, r) where r = f - A_l x on entry and is kept current (Alg. 1 / Alg. 2). */
+int mg_smooth(mg_ctx *ctx, int level, double *x, double *r, int steps, void *stream);
+
+/* f_c = I_l^{l-1} r: restriction = transpose of the canonical embedding, scale 1
+ * (section 2); r on level l, f_c on level l-1, both fields. */
+int mg_restrict(mg_ctx *ctx, int level, const double *r, double *fc, void *stream);
+
+/* x += I_{l-1}^l x_c: canonical embedding (P1 interpolation), section 2. */
+int mg_prolong_add(mg_ctx *ctx, int level, const double *xc, double *x, void *stream);
+
+/* x = A_{k0}^{-1} f on the coarsest level by FP64 LU with partial pivoting. */
+int mg_coarse_solve(mg_ctx *ctx, const double *f, double *x, void *stream);
+
+/* One multigrid iterate on the finest level, in place on x (section 2):
+ * r = f - A x, nu1 smoothing steps, restriction of the defect, gamma
+ * recursive iterates from zero on the coarse-grid problem (exact LU on k0),
+ * prolongation and correction, r = f - A x, nu2 smoothing steps.  With
+ * precision MG_FP32_IR the iterate is one refinement step: FP64 residual,
+ * inner_cycles FP32 cycles from zero on it, FP64 update.  Stream-ordered, no
+ * host synchronisation. */
+int mg_cycle(mg_ctx *ctx, const double *f, double *x, void *stream);
+
+/* Iterate from the initial guess in x until ||f - A x||_2 <= tol ||f||_2.
+ * cycles_out (may be NULL) receives the number of iterates done, relres_out
+ * (may be NULL) the final relative residual.  Synchronises on one norm per
+ * iterate.  Returns MG_OK, MG_ENOTCONV (x = last iterate), MG_ENAN,
+ * MG_EDIVERGE, or an argument / HIP error.  tol must be > 0. */
+int mg_solve(mg_ctx *ctx, const double *f, double *x, double tol, int *cycles_out, double *relres_out,
+             void *stream);
+
+/* Per-launch timing of the finest-level smoothing kernels with HIP events on
+ * the launch stream: enable (1) / disable (0) and reset; read the total time in
+ * milliseconds and the number of timed launches. */
+int mg_timing_enable(mg_ctx *ctx, int enable);
+int mg_timing_read(mg_ctx *ctx, double *total_ms, long *launches);
+
+/* Static message for a status code. */
+const char *mg_strerror(int status);
+/* Last error message recorded on the context ("" if none; static text for NULL). */
+const char *mg_last_error(const mg_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MGKKT_H */

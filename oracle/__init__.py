@@ -29,9 +29,9 @@ _LIB_PATH = os.path.join(_HERE, "libmgo.so")
 _lib = None
 
 NE, LSGS, SLSGS, CGS = 0, 1, 2, 3
-ORDER_LEX, ORDER_COL7, ORDER_COL7SEQ, ORDER_VLEX = 0, 1, 2, 3
+ORDER_LEX, ORDER_COL7, ORDER_COL7SEQ, ORDER_VLEX, ORDER_COL3 = 0, 1, 2, 3, 4
 SMOOTHERS = {"ne": NE, "lsgs": LSGS, "slsgs": SLSGS, "cgs": CGS}
-ORDERS = {"lex": ORDER_LEX, "col7": ORDER_COL7, "col7seq": ORDER_COL7SEQ, "vlex": ORDER_VLEX, "col3": ORDER_COL7}
+ORDERS = {"lex": ORDER_LEX, "col7": ORDER_COL7, "col7seq": ORDER_COL7SEQ, "vlex": ORDER_VLEX, "col3": ORDER_COL3}
 # damping of the normal-equation smoother used in the paper's experiments
 # (section 3): 0.4 for Poisson control, 0.35 for Stokes control
 TAU_POISSON, TAU_STOKES = 0.4, 0.35

@@ -275,7 +275,7 @@ typedef struct {
   /* orderings for the Gauss-Seidel-like smoothers: order[] lists unknowns,
    * gptr[] delimits groups updated from one residual snapshot */
   int *ord[4], *gptr[4], ngroup[4];
-  int *cgs_ord[2]; /* vertex orders for the collective smoother */
+  int *cgs_ord[3]; /* vertex orders for the collective smoother: lex, col7, col3 */
   int ncgs;
   /* coarsest level only: dense LU with partial pivoting */
   double *lu;
@@ -377,17 +377,22 @@ static void build_orders_poisson(mgo_level *L) {
   }
   for (int i = 0; i <= N; i++) L->gptr[MGO_ORDER_VLEX][i] = i;
   L->ngroup[MGO_ORDER_VLEX] = N;
-  /* collective smoother: vertices in lexicographic order, or by the three
-   * colours (i + j) mod 3 (no two neighbours share a colour) */
+  /* collective smoother: vertices in lexicographic order, by the seven colours
+   * (i + 2j) mod 7, or by the three colours (i + j) mod 3 (no two neighbours
+   * share a colour in either colouring) */
   L->ncgs = V;
-  L->cgs_ord[0] = (int *)xmalloc(V * sizeof(int));
-  L->cgs_ord[1] = (int *)xmalloc(V * sizeof(int));
+  for (int o = 0; o < 3; o++) L->cgs_ord[o] = (int *)xmalloc(V * sizeof(int));
   for (int v = 0; v < V; v++) L->cgs_ord[0][v] = v;
   int at = 0;
+  for (int c = 0; c < 7; c++)
+    for (int j = 0; j <= n; j++)
+      for (int i = 0; i <= n; i++)
+        if ((i + 2 * j) % 7 == c) L->cgs_ord[1][at++] = j * (n + 1) + i;
+  at = 0;
   for (int c = 0; c < 3; c++)
     for (int j = 0; j <= n; j++)
       for (int i = 0; i <= n; i++)
-        if ((i + j) % 3 == c) L->cgs_ord[1][at++] = j * (n + 1) + i;
+        if ((i + j) % 3 == c) L->cgs_ord[2][at++] = j * (n + 1) + i;
 }
 
 static void lu_factor(int n, double *a, int *piv) {
@@ -522,8 +527,7 @@ static void level_free(mgo_level *L) {
     free(L->ord[o]);
     free(L->gptr[o]);
   }
-  free(L->cgs_ord[0]);
-  free(L->cgs_ord[1]);
+  for (int o = 0; o < 3; o++) free(L->cgs_ord[o]);
   free(L->lu);
   free(L->piv);
 }
@@ -647,15 +651,25 @@ static void cgs_step(const mgo_level *L, const int *vord, int nvert, double *x, 
 
 void mgo_smooth(const mgo_hier *h, int level, int kind, int order, double tau, double *x, double *r) {
   const mgo_level *L = &h->lv[level];
-  if (order < 0 || order > 3) order = 0;
+  if (order < 0 || order > 4) order = 0;
   switch (kind) {
     case MGO_NE: ne_step(L, tau, x, r); break;
-    case MGO_LSGS: lsgs_groups(L, L->ord[order], L->gptr[order], L->ngroup[order], 0, x, r); break;
+    case MGO_LSGS:
+      if (order == MGO_ORDER_COL3) order = MGO_ORDER_COL7;
+      lsgs_groups(L, L->ord[order], L->gptr[order], L->ngroup[order], 0, x, r);
+      break;
     case MGO_SLSGS:
+      if (order == MGO_ORDER_COL3) order = MGO_ORDER_COL7;
       lsgs_groups(L, L->ord[order], L->gptr[order], L->ngroup[order], 0, x, r);
       lsgs_groups(L, L->ord[order], L->gptr[order], L->ngroup[order], 1, x, r);
       break;
-    case MGO_CGS: cgs_step(L, L->cgs_ord[order == MGO_ORDER_LEX ? 0 : 1], L->ncgs, x, r); break;
+    case MGO_CGS: {
+      int which = 0; /* lexicographic for MGO_ORDER_LEX and MGO_ORDER_VLEX */
+      if (order == MGO_ORDER_COL7 || order == MGO_ORDER_COL7SEQ) which = 1;
+      if (order == MGO_ORDER_COL3) which = 2;
+      cgs_step(L, L->cgs_ord[which], L->ncgs, x, r);
+      break;
+    }
     default: break;
   }
 }

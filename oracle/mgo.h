@@ -52,7 +52,7 @@ void mgo_transpose(const mgo_csr *A, mgo_csr *At);
 typedef struct mgo_hier mgo_hier;
 
 enum { MGO_NE = 0, MGO_LSGS = 1, MGO_SLSGS = 2, MGO_CGS = 3 };
-enum { MGO_ORDER_LEX = 0, MGO_ORDER_COL7 = 1, MGO_ORDER_COL7SEQ = 2, MGO_ORDER_VLEX = 3 };
+enum { MGO_ORDER_LEX = 0, MGO_ORDER_COL7 = 1, MGO_ORDER_COL7SEQ = 2, MGO_ORDER_VLEX = 3, MGO_ORDER_COL3 = 4 };
 
 /* Build levels coarse..fine (fine >= coarse+1 >= 2) of the Poisson control
  * KKT system for regularisation alpha > 0. problem 0 = Poisson control,
@@ -75,8 +75,9 @@ void mgo_residual(const mgo_hier *h, int level, const double *f, const double *x
 
 /* One smoothing step on level l keeping r = f - A x current (x, r in/out).
  * kind: MGO_NE (Alg. 1, damping tau), MGO_LSGS (Alg. 2 in ordering 'order'),
- * MGO_SLSGS (forward then reversed ordering), MGO_CGS (collective point GS,
- * lexicographic if order == MGO_ORDER_LEX else 3 colours). */
+ * MGO_SLSGS (forward then reversed ordering), MGO_CGS (collective point GS
+ * over vertices: lexicographic, 7 colours for MGO_ORDER_COL7, 3 colours for
+ * MGO_ORDER_COL3). */
 void mgo_smooth(const mgo_hier *h, int level, int kind, int order, double tau, double *x, double *r);
 
 /* Alg. 2 over a caller-given ordering: unknowns ord[gptr[g]..gptr[g+1]) form

@@ -1,0 +1,263 @@
+"""Python binding of libmgkkt, the MI355X all-at-once multigrid solver for the
+Poisson-control KKT system of Takacs (arXiv 1502.03917), eq. mp2.
+
+Argument marshalling only: every step of the solver runs in the HIP kernels of
+``csrc/`` behind the C ABI of ``include/mgkkt.h``.  PyTorch supplies device
+memory (FP64 CUDA tensors) and the current stream.  If ``libmgkkt.so`` is
+missing the import of :func:`lib` raises; there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libmgkkt.so")
+
+MG_POISSON, MG_STOKES = 0, 1
+MG_NE, MG_LSGS, MG_SLSGS, MG_CGS = 0, 1, 2, 3
+MG_FP64, MG_FP32_IR = 0, 1
+MG_OK, MG_EINVAL, MG_EHIP, MG_ENOMEM, MG_ENOTCONV, MG_ENAN, MG_EDIVERGE, MG_EUNSUPPORTED = 0, -1, -2, -3, -4, -5, -6, -7
+
+SMOOTHERS = {"ne": MG_NE, "lsgs": MG_LSGS, "slsgs": MG_SLSGS, "cgs": MG_CGS}
+PRECISIONS = {"fp64": MG_FP64, "fp32_ir": MG_FP32_IR}
+PROBLEMS = {"poisson": MG_POISSON, "stokes": MG_STOKES}
+
+
+class MgOpts(ctypes.Structure):
+    _fields_ = [
+        ("smoother", ctypes.c_int),
+        ("nu1", ctypes.c_int),
+        ("nu2", ctypes.c_int),
+        ("gamma", ctypes.c_int),
+        ("tau", ctypes.c_double),
+        ("coarse_level", ctypes.c_int),
+        ("precision", ctypes.c_int),
+        ("max_cycles", ctypes.c_int),
+        ("inner_cycles", ctypes.c_int),
+    ]
+
+
+class MGError(RuntimeError):
+    def __init__(self, status: int, where: str, detail: str = ""):
+        self.status = status
+        msg = f"{where}: {lib().mg_strerror(status).decode()} ({status})"
+        if detail:
+            msg += f": {detail}"
+        super().__init__(msg)
+
+
+_lib = None
+
+
+def lib():
+    """The loaded libmgkkt.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"libmgkkt.so not built ({LIB_PATH}); run __graft_entry__.build()")
+    L = ctypes.CDLL(LIB_PATH)
+    vp, ip, dp, sz = ctypes.c_void_p, ctypes.c_int, ctypes.c_double, ctypes.c_size_t
+    L.mg_default_opts.restype = MgOpts
+    L.mg_default_opts.argtypes = [ip]
+    L.mg_setup.argtypes = [ip, dp, ip, ctypes.POINTER(MgOpts), ctypes.POINTER(vp)]
+    L.mg_destroy.argtypes = [vp]
+    L.mg_destroy.restype = None
+    L.mg_vec_len.argtypes = [vp]
+    L.mg_vec_len.restype = sz
+    L.mg_level_len.argtypes = [vp, ip]
+    L.mg_level_len.restype = sz
+    L.mg_get_opts.argtypes = [vp, ctypes.POINTER(MgOpts)]
+    L.mg_set_opts.argtypes = [vp, ctypes.POINTER(MgOpts)]
+    L.mg_rhs.argtypes = [vp, vp, vp, vp]
+    L.mg_apply.argtypes = [vp, ip, vp, vp, vp]
+    L.mg_residual.argtypes = [vp, ip, vp, vp, vp, ctypes.POINTER(dp), vp]
+    L.mg_smooth.argtypes = [vp, ip, vp, vp, ip, vp]
+    L.mg_restrict.argtypes = [vp, ip, vp, vp, vp]
+    L.mg_prolong_add.argtypes = [vp, ip, vp, vp, vp]
+    L.mg_coarse_solve.argtypes = [vp, vp, vp, vp]
+    L.mg_cycle.argtypes = [vp, vp, vp, vp]
+    L.mg_solve.argtypes = [vp, vp, vp, dp, ctypes.POINTER(ip), ctypes.POINTER(dp), vp]
+    L.mg_timing_enable.argtypes = [vp, ip]
+    L.mg_timing_read.argtypes = [vp, ctypes.POINTER(dp), ctypes.POINTER(ctypes.c_long)]
+    L.mg_strerror.restype = ctypes.c_char_p
+    L.mg_strerror.argtypes = [ip]
+    L.mg_last_error.restype = ctypes.c_char_p
+    L.mg_last_error.argtypes = [vp]
+    for name in ("mg_setup", "mg_get_opts", "mg_set_opts", "mg_rhs", "mg_apply", "mg_residual", "mg_smooth",
+                 "mg_restrict", "mg_prolong_add", "mg_coarse_solve", "mg_cycle", "mg_solve", "mg_timing_enable",
+                 "mg_timing_read"):
+        getattr(L, name).restype = ip
+    _lib = L
+    return L
+
+
+def default_opts(problem: str = "poisson") -> MgOpts:
+    return lib().mg_default_opts(PROBLEMS[problem])
+
+
+def _stream():
+    import torch
+
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+class Solver:
+    """One solver context: level k (n = 2^k cells per side), alpha, options.
+
+    Tensors passed in are FP64 CUDA tensors on the context's device, contiguous,
+    of length ``level_len(level)`` (2 (2^level+1)^2, field-major [y | lambda]).
+    """
+
+    def __init__(self, level: int, alpha: float, problem: str = "poisson", smoother: str = "lsgs", nu1: int = 2,
+                 nu2: int = 2, gamma: int = 1, tau: float | None = None, coarse_level: int = 1,
+                 precision: str = "fp64", max_cycles: int = 200, inner_cycles: int = 1):
+        L = lib()
+        o = L.mg_default_opts(PROBLEMS[problem])
+        o.smoother = SMOOTHERS[smoother]
+        o.nu1, o.nu2, o.gamma = nu1, nu2, gamma
+        o.tau = -1.0 if tau is None else float(tau)
+        o.coarse_level = coarse_level
+        o.precision = PRECISIONS[precision]
+        o.max_cycles = max_cycles
+        o.inner_cycles = inner_cycles
+        h = ctypes.c_void_p()
+        st = L.mg_setup(level, float(alpha), PROBLEMS[problem], ctypes.byref(o), ctypes.byref(h))
+        if st != MG_OK:
+            raise MGError(st, "mg_setup")
+        self._h = h
+        self.level, self.alpha, self.coarse_level = level, float(alpha), coarse_level
+
+    # -- lifetime ---------------------------------------------------------------
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().mg_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- helpers ------------------------------------------------------------------
+    def _check(self, st: int, where: str):
+        if st != MG_OK:
+            raise MGError(st, where, lib().mg_last_error(self._h).decode())
+
+    def _t(self, t, n: int, name: str):
+        import torch
+
+        if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == torch.float64 and t.is_contiguous()):
+            raise TypeError(f"{name}: expected a contiguous float64 CUDA tensor")
+        if t.numel() != n:
+            raise ValueError(f"{name}: expected {n} entries, got {t.numel()}")
+        return ctypes.c_void_p(t.data_ptr())
+
+    def vec_len(self) -> int:
+        return int(lib().mg_vec_len(self._h))
+
+    def level_len(self, level: int) -> int:
+        return int(lib().mg_level_len(self._h, level))
+
+    def nvert(self, level: int | None = None) -> int:
+        return self.level_len(self.level if level is None else level) // 2
+
+    def opts(self) -> MgOpts:
+        o = MgOpts()
+        self._check(lib().mg_get_opts(self._h, ctypes.byref(o)), "mg_get_opts")
+        return o
+
+    def set_opts(self, **kw):
+        o = self.opts()
+        for k, v in kw.items():
+            if k == "smoother":
+                v = SMOOTHERS[v]
+            elif k == "precision":
+                v = PRECISIONS[v]
+            elif k == "tau" and v is None:
+                v = -1.0
+            setattr(o, k, v)
+        self._check(lib().mg_set_opts(self._h, ctypes.byref(o)), "mg_set_opts")
+
+    def _empty(self, n: int):
+        import torch
+
+        return torch.empty(n, dtype=torch.float64, device="cuda")
+
+    # -- entry points -------------------------------------------------------------
+    def rhs(self, yd, f=None):
+        f = self._empty(self.vec_len()) if f is None else f
+        self._check(lib().mg_rhs(self._h, self._t(yd, self.nvert(), "yd"), self._t(f, self.vec_len(), "f"), _stream()), "mg_rhs")
+        return f
+
+    def apply(self, x, level: int | None = None, y=None):
+        l = self.level if level is None else level
+        n = self.level_len(l)
+        y = self._empty(n) if y is None else y
+        self._check(lib().mg_apply(self._h, l, self._t(x, n, "x"), self._t(y, n, "y"), _stream()), "mg_apply")
+        return y
+
+    def residual(self, f, x, level: int | None = None, r=None, norm: bool = False):
+        l = self.level if level is None else level
+        n = self.level_len(l)
+        r = self._empty(n) if r is None else r
+        nrm = ctypes.c_double(0.0)
+        st = lib().mg_residual(self._h, l, self._t(f, n, "f"), self._t(x, n, "x"), self._t(r, n, "r"),
+                               ctypes.byref(nrm) if norm else None, _stream())
+        self._check(st, "mg_residual")
+        return (r, nrm.value) if norm else r
+
+    def smooth(self, x, r, steps: int = 1, level: int | None = None):
+        l = self.level if level is None else level
+        n = self.level_len(l)
+        self._check(lib().mg_smooth(self._h, l, self._t(x, n, "x"), self._t(r, n, "r"), steps, _stream()), "mg_smooth")
+
+    def restrict(self, r, level: int | None = None, fc=None):
+        l = self.level if level is None else level
+        fc = self._empty(self.level_len(l - 1)) if fc is None else fc
+        st = lib().mg_restrict(self._h, l, self._t(r, self.level_len(l), "r"), self._t(fc, self.level_len(l - 1), "fc"), _stream())
+        self._check(st, "mg_restrict")
+        return fc
+
+    def prolong_add(self, xc, x, level: int | None = None):
+        l = self.level if level is None else level
+        st = lib().mg_prolong_add(self._h, l, self._t(xc, self.level_len(l - 1), "xc"), self._t(x, self.level_len(l), "x"), _stream())
+        self._check(st, "mg_prolong_add")
+        return x
+
+    def coarse_solve(self, f, x=None):
+        n = self.level_len(self.coarse_level)
+        x = self._empty(n) if x is None else x
+        self._check(lib().mg_coarse_solve(self._h, self._t(f, n, "f"), self._t(x, n, "x"), _stream()), "mg_coarse_solve")
+        return x
+
+    def cycle(self, f, x):
+        n = self.vec_len()
+        self._check(lib().mg_cycle(self._h, self._t(f, n, "f"), self._t(x, n, "x"), _stream()), "mg_cycle")
+        return x
+
+    def solve(self, f, x=None, tol: float = 1e-10, raise_on_error: bool = True):
+        """Returns (x, cycles, relres, status)."""
+        import torch
+
+        n = self.vec_len()
+        if x is None:
+            x = torch.zeros(n, dtype=torch.float64, device="cuda")
+        it = ctypes.c_int(0)
+        rel = ctypes.c_double(0.0)
+        st = lib().mg_solve(self._h, self._t(f, n, "f"), self._t(x, n, "x"), float(tol), ctypes.byref(it),
+                            ctypes.byref(rel), _stream())
+        if st != MG_OK and raise_on_error:
+            self._check(st, "mg_solve")
+        return x, it.value, rel.value, st
+
+    def timing_enable(self, on: bool = True):
+        self._check(lib().mg_timing_enable(self._h, int(on)), "mg_timing_enable")
+
+    def timing_read(self):
+        ms = ctypes.c_double(0.0)
+        n = ctypes.c_long(0)
+        self._check(lib().mg_timing_read(self._h, ctypes.byref(ms), ctypes.byref(n)), "mg_timing_read")
+        return ms.value, n.value

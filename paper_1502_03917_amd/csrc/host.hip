@@ -1,0 +1,670 @@
+// Host side of libmgkkt: stencil tables, coarsest-level LU, level hierarchy,
+// the multigrid cycle of section 2 (Takacs, arXiv 1502.03917) as a sequence of
+// stream-ordered HIP launches, and the C ABI of include/mgkkt.h.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/mgkkt.h"
+#include "mg_internal.hpp"
+
+using mgk::Lev;
+using mgk::Tab;
+
+namespace {
+
+constexpr int kMaxLevel = 12;
+constexpr int kMaxCoarse = 3;  // coarsest LU of 2 (2^k0+1)^2 <= 162 unknowns
+
+// ---------------------------------------------------------------- tables
+
+int dir_of(int di, int dj) {
+  for (int d = 0; d < mgk::kNDir; d++)
+    if (mgk::kDI[d] == di && mgk::kDJ[d] == dj) return d;
+  return -1;
+}
+
+// Row of vertex (i, j) of M and of the Laplacian stiffness matrix, from the
+// triangles incident to it.  Square (p, q) is split into {(p,q), (p+1,q),
+// (p+1,q+1)} with the right angle at (p+1,q) and {(p,q), (p+1,q+1), (p,q+1)}
+// with the right angle at (p,q+1).  On a right isosceles P1 triangle the local
+// mass matrix is |T|/12 (1 + delta) = h^2/24 (1 + delta); the local stiffness
+// matrix has 1 at the right-angle vertex, 1/2 at the two others, -1/2 along
+// the legs and 0 along the hypotenuse.
+void row_coefs(int i, int j, int n, double M[mgk::kNDir], double Kl[mgk::kNDir]) {
+  const double h2 = 1.0 / ((double)n * (double)n);
+  for (int d = 0; d < mgk::kNDir; d++) M[d] = Kl[d] = 0.0;
+  for (int q = j - 1; q <= j; q++)
+    for (int p = i - 1; p <= i; p++) {
+      if (p < 0 || q < 0 || p >= n || q >= n) continue;
+      const int tri[2][3][2] = {{{p, q}, {p + 1, q}, {p + 1, q + 1}}, {{p, q}, {p + 1, q + 1}, {p, q + 1}}};
+      const int right[2][2] = {{p + 1, q}, {p, q + 1}};
+      for (int t = 0; t < 2; t++) {
+        bool has_v = false;
+        for (int a = 0; a < 3; a++) has_v |= (tri[t][a][0] == i && tri[t][a][1] == j);
+        if (!has_v) continue;
+        const bool v_right = (right[t][0] == i && right[t][1] == j);
+        for (int a = 0; a < 3; a++) {
+          const int wi = tri[t][a][0], wj = tri[t][a][1];
+          const int d = dir_of(wi - i, wj - j);
+          if (d == 0) {
+            M[0] += 2.0 * h2 / 24.0;
+            Kl[0] += v_right ? 1.0 : 0.5;
+          } else {
+            const bool w_right = (right[t][0] == wi && right[t][1] == wj);
+            M[d] += h2 / 24.0;
+            Kl[d] += (v_right || w_right) ? -0.5 : 0.0;
+          }
+        }
+      }
+    }
+}
+
+// representative index of a 3-class / 5-class along one axis (n >= 4)
+int rep3(int c, int n) { return c == 0 ? 0 : (c == 2 ? n : n / 2); }
+int rep5(int c, int n) { return c <= 1 ? c : (c == 2 ? n / 2 : (c == 3 ? n - 1 : n)); }
+
+struct LevelTables {
+  Tab tab;
+  Lev lev;  // tab pointer filled in later
+};
+
+LevelTables make_tables(int level, double alpha, double tau) {
+  const int n = 1 << level;
+  LevelTables out;
+  std::memset(&out, 0, sizeof(out));
+  Tab& T = out.tab;
+  const double sa = std::sqrt(alpha);
+  double W9[9];
+  for (int ci = 0; ci < 3; ci++)
+    for (int cj = 0; cj < 3; cj++) {
+      const int c = ci * 3 + cj;
+      double M[mgk::kNDir], Kl[mgk::kNDir];
+      row_coefs(rep3(ci, n), rep3(cj, n), n, M, Kl);
+      for (int d = 0; d < mgk::kNDir; d++) {
+        T.M[c][d] = M[d];
+        T.K[c][d] = Kl[d] + M[d];
+      }
+      W9[c] = M[0] + sa * (Kl[0] + M[0]);  // diag(M + sqrt(alpha) K)
+      T.Winv[c] = 1.0 / W9[c];
+    }
+  // N_ii = sum_j A_ij^2 / L_jj, L = blockdiag(W, W/alpha)
+  for (int ci = 0; ci < 5; ci++)
+    for (int cj = 0; cj < 5; cj++) {
+      const int i = rep5(ci, n), j = rep5(cj, n);
+      double M[mgk::kNDir], Kl[mgk::kNDir];
+      row_coefs(i, j, n, M, Kl);
+      double nyy = 0.0, nll = 0.0;
+      for (int d = 0; d < mgk::kNDir; d++) {
+        const int ii = i + mgk::kDI[d], jj = j + mgk::kDJ[d];
+        if (ii < 0 || jj < 0 || ii > n || jj > n) continue;
+        const double Wm = W9[mgk::cls3(ii, n) * 3 + mgk::cls3(jj, n)];
+        const double m = M[d], k = Kl[d] + M[d];
+        nyy += (m * m + alpha * k * k) / Wm;
+        nll += (k * k + m * m / alpha) / Wm;
+      }
+      T.Nyi[ci * 5 + cj] = 1.0 / nyy;
+      T.Nli[ci * 5 + cj] = 1.0 / nll;
+    }
+  Lev& L = out.lev;
+  L.n = n;
+  L.ld = n + 1;
+  L.V = (n + 1) * (n + 1);
+  L.alpha = alpha;
+  L.ainv = 1.0 / alpha;
+  L.tau = tau;
+  const int mid = 1 * 3 + 1;  // inside class
+  L.Mc = T.M[mid][0];
+  L.Mo = T.M[mid][1];
+  L.Kc = T.K[mid][0];
+  L.Ka = T.K[mid][1];
+  L.Kd = T.K[mid][5];
+  L.Winv = T.Winv[mid];
+  L.Nyi = T.Nyi[2 * 5 + 2];
+  L.Nli = T.Nli[2 * 5 + 2];
+  L.tab = nullptr;
+  return out;
+}
+
+// dense KKT matrix of a (small) level, row-major, from the row stencils
+std::vector<double> dense_kkt(int level, double alpha) {
+  const int n = 1 << level, V = (n + 1) * (n + 1), N = 2 * V;
+  std::vector<double> A((size_t)N * N, 0.0);
+  for (int j = 0; j <= n; j++)
+    for (int i = 0; i <= n; i++) {
+      double M[mgk::kNDir], Kl[mgk::kNDir];
+      row_coefs(i, j, n, M, Kl);
+      const int v = j * (n + 1) + i;
+      for (int d = 0; d < mgk::kNDir; d++) {
+        const int ii = i + mgk::kDI[d], jj = j + mgk::kDJ[d];
+        if (ii < 0 || jj < 0 || ii > n || jj > n) continue;
+        const int m = jj * (n + 1) + ii;
+        const double k = Kl[d] + M[d];
+        A[(size_t)v * N + m] += M[d];
+        A[(size_t)v * N + V + m] += k;
+        A[(size_t)(V + v) * N + m] += k;
+        A[(size_t)(V + v) * N + V + m] += -M[d] / alpha;
+      }
+    }
+  return A;
+}
+
+// LU with partial (row) pivoting in place; returns false if singular
+bool lu_factor(int N, std::vector<double>& a, std::vector<int>& piv) {
+  piv.assign(N, 0);
+  for (int k = 0; k < N; k++) {
+    int p = k;
+    for (int i = k + 1; i < N; i++)
+      if (std::fabs(a[(size_t)i * N + k]) > std::fabs(a[(size_t)p * N + k])) p = i;
+    piv[k] = p;
+    if (p != k)
+      for (int c = 0; c < N; c++) std::swap(a[(size_t)k * N + c], a[(size_t)p * N + c]);
+    const double d = a[(size_t)k * N + k];
+    if (d == 0.0 || !std::isfinite(d)) return false;
+    for (int i = k + 1; i < N; i++) {
+      const double l = a[(size_t)i * N + k] / d;
+      a[(size_t)i * N + k] = l;
+      for (int c = k + 1; c < N; c++) a[(size_t)i * N + c] -= l * a[(size_t)k * N + c];
+    }
+  }
+  return true;
+}
+
+}  // namespace
+
+// -------------------------------------------------------------------- context
+
+struct LevelBuf {
+  int level = 0;
+  Lev lev{};
+  Tab* d_tab = nullptr;
+  size_t len = 0;  // 2V
+  double *x = nullptr, *f = nullptr, *r = nullptr, *p = nullptr;
+  float *x32 = nullptr, *f32 = nullptr, *r32 = nullptr, *p32 = nullptr;
+};
+
+struct mg_ctx {
+  int problem = 0, level = 0, k0 = 1, device = 0;
+  double alpha = 1.0;
+  mg_opts o{};
+  std::vector<LevelBuf> lv;  // lv[l - k0]
+  int ncoarse = 0;
+  double* d_lu = nullptr;
+  int* d_piv = nullptr;
+  double* d_part = nullptr;  // per-block partial sums
+  size_t npart = 0;
+  double* d_norm = nullptr;  // [0] = ||r||^2 of the latest residual, [1] = ||f||^2
+  double* h_norm = nullptr;  // pinned host copy
+  bool fp32_ready = false;
+  // timing of the finest-level smoothing sweeps
+  bool timing = false;
+  std::vector<hipEvent_t> ev;  // pairs
+  size_t ev_used = 0;
+  double t_ms = 0.0;
+  long t_n = 0;
+  std::string err;
+};
+
+namespace {
+
+const char* kStatusText[] = {"success",
+                             "invalid argument",
+                             "HIP runtime error",
+                             "device memory allocation failed",
+                             "no convergence within max_cycles",
+                             "non-finite residual norm",
+                             "residual diverged",
+                             "not supported by this build"};
+
+int fail(mg_ctx* c, int status, const std::string& msg) {
+  if (c) c->err = msg;
+  return status;
+}
+
+#define HIPCHK(ctx, expr)                                                                                  \
+  do {                                                                                                     \
+    hipError_t e_ = (expr);                                                                                \
+    if (e_ != hipSuccess)                                                                                  \
+      return fail((ctx), e_ == hipErrorOutOfMemory ? MG_ENOMEM : MG_EHIP,                                  \
+                  std::string(#expr) + ": " + hipGetErrorString(e_));                                      \
+  } while (0)
+
+LevelBuf& L_(mg_ctx* c, int l) { return c->lv[l - c->k0]; }
+
+bool valid_opts(const mg_opts* o, int level) {
+  if (!o) return true;
+  if (o->smoother < MG_NE || o->smoother > MG_CGS) return false;
+  if (o->nu1 < 0 || o->nu2 < 0 || o->nu1 > 64 || o->nu2 > 64) return false;
+  if (o->gamma < 1 || o->gamma > 2) return false;
+  if (!std::isfinite(o->tau) || o->tau >= 2.0) return false;
+  if (o->coarse_level < 1 || o->coarse_level > kMaxCoarse) return false;
+  if (level >= 0 && level < o->coarse_level + 1) return false;
+  if (o->precision != MG_FP64 && o->precision != MG_FP32_IR) return false;
+  if (o->max_cycles < 0 || o->max_cycles > 100000) return false;
+  if (o->inner_cycles < 1 || o->inner_cycles > 64) return false;
+  return true;
+}
+
+void destroy_impl(mg_ctx* c) {
+  if (!c) return;
+  (void)hipSetDevice(c->device);
+  for (auto& b : c->lv) {
+    (void)hipFree(b.d_tab);
+    (void)hipFree(b.x);
+    (void)hipFree(b.f);
+    (void)hipFree(b.r);
+    (void)hipFree(b.p);
+    (void)hipFree(b.x32);
+    (void)hipFree(b.f32);
+    (void)hipFree(b.r32);
+    (void)hipFree(b.p32);
+  }
+  (void)hipFree(c->d_lu);
+  (void)hipFree(c->d_piv);
+  (void)hipFree(c->d_part);
+  (void)hipFree(c->d_norm);
+  if (c->h_norm) (void)hipHostFree(c->h_norm);
+  for (auto e : c->ev) (void)hipEventDestroy(e);
+  delete c;
+}
+
+int alloc_fp32(mg_ctx* c) {
+  if (c->fp32_ready) return MG_OK;
+  for (auto& b : c->lv) {
+    const size_t bytes = b.len * sizeof(float);
+    HIPCHK(c, hipMalloc(&b.x32, bytes));
+    HIPCHK(c, hipMalloc(&b.f32, bytes));
+    HIPCHK(c, hipMalloc(&b.r32, bytes));
+    if (b.level > c->k0) HIPCHK(c, hipMalloc(&b.p32, bytes));
+  }
+  c->fp32_ready = true;
+  return MG_OK;
+}
+
+// ------------------------------------------------------------- cycle (T = double / float)
+
+template <typename T>
+struct Work {
+  T *x, *f, *r, *p;
+};
+Work<double> work(LevelBuf& b, double*) { return {b.x, b.f, b.r, b.p}; }
+Work<float> work(LevelBuf& b, float*) { return {b.x32, b.f32, b.r32, b.p32}; }
+
+void timing_begin(mg_ctx* c, hipStream_t s, size_t* slot) {
+  if (c->ev_used + 2 > c->ev.size()) {
+    // fold the recorded pairs into the running total before reusing them
+    if (!c->ev.empty()) {
+      (void)hipEventSynchronize(c->ev[c->ev_used - 1]);
+      for (size_t k = 0; k + 1 < c->ev_used; k += 2) {
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, c->ev[k], c->ev[k + 1]) == hipSuccess) c->t_ms += ms;
+      }
+      c->ev_used = 0;
+    }
+    while (c->ev.size() < 2048) {
+      hipEvent_t e;
+      if (hipEventCreate(&e) != hipSuccess) break;
+      c->ev.push_back(e);
+    }
+  }
+  *slot = c->ev_used;
+  c->ev_used += 2;
+  (void)hipEventRecord(c->ev[*slot], s);
+}
+
+template <typename T>
+int smooth_steps(mg_ctx* c, int l, T* x, T* r, T* p, int steps, hipStream_t s) {
+  LevelBuf& b = L_(c, l);
+  const Lev& L = b.lev;
+  const bool timed = c->timing && l == c->level;
+  for (int it = 0; it < steps; it++) {
+    size_t slot = 0;
+    if (timed) timing_begin(c, s, &slot);
+    switch (c->o.smoother) {
+      case MG_NE:
+        HIPCHK(c, mgk::launch_ne<T>(L, x, r, p, s));
+        break;
+      case MG_LSGS:
+        for (int col = 0; col < 7; col++) HIPCHK(c, mgk::launch_lsgs_phase<T>(L, col, x, r, s));
+        break;
+      case MG_SLSGS:
+        for (int col = 0; col < 7; col++) HIPCHK(c, mgk::launch_lsgs_phase<T>(L, col, x, r, s));
+        for (int col = 6; col >= 0; col--) HIPCHK(c, mgk::launch_lsgs_phase<T>(L, col, x, r, s));
+        break;
+      case MG_CGS:
+        for (int col = 0; col < 7; col++) HIPCHK(c, mgk::launch_cgs_phase<T>(L, col, x, r, s));
+        break;
+    }
+    if (timed) {
+      (void)hipEventRecord(c->ev[slot + 1], s);
+      c->t_n++;
+    }
+  }
+  return MG_OK;
+}
+
+template <typename T>
+int coarse_solve_T(mg_ctx* c, const T* f, T* x, hipStream_t s) {
+  HIPCHK(c, mgk::launch_coarse_solve<T>(c->ncoarse, c->d_lu, c->d_piv, f, x, s));
+  return MG_OK;
+}
+
+// One iterate on level l for A_l x = f; r is level-l workspace.  If
+// residual_current, r already holds f - A_l x.
+template <typename T>
+int cycle_body(mg_ctx* c, int l, const T* f, T* x, T* r, bool residual_current, hipStream_t s) {
+  if (l == c->k0) return coarse_solve_T<T>(c, f, x, s);
+  LevelBuf& b = L_(c, l);
+  LevelBuf& bc = L_(c, l - 1);
+  Work<T> wb = work(b, (T*)nullptr);
+  Work<T> wc = work(bc, (T*)nullptr);
+  int st;
+  if (!residual_current) HIPCHK(c, mgk::launch_residual<T>(b.lev, f, x, r, nullptr, nullptr, s));
+  if ((st = smooth_steps<T>(c, l, x, r, wb.p, c->o.nu1, s)) != MG_OK) return st;
+  // defect restriction; the coarse iterate starts from zero with r_c = f_c
+  const bool coarse_is_k0 = (l - 1 == c->k0);
+  HIPCHK(c, mgk::launch_restrict<T>(b.lev, bc.lev, r, wc.f, coarse_is_k0 ? nullptr : wc.x,
+                                    coarse_is_k0 ? nullptr : wc.r, s));
+  for (int g = 0; g < c->o.gamma; g++) {
+    if ((st = cycle_body<T>(c, l - 1, wc.f, wc.x, wc.r, g == 0, s)) != MG_OK) return st;
+  }
+  HIPCHK(c, mgk::launch_prolong_add<T>(b.lev, bc.lev, wc.x, x, s));
+  HIPCHK(c, mgk::launch_residual<T>(b.lev, f, x, r, nullptr, nullptr, s));
+  return smooth_steps<T>(c, l, x, r, wb.p, c->o.nu2, s);
+}
+
+// ||r||^2 of the fine residual into d_norm[slot] (stream-ordered)
+int residual_norm(mg_ctx* c, const double* f, const double* x, double* r, int slot, hipStream_t s) {
+  LevelBuf& b = L_(c, c->level);
+  int nb = 0;
+  HIPCHK(c, mgk::launch_residual<double>(b.lev, f, x, r, c->d_part, &nb, s));
+  HIPCHK(c, mgk::launch_sum(c->d_part, nb, c->d_norm + slot, s));
+  return MG_OK;
+}
+
+// one refinement step: FP32 cycles from zero on the scaled FP64 residual held
+// in the fine r buffer (with ||r||^2 in d_norm[0]), then x += s c in FP64
+int ir_step(mg_ctx* c, double* x, hipStream_t s) {
+  LevelBuf& b = L_(c, c->level);
+  HIPCHK(c, mgk::launch_to_f32_scaled(b.r, b.len, c->d_norm, b.f32, b.r32, s));
+  HIPCHK(c, mgk::launch_zero_f32(b.x32, b.len, s));
+  int st;
+  for (int k = 0; k < c->o.inner_cycles; k++)
+    if ((st = cycle_body<float>(c, c->level, b.f32, b.x32, b.r32, k == 0, s)) != MG_OK) return st;
+  HIPCHK(c, mgk::launch_axpy_f32(b.x32, b.len, c->d_norm, x, s));
+  return MG_OK;
+}
+
+int check_level(const mg_ctx* c, int l, bool allow_coarsest) {
+  if (l > c->level || l < c->k0) return 0;
+  if (!allow_coarsest && l == c->k0) return 0;
+  return 1;
+}
+
+}  // namespace
+
+// ====================================================================== C ABI
+
+extern "C" {
+
+mg_opts mg_default_opts(int problem) {
+  mg_opts o;
+  o.smoother = MG_LSGS;
+  o.nu1 = 2;
+  o.nu2 = 2;
+  o.gamma = 1;
+  o.tau = problem == MG_STOKES ? 0.35 : 0.4;
+  o.coarse_level = 1;
+  o.precision = MG_FP64;
+  o.max_cycles = 200;
+  o.inner_cycles = 1;
+  return o;
+}
+
+const char* mg_strerror(int status) {
+  if (status > 0 || status < MG_EUNSUPPORTED) return "unknown status";
+  return kStatusText[-status];
+}
+
+const char* mg_last_error(const mg_ctx* ctx) {
+  if (!ctx) return "no context";
+  return ctx->err.c_str();
+}
+
+size_t mg_vec_len(const mg_ctx* ctx) { return ctx ? ctx->lv.back().len : 0; }
+
+size_t mg_level_len(const mg_ctx* ctx, int level) {
+  if (!ctx || level < ctx->k0 || level > ctx->level) return 0;
+  return ctx->lv[level - ctx->k0].len;
+}
+
+int mg_get_opts(const mg_ctx* ctx, mg_opts* out) {
+  if (!ctx || !out) return MG_EINVAL;
+  *out = ctx->o;
+  return MG_OK;
+}
+
+int mg_setup(int level, double alpha, int problem, const mg_opts* opts, mg_ctx** out) {
+  if (!out) return MG_EINVAL;
+  *out = nullptr;
+  if (problem != MG_POISSON && problem != MG_STOKES) return MG_EINVAL;
+  if (!(alpha > 0.0) || !std::isfinite(alpha)) return MG_EINVAL;
+  if (level < 2 || level > kMaxLevel) return MG_EINVAL;
+  if (!valid_opts(opts, level)) return MG_EINVAL;
+  if (problem == MG_STOKES) return MG_EUNSUPPORTED;
+  mg_ctx* c = new (std::nothrow) mg_ctx();
+  if (!c) return MG_ENOMEM;
+  c->problem = problem;
+  c->level = level;
+  c->alpha = alpha;
+  c->o = opts ? *opts : mg_default_opts(problem);
+  if (c->o.tau <= 0.0) c->o.tau = problem == MG_STOKES ? 0.35 : 0.4;
+  c->k0 = c->o.coarse_level;
+  int st = MG_OK;
+  auto bail = [&](int s) {
+    destroy_impl(c);
+    return s;
+  };
+  if (hipGetDevice(&c->device) != hipSuccess) {
+    delete c;
+    return MG_EHIP;
+  }
+  c->lv.resize(level - c->k0 + 1);
+  size_t max_blocks = 1;
+  for (int l = c->k0; l <= level; l++) {
+    LevelBuf& b = L_(c, l);
+    b.level = l;
+    // level 1 can only be the coarsest level, which is solved by the dense LU:
+    // its stencil tables are never read, those of level 2 stand in
+    LevelTables t = make_tables(l < 2 ? 2 : l, alpha, c->o.tau);
+    b.lev = t.lev;
+    const int n = 1 << l;
+    b.lev.n = n;
+    b.lev.ld = n + 1;
+    b.lev.V = (n + 1) * (n + 1);
+    b.len = 2 * (size_t)b.lev.V;
+    if (hipMalloc(&b.d_tab, sizeof(Tab)) != hipSuccess) return bail(MG_ENOMEM);
+    if (hipMemcpy(b.d_tab, &t.tab, sizeof(Tab), hipMemcpyHostToDevice) != hipSuccess) return bail(MG_EHIP);
+    b.lev.tab = b.d_tab;
+    const size_t bytes = b.len * sizeof(double);
+    if (l < level) {
+      if (hipMalloc(&b.x, bytes) != hipSuccess || hipMalloc(&b.f, bytes) != hipSuccess) return bail(MG_ENOMEM);
+    }
+    if (l > c->k0) {
+      if (hipMalloc(&b.r, bytes) != hipSuccess || hipMalloc(&b.p, bytes) != hipSuccess) return bail(MG_ENOMEM);
+    }
+    const size_t nb = (size_t)((n + 1 + 63) / 64) * (size_t)((n + 1 + 3) / 4);
+    if (nb > max_blocks) max_blocks = nb;
+  }
+  // coarsest level: FP64 LU with partial pivoting of A_{k0}
+  {
+    std::vector<double> A = dense_kkt(c->k0, alpha);
+    std::vector<int> piv;
+    const int N = 2 * ((1 << c->k0) + 1) * ((1 << c->k0) + 1);
+    if (!lu_factor(N, A, piv)) return bail(fail(c, MG_EINVAL, "singular coarsest matrix"));
+    c->ncoarse = N;
+    if (hipMalloc(&c->d_lu, A.size() * sizeof(double)) != hipSuccess) return bail(MG_ENOMEM);
+    if (hipMalloc(&c->d_piv, piv.size() * sizeof(int)) != hipSuccess) return bail(MG_ENOMEM);
+    if (hipMemcpy(c->d_lu, A.data(), A.size() * sizeof(double), hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(c->d_piv, piv.data(), piv.size() * sizeof(int), hipMemcpyHostToDevice) != hipSuccess)
+      return bail(MG_EHIP);
+  }
+  if (max_blocks < 1024) max_blocks = 1024;
+  c->npart = max_blocks;
+  if (hipMalloc(&c->d_part, max_blocks * sizeof(double)) != hipSuccess) return bail(MG_ENOMEM);
+  if (hipMalloc(&c->d_norm, 4 * sizeof(double)) != hipSuccess) return bail(MG_ENOMEM);
+  if (hipHostMalloc((void**)&c->h_norm, 4 * sizeof(double), hipHostMallocDefault) != hipSuccess)
+    return bail(MG_ENOMEM);
+  if (c->o.precision == MG_FP32_IR && (st = alloc_fp32(c)) != MG_OK) return bail(st);
+  *out = c;
+  return MG_OK;
+}
+
+void mg_destroy(mg_ctx* ctx) { destroy_impl(ctx); }
+
+int mg_set_opts(mg_ctx* ctx, const mg_opts* opts) {
+  if (!ctx || !opts) return MG_EINVAL;
+  if (!valid_opts(opts, ctx->level)) return MG_EINVAL;
+  if (opts->coarse_level != ctx->k0) return fail(ctx, MG_EINVAL, "coarse_level is fixed at setup");
+  mg_opts o = *opts;
+  if (o.tau <= 0.0) o.tau = ctx->problem == MG_STOKES ? 0.35 : 0.4;
+  if (hipSetDevice(ctx->device) != hipSuccess) return MG_EHIP;
+  if (o.precision == MG_FP32_IR) {
+    int st = alloc_fp32(ctx);
+    if (st != MG_OK) return st;
+  }
+  ctx->o = o;
+  for (auto& b : ctx->lv) b.lev.tau = o.tau;
+  return MG_OK;
+}
+
+int mg_rhs(mg_ctx* ctx, const double* yd, double* f, void* stream) {
+  if (!ctx || !yd || !f) return MG_EINVAL;
+  HIPCHK(ctx, mgk::launch_rhs<double>(L_(ctx, ctx->level).lev, yd, f, (hipStream_t)stream));
+  return MG_OK;
+}
+
+int mg_apply(mg_ctx* ctx, int level, const double* x, double* y, void* stream) {
+  if (!ctx || !x || !y || !check_level(ctx, level, false)) return MG_EINVAL;
+  HIPCHK(ctx, mgk::launch_apply<double>(L_(ctx, level).lev, x, y, (hipStream_t)stream));
+  return MG_OK;
+}
+
+int mg_residual(mg_ctx* ctx, int level, const double* f, const double* x, double* r, double* norm_out,
+                void* stream) {
+  if (!ctx || !f || !x || !r || !check_level(ctx, level, false)) return MG_EINVAL;
+  hipStream_t s = (hipStream_t)stream;
+  LevelBuf& b = L_(ctx, level);
+  if (!norm_out) {
+    HIPCHK(ctx, mgk::launch_residual<double>(b.lev, f, x, r, nullptr, nullptr, s));
+    return MG_OK;
+  }
+  int nb = 0;
+  HIPCHK(ctx, mgk::launch_residual<double>(b.lev, f, x, r, ctx->d_part, &nb, s));
+  HIPCHK(ctx, mgk::launch_sum(ctx->d_part, nb, ctx->d_norm + 2, s));
+  HIPCHK(ctx, hipMemcpyAsync(ctx->h_norm + 2, ctx->d_norm + 2, sizeof(double), hipMemcpyDeviceToHost, s));
+  HIPCHK(ctx, hipStreamSynchronize(s));
+  *norm_out = std::sqrt(ctx->h_norm[2]);
+  return MG_OK;
+}
+
+int mg_smooth(mg_ctx* ctx, int level, double* x, double* r, int steps, void* stream) {
+  if (!ctx || !x || !r || steps < 0 || !check_level(ctx, level, false)) return MG_EINVAL;
+  return smooth_steps<double>(ctx, level, x, r, L_(ctx, level).p, steps, (hipStream_t)stream);
+}
+
+int mg_restrict(mg_ctx* ctx, int level, const double* r, double* fc, void* stream) {
+  if (!ctx || !r || !fc || !check_level(ctx, level, false)) return MG_EINVAL;
+  HIPCHK(ctx, mgk::launch_restrict<double>(L_(ctx, level).lev, L_(ctx, level - 1).lev, r, fc, nullptr, nullptr,
+                                           (hipStream_t)stream));
+  return MG_OK;
+}
+
+int mg_prolong_add(mg_ctx* ctx, int level, const double* xc, double* x, void* stream) {
+  if (!ctx || !xc || !x || !check_level(ctx, level, false)) return MG_EINVAL;
+  HIPCHK(ctx, mgk::launch_prolong_add<double>(L_(ctx, level).lev, L_(ctx, level - 1).lev, xc, x,
+                                              (hipStream_t)stream));
+  return MG_OK;
+}
+
+int mg_coarse_solve(mg_ctx* ctx, const double* f, double* x, void* stream) {
+  if (!ctx || !f || !x) return MG_EINVAL;
+  return coarse_solve_T<double>(ctx, f, x, (hipStream_t)stream);
+}
+
+int mg_cycle(mg_ctx* ctx, const double* f, double* x, void* stream) {
+  if (!ctx || !f || !x) return MG_EINVAL;
+  hipStream_t s = (hipStream_t)stream;
+  LevelBuf& b = L_(ctx, ctx->level);
+  if (ctx->o.precision == MG_FP32_IR) {
+    int st = residual_norm(ctx, f, x, b.r, 0, s);
+    if (st != MG_OK) return st;
+    return ir_step(ctx, x, s);
+  }
+  return cycle_body<double>(ctx, ctx->level, f, x, b.r, false, s);
+}
+
+int mg_solve(mg_ctx* ctx, const double* f, double* x, double tol, int* cycles_out, double* relres_out,
+             void* stream) {
+  if (!ctx || !f || !x || !(tol > 0.0) || !std::isfinite(tol)) return MG_EINVAL;
+  hipStream_t s = (hipStream_t)stream;
+  LevelBuf& b = L_(ctx, ctx->level);
+  int nb = 0;
+  HIPCHK(ctx, mgk::launch_sumsq(f, b.len, ctx->d_part, &nb, s));
+  HIPCHK(ctx, mgk::launch_sum(ctx->d_part, nb, ctx->d_norm + 1, s));
+  double nf = -1.0, rel0 = -1.0, rel = 0.0;
+  int it = 0, st = MG_OK;
+  for (;; it++) {
+    if ((st = residual_norm(ctx, f, x, b.r, 0, s)) != MG_OK) return st;
+    HIPCHK(ctx, hipMemcpyAsync(ctx->h_norm, ctx->d_norm, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIPCHK(ctx, hipStreamSynchronize(s));
+    if (nf < 0.0) nf = std::sqrt(ctx->h_norm[1]) > 0.0 ? std::sqrt(ctx->h_norm[1]) : 1.0;
+    rel = std::sqrt(ctx->h_norm[0]) / nf;
+    if (rel0 < 0.0) rel0 = rel;
+    if (cycles_out) *cycles_out = it;
+    if (relres_out) *relres_out = rel;
+    if (!std::isfinite(rel)) return fail(ctx, MG_ENAN, "non-finite residual norm");
+    if (rel <= tol) return MG_OK;
+    if (rel > 1e3 * rel0 && rel0 > 0.0) return fail(ctx, MG_EDIVERGE, "residual grew above 1e3 x initial");
+    if (it >= ctx->o.max_cycles) return fail(ctx, MG_ENOTCONV, "max_cycles reached");
+    if (ctx->o.precision == MG_FP32_IR)
+      st = ir_step(ctx, x, s);
+    else
+      st = cycle_body<double>(ctx, ctx->level, f, x, b.r, true, s);
+    if (st != MG_OK) return st;
+  }
+}
+
+int mg_timing_enable(mg_ctx* ctx, int enable) {
+  if (!ctx) return MG_EINVAL;
+  if (ctx->ev_used) (void)hipEventSynchronize(ctx->ev[ctx->ev_used - 1]);
+  ctx->ev_used = 0;
+  ctx->t_ms = 0.0;
+  ctx->t_n = 0;
+  ctx->timing = enable != 0;
+  return MG_OK;
+}
+
+int mg_timing_read(mg_ctx* ctx, double* total_ms, long* launches) {
+  if (!ctx || !total_ms || !launches) return MG_EINVAL;
+  if (ctx->ev_used) {
+    HIPCHK(ctx, hipEventSynchronize(ctx->ev[ctx->ev_used - 1]));
+    for (size_t k = 0; k + 1 < ctx->ev_used; k += 2) {
+      float ms = 0.f;
+      HIPCHK(ctx, hipEventElapsedTime(&ms, ctx->ev[k], ctx->ev[k + 1]));
+      ctx->t_ms += ms;
+    }
+    ctx->ev_used = 0;
+  }
+  *total_ms = ctx->t_ms;
+  *launches = ctx->t_n;
+  return MG_OK;
+}
+
+}  // extern "C"

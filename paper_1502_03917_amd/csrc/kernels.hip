@@ -1,0 +1,568 @@
+// HIP kernels of the all-at-once multigrid cycle for the Poisson-control KKT
+// system (Takacs, arXiv 1502.03917, section 1 eq. mp2 and section 2) on gfx950.
+//
+// All kernels are matrix-free: the P1 mass matrix M and K = Klap + M act as
+// 7-point stencils on the (n+1)x(n+1) vertex grid.  Vertices at least one
+// (residual) or two (smoothers) rows away from the boundary use the constant
+// interior coefficients held in the Lev struct (kernel arguments, scalar
+// registers); the few boundary vertices read their coefficients from the small
+// per-level class table.  The path is HBM-bound (about 2-4 flop per byte), so
+// there is no MFMA: each lane owns one vertex and neighbouring lanes read
+// neighbouring addresses.
+#include "mg_internal.hpp"
+
+namespace mgk {
+
+namespace {
+
+constexpr int kBX = 64;  // one wavefront along a grid row
+constexpr int kBY = 4;
+constexpr int kNT = kBX * kBY;
+
+__device__ inline double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+  return v;
+}
+
+// deterministic block sum of one value per thread (256 threads), stored by thread 0
+__device__ inline void block_sum_store(double v, double* out) {
+  __shared__ double sh[kNT / 64];
+  const int tid = threadIdx.x + threadIdx.y * blockDim.x;
+  v = wave_sum(v);
+  if ((tid & 63) == 0) sh[tid >> 6] = v;
+  __syncthreads();
+  if (tid == 0) {
+    double s = 0.0;
+#pragma unroll
+    for (int w = 0; w < kNT / 64; w++) s += sh[w];
+    *out = s;
+  }
+}
+
+template <typename T>
+__device__ inline void coef_MK(const Lev& L, int i, int j, T M[kNDir], T K[kNDir]) {
+  const int c = cls3(i, L.n) * 3 + cls3(j, L.n);
+#pragma unroll
+  for (int d = 0; d < kNDir; d++) {
+    M[d] = (T)L.tab->M[c][d];
+    K[d] = (T)L.tab->K[c][d];
+  }
+}
+
+__device__ inline bool inside(const Lev& L, int i, int j) { return i >= 0 && i <= L.n && j >= 0 && j <= L.n; }
+
+// (A x)_v for both rows of vertex v = (i, j)
+template <typename T>
+__device__ inline void apply_at(const Lev& L, int i, int j, const T* __restrict__ x, T& ay, T& al) {
+  const int v = j * L.ld + i;
+  const T* xy = x;
+  const T* xl = x + L.V;
+  const T ai = (T)L.ainv;
+  if (i >= 1 && i < L.n && j >= 1 && j < L.n) {
+    const int ld = L.ld;
+    const T yc = xy[v], lc = xl[v];
+    const T ya = xy[v + 1] + xy[v - 1] + xy[v + ld] + xy[v - ld];
+    const T yg = xy[v + ld + 1] + xy[v - ld - 1];
+    const T la = xl[v + 1] + xl[v - 1] + xl[v + ld] + xl[v - ld];
+    const T lg = xl[v + ld + 1] + xl[v - ld - 1];
+    const T Mc = (T)L.Mc, Mo = (T)L.Mo, Kc = (T)L.Kc, Ka = (T)L.Ka, Kd = (T)L.Kd;
+    ay = Mc * yc + Mo * (ya + yg) + (Kc * lc + Ka * la + Kd * lg);
+    al = (Kc * yc + Ka * ya + Kd * yg) - ai * (Mc * lc + Mo * (la + lg));
+  } else {
+    T M[kNDir], K[kNDir];
+    coef_MK(L, i, j, M, K);
+    ay = 0;
+    al = 0;
+#pragma unroll
+    for (int d = 0; d < kNDir; d++) {
+      const int ii = i + kDI[d], jj = j + kDJ[d];
+      if (!inside(L, ii, jj)) continue;
+      const int m = jj * L.ld + ii;
+      ay += M[d] * xy[m] + K[d] * xl[m];
+      al += K[d] * xy[m] - ai * M[d] * xl[m];
+    }
+  }
+}
+
+// q = (A^T L^{-1} r) at the two unknowns of vertex (i, j):
+//   q_y = sum_m (M_vm r^y_m + alpha K_vm r^l_m) / W_m
+//   q_l = sum_m (K_vm r^y_m - M_vm r^l_m) / W_m
+// (L = blockdiag(W, W / alpha)); also returns 1/W_v, 1/N_yy, 1/N_ll of v.
+template <typename T>
+__device__ inline void gather_q(const Lev& L, int i, int j, const T* __restrict__ r, T& qy, T& ql, T& wv, T& nyi,
+                                T& nli) {
+  const int v = j * L.ld + i;
+  const T* ry = r;
+  const T* rl = r + L.V;
+  const T al = (T)L.alpha;
+  if (i >= 2 && i <= L.n - 2 && j >= 2 && j <= L.n - 2) {
+    const int ld = L.ld;
+    const T yc = ry[v], lc = rl[v];
+    const T ya = ry[v + 1] + ry[v - 1] + ry[v + ld] + ry[v - ld];
+    const T yg = ry[v + ld + 1] + ry[v - ld - 1];
+    const T la = rl[v + 1] + rl[v - 1] + rl[v + ld] + rl[v - ld];
+    const T lg = rl[v + ld + 1] + rl[v - ld - 1];
+    const T Mc = (T)L.Mc, Mo = (T)L.Mo, Kc = (T)L.Kc, Ka = (T)L.Ka, Kd = (T)L.Kd, Wi = (T)L.Winv;
+    qy = Wi * (Mc * yc + Mo * (ya + yg) + al * (Kc * lc + Ka * la + Kd * lg));
+    ql = Wi * ((Kc * yc + Ka * ya + Kd * yg) - (Mc * lc + Mo * (la + lg)));
+    wv = Wi;
+    nyi = (T)L.Nyi;
+    nli = (T)L.Nli;
+  } else {
+    T M[kNDir], K[kNDir];
+    coef_MK(L, i, j, M, K);
+    qy = 0;
+    ql = 0;
+#pragma unroll
+    for (int d = 0; d < kNDir; d++) {
+      const int ii = i + kDI[d], jj = j + kDJ[d];
+      if (!inside(L, ii, jj)) continue;
+      const int m = jj * L.ld + ii;
+      const T wi = (T)L.tab->Winv[cls3(ii, L.n) * 3 + cls3(jj, L.n)];
+      const T a = ry[m], b = rl[m];
+      qy += (M[d] * a + al * K[d] * b) * wi;
+      ql += (K[d] * a - M[d] * b) * wi;
+    }
+    wv = (T)L.tab->Winv[cls3(i, L.n) * 3 + cls3(j, L.n)];
+    const int c5 = cls5(i, L.n) * 5 + cls5(j, L.n);
+    nyi = (T)L.tab->Nyi[c5];
+    nli = (T)L.tab->Nli[c5];
+  }
+}
+
+// r_m -= A_{m v} (py, pl) for the neighbours m of v (A symmetric: A_mv = A_vm)
+template <typename T>
+__device__ inline void scatter_r(const Lev& L, int i, int j, T py, T pl, T* __restrict__ r) {
+  const int v = j * L.ld + i;
+  T* ry = r;
+  T* rl = r + L.V;
+  const T ai = (T)L.ainv;
+  if (i >= 1 && i < L.n && j >= 1 && j < L.n) {
+    const int ld = L.ld;
+    const T Mc = (T)L.Mc, Mo = (T)L.Mo, Kc = (T)L.Kc, Ka = (T)L.Ka, Kd = (T)L.Kd;
+    const T dyc = Mc * py + Kc * pl, dya = Mo * py + Ka * pl, dyg = Mo * py + Kd * pl;
+    const T dlc = Kc * py - ai * (Mc * pl), dla = Ka * py - ai * (Mo * pl), dlg = Kd * py - ai * (Mo * pl);
+    ry[v] -= dyc;
+    rl[v] -= dlc;
+    ry[v + 1] -= dya;
+    rl[v + 1] -= dla;
+    ry[v - 1] -= dya;
+    rl[v - 1] -= dla;
+    ry[v + ld] -= dya;
+    rl[v + ld] -= dla;
+    ry[v - ld] -= dya;
+    rl[v - ld] -= dla;
+    ry[v + ld + 1] -= dyg;
+    rl[v + ld + 1] -= dlg;
+    ry[v - ld - 1] -= dyg;
+    rl[v - ld - 1] -= dlg;
+  } else {
+    T M[kNDir], K[kNDir];
+    coef_MK(L, i, j, M, K);
+#pragma unroll
+    for (int d = 0; d < kNDir; d++) {
+      const int ii = i + kDI[d], jj = j + kDJ[d];
+      if (!inside(L, ii, jj)) continue;
+      const int m = jj * L.ld + ii;
+      ry[m] -= M[d] * py + K[d] * pl;
+      rl[m] -= K[d] * py - ai * (M[d] * pl);
+    }
+  }
+}
+
+// ------------------------------------------------------------------ kernels
+
+template <typename T, bool HAS_F, bool NORM>
+__global__ __launch_bounds__(kNT) void k_residual(Lev L, const T* __restrict__ f, const T* __restrict__ x,
+                                                  T* __restrict__ r, double* __restrict__ part) {
+  const int i = blockIdx.x * kBX + threadIdx.x;
+  const int j = blockIdx.y * kBY + threadIdx.y;
+  double s2 = 0.0;
+  if (i <= L.n && j <= L.n) {
+    const int v = j * L.ld + i;
+    T ay, al;
+    apply_at(L, i, j, x, ay, al);
+    T ry, rl;
+    if (HAS_F) {
+      ry = f[v] - ay;
+      rl = f[L.V + v] - al;
+    } else {
+      ry = ay;
+      rl = al;
+    }
+    r[v] = ry;
+    r[L.V + v] = rl;
+    if (NORM) s2 = (double)ry * (double)ry + (double)rl * (double)rl;
+  }
+  if (NORM) block_sum_store(s2, &part[blockIdx.y * gridDim.x + blockIdx.x]);
+}
+
+template <typename T>
+__global__ __launch_bounds__(kNT) void k_rhs(Lev L, const double* __restrict__ yd, T* __restrict__ f) {
+  const int i = blockIdx.x * kBX + threadIdx.x;
+  const int j = blockIdx.y * kBY + threadIdx.y;
+  if (i > L.n || j > L.n) return;
+  const int v = j * L.ld + i;
+  double s = 0.0;
+  if (i >= 1 && i < L.n && j >= 1 && j < L.n) {
+    const int ld = L.ld;
+    s = L.Mc * yd[v] + L.Mo * ((yd[v + 1] + yd[v - 1] + yd[v + ld] + yd[v - ld]) + (yd[v + ld + 1] + yd[v - ld - 1]));
+  } else {
+    double M[kNDir], K[kNDir];
+    coef_MK(L, i, j, M, K);
+#pragma unroll
+    for (int d = 0; d < kNDir; d++) {
+      const int ii = i + kDI[d], jj = j + kDJ[d];
+      if (!inside(L, ii, jj)) continue;
+      s += M[d] * yd[jj * L.ld + ii];
+    }
+  }
+  f[v] = (T)s;
+  f[L.V + v] = (T)0;
+}
+
+// Alg. 1, first loop, fused with x += p: p_i = tau (A^T L^{-1} r)_i / L_ii
+template <typename T>
+__global__ __launch_bounds__(kNT) void k_ne_p(Lev L, T* __restrict__ x, const T* __restrict__ r, T* __restrict__ p) {
+  const int i = blockIdx.x * kBX + threadIdx.x;
+  const int j = blockIdx.y * kBY + threadIdx.y;
+  if (i > L.n || j > L.n) return;
+  const int v = j * L.ld + i;
+  T qy, ql, wv, nyi, nli;
+  gather_q(L, i, j, r, qy, ql, wv, nyi, nli);
+  const T tau = (T)L.tau;
+  const T py = tau * qy * wv;
+  const T pl = tau * ql * ((T)L.alpha * wv);
+  p[v] = py;
+  p[L.V + v] = pl;
+  x[v] += py;
+  x[L.V + v] += pl;
+}
+
+// Alg. 1, second loop: r -= A p
+template <typename T>
+__global__ __launch_bounds__(kNT) void k_ne_r(Lev L, const T* __restrict__ p, T* __restrict__ r) {
+  const int i = blockIdx.x * kBX + threadIdx.x;
+  const int j = blockIdx.y * kBY + threadIdx.y;
+  if (i > L.n || j > L.n) return;
+  const int v = j * L.ld + i;
+  T ay, al;
+  apply_at(L, i, j, p, ay, al);
+  r[v] -= ay;
+  r[L.V + v] -= al;
+}
+
+// first vertex of colour c in row j: (i + 2 j) mod 7 == c
+__device__ inline int colour_start(int c, int j) { return ((c - 2 * j) % 7 + 7) % 7; }
+
+// Alg. 2 restricted to the vertices of one colour.  Their closed
+// neighbourhoods are disjoint, so every lane gathers, updates and scatters
+// without conflicts; both unknowns of a vertex use one residual snapshot.
+template <typename T>
+__global__ __launch_bounds__(kNT) void k_lsgs_phase(Lev L, int c, T* __restrict__ x, T* __restrict__ r) {
+  const int t = blockIdx.x * kBX + threadIdx.x;
+  const int j = blockIdx.y * kBY + threadIdx.y;
+  if (j > L.n) return;
+  const int i = colour_start(c, j) + 7 * t;
+  if (i > L.n) return;
+  const int v = j * L.ld + i;
+  T qy, ql, wv, nyi, nli;
+  gather_q(L, i, j, r, qy, ql, wv, nyi, nli);
+  const T py = qy * nyi, pl = ql * nli;
+  x[v] += py;
+  x[L.V + v] += pl;
+  scatter_r(L, i, j, py, pl, r);
+}
+
+// collective point Gauss-Seidel on one colour: solve the 2x2 system
+// [[M_vv, K_vv], [K_vv, -alpha^-1 M_vv]] d = (r^y_v, r^l_v), x += d, r -= A d
+template <typename T>
+__global__ __launch_bounds__(kNT) void k_cgs_phase(Lev L, int c, T* __restrict__ x, T* __restrict__ r) {
+  const int t = blockIdx.x * kBX + threadIdx.x;
+  const int j = blockIdx.y * kBY + threadIdx.y;
+  if (j > L.n) return;
+  const int i = colour_start(c, j) + 7 * t;
+  if (i > L.n) return;
+  const int v = j * L.ld + i;
+  T mvv, kvv;
+  if (i >= 1 && i < L.n && j >= 1 && j < L.n) {
+    mvv = (T)L.Mc;
+    kvv = (T)L.Kc;
+  } else {
+    const int cc = cls3(i, L.n) * 3 + cls3(j, L.n);
+    mvv = (T)L.tab->M[cc][0];
+    kvv = (T)L.tab->K[cc][0];
+  }
+  const T b11 = mvv, b12 = kvv, b21 = kvv, b22 = -(T)L.ainv * mvv;
+  const T det = b11 * b22 - b12 * b21;
+  const T ry = r[v], rl = r[L.V + v];
+  const T dy = (b22 * ry - b12 * rl) / det;
+  const T dl = (b11 * rl - b21 * ry) / det;
+  x[v] += dy;
+  x[L.V + v] += dl;
+  scatter_r(L, i, j, dy, dl, r);
+}
+
+// f_c = P^T r: coarse vertex (I, J) collects the fine residual at (2I, 2J)
+// with weight 1 and at its six lattice neighbours with weight 1/2.
+template <typename T>
+__global__ __launch_bounds__(kNT) void k_restrict(Lev Lf, Lev Lc, const T* __restrict__ r, T* __restrict__ fc,
+                                                  T* __restrict__ xc_zero, T* __restrict__ rc_copy) {
+  const int I = blockIdx.x * kBX + threadIdx.x;
+  const int J = blockIdx.y * kBY + threadIdx.y;
+  if (I > Lc.n || J > Lc.n) return;
+  const int a = 2 * I, b = 2 * J;
+  const int u = b * Lf.ld + a;
+  const T* ry = r;
+  const T* rl = r + Lf.V;
+  T hy = 0, hl = 0;
+  if (a >= 1 && a < Lf.n && b >= 1 && b < Lf.n) {
+    const int ld = Lf.ld;
+    hy = (ry[u + 1] + ry[u - 1] + ry[u + ld] + ry[u - ld]) + (ry[u + ld + 1] + ry[u - ld - 1]);
+    hl = (rl[u + 1] + rl[u - 1] + rl[u + ld] + rl[u - ld]) + (rl[u + ld + 1] + rl[u - ld - 1]);
+  } else {
+#pragma unroll
+    for (int d = 1; d < kNDir; d++) {
+      const int aa = a + kDI[d], bb = b + kDJ[d];
+      if (!inside(Lf, aa, bb)) continue;
+      hy += ry[bb * Lf.ld + aa];
+      hl += rl[bb * Lf.ld + aa];
+    }
+  }
+  const int w = J * Lc.ld + I;
+  const T gy = ry[u] + (T)0.5 * hy, gl = rl[u] + (T)0.5 * hl;
+  fc[w] = gy;
+  fc[Lc.V + w] = gl;
+  if (xc_zero) {
+    xc_zero[w] = (T)0;
+    xc_zero[Lc.V + w] = (T)0;
+  }
+  if (rc_copy) {
+    rc_copy[w] = gy;
+    rc_copy[Lc.V + w] = gl;
+  }
+}
+
+// x += P x_c: P1 interpolation; fine vertices on coarse edges (horizontal,
+// vertical, or the (I,J)-(I+1,J+1) diagonal) take the mean of the endpoints.
+template <typename T>
+__global__ __launch_bounds__(kNT) void k_prolong_add(Lev Lf, Lev Lc, const T* __restrict__ xc, T* __restrict__ x) {
+  const int a = blockIdx.x * kBX + threadIdx.x;
+  const int b = blockIdx.y * kBY + threadIdx.y;
+  if (a > Lf.n || b > Lf.n) return;
+  const int I0 = a >> 1, J0 = b >> 1;
+  const int I1 = (a + 1) >> 1, J1 = (b + 1) >> 1;
+  const int w0 = J0 * Lc.ld + I0, w1 = J1 * Lc.ld + I1;
+  const int u = b * Lf.ld + a;
+  T vy, vl;
+  if (w0 == w1) {
+    vy = xc[w0];
+    vl = xc[Lc.V + w0];
+  } else {
+    vy = (T)0.5 * (xc[w0] + xc[w1]);
+    vl = (T)0.5 * (xc[Lc.V + w0] + xc[Lc.V + w1]);
+  }
+  x[u] += vy;
+  x[Lf.V + u] += vl;
+}
+
+// x = A_{k0}^{-1} f with the FP64 LU factors (row pivots piv) of A_{k0}
+template <typename T>
+__global__ __launch_bounds__(256) void k_coarse_solve(int N, const double* __restrict__ lu, const int* __restrict__ piv,
+                                                      const T* __restrict__ f, T* __restrict__ x) {
+  __shared__ double b[512];
+  const int tid = threadIdx.x;
+  for (int i = tid; i < N; i += blockDim.x) b[i] = (double)f[i];
+  __syncthreads();
+  if (tid == 0)
+    for (int k = 0; k < N; k++)
+      if (piv[k] != k) {
+        const double t = b[k];
+        b[k] = b[piv[k]];
+        b[piv[k]] = t;
+      }
+  __syncthreads();
+  for (int k = 0; k < N; k++) {  // unit lower triangular
+    const double bk = b[k];
+    for (int i = k + 1 + tid; i < N; i += blockDim.x) b[i] -= lu[(size_t)i * N + k] * bk;
+    __syncthreads();
+  }
+  for (int k = N - 1; k >= 0; k--) {  // upper triangular
+    if (tid == 0) b[k] /= lu[(size_t)k * N + k];
+    __syncthreads();
+    const double bk = b[k];
+    for (int i = tid; i < k; i += blockDim.x) b[i] -= lu[(size_t)i * N + k] * bk;
+    __syncthreads();
+  }
+  for (int i = tid; i < N; i += blockDim.x) x[i] = (T)b[i];
+}
+
+__global__ __launch_bounds__(256) void k_sum(const double* __restrict__ part, int n, double* __restrict__ out) {
+  __shared__ double sh[4];
+  const int tid = threadIdx.x;
+  double s = 0.0;
+  for (int k = tid; k < n; k += 256) s += part[k];
+  s = wave_sum(s);
+  if ((tid & 63) == 0) sh[tid >> 6] = s;
+  __syncthreads();
+  if (tid == 0) *out = (sh[0] + sh[1]) + (sh[2] + sh[3]);
+}
+
+__global__ __launch_bounds__(256) void k_sumsq(const double* __restrict__ v, size_t n, double* __restrict__ part) {
+  __shared__ double sh[4];
+  double s = 0.0;
+  for (size_t k = blockIdx.x * 256 + threadIdx.x; k < n; k += (size_t)gridDim.x * 256) s += v[k] * v[k];
+  s = wave_sum(s);
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) part[blockIdx.x] = (sh[0] + sh[1]) + (sh[2] + sh[3]);
+}
+
+// scale of a refinement step: s = ||r||_2 (from its square on the device), 1 if zero
+__device__ inline double ir_scale(const double* nrm2) {
+  const double q = *nrm2;
+  return q > 0.0 ? sqrt(q) : 1.0;
+}
+
+__global__ void k_to_f32_scaled(const double* __restrict__ r, size_t n, const double* __restrict__ nrm2,
+                                float* __restrict__ out, float* __restrict__ out2) {
+  const double inv = 1.0 / ir_scale(nrm2);
+  for (size_t k = blockIdx.x * (size_t)blockDim.x + threadIdx.x; k < n; k += (size_t)gridDim.x * blockDim.x) {
+    const float v = (float)(r[k] * inv);
+    out[k] = v;
+    if (out2) out2[k] = v;
+  }
+}
+
+__global__ void k_axpy_f32(const float* __restrict__ c, size_t n, const double* __restrict__ nrm2,
+                           double* __restrict__ x) {
+  const double scale = ir_scale(nrm2);
+  for (size_t k = blockIdx.x * (size_t)blockDim.x + threadIdx.x; k < n; k += (size_t)gridDim.x * blockDim.x)
+    x[k] += scale * (double)c[k];
+}
+
+__global__ void k_zero_f32(float* __restrict__ v, size_t n) {
+  for (size_t k = blockIdx.x * (size_t)blockDim.x + threadIdx.x; k < n; k += (size_t)gridDim.x * blockDim.x) v[k] = 0.f;
+}
+
+inline dim3 grid_vertices(int n) { return dim3((n + 1 + kBX - 1) / kBX, (n + 1 + kBY - 1) / kBY); }
+inline dim3 grid_colour(int n) { return dim3(((n + 1 + 6) / 7 + kBX - 1) / kBX, (n + 1 + kBY - 1) / kBY); }
+const dim3 kBlock(kBX, kBY);
+
+}  // namespace
+
+// ------------------------------------------------------------------ launchers
+
+template <typename T>
+hipError_t launch_residual(const Lev& L, const T* f, const T* x, T* r, double* part, int* nblocks, hipStream_t s) {
+  const dim3 g = grid_vertices(L.n);
+  if (nblocks) *nblocks = (int)(g.x * g.y);
+  if (part)
+    hipLaunchKernelGGL((k_residual<T, true, true>), g, kBlock, 0, s, L, f, x, r, part);
+  else
+    hipLaunchKernelGGL((k_residual<T, true, false>), g, kBlock, 0, s, L, f, x, r, part);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_apply(const Lev& L, const T* x, T* y, hipStream_t s) {
+  hipLaunchKernelGGL((k_residual<T, false, false>), grid_vertices(L.n), kBlock, 0, s, L, (const T*)nullptr, x, y,
+                     (double*)nullptr);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_rhs(const Lev& L, const double* yd, T* f, hipStream_t s) {
+  hipLaunchKernelGGL((k_rhs<T>), grid_vertices(L.n), kBlock, 0, s, L, yd, f);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_ne(const Lev& L, T* x, T* r, T* p, hipStream_t s) {
+  hipLaunchKernelGGL((k_ne_p<T>), grid_vertices(L.n), kBlock, 0, s, L, x, (const T*)r, p);
+  hipLaunchKernelGGL((k_ne_r<T>), grid_vertices(L.n), kBlock, 0, s, L, (const T*)p, r);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_lsgs_phase(const Lev& L, int colour, T* x, T* r, hipStream_t s) {
+  hipLaunchKernelGGL((k_lsgs_phase<T>), grid_colour(L.n), kBlock, 0, s, L, colour, x, r);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_cgs_phase(const Lev& L, int colour, T* x, T* r, hipStream_t s) {
+  hipLaunchKernelGGL((k_cgs_phase<T>), grid_colour(L.n), kBlock, 0, s, L, colour, x, r);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_restrict(const Lev& Lf, const Lev& Lc, const T* r, T* fc, T* xc_zero, T* rc_copy, hipStream_t s) {
+  hipLaunchKernelGGL((k_restrict<T>), grid_vertices(Lc.n), kBlock, 0, s, Lf, Lc, r, fc, xc_zero, rc_copy);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_prolong_add(const Lev& Lf, const Lev& Lc, const T* xc, T* x, hipStream_t s) {
+  hipLaunchKernelGGL((k_prolong_add<T>), grid_vertices(Lf.n), kBlock, 0, s, Lf, Lc, xc, x);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_coarse_solve(int N, const double* lu, const int* piv, const T* f, T* x, hipStream_t s) {
+  if (N > 512) return hipErrorInvalidValue;
+  hipLaunchKernelGGL((k_coarse_solve<T>), dim3(1), dim3(256), 0, s, N, lu, piv, f, x);
+  return hipGetLastError();
+}
+
+hipError_t launch_sum(const double* part, int n, double* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_sum, dim3(1), dim3(256), 0, s, part, n, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_sumsq(const double* v, size_t n, double* part, int* nblocks, hipStream_t s) {
+  int nb = (int)((n + 255) / 256);
+  if (nb > 1024) nb = 1024;
+  if (nb < 1) nb = 1;
+  *nblocks = nb;
+  hipLaunchKernelGGL(k_sumsq, dim3(nb), dim3(256), 0, s, v, n, part);
+  return hipGetLastError();
+}
+
+static int grid1d(size_t n) {
+  size_t g = (n + 255) / 256;
+  if (g > 4096) g = 4096;
+  return g < 1 ? 1 : (int)g;
+}
+
+hipError_t launch_to_f32_scaled(const double* r, size_t n, const double* nrm2, float* out, float* out2, hipStream_t s) {
+  hipLaunchKernelGGL(k_to_f32_scaled, dim3(grid1d(n)), dim3(256), 0, s, r, n, nrm2, out, out2);
+  return hipGetLastError();
+}
+
+hipError_t launch_axpy_f32(const float* c, size_t n, const double* nrm2, double* x, hipStream_t s) {
+  hipLaunchKernelGGL(k_axpy_f32, dim3(grid1d(n)), dim3(256), 0, s, c, n, nrm2, x);
+  return hipGetLastError();
+}
+
+hipError_t launch_zero_f32(float* v, size_t n, hipStream_t s) {
+  hipLaunchKernelGGL(k_zero_f32, dim3(grid1d(n)), dim3(256), 0, s, v, n);
+  return hipGetLastError();
+}
+
+#define MGK_INSTANTIATE(T)                                                                                          \
+  template hipError_t launch_residual<T>(const Lev&, const T*, const T*, T*, double*, int*, hipStream_t);         \
+  template hipError_t launch_apply<T>(const Lev&, const T*, T*, hipStream_t);                                      \
+  template hipError_t launch_rhs<T>(const Lev&, const double*, T*, hipStream_t);                                   \
+  template hipError_t launch_ne<T>(const Lev&, T*, T*, T*, hipStream_t);                                           \
+  template hipError_t launch_lsgs_phase<T>(const Lev&, int, T*, T*, hipStream_t);                                  \
+  template hipError_t launch_cgs_phase<T>(const Lev&, int, T*, T*, hipStream_t);                                   \
+  template hipError_t launch_restrict<T>(const Lev&, const Lev&, const T*, T*, T*, T*, hipStream_t);              \
+  template hipError_t launch_prolong_add<T>(const Lev&, const Lev&, const T*, T*, hipStream_t);                    \
+  template hipError_t launch_coarse_solve<T>(int, const double*, const int*, const T*, T*, hipStream_t);
+
+MGK_INSTANTIATE(double)
+MGK_INSTANTIATE(float)
+
+}  // namespace mgk

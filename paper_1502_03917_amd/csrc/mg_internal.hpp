@@ -1,0 +1,77 @@
+// Internal declarations shared by the HIP kernels and the host orchestration
+// of libmgkkt (not part of the public C ABI, see include/mgkkt.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+
+namespace mgk {
+
+// Neighbour offsets of the 7-point P1 stencil on the mesh whose squares are
+// split along the (i,j)-(i+1,j+1) diagonal: the vertex itself, E, W, N, S,
+// NE and SW.  Opposite directions are d and d^1 for d >= 1 (1/2, 3/4, 5/6).
+constexpr int kNDir = 7;
+constexpr int kDI[kNDir] = {0, 1, -1, 0, 0, 1, -1};
+constexpr int kDJ[kNDir] = {0, 0, 0, 1, -1, 1, -1};
+
+// Boundary tables of one level (device memory).  Vertex classes:
+//   3x3 classes  c3(i)*3 + c3(j), c3 = 0 (index 0), 1 (inside), 2 (index n);
+//   5x5 classes  c5(i)*5 + c5(j), c5 = 0, 1, 2 (inside), 3 (n-1), 4 (n).
+// Coefficients towards neighbours outside the square are zero.
+struct Tab {
+  double M[9][kNDir];  // M_{v, v+d}
+  double K[9][kNDir];  // K_{v, v+d}, K = Laplacian stiffness + M
+  double Winv[9];      // 1 / W_v with W = diag(M + sqrt(alpha) K)
+  double Nyi[25];      // 1 / (N_k)_{y_v y_v}
+  double Nli[25];      // 1 / (N_k)_{l_v l_v}
+};
+
+// Scalars of one level, passed by value to every kernel.
+struct Lev {
+  int n;    // cells per side (2^level)
+  int ld;   // vertices per row, n + 1
+  int V;    // vertices, (n+1)^2; field offset of lambda
+  double alpha, ainv, tau;
+  double Mc, Mo;      // interior M: centre, each of the six neighbours
+  double Kc, Ka, Kd;  // interior K: centre, E/W/N/S, NE/SW
+  double Winv;        // interior 1 / W
+  double Nyi, Nli;    // 1/N for vertices at distance >= 2 from the boundary
+  const Tab* tab;     // device pointer
+};
+
+__host__ __device__ inline int cls3(int i, int n) { return i == 0 ? 0 : (i == n ? 2 : 1); }
+__host__ __device__ inline int cls5(int i, int n) {
+  return i <= 1 ? i : (i >= n - 1 ? 4 - (n - i) : 2);
+}
+
+// ---- kernel launchers (kernels.hip); all enqueue on stream s ----------------
+template <typename T>
+hipError_t launch_residual(const Lev& L, const T* f, const T* x, T* r, double* part, int* nblocks, hipStream_t s);
+template <typename T>
+hipError_t launch_apply(const Lev& L, const T* x, T* y, hipStream_t s);
+template <typename T>
+hipError_t launch_rhs(const Lev& L, const double* yd, T* f, hipStream_t s);
+template <typename T>
+hipError_t launch_ne(const Lev& L, T* x, T* r, T* p, hipStream_t s);
+template <typename T>
+hipError_t launch_lsgs_phase(const Lev& L, int colour, T* x, T* r, hipStream_t s);
+template <typename T>
+hipError_t launch_cgs_phase(const Lev& L, int colour, T* x, T* r, hipStream_t s);
+template <typename T>
+hipError_t launch_restrict(const Lev& Lf, const Lev& Lc, const T* r, T* fc, T* xc_zero, T* rc_copy, hipStream_t s);
+template <typename T>
+hipError_t launch_prolong_add(const Lev& Lf, const Lev& Lc, const T* xc, T* x, hipStream_t s);
+template <typename T>
+hipError_t launch_coarse_solve(int N, const double* lu, const int* piv, const T* f, T* x, hipStream_t s);
+
+hipError_t launch_sum(const double* part, int n, double* out, hipStream_t s);
+hipError_t launch_sumsq(const double* v, size_t n, double* part, int* nblocks, hipStream_t s);
+
+// FP32-preconditioned iterative refinement glue
+// refinement scale s = sqrt(*nrm2) read on the device (1 if the norm is zero)
+hipError_t launch_to_f32_scaled(const double* r, size_t n, const double* nrm2, float* out, float* out2, hipStream_t s);
+hipError_t launch_axpy_f32(const float* c, size_t n, const double* nrm2, double* x, hipStream_t s);
+hipError_t launch_zero_f32(float* v, size_t n, hipStream_t s);
+
+}  // namespace mgk

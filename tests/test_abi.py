@@ -1,0 +1,95 @@
+"""C-ABI contract checks that need no GPU: the library loads, exports every
+symbol its header declares, and rejects invalid arguments before any HIP call."""
+import ctypes
+import math
+import os
+import re
+
+import pytest
+
+import paper_1502_03917_amd as mg
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "mgkkt.h")
+
+
+def _declared():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(mg_[a-z0-9_]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_symbol():
+    L = mg.lib()
+    names = _declared()
+    assert "mg_setup" in names and "mg_solve" in names and "mg_cycle" in names
+    missing = [n for n in names if not hasattr(L, n)]
+    assert not missing, missing
+
+
+def test_default_opts():
+    o = mg.default_opts("poisson")
+    assert (o.smoother, o.nu1, o.nu2, o.gamma, o.coarse_level, o.precision) == (mg.MG_LSGS, 2, 2, 1, 1, mg.MG_FP64)
+    assert o.tau == pytest.approx(0.4) and o.max_cycles == 200 and o.inner_cycles == 1
+    assert mg.default_opts("stokes").tau == pytest.approx(0.35)
+
+
+def _setup(level=5, alpha=1e-2, problem=0, **kw):
+    L = mg.lib()
+    o = L.mg_default_opts(problem)
+    for k, v in kw.items():
+        setattr(o, k, v)
+    h = ctypes.c_void_p()
+    st = L.mg_setup(level, alpha, problem, ctypes.byref(o), ctypes.byref(h))
+    return st, h
+
+
+@pytest.mark.parametrize("level", [-1, 0, 1, 13, 40])
+def test_setup_rejects_levels(level):
+    assert _setup(level=level)[0] == mg.MG_EINVAL
+
+
+@pytest.mark.parametrize("alpha", [0.0, -1.0, math.nan, math.inf, -math.inf])
+def test_setup_rejects_alpha(alpha):
+    st, h = _setup(alpha=alpha)
+    assert st == mg.MG_EINVAL and not h.value
+
+
+@pytest.mark.parametrize("field,value", [("smoother", 4), ("smoother", -1), ("gamma", 0), ("gamma", 3),
+                                         ("tau", 2.5), ("tau", math.nan), ("coarse_level", 0),
+                                         ("coarse_level", 4), ("precision", 2), ("nu1", -1), ("max_cycles", -5),
+                                         ("inner_cycles", 0)])
+def test_setup_rejects_options(field, value):
+    assert _setup(**{field: value})[0] == mg.MG_EINVAL
+
+
+def test_setup_rejects_level_not_above_coarse():
+    assert _setup(level=3, coarse_level=3)[0] == mg.MG_EINVAL
+
+
+def test_setup_rejects_bad_problem_and_null_out():
+    L = mg.lib()
+    assert _setup(problem=7)[0] == mg.MG_EINVAL
+    assert L.mg_setup(5, 1.0, 0, None, None) == mg.MG_EINVAL
+
+
+def test_null_context_calls():
+    L = mg.lib()
+    assert L.mg_vec_len(None) == 0
+    assert L.mg_level_len(None, 3) == 0
+    assert L.mg_last_error(None) == b"no context"
+    assert L.mg_cycle(None, None, None, None) == mg.MG_EINVAL
+    assert L.mg_solve(None, None, None, 1e-10, None, None, None) == mg.MG_EINVAL
+    assert L.mg_rhs(None, None, None, None) == mg.MG_EINVAL
+    assert L.mg_smooth(None, 3, None, None, 1, None) == mg.MG_EINVAL
+    assert L.mg_timing_enable(None, 1) == mg.MG_EINVAL
+    L.mg_destroy(None)
+
+
+def test_strerror_covers_all_codes():
+    L = mg.lib()
+    texts = {st: L.mg_strerror(st).decode() for st in range(mg.MG_EUNSUPPORTED, 1)}
+    assert texts[mg.MG_OK] == "success"
+    assert len(set(texts.values())) == len(texts)
+    assert L.mg_strerror(5) == b"unknown status"
+    assert L.mg_strerror(-99) == b"unknown status"

@@ -1,0 +1,223 @@
+"""GPU parity: every kernel and every cycle of the HIP path against the FP64
+CPU oracle on the same seeded inputs (through the C ABI)."""
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+
+pytestmark = pytest.mark.gpu
+
+ALPHAS = [1.0, 1e-2, 1e-8]
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+
+    assert torch.cuda.is_available(), "GPU tests need a visible GPU"
+    return torch
+
+
+def _mg():
+    import paper_1502_03917_amd as mg
+
+    return mg
+
+
+def _dev(torch, a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).cuda()
+
+
+def _host(t):
+    import torch
+
+    torch.cuda.synchronize()
+    return t.detach().cpu().numpy()
+
+
+def _relmax(a, b):
+    return np.abs(a - b).max() / max(np.abs(b).max(), 1e-300)
+
+
+@pytest.mark.parametrize("alpha", ALPHAS)
+@pytest.mark.parametrize("level", [3, 6])
+def test_stencil_kernels(torch_cuda, level, alpha):
+    torch = torch_cuda
+    mg = _mg()
+    s = mg.Solver(level, alpha)
+    h = oracle.Hierarchy(level, alpha, coarse=1)
+    n = h.ndof()
+    x = workloads.uniform(n, 21)
+    f = workloads.uniform(n, 22)
+    # A x and f - A x
+    Ax = h.matrix("A") @ x
+    assert _relmax(_host(s.apply(_dev(torch, x))), Ax) < 1e-14
+    r_ref = h.residual(f, x)
+    r_gpu, nrm = s.residual(_dev(torch, f), _dev(torch, x), norm=True)
+    assert _relmax(_host(r_gpu), r_ref) < 1e-13
+    assert nrm == pytest.approx(np.linalg.norm(r_ref), rel=1e-13)
+    # right-hand side (M y_D; 0)
+    yd = workloads.desired_state(level, 1)
+    assert _relmax(_host(s.rhs(_dev(torch, yd))), h.rhs(yd)) < 1e-14
+    # transfers between level and level-1
+    fc_ref = np.concatenate([h.matrix("P").T @ r_ref[: n // 2], h.matrix("P").T @ r_ref[n // 2:]])
+    assert _relmax(_host(s.restrict(_dev(torch, r_ref))), fc_ref) < 1e-14
+    nc = h.ndof(level - 1)
+    xc = workloads.uniform(nc, 23)
+    P = h.matrix("P")
+    xp_ref = x + np.concatenate([P @ xc[: nc // 2], P @ xc[nc // 2:]])
+    xg = _dev(torch, x)
+    s.prolong_add(_dev(torch, xc), xg)
+    assert _relmax(_host(xg), xp_ref) < 1e-15
+
+
+@pytest.mark.parametrize("alpha", ALPHAS)
+@pytest.mark.parametrize("smoother", ["ne", "lsgs", "slsgs", "cgs"])
+@pytest.mark.parametrize("level", [3, 6])
+def test_smoothing_step(torch_cuda, level, alpha, smoother):
+    torch = torch_cuda
+    mg = _mg()
+    s = mg.Solver(level, alpha, smoother=smoother)
+    h = oracle.Hierarchy(level, alpha, coarse=1)
+    n = h.ndof()
+    x = workloads.uniform(n, 31)
+    f = workloads.uniform(n, 32)
+    r = h.residual(f, x)
+    xg, rg = _dev(torch, x), _dev(torch, r)
+    xo, ro = x.copy(), r.copy()
+    for _ in range(2):
+        s.smooth(xg, rg, steps=1)
+        h.smooth(xo, ro, smoother=smoother, order="col7")
+    assert _relmax(_host(xg), xo) < 1e-13
+    assert _relmax(_host(rg), ro) < 1e-12
+
+
+@pytest.mark.parametrize("alpha", ALPHAS)
+@pytest.mark.parametrize("coarse", [1, 2, 3])
+def test_coarse_solve(torch_cuda, alpha, coarse):
+    torch = torch_cuda
+    mg = _mg()
+    s = mg.Solver(coarse + 2, alpha, coarse_level=coarse)
+    h = oracle.Hierarchy(coarse + 2, alpha, coarse=coarse)
+    b = workloads.uniform(h.ndof(coarse), 41)
+    ref = h.coarse_solve(b)
+    got = _host(s.coarse_solve(_dev(torch, b)))
+    A = h.matrix("A", coarse).toarray()
+    # both are backward stable FP64 LU solves of the same matrix
+    assert np.linalg.norm(A @ got - b) <= 1e-13 * np.linalg.norm(A, 2) * np.linalg.norm(got)
+    assert np.linalg.norm(got - ref) <= 1e-11 * np.linalg.norm(ref)
+
+
+CYCLE_CASES = [
+    (5, 1e-2, "lsgs", 1),
+    (5, 1e-2, "ne", 1),
+    (5, 1.0, "lsgs", 2),
+    (5, 1e-8, "lsgs", 1),
+    (7, 1e-4, "lsgs", 1),
+    (7, 1e-4, "ne", 1),
+    (7, 1.0, "slsgs", 1),
+    (7, 1e-8, "cgs", 1),
+    (8, 1e-6, "lsgs", 2),
+]
+
+
+@pytest.mark.parametrize("level,alpha,smoother,gamma", CYCLE_CASES)
+def test_cycle_parity(torch_cuda, level, alpha, smoother, gamma):
+    torch = torch_cuda
+    mg = _mg()
+    nu = 1 if smoother == "slsgs" else 2
+    s = mg.Solver(level, alpha, smoother=smoother, gamma=gamma, nu1=nu, nu2=nu)
+    h = oracle.Hierarchy(level, alpha, coarse=1)
+    yd = workloads.desired_state(level, 1)
+    f = h.rhs(yd)
+    fg = s.rhs(_dev(torch, yd))
+    xg = torch.zeros(h.ndof(), dtype=torch.float64, device="cuda")
+    xo = np.zeros(h.ndof())
+    for m in range(8):
+        s.cycle(fg, xg)
+        h.cycle(f, xo, smoother=smoother, order="col7", gamma=gamma, nu1=nu, nu2=nu)
+        err = np.linalg.norm(_host(xg) - xo) / np.linalg.norm(xo)
+        assert err <= 1e-12, (m, err)
+
+
+@pytest.mark.parametrize("alpha", ALPHAS)
+@pytest.mark.parametrize("smoother", ["ne", "lsgs"])
+def test_solve_parity(torch_cuda, alpha, smoother):
+    torch = torch_cuda
+    mg = _mg()
+    level = 6
+    s = mg.Solver(level, alpha, smoother=smoother)
+    h = oracle.Hierarchy(level, alpha, coarse=1)
+    yd = workloads.desired_state(level, 2)
+    f = h.rhs(yd)
+    xo, it_o, hist = h.solve(f, tol=1e-10, smoother=smoother, order="col7")
+    xg, it_g, rel, st = s.solve(s.rhs(_dev(torch, yd)), tol=1e-10)
+    assert st == mg.MG_OK and rel <= 1e-10
+    assert abs(it_g - it_o) <= 1
+    assert np.linalg.norm(_host(xg) - xo) <= 1e-9 * np.linalg.norm(xo)
+
+
+def test_run_to_run_bitwise(torch_cuda):
+    torch = torch_cuda
+    mg = _mg()
+    level = 7
+    s = mg.Solver(level, 1e-3)
+    yd = _dev(torch, workloads.desired_state(level, 3))
+    f = s.rhs(yd)
+    a, _, _, _ = s.solve(f, tol=1e-10)
+    b, _, _, _ = s.solve(f, tol=1e-10)
+    assert torch.equal(a, b)
+
+
+def test_error_paths(torch_cuda):
+    torch = torch_cuda
+    mg = _mg()
+    level = 6
+    s = mg.Solver(level, 1e-2, max_cycles=2)
+    f = s.rhs(_dev(torch, workloads.desired_state(level, 1)))
+    x, it, rel, st = s.solve(f, tol=1e-10, raise_on_error=False)
+    assert st == mg.MG_ENOTCONV and it == 2 and rel > 1e-10
+    fn = f.clone()
+    fn[5] = float("nan")
+    x, it, rel, st = s.solve(fn, tol=1e-10, raise_on_error=False)
+    assert st == mg.MG_ENAN
+    with pytest.raises(mg.MGError):
+        s.solve(f, tol=-1.0)
+    # an over-damped normal-equation smoother diverges and is reported
+    s2 = mg.Solver(level, 1e-2, smoother="ne", tau=1.99, max_cycles=500)
+    x, it, rel, st = s2.solve(f, tol=1e-10, raise_on_error=False)
+    assert st in (mg.MG_EDIVERGE, mg.MG_ENAN, mg.MG_ENOTCONV)
+
+
+@pytest.mark.parametrize("alpha", [1e-8, 1e-4, 1.0])
+def test_fp32_refinement_reaches_tolerance(torch_cuda, alpha):
+    torch = torch_cuda
+    mg = _mg()
+    level = 8
+    h = oracle.Hierarchy(level, alpha, coarse=1)
+    yd = workloads.desired_state(level, 2)
+    xo, _, _ = h.solve(h.rhs(yd), tol=1e-12, smoother="lsgs", order="col7")
+    s = mg.Solver(level, alpha, precision="fp32_ir")
+    xg, it, rel, st = s.solve(s.rhs(_dev(torch, yd)), tol=1e-10)
+    assert st == mg.MG_OK and rel <= 1e-10
+    assert np.linalg.norm(_host(xg) - xo) <= 1e-8 * np.linalg.norm(xo)
+
+
+def test_full_size_cycle_parity(torch_cuda):
+    # the benchmark's size (2049^2 vertices), one V(2,2) LSGS cycle from zero
+    torch = torch_cuda
+    mg = _mg()
+    level, alpha = 11, 1e-4
+    yd = workloads.desired_state(level, 2)
+    s = mg.Solver(level, alpha)
+    fg = s.rhs(_dev(torch, yd))
+    xg = torch.zeros(s.vec_len(), dtype=torch.float64, device="cuda")
+    s.cycle(fg, xg)
+    xgh = _host(xg)
+    h = oracle.Hierarchy(level, alpha, coarse=1)
+    f = h.rhs(yd)
+    assert _relmax(_host(fg), f) < 1e-14
+    xo = np.zeros(h.ndof())
+    h.cycle(f, xo, smoother="lsgs", order="col7")
+    assert np.linalg.norm(xgh - xo) <= 1e-12 * np.linalg.norm(xo)
