@@ -98,22 +98,23 @@ def main() -> int:
         for _ in range(warmup):
             x.zero_()
             f = s.rhs(yd)
-            s.solve(f, x, tol=args.tol)
+            s.solve(f, x, tol=args.tol, raise_on_error=False)
         torch.cuda.synchronize()
         if timing:
             s.timing_enable(True)
         cycles = 0
         rel = None
+        st = mg.MG_OK
         t0 = time.perf_counter()
         for _ in range(steps):
             x.zero_()
             f = s.rhs(yd)
-            _, it, rel, st = s.solve(f, x, tol=args.tol)
+            _, it, rel, st = s.solve(f, x, tol=args.tol, raise_on_error=False)
             cycles += it * (inner if precision == "fp32_ir" else 1)
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
         out = {"cycles_per_solve": cycles / steps, "ms_per_solve": 1e3 * dt / steps, "relres": rel,
-               "vcycles_per_s": cycles / dt}
+               "vcycles_per_s": cycles / dt, "status": mg.lib().mg_strerror(st).decode()}
         if timing:
             ms, n = s.timing_read()
             s.timing_enable(False)
@@ -125,6 +126,8 @@ def main() -> int:
     log(f"bench: level {args.level}, alpha {args.alpha:g}, {args.smoother}/{args.precision}, "
         f"{args.warmup} warmup + {args.steps} timed solves to {args.tol:g}")
     main_run = run(args.smoother, args.precision, args.alpha, args.steps, args.warmup, timing=True)
+    if main_run["status"] != "success":
+        log(f"bench: the timed solve ended with status '{main_run['status']}' at relres {main_run['relres']:.3e}")
     V = ((1 << args.level) + 1) ** 2
     wbytes = 4 if args.precision == "fp32_ir" else 8
     sweep_bytes = 8 * V * wbytes  # read and write x and r, both fields
@@ -152,6 +155,8 @@ def main() -> int:
         "time_to_tol_ms": main_run["ms_per_solve"],
         "cycles_per_solve": main_run["cycles_per_solve"],
         "final_relres": main_run["relres"],
+        "residual_norm": "L_k^-1 weighted (dual of the paper's L_k error norm)",
+        "solve_status": main_run["status"],
         "unknown_updates_per_s": main_run["vcycles_per_s"] * sum(4 * 2 * ((1 << l) + 1) ** 2 for l in range(2, args.level + 1)),
         "cycle_algorithmic_GBps": main_run["vcycles_per_s"] * cyc_bytes / 1e9,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",

@@ -62,8 +62,20 @@ typedef enum mg_status {
   MG_ENOTCONV = -4,    /* max_cycles reached; x holds the last iterate        */
   MG_ENAN = -5,        /* non-finite residual norm                            */
   MG_EDIVERGE = -6,    /* residual grew above 1e3 times its initial value     */
-  MG_EUNSUPPORTED = -7 /* valid but not provided by this build                */
+  MG_EUNSUPPORTED = -7, /* valid but not provided by this build               */
+  MG_ESTALL = -8        /* residual stagnated: the best relative residual of the last
+                           10 iterates is not half the best of the 10 before (the
+                           rounding floor of the arithmetic); x = last iterate */
 } mg_status;
+
+/* norm of the relative residual ||f - A x|| / ||f|| tested by mg_solve:
+ *  MG_NORM_L2    Euclidean norm of the full block residual
+ *  MG_NORM_LINV  ||r||_{L^-1} = (r^T L_k^-1 r)^{1/2}, L_k = diag(Q_k) of section 2
+ *                (the dual of the norm ||.||_{L_k} in which the paper measures
+ *                convergence).  The Euclidean ratio has an FP64 floor near
+ *                eps h^-2 because x itself is rounded while f = M y_D is O(h^2):
+ *                about 3e-9 at h = 1/2048, above a 1e-10 target. */
+enum mg_norm { MG_NORM_L2 = 0, MG_NORM_LINV = 1 };
 
 typedef struct {
   int smoother;     /* mg_smoother; default MG_LSGS                                  */
@@ -74,6 +86,7 @@ typedef struct {
   int precision;    /* mg_precision; default MG_FP64                                */
   int max_cycles;   /* cap of mg_solve; default 200                                  */
   int inner_cycles; /* FP32 cycles per refinement step (MG_FP32_IR); default 1       */
+  int norm;         /* mg_norm of the stopping test of mg_solve; default MG_NORM_LINV */
 } mg_opts;
 
 /* defaults for a problem (see the field comments) */
@@ -134,11 +147,12 @@ int mg_coarse_solve(mg_ctx *ctx, const double *f, double *x, void *stream);
  * host synchronisation. */
 int mg_cycle(mg_ctx *ctx, const double *f, double *x, void *stream);
 
-/* Iterate from the initial guess in x until ||f - A x||_2 <= tol ||f||_2.
- * cycles_out (may be NULL) receives the number of iterates done, relres_out
- * (may be NULL) the final relative residual.  Synchronises on one norm per
- * iterate.  Returns MG_OK, MG_ENOTCONV (x = last iterate), MG_ENAN,
- * MG_EDIVERGE, or an argument / HIP error.  tol must be > 0. */
+/* Iterate from the initial guess in x until ||f - A x|| <= tol ||f|| in the
+ * context's norm (mg_opts.norm).  cycles_out (may be NULL) receives the number
+ * of iterates done, relres_out (may be NULL) the final relative residual.
+ * Synchronises on one norm per iterate.  Returns MG_OK, MG_ENOTCONV (x = last
+ * iterate), MG_ESTALL (x = last iterate), MG_ENAN, MG_EDIVERGE, or an argument /
+ * HIP error.  tol must be > 0. */
 int mg_solve(mg_ctx *ctx, const double *f, double *x, double tol, int *cycles_out, double *relres_out,
              void *stream);
 

@@ -69,7 +69,7 @@ def _load():
     lib.mgo_smooth_groups.argtypes = [vp, ip, vp, vp, ip, ip, vp, vp]
     lib.mgo_coarse_solve.argtypes = [vp, vp, vp]
     lib.mgo_cycle.argtypes = [vp, ip, ip, ip, dp, ip, ip, ip, vp, vp]
-    lib.mgo_solve.argtypes = [vp, ip, ip, dp, ip, ip, ip, vp, vp, dp, ip, vp]
+    lib.mgo_solve.argtypes = [vp, ip, ip, dp, ip, ip, ip, vp, vp, dp, ip, ip, vp]
     lib.mgo_solve.restype = ip
     _lib = lib
     return lib
@@ -181,14 +181,15 @@ class Hierarchy:
         return x
 
     def solve(self, f, x0=None, tol=1e-10, max_cycles=200, smoother="lsgs", order="col7", tau=None,
-              nu1=2, nu2=2, gamma=1):
-        """Cycles until ||f - A x||_2 <= tol ||f||_2. Returns (x, cycles, history)."""
+              nu1=2, nu2=2, gamma=1, norm="linv"):
+        """Cycles until ||f - A x|| <= tol ||f|| in the Euclidean norm ("l2") or
+        the L_k^{-1} norm ("linv"). Returns (x, cycles, history)."""
         tau = TAU_POISSON if tau is None else tau
         f = np.ascontiguousarray(f, dtype=np.float64)
         x = np.zeros(self.ndof()) if x0 is None else np.array(x0, dtype=np.float64, copy=True)
         hist = np.zeros(max_cycles + 2)
         it = self.lib.mgo_solve(self._h, SMOOTHERS[smoother], ORDERS[order], float(tau), nu1, nu2, gamma,
-                                _ptr(f), _ptr(x), float(tol), max_cycles, _ptr(hist))
+                                _ptr(f), _ptr(x), float(tol), max_cycles, {"l2": 0, "linv": 1}[norm], _ptr(hist))
         n = (max_cycles + 1) if it < 0 else it + 1
         return x, it, hist[:n]
 

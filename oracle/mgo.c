@@ -738,16 +738,24 @@ static double norm2(const double *v, int n) {
   return sqrt(s);
 }
 
+/* Euclidean norm (norm = 0) or (v^T L_k^{-1} v)^{1/2} (norm = 1) */
+static double normL(const mgo_level *L, const double *v, int norm) {
+  if (norm == 0) return norm2(v, L->ndof);
+  double s = 0.0;
+  for (int i = 0; i < L->ndof; i++) s += v[i] * v[i] / L->L[i];
+  return sqrt(s);
+}
+
 int mgo_solve(const mgo_hier *h, int kind, int order, double tau, int nu1, int nu2, int gamma, const double *f,
-              double *x, double tol, int max_cycles, double *hist) {
+              double *x, double tol, int max_cycles, int norm, double *hist) {
   const mgo_level *L = &h->lv[h->fine];
   double *r = (double *)xmalloc((size_t)L->ndof * sizeof(double));
-  double nf = norm2(f, L->ndof);
+  double nf = normL(L, f, norm);
   if (nf == 0.0) nf = 1.0;
   int it = 0;
   for (;; it++) {
     mgo_residual(h, h->fine, f, x, r);
-    double rel = norm2(r, L->ndof) / nf;
+    double rel = normL(L, r, norm) / nf;
     if (hist) hist[it] = rel;
     if (rel <= tol) break;
     if (it == max_cycles) {

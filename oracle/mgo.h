@@ -93,11 +93,12 @@ void mgo_coarse_solve(const mgo_hier *h, const double *f, double *x);
 void mgo_cycle(const mgo_hier *h, int level, int kind, int order, double tau, int nu1, int nu2,
                int gamma, const double *f, double *x);
 
-/* cycles until ||f - A x||_2 <= tol ||f||_2 (or max_cycles).  hist (may be
+/* cycles until ||f - A x|| <= tol ||f|| (or max_cycles), in the Euclidean
+ * norm (norm = 0) or the norm (v^T L_k^{-1} v)^{1/2} (norm = 1).  hist (may be
  * NULL) receives the relative residual before each cycle (max_cycles+1).
  * Returns the number of cycles done, or -1 when max_cycles was hit. */
 int mgo_solve(const mgo_hier *h, int kind, int order, double tau, int nu1, int nu2, int gamma,
-              const double *f, double *x, double tol, int max_cycles, double *hist);
+              const double *f, double *x, double tol, int max_cycles, int norm, double *hist);
 
 #ifdef __cplusplus
 }

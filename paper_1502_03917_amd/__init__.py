@@ -17,7 +17,10 @@ LIB_PATH = os.path.join(_HERE, "libmgkkt.so")
 MG_POISSON, MG_STOKES = 0, 1
 MG_NE, MG_LSGS, MG_SLSGS, MG_CGS = 0, 1, 2, 3
 MG_FP64, MG_FP32_IR = 0, 1
-MG_OK, MG_EINVAL, MG_EHIP, MG_ENOMEM, MG_ENOTCONV, MG_ENAN, MG_EDIVERGE, MG_EUNSUPPORTED = 0, -1, -2, -3, -4, -5, -6, -7
+MG_OK, MG_EINVAL, MG_EHIP, MG_ENOMEM, MG_ENOTCONV, MG_ENAN, MG_EDIVERGE, MG_EUNSUPPORTED, MG_ESTALL = (
+    0, -1, -2, -3, -4, -5, -6, -7, -8)
+MG_NORM_L2, MG_NORM_LINV = 0, 1
+NORMS = {"l2": MG_NORM_L2, "linv": MG_NORM_LINV}
 
 SMOOTHERS = {"ne": MG_NE, "lsgs": MG_LSGS, "slsgs": MG_SLSGS, "cgs": MG_CGS}
 PRECISIONS = {"fp64": MG_FP64, "fp32_ir": MG_FP32_IR}
@@ -35,6 +38,7 @@ class MgOpts(ctypes.Structure):
         ("precision", ctypes.c_int),
         ("max_cycles", ctypes.c_int),
         ("inner_cycles", ctypes.c_int),
+        ("norm", ctypes.c_int),
     ]
 
 
@@ -112,7 +116,7 @@ class Solver:
 
     def __init__(self, level: int, alpha: float, problem: str = "poisson", smoother: str = "lsgs", nu1: int = 2,
                  nu2: int = 2, gamma: int = 1, tau: float | None = None, coarse_level: int = 1,
-                 precision: str = "fp64", max_cycles: int = 200, inner_cycles: int = 1):
+                 precision: str = "fp64", max_cycles: int = 200, inner_cycles: int = 1, norm: str = "linv"):
         L = lib()
         o = L.mg_default_opts(PROBLEMS[problem])
         o.smoother = SMOOTHERS[smoother]
@@ -122,6 +126,7 @@ class Solver:
         o.precision = PRECISIONS[precision]
         o.max_cycles = max_cycles
         o.inner_cycles = inner_cycles
+        o.norm = NORMS[norm]
         h = ctypes.c_void_p()
         st = L.mg_setup(level, float(alpha), PROBLEMS[problem], ctypes.byref(o), ctypes.byref(h))
         if st != MG_OK:
@@ -176,6 +181,8 @@ class Solver:
                 v = SMOOTHERS[v]
             elif k == "precision":
                 v = PRECISIONS[v]
+            elif k == "norm":
+                v = NORMS[v]
             elif k == "tau" and v is None:
                 v = -1.0
             setattr(o, k, v)

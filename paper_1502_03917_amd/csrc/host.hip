@@ -9,6 +9,7 @@
 #include <cstring>
 #include <new>
 #include <string>
+#include <utility>
 #include <vector>
 
 #include "../../include/mgkkt.h"
@@ -21,6 +22,9 @@ namespace {
 
 constexpr int kMaxLevel = 12;
 constexpr int kMaxCoarse = 3;  // coarsest LU of 2 (2^k0+1)^2 <= 162 unknowns
+// mg_solve reports a stall when the best relative residual of the last 10
+// iterates is not below half the best of the 10 before them
+constexpr int kStallWindow = 10;
 
 // ---------------------------------------------------------------- tables
 
@@ -111,6 +115,17 @@ LevelTables make_tables(int level, double alpha, double tau) {
       }
       T.Nyi[ci * 5 + cj] = 1.0 / nyy;
       T.Nli[ci * 5 + cj] = 1.0 / nll;
+      double* blk = T.C5[ci * 5 + cj];
+      for (int d = 0; d < mgk::kNDir; d++) {
+        const int ii = i + mgk::kDI[d], jj = j + mgk::kDJ[d];
+        const bool in = !(ii < 0 || jj < 0 || ii > n || jj > n);
+        blk[d] = in ? M[d] : 0.0;
+        blk[mgk::kNDir + d] = in ? Kl[d] + M[d] : 0.0;
+        blk[2 * mgk::kNDir + d] = in ? 1.0 / W9[mgk::cls3(ii, n) * 3 + mgk::cls3(jj, n)] : 0.0;
+      }
+      blk[3 * mgk::kNDir] = 1.0 / nyy;
+      blk[3 * mgk::kNDir + 1] = 1.0 / nll;
+      blk[3 * mgk::kNDir + 2] = 0.0;
     }
   Lev& L = out.lev;
   L.n = n;
@@ -185,8 +200,9 @@ struct LevelBuf {
   Lev lev{};
   Tab* d_tab = nullptr;
   size_t len = 0;  // 2V
-  double *x = nullptr, *f = nullptr, *r = nullptr, *p = nullptr;
-  float *x32 = nullptr, *f32 = nullptr, *r32 = nullptr, *p32 = nullptr;
+  // r2: second residual buffer; the fused LSGS sweep reads one and writes the other
+  double *x = nullptr, *f = nullptr, *r = nullptr, *r2 = nullptr, *p = nullptr;
+  float *x32 = nullptr, *f32 = nullptr, *r32 = nullptr, *r2_32 = nullptr, *p32 = nullptr;
 };
 
 struct mg_ctx {
@@ -202,6 +218,7 @@ struct mg_ctx {
   double* d_norm = nullptr;  // [0] = ||r||^2 of the latest residual, [1] = ||f||^2
   double* h_norm = nullptr;  // pinned host copy
   bool fp32_ready = false;
+  bool fused = true;  // one kernel per LSGS sweep (else one kernel per colour phase)
   // timing of the finest-level smoothing sweeps
   bool timing = false;
   std::vector<hipEvent_t> ev;  // pairs
@@ -220,7 +237,8 @@ const char* kStatusText[] = {"success",
                              "no convergence within max_cycles",
                              "non-finite residual norm",
                              "residual diverged",
-                             "not supported by this build"};
+                             "not supported by this build",
+                             "residual stagnated at the precision floor"};
 
 int fail(mg_ctx* c, int status, const std::string& msg) {
   if (c) c->err = msg;
@@ -248,6 +266,7 @@ bool valid_opts(const mg_opts* o, int level) {
   if (o->precision != MG_FP64 && o->precision != MG_FP32_IR) return false;
   if (o->max_cycles < 0 || o->max_cycles > 100000) return false;
   if (o->inner_cycles < 1 || o->inner_cycles > 64) return false;
+  if (o->norm != MG_NORM_L2 && o->norm != MG_NORM_LINV) return false;
   return true;
 }
 
@@ -259,10 +278,12 @@ void destroy_impl(mg_ctx* c) {
     (void)hipFree(b.x);
     (void)hipFree(b.f);
     (void)hipFree(b.r);
+    (void)hipFree(b.r2);
     (void)hipFree(b.p);
     (void)hipFree(b.x32);
     (void)hipFree(b.f32);
     (void)hipFree(b.r32);
+    (void)hipFree(b.r2_32);
     (void)hipFree(b.p32);
   }
   (void)hipFree(c->d_lu);
@@ -281,7 +302,10 @@ int alloc_fp32(mg_ctx* c) {
     HIPCHK(c, hipMalloc(&b.x32, bytes));
     HIPCHK(c, hipMalloc(&b.f32, bytes));
     HIPCHK(c, hipMalloc(&b.r32, bytes));
-    if (b.level > c->k0) HIPCHK(c, hipMalloc(&b.p32, bytes));
+    if (b.level > c->k0) {
+      HIPCHK(c, hipMalloc(&b.p32, bytes));
+      HIPCHK(c, hipMalloc(&b.r2_32, bytes));
+    }
   }
   c->fp32_ready = true;
   return MG_OK;
@@ -291,10 +315,10 @@ int alloc_fp32(mg_ctx* c) {
 
 template <typename T>
 struct Work {
-  T *x, *f, *r, *p;
+  T *x, *f, *r, *r2, *p;
 };
-Work<double> work(LevelBuf& b, double*) { return {b.x, b.f, b.r, b.p}; }
-Work<float> work(LevelBuf& b, float*) { return {b.x32, b.f32, b.r32, b.p32}; }
+Work<double> work(LevelBuf& b, double*) { return {b.x, b.f, b.r, b.r2, b.p}; }
+Work<float> work(LevelBuf& b, float*) { return {b.x32, b.f32, b.r32, b.r2_32, b.p32}; }
 
 void timing_begin(mg_ctx* c, hipStream_t s, size_t* slot) {
   if (c->ev_used + 2 > c->ev.size()) {
@@ -318,11 +342,15 @@ void timing_begin(mg_ctx* c, hipStream_t s, size_t* slot) {
   (void)hipEventRecord(c->ev[*slot], s);
 }
 
+// `steps` smoothing steps on level l.  r holds f - A x on entry; the fused
+// LSGS sweeps alternate between r and alt, and r is updated to the buffer
+// holding the current residual on return.
 template <typename T>
-int smooth_steps(mg_ctx* c, int l, T* x, T* r, T* p, int steps, hipStream_t s) {
+int smooth_steps(mg_ctx* c, int l, T* x, T*& r, T* alt, T* p, int steps, hipStream_t s) {
   LevelBuf& b = L_(c, l);
   const Lev& L = b.lev;
   const bool timed = c->timing && l == c->level;
+  const bool fused = c->fused && alt != nullptr;
   for (int it = 0; it < steps; it++) {
     size_t slot = 0;
     if (timed) timing_begin(c, s, &slot);
@@ -331,11 +359,21 @@ int smooth_steps(mg_ctx* c, int l, T* x, T* r, T* p, int steps, hipStream_t s) {
         HIPCHK(c, mgk::launch_ne<T>(L, x, r, p, s));
         break;
       case MG_LSGS:
-        for (int col = 0; col < 7; col++) HIPCHK(c, mgk::launch_lsgs_phase<T>(L, col, x, r, s));
+        if (fused) {
+          HIPCHK(c, mgk::launch_lsgs_sweep<T>(L, 0, x, r, alt, s));
+          std::swap(r, alt);
+        } else {
+          for (int col = 0; col < 7; col++) HIPCHK(c, mgk::launch_lsgs_phase<T>(L, col, x, r, s));
+        }
         break;
       case MG_SLSGS:
-        for (int col = 0; col < 7; col++) HIPCHK(c, mgk::launch_lsgs_phase<T>(L, col, x, r, s));
-        for (int col = 6; col >= 0; col--) HIPCHK(c, mgk::launch_lsgs_phase<T>(L, col, x, r, s));
+        if (fused) {
+          HIPCHK(c, mgk::launch_lsgs_sweep<T>(L, 0, x, r, alt, s));
+          HIPCHK(c, mgk::launch_lsgs_sweep<T>(L, 1, x, alt, r, s));
+        } else {
+          for (int col = 0; col < 7; col++) HIPCHK(c, mgk::launch_lsgs_phase<T>(L, col, x, r, s));
+          for (int col = 6; col >= 0; col--) HIPCHK(c, mgk::launch_lsgs_phase<T>(L, col, x, r, s));
+        }
         break;
       case MG_CGS:
         for (int col = 0; col < 7; col++) HIPCHK(c, mgk::launch_cgs_phase<T>(L, col, x, r, s));
@@ -357,6 +395,8 @@ int coarse_solve_T(mg_ctx* c, const T* f, T* x, hipStream_t s) {
 
 // One iterate on level l for A_l x = f; r is level-l workspace.  If
 // residual_current, r already holds f - A_l x.
+// One iterate on level l for A_l x = f; r is level-l workspace (one of the
+// level's two residual buffers).  If residual_current, r already holds f - A_l x.
 template <typename T>
 int cycle_body(mg_ctx* c, int l, const T* f, T* x, T* r, bool residual_current, hipStream_t s) {
   if (l == c->k0) return coarse_solve_T<T>(c, f, x, s);
@@ -364,9 +404,11 @@ int cycle_body(mg_ctx* c, int l, const T* f, T* x, T* r, bool residual_current, 
   LevelBuf& bc = L_(c, l - 1);
   Work<T> wb = work(b, (T*)nullptr);
   Work<T> wc = work(bc, (T*)nullptr);
+  T* alt = (r == wb.r) ? wb.r2 : wb.r;
   int st;
-  if (!residual_current) HIPCHK(c, mgk::launch_residual<T>(b.lev, f, x, r, nullptr, nullptr, s));
-  if ((st = smooth_steps<T>(c, l, x, r, wb.p, c->o.nu1, s)) != MG_OK) return st;
+  if (!residual_current) HIPCHK(c, mgk::launch_residual<T>(b.lev, f, x, r, nullptr, 0, nullptr, s));
+  if ((st = smooth_steps<T>(c, l, x, r, alt, wb.p, c->o.nu1, s)) != MG_OK) return st;
+  alt = (r == wb.r) ? wb.r2 : wb.r;
   // defect restriction; the coarse iterate starts from zero with r_c = f_c
   const bool coarse_is_k0 = (l - 1 == c->k0);
   HIPCHK(c, mgk::launch_restrict<T>(b.lev, bc.lev, r, wc.f, coarse_is_k0 ? nullptr : wc.x,
@@ -375,15 +417,17 @@ int cycle_body(mg_ctx* c, int l, const T* f, T* x, T* r, bool residual_current, 
     if ((st = cycle_body<T>(c, l - 1, wc.f, wc.x, wc.r, g == 0, s)) != MG_OK) return st;
   }
   HIPCHK(c, mgk::launch_prolong_add<T>(b.lev, bc.lev, wc.x, x, s));
-  HIPCHK(c, mgk::launch_residual<T>(b.lev, f, x, r, nullptr, nullptr, s));
-  return smooth_steps<T>(c, l, x, r, wb.p, c->o.nu2, s);
+  HIPCHK(c, mgk::launch_residual<T>(b.lev, f, x, r, nullptr, 0, nullptr, s));
+  return smooth_steps<T>(c, l, x, r, alt, wb.p, c->o.nu2, s);
 }
+
+int norm_mode(const mg_ctx* c) { return c->o.norm == MG_NORM_LINV ? 2 : 1; }
 
 // ||r||^2 of the fine residual into d_norm[slot] (stream-ordered)
 int residual_norm(mg_ctx* c, const double* f, const double* x, double* r, int slot, hipStream_t s) {
   LevelBuf& b = L_(c, c->level);
   int nb = 0;
-  HIPCHK(c, mgk::launch_residual<double>(b.lev, f, x, r, c->d_part, &nb, s));
+  HIPCHK(c, mgk::launch_residual<double>(b.lev, f, x, r, c->d_part, norm_mode(c), &nb, s));
   HIPCHK(c, mgk::launch_sum(c->d_part, nb, c->d_norm + slot, s));
   return MG_OK;
 }
@@ -424,11 +468,12 @@ mg_opts mg_default_opts(int problem) {
   o.precision = MG_FP64;
   o.max_cycles = 200;
   o.inner_cycles = 1;
+  o.norm = MG_NORM_LINV;
   return o;
 }
 
 const char* mg_strerror(int status) {
-  if (status > 0 || status < MG_EUNSUPPORTED) return "unknown status";
+  if (status > 0 || status < MG_ESTALL) return "unknown status";
   return kStatusText[-status];
 }
 
@@ -466,6 +511,11 @@ int mg_setup(int level, double alpha, int problem, const mg_opts* opts, mg_ctx**
   c->o = opts ? *opts : mg_default_opts(problem);
   if (c->o.tau <= 0.0) c->o.tau = problem == MG_STOKES ? 0.35 : 0.4;
   c->k0 = c->o.coarse_level;
+  {
+    // MGKKT_PHASE_KERNELS=1 selects one launch per colour phase (comparison and testing)
+    const char* e = std::getenv("MGKKT_PHASE_KERNELS");
+    c->fused = !(e && e[0] == '1');
+  }
   int st = MG_OK;
   auto bail = [&](int s) {
     destroy_impl(c);
@@ -497,7 +547,9 @@ int mg_setup(int level, double alpha, int problem, const mg_opts* opts, mg_ctx**
       if (hipMalloc(&b.x, bytes) != hipSuccess || hipMalloc(&b.f, bytes) != hipSuccess) return bail(MG_ENOMEM);
     }
     if (l > c->k0) {
-      if (hipMalloc(&b.r, bytes) != hipSuccess || hipMalloc(&b.p, bytes) != hipSuccess) return bail(MG_ENOMEM);
+      if (hipMalloc(&b.r, bytes) != hipSuccess || hipMalloc(&b.r2, bytes) != hipSuccess ||
+          hipMalloc(&b.p, bytes) != hipSuccess)
+        return bail(MG_ENOMEM);
     }
     const size_t nb = (size_t)((n + 1 + 63) / 64) * (size_t)((n + 1 + 3) / 4);
     if (nb > max_blocks) max_blocks = nb;
@@ -562,11 +614,11 @@ int mg_residual(mg_ctx* ctx, int level, const double* f, const double* x, double
   hipStream_t s = (hipStream_t)stream;
   LevelBuf& b = L_(ctx, level);
   if (!norm_out) {
-    HIPCHK(ctx, mgk::launch_residual<double>(b.lev, f, x, r, nullptr, nullptr, s));
+    HIPCHK(ctx, mgk::launch_residual<double>(b.lev, f, x, r, nullptr, 0, nullptr, s));
     return MG_OK;
   }
   int nb = 0;
-  HIPCHK(ctx, mgk::launch_residual<double>(b.lev, f, x, r, ctx->d_part, &nb, s));
+  HIPCHK(ctx, mgk::launch_residual<double>(b.lev, f, x, r, ctx->d_part, 1, &nb, s));
   HIPCHK(ctx, mgk::launch_sum(ctx->d_part, nb, ctx->d_norm + 2, s));
   HIPCHK(ctx, hipMemcpyAsync(ctx->h_norm + 2, ctx->d_norm + 2, sizeof(double), hipMemcpyDeviceToHost, s));
   HIPCHK(ctx, hipStreamSynchronize(s));
@@ -576,7 +628,13 @@ int mg_residual(mg_ctx* ctx, int level, const double* f, const double* x, double
 
 int mg_smooth(mg_ctx* ctx, int level, double* x, double* r, int steps, void* stream) {
   if (!ctx || !x || !r || steps < 0 || !check_level(ctx, level, false)) return MG_EINVAL;
-  return smooth_steps<double>(ctx, level, x, r, L_(ctx, level).p, steps, (hipStream_t)stream);
+  hipStream_t s = (hipStream_t)stream;
+  LevelBuf& b = L_(ctx, level);
+  double* cur = r;
+  int st = smooth_steps<double>(ctx, level, x, cur, b.r2, b.p, steps, s);
+  if (st != MG_OK) return st;
+  if (cur != r) HIPCHK(ctx, hipMemcpyAsync(r, cur, b.len * sizeof(double), hipMemcpyDeviceToDevice, s));
+  return MG_OK;
 }
 
 int mg_restrict(mg_ctx* ctx, int level, const double* r, double* fc, void* stream) {
@@ -616,10 +674,11 @@ int mg_solve(mg_ctx* ctx, const double* f, double* x, double tol, int* cycles_ou
   hipStream_t s = (hipStream_t)stream;
   LevelBuf& b = L_(ctx, ctx->level);
   int nb = 0;
-  HIPCHK(ctx, mgk::launch_sumsq(f, b.len, ctx->d_part, &nb, s));
+  HIPCHK(ctx, mgk::launch_vnorm(b.lev, f, ctx->d_part, norm_mode(ctx), &nb, s));
   HIPCHK(ctx, mgk::launch_sum(ctx->d_part, nb, ctx->d_norm + 1, s));
   double nf = -1.0, rel0 = -1.0, rel = 0.0;
   int it = 0, st = MG_OK;
+  std::vector<double> hist;
   for (;; it++) {
     if ((st = residual_norm(ctx, f, x, b.r, 0, s)) != MG_OK) return st;
     HIPCHK(ctx, hipMemcpyAsync(ctx->h_norm, ctx->d_norm, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
@@ -632,6 +691,16 @@ int mg_solve(mg_ctx* ctx, const double* f, double* x, double tol, int* cycles_ou
     if (!std::isfinite(rel)) return fail(ctx, MG_ENAN, "non-finite residual norm");
     if (rel <= tol) return MG_OK;
     if (rel > 1e3 * rel0 && rel0 > 0.0) return fail(ctx, MG_EDIVERGE, "residual grew above 1e3 x initial");
+    hist.push_back(rel);
+    if (it + 1 >= 2 * kStallWindow) {
+      double best_new = hist[it], best_old = hist[it - kStallWindow];
+      for (int k = 1; k < kStallWindow; k++) {
+        best_new = std::fmin(best_new, hist[it - k]);
+        best_old = std::fmin(best_old, hist[it - kStallWindow - k]);
+      }
+      if (best_new > 0.5 * best_old)
+        return fail(ctx, MG_ESTALL, "residual stagnated: no factor 2 gained over the last 10 iterates");
+    }
     if (it >= ctx->o.max_cycles) return fail(ctx, MG_ENOTCONV, "max_cycles reached");
     if (ctx->o.precision == MG_FP32_IR)
       st = ir_step(ctx, x, s);

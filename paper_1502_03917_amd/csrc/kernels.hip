@@ -173,7 +173,18 @@ __device__ inline void scatter_r(const Lev& L, int i, int j, T py, T pl, T* __re
 
 // ------------------------------------------------------------------ kernels
 
-template <typename T, bool HAS_F, bool NORM>
+// squared norm contribution of vertex (i, j): Euclidean (mode 1) or weighted
+// by L^{-1} = blockdiag(W^{-1}, alpha W^{-1}) (mode 2)
+template <int MODE>
+__device__ inline double norm_term(const Lev& L, int i, int j, double ry, double rl) {
+  if (MODE == 1) return ry * ry + rl * rl;
+  const double wi = (i >= 1 && i < L.n && j >= 1 && j < L.n) ? L.Winv : L.tab->Winv[cls3(i, L.n) * 3 + cls3(j, L.n)];
+  return wi * (ry * ry + L.alpha * (rl * rl));
+}
+
+// r = f - A x (HAS_F) or r = A x; MODE 1/2 also stores per-block partial sums
+// of the squared Euclidean / L^{-1} norm of r
+template <typename T, bool HAS_F, int MODE>
 __global__ __launch_bounds__(kNT) void k_residual(Lev L, const T* __restrict__ f, const T* __restrict__ x,
                                                   T* __restrict__ r, double* __restrict__ part) {
   const int i = blockIdx.x * kBX + threadIdx.x;
@@ -193,9 +204,22 @@ __global__ __launch_bounds__(kNT) void k_residual(Lev L, const T* __restrict__ f
     }
     r[v] = ry;
     r[L.V + v] = rl;
-    if (NORM) s2 = (double)ry * (double)ry + (double)rl * (double)rl;
+    if (MODE) s2 = norm_term<MODE>(L, i, j, (double)ry, (double)rl);
   }
-  if (NORM) block_sum_store(s2, &part[blockIdx.y * gridDim.x + blockIdx.x]);
+  if (MODE) block_sum_store(s2, &part[blockIdx.y * gridDim.x + blockIdx.x]);
+}
+
+// per-block partial sums of the squared norm of a level vector
+template <int MODE>
+__global__ __launch_bounds__(kNT) void k_vnorm(Lev L, const double* __restrict__ v, double* __restrict__ part) {
+  const int i = blockIdx.x * kBX + threadIdx.x;
+  const int j = blockIdx.y * kBY + threadIdx.y;
+  double s2 = 0.0;
+  if (i <= L.n && j <= L.n) {
+    const int w = j * L.ld + i;
+    s2 = norm_term<MODE>(L, i, j, v[w], v[L.V + w]);
+  }
+  block_sum_store(s2, &part[blockIdx.y * gridDim.x + blockIdx.x]);
 }
 
 template <typename T>
@@ -455,20 +479,33 @@ const dim3 kBlock(kBX, kBY);
 // ------------------------------------------------------------------ launchers
 
 template <typename T>
-hipError_t launch_residual(const Lev& L, const T* f, const T* x, T* r, double* part, int* nblocks, hipStream_t s) {
+hipError_t launch_residual(const Lev& L, const T* f, const T* x, T* r, double* part, int norm_mode, int* nblocks,
+                           hipStream_t s) {
   const dim3 g = grid_vertices(L.n);
   if (nblocks) *nblocks = (int)(g.x * g.y);
-  if (part)
-    hipLaunchKernelGGL((k_residual<T, true, true>), g, kBlock, 0, s, L, f, x, r, part);
+  if (part && norm_mode == 2)
+    hipLaunchKernelGGL((k_residual<T, true, 2>), g, kBlock, 0, s, L, f, x, r, part);
+  else if (part)
+    hipLaunchKernelGGL((k_residual<T, true, 1>), g, kBlock, 0, s, L, f, x, r, part);
   else
-    hipLaunchKernelGGL((k_residual<T, true, false>), g, kBlock, 0, s, L, f, x, r, part);
+    hipLaunchKernelGGL((k_residual<T, true, 0>), g, kBlock, 0, s, L, f, x, r, part);
   return hipGetLastError();
 }
 
 template <typename T>
 hipError_t launch_apply(const Lev& L, const T* x, T* y, hipStream_t s) {
-  hipLaunchKernelGGL((k_residual<T, false, false>), grid_vertices(L.n), kBlock, 0, s, L, (const T*)nullptr, x, y,
+  hipLaunchKernelGGL((k_residual<T, false, 0>), grid_vertices(L.n), kBlock, 0, s, L, (const T*)nullptr, x, y,
                      (double*)nullptr);
+  return hipGetLastError();
+}
+
+hipError_t launch_vnorm(const Lev& L, const double* v, double* part, int norm_mode, int* nblocks, hipStream_t s) {
+  const dim3 g = grid_vertices(L.n);
+  *nblocks = (int)(g.x * g.y);
+  if (norm_mode == 2)
+    hipLaunchKernelGGL((k_vnorm<2>), g, kBlock, 0, s, L, v, part);
+  else
+    hipLaunchKernelGGL((k_vnorm<1>), g, kBlock, 0, s, L, v, part);
   return hipGetLastError();
 }
 
@@ -552,7 +589,7 @@ hipError_t launch_zero_f32(float* v, size_t n, hipStream_t s) {
 }
 
 #define MGK_INSTANTIATE(T)                                                                                          \
-  template hipError_t launch_residual<T>(const Lev&, const T*, const T*, T*, double*, int*, hipStream_t);         \
+  template hipError_t launch_residual<T>(const Lev&, const T*, const T*, T*, double*, int, int*, hipStream_t);         \
   template hipError_t launch_apply<T>(const Lev&, const T*, T*, hipStream_t);                                      \
   template hipError_t launch_rhs<T>(const Lev&, const double*, T*, hipStream_t);                                   \
   template hipError_t launch_ne<T>(const Lev&, T*, T*, T*, hipStream_t);                                           \

@@ -19,12 +19,17 @@ constexpr int kDJ[kNDir] = {0, 0, 0, 1, -1, 1, -1};
 //   3x3 classes  c3(i)*3 + c3(j), c3 = 0 (index 0), 1 (inside), 2 (index n);
 //   5x5 classes  c5(i)*5 + c5(j), c5 = 0, 1, 2 (inside), 3 (n-1), 4 (n).
 // Coefficients towards neighbours outside the square are zero.
+// Per 5x5 class, the block C5[c] holds everything one smoother update needs:
+// M_{v,v+d} (d = 0..6), K_{v,v+d}, 1/W_{v+d} (0 for a neighbour outside the
+// square), 1/N_yy, 1/N_ll, one pad entry.
+constexpr int kC5 = 3 * kNDir + 3;
 struct Tab {
   double M[9][kNDir];  // M_{v, v+d}
   double K[9][kNDir];  // K_{v, v+d}, K = Laplacian stiffness + M
   double Winv[9];      // 1 / W_v with W = diag(M + sqrt(alpha) K)
   double Nyi[25];      // 1 / (N_k)_{y_v y_v}
   double Nli[25];      // 1 / (N_k)_{l_v l_v}
+  double C5[25][kC5];
 };
 
 // Scalars of one level, passed by value to every kernel.
@@ -46,8 +51,12 @@ __host__ __device__ inline int cls5(int i, int n) {
 }
 
 // ---- kernel launchers (kernels.hip); all enqueue on stream s ----------------
+// r = f - A x; with part != nullptr also per-block partial sums of ||r||^2,
+// Euclidean (norm_mode 1) or in the L^{-1} norm (norm_mode 2)
 template <typename T>
-hipError_t launch_residual(const Lev& L, const T* f, const T* x, T* r, double* part, int* nblocks, hipStream_t s);
+hipError_t launch_residual(const Lev& L, const T* f, const T* x, T* r, double* part, int norm_mode, int* nblocks,
+                           hipStream_t s);
+hipError_t launch_vnorm(const Lev& L, const double* v, double* part, int norm_mode, int* nblocks, hipStream_t s);
 template <typename T>
 hipError_t launch_apply(const Lev& L, const T* x, T* y, hipStream_t s);
 template <typename T>
@@ -56,6 +65,10 @@ template <typename T>
 hipError_t launch_ne(const Lev& L, T* x, T* r, T* p, hipStream_t s);
 template <typename T>
 hipError_t launch_lsgs_phase(const Lev& L, int colour, T* x, T* r, hipStream_t s);
+// one full LSGS sweep (all 7 colours; reverse = colours 6..0) reading r_in
+// and writing r_out (distinct buffers), x updated in place
+template <typename T>
+hipError_t launch_lsgs_sweep(const Lev& L, int reverse, T* x, const T* rin, T* rout, hipStream_t s);
 template <typename T>
 hipError_t launch_cgs_phase(const Lev& L, int colour, T* x, T* r, hipStream_t s);
 template <typename T>

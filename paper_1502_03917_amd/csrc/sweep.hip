@@ -1,0 +1,341 @@
+// One fused kernel per LSGS sweep (Alg. 2 of Takacs, arXiv 1502.03917, with
+// the unknowns ordered by the colours c(i,j) = (i + 2j) mod 7) for gfx950.
+//
+// A colour phase updates the vertices of one colour; each of them reads and
+// writes r on its closed neighbourhood, so after 7 phases the residual at a
+// vertex depends on the initial residual up to 14 lattice steps away.  Each
+// workgroup owns a TW x TW tile of vertices.  It loads the residual (both
+// fields) of the tile plus a 14-vertex halo into LDS once, then runs the 7
+// phases in LDS with one barrier after each: phase c visits the vertices of
+// colour c within Chebyshev distance 13 - 2c of the tile, exactly the set
+// whose updates reach the tile, and all of those are computed from correct
+// inputs.  At the end the tile's residual is written to r_out and its x,
+// loaded into registers at the start, is written back with the accumulated
+// corrections.  r is read from r_in and written to r_out (distinct buffers),
+// so no tile sees a neighbour's finished values.
+//
+// Global traffic per owned vertex: x read and written once, r written once,
+// r read once plus the halo share (neighbouring tiles re-read each other's
+// borders, mostly from L2 because consecutive tiles run on the same XCD).
+#include "mg_internal.hpp"
+
+namespace mgk {
+
+namespace {
+
+constexpr int kHalo = 14;
+
+// Workgroup barrier that orders LDS accesses only; global memory needs no
+// ordering inside a sweep (r_in is read-only, r_out and x are per owned vertex).
+__device__ inline void lds_barrier() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
+// Global accesses go through buffer instructions and are issued
+// unconditionally: a masked-off access uses an offset past the end of the
+// buffer, which the hardware turns into a zero load / dropped store.  With a
+// fixed number of memory operations the compiler waits only for the data it
+// is about to use.
+constexpr unsigned kOff = 0x80000000u;  // past the end of every buffer (< 2 GiB each)
+typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+
+__device__ inline __amdgpu_buffer_rsrc_t make_rsrc(const void* p, size_t bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), 0, (int)bytes, 0x00020000);
+}
+__device__ inline double bload(__amdgpu_buffer_rsrc_t r, unsigned off, double*) {
+  return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0));
+}
+__device__ inline float bload(__amdgpu_buffer_rsrc_t r, unsigned off, float*) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0));
+}
+__device__ inline void bstore(__amdgpu_buffer_rsrc_t r, unsigned off, double v) {
+  __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, off, 0, 0);
+}
+__device__ inline void bstore(__amdgpu_buffer_rsrc_t r, unsigned off, float v) {
+  __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, off, 0, 0);
+}
+
+template <int TW>
+struct TileGeom {
+  static constexpr int RMAX = TW + 2 * kHalo;  // widest / tallest region
+  static constexpr int RP = RMAX + 2;          // pitch with one guard cell each side
+  static constexpr int RN = RP * (RMAX + 2);   // region cells with guard rows
+};
+
+template <typename T, int TW, int NT>
+__global__ __launch_bounds__(NT) void k_lsgs_tile(Lev L, int ntx, int nty, int reverse, T* __restrict__ x,
+                                                  const T* __restrict__ rin, T* __restrict__ rout) {
+  using G = TileGeom<TW>;
+  constexpr int NR = (G::RMAX * G::RMAX + NT - 1) / NT;  // region cells per thread
+  constexpr int NX = (TW * TW + NT - 1) / NT;            // owned cells per thread
+  __shared__ T sy[G::RN];
+  __shared__ T sl[G::RN];
+  __shared__ T dxy[TW * TW];
+  __shared__ T dxl[TW * TW];
+  __shared__ T tC[25 * kC5];  // per-class coefficient blocks for vertices near the boundary
+
+  const int n = L.n, ld = L.ld, V = L.V;
+  const int ntiles = ntx * nty;
+  const int nblk = gridDim.x, bid = blockIdx.x;
+  const int tid = threadIdx.x;
+  const size_t vbytes = (size_t)2 * V * sizeof(T);
+  const __amdgpu_buffer_rsrc_t Rin = make_rsrc(rin, vbytes), Rout = make_rsrc(rout, vbytes), Rx = make_rsrc(x, vbytes);
+  const unsigned fo = (unsigned)(V * sizeof(T));  // byte offset of the lambda field
+
+  // Tiles are processed in rounds of nblk; in a round, the blocks of one XCD
+  // (bid % 8) take a contiguous run of tiles, which share halo rows in its L2.
+  auto tile_of = [&](int round) -> int {
+    const int local = (nblk % 8 == 0) ? (bid % 8) * (nblk / 8) + bid / 8 : bid;
+    return round * nblk + local;
+  };
+  struct Box {
+    int i0, i1, j0, j1, ci0, ci1, rj0, rj1;
+  };
+  auto box_of = [&](int tile) -> Box {
+    Box b;
+    const int tx = tile % ntx, ty = tile / ntx;
+    b.i0 = tx * TW;
+    b.i1 = min(n + 1, b.i0 + TW);
+    b.j0 = ty * TW;
+    b.j1 = min(n + 1, b.j0 + TW);
+    b.ci0 = max(0, b.i0 - kHalo);
+    b.ci1 = min(n + 1, b.i1 + kHalo);
+    b.rj0 = max(0, b.j0 - kHalo);
+    b.rj1 = min(n + 1, b.j1 + kHalo);
+    return b;
+  };
+
+  // registers holding the next tile's region of r and its owned x
+  T ry[NR], rl[NR], xy[NX], xl[NX];
+  auto fetch = [&](int tile) {
+    const bool live = tile < ntiles;
+    const Box b = box_of(live ? tile : 0);
+    const int RW = b.ci1 - b.ci0, RH = b.rj1 - b.rj0, OW = b.i1 - b.i0, OH = b.j1 - b.j0;
+#pragma unroll
+    for (int q = 0; q < NX; q++) {
+      const int e = tid + q * NT;
+      const int oj = e / TW, oi = e - oj * TW;
+      const bool ok = live && e < TW * TW && oi < OW && oj < OH;
+      const unsigned o = ok ? (unsigned)(((b.j0 + oj) * ld + b.i0 + oi) * sizeof(T)) : kOff;
+      xy[q] = bload(Rx, o, (T*)nullptr);
+      xl[q] = bload(Rx, ok ? o + fo : kOff, (T*)nullptr);
+    }
+#pragma unroll
+    for (int q = 0; q < NR; q++) {
+      const int e = tid + q * NT;
+      const int lr = e / G::RMAX, li = e - lr * G::RMAX;
+      const bool ok = live && e < G::RMAX * G::RMAX && li < RW && lr < RH;
+      const unsigned o = ok ? (unsigned)(((b.rj0 + lr) * ld + b.ci0 + li) * sizeof(T)) : kOff;
+      ry[q] = bload(Rin, o, (T*)nullptr);
+      rl[q] = bload(Rin, ok ? o + fo : kOff, (T*)nullptr);
+    }
+  };
+  // region r into LDS, corrections cleared
+  auto stash = [&](int tile) {
+    const Box b = box_of(tile < ntiles ? tile : 0);
+    const int RW = b.ci1 - b.ci0, RH = b.rj1 - b.rj0;
+#pragma unroll
+    for (int q = 0; q < NR; q++) {
+      const int e = tid + q * NT;
+      const int lr = e / G::RMAX, li = e - lr * G::RMAX;
+      if (e < G::RMAX * G::RMAX && li < RW && lr < RH) {
+        const int a = (lr + 1) * G::RP + li + 1;
+        sy[a] = ry[q];
+        sl[a] = rl[q];
+      }
+    }
+    for (int e = tid; e < TW * TW; e += NT) {
+      dxy[e] = (T)0;
+      dxl[e] = (T)0;
+    }
+  };
+
+  const int nrounds = (ntiles + nblk - 1) / nblk;
+  if (tile_of(0) >= ntiles) return;  // uniform per block: no tile for this block
+
+  {
+    constexpr int NC = (25 * kC5 + NT - 1) / NT;
+    const double* src = &L.tab->C5[0][0];
+    double v[NC];
+#pragma unroll
+    for (int q = 0; q < NC; q++) v[q] = src[min(tid + q * NT, 25 * kC5 - 1)];
+#pragma unroll
+    for (int q = 0; q < NC; q++)
+      if (tid + q * NT < 25 * kC5) tC[tid + q * NT] = (T)v[q];
+  }
+  fetch(tile_of(0));
+  stash(tile_of(0));
+  lds_barrier();
+
+  const T Mc = (T)L.Mc, Mo = (T)L.Mo, Kc = (T)L.Kc, Ka = (T)L.Ka, Kd = (T)L.Kd, Wi = (T)L.Winv;
+  const T al = (T)L.alpha, ai = (T)L.ainv, Nyi = (T)L.Nyi, Nli = (T)L.Nli;
+
+  for (int round = 0; round < nrounds; round++) {
+    const int tile = tile_of(round);
+    if (tile >= ntiles) break;  // uniform per block
+    const Box b = box_of(tile);
+    const int i0 = b.i0, i1 = b.i1, j0 = b.j0, j1 = b.j1, ci0 = b.ci0, ci1 = b.ci1, rj0 = b.rj0, rj1 = b.rj1;
+    const int OW = i1 - i0, OH = j1 - j0;
+    // x of this tile, loaded with the previous fetch
+    T cxy[NX], cxl[NX];
+#pragma unroll
+    for (int q = 0; q < NX; q++) {
+      cxy[q] = xy[q];
+      cxl[q] = xl[q];
+    }
+    // the next tile's data is in flight while this tile is computed
+    fetch(tile_of(round + 1));
+
+    // one update of the vertex at region cell (lr, li)
+    auto update = [&](int lr, int li) {
+      const int gi = ci0 + li, gj = rj0 + lr;
+      const int b0 = (lr + 1) * G::RP + li + 1;
+      const int bu = b0 + G::RP, bd = b0 - G::RP;
+      T py, pl;
+      // the 14 residual entries are read once; the scatter writes the gathered
+      // values minus the update (no other vertex of the phase touches them)
+      if (gi >= 2 && gi <= n - 2 && gj >= 2 && gj <= n - 2) {
+        const T yc = sy[b0], ye = sy[b0 + 1], yw = sy[b0 - 1], yn = sy[bu], ys = sy[bd], yne = sy[bu + 1],
+                ysw = sy[bd - 1];
+        const T lc = sl[b0], le = sl[b0 + 1], lw = sl[b0 - 1], ln = sl[bu], ls = sl[bd], lne = sl[bu + 1],
+                lsw = sl[bd - 1];
+        const T ya = ye + yw + yn + ys;
+        const T yg = yne + ysw;
+        const T la = le + lw + ln + ls;
+        const T lg = lne + lsw;
+        const T qy = Wi * (Mc * yc + Mo * (ya + yg) + al * (Kc * lc + Ka * la + Kd * lg));
+        const T ql = Wi * ((Kc * yc + Ka * ya + Kd * yg) - (Mc * lc + Mo * (la + lg)));
+        py = qy * Nyi;
+        pl = ql * Nli;
+        const T dyc = Mc * py + Kc * pl, dya = Mo * py + Ka * pl, dyg = Mo * py + Kd * pl;
+        const T dlc = Kc * py - ai * (Mc * pl), dla = Ka * py - ai * (Mo * pl), dlg = Kd * py - ai * (Mo * pl);
+        sy[b0] = yc - dyc;
+        sl[b0] = lc - dlc;
+        sy[b0 + 1] = ye - dya;
+        sl[b0 + 1] = le - dla;
+        sy[b0 - 1] = yw - dya;
+        sl[b0 - 1] = lw - dla;
+        sy[bu] = yn - dya;
+        sl[bu] = ln - dla;
+        sy[bd] = ys - dya;
+        sl[bd] = ls - dla;
+        sy[bu + 1] = yne - dyg;
+        sl[bu + 1] = lne - dlg;
+        sy[bd - 1] = ysw - dyg;
+        sl[bd - 1] = lsw - dlg;
+      } else {
+        // near the domain boundary: the class block gives all coefficients;
+        // neighbours outside the square have zero coefficients and are neither
+        // read nor written
+        const T* cb = &tC[(cls5(gi, n) * 5 + cls5(gj, n)) * kC5];
+        int ad[kNDir];
+        bool in[kNDir];
+        T va[kNDir], vb[kNDir];
+#pragma unroll
+        for (int d = 0; d < kNDir; d++) {
+          const int ii = gi + kDI[d], jj = gj + kDJ[d];
+          in[d] = ii >= 0 && ii <= n && jj >= 0 && jj <= n;
+          ad[d] = in[d] ? b0 + kDJ[d] * G::RP + kDI[d] : b0;
+          va[d] = sy[ad[d]];
+          vb[d] = sl[ad[d]];
+        }
+        T qy = 0, ql = 0;
+#pragma unroll
+        for (int d = 0; d < kNDir; d++) {
+          const T m = cb[d], k = cb[kNDir + d], wi = cb[2 * kNDir + d];
+          qy += (m * va[d] + al * k * vb[d]) * wi;
+          ql += (k * va[d] - m * vb[d]) * wi;
+        }
+        py = qy * cb[3 * kNDir];
+        pl = ql * cb[3 * kNDir + 1];
+#pragma unroll
+        for (int d = 0; d < kNDir; d++) {
+          if (!in[d]) continue;
+          const T m = cb[d], k = cb[kNDir + d];
+          sy[ad[d]] = va[d] - (m * py + k * pl);
+          sl[ad[d]] = vb[d] - (k * py - ai * (m * pl));
+        }
+      }
+      if (gi >= i0 && gi < i1 && gj >= j0 && gj < j1) {
+        const int o = (gj - j0) * TW + (gi - i0);
+        dxy[o] = py;
+        dxl[o] = pl;
+      }
+    };
+
+    for (int ph = 0; ph < 7; ph++) {
+      const int colour = reverse ? 6 - ph : ph;
+      const int d = kHalo - 1 - 2 * ph;  // Chebyshev radius of the phase window around the tile
+      const int wl = max(ci0, i0 - d), wh = min(ci1, i1 + d);
+      const int wb = max(rj0, j0 - d), wt = min(rj1, j1 + d);
+      const int S = (wh - wl + 6) / 7 + 1;  // colour slots per row (first slot within [wl, wl+7))
+      const int nitems = (wt - wb) * S;
+      for (int k = tid; k < nitems; k += NT) {
+        const int rr = k / S, t = k - rr * S;
+        const int gj = wb + rr;
+        const int gi = wl + ((colour - 2 * gj - wl) % 7 + 7) % 7 + 7 * t;
+        if (gi < wh) update(gj - rj0, gi - ci0);
+      }
+      lds_barrier();
+    }
+
+    // owned tile out: r to r_out, x + corrections to x
+#pragma unroll
+    for (int q = 0; q < NX; q++) {
+      const int e = tid + q * NT;
+      const int oj = e / TW, oi = e - oj * TW;
+      const bool ok = e < TW * TW && oi < OW && oj < OH;
+      const int a = ok ? (oj + j0 - rj0 + 1) * G::RP + (oi + i0 - ci0) + 1 : 0;
+      const int od = ok ? e : 0;
+      const unsigned o = ok ? (unsigned)(((j0 + oj) * ld + i0 + oi) * sizeof(T)) : kOff;
+      const unsigned o2 = ok ? o + fo : kOff;
+      bstore(Rout, o, sy[a]);
+      bstore(Rout, o2, sl[a]);
+      bstore(Rx, o, cxy[q] + dxy[od]);
+      bstore(Rx, o2, cxl[q] + dxl[od]);
+    }
+    lds_barrier();
+    stash(tile_of(round + 1));
+    lds_barrier();
+  }
+}
+
+inline int tiles_along(int npts, int TW) { return (npts + TW - 1) / TW; }
+
+// persistent launch: at most `resident` workgroups, each looping over tiles
+template <typename T, int TW, int NT>
+hipError_t launch_tile_cfg(const Lev& L, int resident, int reverse, T* x, const T* rin, T* rout, hipStream_t s) {
+  const int nt = tiles_along(L.n + 1, TW);
+  const int nblk = nt * nt < resident ? nt * nt : resident;
+  hipLaunchKernelGGL((k_lsgs_tile<T, TW, NT>), dim3(nblk), dim3(NT), 0, s, L, nt, nt, reverse, x, rin, rout);
+  return hipGetLastError();
+}
+
+// workgroups that fit on the device at once (multiprocessors x per-CU count)
+int resident_blocks(int per_cu) {
+  static int cus = 0;
+  if (cus == 0) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0)
+      cus = 256;
+  }
+  return cus * per_cu;
+}
+
+}  // namespace
+
+template <>
+hipError_t launch_lsgs_sweep<double>(const Lev& L, int reverse, double* x, const double* rin, double* rout,
+                                     hipStream_t s) {
+  return launch_tile_cfg<double, 48, 512>(L, resident_blocks(1), reverse, x, rin, rout, s);
+}
+
+template <>
+hipError_t launch_lsgs_sweep<float>(const Lev& L, int reverse, float* x, const float* rin, float* rout,
+                                    hipStream_t s) {
+  return launch_tile_cfg<float, 48, 512>(L, resident_blocks(2), reverse, x, rin, rout, s);
+}
+
+}  // namespace mgk

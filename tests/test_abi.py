@@ -31,6 +31,7 @@ def test_default_opts():
     o = mg.default_opts("poisson")
     assert (o.smoother, o.nu1, o.nu2, o.gamma, o.coarse_level, o.precision) == (mg.MG_LSGS, 2, 2, 1, 1, mg.MG_FP64)
     assert o.tau == pytest.approx(0.4) and o.max_cycles == 200 and o.inner_cycles == 1
+    assert o.norm == mg.MG_NORM_LINV
     assert mg.default_opts("stokes").tau == pytest.approx(0.35)
 
 
@@ -58,7 +59,7 @@ def test_setup_rejects_alpha(alpha):
 @pytest.mark.parametrize("field,value", [("smoother", 4), ("smoother", -1), ("gamma", 0), ("gamma", 3),
                                          ("tau", 2.5), ("tau", math.nan), ("coarse_level", 0),
                                          ("coarse_level", 4), ("precision", 2), ("nu1", -1), ("max_cycles", -5),
-                                         ("inner_cycles", 0)])
+                                         ("inner_cycles", 0), ("norm", 2), ("norm", -1)])
 def test_setup_rejects_options(field, value):
     assert _setup(**{field: value})[0] == mg.MG_EINVAL
 
@@ -88,7 +89,7 @@ def test_null_context_calls():
 
 def test_strerror_covers_all_codes():
     L = mg.lib()
-    texts = {st: L.mg_strerror(st).decode() for st in range(mg.MG_EUNSUPPORTED, 1)}
+    texts = {st: L.mg_strerror(st).decode() for st in range(mg.MG_ESTALL, 1)}
     assert texts[mg.MG_OK] == "success"
     assert len(set(texts.values())) == len(texts)
     assert L.mg_strerror(5) == b"unknown status"

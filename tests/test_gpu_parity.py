@@ -109,6 +109,29 @@ def test_coarse_solve(torch_cuda, alpha, coarse):
     assert np.linalg.norm(got - ref) <= 1e-11 * np.linalg.norm(ref)
 
 
+@pytest.mark.parametrize("smoother", ["lsgs", "slsgs"])
+@pytest.mark.parametrize("level", [7, 10])
+def test_fused_sweep_matches_phase_kernels(torch_cuda, monkeypatch, level, smoother):
+    # one fused kernel per sweep vs one launch per colour phase: same arithmetic
+    torch = torch_cuda
+    mg = _mg()
+    alpha = 1e-3
+    monkeypatch.setenv("MGKKT_PHASE_KERNELS", "1")
+    sp = mg.Solver(level, alpha, smoother=smoother)
+    monkeypatch.delenv("MGKKT_PHASE_KERNELS")
+    sf = mg.Solver(level, alpha, smoother=smoother)
+    n = sf.vec_len()
+    x = workloads.uniform(n, 51)
+    f = workloads.uniform(n, 52)
+    r = _host(sf.residual(_dev(torch, f), _dev(torch, x)))
+    xa, ra = _dev(torch, x), _dev(torch, r)
+    xb, rb = _dev(torch, x), _dev(torch, r)
+    sp.smooth(xa, ra, steps=3)
+    sf.smooth(xb, rb, steps=3)
+    assert _relmax(_host(xb), _host(xa)) < 1e-14
+    assert _relmax(_host(rb), _host(ra)) < 1e-13
+
+
 CYCLE_CASES = [
     (5, 1e-2, "lsgs", 1),
     (5, 1e-2, "ne", 1),
@@ -119,6 +142,8 @@ CYCLE_CASES = [
     (7, 1.0, "slsgs", 1),
     (7, 1e-8, "cgs", 1),
     (8, 1e-6, "lsgs", 2),
+    (10, 1e-2, "lsgs", 1),
+    (10, 1e-5, "slsgs", 1),
 ]
 
 
@@ -141,17 +166,18 @@ def test_cycle_parity(torch_cuda, level, alpha, smoother, gamma):
         assert err <= 1e-12, (m, err)
 
 
+@pytest.mark.parametrize("norm", ["l2", "linv"])
 @pytest.mark.parametrize("alpha", ALPHAS)
 @pytest.mark.parametrize("smoother", ["ne", "lsgs"])
-def test_solve_parity(torch_cuda, alpha, smoother):
+def test_solve_parity(torch_cuda, alpha, smoother, norm):
     torch = torch_cuda
     mg = _mg()
     level = 6
-    s = mg.Solver(level, alpha, smoother=smoother)
+    s = mg.Solver(level, alpha, smoother=smoother, norm=norm)
     h = oracle.Hierarchy(level, alpha, coarse=1)
     yd = workloads.desired_state(level, 2)
     f = h.rhs(yd)
-    xo, it_o, hist = h.solve(f, tol=1e-10, smoother=smoother, order="col7")
+    xo, it_o, hist = h.solve(f, tol=1e-10, smoother=smoother, order="col7", norm=norm)
     xg, it_g, rel, st = s.solve(s.rhs(_dev(torch, yd)), tol=1e-10)
     assert st == mg.MG_OK and rel <= 1e-10
     assert abs(it_g - it_o) <= 1
@@ -184,6 +210,11 @@ def test_error_paths(torch_cuda):
     assert st == mg.MG_ENAN
     with pytest.raises(mg.MGError):
         s.solve(f, tol=-1.0)
+    # below the FP64 rounding floor of the Euclidean ratio the solve reports a stall
+    s3 = mg.Solver(10, 1.0, norm="l2")
+    f3 = s3.rhs(_dev(torch, workloads.desired_state(10, 1)))
+    x, it, rel, st = s3.solve(f3, tol=1e-14, raise_on_error=False)
+    assert st == mg.MG_ESTALL and it < 100 and rel < 1e-6
     # an over-damped normal-equation smoother diverges and is reported
     s2 = mg.Solver(level, 1e-2, smoother="ne", tau=1.99, max_cycles=500)
     x, it, rel, st = s2.solve(f, tol=1e-10, raise_on_error=False)
