@@ -219,6 +219,18 @@ struct mg_ctx {
   double* h_norm = nullptr;  // pinned host copy
   bool fp32_ready = false;
   bool fused = true;  // one kernel per LSGS sweep (else one kernel per colour phase)
+  // coarse-level tail: one workgroup runs the sub-cycle on levels k0..tail_T
+  int tail_T = 0;       // 0: no tail
+  bool tail_allowed = true;
+  int4* d_tail_ops = nullptr;
+  mgk::TailLaunch tail{};
+  // HIP graph of one solver iterate (cycle + residual norm) for fixed f, x
+  hipStream_t cap_stream = nullptr;  // capture stream (default priority)
+  bool graphs = true;
+  hipGraphExec_t gexec = nullptr;
+  const double* g_f = nullptr;
+  double* g_x = nullptr;
+  bool capturing = false;
   // timing of the finest-level smoothing sweeps
   bool timing = false;
   std::vector<hipEvent_t> ev;  // pairs
@@ -288,10 +300,13 @@ void destroy_impl(mg_ctx* c) {
   }
   (void)hipFree(c->d_lu);
   (void)hipFree(c->d_piv);
+  (void)hipFree(c->d_tail_ops);
   (void)hipFree(c->d_part);
   (void)hipFree(c->d_norm);
   if (c->h_norm) (void)hipHostFree(c->h_norm);
   for (auto e : c->ev) (void)hipEventDestroy(e);
+  if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
+  if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
   delete c;
 }
 
@@ -320,7 +335,9 @@ struct Work {
 Work<double> work(LevelBuf& b, double*) { return {b.x, b.f, b.r, b.r2, b.p}; }
 Work<float> work(LevelBuf& b, float*) { return {b.x32, b.f32, b.r32, b.r2_32, b.p32}; }
 
-void timing_begin(mg_ctx* c, hipStream_t s, size_t* slot) {
+// start a timed sweep with an event pair from the pool (folded into the
+// running total when it fills up); timed solves run without graphs
+hipEvent_t timing_begin(mg_ctx* c, hipStream_t s, size_t* slot) {
   if (c->ev_used + 2 > c->ev.size()) {
     // fold the recorded pairs into the running total before reusing them
     if (!c->ev.empty()) {
@@ -340,6 +357,7 @@ void timing_begin(mg_ctx* c, hipStream_t s, size_t* slot) {
   *slot = c->ev_used;
   c->ev_used += 2;
   (void)hipEventRecord(c->ev[*slot], s);
+  return c->ev[*slot + 1];
 }
 
 // `steps` smoothing steps on level l.  r holds f - A x on entry; the fused
@@ -349,11 +367,12 @@ template <typename T>
 int smooth_steps(mg_ctx* c, int l, T* x, T*& r, T* alt, T* p, int steps, hipStream_t s) {
   LevelBuf& b = L_(c, l);
   const Lev& L = b.lev;
-  const bool timed = c->timing && l == c->level;
+  const bool timed = c->timing && l == c->level && !c->capturing;
   const bool fused = c->fused && alt != nullptr;
   for (int it = 0; it < steps; it++) {
     size_t slot = 0;
-    if (timed) timing_begin(c, s, &slot);
+    hipEvent_t stop = nullptr;
+    if (timed) stop = timing_begin(c, s, &slot);
     switch (c->o.smoother) {
       case MG_NE:
         HIPCHK(c, mgk::launch_ne<T>(L, x, r, p, s));
@@ -379,8 +398,8 @@ int smooth_steps(mg_ctx* c, int l, T* x, T*& r, T* alt, T* p, int steps, hipStre
         for (int col = 0; col < 7; col++) HIPCHK(c, mgk::launch_cgs_phase<T>(L, col, x, r, s));
         break;
     }
-    if (timed) {
-      (void)hipEventRecord(c->ev[slot + 1], s);
+    if (timed && stop) {
+      (void)hipEventRecord(stop, s);
       c->t_n++;
     }
   }
@@ -395,6 +414,59 @@ int coarse_solve_T(mg_ctx* c, const T* f, T* x, hipStream_t s) {
 
 // One iterate on level l for A_l x = f; r is level-l workspace.  If
 // residual_current, r already holds f - A_l x.
+// Op list of one iterate on level l of the tail (same steps as cycle_body):
+// nu1 smoothing steps, restriction (x_{l-1} = 0, r_{l-1} = f_{l-1}), gamma
+// coarse iterates (a fresh residual before the second), prolongation with the
+// new residual, nu2 smoothing steps; the coarsest level is the LU solve.
+void tail_ops(const mg_ctx* c, int l, std::vector<int4>& ops) {
+  if (l == c->k0) {
+    ops.push_back(make_int4(mgk::kTailCoarse, l, 0, 0));
+    return;
+  }
+  if (c->o.nu1) ops.push_back(make_int4(mgk::kTailSmooth, l, c->o.nu1, 0));
+  ops.push_back(make_int4(mgk::kTailRestrict, l, 0, 0));
+  for (int g = 0; g < c->o.gamma; g++) {
+    if (g > 0 && l - 1 > c->k0) ops.push_back(make_int4(mgk::kTailResidual, l - 1, 0, 0));
+    tail_ops(c, l - 1, ops);
+  }
+  ops.push_back(make_int4(mgk::kTailProlongResidual, l, 0, 0));
+  if (c->o.nu2) ops.push_back(make_int4(mgk::kTailSmooth, l, c->o.nu2, 0));
+}
+
+// (Re)build the tail for the context's options; tail level min(5, level - 1)
+int setup_tail(mg_ctx* c) {
+  (void)hipFree(c->d_tail_ops);
+  c->d_tail_ops = nullptr;
+  c->tail_T = 0;
+  const int T = c->level - 1 < 5 ? c->level - 1 : 5;
+  if (!c->tail_allowed || T <= c->k0 || c->k0 > 2 || c->problem != MG_POISSON) return MG_OK;
+  std::vector<int4> ops;
+  tail_ops(c, T, ops);
+  HIPCHK(c, hipMalloc(&c->d_tail_ops, ops.size() * sizeof(int4)));
+  HIPCHK(c, hipMemcpy(c->d_tail_ops, ops.data(), ops.size() * sizeof(int4), hipMemcpyHostToDevice));
+  mgk::TailLaunch& t = c->tail;
+  t.k0 = c->k0;
+  t.T = T;
+  t.nops = (int)ops.size();
+  static const int map[4] = {mgk::MG_TAIL_NE, mgk::MG_TAIL_LSGS, mgk::MG_TAIL_SLSGS, mgk::MG_TAIL_CGS};
+  t.smoother = map[c->o.smoother];
+  t.tau = c->o.tau;
+  t.ops = c->d_tail_ops;
+  t.lu = c->d_lu;
+  t.piv = c->d_piv;
+  t.ncoarse = c->ncoarse;
+  for (int l = c->k0; l <= T; l++) t.lev[l] = L_(c, l).lev;
+  const size_t need = mgk::tail_lds_bytes<double>(c->k0, T);
+  int dev = 0, maxlds = 0;
+  HIPCHK(c, hipGetDevice(&dev));
+  HIPCHK(c, hipDeviceGetAttribute(&maxlds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
+  t.max_lds = (size_t)maxlds;
+  if (need > t.max_lds) return MG_OK;  // does not fit: no tail
+  HIPCHK(c, mgk::tail_allow_lds(need));
+  c->tail_T = T;
+  return MG_OK;
+}
+
 // One iterate on level l for A_l x = f; r is level-l workspace (one of the
 // level's two residual buffers).  If residual_current, r already holds f - A_l x.
 template <typename T>
@@ -411,10 +483,14 @@ int cycle_body(mg_ctx* c, int l, const T* f, T* x, T* r, bool residual_current, 
   alt = (r == wb.r) ? wb.r2 : wb.r;
   // defect restriction; the coarse iterate starts from zero with r_c = f_c
   const bool coarse_is_k0 = (l - 1 == c->k0);
-  HIPCHK(c, mgk::launch_restrict<T>(b.lev, bc.lev, r, wc.f, coarse_is_k0 ? nullptr : wc.x,
-                                    coarse_is_k0 ? nullptr : wc.r, s));
+  const bool tail = (l - 1 == c->tail_T);
+  HIPCHK(c, mgk::launch_restrict<T>(b.lev, bc.lev, r, wc.f, (coarse_is_k0 || tail) ? nullptr : wc.x,
+                                    (coarse_is_k0 || tail) ? nullptr : wc.r, s));
   for (int g = 0; g < c->o.gamma; g++) {
-    if ((st = cycle_body<T>(c, l - 1, wc.f, wc.x, wc.r, g == 0, s)) != MG_OK) return st;
+    if (tail)
+      HIPCHK(c, mgk::launch_tail<T>(c->tail, wc.f, wc.x, g == 0 ? 1 : 0, s));
+    else if ((st = cycle_body<T>(c, l - 1, wc.f, wc.x, wc.r, g == 0, s)) != MG_OK)
+      return st;
   }
   HIPCHK(c, mgk::launch_prolong_add<T>(b.lev, bc.lev, wc.x, x, s));
   HIPCHK(c, mgk::launch_residual<T>(b.lev, f, x, r, nullptr, 0, nullptr, s));
@@ -442,6 +518,49 @@ int ir_step(mg_ctx* c, double* x, hipStream_t s) {
   for (int k = 0; k < c->o.inner_cycles; k++)
     if ((st = cycle_body<float>(c, c->level, b.f32, b.x32, b.r32, k == 0, s)) != MG_OK) return st;
   HIPCHK(c, mgk::launch_axpy_f32(b.x32, b.len, c->d_norm, x, s));
+  return MG_OK;
+}
+
+// one solver iterate for fixed (f, x): cycle (FP64) or refinement step
+// (FP32 cycles), then the fine residual and its squared norm in d_norm[0]
+int iterate(mg_ctx* c, const double* f, double* x, hipStream_t s) {
+  LevelBuf& b = L_(c, c->level);
+  int st = c->o.precision == MG_FP32_IR ? ir_step(c, x, s) : cycle_body<double>(c, c->level, f, x, b.r, true, s);
+  if (st != MG_OK) return st;
+  return residual_norm(c, f, x, b.r, 0, s);
+}
+
+void drop_graph(mg_ctx* c) {
+  if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
+  c->gexec = nullptr;
+  c->g_f = nullptr;
+  c->g_x = nullptr;
+}
+
+// graph of iterate() for (f, x) and the current options / timing state
+int ensure_graph(mg_ctx* c, const double* f, double* x) {
+  if (c->gexec && c->g_f == f && c->g_x == x) return MG_OK;
+  drop_graph(c);
+  if (!c->cap_stream) HIPCHK(c, hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
+  hipGraph_t g = nullptr;
+  HIPCHK(c, hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
+  c->capturing = true;
+  int st = iterate(c, f, x, c->cap_stream);
+  c->capturing = false;
+  hipError_t e = hipStreamEndCapture(c->cap_stream, &g);
+  if (st != MG_OK) {
+    if (g) (void)hipGraphDestroy(g);
+    return st;
+  }
+  if (e != hipSuccess) return fail(c, MG_EHIP, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
+  e = hipGraphInstantiate(&c->gexec, g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  if (e != hipSuccess) {
+    c->gexec = nullptr;
+    return fail(c, MG_EHIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
+  }
+  c->g_f = f;
+  c->g_x = x;
   return MG_OK;
 }
 
@@ -515,6 +634,12 @@ int mg_setup(int level, double alpha, int problem, const mg_opts* opts, mg_ctx**
     // MGKKT_PHASE_KERNELS=1 selects one launch per colour phase (comparison and testing)
     const char* e = std::getenv("MGKKT_PHASE_KERNELS");
     c->fused = !(e && e[0] == '1');
+    // MGKKT_NO_TAIL=1 runs the coarse levels with the per-level kernels
+    const char* t = std::getenv("MGKKT_NO_TAIL");
+    c->tail_allowed = !(t && t[0] == '1');
+    // MGKKT_NO_GRAPH=1 makes mg_solve launch every kernel eagerly
+    const char* g = std::getenv("MGKKT_NO_GRAPH");
+    c->graphs = !(g && g[0] == '1');
   }
   int st = MG_OK;
   auto bail = [&](int s) {
@@ -574,6 +699,7 @@ int mg_setup(int level, double alpha, int problem, const mg_opts* opts, mg_ctx**
   if (hipHostMalloc((void**)&c->h_norm, 4 * sizeof(double), hipHostMallocDefault) != hipSuccess)
     return bail(MG_ENOMEM);
   if (c->o.precision == MG_FP32_IR && (st = alloc_fp32(c)) != MG_OK) return bail(st);
+  if ((st = setup_tail(c)) != MG_OK) return bail(st);
   *out = c;
   return MG_OK;
 }
@@ -593,7 +719,8 @@ int mg_set_opts(mg_ctx* ctx, const mg_opts* opts) {
   }
   ctx->o = o;
   for (auto& b : ctx->lv) b.lev.tau = o.tau;
-  return MG_OK;
+  drop_graph(ctx);
+  return setup_tail(ctx);
 }
 
 int mg_rhs(mg_ctx* ctx, const double* yd, double* f, void* stream) {
@@ -679,8 +806,8 @@ int mg_solve(mg_ctx* ctx, const double* f, double* x, double tol, int* cycles_ou
   double nf = -1.0, rel0 = -1.0, rel = 0.0;
   int it = 0, st = MG_OK;
   std::vector<double> hist;
+  if ((st = residual_norm(ctx, f, x, b.r, 0, s)) != MG_OK) return st;
   for (;; it++) {
-    if ((st = residual_norm(ctx, f, x, b.r, 0, s)) != MG_OK) return st;
     HIPCHK(ctx, hipMemcpyAsync(ctx->h_norm, ctx->d_norm, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
     HIPCHK(ctx, hipStreamSynchronize(s));
     if (nf < 0.0) nf = std::sqrt(ctx->h_norm[1]) > 0.0 ? std::sqrt(ctx->h_norm[1]) : 1.0;
@@ -702,16 +829,18 @@ int mg_solve(mg_ctx* ctx, const double* f, double* x, double tol, int* cycles_ou
         return fail(ctx, MG_ESTALL, "residual stagnated: no factor 2 gained over the last 10 iterates");
     }
     if (it >= ctx->o.max_cycles) return fail(ctx, MG_ENOTCONV, "max_cycles reached");
-    if (ctx->o.precision == MG_FP32_IR)
-      st = ir_step(ctx, x, s);
-    else
-      st = cycle_body<double>(ctx, ctx->level, f, x, b.r, true, s);
-    if (st != MG_OK) return st;
+    if (ctx->graphs && !ctx->timing) {
+      if ((st = ensure_graph(ctx, f, x)) != MG_OK) return st;
+      HIPCHK(ctx, hipGraphLaunch(ctx->gexec, s));
+    } else if ((st = iterate(ctx, f, x, s)) != MG_OK) {
+      return st;
+    }
   }
 }
 
 int mg_timing_enable(mg_ctx* ctx, int enable) {
   if (!ctx) return MG_EINVAL;
+  drop_graph(ctx);
   if (ctx->ev_used) (void)hipEventSynchronize(ctx->ev[ctx->ev_used - 1]);
   ctx->ev_used = 0;
   ctx->t_ms = 0.0;

@@ -45,6 +45,22 @@ struct Lev {
   const Tab* tab;     // device pointer
 };
 
+// ---- coarse-level tail (tail.hip): one workgroup runs the sub-cycle on
+// levels k0..T from a host-built op list
+constexpr int kTailMaxLevels = 6;  // highest tail level supported
+constexpr int kTailThreads = 256;  // a few waves: the tail is a chain of small barrier-separated steps
+enum { kTailSmooth = 1, kTailResidual = 2, kTailRestrict = 3, kTailCoarse = 4, kTailProlongResidual = 5 };
+enum { MG_TAIL_NE = 0, MG_TAIL_LSGS = 1, MG_TAIL_SLSGS = 2, MG_TAIL_CGS = 3 };
+struct TailLaunch {
+  int k0, T, nops, smoother, ncoarse;
+  double tau;
+  const int4* ops;  // device op list (x = op, y = level, z = count)
+  const double* lu;
+  const int* piv;
+  Lev lev[kTailMaxLevels + 1];
+  size_t max_lds;
+};
+
 __host__ __device__ inline int cls3(int i, int n) { return i == 0 ? 0 : (i == n ? 2 : 1); }
 __host__ __device__ inline int cls5(int i, int n) {
   return i <= 1 ? i : (i >= n - 1 ? 4 - (n - i) : 2);
@@ -77,6 +93,13 @@ template <typename T>
 hipError_t launch_prolong_add(const Lev& Lf, const Lev& Lc, const T* xc, T* x, hipStream_t s);
 template <typename T>
 hipError_t launch_coarse_solve(int N, const double* lu, const int* piv, const T* f, T* x, hipStream_t s);
+
+// f_T in, x_T in/out (first: x_T starts at zero); see TailLaunch
+template <typename T>
+hipError_t launch_tail(const TailLaunch& tl, const T* fT, T* xT, int first, hipStream_t s);
+template <typename T>
+size_t tail_lds_bytes(int k0, int Tl);
+hipError_t tail_allow_lds(size_t bytes);
 
 hipError_t launch_sum(const double* part, int n, double* out, hipStream_t s);
 hipError_t launch_sumsq(const double* v, size_t n, double* part, int* nblocks, hipStream_t s);

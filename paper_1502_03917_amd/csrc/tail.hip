@@ -1,0 +1,390 @@
+// Coarse-level tail of the multigrid cycle (section 2 of Takacs, arXiv
+// 1502.03917) in one workgroup.
+//
+// On the coarse levels a cycle is a long chain of tiny dependent steps, so
+// separate kernel launches cost far more than the arithmetic.  Here one
+// workgroup keeps x, r and f of every level k0..T in LDS and runs the whole
+// sub-cycle from a schedule of operations built by the host (smoothing,
+// restriction, the FP64 LU solve on k0, prolongation + residual), reading f_T
+// from global memory at the start and writing x_T back at the end.  All
+// vertices use the per-class coefficient blocks of the level table, so
+// boundary and interior vertices take the same path.
+#include <cstring>
+
+#include "mg_internal.hpp"
+
+namespace mgk {
+
+namespace {
+
+__device__ inline void bar() { __syncthreads(); }
+
+// bytes of the shared scratch: NE corrections of level T (2 V_T entries) or
+// the FP64 right-hand side of the coarsest solve, whichever is larger
+template <typename T>
+__host__ __device__ inline size_t tail_scratch_bytes(int VT, int ncoarse) {
+  const size_t a = (size_t)2 * VT * sizeof(T), b = (size_t)ncoarse * sizeof(double);
+  return a > b ? a : b;
+}
+
+struct TailLevel {
+  int n, ld, V;
+  int ox, or_, of;  // LDS offsets (elements) of x, r, f (2V each)
+};
+
+template <typename T>
+struct TailArgs {
+  TailLevel lv[kTailMaxLevels + 1];  // indexed by level
+  Lev lev[kTailMaxLevels + 1];       // stencil constants and table pointer per level
+  int k0, tlev, nops, smoother;  // tlev: the top level of the tail
+  double tau;
+  const int4* ops;       // device op list
+  const double* lu;      // coarsest LU factors (row pivots piv)
+  const int* piv;
+  int ncoarse;
+  const T* fT;           // f on level T (global)
+  T* xT;                 // x on level T (global): in (if !first) / out
+  int first;             // 1: x_T starts at zero and r_T = f_T
+};
+
+}  // namespace
+
+template <typename T>
+__global__ __launch_bounds__(kTailThreads) void k_tail(TailArgs<T> A) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  T* sm = reinterpret_cast<T*>(smem_raw);
+  const int tid = threadIdx.x;
+  constexpr int NT = kTailThreads;
+  // shared layout after the level arrays: per-level class blocks, NE scratch p,
+  // coarsest LU (double)
+  const int Tl = A.tlev, k0 = A.k0;
+  int off_end = 0;
+  for (int l = k0; l <= Tl; l++) off_end = max(off_end, A.lv[l].of + 2 * A.lv[l].V);
+  T* tC = sm + off_end;                                 // 25 * kC5 per level l in (k0, T]
+  // NE scratch (2 V_T entries, also the coarse right-hand side in FP64), 16-byte aligned
+  T* sp = reinterpret_cast<T*>((reinterpret_cast<size_t>(tC + (kTailMaxLevels + 1) * 25 * kC5) + 15) & ~size_t(15));
+  double* slu = reinterpret_cast<double*>(
+      (reinterpret_cast<size_t>(sp) + tail_scratch_bytes<T>(A.lv[Tl].V, A.ncoarse) + 15) & ~size_t(15));
+  const int N0 = A.ncoarse;
+
+  // ---- load tables, LU, f_T and x_T
+  for (int l = k0 + 1; l <= Tl; l++)
+    for (int e = tid; e < 25 * kC5; e += NT) tC[l * 25 * kC5 + e] = (T)(&A.lev[l].tab->C5[0][0])[e];
+  for (int e = tid; e < N0 * N0; e += NT) slu[e] = A.lu[e];
+  {
+    const TailLevel& L = A.lv[Tl];
+    for (int e = tid; e < 2 * L.V; e += NT) {
+      const T fv = A.fT[e];
+      sm[L.of + e] = fv;
+      sm[L.ox + e] = A.first ? (T)0 : A.xT[e];
+    }
+  }
+  bar();
+
+  // (A x) at vertex (i, j) of level l from LDS array xa (both rows)
+  auto apply_v = [&](int l, const T* xa, int i, int j, T& ay, T& al) {
+    const TailLevel& L = A.lv[l];
+    const T* cb = &tC[(l * 25 + cls5(i, L.n) * 5 + cls5(j, L.n)) * kC5];
+    const T ainv = (T)A.lev[l].ainv;
+    ay = 0;
+    al = 0;
+#pragma unroll
+    for (int d = 0; d < kNDir; d++) {
+      const int ii = i + kDI[d], jj = j + kDJ[d];
+      if (ii < 0 || jj < 0 || ii > L.n || jj > L.n) continue;
+      const int m = jj * L.ld + ii;
+      const T a = xa[m], b = xa[L.V + m];
+      ay += cb[d] * a + cb[kNDir + d] * b;
+      al += cb[kNDir + d] * a - ainv * cb[d] * b;
+    }
+  };
+  // r = f - A x on level l
+  auto residual = [&](int l) {  // no barrier inside
+    const TailLevel& L = A.lv[l];
+    for (int v = tid; v < L.V; v += NT) {
+      const int j = v / L.ld, i = v - j * L.ld;
+      T ay, al;
+      apply_v(l, sm + L.ox, i, j, ay, al);
+      sm[L.or_ + v] = sm[L.of + v] - ay;
+      sm[L.or_ + L.V + v] = sm[L.of + L.V + v] - al;
+    }
+  };
+  // one vertex of a Gauss-Seidel-like phase: LSGS (Alg. 2) or collective GS
+  auto gs_vertex = [&](int l, int i, int j, bool collective) {
+    const TailLevel& L = A.lv[l];
+    const T* cb = &tC[(l * 25 + cls5(i, L.n) * 5 + cls5(j, L.n)) * kC5];
+    const T al = (T)A.lev[l].alpha, ainv = (T)A.lev[l].ainv;
+    T* ry = sm + L.or_;
+    T* rl = ry + L.V;
+    int m[kNDir];
+    bool in[kNDir];
+    T va[kNDir], vb[kNDir];
+#pragma unroll
+    for (int d = 0; d < kNDir; d++) {
+      const int ii = i + kDI[d], jj = j + kDJ[d];
+      in[d] = ii >= 0 && jj >= 0 && ii <= L.n && jj <= L.n;
+      m[d] = in[d] ? jj * L.ld + ii : j * L.ld + i;
+      va[d] = ry[m[d]];
+      vb[d] = rl[m[d]];
+    }
+    T py, pl;
+    if (!collective) {
+      T qy = 0, ql = 0;
+#pragma unroll
+      for (int d = 0; d < kNDir; d++) {
+        const T mm = cb[d], k = cb[kNDir + d], wi = cb[2 * kNDir + d];
+        qy += (mm * va[d] + al * k * vb[d]) * wi;
+        ql += (k * va[d] - mm * vb[d]) * wi;
+      }
+      py = qy * cb[3 * kNDir];
+      pl = ql * cb[3 * kNDir + 1];
+    } else {
+      const T b11 = cb[0], b12 = cb[kNDir], b21 = cb[kNDir], b22 = -ainv * cb[0];
+      const T det = b11 * b22 - b12 * b21;
+      py = (b22 * va[0] - b12 * vb[0]) / det;
+      pl = (b11 * vb[0] - b21 * va[0]) / det;
+    }
+    const int v = j * L.ld + i;
+    sm[L.ox + v] += py;
+    sm[L.ox + L.V + v] += pl;
+#pragma unroll
+    for (int d = 0; d < kNDir; d++) {
+      if (!in[d]) continue;
+      ry[m[d]] = va[d] - (cb[d] * py + cb[kNDir + d] * pl);
+      rl[m[d]] = vb[d] - (cb[kNDir + d] * py - ainv * (cb[d] * pl));
+    }
+  };
+  auto gs_sweep = [&](int l, bool reverse, bool collective) {
+    const TailLevel& L = A.lv[l];
+    const int S = (L.ld + 6) / 7;
+    for (int ph = 0; ph < 7; ph++) {
+      const int c = reverse ? 6 - ph : ph;
+      for (int k = tid; k < L.ld * S; k += NT) {
+        const int j = k / S, t = k - j * S;
+        const int i = ((c - 2 * j) % 7 + 7) % 7 + 7 * t;
+        if (i <= L.n) gs_vertex(l, i, j, collective);
+      }
+      bar();
+    }
+  };
+  // normal-equation step (Alg. 1): p = tau L^-1 A^T L^-1 r for all unknowns, x += p, r -= A p
+  auto ne_step = [&](int l) {
+    const TailLevel& L = A.lv[l];
+    const T al = (T)A.lev[l].alpha, tau = (T)A.tau;
+    const T* ry = sm + L.or_;
+    const T* rl = ry + L.V;
+    for (int v = tid; v < L.V; v += NT) {
+      const int j = v / L.ld, i = v - j * L.ld;
+      const T* cb = &tC[(l * 25 + cls5(i, L.n) * 5 + cls5(j, L.n)) * kC5];
+      T qy = 0, ql = 0, wv = 0;
+#pragma unroll
+      for (int d = 0; d < kNDir; d++) {
+        const int ii = i + kDI[d], jj = j + kDJ[d];
+        if (ii < 0 || jj < 0 || ii > L.n || jj > L.n) continue;
+        const int m = jj * L.ld + ii;
+        const T mm = cb[d], k = cb[kNDir + d], wi = cb[2 * kNDir + d];
+        qy += (mm * ry[m] + al * k * rl[m]) * wi;
+        ql += (k * ry[m] - mm * rl[m]) * wi;
+        if (d == 0) wv = wi;
+      }
+      const T py = tau * qy * wv, pl = tau * ql * (al * wv);
+      sp[v] = py;
+      sp[L.V + v] = pl;
+      sm[L.ox + v] += py;
+      sm[L.ox + L.V + v] += pl;
+    }
+    bar();
+    for (int v = tid; v < L.V; v += NT) {
+      const int j = v / L.ld, i = v - j * L.ld;
+      T ay, alv;
+      apply_v(l, sp, i, j, ay, alv);
+      sm[L.or_ + v] -= ay;
+      sm[L.or_ + L.V + v] -= alv;
+    }
+    bar();
+  };
+
+  // level T starts from x_T = 0 (r_T = f_T) or from the given x_T (r_T = f_T - A x_T)
+  if (A.first) {
+    const TailLevel& L = A.lv[Tl];
+    for (int e = tid; e < 2 * L.V; e += NT) sm[L.or_ + e] = sm[L.of + e];
+  } else {
+    residual(Tl);
+  }
+  bar();
+
+  for (int o = 0; o < A.nops; o++) {
+    const int4 op = A.ops[o];
+    const int l = op.y;
+    switch (op.x) {
+      case kTailSmooth:
+        for (int s = 0; s < op.z; s++) {
+          if (A.smoother == MG_TAIL_NE)
+            ne_step(l);
+          else if (A.smoother == MG_TAIL_LSGS)
+            gs_sweep(l, false, false);
+          else if (A.smoother == MG_TAIL_SLSGS) {
+            gs_sweep(l, false, false);
+            gs_sweep(l, true, false);
+          } else
+            gs_sweep(l, false, true);
+        }
+        break;
+      case kTailResidual:
+        residual(l);
+        bar();
+        break;
+      case kTailRestrict: {  // f_{l-1} = P^T r_l; if l-1 > k0: x_{l-1} = 0, r_{l-1} = f_{l-1}
+        const TailLevel& Lf = A.lv[l];
+        const TailLevel& Lc = A.lv[l - 1];
+        for (int w = tid; w < Lc.V; w += NT) {
+          const int J = w / Lc.ld, I = w - J * Lc.ld;
+          const int a = 2 * I, b = 2 * J;
+          T gy = sm[Lf.or_ + b * Lf.ld + a], gl = sm[Lf.or_ + Lf.V + b * Lf.ld + a];
+          T hy = 0, hl = 0;
+#pragma unroll
+          for (int d = 1; d < kNDir; d++) {
+            const int aa = a + kDI[d], bb = b + kDJ[d];
+            if (aa < 0 || bb < 0 || aa > Lf.n || bb > Lf.n) continue;
+            hy += sm[Lf.or_ + bb * Lf.ld + aa];
+            hl += sm[Lf.or_ + Lf.V + bb * Lf.ld + aa];
+          }
+          gy += (T)0.5 * hy;
+          gl += (T)0.5 * hl;
+          sm[Lc.of + w] = gy;
+          sm[Lc.of + Lc.V + w] = gl;
+          if (l - 1 > k0) {
+            sm[Lc.ox + w] = 0;
+            sm[Lc.ox + Lc.V + w] = 0;
+            sm[Lc.or_ + w] = gy;
+            sm[Lc.or_ + Lc.V + w] = gl;
+          }
+        }
+        bar();
+        break;
+      }
+      case kTailCoarse: {  // x_k0 = A_k0^{-1} f_k0, FP64 LU with row pivots
+        const TailLevel& Lc = A.lv[k0];
+        double* b = reinterpret_cast<double*>(sp);  // NE scratch is free here
+        for (int e = tid; e < N0; e += NT) b[e] = (double)sm[Lc.of + e];
+        bar();
+        if (tid == 0)
+          for (int k = 0; k < N0; k++)
+            if (A.piv[k] != k) {
+              const double t = b[k];
+              b[k] = b[A.piv[k]];
+              b[A.piv[k]] = t;
+            }
+        bar();
+        for (int k = 0; k < N0; k++) {
+          const double bk = b[k];
+          for (int i = k + 1 + tid; i < N0; i += NT) b[i] -= slu[i * N0 + k] * bk;
+          bar();
+        }
+        for (int k = N0 - 1; k >= 0; k--) {
+          if (tid == 0) b[k] /= slu[k * N0 + k];
+          bar();
+          const double bk = b[k];
+          for (int i = tid; i < k; i += NT) b[i] -= slu[i * N0 + k] * bk;
+          bar();
+        }
+        for (int e = tid; e < N0; e += NT) sm[Lc.ox + e] = (T)b[e];
+        bar();
+        break;
+      }
+      case kTailProlongResidual: {  // x_l += P x_{l-1}, then r_l = f_l - A x_l
+        const TailLevel& Lf = A.lv[l];
+        const TailLevel& Lc = A.lv[l - 1];
+        for (int u = tid; u < Lf.V; u += NT) {
+          const int b = u / Lf.ld, a = u - b * Lf.ld;
+          const int w0 = (b >> 1) * Lc.ld + (a >> 1), w1 = ((b + 1) >> 1) * Lc.ld + ((a + 1) >> 1);
+          T vy, vl;
+          if (w0 == w1) {
+            vy = sm[Lc.ox + w0];
+            vl = sm[Lc.ox + Lc.V + w0];
+          } else {
+            vy = (T)0.5 * (sm[Lc.ox + w0] + sm[Lc.ox + w1]);
+            vl = (T)0.5 * (sm[Lc.ox + Lc.V + w0] + sm[Lc.ox + Lc.V + w1]);
+          }
+          sm[Lf.ox + u] += vy;
+          sm[Lf.ox + Lf.V + u] += vl;
+        }
+        bar();
+        residual(l);
+        bar();
+        break;
+      }
+      default:
+        break;
+    }
+  }
+
+  // ---- x_T out
+  {
+    const TailLevel& L = A.lv[Tl];
+    for (int e = tid; e < 2 * L.V; e += NT) A.xT[e] = sm[L.ox + e];
+  }
+}
+
+// host-side layout of the tail: LDS offsets and bytes
+template <typename T>
+size_t tail_layout(int k0, int Tl, TailLevel* lv) {
+  int at = 0;
+  for (int l = k0; l <= Tl; l++) {
+    const int n = 1 << l;
+    lv[l].n = n;
+    lv[l].ld = n + 1;
+    lv[l].V = (n + 1) * (n + 1);
+    lv[l].ox = at;
+    at += 2 * lv[l].V;
+    lv[l].or_ = at;
+    at += 2 * lv[l].V;
+    lv[l].of = at;
+    at += 2 * lv[l].V;
+  }
+  const int N0 = 2 * ((1 << k0) + 1) * ((1 << k0) + 1);
+  return (size_t)at * sizeof(T) + (size_t)(kTailMaxLevels + 1) * 25 * kC5 * sizeof(T) + 16 +
+         tail_scratch_bytes<T>(lv[Tl].V, N0) + 16 + (size_t)N0 * N0 * sizeof(double);
+}
+
+template <typename T>
+hipError_t launch_tail(const TailLaunch& tl, const T* fT, T* xT, int first, hipStream_t s) {
+  TailArgs<T> a;
+  memset(&a, 0, sizeof(a));
+  const size_t bytes = tail_layout<T>(tl.k0, tl.T, a.lv);
+  if (bytes > tl.max_lds) return hipErrorInvalidValue;
+  for (int l = tl.k0; l <= tl.T; l++) a.lev[l] = tl.lev[l];
+  a.k0 = tl.k0;
+  a.tlev = tl.T;
+  a.nops = tl.nops;
+  a.ops = tl.ops;
+  a.smoother = tl.smoother;
+  a.tau = tl.tau;
+  a.lu = tl.lu;
+  a.piv = tl.piv;
+  a.ncoarse = tl.ncoarse;
+  a.fT = fT;
+  a.xT = xT;
+  a.first = first;
+  hipLaunchKernelGGL((k_tail<T>), dim3(1), dim3(kTailThreads), bytes, s, a);
+  return hipGetLastError();
+}
+
+template <typename T>
+size_t tail_lds_bytes(int k0, int Tl) {
+  TailLevel lv[kTailMaxLevels + 1];
+  return tail_layout<T>(k0, Tl, lv);
+}
+
+hipError_t tail_allow_lds(size_t bytes) {
+  hipError_t e = hipFuncSetAttribute((const void*)k_tail<double>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+  if (e != hipSuccess) return e;
+  return hipFuncSetAttribute((const void*)k_tail<float>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+}
+
+template hipError_t launch_tail<double>(const TailLaunch&, const double*, double*, int, hipStream_t);
+template hipError_t launch_tail<float>(const TailLaunch&, const float*, float*, int, hipStream_t);
+template size_t tail_lds_bytes<double>(int, int);
+template size_t tail_lds_bytes<float>(int, int);
+
+}  // namespace mgk

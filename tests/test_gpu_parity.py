@@ -132,6 +132,59 @@ def test_fused_sweep_matches_phase_kernels(torch_cuda, monkeypatch, level, smoot
     assert _relmax(_host(rb), _host(ra)) < 1e-13
 
 
+@pytest.mark.parametrize("smoother,gamma", [("lsgs", 1), ("ne", 1), ("slsgs", 2), ("cgs", 1)])
+@pytest.mark.parametrize("level", [4, 7])
+def test_coarse_tail_matches_level_kernels(torch_cuda, monkeypatch, level, smoother, gamma):
+    # the one-workgroup tail (levels <= 5 in LDS) against the per-level launches
+    torch = torch_cuda
+    mg = _mg()
+    alpha = 1e-4
+    nu = 1 if smoother == "slsgs" else 2
+    monkeypatch.setenv("MGKKT_NO_TAIL", "1")
+    sa = mg.Solver(level, alpha, smoother=smoother, gamma=gamma, nu1=nu, nu2=nu)
+    monkeypatch.delenv("MGKKT_NO_TAIL")
+    sb = mg.Solver(level, alpha, smoother=smoother, gamma=gamma, nu1=nu, nu2=nu)
+    yd = _dev(torch, workloads.desired_state(level, 1))
+    fa, fb = sa.rhs(yd), sb.rhs(yd)
+    xa = torch.zeros(sa.vec_len(), dtype=torch.float64, device="cuda")
+    xb = torch.zeros_like(xa)
+    for _ in range(3):
+        sa.cycle(fa, xa)
+        sb.cycle(fb, xb)
+    assert _relmax(_host(xb), _host(xa)) < 1e-12
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32_ir"])
+def test_graph_replays_match_eager(torch_cuda, monkeypatch, precision):
+    # mg_solve replays one captured iterate per cycle; after k replays the
+    # iterate equals k eager iterates bit for bit, for every k
+    torch = torch_cuda
+    mg = _mg()
+    level, alpha = 8, 1e-3
+    monkeypatch.setenv("MGKKT_NO_GRAPH", "1")
+    se = mg.Solver(level, alpha, precision=precision)
+    monkeypatch.delenv("MGKKT_NO_GRAPH")
+    sg = mg.Solver(level, alpha, precision=precision)
+    yd = _dev(torch, workloads.desired_state(level, 2))
+    f = se.rhs(yd)
+    for k in range(1, 6):
+        se.set_opts(max_cycles=k)
+        sg.set_opts(max_cycles=k)
+        xe, ie, re, ste = se.solve(f, tol=1e-14, raise_on_error=False)
+        xg, ig, rg, stg = sg.solve(f, tol=1e-14, raise_on_error=False)
+        assert ie == ig == k and ste == stg == mg.MG_ENOTCONV
+        assert torch.equal(xe, xg), k
+        assert re == rg
+    # sweep timing (the timed solve runs its kernels without the graph)
+    sg.set_opts(max_cycles=200)
+    sg.timing_enable(True)
+    xg, it, rel, st = sg.solve(f, tol=1e-10)
+    ms, n = sg.timing_read()
+    sg.timing_enable(False)
+    assert st == mg.MG_OK and n == 4 * it and ms > 0
+    torch.cuda.synchronize()
+
+
 CYCLE_CASES = [
     (5, 1e-2, "lsgs", 1),
     (5, 1e-2, "ne", 1),
