@@ -11,6 +11,8 @@ oracle timed on a bounded sample on the host cores.
 from __future__ import annotations
 
 import argparse
+import csv
+import hashlib
 import json
 import os
 import sys
@@ -22,6 +24,15 @@ if ROOT not in sys.path:
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
 METRIC = "V-cycles/s and HBM GB/s at 2049^2 Poisson control; time to rel. residual 1e-10"
+
+# The HBM traffic of the finest-level sweep is measured with hardware counters
+# (FETCH_SIZE, WRITE_SIZE) in separate profiler runs and recorded, together
+# with a hash of the sources the kernel is built from, in TRAFFIC_RECORD; the
+# figure is reported only while those sources are unchanged.
+SWEEP_SOURCES = ("paper_1502_03917_amd/csrc/sweep.hip", "paper_1502_03917_amd/csrc/mg_internal.hpp",
+                 "paper_1502_03917_amd/build.py")
+TRAFFIC_RECORD = os.path.join(ROOT, "profiles", "lsgs_sweep_2049sq_traffic.txt")
+COPY_MIB = 512  # size of the plain copy that calibrates the counters
 
 
 def log(msg: str) -> None:
@@ -40,6 +51,150 @@ def words_per_cycle(level: int, coarse: int, nu1: int, nu2: int, sweep_words: fl
     V = ((1 << level) + 1) ** 2
     total += 6 * V
     return total
+
+
+def sweep_source_hash() -> str:
+    h = hashlib.sha256()
+    for rel in SWEEP_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def read_record(path: str) -> dict:
+    out = {}
+    if os.path.exists(path):
+        for line in open(path):
+            if ":" in line and not line.startswith((" ", "#", "|")):
+                k, v = line.split(":", 1)
+                out[k.strip()] = v.strip()
+    return out
+
+
+def recorded_traffic(precision: str, level: int):
+    """HBM bytes per finest-level sweep from the counter record, or None when
+    the record is missing, was taken for another configuration, or the sweep
+    sources have changed since."""
+    rec = read_record(TRAFFIC_RECORD)
+    key = f"traffic_bytes_per_launch_{precision}"
+    if rec.get("source_hash") != sweep_source_hash() or rec.get("level") != str(level) or key not in rec:
+        return None
+    return float(rec[key])
+
+
+# --- profiler output summaries (rocprofv3 --output-format csv) ----------------
+
+def _csv_rows(directory: str, suffix: str):
+    rows = []
+    for dirpath, _, files in os.walk(directory):
+        for fn in files:
+            if fn.endswith(suffix):
+                with open(os.path.join(dirpath, fn), newline="") as fh:
+                    rows.extend(csv.DictReader(fh))
+    return rows
+
+
+def kernel_trace_summary(directory: str):
+    """Per (kernel, grid size) dispatch count and average duration in us."""
+    agg = {}
+    for r in _csv_rows(directory, "kernel_trace.csv"):
+        key = (r["Kernel_Name"], int(r.get("Grid_Size_X") or r.get("Grid_Size")))
+        d = (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) * 1e-3
+        a = agg.setdefault(key, [0, 0.0])
+        a[0] += 1
+        a[1] += d
+    return {k: (n, t / n) for k, (n, t) in agg.items()}
+
+
+def counter_summary(directory: str):
+    """Per (kernel, grid size, counter) dispatch count and average value."""
+    agg = {}
+    for r in _csv_rows(directory, "counter_collection.csv"):
+        key = (r["Kernel_Name"], int(r["Grid_Size"]), r["Counter_Name"])
+        a = agg.setdefault(key, [0, 0.0])
+        a[0] += 1
+        a[1] += float(r["Counter_Value"])
+    return {k: (n, v / n) for k, (n, v) in agg.items()}
+
+
+def finest_sweep_grid(level: int, precision: str, cus: int = 256) -> int:
+    """Work-items launched by the finest-level sweep (512-wide workgroups,
+    48 x 48 tiles): FP64 with two or more full rounds of tiles runs persistent
+    with balanced rounds, otherwise one workgroup per tile; grids are rounded
+    up to a multiple of 8."""
+    side = -(-((1 << level) + 1) // 48)
+    tiles = side * side
+    r8 = lambda v: -(-v // 8) * 8
+    if precision == "fp64" and tiles >= 2 * cus:
+        rounds = -(-tiles // cus)
+        return 512 * r8(-(-tiles // rounds))
+    return 512 * r8(tiles)
+
+
+def print_summary(args) -> int:
+    """Summarise a kernel trace (--trace DIR) or write the traffic record from
+    four counter runs (--fetch/--write over the bench, --copy-fetch/--copy-write
+    over `bench.py --copy-probe`)."""
+    if args.trace:
+        rows = sorted(kernel_trace_summary(args.trace).items(), key=lambda kv: -kv[1][0] * kv[1][1])
+        print(f"{'kernel':100s} {'grid':>9s} {'calls':>7s} {'avg_us':>10s} {'total_ms':>10s}")
+        for (name, grid), (n, avg) in rows:
+            print(f"{name[:100]:100s} {grid:9d} {n:7d} {avg:10.2f} {n * avg * 1e-3:10.3f}")
+        return 0
+    fetch, write = counter_summary(args.fetch), counter_summary(args.write)
+    cfetch, cwrite = counter_summary(args.copy_fetch), counter_summary(args.copy_write)
+    copy_bytes = COPY_MIB << 20
+
+    def copy_kib(table, counter):
+        # the copy probe's dispatches that move COPY_MIB (the largest copy kernel entries)
+        vals = [(n * v, n) for (name, _, c), (n, v) in table.items() if c == counter and "copy" in name.lower()]
+        tot, n = max(vals)
+        return tot / n
+
+    f_fetch = copy_bytes / (copy_kib(cfetch, "FETCH_SIZE") * 1024.0)
+    f_write = copy_bytes / (copy_kib(cwrite, "WRITE_SIZE") * 1024.0)
+    grid = finest_sweep_grid(args.level, args.precision)
+    sweep = [(k, v) for k, v in fetch.items() if "k_lsgs_tile" in k[0] and k[1] == grid]
+    wsweep = [(k, v) for k, v in write.items() if "k_lsgs_tile" in k[0] and k[1] == grid]
+    if len(sweep) != 1 or len(wsweep) != 1:
+        print("expected one finest-level sweep entry per counter run", sweep, wsweep, file=sys.stderr)
+        return 1
+    (kname, _, _), (nf, fk) = sweep[0]
+    (_, (nw, wk)) = wsweep[0]
+    rd, wr = fk * 1024.0 * f_fetch, wk * 1024.0 * f_write
+    V = ((1 << args.level) + 1) ** 2
+    wb = 4 if args.precision == "fp32_ir" else 8
+    print(f"# HBM traffic of the finest-level LSGS sweep, {(1 << args.level) + 1}^2 vertices, {args.precision}")
+    print(f"kernel: {kname}")
+    print(f"grid: {grid}")
+    print(f"level: {args.level}")
+    print(f"source_hash: {sweep_source_hash()}")
+    print(f"copy_fetch_factor: {f_fetch:.4f}")
+    print(f"copy_write_factor: {f_write:.4f}")
+    print(f"fetch_kib_per_dispatch: {fk:.1f}  (dispatches: {nf})")
+    print(f"write_kib_per_dispatch: {wk:.1f}  (dispatches: {nw})")
+    print(f"read_bytes_per_launch: {rd:.0f}")
+    print(f"write_bytes_per_launch: {wr:.0f}")
+    print(f"traffic_bytes_per_launch_{args.precision}: {rd + wr:.0f}")
+    print(f"algorithmic_bytes_per_launch: {8 * V * wb}")
+    print(f"traffic_over_algorithmic: {(rd + wr) / (8 * V * wb):.3f}")
+    return 0
+
+
+def copy_probe() -> int:
+    """A plain device-to-device copy of COPY_MIB, five times: the reference
+    that scales the traffic counters."""
+    import torch
+
+    n = (COPY_MIB << 20) // 8
+    a = torch.ones(n, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    torch.cuda.synchronize()
+    for _ in range(5):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes": n * 8, "copies": 5}), flush=True)
+    return 0
 
 
 def cpu_baseline(level: int, alpha: float, seed: int, smoother: str, cycles: int):
@@ -74,7 +229,16 @@ def main() -> int:
     ap.add_argument("--cpu-cycles", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--variants", action="store_true", help="also time the other smoother/precision/alpha variants")
+    ap.add_argument("--copy-probe", action="store_true", help="run only the plain copy that calibrates the counters")
+    ap.add_argument("--trace", help="summarise a rocprofv3 kernel-trace CSV directory and exit")
+    ap.add_argument("--fetch", help="FETCH_SIZE counter CSV directory of a bench run (with --write, --copy-*)")
+    ap.add_argument("--write", help="WRITE_SIZE counter CSV directory of a bench run")
+    ap.add_argument("--copy-fetch", help="FETCH_SIZE counter CSV directory of --copy-probe")
+    ap.add_argument("--copy-write", help="WRITE_SIZE counter CSV directory of --copy-probe")
     args = ap.parse_args()
+
+    if args.trace or args.fetch:
+        return print_summary(args)
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py: this solver runs on one GPU; --gpus must be 1 (multi-GPU sharding is design only)",
@@ -89,6 +253,8 @@ def main() -> int:
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
+    if args.copy_probe:
+        return copy_probe()
     yd = torch.from_numpy(workloads.desired_state(args.level, args.seed)).cuda()
 
     def run(smoother, precision, alpha, steps, warmup, timing=False):
@@ -138,6 +304,7 @@ def main() -> int:
     wbytes = 4 if args.precision == "fp32_ir" else 8
     sweep_bytes = 8 * V * wbytes  # read and write x and r, both fields
     achieved = sweep_bytes / (main_run["sweep_ms"] * 1e-3) / 1e9
+    traffic = recorded_traffic(args.precision, args.level)
     cyc_bytes = words_per_cycle(args.level, 1, 2, 2) * wbytes
     if args.precision == "fp32_ir":
         cyc_bytes += V * 2 * (8 + 8 + 8 + 4 + 8)  # FP64 residual (f, x -> r), scaled cast, FP64 update
@@ -166,9 +333,10 @@ def main() -> int:
         "unknown_updates_per_s": main_run["vcycles_per_s"] * sum(4 * 2 * ((1 << l) + 1) ** 2 for l in range(2, args.level + 1)),
         "cycle_algorithmic_GBps": main_run["vcycles_per_s"] * cyc_bytes / 1e9,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "kernel": "finest-level smoothing sweep", "sweep_ms": main_run["sweep_ms"],
-                     "algorithmic_bytes_per_sweep": sweep_bytes},
+                     "sweeps_timed": main_run["sweeps_timed"], "algorithmic_bytes_per_sweep": sweep_bytes,
+                     "traffic_unit": "bytes per launch"},
     }
     if args.variants:
         var = {}

@@ -116,6 +116,25 @@ int mg_set_opts(mg_ctx *ctx, const mg_opts *opts);
  * entries), f the fine-level right-hand side (2V entries), eq. mp2. */
 int mg_rhs(mg_ctx *ctx, const double *yd, double *f, void *stream);
 
+/* Control u = alpha^-1 lambda recovered from a solution x = (y; lambda) of
+ * eq. mp2 (section 1: the optimality condition alpha M u = M lambda).
+ * x: device, 2V entries; u: device, V entries (caller-owned).
+ * Poisson control only (MG_EUNSUPPORTED otherwise). */
+int mg_control(mg_ctx *ctx, const double *x, double *u, void *stream);
+
+/* Reverse-mode derivative of a loss of the solution of eq. mp2 with respect
+ * to the data y_D and the regularisation parameter alpha.  A_k is symmetric
+ * (eq. mp2), so the adjoint system A x_adj = dLoss/dx is solved with the same
+ * context (mg_solve on the right-hand side dLoss/dx).  Given the solution x
+ * and x_adj (device, 2V entries each):
+ *   grad_yd[V]    = M_k x_adj^y                    (f = (M_k y_D; 0))
+ *   *grad_alpha   = -alpha^-2 (x_adj^lambda)^T M_k lambda
+ *                   (dA/dalpha = blockdiag(0, alpha^-2 M_k))
+ * grad_yd and grad_alpha (one double) are device memory; the result is
+ * stream-ordered (no synchronisation).  Poisson control only. */
+int mg_adjoint_grad(mg_ctx *ctx, const double *x, const double *xadj, double *grad_yd, double *grad_alpha,
+                    void *stream);
+
 /* y = A_l x on level l (section 1, eq. mp2). */
 int mg_apply(mg_ctx *ctx, int level, const double *x, double *y, void *stream);
 

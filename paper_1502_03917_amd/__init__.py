@@ -75,6 +75,8 @@ def lib():
     L.mg_get_opts.argtypes = [vp, ctypes.POINTER(MgOpts)]
     L.mg_set_opts.argtypes = [vp, ctypes.POINTER(MgOpts)]
     L.mg_rhs.argtypes = [vp, vp, vp, vp]
+    L.mg_control.argtypes = [vp, vp, vp, vp]
+    L.mg_adjoint_grad.argtypes = [vp, vp, vp, vp, vp, vp]
     L.mg_apply.argtypes = [vp, ip, vp, vp, vp]
     L.mg_residual.argtypes = [vp, ip, vp, vp, vp, ctypes.POINTER(dp), vp]
     L.mg_smooth.argtypes = [vp, ip, vp, vp, ip, vp]
@@ -89,7 +91,7 @@ def lib():
     L.mg_strerror.argtypes = [ip]
     L.mg_last_error.restype = ctypes.c_char_p
     L.mg_last_error.argtypes = [vp]
-    for name in ("mg_setup", "mg_get_opts", "mg_set_opts", "mg_rhs", "mg_apply", "mg_residual", "mg_smooth",
+    for name in ("mg_setup", "mg_get_opts", "mg_set_opts", "mg_rhs", "mg_control", "mg_adjoint_grad", "mg_apply", "mg_residual", "mg_smooth",
                  "mg_restrict", "mg_prolong_add", "mg_coarse_solve", "mg_cycle", "mg_solve", "mg_timing_enable",
                  "mg_timing_read"):
         getattr(L, name).restype = ip
@@ -199,6 +201,22 @@ class Solver:
         self._check(lib().mg_rhs(self._h, self._t(yd, self.nvert(), "yd"), self._t(f, self.vec_len(), "f"), _stream()), "mg_rhs")
         return f
 
+    def control(self, x, u=None):
+        """u = lambda / alpha (section 1)."""
+        u = self._empty(self.nvert()) if u is None else u
+        self._check(lib().mg_control(self._h, self._t(x, self.vec_len(), "x"), self._t(u, self.nvert(), "u"), _stream()),
+                    "mg_control")
+        return u
+
+    def adjoint_grad(self, x, xadj, grad_yd=None, grad_alpha=None):
+        """(M x_adj^y, -alpha^-2 (x_adj^lambda)^T M lambda) as device tensors."""
+        g = self._empty(self.nvert()) if grad_yd is None else grad_yd
+        a = self._empty(1) if grad_alpha is None else grad_alpha
+        st = lib().mg_adjoint_grad(self._h, self._t(x, self.vec_len(), "x"), self._t(xadj, self.vec_len(), "xadj"),
+                                   self._t(g, self.nvert(), "grad_yd"), self._t(a, 1, "grad_alpha"), _stream())
+        self._check(st, "mg_adjoint_grad")
+        return g, a
+
     def apply(self, x, level: int | None = None, y=None):
         l = self.level if level is None else level
         n = self.level_len(l)
@@ -268,3 +286,79 @@ class Solver:
         n = ctypes.c_long(0)
         self._check(lib().mg_timing_read(self._h, ctypes.byref(ms), ctypes.byref(n)), "mg_timing_read")
         return ms.value, n.value
+
+
+# --- differentiable solve ---------------------------------------------------------
+
+_ACCEPT = (MG_OK, MG_ESTALL)  # a stall is convergence to the rounding floor
+
+
+def _solve_or_raise(solver: "Solver", f, tol: float):
+    import torch
+
+    x = torch.zeros(solver.vec_len(), dtype=torch.float64, device="cuda")
+    x, _, _, st = solver.solve(f, x, tol=tol, raise_on_error=False)
+    if st not in _ACCEPT:
+        solver._check(st, "mg_solve")
+    return x
+
+
+def _make_function():
+    import torch
+
+    class MGSolve(torch.autograd.Function):
+        """x = A(alpha)^-1 (M y_D; 0), eq. mp2, with a hand-written backward:
+        the adjoint system A x_adj = dLoss/dx (A symmetric) is solved by the
+        same multigrid, then dLoss/dy_D = M x_adj^y and
+        dLoss/dalpha = -alpha^-2 (x_adj^lambda)^T M lambda."""
+
+        @staticmethod
+        def forward(ctx, yd, alpha, solver, tol):
+            f = solver.rhs(yd.detach().contiguous())
+            x = _solve_or_raise(solver, f, tol)
+            ctx.save_for_backward(x)
+            ctx.solver, ctx.tol = solver, tol
+            ctx.alpha_shape = alpha.shape
+            return x
+
+        @staticmethod
+        def backward(ctx, gx):
+            (x,) = ctx.saved_tensors
+            xa = _solve_or_raise(ctx.solver, gx.contiguous(), ctx.tol)
+            gyd, ga = ctx.solver.adjoint_grad(x, xa)
+            return gyd, ga.reshape(ctx.alpha_shape), None, None
+
+    return MGSolve
+
+
+_MGSolve = None
+_SOLVERS: dict = {}
+
+
+def mg_solve_fn():
+    """The torch.autograd.Function of the differentiable solve."""
+    global _MGSolve
+    if _MGSolve is None:
+        _MGSolve = _make_function()
+    return _MGSolve
+
+
+def solve(yd, alpha, level: int, tol: float = 1e-12, **opts):
+    """Differentiable solve of eq. mp2 for desired state yd ((2^level+1)^2
+    nodal values, FP64 CUDA tensor) and alpha (float or 0-d/1-element FP64
+    tensor).  Returns (y, lam, u): y and lam are differentiable views of the
+    solution; u = lam / alpha is computed by the library and carries no
+    gradient (differentiate lam / alpha instead).  Solvers are cached per
+    (level, alpha, options)."""
+    import torch
+
+    a = alpha if isinstance(alpha, torch.Tensor) else torch.tensor(float(alpha), dtype=torch.float64, device="cuda")
+    key = (level, float(a.detach().cpu()), tuple(sorted(opts.items())))
+    s = _SOLVERS.get(key)
+    if s is None:
+        s = _SOLVERS[key] = Solver(level, key[1], **opts)
+    x = mg_solve_fn().apply(yd, a, s, tol)
+    V = s.nvert()
+    with torch.no_grad():
+        u = s.control(x.detach())
+    return x[:V], x[V:], u

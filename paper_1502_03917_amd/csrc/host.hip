@@ -729,6 +729,25 @@ int mg_rhs(mg_ctx* ctx, const double* yd, double* f, void* stream) {
   return MG_OK;
 }
 
+int mg_control(mg_ctx* ctx, const double* x, double* u, void* stream) {
+  if (!ctx || !x || !u) return MG_EINVAL;
+  if (ctx->problem != MG_POISSON) return fail(ctx, MG_EUNSUPPORTED, "mg_control: Poisson control only");
+  HIPCHK(ctx, mgk::launch_control(L_(ctx, ctx->level).lev, x, u, (hipStream_t)stream));
+  return MG_OK;
+}
+
+int mg_adjoint_grad(mg_ctx* ctx, const double* x, const double* xadj, double* grad_yd, double* grad_alpha,
+                    void* stream) {
+  if (!ctx || !x || !xadj || !grad_yd || !grad_alpha) return MG_EINVAL;
+  if (ctx->problem != MG_POISSON) return fail(ctx, MG_EUNSUPPORTED, "mg_adjoint_grad: Poisson control only");
+  hipStream_t s = (hipStream_t)stream;
+  const LevelBuf& b = L_(ctx, ctx->level);
+  int nb = 0;
+  HIPCHK(ctx, mgk::launch_adjoint_grad(b.lev, x, xadj, grad_yd, ctx->d_part, &nb, s));
+  HIPCHK(ctx, mgk::launch_sum(ctx->d_part, nb, grad_alpha, s, -1.0 / (ctx->alpha * ctx->alpha)));
+  return MG_OK;
+}
+
 int mg_apply(mg_ctx* ctx, int level, const double* x, double* y, void* stream) {
   if (!ctx || !x || !y || !check_level(ctx, level, false)) return MG_EINVAL;
   HIPCHK(ctx, mgk::launch_apply<double>(L_(ctx, level).lev, x, y, (hipStream_t)stream));

@@ -246,6 +246,52 @@ __global__ __launch_bounds__(kNT) void k_rhs(Lev L, const double* __restrict__ y
   f[L.V + v] = (T)0;
 }
 
+// (M v)_w of one field at vertex (i, j)
+__device__ inline double mass_at(const Lev& L, int i, int j, const double* __restrict__ v) {
+  const int w = j * L.ld + i;
+  if (i >= 1 && i < L.n && j >= 1 && j < L.n) {
+    const int ld = L.ld;
+    return L.Mc * v[w] + L.Mo * ((v[w + 1] + v[w - 1] + v[w + ld] + v[w - ld]) + (v[w + ld + 1] + v[w - ld - 1]));
+  }
+  double M[kNDir], K[kNDir];
+  coef_MK(L, i, j, M, K);
+  double s = 0.0;
+#pragma unroll
+  for (int d = 0; d < kNDir; d++) {
+    const int ii = i + kDI[d], jj = j + kDJ[d];
+    if (inside(L, ii, jj)) s += M[d] * v[jj * L.ld + ii];
+  }
+  return s;
+}
+
+// Gradient of a loss of the solution x of eq. mp2 through the adjoint x_a
+// (A x_a = dLoss/dx, A symmetric): the right-hand side (M y_D; 0) gives
+// dLoss/dy_D = M x_a^y, and dA/dalpha = blockdiag(0, alpha^-2 M) gives
+// dLoss/dalpha = -alpha^-2 (x_a^lambda)^T M lambda; this kernel stores the
+// first and per-block partial sums of (x_a^lambda)^T M lambda.
+__global__ __launch_bounds__(kNT) void k_adjoint_grad(Lev L, const double* __restrict__ x,
+                                                      const double* __restrict__ xa, double* __restrict__ gyd,
+                                                      double* __restrict__ part) {
+  const int i = blockIdx.x * kBX + threadIdx.x;
+  const int j = blockIdx.y * kBY + threadIdx.y;
+  double s = 0.0;
+  if (i <= L.n && j <= L.n) {
+    const int v = j * L.ld + i;
+    gyd[v] = mass_at(L, i, j, xa);
+    s = xa[L.V + v] * mass_at(L, i, j, x + L.V);
+  }
+  block_sum_store(s, &part[blockIdx.y * gridDim.x + blockIdx.x]);
+}
+
+// control u = alpha^-1 lambda (section 1)
+__global__ __launch_bounds__(kNT) void k_control(Lev L, const double* __restrict__ x, double* __restrict__ u) {
+  const int i = blockIdx.x * kBX + threadIdx.x;
+  const int j = blockIdx.y * kBY + threadIdx.y;
+  if (i > L.n || j > L.n) return;
+  const int v = j * L.ld + i;
+  u[v] = x[L.V + v] * L.ainv;
+}
+
 // Alg. 1, first loop, fused with x += p: p_i = tau (A^T L^{-1} r)_i / L_ii
 template <typename T>
 __global__ __launch_bounds__(kNT) void k_ne_p(Lev L, T* __restrict__ x, const T* __restrict__ r, T* __restrict__ p) {
@@ -422,7 +468,8 @@ __global__ __launch_bounds__(256) void k_coarse_solve(int N, const double* __res
   for (int i = tid; i < N; i += blockDim.x) x[i] = (T)b[i];
 }
 
-__global__ __launch_bounds__(256) void k_sum(const double* __restrict__ part, int n, double* __restrict__ out) {
+__global__ __launch_bounds__(256) void k_sum(const double* __restrict__ part, int n, double scale,
+                                             double* __restrict__ out) {
   __shared__ double sh[4];
   const int tid = threadIdx.x;
   double s = 0.0;
@@ -430,7 +477,7 @@ __global__ __launch_bounds__(256) void k_sum(const double* __restrict__ part, in
   s = wave_sum(s);
   if ((tid & 63) == 0) sh[tid >> 6] = s;
   __syncthreads();
-  if (tid == 0) *out = (sh[0] + sh[1]) + (sh[2] + sh[3]);
+  if (tid == 0) *out = scale * ((sh[0] + sh[1]) + (sh[2] + sh[3]));
 }
 
 __global__ __launch_bounds__(256) void k_sumsq(const double* __restrict__ v, size_t n, double* __restrict__ part) {
@@ -553,8 +600,21 @@ hipError_t launch_coarse_solve(int N, const double* lu, const int* piv, const T*
   return hipGetLastError();
 }
 
-hipError_t launch_sum(const double* part, int n, double* out, hipStream_t s) {
-  hipLaunchKernelGGL(k_sum, dim3(1), dim3(256), 0, s, part, n, out);
+hipError_t launch_sum(const double* part, int n, double* out, hipStream_t s, double scale) {
+  hipLaunchKernelGGL(k_sum, dim3(1), dim3(256), 0, s, part, n, scale, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_adjoint_grad(const Lev& L, const double* x, const double* xa, double* gyd, double* part,
+                               int* nblocks, hipStream_t s) {
+  const dim3 g = grid_vertices(L.n);
+  *nblocks = (int)(g.x * g.y);
+  hipLaunchKernelGGL(k_adjoint_grad, g, kBlock, 0, s, L, x, xa, gyd, part);
+  return hipGetLastError();
+}
+
+hipError_t launch_control(const Lev& L, const double* x, double* u, hipStream_t s) {
+  hipLaunchKernelGGL(k_control, grid_vertices(L.n), kBlock, 0, s, L, x, u);
   return hipGetLastError();
 }
 

@@ -101,7 +101,13 @@ template <typename T>
 size_t tail_lds_bytes(int k0, int Tl);
 hipError_t tail_allow_lds(size_t bytes);
 
-hipError_t launch_sum(const double* part, int n, double* out, hipStream_t s);
+// *out = scale * (sum of the n partials)
+hipError_t launch_sum(const double* part, int n, double* out, hipStream_t s, double scale = 1.0);
+// gyd = M xa^y; part = per-block partial sums of (xa^lambda)^T M lambda
+hipError_t launch_adjoint_grad(const Lev& L, const double* x, const double* xa, double* gyd, double* part,
+                               int* nblocks, hipStream_t s);
+// u = lambda / alpha
+hipError_t launch_control(const Lev& L, const double* x, double* u, hipStream_t s);
 hipError_t launch_sumsq(const double* v, size_t n, double* part, int* nblocks, hipStream_t s);
 
 // FP32-preconditioned iterative refinement glue

@@ -64,7 +64,10 @@ struct TileGeom {
   static constexpr int RN = RP * (RMAX + 2);   // region cells with guard rows
 };
 
-template <typename T, int TW, int NT>
+// PERSIST: fewer workgroups than tiles; each loops over tiles (round r takes
+// tile r * gridDim.x + its slot) and loads the next tile into registers while
+// the current one is computed.  Otherwise one tile per workgroup.
+template <typename T, int TW, int NT, bool PERSIST>
 __global__ __launch_bounds__(NT) void k_lsgs_tile(Lev L, int ntx, int nty, int reverse, T* __restrict__ x,
                                                   const T* __restrict__ rin, T* __restrict__ rout) {
   using G = TileGeom<TW>;
@@ -84,12 +87,12 @@ __global__ __launch_bounds__(NT) void k_lsgs_tile(Lev L, int ntx, int nty, int r
   const __amdgpu_buffer_rsrc_t Rin = make_rsrc(rin, vbytes), Rout = make_rsrc(rout, vbytes), Rx = make_rsrc(x, vbytes);
   const unsigned fo = (unsigned)(V * sizeof(T));  // byte offset of the lambda field
 
-  // Tiles are processed in rounds of nblk; in a round, the blocks of one XCD
-  // (bid % 8) take a contiguous run of tiles, which share halo rows in its L2.
-  auto tile_of = [&](int round) -> int {
-    const int local = (nblk % 8 == 0) ? (bid % 8) * (nblk / 8) + bid / 8 : bid;
-    return round * nblk + local;
-  };
+  // The workgroups of one XCD (bid % 8) take a contiguous run of tiles, which
+  // share halo rows in that XCD's L2 (the grid is a multiple of 8).
+  const int slot = (nblk % 8 == 0) ? (bid % 8) * (nblk / 8) + bid / 8 : bid;
+  const int nrounds = PERSIST ? (ntiles + nblk - 1) / nblk : 1;
+  auto tile_of = [&](int round) { return round * nblk + slot; };
+  if (slot >= ntiles) return;  // padding workgroup
   struct Box {
     int i0, i1, j0, j1, ci0, ci1, rj0, rj1;
   };
@@ -107,17 +110,17 @@ __global__ __launch_bounds__(NT) void k_lsgs_tile(Lev L, int ntx, int nty, int r
     return b;
   };
 
-  // registers holding the next tile's region of r and its owned x
+  // the tile's region of r and its owned x, loaded into registers first so
+  // that every load is in flight before the first LDS store
   T ry[NR], rl[NR], xy[NX], xl[NX];
   auto fetch = [&](int tile) {
-    const bool live = tile < ntiles;
-    const Box b = box_of(live ? tile : 0);
+    const Box b = box_of(tile);
     const int RW = b.ci1 - b.ci0, RH = b.rj1 - b.rj0, OW = b.i1 - b.i0, OH = b.j1 - b.j0;
 #pragma unroll
     for (int q = 0; q < NX; q++) {
       const int e = tid + q * NT;
       const int oj = e / TW, oi = e - oj * TW;
-      const bool ok = live && e < TW * TW && oi < OW && oj < OH;
+      const bool ok = e < TW * TW && oi < OW && oj < OH;
       const unsigned o = ok ? (unsigned)(((b.j0 + oj) * ld + b.i0 + oi) * sizeof(T)) : kOff;
       xy[q] = bload(Rx, o, (T*)nullptr);
       xl[q] = bload(Rx, ok ? o + fo : kOff, (T*)nullptr);
@@ -126,7 +129,7 @@ __global__ __launch_bounds__(NT) void k_lsgs_tile(Lev L, int ntx, int nty, int r
     for (int q = 0; q < NR; q++) {
       const int e = tid + q * NT;
       const int lr = e / G::RMAX, li = e - lr * G::RMAX;
-      const bool ok = live && e < G::RMAX * G::RMAX && li < RW && lr < RH;
+      const bool ok = e < G::RMAX * G::RMAX && li < RW && lr < RH;
       const unsigned o = ok ? (unsigned)(((b.rj0 + lr) * ld + b.ci0 + li) * sizeof(T)) : kOff;
       ry[q] = bload(Rin, o, (T*)nullptr);
       rl[q] = bload(Rin, ok ? o + fo : kOff, (T*)nullptr);
@@ -134,7 +137,7 @@ __global__ __launch_bounds__(NT) void k_lsgs_tile(Lev L, int ntx, int nty, int r
   };
   // region r into LDS, corrections cleared
   auto stash = [&](int tile) {
-    const Box b = box_of(tile < ntiles ? tile : 0);
+    const Box b = box_of(tile);
     const int RW = b.ci1 - b.ci0, RH = b.rj1 - b.rj0;
 #pragma unroll
     for (int q = 0; q < NR; q++) {
@@ -151,9 +154,6 @@ __global__ __launch_bounds__(NT) void k_lsgs_tile(Lev L, int ntx, int nty, int r
       dxl[e] = (T)0;
     }
   };
-
-  const int nrounds = (ntiles + nblk - 1) / nblk;
-  if (tile_of(0) >= ntiles) return;  // uniform per block: no tile for this block
 
   {
     constexpr int NC = (25 * kC5 + NT - 1) / NT;
@@ -174,19 +174,21 @@ __global__ __launch_bounds__(NT) void k_lsgs_tile(Lev L, int ntx, int nty, int r
 
   for (int round = 0; round < nrounds; round++) {
     const int tile = tile_of(round);
-    if (tile >= ntiles) break;  // uniform per block
+    const bool more = PERSIST && round + 1 < nrounds && tile_of(round + 1) < ntiles;  // uniform per block
     const Box b = box_of(tile);
     const int i0 = b.i0, i1 = b.i1, j0 = b.j0, j1 = b.j1, ci0 = b.ci0, ci1 = b.ci1, rj0 = b.rj0, rj1 = b.rj1;
     const int OW = i1 - i0, OH = j1 - j0;
-    // x of this tile, loaded with the previous fetch
+    // this tile's x (registers of the previous fetch), then the next tile's
+    // loads are put in flight
     T cxy[NX], cxl[NX];
 #pragma unroll
     for (int q = 0; q < NX; q++) {
       cxy[q] = xy[q];
       cxl[q] = xl[q];
     }
-    // the next tile's data is in flight while this tile is computed
-    fetch(tile_of(round + 1));
+    if constexpr (PERSIST) {
+      if (more) fetch(tile_of(round + 1));
+    }
 
     // one update of the vertex at region cell (lr, li)
     auto update = [&](int lr, int li) {
@@ -296,6 +298,7 @@ __global__ __launch_bounds__(NT) void k_lsgs_tile(Lev L, int ntx, int nty, int r
       bstore(Rx, o, cxy[q] + dxy[od]);
       bstore(Rx, o2, cxl[q] + dxl[od]);
     }
+    if (!more) break;
     lds_barrier();
     stash(tile_of(round + 1));
     lds_barrier();
@@ -304,24 +307,40 @@ __global__ __launch_bounds__(NT) void k_lsgs_tile(Lev L, int ntx, int nty, int r
 
 inline int tiles_along(int npts, int TW) { return (npts + TW - 1) / TW; }
 
-// persistent launch: at most `resident` workgroups, each looping over tiles
-template <typename T, int TW, int NT>
-hipError_t launch_tile_cfg(const Lev& L, int resident, int reverse, T* x, const T* rin, T* rout, hipStream_t s) {
-  const int nt = tiles_along(L.n + 1, TW);
-  const int nblk = nt * nt < resident ? nt * nt : resident;
-  hipLaunchKernelGGL((k_lsgs_tile<T, TW, NT>), dim3(nblk), dim3(NT), 0, s, L, nt, nt, reverse, x, rin, rout);
-  return hipGetLastError();
-}
+// Grid shape.  With one workgroup resident per CU (FP64: the tile needs
+// 139 KB of LDS) and at least two full rounds of tiles, the launch is
+// persistent: the rounds are balanced (every workgroup gets the same number
+// of tiles, up to one) and the next tile's loads overlap the current tile's
+// LDS work.  Otherwise (fewer tiles, or FP32 with two workgroups per CU that
+// overlap each other) one workgroup per tile.  Grids are multiples of 8 for
+// the XCD-aware order; spare workgroups exit at once.
+inline int round8(int v) { return (v + 7) / 8 * 8; }
 
-// workgroups that fit on the device at once (multiprocessors x per-CU count)
-int resident_blocks(int per_cu) {
+int cu_count() {
   static int cus = 0;
   if (cus == 0) {
     int dev = 0;
-    if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0)
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0)
       cus = 256;
   }
-  return cus * per_cu;
+  return cus;
+}
+
+template <typename T, int TW, int NT>
+hipError_t launch_tile_cfg(const Lev& L, bool allow_persistent, int reverse, T* x, const T* rin, T* rout,
+                           hipStream_t s) {
+  const int nt = tiles_along(L.n + 1, TW);
+  const int tiles = nt * nt, resident = cu_count();
+  if (allow_persistent && tiles >= 2 * resident) {
+    const int rounds = (tiles + resident - 1) / resident;
+    const int nblk = round8((tiles + rounds - 1) / rounds);
+    hipLaunchKernelGGL((k_lsgs_tile<T, TW, NT, true>), dim3(nblk), dim3(NT), 0, s, L, nt, nt, reverse, x, rin, rout);
+  } else {
+    hipLaunchKernelGGL((k_lsgs_tile<T, TW, NT, false>), dim3(round8(tiles)), dim3(NT), 0, s, L, nt, nt, reverse, x,
+                       rin, rout);
+  }
+  return hipGetLastError();
 }
 
 }  // namespace
@@ -329,13 +348,13 @@ int resident_blocks(int per_cu) {
 template <>
 hipError_t launch_lsgs_sweep<double>(const Lev& L, int reverse, double* x, const double* rin, double* rout,
                                      hipStream_t s) {
-  return launch_tile_cfg<double, 48, 512>(L, resident_blocks(1), reverse, x, rin, rout, s);
+  return launch_tile_cfg<double, 48, 512>(L, true, reverse, x, rin, rout, s);
 }
 
 template <>
 hipError_t launch_lsgs_sweep<float>(const Lev& L, int reverse, float* x, const float* rin, float* rout,
                                     hipStream_t s) {
-  return launch_tile_cfg<float, 48, 512>(L, resident_blocks(2), reverse, x, rin, rout, s);
+  return launch_tile_cfg<float, 48, 512>(L, false, reverse, x, rin, rout, s);
 }
 
 }  // namespace mgk

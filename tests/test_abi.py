@@ -84,6 +84,8 @@ def test_null_context_calls():
     assert L.mg_rhs(None, None, None, None) == mg.MG_EINVAL
     assert L.mg_smooth(None, 3, None, None, 1, None) == mg.MG_EINVAL
     assert L.mg_timing_enable(None, 1) == mg.MG_EINVAL
+    assert L.mg_control(None, None, None, None) == mg.MG_EINVAL
+    assert L.mg_adjoint_grad(None, None, None, None, None, None) == mg.MG_EINVAL
     L.mg_destroy(None)
 
 

@@ -1,0 +1,121 @@
+"""GPU: reverse-mode derivatives of the solution of eq. mp2 (section 1) with
+respect to the desired state y_D and alpha, through the C ABI
+(mg_adjoint_grad, mg_control) and the torch.autograd.Function whose backward
+solves the adjoint system with the same multigrid (A symmetric)."""
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+
+    assert torch.cuda.is_available(), "GPU tests need a visible GPU"
+    return torch
+
+
+def _dev(torch, a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).cuda()
+
+
+def _host(t):
+    import torch
+
+    torch.cuda.synchronize()
+    return t.detach().cpu().numpy()
+
+
+@pytest.mark.parametrize("alpha", [1.0, 1e-4])
+@pytest.mark.parametrize("level", [3, 6])
+def test_gradient_kernel_and_control(torch_cuda, level, alpha):
+    """grad_yd = M x_adj^y, grad_alpha = -alpha^-2 (x_adj^lambda)^T M lambda,
+    u = lambda / alpha on seeded vectors, against the oracle's assembled M."""
+    import paper_1502_03917_amd as mg
+
+    torch = torch_cuda
+    s = mg.Solver(level, alpha)
+    h = oracle.Hierarchy(level, alpha, coarse=1)
+    M = h.matrix("M")
+    V = M.shape[0]
+    x = workloads.uniform(2 * V, 31)
+    xa = workloads.uniform(2 * V, 32)
+    gyd, ga = s.adjoint_grad(_dev(torch, x), _dev(torch, xa))
+    ref_g = M @ xa[:V]
+    ref_a = -float(xa[V:] @ (M @ x[V:])) / alpha**2
+    assert np.abs(_host(gyd) - ref_g).max() <= 1e-14 * np.abs(ref_g).max()
+    assert _host(ga)[0] == pytest.approx(ref_a, rel=1e-12)
+    u = _host(s.control(_dev(torch, x)))
+    assert np.abs(u - x[V:] / alpha).max() <= 1e-15 * np.abs(x[V:] / alpha).max()
+
+
+def _loss(torch, y, yt):
+    return 0.5 * torch.dot(y - yt, y - yt)
+
+
+@pytest.mark.parametrize("alpha", [1e-2, 1e-4])
+def test_autograd_matches_oracle_gradient(torch_cuda, alpha):
+    """Loss 0.5 ||y - y_target||^2: the autograd gradient against the oracle's
+    adjoint gradient (both solves to relative residual 1e-13)."""
+    import paper_1502_03917_amd as mg
+
+    torch = torch_cuda
+    level = 6
+    h = oracle.Hierarchy(level, alpha, coarse=1)
+    yd_np = workloads.desired_state(level, 4)
+    yt_np = workloads.desired_state(level, 5)
+    loss_ref, g_ref, a_ref, x_ref, _ = oracle.adjoint_gradient(h, yd_np, yt_np, tol=1e-13)
+    yd = _dev(torch, yd_np).requires_grad_(True)
+    al = torch.tensor(alpha, dtype=torch.float64, device="cuda", requires_grad=True)
+    y, lam, u = mg.solve(yd, al, level, tol=1e-13)
+    loss = _loss(torch, y, _dev(torch, yt_np))
+    loss.backward()
+    V = yd_np.size
+    assert np.abs(_host(y) - x_ref[:V]).max() <= 1e-10 * np.abs(x_ref[:V]).max()
+    assert _host(u) == pytest.approx(x_ref[V:] / alpha, rel=1e-9, abs=1e-9 * np.abs(x_ref[V:] / alpha).max())
+    assert float(loss) == pytest.approx(loss_ref, rel=1e-10)
+    g = _host(yd.grad)
+    assert np.abs(g - g_ref).max() <= 1e-9 * np.abs(g_ref).max()
+    assert float(al.grad) == pytest.approx(a_ref, rel=1e-9)
+
+
+def test_gradient_matches_central_differences_1025(torch_cuda):
+    """1025^2 vertices, alpha = 1e-4, y_D seed 4, y_target seed 5, direction
+    seed 6: central differences with step 1e-6 (relative for alpha, absolute
+    along a unit-max-norm direction for y_D) against the adjoint gradient.
+    Loss differences are 1e-6 of the loss, so solve rounding (relative
+    residual ~1e-13) limits the agreement to about 1e-6."""
+    import paper_1502_03917_amd as mg
+
+    torch = torch_cuda
+    level, alpha = 10, 1e-4
+    yd_np = workloads.desired_state(level, 4)
+    yt = _dev(torch, workloads.desired_state(level, 5))
+    e_np = workloads.uniform(yd_np.size, 6)
+    e_np /= np.abs(e_np).max()
+    yd = _dev(torch, yd_np).requires_grad_(True)
+    al = torch.tensor(alpha, dtype=torch.float64, device="cuda", requires_grad=True)
+    y, _, _ = mg.solve(yd, al, level, tol=1e-14)
+    _loss(torch, y, yt).backward()
+    g_dir = float(torch.dot(yd.grad, _dev(torch, e_np)))
+    g_al = float(al.grad)
+
+    def L(yd_v, a):
+        with torch.no_grad():
+            yy, _, _ = mg.solve(yd_v, a, level, tol=1e-14)
+            return float(_loss(torch, yy, yt))
+
+    eps = 1e-6
+    e = _dev(torch, e_np)
+    fd_dir = (L(yd.detach() + eps * e, alpha) - L(yd.detach() - eps * e, alpha)) / (2 * eps)
+    d = 1e-6 * alpha
+    fd_al = (L(yd.detach(), alpha + d) - L(yd.detach(), alpha - d)) / (2 * d)
+    err_dir = abs(fd_dir - g_dir) / abs(g_dir)
+    err_al = abs(fd_al - g_al) / abs(g_al)
+    print(f"directional y_D: adjoint {g_dir:.12e} fd {fd_dir:.12e} rel {err_dir:.2e}; "
+          f"alpha: adjoint {g_al:.12e} fd {fd_al:.12e} rel {err_al:.2e}", flush=True)
+    assert err_dir <= 1e-6 and err_al <= 1e-6
