@@ -186,6 +186,42 @@ const char *mg_strerror(int status);
 /* Last error message recorded on the context ("" if none; static text for NULL). */
 const char *mg_last_error(const mg_ctx *ctx);
 
+/* ---- batches of independent instances -------------------------------------
+ * count instances of eq. mp2, instance i on level levels[i] (its own
+ * (2^levels[i]+1)^2 vertex grid) with alpha alphas[i], all with the same
+ * options.  Each instance owns a context's workspace; the batched V-cycle
+ * (section 2) runs every level step as one launch over all instances whose
+ * finest level reaches it, the coarse levels k0..5 as one workgroup per
+ * instance, and each batched iterate is replayed from one HIP graph.
+ * Instances converge (and stop) independently.
+ * Requirements: MG_POISSON; 1 <= count <= 1024; every level in [6, 12];
+ * gamma = 1 (V-cycle); inner_cycles = 1; coarse_level <= 2 (otherwise
+ * MG_EUNSUPPORTED).  The batch must not be used from two host threads or
+ * streams at once. */
+typedef struct mg_batch mg_batch;
+
+int mg_batch_setup(int count, const int *levels, const double *alphas, int problem, const mg_opts *opts,
+                   mg_batch **out);
+void mg_batch_destroy(mg_batch *batch);
+/* number of instances (0 for NULL) */
+int mg_batch_count(const mg_batch *batch);
+/* unknowns of instance i, 2 (2^levels[i]+1)^2 (0 if out of range) */
+size_t mg_batch_vec_len(const mg_batch *batch, int i);
+/* f_i = (M y_D,i; 0) for every instance: yd and f are HOST arrays of count
+ * DEVICE pointers (instance i: (2^l+1)^2 and 2 (2^l+1)^2 entries). */
+int mg_batch_rhs(mg_batch *batch, const double *const *yd, double *const *f, void *stream);
+/* Solve every instance from its initial guess x_i (in/out) until its
+ * relative residual (norm of opts.norm) is <= tol, as mg_solve does for one
+ * context.  f and x are HOST arrays of count DEVICE pointers.  Per-instance
+ * results go to the optional host arrays cycles_out, relres_out and
+ * status_out (count entries; status as mg_solve would return).  Returns
+ * MG_OK if every instance succeeded, else the status of the first failing
+ * instance (message in mg_batch_last_error).  Synchronises the stream once
+ * per iterate. */
+int mg_batch_solve(mg_batch *batch, const double *const *f, double *const *x, double tol, int *cycles_out,
+                   double *relres_out, int *status_out, void *stream);
+const char *mg_batch_last_error(const mg_batch *batch);
+
 #ifdef __cplusplus
 }
 #endif

@@ -87,6 +87,22 @@ def lib():
     L.mg_solve.argtypes = [vp, vp, vp, dp, ctypes.POINTER(ip), ctypes.POINTER(dp), vp]
     L.mg_timing_enable.argtypes = [vp, ip]
     L.mg_timing_read.argtypes = [vp, ctypes.POINTER(dp), ctypes.POINTER(ctypes.c_long)]
+    L.mg_batch_setup.argtypes = [ip, ctypes.POINTER(ip), ctypes.POINTER(dp), ip, ctypes.POINTER(MgOpts),
+                                 ctypes.POINTER(vp)]
+    L.mg_batch_setup.restype = ip
+    L.mg_batch_destroy.argtypes = [vp]
+    L.mg_batch_destroy.restype = None
+    L.mg_batch_count.argtypes = [vp]
+    L.mg_batch_count.restype = ip
+    L.mg_batch_vec_len.argtypes = [vp, ip]
+    L.mg_batch_vec_len.restype = sz
+    L.mg_batch_rhs.argtypes = [vp, ctypes.POINTER(vp), ctypes.POINTER(vp), vp]
+    L.mg_batch_rhs.restype = ip
+    L.mg_batch_solve.argtypes = [vp, ctypes.POINTER(vp), ctypes.POINTER(vp), dp, ctypes.POINTER(ip),
+                                 ctypes.POINTER(dp), ctypes.POINTER(ip), vp]
+    L.mg_batch_solve.restype = ip
+    L.mg_batch_last_error.argtypes = [vp]
+    L.mg_batch_last_error.restype = ctypes.c_char_p
     L.mg_strerror.restype = ctypes.c_char_p
     L.mg_strerror.argtypes = [ip]
     L.mg_last_error.restype = ctypes.c_char_p
@@ -286,6 +302,83 @@ class Solver:
         n = ctypes.c_long(0)
         self._check(lib().mg_timing_read(self._h, ctypes.byref(ms), ctypes.byref(n)), "mg_timing_read")
         return ms.value, n.value
+
+
+# --- batches of independent instances ----------------------------------------------
+
+class Batch:
+    """Independent instances (level_i, alpha_i) solved together (mg_batch_*)."""
+
+    def __init__(self, levels, alphas, smoother: str = "lsgs", precision: str = "fp64", **kw):
+        o = default_opts("poisson")
+        o.smoother = SMOOTHERS[smoother]
+        o.precision = PRECISIONS[precision]
+        for k, v in kw.items():
+            setattr(o, k, NORMS[v] if k == "norm" else v)
+        self.levels = [int(l) for l in levels]
+        self.alphas = [float(a) for a in alphas]
+        n = len(self.levels)
+        self._h = ctypes.c_void_p()
+        st = lib().mg_batch_setup(n, (ctypes.c_int * n)(*self.levels), (ctypes.c_double * n)(*self.alphas),
+                                  MG_POISSON, ctypes.byref(o), ctypes.byref(self._h))
+        if st != MG_OK:
+            raise MGError(st, "mg_batch_setup")
+
+    def close(self):
+        if getattr(self, "_h", None) and self._h.value:
+            lib().mg_batch_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __len__(self):
+        return lib().mg_batch_count(self._h)
+
+    def vec_len(self, i: int) -> int:
+        return lib().mg_batch_vec_len(self._h, i)
+
+    def _ptrs(self, ts, lens, name):
+        import torch
+
+        n = len(self)
+        if len(ts) != n:
+            raise ValueError(f"{name}: expected {n} tensors")
+        for t, m in zip(ts, lens):
+            if not (t.is_cuda and t.dtype == torch.float64 and t.is_contiguous() and t.numel() == m):
+                raise ValueError(f"{name}: contiguous FP64 CUDA tensors of the instance sizes required")
+        return (ctypes.c_void_p * n)(*[t.data_ptr() for t in ts])
+
+    def rhs(self, yds):
+        import torch
+
+        n = len(self)
+        fs = [torch.empty(self.vec_len(i), dtype=torch.float64, device="cuda") for i in range(n)]
+        st = lib().mg_batch_rhs(self._h, self._ptrs(yds, [self.vec_len(i) // 2 for i in range(n)], "yd"),
+                                self._ptrs(fs, [self.vec_len(i) for i in range(n)], "f"), _stream())
+        if st != MG_OK:
+            raise MGError(st, "mg_batch_rhs", lib().mg_batch_last_error(self._h).decode())
+        return fs
+
+    def solve(self, fs, xs=None, tol: float = 1e-10, raise_on_error: bool = True):
+        """Returns (xs, cycles, relres, statuses, status)."""
+        import torch
+
+        n = len(self)
+        lens = [self.vec_len(i) for i in range(n)]
+        if xs is None:
+            xs = [torch.zeros(m, dtype=torch.float64, device="cuda") for m in lens]
+        cyc = (ctypes.c_int * n)()
+        rel = (ctypes.c_double * n)()
+        sts = (ctypes.c_int * n)()
+        st = lib().mg_batch_solve(self._h, self._ptrs(fs, lens, "f"), self._ptrs(xs, lens, "x"), float(tol), cyc, rel,
+                                  sts, _stream())
+        if st != MG_OK and raise_on_error:
+            raise MGError(st, "mg_batch_solve", lib().mg_batch_last_error(self._h).decode())
+        return xs, list(cyc), list(rel), list(sts), st
 
 
 # --- differentiable solve ---------------------------------------------------------

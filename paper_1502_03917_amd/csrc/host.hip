@@ -8,7 +8,9 @@
 #include <cstdlib>
 #include <cstring>
 #include <new>
+#include <algorithm>
 #include <string>
+#include <type_traits>
 #include <utility>
 #include <vector>
 
@@ -25,6 +27,9 @@ constexpr int kMaxCoarse = 3;  // coarsest LU of 2 (2^k0+1)^2 <= 162 unknowns
 // mg_solve reports a stall when the best relative residual of the last 10
 // iterates is not below half the best of the 10 before them
 constexpr int kStallWindow = 10;
+// batches: every instance needs the coarse-level tail on levels k0..5
+constexpr int kMaxBatch = 1024;
+constexpr int kBatchMinLevel = 6;
 
 // ---------------------------------------------------------------- tables
 
@@ -499,6 +504,35 @@ int cycle_body(mg_ctx* c, int l, const T* f, T* x, T* r, bool residual_current, 
 
 int norm_mode(const mg_ctx* c) { return c->o.norm == MG_NORM_LINV ? 2 : 1; }
 
+// Stopping rule of the solve loop, applied after every iterate (it = number
+// of iterates so far) to ||r||^2 and ||f||^2: returns kContinue or the final
+// status with a message.
+constexpr int kContinue = 1;
+struct Monitor {
+  double nf = -1.0, rel0 = -1.0, rel = 0.0;
+  std::vector<double> hist;
+  int check(double r2, double f2, double tol, int it, int max_cycles, const char** why) {
+    if (nf < 0.0) nf = std::sqrt(f2) > 0.0 ? std::sqrt(f2) : 1.0;
+    rel = std::sqrt(r2) / nf;
+    if (rel0 < 0.0) rel0 = rel;
+    if (!std::isfinite(rel)) return *why = "non-finite residual norm", MG_ENAN;
+    if (rel <= tol) return MG_OK;
+    if (rel > 1e3 * rel0 && rel0 > 0.0) return *why = "residual grew above 1e3 x initial", MG_EDIVERGE;
+    hist.push_back(rel);
+    if (it + 1 >= 2 * kStallWindow) {
+      double best_new = hist[it], best_old = hist[it - kStallWindow];
+      for (int k = 1; k < kStallWindow; k++) {
+        best_new = std::fmin(best_new, hist[it - k]);
+        best_old = std::fmin(best_old, hist[it - kStallWindow - k]);
+      }
+      if (best_new > 0.5 * best_old)
+        return *why = "residual stagnated: no factor 2 gained over the last 10 iterates", MG_ESTALL;
+    }
+    if (it >= max_cycles) return *why = "max_cycles reached", MG_ENOTCONV;
+    return kContinue;
+  }
+};
+
 // ||r||^2 of the fine residual into d_norm[slot] (stream-ordered)
 int residual_norm(mg_ctx* c, const double* f, const double* x, double* r, int slot, hipStream_t s) {
   LevelBuf& b = L_(c, c->level);
@@ -822,32 +856,18 @@ int mg_solve(mg_ctx* ctx, const double* f, double* x, double tol, int* cycles_ou
   int nb = 0;
   HIPCHK(ctx, mgk::launch_vnorm(b.lev, f, ctx->d_part, norm_mode(ctx), &nb, s));
   HIPCHK(ctx, mgk::launch_sum(ctx->d_part, nb, ctx->d_norm + 1, s));
-  double nf = -1.0, rel0 = -1.0, rel = 0.0;
-  int it = 0, st = MG_OK;
-  std::vector<double> hist;
+  Monitor mon;
+  int st = MG_OK;
   if ((st = residual_norm(ctx, f, x, b.r, 0, s)) != MG_OK) return st;
-  for (;; it++) {
+  for (int it = 0;; it++) {
     HIPCHK(ctx, hipMemcpyAsync(ctx->h_norm, ctx->d_norm, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
     HIPCHK(ctx, hipStreamSynchronize(s));
-    if (nf < 0.0) nf = std::sqrt(ctx->h_norm[1]) > 0.0 ? std::sqrt(ctx->h_norm[1]) : 1.0;
-    rel = std::sqrt(ctx->h_norm[0]) / nf;
-    if (rel0 < 0.0) rel0 = rel;
+    const char* why = "";
+    const int verdict = mon.check(ctx->h_norm[0], ctx->h_norm[1], tol, it, ctx->o.max_cycles, &why);
     if (cycles_out) *cycles_out = it;
-    if (relres_out) *relres_out = rel;
-    if (!std::isfinite(rel)) return fail(ctx, MG_ENAN, "non-finite residual norm");
-    if (rel <= tol) return MG_OK;
-    if (rel > 1e3 * rel0 && rel0 > 0.0) return fail(ctx, MG_EDIVERGE, "residual grew above 1e3 x initial");
-    hist.push_back(rel);
-    if (it + 1 >= 2 * kStallWindow) {
-      double best_new = hist[it], best_old = hist[it - kStallWindow];
-      for (int k = 1; k < kStallWindow; k++) {
-        best_new = std::fmin(best_new, hist[it - k]);
-        best_old = std::fmin(best_old, hist[it - kStallWindow - k]);
-      }
-      if (best_new > 0.5 * best_old)
-        return fail(ctx, MG_ESTALL, "residual stagnated: no factor 2 gained over the last 10 iterates");
-    }
-    if (it >= ctx->o.max_cycles) return fail(ctx, MG_ENOTCONV, "max_cycles reached");
+    if (relres_out) *relres_out = mon.rel;
+    if (verdict == MG_OK) return MG_OK;
+    if (verdict != kContinue) return fail(ctx, verdict, why);
     if (ctx->graphs && !ctx->timing) {
       if ((st = ensure_graph(ctx, f, x)) != MG_OK) return st;
       HIPCHK(ctx, hipGraphLaunch(ctx->gexec, s));
@@ -882,6 +902,453 @@ int mg_timing_read(mg_ctx* ctx, double* total_ms, long* launches) {
   *total_ms = ctx->t_ms;
   *launches = ctx->t_n;
   return MG_OK;
+}
+
+}  // extern "C"
+
+// ====================================================================== batch
+//
+// Independent instances (their own level, alpha and data) solved together.
+// Every instance keeps its own context (workspace, tables, coarse LU, tail
+// schedule); a batched V-cycle runs the levels from the highest finest level
+// down to the tail level and back, and each step is one launch covering every
+// instance whose finest level reaches that level (they share its geometry).
+// The coarse-level tail runs one workgroup per instance.  One batched iterate
+// is captured as a HIP graph; between replays the host reads all residual
+// norms with one copy, applies the stopping rule per instance, and switches
+// finished instances off through a device flag that every kernel checks.
+
+struct mg_batch {
+  int count = 0, k0 = 1, T = 0, Lmax = 0, device = 0;
+  mg_opts o{};
+  std::vector<mg_ctx*> inst;
+  std::vector<int> level;
+  int* d_active = nullptr;
+  int* h_active = nullptr;
+  double* d_norms = nullptr;  // gathered (||r||^2, ||f||^2) per instance
+  double* h_norms = nullptr;
+  double** d_normptr = nullptr;
+  struct Group {
+    int L = 0;
+    std::vector<int> members;
+    mgk::BInst<double>* d64 = nullptr;
+    mgk::BInst<float>* d32 = nullptr;
+  };
+  std::vector<Group> groups;  // levels T+1 .. Lmax
+  struct Fine {
+    int F = 0;
+    std::vector<int> members;
+    mgk::BFine* d = nullptr;
+  };
+  std::vector<Fine> fine;  // one per distinct finest level
+  void* d_tail64 = nullptr;
+  void* d_tail32 = nullptr;
+  size_t tail_lds = 0;
+  std::vector<const double*> uf;
+  std::vector<double*> ux;
+  hipStream_t cap = nullptr;
+  hipGraphExec_t gexec = nullptr;
+  bool graphs = true;
+  std::string err;
+};
+
+namespace {
+
+int bfail(mg_batch* b, int status, const std::string& msg) {
+  if (b) b->err = msg;
+  return status;
+}
+
+#define BCHK(b, expr)                                                                                      \
+  do {                                                                                                     \
+    hipError_t e_ = (expr);                                                                                \
+    if (e_ != hipSuccess)                                                                                  \
+      return bfail((b), e_ == hipErrorOutOfMemory ? MG_ENOMEM : MG_EHIP,                                   \
+                   std::string(#expr) + ": " + hipGetErrorString(e_));                                     \
+  } while (0)
+
+void batch_free(mg_batch* b) {
+  if (!b) return;
+  (void)hipSetDevice(b->device);
+  if (b->gexec) (void)hipGraphExecDestroy(b->gexec);
+  if (b->cap) (void)hipStreamDestroy(b->cap);
+  for (auto& g : b->groups) {
+    (void)hipFree(g.d64);
+    (void)hipFree(g.d32);
+  }
+  for (auto& f : b->fine) (void)hipFree(f.d);
+  (void)hipFree(b->d_tail64);
+  (void)hipFree(b->d_tail32);
+  (void)hipFree(b->d_active);
+  (void)hipFree(b->d_norms);
+  (void)hipFree(b->d_normptr);
+  if (b->h_active) (void)hipHostFree(b->h_active);
+  if (b->h_norms) (void)hipHostFree(b->h_norms);
+  for (auto c : b->inst) destroy_impl(c);
+  delete b;
+}
+
+mg_batch::Group& group_of(mg_batch* b, int L) { return b->groups[L - b->T - 1]; }
+
+// per-level descriptors of instance i at level L (FP64: the caller's f and x
+// on the instance's finest level)
+template <typename T>
+mgk::BInst<T> make_binst(mg_batch* b, int i, int L, const double* uf, double* ux) {
+  mg_ctx* c = b->inst[i];
+  LevelBuf& lb = L_(c, L);
+  LevelBuf& lc = L_(c, L - 1);
+  Work<T> w = work(lb, (T*)nullptr), wc = work(lc, (T*)nullptr);
+  mgk::BInst<T> a{};
+  a.L = lb.lev;
+  a.Lc = lc.lev;
+  a.x = w.x;
+  a.f = w.f;
+  if constexpr (std::is_same<T, double>::value) {
+    if (L == c->level) {
+      a.x = ux;
+      a.f = const_cast<double*>(uf);
+    }
+  }
+  a.r = w.r;
+  a.r2 = w.r2;
+  a.p = w.p;
+  a.xc = wc.x;
+  a.fc = wc.f;
+  a.rc = wc.r;
+  a.active = b->d_active + i;
+  return a;
+}
+
+// descriptors that hold the caller's pointers (FP64 levels, finest levels)
+int batch_bind(mg_batch* b, const double* const* f, double* const* x, hipStream_t s) {
+  bool same = !b->uf.empty();
+  for (int i = 0; same && i < b->count; i++) same = b->uf[i] == f[i] && b->ux[i] == x[i];
+  if (same) return MG_OK;
+  BCHK(b, hipStreamSynchronize(s));
+  b->uf.assign(f, f + b->count);
+  b->ux.assign(x, x + b->count);
+  for (auto& g : b->groups) {
+    std::vector<mgk::BInst<double>> h;
+    for (int i : g.members) h.push_back(make_binst<double>(b, i, g.L, f[i], x[i]));
+    BCHK(b, hipMemcpy(g.d64, h.data(), h.size() * sizeof(h[0]), hipMemcpyHostToDevice));
+  }
+  for (auto& fg : b->fine) {
+    std::vector<mgk::BFine> h;
+    for (int i : fg.members) {
+      mg_ctx* c = b->inst[i];
+      LevelBuf& lb = L_(c, c->level);
+      mgk::BFine a{};
+      a.L = lb.lev;
+      a.f = f[i];
+      a.x = x[i];
+      a.r = lb.r;
+      a.f32 = lb.f32;
+      a.x32 = lb.x32;
+      a.r32 = lb.r32;
+      a.part = c->d_part;
+      a.norm = c->d_norm;
+      a.active = b->d_active + i;
+      h.push_back(a);
+    }
+    BCHK(b, hipMemcpy(fg.d, h.data(), h.size() * sizeof(h[0]), hipMemcpyHostToDevice));
+  }
+  if (b->gexec) (void)hipGraphExecDestroy(b->gexec);
+  b->gexec = nullptr;
+  return MG_OK;
+}
+
+template <typename T>
+const mgk::BInst<T>* gdev(const mg_batch::Group& g);
+template <>
+const mgk::BInst<double>* gdev<double>(const mg_batch::Group& g) {
+  return g.d64;
+}
+template <>
+const mgk::BInst<float>* gdev<float>(const mg_batch::Group& g) {
+  return g.d32;
+}
+
+template <typename T>
+int batch_smooth(mg_batch* b, const mg_batch::Group& g, int steps, int& sel, hipStream_t s) {
+  const int n = 1 << g.L, cnt = (int)g.members.size();
+  const mgk::BInst<T>* d = gdev<T>(g);
+  for (int it = 0; it < steps; it++) {
+    switch (b->o.smoother) {
+      case MG_NE:
+        BCHK(b, mgk::launch_b_ne<T>(d, cnt, n, sel, s));
+        break;
+      case MG_LSGS:
+        BCHK(b, mgk::launch_b_lsgs_sweep<T>(d, cnt, n, 0, sel, s));
+        sel ^= 1;
+        break;
+      case MG_SLSGS:
+        BCHK(b, mgk::launch_b_lsgs_sweep<T>(d, cnt, n, 0, sel, s));
+        BCHK(b, mgk::launch_b_lsgs_sweep<T>(d, cnt, n, 1, sel ^ 1, s));
+        break;
+      case MG_CGS:
+        for (int col = 0; col < 7; col++) BCHK(b, mgk::launch_b_cgs_phase<T>(d, cnt, n, col, sel, s));
+        break;
+    }
+  }
+  return MG_OK;
+}
+
+// one batched V-cycle; on entry the finest-level residual of every instance
+// is current in its r buffer
+template <typename T>
+int batch_cycle(mg_batch* b, hipStream_t s) {
+  std::vector<int> sel(b->Lmax + 1, 0);
+  int st;
+  for (int L = b->Lmax; L > b->T; L--) {
+    const mg_batch::Group& g = group_of(b, L);
+    int sl = 0;
+    if ((st = batch_smooth<T>(b, g, b->o.nu1, sl, s)) != MG_OK) return st;
+    BCHK(b, mgk::launch_b_restrict<T>(gdev<T>(g), (int)g.members.size(), 1 << (L - 1), sl, L - 1 > b->T ? 1 : 0, s));
+    sel[L] = sl;
+  }
+  BCHK(b, mgk::launch_b_tail<T>(std::is_same<T, double>::value ? b->d_tail64 : b->d_tail32, b->count, b->tail_lds, s));
+  for (int L = b->T + 1; L <= b->Lmax; L++) {
+    const mg_batch::Group& g = group_of(b, L);
+    const int cnt = (int)g.members.size();
+    int sl = sel[L];
+    BCHK(b, mgk::launch_b_prolong_add<T>(gdev<T>(g), cnt, 1 << L, s));
+    BCHK(b, mgk::launch_b_residual<T>(gdev<T>(g), cnt, 1 << L, sl, s));
+    if ((st = batch_smooth<T>(b, g, b->o.nu2, sl, s)) != MG_OK) return st;
+  }
+  return MG_OK;
+}
+
+// finest-level residuals and their squared norms into norm[0] of every instance
+int batch_residual_norms(mg_batch* b, hipStream_t s) {
+  const int mode = b->o.norm == MG_NORM_LINV ? 2 : 1;
+  for (auto& fg : b->fine) {
+    const int cnt = (int)fg.members.size();
+    BCHK(b, mgk::launch_b_residual_norm(fg.d, cnt, 1 << fg.F, mode, s));
+    BCHK(b, mgk::launch_b_sum(fg.d, cnt, mgk::residual_blocks(1 << fg.F), 0, s));
+  }
+  return MG_OK;
+}
+
+// one iterate for every active instance, then the gathered norms
+int batch_iterate(mg_batch* b, hipStream_t s) {
+  int st;
+  if (b->o.precision == MG_FP32_IR) {
+    for (auto& fg : b->fine) {
+      const size_t len = 2 * (size_t)((1 << fg.F) + 1) * ((1 << fg.F) + 1);
+      BCHK(b, mgk::launch_b_to_f32_scaled(fg.d, (int)fg.members.size(), len, s));
+      BCHK(b, mgk::launch_b_zero_x32(fg.d, (int)fg.members.size(), len, s));
+    }
+    if ((st = batch_cycle<float>(b, s)) != MG_OK) return st;
+    for (auto& fg : b->fine) {
+      const size_t len = 2 * (size_t)((1 << fg.F) + 1) * ((1 << fg.F) + 1);
+      BCHK(b, mgk::launch_b_axpy_f32(fg.d, (int)fg.members.size(), len, s));
+    }
+  } else if ((st = batch_cycle<double>(b, s)) != MG_OK) {
+    return st;
+  }
+  if ((st = batch_residual_norms(b, s)) != MG_OK) return st;
+  BCHK(b, mgk::launch_b_gather_norms(b->d_normptr, b->count, b->d_norms, s));
+  return MG_OK;
+}
+
+int batch_graph(mg_batch* b) {
+  if (b->gexec) return MG_OK;
+  if (!b->cap) BCHK(b, hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking));
+  hipGraph_t g = nullptr;
+  BCHK(b, hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal));
+  int st = batch_iterate(b, b->cap);
+  hipError_t e = hipStreamEndCapture(b->cap, &g);
+  if (st != MG_OK) {
+    if (g) (void)hipGraphDestroy(g);
+    return st;
+  }
+  if (e != hipSuccess) return bfail(b, MG_EHIP, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
+  e = hipGraphInstantiate(&b->gexec, g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  if (e != hipSuccess) {
+    b->gexec = nullptr;
+    return bfail(b, MG_EHIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
+  }
+  return MG_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int mg_batch_setup(int count, const int* levels, const double* alphas, int problem, const mg_opts* opts,
+                   mg_batch** out) {
+  if (!out) return MG_EINVAL;
+  *out = nullptr;
+  if (count < 1 || count > kMaxBatch || !levels || !alphas) return MG_EINVAL;
+  if (problem != MG_POISSON && problem != MG_STOKES) return MG_EINVAL;
+  mg_opts o = mg_default_opts(problem);
+  if (opts) o = *opts;
+  if (!valid_opts(&o, -1)) return MG_EINVAL;
+  for (int i = 0; i < count; i++) {
+    if (levels[i] < kBatchMinLevel || levels[i] > kMaxLevel) return MG_EINVAL;
+    if (!(alphas[i] > 0.0) || !std::isfinite(alphas[i])) return MG_EINVAL;
+  }
+  if (problem != MG_POISSON || o.gamma != 1 || o.inner_cycles != 1 || o.coarse_level > 2) return MG_EUNSUPPORTED;
+  mg_batch* b = new mg_batch;
+  b->count = count;
+  b->o = o;
+  b->k0 = o.coarse_level;
+  (void)hipGetDevice(&b->device);
+  b->graphs = std::getenv("MGKKT_NO_GRAPH") == nullptr;
+  auto bail = [&](int st) {
+    batch_free(b);
+    return st;
+  };
+  for (int i = 0; i < count; i++) {
+    mg_ctx* c = nullptr;
+    int st = mg_setup(levels[i], alphas[i], problem, &o, &c);
+    if (st != MG_OK) return bail(st);
+    b->inst.push_back(c);
+    b->level.push_back(levels[i]);
+    b->Lmax = std::max(b->Lmax, levels[i]);
+    if (c->tail_T == 0) return bail(MG_EUNSUPPORTED);  // the coarse-level tail is required
+    if (i == 0) b->T = c->tail_T;
+    if (c->tail_T != b->T) return bail(MG_EUNSUPPORTED);
+  }
+  if (hipMalloc(&b->d_active, count * sizeof(int)) != hipSuccess ||
+      hipMalloc(&b->d_norms, 2 * count * sizeof(double)) != hipSuccess ||
+      hipMalloc(&b->d_normptr, count * sizeof(double*)) != hipSuccess ||
+      hipHostMalloc((void**)&b->h_active, count * sizeof(int), hipHostMallocDefault) != hipSuccess ||
+      hipHostMalloc((void**)&b->h_norms, 2 * count * sizeof(double), hipHostMallocDefault) != hipSuccess)
+    return bail(MG_ENOMEM);
+  {
+    std::vector<double*> np;
+    for (auto c : b->inst) np.push_back(c->d_norm);
+    if (hipMemcpy(b->d_normptr, np.data(), count * sizeof(double*), hipMemcpyHostToDevice) != hipSuccess)
+      return bail(MG_EHIP);
+  }
+  // level groups; FP32 descriptors are fixed (library buffers only)
+  for (int L = b->T + 1; L <= b->Lmax; L++) {
+    mg_batch::Group g;
+    g.L = L;
+    for (int i = 0; i < count; i++)
+      if (levels[i] >= L) g.members.push_back(i);
+    if (hipMalloc(&g.d64, g.members.size() * sizeof(mgk::BInst<double>)) != hipSuccess) return bail(MG_ENOMEM);
+    if (o.precision == MG_FP32_IR) {
+      std::vector<mgk::BInst<float>> h;
+      for (int i : g.members) h.push_back(make_binst<float>(b, i, L, nullptr, nullptr));
+      if (hipMalloc(&g.d32, h.size() * sizeof(h[0])) != hipSuccess) return bail(MG_ENOMEM);
+      if (hipMemcpy(g.d32, h.data(), h.size() * sizeof(h[0]), hipMemcpyHostToDevice) != hipSuccess)
+        return bail(MG_EHIP);
+    }
+    b->groups.push_back(g);
+  }
+  for (int F = b->T + 1; F <= b->Lmax; F++) {
+    mg_batch::Fine fg;
+    fg.F = F;
+    for (int i = 0; i < count; i++)
+      if (levels[i] == F) fg.members.push_back(i);
+    if (fg.members.empty()) continue;
+    if (hipMalloc(&fg.d, fg.members.size() * sizeof(mgk::BFine)) != hipSuccess) return bail(MG_ENOMEM);
+    b->fine.push_back(fg);
+  }
+  // tail schedules: level-T buffers of every instance (x_T starts at zero)
+  {
+    const size_t sz64 = mgk::tail_args_bytes<double>(), sz32 = mgk::tail_args_bytes<float>();
+    std::vector<unsigned char> h64(sz64 * count), h32(sz32 * count);
+    for (int i = 0; i < count; i++) {
+      mg_ctx* c = b->inst[i];
+      LevelBuf& lt = L_(c, b->T);
+      mgk::make_tail_args<double>(c->tail, lt.f, lt.x, 1, b->d_active + i, h64.data() + i * sz64);
+      if (o.precision == MG_FP32_IR)
+        mgk::make_tail_args<float>(c->tail, lt.f32, lt.x32, 1, b->d_active + i, h32.data() + i * sz32);
+    }
+    if (hipMalloc(&b->d_tail64, h64.size()) != hipSuccess) return bail(MG_ENOMEM);
+    if (hipMemcpy(b->d_tail64, h64.data(), h64.size(), hipMemcpyHostToDevice) != hipSuccess) return bail(MG_EHIP);
+    if (o.precision == MG_FP32_IR) {
+      if (hipMalloc(&b->d_tail32, h32.size()) != hipSuccess) return bail(MG_ENOMEM);
+      if (hipMemcpy(b->d_tail32, h32.data(), h32.size(), hipMemcpyHostToDevice) != hipSuccess) return bail(MG_EHIP);
+    }
+    b->tail_lds = std::max(mgk::tail_lds_bytes<double>(b->k0, b->T),
+                           o.precision == MG_FP32_IR ? mgk::tail_lds_bytes<float>(b->k0, b->T) : size_t(0));
+  }
+  *out = b;
+  return MG_OK;
+}
+
+void mg_batch_destroy(mg_batch* b) { batch_free(b); }
+
+int mg_batch_count(const mg_batch* b) { return b ? b->count : 0; }
+
+size_t mg_batch_vec_len(const mg_batch* b, int i) {
+  return (b && i >= 0 && i < b->count) ? mg_vec_len(b->inst[i]) : 0;
+}
+
+const char* mg_batch_last_error(const mg_batch* b) { return b ? b->err.c_str() : "no batch"; }
+
+int mg_batch_rhs(mg_batch* b, const double* const* yd, double* const* f, void* stream) {
+  if (!b || !yd || !f) return MG_EINVAL;
+  for (int i = 0; i < b->count; i++)
+    if (!yd[i] || !f[i]) return MG_EINVAL;
+  for (int i = 0; i < b->count; i++) {
+    const int st = mg_rhs(b->inst[i], yd[i], f[i], stream);
+    if (st != MG_OK) return bfail(b, st, b->inst[i]->err);
+  }
+  return MG_OK;
+}
+
+int mg_batch_solve(mg_batch* b, const double* const* f, double* const* x, double tol, int* cycles_out,
+                   double* relres_out, int* status_out, void* stream) {
+  if (!b || !f || !x || !(tol > 0.0) || !std::isfinite(tol)) return MG_EINVAL;
+  for (int i = 0; i < b->count; i++)
+    if (!f[i] || !x[i]) return MG_EINVAL;
+  hipStream_t s = (hipStream_t)stream;
+  int st;
+  if ((st = batch_bind(b, f, x, s)) != MG_OK) return st;
+  const int n = b->count, mode = b->o.norm == MG_NORM_LINV ? 2 : 1;
+  // ||f|| and the initial residual of every instance
+  for (int i = 0; i < n; i++) b->h_active[i] = 1;
+  BCHK(b, hipMemcpyAsync(b->d_active, b->h_active, n * sizeof(int), hipMemcpyHostToDevice, s));
+  for (auto& fg : b->fine) {
+    const int cnt = (int)fg.members.size();
+    BCHK(b, mgk::launch_b_vnorm(fg.d, cnt, 1 << fg.F, mode, s));
+    BCHK(b, mgk::launch_b_sum(fg.d, cnt, mgk::residual_blocks(1 << fg.F), 1, s));
+  }
+  if ((st = batch_residual_norms(b, s)) != MG_OK) return st;
+  BCHK(b, mgk::launch_b_gather_norms(b->d_normptr, n, b->d_norms, s));
+  std::vector<Monitor> mon(n);
+  std::vector<int> verdict(n, kContinue), cyc(n, 0);
+  std::vector<double> rel(n, 0.0);
+  std::string why0;
+  for (int it = 0;; it++) {
+    BCHK(b, hipMemcpyAsync(b->h_norms, b->d_norms, 2 * n * sizeof(double), hipMemcpyDeviceToHost, s));
+    BCHK(b, hipStreamSynchronize(s));
+    int live = 0;
+    for (int i = 0; i < n; i++) {
+      if (verdict[i] != kContinue) continue;
+      const char* why = "";
+      cyc[i] = it;
+      verdict[i] = mon[i].check(b->h_norms[2 * i], b->h_norms[2 * i + 1], tol, it, b->o.max_cycles, &why);
+      rel[i] = mon[i].rel;
+      if (verdict[i] != kContinue && verdict[i] != MG_OK && why0.empty())
+        why0 = "instance " + std::to_string(i) + ": " + why;
+      b->h_active[i] = verdict[i] == kContinue ? 1 : 0;
+      live += b->h_active[i];
+    }
+    if (!live) break;
+    BCHK(b, hipMemcpyAsync(b->d_active, b->h_active, n * sizeof(int), hipMemcpyHostToDevice, s));
+    if (b->graphs) {
+      if ((st = batch_graph(b)) != MG_OK) return st;
+      BCHK(b, hipGraphLaunch(b->gexec, s));
+    } else if ((st = batch_iterate(b, s)) != MG_OK) {
+      return st;
+    }
+  }
+  int result = MG_OK;
+  for (int i = 0; i < n; i++) {
+    if (cycles_out) cycles_out[i] = cyc[i];
+    if (relres_out) relres_out[i] = rel[i];
+    if (status_out) status_out[i] = verdict[i];
+    if (verdict[i] != MG_OK && result == MG_OK) result = verdict[i];
+  }
+  if (result != MG_OK) b->err = why0;
+  return result;
 }
 
 }  // extern "C"

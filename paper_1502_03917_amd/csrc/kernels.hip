@@ -185,7 +185,7 @@ __device__ inline double norm_term(const Lev& L, int i, int j, double ry, double
 // r = f - A x (HAS_F) or r = A x; MODE 1/2 also stores per-block partial sums
 // of the squared Euclidean / L^{-1} norm of r
 template <typename T, bool HAS_F, int MODE>
-__global__ __launch_bounds__(kNT) void k_residual(Lev L, const T* __restrict__ f, const T* __restrict__ x,
+__device__ __forceinline__ void residual_body(Lev L, const T* __restrict__ f, const T* __restrict__ x,
                                                   T* __restrict__ r, double* __restrict__ part) {
   const int i = blockIdx.x * kBX + threadIdx.x;
   const int j = blockIdx.y * kBY + threadIdx.y;
@@ -208,6 +208,9 @@ __global__ __launch_bounds__(kNT) void k_residual(Lev L, const T* __restrict__ f
   }
   if (MODE) block_sum_store(s2, &part[blockIdx.y * gridDim.x + blockIdx.x]);
 }
+template <typename T, bool HAS_F, int MODE>
+__global__ __launch_bounds__(kNT) void k_residual(Lev L, const T* __restrict__ f, const T* __restrict__ x,
+                                                  T* __restrict__ r, double* __restrict__ part) { residual_body<T, HAS_F, MODE>(L, f, x, r, part); }
 
 // per-block partial sums of the squared norm of a level vector
 template <int MODE>
@@ -223,7 +226,7 @@ __global__ __launch_bounds__(kNT) void k_vnorm(Lev L, const double* __restrict__
 }
 
 template <typename T>
-__global__ __launch_bounds__(kNT) void k_rhs(Lev L, const double* __restrict__ yd, T* __restrict__ f) {
+__device__ __forceinline__ void rhs_body(Lev L, const double* __restrict__ yd, T* __restrict__ f) {
   const int i = blockIdx.x * kBX + threadIdx.x;
   const int j = blockIdx.y * kBY + threadIdx.y;
   if (i > L.n || j > L.n) return;
@@ -245,6 +248,8 @@ __global__ __launch_bounds__(kNT) void k_rhs(Lev L, const double* __restrict__ y
   f[v] = (T)s;
   f[L.V + v] = (T)0;
 }
+template <typename T>
+__global__ __launch_bounds__(kNT) void k_rhs(Lev L, const double* __restrict__ yd, T* __restrict__ f) { rhs_body<T>(L, yd, f); }
 
 // (M v)_w of one field at vertex (i, j)
 __device__ inline double mass_at(const Lev& L, int i, int j, const double* __restrict__ v) {
@@ -294,7 +299,7 @@ __global__ __launch_bounds__(kNT) void k_control(Lev L, const double* __restrict
 
 // Alg. 1, first loop, fused with x += p: p_i = tau (A^T L^{-1} r)_i / L_ii
 template <typename T>
-__global__ __launch_bounds__(kNT) void k_ne_p(Lev L, T* __restrict__ x, const T* __restrict__ r, T* __restrict__ p) {
+__device__ __forceinline__ void ne_p_body(Lev L, T* __restrict__ x, const T* __restrict__ r, T* __restrict__ p) {
   const int i = blockIdx.x * kBX + threadIdx.x;
   const int j = blockIdx.y * kBY + threadIdx.y;
   if (i > L.n || j > L.n) return;
@@ -309,10 +314,12 @@ __global__ __launch_bounds__(kNT) void k_ne_p(Lev L, T* __restrict__ x, const T*
   x[v] += py;
   x[L.V + v] += pl;
 }
+template <typename T>
+__global__ __launch_bounds__(kNT) void k_ne_p(Lev L, T* __restrict__ x, const T* __restrict__ r, T* __restrict__ p) { ne_p_body<T>(L, x, r, p); }
 
 // Alg. 1, second loop: r -= A p
 template <typename T>
-__global__ __launch_bounds__(kNT) void k_ne_r(Lev L, const T* __restrict__ p, T* __restrict__ r) {
+__device__ __forceinline__ void ne_r_body(Lev L, const T* __restrict__ p, T* __restrict__ r) {
   const int i = blockIdx.x * kBX + threadIdx.x;
   const int j = blockIdx.y * kBY + threadIdx.y;
   if (i > L.n || j > L.n) return;
@@ -322,6 +329,8 @@ __global__ __launch_bounds__(kNT) void k_ne_r(Lev L, const T* __restrict__ p, T*
   r[v] -= ay;
   r[L.V + v] -= al;
 }
+template <typename T>
+__global__ __launch_bounds__(kNT) void k_ne_r(Lev L, const T* __restrict__ p, T* __restrict__ r) { ne_r_body<T>(L, p, r); }
 
 // first vertex of colour c in row j: (i + 2 j) mod 7 == c
 __device__ inline int colour_start(int c, int j) { return ((c - 2 * j) % 7 + 7) % 7; }
@@ -348,7 +357,7 @@ __global__ __launch_bounds__(kNT) void k_lsgs_phase(Lev L, int c, T* __restrict_
 // collective point Gauss-Seidel on one colour: solve the 2x2 system
 // [[M_vv, K_vv], [K_vv, -alpha^-1 M_vv]] d = (r^y_v, r^l_v), x += d, r -= A d
 template <typename T>
-__global__ __launch_bounds__(kNT) void k_cgs_phase(Lev L, int c, T* __restrict__ x, T* __restrict__ r) {
+__device__ __forceinline__ void cgs_phase_body(Lev L, int c, T* __restrict__ x, T* __restrict__ r) {
   const int t = blockIdx.x * kBX + threadIdx.x;
   const int j = blockIdx.y * kBY + threadIdx.y;
   if (j > L.n) return;
@@ -373,11 +382,13 @@ __global__ __launch_bounds__(kNT) void k_cgs_phase(Lev L, int c, T* __restrict__
   x[L.V + v] += dl;
   scatter_r(L, i, j, dy, dl, r);
 }
+template <typename T>
+__global__ __launch_bounds__(kNT) void k_cgs_phase(Lev L, int c, T* __restrict__ x, T* __restrict__ r) { cgs_phase_body<T>(L, c, x, r); }
 
 // f_c = P^T r: coarse vertex (I, J) collects the fine residual at (2I, 2J)
 // with weight 1 and at its six lattice neighbours with weight 1/2.
 template <typename T>
-__global__ __launch_bounds__(kNT) void k_restrict(Lev Lf, Lev Lc, const T* __restrict__ r, T* __restrict__ fc,
+__device__ __forceinline__ void restrict_body(Lev Lf, Lev Lc, const T* __restrict__ r, T* __restrict__ fc,
                                                   T* __restrict__ xc_zero, T* __restrict__ rc_copy) {
   const int I = blockIdx.x * kBX + threadIdx.x;
   const int J = blockIdx.y * kBY + threadIdx.y;
@@ -413,11 +424,14 @@ __global__ __launch_bounds__(kNT) void k_restrict(Lev Lf, Lev Lc, const T* __res
     rc_copy[Lc.V + w] = gl;
   }
 }
+template <typename T>
+__global__ __launch_bounds__(kNT) void k_restrict(Lev Lf, Lev Lc, const T* __restrict__ r, T* __restrict__ fc,
+                                                  T* __restrict__ xc_zero, T* __restrict__ rc_copy) { restrict_body<T>(Lf, Lc, r, fc, xc_zero, rc_copy); }
 
 // x += P x_c: P1 interpolation; fine vertices on coarse edges (horizontal,
 // vertical, or the (I,J)-(I+1,J+1) diagonal) take the mean of the endpoints.
 template <typename T>
-__global__ __launch_bounds__(kNT) void k_prolong_add(Lev Lf, Lev Lc, const T* __restrict__ xc, T* __restrict__ x) {
+__device__ __forceinline__ void prolong_add_body(Lev Lf, Lev Lc, const T* __restrict__ xc, T* __restrict__ x) {
   const int a = blockIdx.x * kBX + threadIdx.x;
   const int b = blockIdx.y * kBY + threadIdx.y;
   if (a > Lf.n || b > Lf.n) return;
@@ -436,6 +450,8 @@ __global__ __launch_bounds__(kNT) void k_prolong_add(Lev Lf, Lev Lc, const T* __
   x[u] += vy;
   x[Lf.V + u] += vl;
 }
+template <typename T>
+__global__ __launch_bounds__(kNT) void k_prolong_add(Lev Lf, Lev Lc, const T* __restrict__ xc, T* __restrict__ x) { prolong_add_body<T>(Lf, Lc, xc, x); }
 
 // x = A_{k0}^{-1} f with the FP64 LU factors (row pivots piv) of A_{k0}
 template <typename T>
@@ -468,7 +484,7 @@ __global__ __launch_bounds__(256) void k_coarse_solve(int N, const double* __res
   for (int i = tid; i < N; i += blockDim.x) x[i] = (T)b[i];
 }
 
-__global__ __launch_bounds__(256) void k_sum(const double* __restrict__ part, int n, double scale,
+__device__ __forceinline__ void sum_body(const double* __restrict__ part, int n, double scale,
                                              double* __restrict__ out) {
   __shared__ double sh[4];
   const int tid = threadIdx.x;
@@ -479,6 +495,8 @@ __global__ __launch_bounds__(256) void k_sum(const double* __restrict__ part, in
   __syncthreads();
   if (tid == 0) *out = scale * ((sh[0] + sh[1]) + (sh[2] + sh[3]));
 }
+__global__ __launch_bounds__(256) void k_sum(const double* __restrict__ part, int n, double scale,
+                                             double* __restrict__ out) { sum_body(part, n, scale, out); }
 
 __global__ __launch_bounds__(256) void k_sumsq(const double* __restrict__ v, size_t n, double* __restrict__ part) {
   __shared__ double sh[4];
@@ -496,7 +514,7 @@ __device__ inline double ir_scale(const double* nrm2) {
   return q > 0.0 ? sqrt(q) : 1.0;
 }
 
-__global__ void k_to_f32_scaled(const double* __restrict__ r, size_t n, const double* __restrict__ nrm2,
+__device__ __forceinline__ void to_f32_scaled_body(const double* __restrict__ r, size_t n, const double* __restrict__ nrm2,
                                 float* __restrict__ out, float* __restrict__ out2) {
   const double inv = 1.0 / ir_scale(nrm2);
   for (size_t k = blockIdx.x * (size_t)blockDim.x + threadIdx.x; k < n; k += (size_t)gridDim.x * blockDim.x) {
@@ -505,16 +523,120 @@ __global__ void k_to_f32_scaled(const double* __restrict__ r, size_t n, const do
     if (out2) out2[k] = v;
   }
 }
+__global__ void k_to_f32_scaled(const double* __restrict__ r, size_t n, const double* __restrict__ nrm2,
+                                float* __restrict__ out, float* __restrict__ out2) { to_f32_scaled_body(r, n, nrm2, out, out2); }
 
-__global__ void k_axpy_f32(const float* __restrict__ c, size_t n, const double* __restrict__ nrm2,
+__device__ __forceinline__ void axpy_f32_body(const float* __restrict__ c, size_t n, const double* __restrict__ nrm2,
                            double* __restrict__ x) {
   const double scale = ir_scale(nrm2);
   for (size_t k = blockIdx.x * (size_t)blockDim.x + threadIdx.x; k < n; k += (size_t)gridDim.x * blockDim.x)
     x[k] += scale * (double)c[k];
 }
+__global__ void k_axpy_f32(const float* __restrict__ c, size_t n, const double* __restrict__ nrm2,
+                           double* __restrict__ x) { axpy_f32_body(c, n, nrm2, x); }
 
-__global__ void k_zero_f32(float* __restrict__ v, size_t n) {
+__device__ __forceinline__ void zero_f32_body(float* __restrict__ v, size_t n) {
   for (size_t k = blockIdx.x * (size_t)blockDim.x + threadIdx.x; k < n; k += (size_t)gridDim.x * blockDim.x) v[k] = 0.f;
+}
+__global__ void k_zero_f32(float* __restrict__ v, size_t n) { zero_f32_body(v, n); }
+
+// ---- batched wrappers: instance blockIdx.z (vertex grids) / blockIdx.y (1D)
+template <typename T>
+__device__ inline T* cur_r(const BInst<T>& a, int sel) { return sel ? a.r2 : a.r; }
+
+template <typename T>
+__global__ __launch_bounds__(kNT) void kb_residual(const BInst<T>* __restrict__ B, int sel) {
+  const BInst<T>& a = B[blockIdx.z];
+  if (!*a.active) return;
+  residual_body<T, true, 0>(a.L, a.f, a.x, cur_r(a, sel), nullptr);
+}
+
+template <typename T>
+__global__ __launch_bounds__(kNT) void kb_ne_p(const BInst<T>* __restrict__ B, int sel) {
+  const BInst<T>& a = B[blockIdx.z];
+  if (!*a.active) return;
+  ne_p_body<T>(a.L, a.x, cur_r(a, sel), a.p);
+}
+
+template <typename T>
+__global__ __launch_bounds__(kNT) void kb_ne_r(const BInst<T>* __restrict__ B, int sel) {
+  const BInst<T>& a = B[blockIdx.z];
+  if (!*a.active) return;
+  ne_r_body<T>(a.L, a.p, cur_r(a, sel));
+}
+
+template <typename T>
+__global__ __launch_bounds__(kNT) void kb_cgs_phase(const BInst<T>* __restrict__ B, int c, int sel) {
+  const BInst<T>& a = B[blockIdx.z];
+  if (!*a.active) return;
+  cgs_phase_body<T>(a.L, c, a.x, cur_r(a, sel));
+}
+
+template <typename T>
+__global__ __launch_bounds__(kNT) void kb_restrict(const BInst<T>* __restrict__ B, int sel, int zero_coarse) {
+  const BInst<T>& a = B[blockIdx.z];
+  if (!*a.active) return;
+  restrict_body<T>(a.L, a.Lc, cur_r(a, sel), a.fc, zero_coarse ? a.xc : nullptr, zero_coarse ? a.rc : nullptr);
+}
+
+template <typename T>
+__global__ __launch_bounds__(kNT) void kb_prolong_add(const BInst<T>* __restrict__ B) {
+  const BInst<T>& a = B[blockIdx.z];
+  if (!*a.active) return;
+  prolong_add_body<T>(a.L, a.Lc, a.xc, a.x);
+}
+
+template <int MODE>
+__global__ __launch_bounds__(kNT) void kb_residual_norm(const BFine* __restrict__ B) {
+  const BFine& a = B[blockIdx.z];
+  if (!*a.active) return;
+  residual_body<double, true, MODE>(a.L, a.f, a.x, a.r, a.part);
+}
+
+template <int MODE>
+__global__ __launch_bounds__(kNT) void kb_vnorm(const BFine* __restrict__ B) {
+  const BFine& a = B[blockIdx.z];
+  if (!*a.active) return;
+  const Lev& L = a.L;
+  const int i = blockIdx.x * kBX + threadIdx.x;
+  const int j = blockIdx.y * kBY + threadIdx.y;
+  double s2 = 0.0;
+  if (i <= L.n && j <= L.n) {
+    const int w = j * L.ld + i;
+    s2 = norm_term<MODE>(L, i, j, a.f[w], a.f[L.V + w]);
+  }
+  block_sum_store(s2, &a.part[blockIdx.y * gridDim.x + blockIdx.x]);
+}
+
+__global__ __launch_bounds__(256) void kb_sum(const BFine* __restrict__ B, int nparts, int slot) {
+  const BFine& a = B[blockIdx.x];
+  if (!*a.active) return;
+  sum_body(a.part, nparts, 1.0, a.norm + slot);
+}
+
+__global__ void kb_to_f32_scaled(const BFine* __restrict__ B, size_t len) {
+  const BFine& a = B[blockIdx.y];
+  if (!*a.active) return;
+  to_f32_scaled_body(a.r, len, a.norm, a.f32, a.r32);
+}
+
+__global__ void kb_zero_x32(const BFine* __restrict__ B, size_t len) {
+  const BFine& a = B[blockIdx.y];
+  if (!*a.active) return;
+  zero_f32_body(a.x32, len);
+}
+
+__global__ void kb_axpy_f32(const BFine* __restrict__ B, size_t len) {
+  const BFine& a = B[blockIdx.y];
+  if (!*a.active) return;
+  axpy_f32_body(a.x32, len, a.norm, a.x);
+}
+
+__global__ void kb_gather_norms(const double* const* __restrict__ norms, int count, double* __restrict__ out) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= count) return;
+  out[2 * b] = norms[b][0];
+  out[2 * b + 1] = norms[b][1];
 }
 
 inline dim3 grid_vertices(int n) { return dim3((n + 1 + kBX - 1) / kBX, (n + 1 + kBY - 1) / kBY); }
@@ -648,6 +770,91 @@ hipError_t launch_zero_f32(float* v, size_t n, hipStream_t s) {
   return hipGetLastError();
 }
 
+int residual_blocks(int n) {
+  const dim3 g = grid_vertices(n);
+  return (int)(g.x * g.y);
+}
+
+static dim3 zgrid(dim3 g, int count) { return dim3(g.x, g.y, count); }
+
+template <typename T>
+hipError_t launch_b_residual(const BInst<T>* d, int count, int n, int sel, hipStream_t s) {
+  hipLaunchKernelGGL((kb_residual<T>), zgrid(grid_vertices(n), count), kBlock, 0, s, d, sel);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_b_ne(const BInst<T>* d, int count, int n, int sel, hipStream_t s) {
+  hipLaunchKernelGGL((kb_ne_p<T>), zgrid(grid_vertices(n), count), kBlock, 0, s, d, sel);
+  hipLaunchKernelGGL((kb_ne_r<T>), zgrid(grid_vertices(n), count), kBlock, 0, s, d, sel);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_b_cgs_phase(const BInst<T>* d, int count, int n, int colour, int sel, hipStream_t s) {
+  hipLaunchKernelGGL((kb_cgs_phase<T>), zgrid(grid_colour(n), count), kBlock, 0, s, d, colour, sel);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_b_restrict(const BInst<T>* d, int count, int nc, int sel, int zero_coarse, hipStream_t s) {
+  hipLaunchKernelGGL((kb_restrict<T>), zgrid(grid_vertices(nc), count), kBlock, 0, s, d, sel, zero_coarse);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_b_prolong_add(const BInst<T>* d, int count, int nf, hipStream_t s) {
+  hipLaunchKernelGGL((kb_prolong_add<T>), zgrid(grid_vertices(nf), count), kBlock, 0, s, d);
+  return hipGetLastError();
+}
+
+hipError_t launch_b_residual_norm(const BFine* d, int count, int n, int norm_mode, hipStream_t s) {
+  if (norm_mode == 2)
+    hipLaunchKernelGGL((kb_residual_norm<2>), zgrid(grid_vertices(n), count), kBlock, 0, s, d);
+  else
+    hipLaunchKernelGGL((kb_residual_norm<1>), zgrid(grid_vertices(n), count), kBlock, 0, s, d);
+  return hipGetLastError();
+}
+
+hipError_t launch_b_vnorm(const BFine* d, int count, int n, int norm_mode, hipStream_t s) {
+  if (norm_mode == 2)
+    hipLaunchKernelGGL((kb_vnorm<2>), zgrid(grid_vertices(n), count), kBlock, 0, s, d);
+  else
+    hipLaunchKernelGGL((kb_vnorm<1>), zgrid(grid_vertices(n), count), kBlock, 0, s, d);
+  return hipGetLastError();
+}
+
+hipError_t launch_b_sum(const BFine* d, int count, int nparts, int slot, hipStream_t s) {
+  hipLaunchKernelGGL(kb_sum, dim3(count), dim3(256), 0, s, d, nparts, slot);
+  return hipGetLastError();
+}
+
+static dim3 ygrid(size_t len, int count) {
+  size_t g = (len + 255) / 256;
+  if (g > 1024) g = 1024;
+  return dim3(g < 1 ? 1 : (unsigned)g, count);
+}
+
+hipError_t launch_b_to_f32_scaled(const BFine* d, int count, size_t len, hipStream_t s) {
+  hipLaunchKernelGGL(kb_to_f32_scaled, ygrid(len, count), dim3(256), 0, s, d, len);
+  return hipGetLastError();
+}
+
+hipError_t launch_b_zero_x32(const BFine* d, int count, size_t len, hipStream_t s) {
+  hipLaunchKernelGGL(kb_zero_x32, ygrid(len, count), dim3(256), 0, s, d, len);
+  return hipGetLastError();
+}
+
+hipError_t launch_b_axpy_f32(const BFine* d, int count, size_t len, hipStream_t s) {
+  hipLaunchKernelGGL(kb_axpy_f32, ygrid(len, count), dim3(256), 0, s, d, len);
+  return hipGetLastError();
+}
+
+hipError_t launch_b_gather_norms(const double* const* d, int count, double* out, hipStream_t s) {
+  hipLaunchKernelGGL(kb_gather_norms, dim3((count + 63) / 64), dim3(64), 0, s, d, count, out);
+  return hipGetLastError();
+}
+
 #define MGK_INSTANTIATE(T)                                                                                          \
   template hipError_t launch_residual<T>(const Lev&, const T*, const T*, T*, double*, int, int*, hipStream_t);         \
   template hipError_t launch_apply<T>(const Lev&, const T*, T*, hipStream_t);                                      \
@@ -657,7 +864,12 @@ hipError_t launch_zero_f32(float* v, size_t n, hipStream_t s) {
   template hipError_t launch_cgs_phase<T>(const Lev&, int, T*, T*, hipStream_t);                                   \
   template hipError_t launch_restrict<T>(const Lev&, const Lev&, const T*, T*, T*, T*, hipStream_t);              \
   template hipError_t launch_prolong_add<T>(const Lev&, const Lev&, const T*, T*, hipStream_t);                    \
-  template hipError_t launch_coarse_solve<T>(int, const double*, const int*, const T*, T*, hipStream_t);
+  template hipError_t launch_coarse_solve<T>(int, const double*, const int*, const T*, T*, hipStream_t);         \
+  template hipError_t launch_b_residual<T>(const BInst<T>*, int, int, int, hipStream_t);                          \
+  template hipError_t launch_b_ne<T>(const BInst<T>*, int, int, int, hipStream_t);                                \
+  template hipError_t launch_b_cgs_phase<T>(const BInst<T>*, int, int, int, int, hipStream_t);                    \
+  template hipError_t launch_b_restrict<T>(const BInst<T>*, int, int, int, int, hipStream_t);                     \
+  template hipError_t launch_b_prolong_add<T>(const BInst<T>*, int, int, hipStream_t);
 
 MGK_INSTANTIATE(double)
 MGK_INSTANTIATE(float)

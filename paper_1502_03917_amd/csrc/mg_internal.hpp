@@ -66,6 +66,27 @@ __host__ __device__ inline int cls5(int i, int n) {
   return i <= 1 ? i : (i >= n - 1 ? 4 - (n - i) : 2);
 }
 
+// ---- batched launches: many independent instances of the same level in one
+// launch; the instance is blockIdx.z (vertex-grid kernels) or blockIdx.y (tile
+// sweep, one-dimensional kernels), its arguments come from a device array,
+// and an instance whose flag is 0 is skipped (its blocks exit at once).
+template <typename T>
+struct BInst {
+  Lev L, Lc;              // the level and the next coarser one
+  T *x, *f, *r, *r2, *p;  // level buffers (r2: ping-pong partner of r)
+  T *xc, *fc, *rc;        // coarser-level buffers
+  const int* active;
+};
+// the finest level of an instance: the FP64 outer iteration
+struct BFine {
+  Lev L;
+  const double* f;
+  double *x, *r;
+  float *f32, *x32, *r32;  // FP32 cycle buffers of the finest level (refinement)
+  double *part, *norm;     // per-block partial sums; norm[0] = ||r||^2, norm[1] = ||f||^2
+  const int* active;
+};
+
 // ---- kernel launchers (kernels.hip); all enqueue on stream s ----------------
 // r = f - A x; with part != nullptr also per-block partial sums of ||r||^2,
 // Euclidean (norm_mode 1) or in the L^{-1} norm (norm_mode 2)
@@ -109,6 +130,42 @@ hipError_t launch_adjoint_grad(const Lev& L, const double* x, const double* xa, 
 // u = lambda / alpha
 hipError_t launch_control(const Lev& L, const double* x, double* u, hipStream_t s);
 hipError_t launch_sumsq(const double* v, size_t n, double* part, int* nblocks, hipStream_t s);
+
+// batched forms (count instances of level n; `sel` picks r (0) or r2 (1) as
+// the current residual buffer)
+template <typename T>
+hipError_t launch_b_residual(const BInst<T>* d, int count, int n, int sel, hipStream_t s);
+template <typename T>
+hipError_t launch_b_ne(const BInst<T>* d, int count, int n, int sel, hipStream_t s);
+template <typename T>
+hipError_t launch_b_cgs_phase(const BInst<T>* d, int count, int n, int colour, int sel, hipStream_t s);
+// one LSGS sweep reading the `sel` buffer and writing the other
+template <typename T>
+hipError_t launch_b_lsgs_sweep(const BInst<T>* d, int count, int n, int reverse, int sel, hipStream_t s);
+// f_c = P^T r (the `sel` buffer); with zero_coarse also x_c = 0, r_c = f_c
+template <typename T>
+hipError_t launch_b_restrict(const BInst<T>* d, int count, int nc, int sel, int zero_coarse, hipStream_t s);
+template <typename T>
+hipError_t launch_b_prolong_add(const BInst<T>* d, int count, int nf, hipStream_t s);
+// finest level: r = f - A x with norm partials (norm_mode 1 Euclidean, 2 L^-1),
+// or partials of ||f|| (vnorm); sums into norm[slot]
+hipError_t launch_b_residual_norm(const BFine* d, int count, int n, int norm_mode, hipStream_t s);
+hipError_t launch_b_vnorm(const BFine* d, int count, int n, int norm_mode, hipStream_t s);
+hipError_t launch_b_sum(const BFine* d, int count, int nparts, int slot, hipStream_t s);
+hipError_t launch_b_to_f32_scaled(const BFine* d, int count, size_t len, hipStream_t s);
+hipError_t launch_b_zero_x32(const BFine* d, int count, size_t len, hipStream_t s);
+hipError_t launch_b_axpy_f32(const BFine* d, int count, size_t len, hipStream_t s);
+// out[2b] = norms[b][0], out[2b+1] = norms[b][1] for b < count
+hipError_t launch_b_gather_norms(const double* const* norms, int count, double* out, hipStream_t s);
+int residual_blocks(int n);  // partial sums written by a level-n residual
+// batched tail: one workgroup per instance; `args` is a device array built
+// with make_tail_args
+template <typename T>
+size_t tail_args_bytes();
+template <typename T>
+void make_tail_args(const TailLaunch& tl, const T* fT, T* xT, int first, const int* active, void* out);
+template <typename T>
+hipError_t launch_b_tail(const void* args, int count, size_t lds_bytes, hipStream_t s);
 
 // FP32-preconditioned iterative refinement glue
 // refinement scale s = sqrt(*nrm2) read on the device (1 if the norm is zero)

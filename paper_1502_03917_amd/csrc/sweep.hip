@@ -68,8 +68,8 @@ struct TileGeom {
 // tile r * gridDim.x + its slot) and loads the next tile into registers while
 // the current one is computed.  Otherwise one tile per workgroup.
 template <typename T, int TW, int NT, bool PERSIST>
-__global__ __launch_bounds__(NT) void k_lsgs_tile(Lev L, int ntx, int nty, int reverse, T* __restrict__ x,
-                                                  const T* __restrict__ rin, T* __restrict__ rout) {
+__device__ __forceinline__ void lsgs_tile_body(const Lev& L, int ntx, int nty, int reverse, T* __restrict__ x,
+                                               const T* __restrict__ rin, T* __restrict__ rout) {
   using G = TileGeom<TW>;
   constexpr int NR = (G::RMAX * G::RMAX + NT - 1) / NT;  // region cells per thread
   constexpr int NX = (TW * TW + NT - 1) / NT;            // owned cells per thread
@@ -305,6 +305,21 @@ __global__ __launch_bounds__(NT) void k_lsgs_tile(Lev L, int ntx, int nty, int r
   }
 }
 
+template <typename T, int TW, int NT, bool PERSIST>
+__global__ __launch_bounds__(NT) void k_lsgs_tile(Lev L, int ntx, int nty, int reverse, T* __restrict__ x,
+                                                  const T* __restrict__ rin, T* __restrict__ rout) {
+  lsgs_tile_body<T, TW, NT, PERSIST>(L, ntx, nty, reverse, x, rin, rout);
+}
+
+// many instances of one level: instance blockIdx.y, residual read from r
+// (sel 0) or r2 (sel 1) and written to the other
+template <typename T, int TW, int NT>
+__global__ __launch_bounds__(NT) void kb_lsgs_tile(const BInst<T>* __restrict__ B, int ntx, int reverse, int sel) {
+  const BInst<T>& a = B[blockIdx.y];
+  if (!*a.active) return;
+  lsgs_tile_body<T, TW, NT, false>(a.L, ntx, ntx, reverse, a.x, sel ? a.r2 : a.r, sel ? a.r : a.r2);
+}
+
 inline int tiles_along(int npts, int TW) { return (npts + TW - 1) / TW; }
 
 // Grid shape.  With one workgroup resident per CU (FP64: the tile needs
@@ -344,6 +359,15 @@ hipError_t launch_tile_cfg(const Lev& L, bool allow_persistent, int reverse, T* 
 }
 
 }  // namespace
+
+template <typename T>
+hipError_t launch_b_lsgs_sweep(const BInst<T>* d, int count, int n, int reverse, int sel, hipStream_t s) {
+  const int nt = tiles_along(n + 1, 48);
+  hipLaunchKernelGGL((kb_lsgs_tile<T, 48, 512>), dim3(round8(nt * nt), count), dim3(512), 0, s, d, nt, reverse, sel);
+  return hipGetLastError();
+}
+template hipError_t launch_b_lsgs_sweep<double>(const BInst<double>*, int, int, int, int, hipStream_t);
+template hipError_t launch_b_lsgs_sweep<float>(const BInst<float>*, int, int, int, int, hipStream_t);
 
 template <>
 hipError_t launch_lsgs_sweep<double>(const Lev& L, int reverse, double* x, const double* rin, double* rout,

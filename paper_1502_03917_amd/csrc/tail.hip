@@ -45,12 +45,13 @@ struct TailArgs {
   const T* fT;           // f on level T (global)
   T* xT;                 // x on level T (global): in (if !first) / out
   int first;             // 1: x_T starts at zero and r_T = f_T
+  const int* active;     // batched launches: 0 = skip this instance (nullptr: always run)
 };
 
 }  // namespace
 
 template <typename T>
-__global__ __launch_bounds__(kTailThreads) void k_tail(TailArgs<T> A) {
+__device__ __forceinline__ void tail_body(const TailArgs<T>& A) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   T* sm = reinterpret_cast<T*>(smem_raw);
   const int tid = threadIdx.x;
@@ -326,6 +327,19 @@ __global__ __launch_bounds__(kTailThreads) void k_tail(TailArgs<T> A) {
   }
 }
 
+template <typename T>
+__global__ __launch_bounds__(kTailThreads) void k_tail(TailArgs<T> A) {
+  tail_body<T>(A);
+}
+
+// one workgroup per instance of a batch
+template <typename T>
+__global__ __launch_bounds__(kTailThreads) void kb_tail(const TailArgs<T>* __restrict__ all) {
+  const TailArgs<T>& A = all[blockIdx.x];
+  if (A.active && !*A.active) return;
+  tail_body<T>(A);
+}
+
 // host-side layout of the tail: LDS offsets and bytes
 template <typename T>
 size_t tail_layout(int k0, int Tl, TailLevel* lv) {
@@ -348,11 +362,9 @@ size_t tail_layout(int k0, int Tl, TailLevel* lv) {
 }
 
 template <typename T>
-hipError_t launch_tail(const TailLaunch& tl, const T* fT, T* xT, int first, hipStream_t s) {
-  TailArgs<T> a;
+size_t fill_tail_args(const TailLaunch& tl, const T* fT, T* xT, int first, const int* active, TailArgs<T>& a) {
   memset(&a, 0, sizeof(a));
   const size_t bytes = tail_layout<T>(tl.k0, tl.T, a.lv);
-  if (bytes > tl.max_lds) return hipErrorInvalidValue;
   for (int l = tl.k0; l <= tl.T; l++) a.lev[l] = tl.lev[l];
   a.k0 = tl.k0;
   a.tlev = tl.T;
@@ -366,7 +378,33 @@ hipError_t launch_tail(const TailLaunch& tl, const T* fT, T* xT, int first, hipS
   a.fT = fT;
   a.xT = xT;
   a.first = first;
+  a.active = active;
+  return bytes;
+}
+
+template <typename T>
+hipError_t launch_tail(const TailLaunch& tl, const T* fT, T* xT, int first, hipStream_t s) {
+  TailArgs<T> a;
+  const size_t bytes = fill_tail_args<T>(tl, fT, xT, first, nullptr, a);
+  if (bytes > tl.max_lds) return hipErrorInvalidValue;
   hipLaunchKernelGGL((k_tail<T>), dim3(1), dim3(kTailThreads), bytes, s, a);
+  return hipGetLastError();
+}
+
+template <typename T>
+size_t tail_args_bytes() {
+  return sizeof(TailArgs<T>);
+}
+
+template <typename T>
+void make_tail_args(const TailLaunch& tl, const T* fT, T* xT, int first, const int* active, void* out) {
+  (void)fill_tail_args<T>(tl, fT, xT, first, active, *static_cast<TailArgs<T>*>(out));
+}
+
+template <typename T>
+hipError_t launch_b_tail(const void* args, int count, size_t lds_bytes, hipStream_t s) {
+  hipLaunchKernelGGL((kb_tail<T>), dim3(count), dim3(kTailThreads), lds_bytes, s,
+                     static_cast<const TailArgs<T>*>(args));
   return hipGetLastError();
 }
 
@@ -377,14 +415,24 @@ size_t tail_lds_bytes(int k0, int Tl) {
 }
 
 hipError_t tail_allow_lds(size_t bytes) {
-  hipError_t e = hipFuncSetAttribute((const void*)k_tail<double>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
-  if (e != hipSuccess) return e;
-  return hipFuncSetAttribute((const void*)k_tail<float>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+  const void* fns[4] = {(const void*)k_tail<double>, (const void*)k_tail<float>, (const void*)kb_tail<double>,
+                        (const void*)kb_tail<float>};
+  for (const void* fn : fns) {
+    hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 
 template hipError_t launch_tail<double>(const TailLaunch&, const double*, double*, int, hipStream_t);
 template hipError_t launch_tail<float>(const TailLaunch&, const float*, float*, int, hipStream_t);
 template size_t tail_lds_bytes<double>(int, int);
 template size_t tail_lds_bytes<float>(int, int);
+template size_t tail_args_bytes<double>();
+template size_t tail_args_bytes<float>();
+template void make_tail_args<double>(const TailLaunch&, const double*, double*, int, const int*, void*);
+template void make_tail_args<float>(const TailLaunch&, const float*, float*, int, const int*, void*);
+template hipError_t launch_b_tail<double>(const void*, int, size_t, hipStream_t);
+template hipError_t launch_b_tail<float>(const void*, int, size_t, hipStream_t);
 
 }  // namespace mgk

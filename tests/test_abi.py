@@ -86,7 +86,39 @@ def test_null_context_calls():
     assert L.mg_timing_enable(None, 1) == mg.MG_EINVAL
     assert L.mg_control(None, None, None, None) == mg.MG_EINVAL
     assert L.mg_adjoint_grad(None, None, None, None, None, None) == mg.MG_EINVAL
+    assert L.mg_batch_count(None) == 0
+    assert L.mg_batch_vec_len(None, 0) == 0
+    assert L.mg_batch_last_error(None) == b"no batch"
+    assert L.mg_batch_rhs(None, None, None, None) == mg.MG_EINVAL
+    assert L.mg_batch_solve(None, None, None, 1e-10, None, None, None, None) == mg.MG_EINVAL
+    L.mg_batch_destroy(None)
     L.mg_destroy(None)
+
+
+def _batch_setup(levels, alphas, **kw):
+    L = mg.lib()
+    o = L.mg_default_opts(0)
+    for k, v in kw.items():
+        setattr(o, k, v)
+    n = len(levels)
+    h = ctypes.c_void_p()
+    st = L.mg_batch_setup(n, (ctypes.c_int * n)(*levels), (ctypes.c_double * n)(*alphas), 0, ctypes.byref(o),
+                          ctypes.byref(h))
+    return st, h
+
+
+@pytest.mark.parametrize("levels,alphas", [([], []), ([5], [1.0]), ([13], [1.0]), ([7, 8], [1.0, 0.0]),
+                                           ([7], [math.nan]), ([7], [-1.0])])
+def test_batch_setup_rejects_arguments(levels, alphas):
+    st, h = _batch_setup(levels, alphas) if levels else (mg.lib().mg_batch_setup(0, None, None, 0, None,
+                                                                                  ctypes.byref(ctypes.c_void_p())), None)
+    assert st == mg.MG_EINVAL
+
+
+@pytest.mark.parametrize("field,value", [("gamma", 2), ("inner_cycles", 2), ("coarse_level", 3)])
+def test_batch_setup_unsupported_options(field, value):
+    # rejected before any device allocation
+    assert _batch_setup([7, 8], [1.0, 1e-4], **{field: value})[0] == mg.MG_EUNSUPPORTED
 
 
 def test_strerror_covers_all_codes():

@@ -77,7 +77,7 @@ def test_autograd_matches_oracle_gradient(torch_cuda, alpha):
     V = yd_np.size
     assert np.abs(_host(y) - x_ref[:V]).max() <= 1e-10 * np.abs(x_ref[:V]).max()
     assert _host(u) == pytest.approx(x_ref[V:] / alpha, rel=1e-9, abs=1e-9 * np.abs(x_ref[V:] / alpha).max())
-    assert float(loss) == pytest.approx(loss_ref, rel=1e-10)
+    assert float(loss.detach()) == pytest.approx(loss_ref, rel=1e-10)
     g = _host(yd.grad)
     assert np.abs(g - g_ref).max() <= 1e-9 * np.abs(g_ref).max()
     assert float(al.grad) == pytest.approx(a_ref, rel=1e-9)
