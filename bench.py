@@ -197,6 +197,59 @@ def copy_probe() -> int:
     return 0
 
 
+def batch_measure(steps: int, tol: float):
+    """64 independent instances (257^2, 513^2 or 1025^2 vertices, alpha
+    log-uniform in [1e-8, 1], y_D seeds 3000 + i), FP32 cycles inside FP64
+    refinement, solved together from x = 0; timed with the batched iterate
+    replayed from a HIP graph and launched eagerly."""
+    import torch
+
+    import paper_1502_03917_amd as mg
+    import workloads
+
+    inst = workloads.batch_instances(64, seed=3)
+    levels = [l for l, _, _ in inst]
+    alphas = [a for _, a, _ in inst]
+    yds = [torch.from_numpy(workloads.desired_state(l, sd)).cuda() for l, _, sd in inst]
+    out = {"instances": len(inst), "levels": {str(l): levels.count(l) for l in sorted(set(levels))},
+           "unknowns": sum(2 * ((1 << l) + 1) ** 2 for l in levels), "precision": "fp32_ir", "tol": tol}
+
+    def timed(graph: bool):
+        if not graph:
+            os.environ["MGKKT_NO_GRAPH"] = "1"
+        try:
+            b = mg.Batch(levels, alphas, precision="fp32_ir")
+        finally:
+            os.environ.pop("MGKKT_NO_GRAPH", None)
+        fs = b.rhs(yds)
+        xs = [torch.zeros(b.vec_len(i), dtype=torch.float64, device="cuda") for i in range(len(inst))]
+        b.solve(fs, xs, tol=tol, raise_on_error=False)  # warm-up (graph capture)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        cyc_total, st = 0, 0
+        for _ in range(steps):
+            for x in xs:
+                x.zero_()
+            _, cyc, rel, _, st = b.solve(fs, xs, tol=tol, raise_on_error=False)
+            cyc_total += sum(cyc)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / steps
+        b.close()
+        return dt, cyc_total / steps, cyc, rel, st
+
+    dt, cyc_sum, cyc, rel, st = timed(True)
+    dt_eager, _, _, _, _ = timed(False)
+    nbytes = 0.0
+    for l, c in zip(levels, cyc):
+        V = ((1 << l) + 1) ** 2
+        nbytes += c * (words_per_cycle(l, 1, 2, 2) * 4 + V * 2 * (8 + 8 + 8 + 4 + 8))
+    out.update({"ms_per_solve": 1e3 * dt, "ms_per_solve_eager": 1e3 * dt_eager,
+                "instance_vcycles_per_s": cyc_sum / dt, "cycles_min_max": [min(cyc), max(cyc)],
+                "max_relres": max(rel), "status": mg.lib().mg_strerror(st).decode(),
+                "aggregate_algorithmic_GBps": nbytes / dt / 1e9})
+    return out
+
+
 def cpu_baseline(level: int, alpha: float, seed: int, smoother: str, cycles: int):
     import numpy as np
 
@@ -228,6 +281,8 @@ def main() -> int:
     ap.add_argument("--seed", type=int, default=2)
     ap.add_argument("--cpu-cycles", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-batch", action="store_true", help="skip the 64-instance batched solve")
+    ap.add_argument("--batch-only", action="store_true", help="run only the 64-instance batched solve")
     ap.add_argument("--variants", action="store_true", help="also time the other smoother/precision/alpha variants")
     ap.add_argument("--copy-probe", action="store_true", help="run only the plain copy that calibrates the counters")
     ap.add_argument("--trace", help="summarise a rocprofv3 kernel-trace CSV directory and exit")
@@ -255,6 +310,9 @@ def main() -> int:
     torch.cuda.set_device(0)
     if args.copy_probe:
         return copy_probe()
+    if args.batch_only:
+        print(json.dumps(batch_measure(max(2, args.steps // 3), args.tol)), flush=True)
+        return 0
     yd = torch.from_numpy(workloads.desired_state(args.level, args.seed)).cuda()
 
     def run(smoother, precision, alpha, steps, warmup, timing=False):
@@ -347,6 +405,9 @@ def main() -> int:
                     log(f"bench: variant {key}")
                     var[key] = run(sm, pr, al, 2, 1)
         result["variants"] = var
+    if not args.no_batch:
+        log("bench: batched solve of 64 instances (fp32_ir)")
+        result["batch"] = batch_measure(max(2, args.steps // 3), args.tol)
     if not args.no_cpu_baseline:
         log(f"bench: CPU oracle baseline ({args.cpu_cycles} cycles)")
         result["cpu_baseline"] = cpu_baseline(args.level, args.alpha, args.seed, args.smoother, args.cpu_cycles)

@@ -28,13 +28,14 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _LIB_PATH = os.path.join(_HERE, "libmgo.so")
 _lib = None
 
-NE, LSGS, SLSGS, CGS = 0, 1, 2, 3
+NE, LSGS, SLSGS, CGS, VANKA = 0, 1, 2, 3, 4
 ORDER_LEX, ORDER_COL7, ORDER_COL7SEQ, ORDER_VLEX, ORDER_COL3 = 0, 1, 2, 3, 4
-SMOOTHERS = {"ne": NE, "lsgs": LSGS, "slsgs": SLSGS, "cgs": CGS}
+SMOOTHERS = {"ne": NE, "lsgs": LSGS, "slsgs": SLSGS, "cgs": CGS, "vanka": VANKA}
 ORDERS = {"lex": ORDER_LEX, "col7": ORDER_COL7, "col7seq": ORDER_COL7SEQ, "vlex": ORDER_VLEX, "col3": ORDER_COL3}
 # damping of the normal-equation smoother used in the paper's experiments
-# (section 3): 0.4 for Poisson control, 0.35 for Stokes control
-TAU_POISSON, TAU_STOKES = 0.4, 0.35
+# (section 3): 0.4 for Poisson control, 0.35 for Stokes control; the Stokes
+# patch (Vanka-type) smoother is damped with 0.4
+TAU_POISSON, TAU_STOKES, TAU_VANKA = 0.4, 0.35, 0.4
 
 
 def build(force: bool = True) -> str:
@@ -71,6 +72,10 @@ def _load():
     lib.mgo_cycle.argtypes = [vp, ip, ip, ip, dp, ip, ip, ip, vp, vp]
     lib.mgo_solve.argtypes = [vp, ip, ip, dp, ip, ip, ip, vp, vp, dp, ip, ip, vp]
     lib.mgo_solve.restype = ip
+    lib.mgo_project.argtypes = [vp, ip, vp]
+    lib.mgo_assemble_p2.argtypes = [ip, ip, vp, vp, vp, vp]
+    lib.mgo_prolongation_p2.argtypes = [ip, ip, vp]
+    lib.mgo_csr_free.argtypes = [vp]
     _lib = lib
     return lib
 
@@ -80,14 +85,59 @@ def _ptr(a: np.ndarray):
     return a.ctypes.data_as(ctypes.c_void_p)
 
 
-class Hierarchy:
-    """Levels coarse..fine of the Poisson control KKT system (eq. mp2).
+class _Csr(ctypes.Structure):
+    _fields_ = [("nrows", ctypes.c_int), ("ncols", ctypes.c_int), ("nnz", ctypes.c_int),
+                ("rowptr", ctypes.POINTER(ctypes.c_int)), ("col", ctypes.POINTER(ctypes.c_int)),
+                ("val", ctypes.POINTER(ctypes.c_double))]
 
-    Level l has n = 2^l cells per side of the unit square, (n+1)^2 vertices
-    and 2 (n+1)^2 unknowns x = (y; lambda), field-major.
+
+def _take(c: _Csr):
+    import scipy.sparse as sp
+
+    rp = np.ctypeslib.as_array(c.rowptr, shape=(c.nrows + 1,)).copy()
+    ci = np.ctypeslib.as_array(c.col, shape=(max(c.nnz, 1),))[: c.nnz].copy()
+    va = np.ctypeslib.as_array(c.val, shape=(max(c.nnz, 1),))[: c.nnz].copy()
+    out = sp.csr_matrix((va, ci, rp), shape=(c.nrows, c.ncols))
+    _load().mgo_csr_free(ctypes.byref(c))
+    return out
+
+
+def taylor_hood(n: int, full: bool = False):
+    """(M, K, D1, D2) of the P2/P1 pair with n cells per side (eq. mp3 blocks):
+    scalar P2 mass and Laplacian stiffness over the interior P2 nodes (or all
+    nodes), and D_c = -int q d_c phi with rows over the P1 vertices."""
+    mats = [_Csr() for _ in range(4)]
+    _load().mgo_assemble_p2(n, int(full), *[ctypes.byref(m) for m in mats])
+    return tuple(_take(m) for m in mats)
+
+
+def prolongation_p2(nc: int, full: bool = False):
+    c = _Csr()
+    _load().mgo_prolongation_p2(nc, int(full), ctypes.byref(c))
+    return _take(c)
+
+
+def p2_nodes(level: int, full: bool = False):
+    """Coordinates (X, Y) of the P2 nodes of level `level` in index order."""
+    n = 1 << level
+    idx = np.arange(0, 2 * n + 1) if full else np.arange(1, 2 * n)
+    B, A = np.meshgrid(idx, idx, indexing="ij")
+    return (A / (2.0 * n)).ravel(), (B / (2.0 * n)).ravel()
+
+
+class Hierarchy:
+    """Levels coarse..fine of the Poisson control KKT system (eq. mp2,
+    problem 0 / "poisson") or of the Stokes control system (eq. mp3,
+    problem 1 / "stokes", Taylor-Hood).
+
+    Poisson: level l has n = 2^l cells per side of the unit square, (n+1)^2
+    vertices and 2 (n+1)^2 unknowns x = (y; lambda), field-major.
+    Stokes: [v1 | v2 | p | lambda1 | lambda2 | mu] with (2n-1)^2 interior P2
+    nodes per velocity component and (n+1)^2 pressure vertices.
     """
 
-    def __init__(self, level: int, alpha: float, coarse: int = 1, problem: int = 0):
+    def __init__(self, level: int, alpha: float, coarse: int = 1, problem=0):
+        problem = {"poisson": 0, "stokes": 1}.get(problem, problem)
         self.lib = _load()
         self.level, self.coarse, self.alpha, self.problem = level, coarse, float(alpha), problem
         h = self.lib.mgo_create(problem, level, coarse, float(alpha))
@@ -105,6 +155,11 @@ class Hierarchy:
             self.close()
         except Exception:
             pass
+
+    def _tau(self, smoother: str) -> float:
+        if smoother == "vanka":
+            return TAU_VANKA
+        return TAU_STOKES if self.problem == 1 else TAU_POISSON
 
     def ndof(self, level: int | None = None) -> int:
         return self.lib.mgo_ndof(self._h, self.level if level is None else level)
@@ -153,7 +208,7 @@ class Hierarchy:
     def smooth(self, x: np.ndarray, r: np.ndarray, smoother="lsgs", order="col7", tau=None, level=None):
         """One smoothing step in place on (x, r), r = f - A x kept current."""
         l = self.level if level is None else level
-        tau = TAU_POISSON if tau is None else tau
+        tau = self._tau(smoother) if tau is None else tau
         self.lib.mgo_smooth(self._h, l, SMOOTHERS[smoother], ORDERS[order], float(tau), _ptr(x), _ptr(r))
 
     def smooth_groups(self, x: np.ndarray, r: np.ndarray, groups, reverse=False, level=None):
@@ -175,7 +230,7 @@ class Hierarchy:
     def cycle(self, f, x, smoother="lsgs", order="col7", tau=None, nu1=2, nu2=2, gamma=1, level=None):
         """One multigrid iterate in place on x (x must be a float64 C array)."""
         l = self.level if level is None else level
-        tau = TAU_POISSON if tau is None else tau
+        tau = self._tau(smoother) if tau is None else tau
         f = np.ascontiguousarray(f, dtype=np.float64)
         self.lib.mgo_cycle(self._h, l, SMOOTHERS[smoother], ORDERS[order], float(tau), nu1, nu2, gamma, _ptr(f), _ptr(x))
         return x
@@ -184,7 +239,7 @@ class Hierarchy:
               nu1=2, nu2=2, gamma=1, norm="linv"):
         """Cycles until ||f - A x|| <= tol ||f|| in the Euclidean norm ("l2") or
         the L_k^{-1} norm ("linv"). Returns (x, cycles, history)."""
-        tau = TAU_POISSON if tau is None else tau
+        tau = self._tau(smoother) if tau is None else tau
         f = np.ascontiguousarray(f, dtype=np.float64)
         x = np.zeros(self.ndof()) if x0 is None else np.array(x0, dtype=np.float64, copy=True)
         hist = np.zeros(max_cycles + 2)
@@ -196,14 +251,39 @@ class Hierarchy:
     # -- post-processing written from the problem statement -----------------
 
     def rhs(self, yd: np.ndarray, level: int | None = None) -> np.ndarray:
-        """f = (M y_D; 0) with y_D the nodal values of the desired state."""
+        """Poisson: f = (M y_D; 0) with y_D the nodal values of the desired
+        state.  Stokes: f = (M v_D; 0; 0; 0) with v_D = [v1 | v2] the desired
+        velocity at the interior P2 nodes (M the P2 mass of each component)."""
         M = self.matrix("M", level)
         V = M.shape[0]
+        yd = np.asarray(yd, dtype=np.float64)
+        if self.problem == 1:
+            f = np.zeros(self.ndof(level))
+            f[:V] = M @ yd[:V]
+            f[V:2 * V] = M @ yd[V:2 * V]
+            return f
         f = np.zeros(2 * V)
-        f[:V] = M @ np.asarray(yd, dtype=np.float64)
+        f[:V] = M @ yd
         return f
 
+    def project(self, x: np.ndarray, level: int | None = None) -> np.ndarray:
+        """Stokes: p and mu shifted to zero mean (in place); Poisson: no-op."""
+        self.lib.mgo_project(self._h, self.level if level is None else level, _ptr(x))
+        return x
+
+    def fields(self, level: int | None = None):
+        """Stokes: slices of v1, v2, p, lambda1, lambda2, mu."""
+        l = self.level if level is None else level
+        n = 1 << l
+        nv, np_ = (2 * n - 1) ** 2, (n + 1) ** 2
+        sizes = [nv, nv, np_, nv, nv, np_]
+        offs = np.concatenate([[0], np.cumsum(sizes)])
+        return [slice(int(offs[i]), int(offs[i + 1])) for i in range(6)]
+
     def control(self, x: np.ndarray) -> np.ndarray:
+        if self.problem == 1:
+            fl = self.fields()
+            return np.concatenate([x[fl[3]], x[fl[4]]]) / self.alpha
         V = x.shape[0] // 2
         return x[V:] / self.alpha
 

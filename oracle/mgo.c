@@ -277,9 +277,17 @@ typedef struct {
   int *ord[4], *gptr[4], ngroup[4];
   int *cgs_ord[3]; /* vertex orders for the collective smoother: lex, col7, col3 */
   int ncgs;
-  /* coarsest level only: dense LU with partial pivoting */
+  /* coarsest level only: dense LU with partial pivoting (Stokes: of the
+   * matrix bordered by the two mean-value constraints) */
   double *lu;
   int *piv;
+  int nlu;
+  /* Stokes: P2 nodes per velocity component, P1 vertices, the divergence
+   * blocks of the two components, and the Vanka patches (one per vertex) */
+  int nv, np;
+  mgo_csr D1, D2;
+  int *patch_ptr, *patch_dof;
+  int *vanka_ord[2];
 } mgo_level;
 
 struct mgo_hier {
@@ -475,10 +483,449 @@ static int build_level_poisson(mgo_level *L, int n, double alpha) {
   return 0;
 }
 
+/* ------------------------------------------- Stokes control (Taylor-Hood) */
+/*
+ * Eq. mp3 with P2 velocity (v = 0 on the boundary: interior P2 nodes only)
+ * and P1 pressure on the same mesh.  P2 nodes live on the half-step lattice
+ * (a, b), 0 <= a, b <= 2n, at (a h/2, b h/2): vertices at even (a, b), edge
+ * midpoints elsewhere.  Unknowns [v1 | v2 | p | lambda1 | lambda2 | mu],
+ * interior P2 node (a, b) -> (b-1)(2n-1) + (a-1), vertex (i, j) -> j(n+1)+i.
+ * Element matrices are integrated exactly in barycentric coordinates:
+ *   int_T l1^a l2^b l3^c = 2 |T| a! b! c! / (a+b+c+2)!.
+ */
+
+/* polynomial in the barycentric coordinates, total degree <= 4 */
+typedef struct {
+  double c[5][5][5];
+} bpoly;
+
+static void bp_zero(bpoly *p) { memset(p, 0, sizeof(*p)); }
+
+static void bp_mul(const bpoly *x, const bpoly *y, bpoly *out) {
+  bp_zero(out);
+  for (int a = 0; a <= 4; a++)
+    for (int b = 0; a + b <= 4; b++)
+      for (int c = 0; a + b + c <= 4; c++) {
+        if (x->c[a][b][c] == 0.0) continue;
+        for (int d = 0; a + d <= 4; d++)
+          for (int e = 0; a + b + d + e <= 4; e++)
+            for (int f = 0; a + b + c + d + e + f <= 4; f++)
+              out->c[a + d][b + e][c + f] += x->c[a][b][c] * y->c[d][e][f];
+      }
+}
+
+/* d/d l_k */
+static void bp_diff(const bpoly *x, int k, bpoly *out) {
+  bp_zero(out);
+  for (int a = 0; a <= 4; a++)
+    for (int b = 0; a + b <= 4; b++)
+      for (int c = 0; a + b + c <= 4; c++) {
+        double v = x->c[a][b][c];
+        if (v == 0.0) continue;
+        if (k == 0 && a > 0) out->c[a - 1][b][c] += a * v;
+        if (k == 1 && b > 0) out->c[a][b - 1][c] += b * v;
+        if (k == 2 && c > 0) out->c[a][b][c - 1] += c * v;
+      }
+}
+
+static double fact(int k) {
+  double f = 1.0;
+  for (int i = 2; i <= k; i++) f *= i;
+  return f;
+}
+
+static double bp_int(const bpoly *x, double area) {
+  double s = 0.0;
+  for (int a = 0; a <= 4; a++)
+    for (int b = 0; a + b <= 4; b++)
+      for (int c = 0; a + b + c <= 4; c++)
+        if (x->c[a][b][c] != 0.0) s += x->c[a][b][c] * 2.0 * area * fact(a) * fact(b) * fact(c) / fact(a + b + c + 2);
+  return s;
+}
+
+/* P2 basis of a triangle: local nodes 0, 1, 2 (vertices), 3 = mid(0,1),
+ * 4 = mid(1,2), 5 = mid(0,2); phi_k = l_k (2 l_k - 1), phi_ij = 4 l_i l_j */
+static void p2_basis(bpoly phi[6]) {
+  static const int e[3][2] = {{0, 1}, {1, 2}, {0, 2}};
+  for (int k = 0; k < 6; k++) bp_zero(&phi[k]);
+  phi[0].c[2][0][0] = 2.0, phi[0].c[1][0][0] = -1.0;
+  phi[1].c[0][2][0] = 2.0, phi[1].c[0][1][0] = -1.0;
+  phi[2].c[0][0][2] = 2.0, phi[2].c[0][0][1] = -1.0;
+  for (int m = 0; m < 3; m++) {
+    int pw[3] = {0, 0, 0};
+    pw[e[m][0]] = 1;
+    pw[e[m][1]] = 1;
+    phi[3 + m].c[pw[0]][pw[1]][pw[2]] = 4.0;
+  }
+}
+
+/* local P2 mass, stiffness, and divergence blocks -int q_i d_x phi_j, -int q_i d_y phi_j
+ * (q_i = l_i, the P1 basis) of the triangle with vertices (px, py) */
+static void p2_local(const double px[3], const double py[3], double Ml[6][6], double Kl[6][6], double Dx[3][6],
+                     double Dy[3][6]) {
+  double area2 = (px[1] - px[0]) * (py[2] - py[0]) - (px[2] - px[0]) * (py[1] - py[0]);
+  double area = 0.5 * fabs(area2);
+  double gx[3], gy[3]; /* gradients of the barycentric coordinates */
+  for (int i = 0; i < 3; i++) {
+    int j = (i + 1) % 3, k = (i + 2) % 3;
+    gx[i] = (py[j] - py[k]) / area2;
+    gy[i] = (px[k] - px[j]) / area2;
+  }
+  bpoly phi[6], dphi[6][3], t;
+  p2_basis(phi);
+  for (int a = 0; a < 6; a++)
+    for (int k = 0; k < 3; k++) bp_diff(&phi[a], k, &dphi[a][k]);
+  for (int a = 0; a < 6; a++)
+    for (int b = 0; b < 6; b++) {
+      bp_mul(&phi[a], &phi[b], &t);
+      Ml[a][b] = bp_int(&t, area);
+      double kab = 0.0;
+      for (int k = 0; k < 3; k++)
+        for (int m = 0; m < 3; m++) {
+          bp_mul(&dphi[a][k], &dphi[b][m], &t);
+          kab += (gx[k] * gx[m] + gy[k] * gy[m]) * bp_int(&t, area);
+        }
+      Kl[a][b] = kab;
+    }
+  for (int i = 0; i < 3; i++) {
+    bpoly q;
+    bp_zero(&q);
+    if (i == 0) q.c[1][0][0] = 1.0;
+    if (i == 1) q.c[0][1][0] = 1.0;
+    if (i == 2) q.c[0][0][1] = 1.0;
+    for (int b = 0; b < 6; b++) {
+      double sx = 0.0, sy = 0.0;
+      for (int k = 0; k < 3; k++) {
+        bp_mul(&q, &dphi[b][k], &t);
+        double v = bp_int(&t, area);
+        sx += gx[k] * v;
+        sy += gy[k] * v;
+      }
+      Dx[i][b] = -sx;
+      Dy[i][b] = -sy;
+    }
+  }
+}
+
+/* half-lattice coordinates of the 6 P2 nodes of triangle t of square (i, j) */
+static void p2_tri_nodes(int i, int j, int t, int na[6], int nb[6], int vi[3], int vj[3]) {
+  square_triangles(i, j, t, vi, vj);
+  for (int k = 0; k < 3; k++) {
+    na[k] = 2 * vi[k];
+    nb[k] = 2 * vj[k];
+  }
+  static const int e[3][2] = {{0, 1}, {1, 2}, {0, 2}};
+  for (int m = 0; m < 3; m++) {
+    na[3 + m] = vi[e[m][0]] + vi[e[m][1]];
+    nb[3 + m] = vj[e[m][0]] + vj[e[m][1]];
+  }
+}
+
+/* P2 node index: interior numbering (full = 0, boundary -> -1) or all (2n+1)^2 nodes */
+static int p2_index(int n, int a, int b, int full) {
+  if (full) return b * (2 * n + 1) + a;
+  if (a < 1 || b < 1 || a > 2 * n - 1 || b > 2 * n - 1) return -1;
+  return (b - 1) * (2 * n - 1) + (a - 1);
+}
+
+void mgo_assemble_p2(int n, int full, mgo_csr *M, mgo_csr *K, mgo_csr *D1, mgo_csr *D2) {
+  int nv = full ? (2 * n + 1) * (2 * n + 1) : (2 * n - 1) * (2 * n - 1);
+  int np = (n + 1) * (n + 1);
+  double h = 1.0 / n;
+  rowbuild bm, bk, b1, b2;
+  rb_init(&bm, nv, nv, 25);
+  rb_init(&bk, nv, nv, 25);
+  rb_init(&b1, np, nv, 32);
+  rb_init(&b2, np, nv, 32);
+  for (int j = 0; j < n; j++)
+    for (int i = 0; i < n; i++)
+      for (int t = 0; t < 2; t++) {
+        int na[6], nb[6], vi[3], vj[3];
+        p2_tri_nodes(i, j, t, na, nb, vi, vj);
+        double px[3], py[3];
+        for (int k = 0; k < 3; k++) {
+          px[k] = vi[k] * h;
+          py[k] = vj[k] * h;
+        }
+        double Ml[6][6], Kl[6][6], Dx[3][6], Dy[3][6];
+        p2_local(px, py, Ml, Kl, Dx, Dy);
+        int g[6];
+        for (int a = 0; a < 6; a++) g[a] = p2_index(n, na[a], nb[a], full);
+        for (int a = 0; a < 6; a++) {
+          if (g[a] < 0) continue;
+          for (int b = 0; b < 6; b++) {
+            if (g[b] < 0) continue;
+            rb_add(&bm, g[a], g[b], Ml[a][b]);
+            rb_add(&bk, g[a], g[b], Kl[a][b]);
+          }
+        }
+        for (int q = 0; q < 3; q++) {
+          int vq = vj[q] * (n + 1) + vi[q];
+          for (int b = 0; b < 6; b++) {
+            if (g[b] < 0) continue;
+            rb_add(&b1, vq, g[b], Dx[q][b]);
+            rb_add(&b2, vq, g[b], Dy[q][b]);
+          }
+        }
+      }
+  rb_finish(&bm, M);
+  rb_finish(&bk, K);
+  rb_finish(&b1, D1);
+  rb_finish(&b2, D2);
+}
+
+/* P2 interpolation of the coarse P2 space (nc cells per side) at the fine P2
+ * nodes (2 nc cells per side): the coarse basis functions evaluated at each
+ * fine node.  Interior nodes only (full = 0) or all nodes. */
+void mgo_prolongation_p2(int nc, int full, mgo_csr *P) {
+  int nf = 2 * nc;
+  int nrow = full ? (2 * nf + 1) * (2 * nf + 1) : (2 * nf - 1) * (2 * nf - 1);
+  int ncol = full ? (2 * nc + 1) * (2 * nc + 1) : (2 * nc - 1) * (2 * nc - 1);
+  rowbuild b;
+  rb_init(&b, nrow, ncol, 6);
+  double hc = 1.0 / nc;
+  bpoly phi[6];
+  p2_basis(phi);
+  for (int fb = 0; fb <= 2 * nf; fb++)
+    for (int fa = 0; fa <= 2 * nf; fa++) {
+      int row = p2_index(nf, fa, fb, full);
+      if (row < 0) continue;
+      double X = fa / (2.0 * nf), Y = fb / (2.0 * nf);
+      int i = (int)floor(X / hc), j = (int)floor(Y / hc);
+      if (i > nc - 1) i = nc - 1;
+      if (j > nc - 1) j = nc - 1;
+      /* the "/" diagonal splits the square into x - i hc >= y - j hc (t = 0) and the rest */
+      int t = (X - i * hc >= Y - j * hc) ? 0 : 1;
+      int na[6], nb[6], vi[3], vj[3];
+      p2_tri_nodes(i, j, t, na, nb, vi, vj);
+      double px[3], py[3], lam[3];
+      for (int k = 0; k < 3; k++) {
+        px[k] = vi[k] * hc;
+        py[k] = vj[k] * hc;
+      }
+      barycentric(px, py, X, Y, lam);
+      for (int a = 0; a < 6; a++) {
+        int col = p2_index(nc, na[a], nb[a], full);
+        if (col < 0) continue;
+        double w = 0.0;
+        for (int aa = 0; aa <= 2; aa++)
+          for (int bb = 0; aa + bb <= 2; bb++)
+            for (int cc = 0; aa + bb + cc <= 2; cc++)
+              if (phi[a].c[aa][bb][cc] != 0.0)
+                w += phi[a].c[aa][bb][cc] * pow(lam[0], aa) * pow(lam[1], bb) * pow(lam[2], cc);
+        if (fabs(w) > 1e-12) rb_add(&b, row, col, w);
+      }
+    }
+  rb_finish(&b, P);
+}
+
+/* eq. mp3: rows/columns [v1 | v2 | p | lambda1 | lambda2 | mu] */
+static void build_kkt_stokes(mgo_level *L, double alpha) {
+  int nv = L->nv, np = L->np;
+  int ov[2] = {0, nv}, op = 2 * nv, ol[2] = {2 * nv + np, 3 * nv + np}, om = 4 * nv + np;
+  rowbuild b;
+  rb_init(&b, L->ndof, L->ndof, 64);
+  const mgo_csr *D[2] = {&L->D1, &L->D2};
+  for (int c = 0; c < 2; c++) {
+    for (int r = 0; r < nv; r++) {
+      for (int k = L->M.rowptr[r]; k < L->M.rowptr[r + 1]; k++) {
+        int cc = L->M.col[k];
+        double m = L->M.val[k];
+        rb_add(&b, ov[c] + r, ov[c] + cc, m);          /* M v            */
+        rb_add(&b, ol[c] + r, ol[c] + cc, -m / alpha); /* -alpha^-1 M lambda */
+      }
+      for (int k = L->Klap.rowptr[r]; k < L->Klap.rowptr[r + 1]; k++) {
+        int cc = L->Klap.col[k];
+        rb_add(&b, ov[c] + r, ol[c] + cc, L->Klap.val[k]); /* K lambda */
+        rb_add(&b, ol[c] + r, ov[c] + cc, L->Klap.val[k]); /* K v      */
+      }
+    }
+    for (int q = 0; q < np; q++)
+      for (int k = D[c]->rowptr[q]; k < D[c]->rowptr[q + 1]; k++) {
+        int a = D[c]->col[k];
+        double d = D[c]->val[k];
+        rb_add(&b, op + q, ol[c] + a, d); /* D lambda   */
+        rb_add(&b, om + q, ov[c] + a, d); /* D v        */
+        rb_add(&b, ov[c] + a, om + q, d); /* D^T mu     */
+        rb_add(&b, ol[c] + a, op + q, d); /* D^T p      */
+      }
+  }
+  rb_finish(&b, &L->A);
+  mgo_transpose(&L->A, &L->At);
+}
+
+/* L_k = blockdiag(W^, W^, P^, W^/alpha, W^/alpha, P^/alpha) with
+ * W^ = diag(M + alpha^{1/2} K) and P^ = alpha diag(D W^-1 D^T) (section 2) */
+static void build_L_stokes(mgo_level *L, double alpha) {
+  int nv = L->nv, np = L->np;
+  double *W = (double *)xmalloc((size_t)nv * sizeof(double));
+  for (int a = 0; a < nv; a++) W[a] = csr_entry(&L->M, a, a) + sqrt(alpha) * csr_entry(&L->Klap, a, a);
+  for (int a = 0; a < nv; a++) {
+    L->L[a] = L->L[nv + a] = W[a];
+    L->L[2 * nv + np + a] = L->L[3 * nv + np + a] = W[a] / alpha;
+  }
+  for (int q = 0; q < np; q++) {
+    double s = 0.0;
+    for (int k = L->D1.rowptr[q]; k < L->D1.rowptr[q + 1]; k++) s += L->D1.val[k] * L->D1.val[k] / W[L->D1.col[k]];
+    for (int k = L->D2.rowptr[q]; k < L->D2.rowptr[q + 1]; k++) s += L->D2.val[k] * L->D2.val[k] / W[L->D2.col[k]];
+    L->L[2 * nv + q] = alpha * s;
+    L->L[4 * nv + np + q] = s;
+  }
+  free(W);
+}
+
+/* Orderings of Alg. 2 for Stokes.  LEX: every unknown in index order.
+ * COL7 (the GPU order): for velocity component c = 1, 2 and the 25 colours
+ * (a mod 5) + 5 (b mod 5) of the interior P2 nodes, groups {v_c, lambda_c} of
+ * one node; then for the 9 colours (i mod 3) + 3 (j mod 3) of the vertices,
+ * groups {p, mu} of one vertex.  COL7SEQ: the same with one unknown per group. */
+static void build_orders_stokes(mgo_level *L) {
+  int n = L->n, nv = L->nv, np = L->np, N = L->ndof, m = 2 * n - 1;
+  for (int o = 0; o < 4; o++) {
+    L->ord[o] = (int *)xmalloc((size_t)N * sizeof(int));
+    L->gptr[o] = (int *)xmalloc(((size_t)N + 1) * sizeof(int));
+  }
+  for (int o = 0; o < 4; o += 3) { /* LEX and VLEX */
+    for (int i = 0; i < N; i++) L->ord[o][i] = L->gptr[o][i] = i;
+    L->gptr[o][N] = N;
+    L->ngroup[o] = N;
+  }
+  for (int o = 1; o <= 2; o++) {
+    int at = 0, g = 0;
+    for (int c = 0; c < 2; c++)
+      for (int col = 0; col < 25; col++)
+        for (int b = 1; b <= m; b++)
+          for (int a = 1; a <= m; a++) {
+            if ((a % 5) + 5 * (b % 5) != col) continue;
+            int node = (b - 1) * m + (a - 1);
+            int iv = c * nv + node, il = 2 * nv + np + c * nv + node;
+            L->gptr[o][g++] = at;
+            L->ord[o][at++] = iv;
+            if (o == 2) L->gptr[o][g++] = at;
+            L->ord[o][at++] = il;
+          }
+    for (int col = 0; col < 9; col++)
+      for (int j = 0; j <= n; j++)
+        for (int i = 0; i <= n; i++) {
+          if ((i % 3) + 3 * (j % 3) != col) continue;
+          int q = j * (n + 1) + i;
+          L->gptr[o][g++] = at;
+          L->ord[o][at++] = 2 * nv + q;
+          if (o == 2) L->gptr[o][g++] = at;
+          L->ord[o][at++] = 4 * nv + np + q;
+        }
+    L->gptr[o][g] = at;
+    L->ngroup[o] = g;
+  }
+}
+
+/* Vanka patches (section 2, Stokes): for vertex (i, j) its p and mu, and
+ * v1, v2, lambda1, lambda2 at the P2 node of the vertex and at the midpoints
+ * of the (up to 6) mesh edges ending at it, where those nodes are interior.
+ * Patch orders: lexicographic vertices, or 9 colours (i mod 3) + 3 (j mod 3). */
+static void build_patches_stokes(mgo_level *L) {
+  int n = L->n, nv = L->nv, np = L->np, m = 2 * n - 1;
+  static const int di[7] = {0, 1, -1, 0, 0, 1, -1}, dj[7] = {0, 0, 0, 1, -1, 1, -1};
+  L->patch_ptr = (int *)xmalloc(((size_t)np + 1) * sizeof(int));
+  L->patch_dof = (int *)xmalloc((size_t)np * 30 * sizeof(int));
+  int at = 0;
+  for (int j = 0; j <= n; j++)
+    for (int i = 0; i <= n; i++) {
+      int q = j * (n + 1) + i;
+      L->patch_ptr[q] = at;
+      L->patch_dof[at++] = 2 * nv + q;
+      L->patch_dof[at++] = 4 * nv + np + q;
+      for (int d = 0; d < 7; d++) {
+        int ii = i + di[d], jj = j + dj[d];
+        if (ii < 0 || jj < 0 || ii > n || jj > n) continue;
+        int a = i + ii, b = j + jj; /* vertex node (d = 0) or edge midpoint, half-lattice */
+        if (a < 1 || b < 1 || a > m || b > m) continue;
+        int node = (b - 1) * m + (a - 1);
+        L->patch_dof[at++] = node;
+        L->patch_dof[at++] = nv + node;
+        L->patch_dof[at++] = 2 * nv + np + node;
+        L->patch_dof[at++] = 3 * nv + np + node;
+      }
+    }
+  L->patch_ptr[np] = at;
+  L->vanka_ord[0] = (int *)xmalloc((size_t)np * sizeof(int));
+  L->vanka_ord[1] = (int *)xmalloc((size_t)np * sizeof(int));
+  for (int q = 0; q < np; q++) L->vanka_ord[0][q] = q;
+  int k = 0;
+  for (int col = 0; col < 9; col++)
+    for (int j = 0; j <= n; j++)
+      for (int i = 0; i <= n; i++)
+        if ((i % 3) + 3 * (j % 3) == col) L->vanka_ord[1][k++] = j * (n + 1) + i;
+}
+
+static int build_level_stokes(mgo_level *L, int n, double alpha) {
+  L->n = n;
+  L->nv = (2 * n - 1) * (2 * n - 1);
+  L->np = (n + 1) * (n + 1);
+  int nv = L->nv, np = L->np;
+  L->ndof = 4 * nv + 2 * np;
+  L->nfield = 6;
+  int off[6] = {0, nv, 2 * nv, 2 * nv + np, 3 * nv + np, 4 * nv + np};
+  int kind[6] = {0, 0, 1, 0, 0, 1};
+  for (int fl = 0; fl < 6; fl++) {
+    L->foff[fl] = off[fl];
+    L->fkind[fl] = kind[fl];
+    L->fdim[fl] = kind[fl] ? np : nv;
+  }
+  /* scalar P2 mass (M) and Laplacian stiffness (Klap), divergence blocks,
+   * and the P1 pressure mass (Mp) for the mean-value constraint */
+  mgo_assemble_p2(n, 0, &L->M, &L->Klap, &L->D1, &L->D2);
+  mgo_csr Kp1;
+  mgo_assemble_p1(n, &L->Mp, &Kp1);
+  mgo_csr_free(&Kp1);
+  {
+    /* B = [D1 D2] (np x 2 nv), for inspection */
+    rowbuild b;
+    rb_init(&b, np, 2 * nv, 48);
+    for (int q = 0; q < np; q++) {
+      for (int k = L->D1.rowptr[q]; k < L->D1.rowptr[q + 1]; k++) rb_add(&b, q, L->D1.col[k], L->D1.val[k]);
+      for (int k = L->D2.rowptr[q]; k < L->D2.rowptr[q + 1]; k++) rb_add(&b, q, nv + L->D2.col[k], L->D2.val[k]);
+    }
+    rb_finish(&b, &L->B);
+  }
+  build_kkt_stokes(L, alpha);
+  level_alloc_work(L);
+  build_L_stokes(L, alpha);
+  build_Ndiag(L);
+  build_orders_stokes(L);
+  build_patches_stokes(L);
+  return 0;
+}
+
+/* weights of the pressure mean: w = Mp 1 (int of each P1 basis function) */
+static void pressure_weights(const mgo_level *L, double *w) {
+  for (int q = 0; q < L->np; q++) {
+    double s = 0.0;
+    for (int k = L->Mp.rowptr[q]; k < L->Mp.rowptr[q + 1]; k++) s += L->Mp.val[k];
+    w[q] = s;
+  }
+}
+
+/* p and mu with zero mean: v -= (w^T v / w^T 1) 1 */
+static void project_means(const mgo_level *L, double *x) {
+  double *w = (double *)xmalloc((size_t)L->np * sizeof(double));
+  pressure_weights(L, w);
+  double ww = 0.0;
+  for (int q = 0; q < L->np; q++) ww += w[q];
+  int offs[2] = {2 * L->nv, 4 * L->nv + L->np};
+  for (int t = 0; t < 2; t++) {
+    double s = 0.0;
+    for (int q = 0; q < L->np; q++) s += w[q] * x[offs[t] + q];
+    double c = s / ww;
+    for (int q = 0; q < L->np; q++) x[offs[t] + q] -= c;
+  }
+  free(w);
+}
+
 /* ------------------------------------------------------ create / destroy */
 
 mgo_hier *mgo_create(int problem, int fine, int coarse, double alpha) {
-  if (problem != 0) return NULL;
+  if (problem != 0 && problem != 1) return NULL;
   if (!(alpha > 0.0) || !isfinite(alpha) || coarse < 1 || fine < coarse + 1 || fine > 12) return NULL;
   mgo_hier *h = (mgo_hier *)xcalloc(1, sizeof(mgo_hier));
   h->problem = problem;
@@ -488,20 +935,45 @@ mgo_hier *mgo_create(int problem, int fine, int coarse, double alpha) {
   h->lv = (mgo_level *)xcalloc((size_t)fine + 1, sizeof(mgo_level));
   for (int l = coarse; l <= fine; l++) {
     mgo_level *L = &h->lv[l];
-    build_level_poisson(L, 1 << l, alpha);
+    if (problem == 0) {
+      build_level_poisson(L, 1 << l, alpha);
+    } else {
+      build_level_stokes(L, 1 << l, alpha);
+    }
     if (l > coarse) {
-      mgo_prolongation_p1(1 << (l - 1), &L->Pk[0]);
-      mgo_transpose(&L->Pk[0], &L->Rk[0]); /* restriction = transpose, scale 1 */
+      if (problem == 0) {
+        mgo_prolongation_p1(1 << (l - 1), &L->Pk[0]);
+        mgo_transpose(&L->Pk[0], &L->Rk[0]); /* restriction = transpose, scale 1 */
+      } else {
+        mgo_prolongation_p2(1 << (l - 1), 0, &L->Pk[0]);
+        mgo_transpose(&L->Pk[0], &L->Rk[0]);
+        mgo_prolongation_p1(1 << (l - 1), &L->Pk[1]);
+        mgo_transpose(&L->Pk[1], &L->Rk[1]);
+      }
     }
   }
-  /* coarsest level: dense LU with partial pivoting of A_{k0} */
+  /* coarsest level: dense LU with partial pivoting of A_{k0}; for Stokes of
+   * [[A, C], [C^T, 0]] with C = the pressure-mean weights in the p and mu rows,
+   * which removes the constant pressures from the kernel of A */
   mgo_level *C = &h->lv[coarse];
-  int N = C->ndof;
-  C->lu = (double *)xcalloc((size_t)N * N, sizeof(double));
-  C->piv = (int *)xcalloc(N, sizeof(int));
+  int N = C->ndof, NB = problem == 0 ? N : N + 2;
+  C->nlu = NB;
+  C->lu = (double *)xcalloc((size_t)NB * NB, sizeof(double));
+  C->piv = (int *)xcalloc(NB, sizeof(int));
   for (int r = 0; r < N; r++)
-    for (int k = C->A.rowptr[r]; k < C->A.rowptr[r + 1]; k++) C->lu[(size_t)r * N + C->A.col[k]] = C->A.val[k];
-  lu_factor(N, C->lu, C->piv);
+    for (int k = C->A.rowptr[r]; k < C->A.rowptr[r + 1]; k++) C->lu[(size_t)r * NB + C->A.col[k]] = C->A.val[k];
+  if (problem == 1) {
+    double *w = (double *)xmalloc((size_t)C->np * sizeof(double));
+    pressure_weights(C, w);
+    int offs[2] = {2 * C->nv, 4 * C->nv + C->np};
+    for (int t = 0; t < 2; t++)
+      for (int q = 0; q < C->np; q++) {
+        C->lu[(size_t)(offs[t] + q) * NB + N + t] = w[q];
+        C->lu[(size_t)(N + t) * NB + offs[t] + q] = w[q];
+      }
+    free(w);
+  }
+  lu_factor(NB, C->lu, C->piv);
   return h;
 }
 
@@ -530,6 +1002,12 @@ static void level_free(mgo_level *L) {
   for (int o = 0; o < 3; o++) free(L->cgs_ord[o]);
   free(L->lu);
   free(L->piv);
+  mgo_csr_free(&L->D1);
+  mgo_csr_free(&L->D2);
+  free(L->patch_ptr);
+  free(L->patch_dof);
+  free(L->vanka_ord[0]);
+  free(L->vanka_ord[1]);
 }
 
 void mgo_destroy(mgo_hier *h) {
@@ -649,6 +1127,31 @@ static void cgs_step(const mgo_level *L, const int *vord, int nvert, double *x, 
   }
 }
 
+/* Patch (Vanka-type) smoother for Stokes (section 2): for each patch P_i in
+ * turn, x += tau P_i (P_i^T A P_i)^{-1} P_i^T r, r -= tau A P_i (...)
+ * (multiplicative, damped). */
+static void vanka_step(const mgo_level *L, const int *vord, double tau, double *x, double *r) {
+  const mgo_csr *A = &L->A, *At = &L->At;
+  double a[30 * 30], rl[30], d[30];
+  int piv[30];
+  for (int t = 0; t < L->np; t++) {
+    int q = vord[t];
+    int b = L->patch_ptr[q], e = L->patch_ptr[q + 1], m = e - b;
+    const int *dof = L->patch_dof + b;
+    for (int u = 0; u < m; u++) {
+      rl[u] = r[dof[u]];
+      for (int w = 0; w < m; w++) a[u * m + w] = csr_entry(A, dof[u], dof[w]);
+    }
+    lu_factor(m, a, piv);
+    lu_solve(m, a, piv, rl, d);
+    for (int u = 0; u < m; u++) {
+      double du = tau * d[u];
+      x[dof[u]] += du;
+      for (int k = At->rowptr[dof[u]]; k < At->rowptr[dof[u] + 1]; k++) r[At->col[k]] -= At->val[k] * du;
+    }
+  }
+}
+
 void mgo_smooth(const mgo_hier *h, int level, int kind, int order, double tau, double *x, double *r) {
   const mgo_level *L = &h->lv[level];
   if (order < 0 || order > 4) order = 0;
@@ -663,7 +1166,11 @@ void mgo_smooth(const mgo_hier *h, int level, int kind, int order, double tau, d
       lsgs_groups(L, L->ord[order], L->gptr[order], L->ngroup[order], 0, x, r);
       lsgs_groups(L, L->ord[order], L->gptr[order], L->ngroup[order], 1, x, r);
       break;
+    case MGO_VANKA:
+      if (L->patch_ptr) vanka_step(L, L->vanka_ord[order == MGO_ORDER_LEX ? 0 : 1], tau, x, r);
+      break;
     case MGO_CGS: {
+      if (!L->cgs_ord[0]) break; /* Poisson only */
       int which = 0; /* lexicographic for MGO_ORDER_LEX and MGO_ORDER_VLEX */
       if (order == MGO_ORDER_COL7 || order == MGO_ORDER_COL7SEQ) which = 1;
       if (order == MGO_ORDER_COL3) which = 2;
@@ -681,7 +1188,17 @@ void mgo_smooth_groups(const mgo_hier *h, int level, const int *ord, const int *
 
 void mgo_coarse_solve(const mgo_hier *h, const double *f, double *x) {
   const mgo_level *C = &h->lv[h->coarse];
-  lu_solve(C->ndof, C->lu, C->piv, f, x);
+  if (C->nlu == C->ndof) {
+    lu_solve(C->ndof, C->lu, C->piv, f, x);
+    return;
+  }
+  /* bordered system: right-hand side (f; 0, 0), solution (x; multipliers) */
+  double *fb = (double *)xcalloc(C->nlu, sizeof(double)), *xb = (double *)xcalloc(C->nlu, sizeof(double));
+  memcpy(fb, f, (size_t)C->ndof * sizeof(double));
+  lu_solve(C->nlu, C->lu, C->piv, fb, xb);
+  memcpy(x, xb, (size_t)C->ndof * sizeof(double));
+  free(fb);
+  free(xb);
 }
 
 /* fine-level field-wise transfers: restriction with P^T, prolongation with P */
@@ -727,9 +1244,22 @@ static void cycle_rec(const mgo_hier *h, int l, int kind, int order, double tau,
   for (int s = 0; s < nu2; s++) mgo_smooth(h, l, kind, order, tau, x, r);
 }
 
+/* a cycle on the finest level of the call; for Stokes the pressure p and
+ * the multiplier mu are then shifted to zero mean (the constants span the
+ * kernel of A_k and leave every residual unchanged) */
+static void top_cycle(const mgo_hier *h, int level, int kind, int order, double tau, int nu1, int nu2, int gamma,
+                      const double *f, double *x) {
+  cycle_rec(h, level, kind, order, tau, nu1, nu2, gamma, f, x);
+  if (h->problem == 1) project_means(&h->lv[level], x);
+}
+
 void mgo_cycle(const mgo_hier *h, int level, int kind, int order, double tau, int nu1, int nu2, int gamma,
                const double *f, double *x) {
-  cycle_rec(h, level, kind, order, tau, nu1, nu2, gamma, f, x);
+  top_cycle(h, level, kind, order, tau, nu1, nu2, gamma, f, x);
+}
+
+void mgo_project(const mgo_hier *h, int level, double *x) {
+  if (h->problem == 1) project_means(&h->lv[level], x);
 }
 
 static double norm2(const double *v, int n) {
@@ -762,7 +1292,7 @@ int mgo_solve(const mgo_hier *h, int kind, int order, double tau, int nu1, int n
       it = -1;
       break;
     }
-    cycle_rec(h, h->fine, kind, order, tau, nu1, nu2, gamma, f, x);
+    top_cycle(h, h->fine, kind, order, tau, nu1, nu2, gamma, f, x);
   }
   free(r);
   return it;

@@ -48,10 +48,21 @@ void mgo_prolongation_p1(int nc, mgo_csr *P);
 /* transpose */
 void mgo_transpose(const mgo_csr *A, mgo_csr *At);
 
+/* Taylor-Hood pieces (Stokes control, eq. mp3), n cells per side: scalar P2
+ * mass M and Laplacian stiffness K, and the divergence blocks
+ * D1 = -int q d_x phi, D2 = -int q d_y phi (rows: P1 vertices), over the
+ * interior P2 nodes (full = 0; velocity vanishes on the boundary) or over
+ * all (2n+1)^2 nodes (full = 1).  P2 node (a, b) of the half-step lattice,
+ * at (a/(2n), b/(2n)), has index (b-1)(2n-1)+(a-1) (interior) or
+ * b(2n+1)+a (full). */
+void mgo_assemble_p2(int n, int full, mgo_csr *M, mgo_csr *K, mgo_csr *D1, mgo_csr *D2);
+/* P2 interpolation from nc to 2 nc cells per side (interior or all nodes) */
+void mgo_prolongation_p2(int nc, int full, mgo_csr *P);
+
 /* opaque multigrid hierarchy */
 typedef struct mgo_hier mgo_hier;
 
-enum { MGO_NE = 0, MGO_LSGS = 1, MGO_SLSGS = 2, MGO_CGS = 3 };
+enum { MGO_NE = 0, MGO_LSGS = 1, MGO_SLSGS = 2, MGO_CGS = 3, MGO_VANKA = 4 };
 enum { MGO_ORDER_LEX = 0, MGO_ORDER_COL7 = 1, MGO_ORDER_COL7SEQ = 2, MGO_ORDER_VLEX = 3, MGO_ORDER_COL3 = 4 };
 
 /* Build levels coarse..fine (fine >= coarse+1 >= 2) of the Poisson control
@@ -75,9 +86,15 @@ void mgo_residual(const mgo_hier *h, int level, const double *f, const double *x
 
 /* One smoothing step on level l keeping r = f - A x current (x, r in/out).
  * kind: MGO_NE (Alg. 1, damping tau), MGO_LSGS (Alg. 2 in ordering 'order'),
- * MGO_SLSGS (forward then reversed ordering), MGO_CGS (collective point GS
- * over vertices: lexicographic, 7 colours for MGO_ORDER_COL7, 3 colours for
- * MGO_ORDER_COL3). */
+ * MGO_SLSGS (forward then reversed ordering), MGO_CGS (Poisson: collective
+ * point GS over vertices: lexicographic, 7 colours for MGO_ORDER_COL7, 3
+ * colours for MGO_ORDER_COL3), MGO_VANKA (Stokes: damped patch smoother over
+ * the vertex patches, lexicographic for MGO_ORDER_LEX, else 9 colours).
+ * Stokes orderings of Alg. 2: MGO_ORDER_LEX every unknown in index order;
+ * MGO_ORDER_COL7 the colour order (25 P2-node colours (a mod 5)+5(b mod 5)
+ * per velocity component with {v_c, lambda_c} grouped, then 9 vertex colours
+ * (i mod 3)+3(j mod 3) with {p, mu} grouped); MGO_ORDER_COL7SEQ the same with
+ * one unknown per group. */
 void mgo_smooth(const mgo_hier *h, int level, int kind, int order, double tau, double *x, double *r);
 
 /* Alg. 2 over a caller-given ordering: unknowns ord[gptr[g]..gptr[g+1]) form
@@ -88,6 +105,10 @@ void mgo_smooth_groups(const mgo_hier *h, int level, const int *ord, const int *
 
 /* exact coarsest-level solve x = A^{-1} f by dense LU with partial pivoting */
 void mgo_coarse_solve(const mgo_hier *h, const double *f, double *x);
+
+/* Stokes: shift p and mu of a level-l vector to zero mean (weights Mp 1);
+ * no-op for Poisson.  mgo_cycle and mgo_solve do this after every cycle. */
+void mgo_project(const mgo_hier *h, int level, double *x);
 
 /* one multigrid cycle (gamma = 1 V, 2 W) on level l, in place on x */
 void mgo_cycle(const mgo_hier *h, int level, int kind, int order, double tau, int nu1, int nu2,
