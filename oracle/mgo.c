@@ -821,7 +821,9 @@ static void build_orders_stokes(mgo_level *L) {
 
 /* Vanka patches (section 2, Stokes): for vertex (i, j) its p and mu, and
  * v1, v2, lambda1, lambda2 at the P2 node of the vertex and at the midpoints
- * of the (up to 6) mesh edges ending at it, where those nodes are interior.
+ * of the (up to 6) mesh edges ending at it, where those nodes are interior
+ * (two corners, whose edges all lie on the boundary, take the interior nodes
+ * of their triangles instead).
  * Patch orders: lexicographic vertices, or 9 colours (i mod 3) + 3 (j mod 3). */
 static void build_patches_stokes(mgo_level *L) {
   int n = L->n, nv = L->nv, np = L->np, m = 2 * n - 1;
@@ -845,6 +847,32 @@ static void build_patches_stokes(mgo_level *L) {
         L->patch_dof[at++] = nv + node;
         L->patch_dof[at++] = 2 * nv + np + node;
         L->patch_dof[at++] = 3 * nv + np + node;
+      }
+      if (at - L->patch_ptr[q] == 2) {
+        /* every edge at this vertex lies on the boundary (the corners (n, 0)
+         * and (0, n)): the patch takes the interior P2 nodes of the triangles
+         * that contain the vertex instead, so that its matrix is regular */
+        for (int sj = j - 1; sj <= j; sj++)
+          for (int si = i - 1; si <= i; si++) {
+            if (si < 0 || sj < 0 || si >= n || sj >= n) continue;
+            for (int t = 0; t < 2; t++) {
+              int na[6], nb[6], vi[3], vj[3];
+              p2_tri_nodes(si, sj, t, na, nb, vi, vj);
+              int has = 0;
+              for (int k = 0; k < 3; k++) has |= (vi[k] == i && vj[k] == j);
+              if (!has) continue;
+              for (int k = 0; k < 6; k++) {
+                if (na[k] < 1 || nb[k] < 1 || na[k] > m || nb[k] > m) continue;
+                int node = (nb[k] - 1) * m + (na[k] - 1), dup = 0;
+                for (int u = L->patch_ptr[q]; u < at; u++) dup |= L->patch_dof[u] == node;
+                if (dup) continue;
+                L->patch_dof[at++] = node;
+                L->patch_dof[at++] = nv + node;
+                L->patch_dof[at++] = 2 * nv + np + node;
+                L->patch_dof[at++] = 3 * nv + np + node;
+              }
+            }
+          }
       }
     }
   L->patch_ptr[np] = at;

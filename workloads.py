@@ -68,3 +68,19 @@ def stream_function_velocity(X: np.ndarray, Y: np.ndarray, seed: int):
         v1 += a * l * np.pi * np.sin(k * np.pi * X) * np.cos(l * np.pi * Y)
         v2 -= a * k * np.pi * np.cos(k * np.pi * X) * np.sin(l * np.pi * Y)
     return v1, v2
+
+
+def p2_interior_coords(level: int):
+    """Points of the interior nodes of the half-step lattice of a level with
+    n = 2^level cells per side: (a/(2n), b/(2n)) for 1 <= a, b <= 2n-1, in the
+    order (b-1)(2n-1) + (a-1) (the velocity unknowns of the Stokes problem)."""
+    n = 1 << level
+    t = np.arange(1, 2 * n, dtype=np.float64) / (2 * n)
+    X, Y = np.meshgrid(t, t, indexing="xy")
+    return X.ravel(), Y.ravel()
+
+
+def desired_velocity(level: int, seed: int) -> np.ndarray:
+    """[v1 | v2] of the divergence-free desired velocity at the interior P2 nodes."""
+    v1, v2 = stream_function_velocity(*p2_interior_coords(level), seed)
+    return np.concatenate([v1, v2])
