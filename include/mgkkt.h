@@ -42,12 +42,19 @@ enum mg_problem { MG_POISSON = 0, MG_STOKES = 1 };
 /* smoothers of section 2:
  *  MG_NE    normal-equation smoother x += tau L^-1 A^T L^-1 (f - A x) (Alg. 1)
  *  MG_LSGS  least-squares Gauss-Seidel x += trig(N)^-1 A^T L^-1 (f - A x),
- *           N = A^T L^-1 A (Alg. 2), unknowns visited in 7 colours
+ *           N = A^T L^-1 A (Alg. 2).  Poisson: unknowns visited in 7 colours
  *           c(i,j) = (i + 2 j) mod 7; a vertex's y and lambda are updated
- *           together from one residual snapshot (their N entry is zero)
+ *           together from one residual snapshot (their N entry is zero).
+ *           Stokes: per velocity component 25 colours (a mod 5) + 5 (b mod 5)
+ *           of the interior P2 nodes (v_c and lambda_c of a node together),
+ *           then 9 colours (i mod 3) + 3 (j mod 3) of the vertices (p and mu
+ *           of a vertex together)
  *  MG_SLSGS symmetric LSGS: one LSGS sweep, then one in reversed order (eq. mcNhat)
- *  MG_CGS   collective point Gauss-Seidel: 2x2 solve per vertex, 7 colours */
-enum mg_smoother { MG_NE = 0, MG_LSGS = 1, MG_SLSGS = 2, MG_CGS = 3 };
+ *  MG_CGS   Poisson only: collective point Gauss-Seidel, 2x2 solve per vertex, 7 colours
+ *  MG_VANKA Stokes only: patch (Vanka-type) smoother, one patch per vertex (its
+ *           p and mu, and v, lambda at the vertex and at the midpoints of its
+ *           edges), damped with tau (default 0.4), 9 colours (i mod 3) + 3 (j mod 3) */
+enum mg_smoother { MG_NE = 0, MG_LSGS = 1, MG_SLSGS = 2, MG_CGS = 3, MG_VANKA = 4 };
 
 /* arithmetic of the cycles: FP64 throughout, or FP32 cycles used as the
  * preconditioner of FP64 iterative refinement (outer residual, update and the

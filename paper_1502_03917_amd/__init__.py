@@ -15,14 +15,14 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libmgkkt.so")
 
 MG_POISSON, MG_STOKES = 0, 1
-MG_NE, MG_LSGS, MG_SLSGS, MG_CGS = 0, 1, 2, 3
+MG_NE, MG_LSGS, MG_SLSGS, MG_CGS, MG_VANKA = 0, 1, 2, 3, 4
 MG_FP64, MG_FP32_IR = 0, 1
 MG_OK, MG_EINVAL, MG_EHIP, MG_ENOMEM, MG_ENOTCONV, MG_ENAN, MG_EDIVERGE, MG_EUNSUPPORTED, MG_ESTALL = (
     0, -1, -2, -3, -4, -5, -6, -7, -8)
 MG_NORM_L2, MG_NORM_LINV = 0, 1
 NORMS = {"l2": MG_NORM_L2, "linv": MG_NORM_LINV}
 
-SMOOTHERS = {"ne": MG_NE, "lsgs": MG_LSGS, "slsgs": MG_SLSGS, "cgs": MG_CGS}
+SMOOTHERS = {"ne": MG_NE, "lsgs": MG_LSGS, "slsgs": MG_SLSGS, "cgs": MG_CGS, "vanka": MG_VANKA}
 PRECISIONS = {"fp64": MG_FP64, "fp32_ir": MG_FP32_IR}
 PROBLEMS = {"poisson": MG_POISSON, "stokes": MG_STOKES}
 
@@ -151,6 +151,7 @@ class Solver:
             raise MGError(st, "mg_setup")
         self._h = h
         self.level, self.alpha, self.coarse_level = level, float(alpha), coarse_level
+        self.problem = problem
 
     # -- lifetime ---------------------------------------------------------------
     def close(self):
@@ -212,9 +213,17 @@ class Solver:
         return torch.empty(n, dtype=torch.float64, device="cuda")
 
     # -- entry points -------------------------------------------------------------
+    def data_len(self) -> int:
+        """Length of the data of mg_rhs: y_D at the (2^l+1)^2 vertices (Poisson)
+        or [v1 | v2] at the (2^(l+1)-1)^2 interior P2 nodes (Stokes)."""
+        if self.problem == "stokes":
+            return 2 * ((1 << (self.level + 1)) - 1) ** 2
+        return self.nvert()
+
     def rhs(self, yd, f=None):
         f = self._empty(self.vec_len()) if f is None else f
-        self._check(lib().mg_rhs(self._h, self._t(yd, self.nvert(), "yd"), self._t(f, self.vec_len(), "f"), _stream()), "mg_rhs")
+        self._check(lib().mg_rhs(self._h, self._t(yd, self.data_len(), "yd"), self._t(f, self.vec_len(), "f"), _stream()),
+                    "mg_rhs")
         return f
 
     def control(self, x, u=None):

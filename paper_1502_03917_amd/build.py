@@ -8,7 +8,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libmgkkt.so")
-SOURCES = ["csrc/kernels.hip", "csrc/sweep.hip", "csrc/tail.hip", "csrc/host.hip"]
+SOURCES = ["csrc/kernels.hip", "csrc/sweep.hip", "csrc/tail.hip", "csrc/stokes.hip", "csrc/host.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 FLAGS = [

@@ -243,6 +243,8 @@ struct mg_ctx {
   double t_ms = 0.0;
   long t_n = 0;
   std::string err;
+  // Stokes control: the CSR-based solver of stokes.hip (nullptr for Poisson)
+  mgk::Stokes* st = nullptr;
 };
 
 namespace {
@@ -272,9 +274,14 @@ int fail(mg_ctx* c, int status, const std::string& msg) {
 
 LevelBuf& L_(mg_ctx* c, int l) { return c->lv[l - c->k0]; }
 
+// paper defaults (section 3): NE 0.4 (Poisson) / 0.35 (Stokes), patch smoother 0.4
+double default_tau(int problem, int smoother) {
+  return (problem == MG_STOKES && smoother != MG_VANKA) ? 0.35 : 0.4;
+}
+
 bool valid_opts(const mg_opts* o, int level) {
   if (!o) return true;
-  if (o->smoother < MG_NE || o->smoother > MG_CGS) return false;
+  if (o->smoother < MG_NE || o->smoother > MG_VANKA) return false;
   if (o->nu1 < 0 || o->nu2 < 0 || o->nu1 > 64 || o->nu2 > 64) return false;
   if (o->gamma < 1 || o->gamma > 2) return false;
   if (!std::isfinite(o->tau) || o->tau >= 2.0) return false;
@@ -312,6 +319,7 @@ void destroy_impl(mg_ctx* c) {
   for (auto e : c->ev) (void)hipEventDestroy(e);
   if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
   if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
+  mgk::stokes_destroy(c->st);
   delete c;
 }
 
@@ -535,9 +543,11 @@ struct Monitor {
 
 // ||r||^2 of the fine residual into d_norm[slot] (stream-ordered)
 int residual_norm(mg_ctx* c, const double* f, const double* x, double* r, int slot, hipStream_t s) {
-  LevelBuf& b = L_(c, c->level);
   int nb = 0;
-  HIPCHK(c, mgk::launch_residual<double>(b.lev, f, x, r, c->d_part, norm_mode(c), &nb, s));
+  if (c->st)
+    HIPCHK(c, mgk::stokes_residual(c->st, c->level, f, x, r, c->d_part, norm_mode(c), &nb, s));
+  else
+    HIPCHK(c, mgk::launch_residual<double>(L_(c, c->level).lev, f, x, r, c->d_part, norm_mode(c), &nb, s));
   HIPCHK(c, mgk::launch_sum(c->d_part, nb, c->d_norm + slot, s));
   return MG_OK;
 }
@@ -557,7 +567,17 @@ int ir_step(mg_ctx* c, double* x, hipStream_t s) {
 
 // one solver iterate for fixed (f, x): cycle (FP64) or refinement step
 // (FP32 cycles), then the fine residual and its squared norm in d_norm[0]
+// the residual buffer of the finest level
+double* fine_r(mg_ctx* c) { return c->st ? mgk::stokes_fine_r(c->st) : L_(c, c->level).r; }
+
 int iterate(mg_ctx* c, const double* f, double* x, hipStream_t s) {
+  if (c->st) {
+    if (c->o.precision == MG_FP32_IR)
+      HIPCHK(c, mgk::stokes_ir_step(c->st, x, s, c->d_norm));
+    else
+      HIPCHK(c, mgk::stokes_cycle(c->st, f, x, fine_r(c), true, s));
+    return residual_norm(c, f, x, fine_r(c), 0, s);
+  }
   LevelBuf& b = L_(c, c->level);
   int st = c->o.precision == MG_FP32_IR ? ir_step(c, x, s) : cycle_body<double>(c, c->level, f, x, b.r, true, s);
   if (st != MG_OK) return st;
@@ -606,6 +626,33 @@ int check_level(const mg_ctx* c, int l, bool allow_coarsest) {
 
 }  // namespace
 
+namespace {
+// Stokes contexts: the CSR solver object plus the norm workspace of the context
+int setup_stokes(mg_ctx* c, mg_ctx** out) {
+  const char* g = std::getenv("MGKKT_NO_GRAPH");
+  c->graphs = !(g && g[0] == '1');
+  c->tail_allowed = false;
+  if (hipGetDevice(&c->device) != hipSuccess) {
+    delete c;
+    return MG_EHIP;
+  }
+  int st = mgk::stokes_create(c->level, c->k0, c->alpha, c->o, &c->st, &c->err);
+  if (st != MG_OK) {
+    destroy_impl(c);
+    return st;
+  }
+  c->npart = mgk::stokes_partials(c->st);
+  if (hipMalloc(&c->d_part, c->npart * sizeof(double)) != hipSuccess ||
+      hipMalloc(&c->d_norm, 4 * sizeof(double)) != hipSuccess ||
+      hipHostMalloc((void**)&c->h_norm, 4 * sizeof(double), hipHostMallocDefault) != hipSuccess) {
+    destroy_impl(c);
+    return MG_ENOMEM;
+  }
+  *out = c;
+  return MG_OK;
+}
+}  // namespace
+
 // ====================================================================== C ABI
 
 extern "C" {
@@ -635,10 +682,14 @@ const char* mg_last_error(const mg_ctx* ctx) {
   return ctx->err.c_str();
 }
 
-size_t mg_vec_len(const mg_ctx* ctx) { return ctx ? ctx->lv.back().len : 0; }
+size_t mg_vec_len(const mg_ctx* ctx) {
+  if (!ctx) return 0;
+  return ctx->st ? mgk::stokes_len(ctx->st, ctx->level) : ctx->lv.back().len;
+}
 
 size_t mg_level_len(const mg_ctx* ctx, int level) {
   if (!ctx || level < ctx->k0 || level > ctx->level) return 0;
+  if (ctx->st) return mgk::stokes_len(ctx->st, level);
   return ctx->lv[level - ctx->k0].len;
 }
 
@@ -655,15 +706,20 @@ int mg_setup(int level, double alpha, int problem, const mg_opts* opts, mg_ctx**
   if (!(alpha > 0.0) || !std::isfinite(alpha)) return MG_EINVAL;
   if (level < 2 || level > kMaxLevel) return MG_EINVAL;
   if (!valid_opts(opts, level)) return MG_EINVAL;
-  if (problem == MG_STOKES) return MG_EUNSUPPORTED;
+  {
+    const mg_opts& q = opts ? *opts : mg_default_opts(problem);
+    if (problem == MG_POISSON && q.smoother == MG_VANKA) return MG_EUNSUPPORTED;
+    if (problem == MG_STOKES && (q.smoother == MG_CGS || q.coarse_level > 2)) return MG_EUNSUPPORTED;
+  }
   mg_ctx* c = new (std::nothrow) mg_ctx();
   if (!c) return MG_ENOMEM;
   c->problem = problem;
   c->level = level;
   c->alpha = alpha;
   c->o = opts ? *opts : mg_default_opts(problem);
-  if (c->o.tau <= 0.0) c->o.tau = problem == MG_STOKES ? 0.35 : 0.4;
+  if (c->o.tau <= 0.0) c->o.tau = default_tau(problem, c->o.smoother);
   c->k0 = c->o.coarse_level;
+  if (problem == MG_STOKES) return setup_stokes(c, out);
   {
     // MGKKT_PHASE_KERNELS=1 selects one launch per colour phase (comparison and testing)
     const char* e = std::getenv("MGKKT_PHASE_KERNELS");
@@ -745,7 +801,15 @@ int mg_set_opts(mg_ctx* ctx, const mg_opts* opts) {
   if (!valid_opts(opts, ctx->level)) return MG_EINVAL;
   if (opts->coarse_level != ctx->k0) return fail(ctx, MG_EINVAL, "coarse_level is fixed at setup");
   mg_opts o = *opts;
-  if (o.tau <= 0.0) o.tau = ctx->problem == MG_STOKES ? 0.35 : 0.4;
+  if (o.tau <= 0.0) o.tau = default_tau(ctx->problem, o.smoother);
+  if (ctx->st) {
+    if (o.smoother != ctx->o.smoother || o.precision != ctx->o.precision)
+      return fail(ctx, MG_EUNSUPPORTED, "Stokes: smoother and precision are fixed at setup");
+    ctx->o = o;
+    mgk::stokes_set(ctx->st, o);
+    drop_graph(ctx);
+    return MG_OK;
+  }
   if (hipSetDevice(ctx->device) != hipSuccess) return MG_EHIP;
   if (o.precision == MG_FP32_IR) {
     int st = alloc_fp32(ctx);
@@ -759,6 +823,10 @@ int mg_set_opts(mg_ctx* ctx, const mg_opts* opts) {
 
 int mg_rhs(mg_ctx* ctx, const double* yd, double* f, void* stream) {
   if (!ctx || !yd || !f) return MG_EINVAL;
+  if (ctx->st) {
+    HIPCHK(ctx, mgk::stokes_rhs(ctx->st, yd, f, (hipStream_t)stream));
+    return MG_OK;
+  }
   HIPCHK(ctx, mgk::launch_rhs<double>(L_(ctx, ctx->level).lev, yd, f, (hipStream_t)stream));
   return MG_OK;
 }
@@ -784,6 +852,10 @@ int mg_adjoint_grad(mg_ctx* ctx, const double* x, const double* xadj, double* gr
 
 int mg_apply(mg_ctx* ctx, int level, const double* x, double* y, void* stream) {
   if (!ctx || !x || !y || !check_level(ctx, level, false)) return MG_EINVAL;
+  if (ctx->st) {
+    HIPCHK(ctx, mgk::stokes_apply(ctx->st, level, x, y, (hipStream_t)stream));
+    return MG_OK;
+  }
   HIPCHK(ctx, mgk::launch_apply<double>(L_(ctx, level).lev, x, y, (hipStream_t)stream));
   return MG_OK;
 }
@@ -792,13 +864,18 @@ int mg_residual(mg_ctx* ctx, int level, const double* f, const double* x, double
                 void* stream) {
   if (!ctx || !f || !x || !r || !check_level(ctx, level, false)) return MG_EINVAL;
   hipStream_t s = (hipStream_t)stream;
-  LevelBuf& b = L_(ctx, level);
-  if (!norm_out) {
-    HIPCHK(ctx, mgk::launch_residual<double>(b.lev, f, x, r, nullptr, 0, nullptr, s));
-    return MG_OK;
-  }
   int nb = 0;
-  HIPCHK(ctx, mgk::launch_residual<double>(b.lev, f, x, r, ctx->d_part, 1, &nb, s));
+  if (ctx->st) {
+    HIPCHK(ctx, mgk::stokes_residual(ctx->st, level, f, x, r, norm_out ? ctx->d_part : nullptr, 1, &nb, s));
+    if (!norm_out) return MG_OK;
+  } else {
+    LevelBuf& b = L_(ctx, level);
+    if (!norm_out) {
+      HIPCHK(ctx, mgk::launch_residual<double>(b.lev, f, x, r, nullptr, 0, nullptr, s));
+      return MG_OK;
+    }
+    HIPCHK(ctx, mgk::launch_residual<double>(b.lev, f, x, r, ctx->d_part, 1, &nb, s));
+  }
   HIPCHK(ctx, mgk::launch_sum(ctx->d_part, nb, ctx->d_norm + 2, s));
   HIPCHK(ctx, hipMemcpyAsync(ctx->h_norm + 2, ctx->d_norm + 2, sizeof(double), hipMemcpyDeviceToHost, s));
   HIPCHK(ctx, hipStreamSynchronize(s));
@@ -809,6 +886,10 @@ int mg_residual(mg_ctx* ctx, int level, const double* f, const double* x, double
 int mg_smooth(mg_ctx* ctx, int level, double* x, double* r, int steps, void* stream) {
   if (!ctx || !x || !r || steps < 0 || !check_level(ctx, level, false)) return MG_EINVAL;
   hipStream_t s = (hipStream_t)stream;
+  if (ctx->st) {
+    HIPCHK(ctx, mgk::stokes_smooth(ctx->st, level, x, r, steps, s));
+    return MG_OK;
+  }
   LevelBuf& b = L_(ctx, level);
   double* cur = r;
   int st = smooth_steps<double>(ctx, level, x, cur, b.r2, b.p, steps, s);
@@ -819,6 +900,10 @@ int mg_smooth(mg_ctx* ctx, int level, double* x, double* r, int steps, void* str
 
 int mg_restrict(mg_ctx* ctx, int level, const double* r, double* fc, void* stream) {
   if (!ctx || !r || !fc || !check_level(ctx, level, false)) return MG_EINVAL;
+  if (ctx->st) {
+    HIPCHK(ctx, mgk::stokes_restrict(ctx->st, level, r, fc, (hipStream_t)stream));
+    return MG_OK;
+  }
   HIPCHK(ctx, mgk::launch_restrict<double>(L_(ctx, level).lev, L_(ctx, level - 1).lev, r, fc, nullptr, nullptr,
                                            (hipStream_t)stream));
   return MG_OK;
@@ -826,6 +911,10 @@ int mg_restrict(mg_ctx* ctx, int level, const double* r, double* fc, void* strea
 
 int mg_prolong_add(mg_ctx* ctx, int level, const double* xc, double* x, void* stream) {
   if (!ctx || !xc || !x || !check_level(ctx, level, false)) return MG_EINVAL;
+  if (ctx->st) {
+    HIPCHK(ctx, mgk::stokes_prolong_add(ctx->st, level, xc, x, (hipStream_t)stream));
+    return MG_OK;
+  }
   HIPCHK(ctx, mgk::launch_prolong_add<double>(L_(ctx, level).lev, L_(ctx, level - 1).lev, xc, x,
                                               (hipStream_t)stream));
   return MG_OK;
@@ -833,12 +922,26 @@ int mg_prolong_add(mg_ctx* ctx, int level, const double* xc, double* x, void* st
 
 int mg_coarse_solve(mg_ctx* ctx, const double* f, double* x, void* stream) {
   if (!ctx || !f || !x) return MG_EINVAL;
+  if (ctx->st) {
+    HIPCHK(ctx, mgk::stokes_coarse_solve(ctx->st, f, x, (hipStream_t)stream));
+    return MG_OK;
+  }
   return coarse_solve_T<double>(ctx, f, x, (hipStream_t)stream);
 }
 
 int mg_cycle(mg_ctx* ctx, const double* f, double* x, void* stream) {
   if (!ctx || !f || !x) return MG_EINVAL;
   hipStream_t s = (hipStream_t)stream;
+  if (ctx->st) {
+    if (ctx->o.precision == MG_FP32_IR) {
+      int st = residual_norm(ctx, f, x, fine_r(ctx), 0, s);
+      if (st != MG_OK) return st;
+      HIPCHK(ctx, mgk::stokes_ir_step(ctx->st, x, s, ctx->d_norm));
+      return MG_OK;
+    }
+    HIPCHK(ctx, mgk::stokes_cycle(ctx->st, f, x, fine_r(ctx), false, s));
+    return MG_OK;
+  }
   LevelBuf& b = L_(ctx, ctx->level);
   if (ctx->o.precision == MG_FP32_IR) {
     int st = residual_norm(ctx, f, x, b.r, 0, s);
@@ -852,13 +955,15 @@ int mg_solve(mg_ctx* ctx, const double* f, double* x, double tol, int* cycles_ou
              void* stream) {
   if (!ctx || !f || !x || !(tol > 0.0) || !std::isfinite(tol)) return MG_EINVAL;
   hipStream_t s = (hipStream_t)stream;
-  LevelBuf& b = L_(ctx, ctx->level);
   int nb = 0;
-  HIPCHK(ctx, mgk::launch_vnorm(b.lev, f, ctx->d_part, norm_mode(ctx), &nb, s));
+  if (ctx->st)
+    HIPCHK(ctx, mgk::stokes_vnorm(ctx->st, f, ctx->d_part, norm_mode(ctx), &nb, s));
+  else
+    HIPCHK(ctx, mgk::launch_vnorm(L_(ctx, ctx->level).lev, f, ctx->d_part, norm_mode(ctx), &nb, s));
   HIPCHK(ctx, mgk::launch_sum(ctx->d_part, nb, ctx->d_norm + 1, s));
   Monitor mon;
   int st = MG_OK;
-  if ((st = residual_norm(ctx, f, x, b.r, 0, s)) != MG_OK) return st;
+  if ((st = residual_norm(ctx, f, x, fine_r(ctx), 0, s)) != MG_OK) return st;
   for (int it = 0;; it++) {
     HIPCHK(ctx, hipMemcpyAsync(ctx->h_norm, ctx->d_norm, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
     HIPCHK(ctx, hipStreamSynchronize(s));

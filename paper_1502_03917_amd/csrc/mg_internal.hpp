@@ -5,6 +5,9 @@
 #include <hip/hip_runtime.h>
 
 #include <cstddef>
+#include <string>
+
+#include "../../include/mgkkt.h"
 
 namespace mgk {
 
@@ -166,6 +169,27 @@ template <typename T>
 void make_tail_args(const TailLaunch& tl, const T* fT, T* xT, int first, const int* active, void* out);
 template <typename T>
 hipError_t launch_b_tail(const void* args, int count, size_t lds_bytes, hipStream_t s);
+
+// ---- Stokes control (stokes.hip): one CSR-based solver object per context
+struct Stokes;
+int stokes_create(int level, int k0, double alpha, const mg_opts& o, Stokes** out, std::string* err);
+void stokes_destroy(Stokes* S);
+size_t stokes_len(const Stokes* S, int level);
+size_t stokes_partials(const Stokes* S);  // norm partial sums written on the finest level
+void stokes_set(Stokes* S, const mg_opts& o);  // nu1, nu2, gamma, tau
+hipError_t stokes_rhs(Stokes* S, const double* vd, double* f, hipStream_t s);
+hipError_t stokes_apply(Stokes* S, int l, const double* x, double* y, hipStream_t s);
+hipError_t stokes_residual(Stokes* S, int l, const double* f, const double* x, double* r, double* part,
+                           int norm_mode, int* nparts, hipStream_t s);
+hipError_t stokes_vnorm(Stokes* S, const double* v, double* part, int norm_mode, int* nparts, hipStream_t s);
+hipError_t stokes_smooth(Stokes* S, int l, double* x, double* r, int steps, hipStream_t s);
+hipError_t stokes_restrict(Stokes* S, int l, const double* r, double* fc, hipStream_t s);
+hipError_t stokes_prolong_add(Stokes* S, int l, const double* xc, double* x, hipStream_t s);
+hipError_t stokes_coarse_solve(Stokes* S, const double* f, double* x, hipStream_t s);
+hipError_t stokes_project(Stokes* S, int l, double* x, hipStream_t s);
+hipError_t stokes_cycle(Stokes* S, const double* f, double* x, double* r, bool current, hipStream_t s);
+double* stokes_fine_r(Stokes* S);
+hipError_t stokes_ir_step(Stokes* S, double* x, hipStream_t s, const double* nrm2);
 
 // FP32-preconditioned iterative refinement glue
 // refinement scale s = sqrt(*nrm2) read on the device (1 if the norm is zero)

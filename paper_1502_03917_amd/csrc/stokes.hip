@@ -1,0 +1,1177 @@
+// Stokes control (Takacs, arXiv 1502.03917, section 1 eq. mp3) on gfx950:
+// Taylor-Hood P2 velocity (zero on the boundary) / P1 pressure on the
+// uniform mesh of the unit square split along the (i,j)-(i+1,j+1)
+// diagonals, the smoothers of section 2 and the multigrid cycle.
+//
+// Unknowns [v1 | v2 | p | lambda1 | lambda2 | mu]: v_c and lambda_c on the
+// (2n-1)^2 interior nodes (a, b) of the half-step lattice (index
+// (b-1)(2n-1)+(a-1)), p and mu on the (n+1)^2 vertices (index j(n+1)+i).
+//
+// The operator has six coupled fields and two element types, so it is kept
+// as one CSR matrix per level (assembled here on the host from element
+// matrices computed by Gauss quadrature), and the kernels walk its rows:
+// one thread per row for the residual and the normal-equation smoother, one
+// thread per group of unknowns for a colour phase of the LSGS sweep (Alg. 2),
+// one thread per patch for a colour phase of the patch (Vanka-type) smoother.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "mg_internal.hpp"
+
+namespace mgk {
+
+namespace {
+
+constexpr int kSNT = 256;
+constexpr int kMaxPatch = 30;
+
+// ------------------------------------------------------------ host assembly
+
+// Collapsed Gauss-Legendre rule on the reference triangle {xi, eta >= 0,
+// xi + eta <= 1}: 3 x 3 points of the square mapped by eta = (1 - u) t; exact
+// for polynomials of degree 4 (P2 x P2 products).
+struct TriRule {
+  double xi[9], eta[9], w[9];
+  TriRule() {
+    const double g[3] = {0.5 - std::sqrt(15.0) / 10.0, 0.5, 0.5 + std::sqrt(15.0) / 10.0};
+    const double gw[3] = {5.0 / 18.0, 8.0 / 18.0, 5.0 / 18.0};
+    int k = 0;
+    for (int a = 0; a < 3; a++)
+      for (int b = 0; b < 3; b++, k++) {
+        xi[k] = g[a];
+        eta[k] = (1.0 - g[a]) * g[b];
+        w[k] = gw[a] * gw[b] * (1.0 - g[a]);
+      }
+  }
+};
+
+// P2 shape functions on the reference triangle and their (xi, eta) gradients;
+// nodes 0, 1, 2 = vertices (0,0), (1,0), (0,1); 3 = mid(0,1), 4 = mid(1,2), 5 = mid(0,2)
+void p2_shape(double xi, double eta, double N[6], double dN[6][2]) {
+  const double l[3] = {1.0 - xi - eta, xi, eta};
+  const double dl[3][2] = {{-1.0, -1.0}, {1.0, 0.0}, {0.0, 1.0}};
+  for (int k = 0; k < 3; k++) {
+    N[k] = l[k] * (2.0 * l[k] - 1.0);
+    for (int d = 0; d < 2; d++) dN[k][d] = (4.0 * l[k] - 1.0) * dl[k][d];
+  }
+  const int e[3][2] = {{0, 1}, {1, 2}, {0, 2}};
+  for (int m = 0; m < 3; m++) {
+    const int a = e[m][0], b = e[m][1];
+    N[3 + m] = 4.0 * l[a] * l[b];
+    for (int d = 0; d < 2; d++) dN[3 + m][d] = 4.0 * (dl[a][d] * l[b] + l[a] * dl[b][d]);
+  }
+}
+
+// Element matrices of a triangle with corners c[3] (physical coordinates):
+// P2 mass, P2 Laplacian stiffness, and Dc[q][a] = -int l_q d_c N_a.
+void p2_element(const double cx[3], const double cy[3], double M[6][6], double K[6][6], double D[2][3][6]) {
+  static const TriRule R;
+  const double J00 = cx[1] - cx[0], J01 = cx[2] - cx[0], J10 = cy[1] - cy[0], J11 = cy[2] - cy[0];
+  const double det = J00 * J11 - J01 * J10, adet = std::fabs(det);
+  // inverse transpose: grad_x = J^-T grad_xi
+  const double I00 = J11 / det, I01 = -J10 / det, I10 = -J01 / det, I11 = J00 / det;
+  std::memset(M, 0, sizeof(double) * 36);
+  std::memset(K, 0, sizeof(double) * 36);
+  std::memset(D, 0, sizeof(double) * 36);
+  for (int p = 0; p < 9; p++) {
+    double N[6], dN[6][2], gx[6], gy[6];
+    p2_shape(R.xi[p], R.eta[p], N, dN);
+    for (int a = 0; a < 6; a++) {
+      gx[a] = I00 * dN[a][0] + I01 * dN[a][1];
+      gy[a] = I10 * dN[a][0] + I11 * dN[a][1];
+    }
+    const double w = R.w[p] * adet;
+    const double l[3] = {1.0 - R.xi[p] - R.eta[p], R.xi[p], R.eta[p]};
+    for (int a = 0; a < 6; a++) {
+      for (int b = 0; b < 6; b++) {
+        M[a][b] += w * N[a] * N[b];
+        K[a][b] += w * (gx[a] * gx[b] + gy[a] * gy[b]);
+      }
+      for (int q = 0; q < 3; q++) {
+        D[0][q][a] -= w * l[q] * gx[a];
+        D[1][q][a] -= w * l[q] * gy[a];
+      }
+    }
+  }
+}
+
+// The two triangles of a cell (unit cell corner at the origin), local nodes
+// as offsets on the half-step lattice: vertices, then mid(0,1), mid(1,2), mid(0,2).
+struct CellTri {
+  int hu[6], hv[6];  // half-lattice offsets of the 6 nodes
+  int vi[3], vj[3];  // vertex offsets (cells)
+};
+const CellTri kTri[2] = {
+    // lower: (0,0), (1,0), (1,1)
+    {{0, 2, 2, 1, 2, 1}, {0, 0, 2, 0, 1, 1}, {0, 1, 1}, {0, 0, 1}},
+    // upper: (0,0), (1,1), (0,1)
+    {{0, 2, 0, 1, 1, 0}, {0, 2, 2, 1, 2, 1}, {0, 1, 0}, {0, 1, 1}},
+};
+
+struct HCsr {
+  int nrows = 0, ncols = 0;
+  std::vector<int> rp, col;
+  std::vector<double> val;
+};
+
+// row builder with a fixed capacity per row; duplicates accumulate
+struct RowAcc {
+  int nrows, ncols, cap;
+  std::vector<int> cnt, col;
+  std::vector<double> val;
+  RowAcc(int nr, int nc, int c) : nrows(nr), ncols(nc), cap(c), cnt(nr, 0), col((size_t)nr * c), val((size_t)nr * c) {}
+  bool add(int r, int c, double v) {
+    int* cs = &col[(size_t)r * cap];
+    double* vs = &val[(size_t)r * cap];
+    for (int k = 0; k < cnt[r]; k++)
+      if (cs[k] == c) {
+        vs[k] += v;
+        return true;
+      }
+    if (cnt[r] == cap) return false;
+    cs[cnt[r]] = c;
+    vs[cnt[r]] = v;
+    cnt[r]++;
+    return true;
+  }
+  HCsr finish() const {
+    HCsr A;
+    A.nrows = nrows;
+    A.ncols = ncols;
+    A.rp.assign(nrows + 1, 0);
+    for (int r = 0; r < nrows; r++) A.rp[r + 1] = A.rp[r] + cnt[r];
+    A.col.resize(A.rp[nrows]);
+    A.val.resize(A.rp[nrows]);
+    std::vector<std::pair<int, double>> row;
+    for (int r = 0; r < nrows; r++) {
+      row.clear();
+      for (int k = 0; k < cnt[r]; k++) row.emplace_back(col[(size_t)r * cap + k], val[(size_t)r * cap + k]);
+      std::sort(row.begin(), row.end(), [](const std::pair<int, double>& a, const std::pair<int, double>& b) {
+        return a.first < b.first;
+      });
+      for (int k = 0; k < cnt[r]; k++) {
+        A.col[A.rp[r] + k] = row[k].first;
+        A.val[A.rp[r] + k] = row[k].second;
+      }
+    }
+    return A;
+  }
+};
+
+HCsr transpose(const HCsr& A) {
+  HCsr T;
+  T.nrows = A.ncols;
+  T.ncols = A.nrows;
+  T.rp.assign(T.nrows + 1, 0);
+  for (int c : A.col) T.rp[c + 1]++;
+  for (int r = 0; r < T.nrows; r++) T.rp[r + 1] += T.rp[r];
+  T.col.resize(A.col.size());
+  T.val.resize(A.val.size());
+  std::vector<int> at(T.rp.begin(), T.rp.end() - 1);
+  for (int r = 0; r < A.nrows; r++)
+    for (int k = A.rp[r]; k < A.rp[r + 1]; k++) {
+      const int d = at[A.col[k]]++;
+      T.col[d] = r;
+      T.val[d] = A.val[k];
+    }
+  return T;
+}
+
+double entry(const HCsr& A, int r, int c) {
+  const int* b = A.col.data() + A.rp[r];
+  const int* e = A.col.data() + A.rp[r + 1];
+  const int* it = std::lower_bound(b, e, c);
+  return (it != e && *it == c) ? A.val[it - A.col.data()] : 0.0;
+}
+
+// interior P2 node index, -1 on the boundary
+inline int node_of(int n, int a, int b) {
+  const int m = 2 * n - 1;
+  if (a < 1 || b < 1 || a > m || b > m) return -1;
+  return (b - 1) * m + (a - 1);
+}
+
+struct Blocks {
+  HCsr Ms, Ks, D[2];   // scalar P2 mass and stiffness (interior nodes); divergence rows over vertices
+  std::vector<double> w;  // pressure-mean weights int(phi_q)
+};
+
+bool assemble_blocks(int n, Blocks& B) {
+  const int m = 2 * n - 1, nv = m * m, np = (n + 1) * (n + 1);
+  const double h = 1.0 / n;
+  double Me[2][6][6], Ke[2][6][6], De[2][2][3][6];
+  for (int t = 0; t < 2; t++) {
+    double cx[3], cy[3];
+    for (int k = 0; k < 3; k++) {
+      cx[k] = kTri[t].vi[k] * h;
+      cy[k] = kTri[t].vj[k] * h;
+    }
+    p2_element(cx, cy, Me[t], Ke[t], De[t]);
+  }
+  RowAcc M(nv, nv, 24), K(nv, nv, 24), D0(np, nv, 24), D1(np, nv, 24);
+  B.w.assign(np, 0.0);
+  for (int j = 0; j < n; j++)
+    for (int i = 0; i < n; i++)
+      for (int t = 0; t < 2; t++) {
+        int g[6];
+        for (int a = 0; a < 6; a++) g[a] = node_of(n, 2 * i + kTri[t].hu[a], 2 * j + kTri[t].hv[a]);
+        for (int a = 0; a < 6; a++) {
+          if (g[a] < 0) continue;
+          for (int b = 0; b < 6; b++)
+            if (g[b] >= 0 && !(M.add(g[a], g[b], Me[t][a][b]) && K.add(g[a], g[b], Ke[t][a][b]))) return false;
+        }
+        for (int q = 0; q < 3; q++) {
+          const int vq = (j + kTri[t].vj[q]) * (n + 1) + i + kTri[t].vi[q];
+          B.w[vq] += h * h / 6.0;  // int over the triangle of a P1 basis function: |T| / 3
+          for (int a = 0; a < 6; a++)
+            if (g[a] >= 0 && !(D0.add(vq, g[a], De[t][0][q][a]) && D1.add(vq, g[a], De[t][1][q][a]))) return false;
+        }
+      }
+  B.Ms = M.finish();
+  B.Ks = K.finish();
+  B.D[0] = D0.finish();
+  B.D[1] = D1.finish();
+  return true;
+}
+
+// The operator of eq. mp3 as one CSR matrix (rows in field order; the
+// sub-rows of each row are already sorted by column and lie in increasing
+// column blocks).
+HCsr assemble_kkt(int n, double alpha, const Blocks& B) {
+  const int m = 2 * n - 1, nv = m * m, np = (n + 1) * (n + 1);
+  const int ov[2] = {0, nv}, op = 2 * nv, ol[2] = {2 * nv + np, 3 * nv + np}, om = 4 * nv + np;
+  const HCsr Dt[2] = {transpose(B.D[0]), transpose(B.D[1])};
+  HCsr A;
+  A.nrows = A.ncols = 4 * nv + 2 * np;
+  A.rp.reserve(A.nrows + 1);
+  A.rp.push_back(0);
+  auto put = [&](const HCsr& S, int r, int off, double scale) {
+    for (int k = S.rp[r]; k < S.rp[r + 1]; k++) {
+      A.col.push_back(off + S.col[k]);
+      A.val.push_back(scale * S.val[k]);
+    }
+  };
+  auto endrow = [&]() { A.rp.push_back((int)A.col.size()); };
+  for (int c = 0; c < 2; c++)  // v_c: M v_c + K lambda_c + D_c^T mu
+    for (int a = 0; a < nv; a++) {
+      put(B.Ms, a, ov[c], 1.0);
+      put(B.Ks, a, ol[c], 1.0);
+      put(Dt[c], a, om, 1.0);
+      endrow();
+    }
+  for (int q = 0; q < np; q++) {  // p: D_1 lambda_1 + D_2 lambda_2
+    put(B.D[0], q, ol[0], 1.0);
+    put(B.D[1], q, ol[1], 1.0);
+    endrow();
+  }
+  for (int c = 0; c < 2; c++)  // lambda_c: K v_c + D_c^T p - alpha^-1 M lambda_c
+    for (int a = 0; a < nv; a++) {
+      put(B.Ks, a, ov[c], 1.0);
+      put(Dt[c], a, op, 1.0);
+      put(B.Ms, a, ol[c], -1.0 / alpha);
+      endrow();
+    }
+  for (int q = 0; q < np; q++) {  // mu: D_1 v_1 + D_2 v_2
+    put(B.D[0], q, ov[0], 1.0);
+    put(B.D[1], q, ov[1], 1.0);
+    endrow();
+  }
+  return A;
+}
+
+// Prolongation from nc to 2 nc cells per side for the whole vector:
+// P2 interpolation for v and lambda, P1 interpolation for p and mu.
+HCsr assemble_prolongation(int nc) {
+  const int nf = 2 * nc, mc = 2 * nc - 1, mf = 2 * nf - 1;
+  const int nvc = mc * mc, nvf = mf * mf, npc = (nc + 1) * (nc + 1), npf = (nf + 1) * (nf + 1);
+  // P2 block: the coarse basis evaluated at the fine interior nodes
+  RowAcc P2(nvf, nvc, 6);
+  for (int b = 1; b <= mf; b++)
+    for (int a = 1; a <= mf; a++) {
+      const int row = (b - 1) * mf + (a - 1);
+      int I = a / 4, J = b / 4;
+      if (I > nc - 1) I = nc - 1;
+      if (J > nc - 1) J = nc - 1;
+      const double s = a / 4.0 - I, t = b / 4.0 - J;
+      const int tri = (s >= t) ? 0 : 1;
+      const double xi = tri == 0 ? s - t : s, eta = tri == 0 ? t : t - s;
+      double N[6], dN[6][2];
+      p2_shape(xi, eta, N, dN);
+      for (int k = 0; k < 6; k++) {
+        const int col = node_of(nc, 2 * I + kTri[tri].hu[k], 2 * J + kTri[tri].hv[k]);
+        if (col >= 0 && N[k] != 0.0) P2.add(row, col, N[k]);
+      }
+    }
+  // P1 block: coarse vertices copied, fine vertices on coarse edges averaged
+  RowAcc P1(npf, npc, 2);
+  for (int j = 0; j <= nf; j++)
+    for (int i = 0; i <= nf; i++) {
+      const int row = j * (nf + 1) + i;
+      const int i0 = i / 2, j0 = j / 2, i1 = (i + 1) / 2, j1 = (j + 1) / 2;
+      if (i0 == i1 && j0 == j1) {
+        P1.add(row, j0 * (nc + 1) + i0, 1.0);
+      } else {
+        P1.add(row, j0 * (nc + 1) + i0, 0.5);
+        P1.add(row, j1 * (nc + 1) + i1, 0.5);
+      }
+    }
+  const HCsr h2 = P2.finish(), h1 = P1.finish();
+  HCsr P;
+  P.nrows = 4 * nvf + 2 * npf;
+  P.ncols = 4 * nvc + 2 * npc;
+  P.rp.push_back(0);
+  const int foff[6] = {0, nvc, 2 * nvc, 2 * nvc + npc, 3 * nvc + npc, 4 * nvc + npc};
+  const bool p1[6] = {false, false, true, false, false, true};
+  for (int fl = 0; fl < 6; fl++) {
+    const HCsr& S = p1[fl] ? h1 : h2;
+    for (int r = 0; r < S.nrows; r++) {
+      for (int k = S.rp[r]; k < S.rp[r + 1]; k++) {
+        P.col.push_back(foff[fl] + S.col[k]);
+        P.val.push_back(S.val[k]);
+      }
+      P.rp.push_back((int)P.col.size());
+    }
+  }
+  return P;
+}
+
+void lu_dense(int n, std::vector<double>& a, std::vector<int>& piv, bool& ok) {
+  piv.resize(n);
+  ok = true;
+  for (int k = 0; k < n; k++) {
+    int p = k;
+    for (int i = k + 1; i < n; i++)
+      if (std::fabs(a[(size_t)i * n + k]) > std::fabs(a[(size_t)p * n + k])) p = i;
+    piv[k] = p;
+    if (p != k)
+      for (int c = 0; c < n; c++) std::swap(a[(size_t)k * n + c], a[(size_t)p * n + c]);
+    const double d = a[(size_t)k * n + k];
+    if (d == 0.0) {
+      ok = false;
+      return;
+    }
+    for (int i = k + 1; i < n; i++) {
+      const double f = a[(size_t)i * n + k] / d;
+      a[(size_t)i * n + k] = f;
+      for (int c = k + 1; c < n; c++) a[(size_t)i * n + c] -= f * a[(size_t)k * n + c];
+    }
+  }
+}
+
+// Colour phases of Alg. 2 for the level with n cells per side: per velocity
+// component c, 25 colours (a mod 5) + 5 (b mod 5) of the interior P2 nodes
+// with groups {v_c, lambda_c} of one node; then 9 colours (i mod 3) + 3 (j mod 3)
+// of the vertices with groups {p, mu}.  Phase k spans groups [ph[k], ph[k+1]).
+void colour_groups(int n, std::vector<int2>& grp, std::vector<int>& ph) {
+  const int m = 2 * n - 1, nv = m * m, np = (n + 1) * (n + 1);
+  const int op = 2 * nv, ol = 2 * nv + np, om = 4 * nv + np;
+  grp.clear();
+  ph.assign(1, 0);
+  for (int c = 0; c < 2; c++)
+    for (int col = 0; col < 25; col++) {
+      for (int b = 1; b <= m; b++)
+        for (int a = 1; a <= m; a++)
+          if (a % 5 + 5 * (b % 5) == col) {
+            const int node = (b - 1) * m + (a - 1);
+            grp.push_back(make_int2(c * nv + node, ol + c * nv + node));
+          }
+      ph.push_back((int)grp.size());
+    }
+  for (int col = 0; col < 9; col++) {
+    for (int j = 0; j <= n; j++)
+      for (int i = 0; i <= n; i++)
+        if (i % 3 + 3 * (j % 3) == col) {
+          const int q = j * (n + 1) + i;
+          grp.push_back(make_int2(op + q, om + q));
+        }
+    ph.push_back((int)grp.size());
+  }
+}
+
+// Patches of the patch smoother (one per vertex) with the LU factors of their
+// matrices; patches listed by colour (i mod 3) + 3 (j mod 3), phase k spans
+// order[ph[k] .. ph[k+1]).
+bool build_patches(int n, const HCsr& A, std::vector<int>& dptr, std::vector<int>& dof, std::vector<int>& piv,
+                   std::vector<long long>& luptr, std::vector<double>& lu, std::vector<int>& order,
+                   std::vector<int>& ph, std::string* err) {
+  const int m = 2 * n - 1, nv = m * m, np = (n + 1) * (n + 1);
+  const int op = 2 * nv, ol = 2 * nv + np, om = 4 * nv + np;
+  dptr.assign(np + 1, 0);
+  luptr.assign(np + 1, 0);
+  dof.clear();
+  piv.clear();
+  lu.clear();
+  order.clear();
+  auto vel = [&](int node, std::vector<int>& d) {
+    d.push_back(node);
+    d.push_back(nv + node);
+    d.push_back(ol + node);
+    d.push_back(ol + nv + node);
+  };
+  const int di[7] = {0, 1, -1, 0, 0, 1, -1}, dj[7] = {0, 0, 0, 1, -1, 1, -1};
+  for (int j = 0; j <= n; j++)
+    for (int i = 0; i <= n; i++) {
+      const int q = j * (n + 1) + i;
+      std::vector<int> d = {op + q, om + q};
+      for (int e = 0; e < 7; e++) {
+        const int ii = i + di[e], jj = j + dj[e];
+        if (ii < 0 || jj < 0 || ii > n || jj > n) continue;
+        const int node = node_of(n, i + ii, j + jj);
+        if (node >= 0) vel(node, d);
+      }
+      if (d.size() == 2) {
+        // every edge at the vertex lies on the boundary: the interior nodes
+        // of the triangles containing the vertex
+        for (int cj = j - 1; cj <= j; cj++)
+          for (int ci = i - 1; ci <= i; ci++) {
+            if (ci < 0 || cj < 0 || ci >= n || cj >= n) continue;
+            for (int t = 0; t < 2; t++) {
+              bool has = false;
+              for (int k = 0; k < 3; k++) has |= (ci + kTri[t].vi[k] == i && cj + kTri[t].vj[k] == j);
+              if (!has) continue;
+              for (int k = 0; k < 6; k++) {
+                const int node = node_of(n, 2 * ci + kTri[t].hu[k], 2 * cj + kTri[t].hv[k]);
+                if (node >= 0 && std::find(d.begin(), d.end(), node) == d.end()) vel(node, d);
+              }
+            }
+          }
+      }
+      const int msz = (int)d.size();
+      if (msz > kMaxPatch) {
+        *err = "stokes: patch larger than 30 unknowns";
+        return false;
+      }
+      std::vector<double> a((size_t)msz * msz);
+      for (int u = 0; u < msz; u++)
+        for (int v = 0; v < msz; v++) a[(size_t)u * msz + v] = entry(A, d[u], d[v]);
+      std::vector<int> pv;
+      bool ok;
+      lu_dense(msz, a, pv, ok);
+      if (!ok) {
+        *err = "stokes: singular patch matrix";
+        return false;
+      }
+      dptr[q + 1] = dptr[q] + msz;
+      luptr[q + 1] = luptr[q] + (long long)msz * msz;
+      dof.insert(dof.end(), d.begin(), d.end());
+      piv.insert(piv.end(), pv.begin(), pv.end());
+      lu.insert(lu.end(), a.begin(), a.end());
+    }
+  ph.assign(1, 0);
+  for (int col = 0; col < 9; col++) {
+    for (int j = 0; j <= n; j++)
+      for (int i = 0; i <= n; i++)
+        if (i % 3 + 3 * (j % 3) == col) order.push_back(j * (n + 1) + i);
+    ph.push_back((int)order.size());
+  }
+  return true;
+}
+
+// ------------------------------------------------------------------ kernels
+
+__device__ inline double wsum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+  return v;
+}
+
+__device__ inline void block_store(double v, double* out) {
+  __shared__ double sh[kSNT / 64];
+  v = wsum(v);
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double s = 0.0;
+    for (int w = 0; w < kSNT / 64; w++) s += sh[w];
+    *out = s;
+  }
+}
+
+// r = f - A x (MODE 0), with per-block partial sums of ||r||_2^2 (1) or
+// r^T L^-1 r (2); f == nullptr gives r = A x
+template <typename T, int MODE>
+__global__ __launch_bounds__(kSNT) void ks_resid(int n, const int* __restrict__ rp, const int* __restrict__ col,
+                                                 const T* __restrict__ val, const T* __restrict__ f,
+                                                 const T* __restrict__ x, T* __restrict__ r,
+                                                 const double* __restrict__ Ld, double* __restrict__ part) {
+  const int i = blockIdx.x * kSNT + threadIdx.x;
+  double s2 = 0.0;
+  if (i < n) {
+    T s = 0;
+    for (int k = rp[i]; k < rp[i + 1]; k++) s += val[k] * x[col[k]];
+    const T ri = f ? f[i] - s : s;
+    r[i] = ri;
+    if (MODE == 1) s2 = (double)ri * (double)ri;
+    if (MODE == 2) s2 = (double)ri * (double)ri / Ld[i];
+  }
+  if (MODE) block_store(s2, &part[blockIdx.x]);
+}
+
+// per-block partial sums of ||v||^2 (MODE 1) or v^T L^-1 v (MODE 2)
+template <int MODE>
+__global__ __launch_bounds__(kSNT) void ks_vnorm(int n, const double* __restrict__ v, const double* __restrict__ Ld,
+                                                 double* __restrict__ part) {
+  const int i = blockIdx.x * kSNT + threadIdx.x;
+  double s2 = 0.0;
+  if (i < n) s2 = MODE == 1 ? v[i] * v[i] : v[i] * v[i] / Ld[i];
+  block_store(s2, &part[blockIdx.x]);
+}
+
+// y = A x (ADD 0) or y += A x (ADD 1); restriction variant also writes x_c = 0, r_c = f_c
+template <typename T, int ADD>
+__global__ __launch_bounds__(kSNT) void ks_spmv(int n, const int* __restrict__ rp, const int* __restrict__ col,
+                                                const T* __restrict__ val, const T* __restrict__ x, T* __restrict__ y,
+                                                T* __restrict__ zero_out, T* __restrict__ copy_out) {
+  const int i = blockIdx.x * kSNT + threadIdx.x;
+  if (i >= n) return;
+  T s = 0;
+  for (int k = rp[i]; k < rp[i + 1]; k++) s += val[k] * x[col[k]];
+  if (ADD) {
+    y[i] += s;
+  } else {
+    y[i] = s;
+    if (zero_out) zero_out[i] = (T)0;
+    if (copy_out) copy_out[i] = s;
+  }
+}
+
+// Alg. 1, first loop with x += p: p_i = tau (sum_j A_ij r_j / L_jj) / L_ii
+template <typename T>
+__global__ __launch_bounds__(kSNT) void ks_ne_p(int n, const int* __restrict__ rp, const int* __restrict__ col,
+                                                const T* __restrict__ val, const T* __restrict__ Linv, T tau,
+                                                const T* __restrict__ r, T* __restrict__ x, T* __restrict__ p) {
+  const int i = blockIdx.x * kSNT + threadIdx.x;
+  if (i >= n) return;
+  T q = 0;
+  for (int k = rp[i]; k < rp[i + 1]; k++) q += val[k] * Linv[col[k]] * r[col[k]];
+  const T pi = tau * q * Linv[i];
+  p[i] = pi;
+  x[i] += pi;
+}
+
+// Alg. 1, second loop: r -= A p (A symmetric: row i holds the column)
+template <typename T>
+__global__ __launch_bounds__(kSNT) void ks_ne_r(int n, const int* __restrict__ rp, const int* __restrict__ col,
+                                                const T* __restrict__ val, const T* __restrict__ p, T* __restrict__ r) {
+  const int i = blockIdx.x * kSNT + threadIdx.x;
+  if (i >= n) return;
+  T s = 0;
+  for (int k = rp[i]; k < rp[i + 1]; k++) s += val[k] * p[col[k]];
+  r[i] -= s;
+}
+
+// One colour phase of Alg. 2: every group (two unknowns whose entry of
+// N = A^T L^-1 A is zero) takes both q from the residual, updates x, and
+// subtracts A_ji p_i from r; groups of a phase share no residual entry.
+template <typename T>
+__global__ __launch_bounds__(kSNT) void ks_lsgs(int g0, int ng, const int2* __restrict__ grp,
+                                                const int* __restrict__ rp, const int* __restrict__ col,
+                                                const T* __restrict__ val, const T* __restrict__ Linv,
+                                                const T* __restrict__ Ninv, T* __restrict__ x, T* __restrict__ r) {
+  const int g = blockIdx.x * kSNT + threadIdx.x;
+  if (g >= ng) return;
+  const int2 u = grp[g0 + g];
+  T q1 = 0, q2 = 0;
+  for (int k = rp[u.x]; k < rp[u.x + 1]; k++) q1 += val[k] * Linv[col[k]] * r[col[k]];
+  for (int k = rp[u.y]; k < rp[u.y + 1]; k++) q2 += val[k] * Linv[col[k]] * r[col[k]];
+  const T p1 = q1 * Ninv[u.x], p2 = q2 * Ninv[u.y];
+  x[u.x] += p1;
+  x[u.y] += p2;
+  for (int k = rp[u.x]; k < rp[u.x + 1]; k++) r[col[k]] -= val[k] * p1;
+  for (int k = rp[u.y]; k < rp[u.y + 1]; k++) r[col[k]] -= val[k] * p2;
+}
+
+// One colour phase of the patch smoother: x_P += tau A_PP^-1 r_P,
+// r -= tau A_{:,P} A_PP^-1 r_P (LU factors of A_PP with row pivots, FP64)
+template <typename T>
+__global__ __launch_bounds__(64) void ks_vanka(int p0, int npatch, const int* __restrict__ order,
+                                               const int* __restrict__ dptr, const int* __restrict__ dof,
+                                               const long long* __restrict__ luptr, const double* __restrict__ lu,
+                                               const int* __restrict__ piv, const int* __restrict__ rp,
+                                               const int* __restrict__ col, const T* __restrict__ val, double tau,
+                                               T* __restrict__ x, T* __restrict__ r) {
+  const int t = blockIdx.x * 64 + threadIdx.x;
+  if (t >= npatch) return;
+  const int q = order[p0 + t];
+  const int b = dptr[q], m = dptr[q + 1] - b;
+  const double* a = lu + luptr[q];
+  const int* pv = piv + b;
+  double y[kMaxPatch];
+  for (int u = 0; u < m; u++) y[u] = (double)r[dof[b + u]];
+  for (int k = 0; k < m; k++)
+    if (pv[k] != k) {
+      const double s = y[k];
+      y[k] = y[pv[k]];
+      y[pv[k]] = s;
+    }
+  for (int i = 1; i < m; i++)
+    for (int c = 0; c < i; c++) y[i] -= a[i * m + c] * y[c];
+  for (int i = m - 1; i >= 0; i--) {
+    for (int c = i + 1; c < m; c++) y[i] -= a[i * m + c] * y[c];
+    y[i] /= a[i * m + i];
+  }
+  for (int u = 0; u < m; u++) {
+    const int i = dof[b + u];
+    const T du = (T)(tau * y[u]);
+    x[i] += du;
+    for (int k = rp[i]; k < rp[i + 1]; k++) r[col[k]] -= val[k] * du;
+  }
+}
+
+// pressure and multiplier means: per-block partial sums of w.p and w.mu
+template <typename T>
+__global__ __launch_bounds__(kSNT) void ks_wsum(int np, const double* __restrict__ w, const T* __restrict__ vp,
+                                                const T* __restrict__ vm, double* __restrict__ part) {
+  const int q = blockIdx.x * kSNT + threadIdx.x;
+  const double a = q < np ? w[q] * (double)vp[q] : 0.0;
+  const double b = q < np ? w[q] * (double)vm[q] : 0.0;
+  block_store(a, &part[2 * blockIdx.x]);
+  __syncthreads();
+  block_store(b, &part[2 * blockIdx.x + 1]);
+}
+
+// s[0], s[1] = the two means (sums / wsum)
+__global__ __launch_bounds__(kSNT) void ks_means(const double* __restrict__ part, int nb, double inv_w,
+                                                 double* __restrict__ s) {
+  double a = 0.0, b = 0.0;
+  for (int k = threadIdx.x; k < nb; k += kSNT) {
+    a += part[2 * k];
+    b += part[2 * k + 1];
+  }
+  block_store(a, &s[0]);
+  __syncthreads();
+  block_store(b, &s[1]);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    s[0] *= inv_w;
+    s[1] *= inv_w;
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(kSNT) void ks_shift(int np, const double* __restrict__ s, T* __restrict__ vp,
+                                                 T* __restrict__ vm) {
+  const int q = blockIdx.x * kSNT + threadIdx.x;
+  if (q >= np) return;
+  vp[q] = (T)((double)vp[q] - s[0]);
+  vm[q] = (T)((double)vm[q] - s[1]);
+}
+
+// coarsest level: LU solve of the system bordered by the two mean constraints
+template <typename T>
+__global__ __launch_bounds__(256) void ks_coarse(int N, int NB, const double* __restrict__ lu,
+                                                 const int* __restrict__ piv, const T* __restrict__ f,
+                                                 T* __restrict__ x) {
+  __shared__ double b[512];
+  const int tid = threadIdx.x;
+  for (int i = tid; i < NB; i += blockDim.x) b[i] = i < N ? (double)f[i] : 0.0;
+  __syncthreads();
+  if (tid == 0)
+    for (int k = 0; k < NB; k++)
+      if (piv[k] != k) {
+        const double t = b[k];
+        b[k] = b[piv[k]];
+        b[piv[k]] = t;
+      }
+  __syncthreads();
+  for (int k = 0; k < NB; k++) {
+    const double bk = b[k];
+    for (int i = k + 1 + tid; i < NB; i += blockDim.x) b[i] -= lu[(size_t)i * NB + k] * bk;
+    __syncthreads();
+  }
+  for (int k = NB - 1; k >= 0; k--) {
+    if (tid == 0) b[k] /= lu[(size_t)k * NB + k];
+    __syncthreads();
+    const double bk = b[k];
+    for (int i = tid; i < k; i += blockDim.x) b[i] -= lu[(size_t)i * NB + k] * bk;
+    __syncthreads();
+  }
+  for (int i = tid; i < N; i += blockDim.x) x[i] = (T)b[i];
+}
+
+// f = (M vd_1; M vd_2; 0; 0; 0; 0) with the scalar P2 mass M
+__global__ __launch_bounds__(kSNT) void ks_rhs(int nv, int ndof, const int* __restrict__ rp,
+                                               const int* __restrict__ col, const double* __restrict__ val,
+                                               const double* __restrict__ vd, double* __restrict__ f) {
+  const int i = blockIdx.x * kSNT + threadIdx.x;
+  if (i >= ndof) return;
+  double s = 0.0;
+  if (i < 2 * nv) {
+    const int c = i / nv, a = i - c * nv;
+    for (int k = rp[a]; k < rp[a + 1]; k++) s += val[k] * vd[c * nv + col[k]];
+  }
+  f[i] = s;
+}
+
+inline int blocks_for(int n, int nt = kSNT) { return (n + nt - 1) / nt; }
+
+template <typename T>
+struct Dev {
+  T* p = nullptr;
+};
+
+template <typename T>
+hipError_t upload(T** d, const T* h, size_t n) {
+  if (n == 0) {
+    *d = nullptr;
+    return hipSuccess;
+  }
+  hipError_t e = hipMalloc(d, n * sizeof(T));
+  if (e != hipSuccess) return e;
+  return hipMemcpy(*d, h, n * sizeof(T), hipMemcpyHostToDevice);
+}
+
+}  // namespace
+
+// ------------------------------------------------------------ solver object
+
+struct StokesLevel {
+  int l = 0, n = 0, nv = 0, np = 0, ndof = 0;
+  int *A_rp = nullptr, *A_col = nullptr;
+  double* A_val = nullptr;
+  float* A_val32 = nullptr;
+  double *Ld = nullptr, *Linv = nullptr, *Ninv = nullptr;
+  float *Linv32 = nullptr, *Ninv32 = nullptr;
+  // prolongation from level l-1 and restriction to it (its transpose)
+  int *P_rp = nullptr, *P_col = nullptr, *R_rp = nullptr, *R_col = nullptr;
+  double *P_val = nullptr, *R_val = nullptr;
+  float *P_val32 = nullptr, *R_val32 = nullptr;
+  // LSGS colour phases: groups of two unknowns, phase g spans groups [gph[g], gph[g+1])
+  int2* groups = nullptr;
+  std::vector<int> gph;
+  // patch smoother: patches (one per vertex) ordered by colour, phase spans vph
+  int *v_order = nullptr, *v_dptr = nullptr, *v_dof = nullptr, *v_piv = nullptr;
+  long long* v_luptr = nullptr;
+  double* v_lu = nullptr;
+  std::vector<int> vph;
+  // pressure-mean weights
+  double* w = nullptr;
+  double wsum = 0.0;
+  // workspace (the finest level takes the caller's x and f)
+  double *x = nullptr, *f = nullptr, *r = nullptr, *p = nullptr;
+  float *x32 = nullptr, *f32 = nullptr, *r32 = nullptr, *p32 = nullptr;
+};
+
+struct Stokes {
+  int level = 0, k0 = 1, smoother = 1, nu1 = 2, nu2 = 2, gamma = 1;
+  double alpha = 1.0, tau = 0.35;
+  bool fp32 = false;
+  std::vector<StokesLevel> lv;  // lv[l - k0]
+  int *M_rp = nullptr, *M_col = nullptr;  // scalar P2 mass of the finest level (right-hand side)
+  double* M_val = nullptr;
+  double* lu = nullptr;  // bordered coarsest LU
+  int* piv = nullptr;
+  int nlu = 0, ncoarse = 0;
+  double* part = nullptr;  // partial sums of the mean projection
+  double* means = nullptr;
+  size_t npart = 0;
+  std::vector<void*> owned;
+  StokesLevel& L(int l) { return lv[l - k0]; }
+};
+
+namespace {
+
+template <typename T>
+hipError_t up(Stokes* S, T** d, const std::vector<T>& h) {
+  hipError_t e = upload(d, h.data(), h.size());
+  if (e == hipSuccess && *d) S->owned.push_back(*d);
+  return e;
+}
+
+template <typename T>
+hipError_t zalloc(Stokes* S, T** d, size_t n) {
+  hipError_t e = hipMalloc(d, n * sizeof(T));
+  if (e == hipSuccess) S->owned.push_back(*d);
+  return e;
+}
+
+#define SCHK(expr)                          \
+  do {                                      \
+    hipError_t e_ = (expr);                 \
+    if (e_ != hipSuccess) return e_;        \
+  } while (0)
+
+std::vector<float> to32(const std::vector<double>& v) { return std::vector<float>(v.begin(), v.end()); }
+
+hipError_t build_level(Stokes* S, int l, bool finest, std::string* err) {
+  StokesLevel& L = S->L(l);
+  const int n = 1 << l, m = 2 * n - 1;
+  L.l = l;
+  L.n = n;
+  L.nv = m * m;
+  L.np = (n + 1) * (n + 1);
+  L.ndof = 4 * L.nv + 2 * L.np;
+  Blocks B;
+  if (!assemble_blocks(n, B)) {
+    *err = "stokes: element assembly overflow";
+    return hipErrorInvalidValue;
+  }
+  const HCsr A = assemble_kkt(n, S->alpha, B);
+  SCHK(up(S, &L.A_rp, A.rp));
+  SCHK(up(S, &L.A_col, A.col));
+  SCHK(up(S, &L.A_val, A.val));
+  // L = (W^, W^, P^, W^/alpha, W^/alpha, P^/alpha), W^ = diag(M + alpha^1/2 K), P^ = alpha diag(D W^-1 D^T)
+  std::vector<double> Ld(L.ndof), W(L.nv);
+  for (int a = 0; a < L.nv; a++) W[a] = entry(B.Ms, a, a) + std::sqrt(S->alpha) * entry(B.Ks, a, a);
+  const int op = 2 * L.nv, ol = 2 * L.nv + L.np, om = 4 * L.nv + L.np;
+  for (int a = 0; a < L.nv; a++) {
+    Ld[a] = Ld[L.nv + a] = W[a];
+    Ld[ol + a] = Ld[ol + L.nv + a] = W[a] / S->alpha;
+  }
+  for (int q = 0; q < L.np; q++) {
+    double s = 0.0;
+    for (int c = 0; c < 2; c++)
+      for (int k = B.D[c].rp[q]; k < B.D[c].rp[q + 1]; k++) s += B.D[c].val[k] * B.D[c].val[k] / W[B.D[c].col[k]];
+    Ld[op + q] = S->alpha * s;
+    Ld[om + q] = s;
+  }
+  std::vector<double> Linv(L.ndof), Ninv(L.ndof);
+  for (int i = 0; i < L.ndof; i++) Linv[i] = 1.0 / Ld[i];
+  for (int i = 0; i < L.ndof; i++) {  // N_ii = sum_j A_ij^2 / L_jj (A symmetric)
+    double s = 0.0;
+    for (int k = A.rp[i]; k < A.rp[i + 1]; k++) s += A.val[k] * A.val[k] * Linv[A.col[k]];
+    Ninv[i] = 1.0 / s;
+  }
+  SCHK(up(S, &L.Ld, Ld));
+  SCHK(up(S, &L.Linv, Linv));
+  SCHK(up(S, &L.Ninv, Ninv));
+  SCHK(up(S, &L.w, B.w));
+  L.wsum = 0.0;
+  for (double v : B.w) L.wsum += v;
+  if (S->fp32) {
+    SCHK(up(S, &L.A_val32, to32(A.val)));
+    SCHK(up(S, &L.Linv32, to32(Linv)));
+    SCHK(up(S, &L.Ninv32, to32(Ninv)));
+  }
+  std::vector<int2> grp;
+  colour_groups(n, grp, L.gph);
+  SCHK(up(S, &L.groups, grp));
+  // patches of the patch smoother
+  if (S->smoother == MG_VANKA) {
+    std::vector<int> dptr, dof, piv, order;
+    std::vector<long long> luptr;
+    std::vector<double> lu;
+    if (!build_patches(n, A, dptr, dof, piv, luptr, lu, order, L.vph, err)) return hipErrorInvalidValue;
+    SCHK(up(S, &L.v_order, order));
+    SCHK(up(S, &L.v_dptr, dptr));
+    SCHK(up(S, &L.v_dof, dof));
+    SCHK(up(S, &L.v_piv, piv));
+    SCHK(up(S, &L.v_luptr, luptr));
+    SCHK(up(S, &L.v_lu, lu));
+  }
+  // transfers from / to level l-1
+  if (l > S->k0) {
+    const HCsr P = assemble_prolongation(n / 2), R = transpose(P);
+    SCHK(up(S, &L.P_rp, P.rp));
+    SCHK(up(S, &L.P_col, P.col));
+    SCHK(up(S, &L.P_val, P.val));
+    SCHK(up(S, &L.R_rp, R.rp));
+    SCHK(up(S, &L.R_col, R.col));
+    SCHK(up(S, &L.R_val, R.val));
+    if (S->fp32) {
+      SCHK(up(S, &L.P_val32, to32(P.val)));
+      SCHK(up(S, &L.R_val32, to32(R.val)));
+    }
+  }
+  // workspace
+  const size_t nd = L.ndof;
+  if (!finest) {
+    SCHK(zalloc(S, &L.x, nd));
+    SCHK(zalloc(S, &L.f, nd));
+  }
+  SCHK(zalloc(S, &L.r, nd));
+  SCHK(zalloc(S, &L.p, nd));
+  if (S->fp32) {
+    SCHK(zalloc(S, &L.x32, nd));
+    SCHK(zalloc(S, &L.f32, nd));
+    SCHK(zalloc(S, &L.r32, nd));
+    SCHK(zalloc(S, &L.p32, nd));
+  }
+  if (finest) {
+    SCHK(up(S, &S->M_rp, B.Ms.rp));
+    SCHK(up(S, &S->M_col, B.Ms.col));
+    SCHK(up(S, &S->M_val, B.Ms.val));
+  }
+  if (l == S->k0) {
+    // bordered coarsest matrix [[A, C], [C^T, 0]], C = mean weights in the p and mu rows
+    const int N = L.ndof, NB = N + 2;
+    std::vector<double> a((size_t)NB * NB, 0.0);
+    for (int r = 0; r < N; r++)
+      for (int k = A.rp[r]; k < A.rp[r + 1]; k++) a[(size_t)r * NB + A.col[k]] = A.val[k];
+    for (int q = 0; q < L.np; q++) {
+      a[(size_t)(op + q) * NB + N] = a[(size_t)N * NB + op + q] = B.w[q];
+      a[(size_t)(om + q) * NB + N + 1] = a[(size_t)(N + 1) * NB + om + q] = B.w[q];
+    }
+    std::vector<int> pv;
+    bool ok;
+    lu_dense(NB, a, pv, ok);
+    if (!ok) {
+      *err = "stokes: singular coarsest matrix";
+      return hipErrorInvalidValue;
+    }
+    SCHK(up(S, &S->lu, a));
+    SCHK(up(S, &S->piv, pv));
+    S->nlu = NB;
+    S->ncoarse = N;
+  }
+  return hipSuccess;
+}
+
+template <typename T>
+struct SV;
+template <>
+struct SV<double> {
+  static double* x(StokesLevel& L) { return L.x; }
+  static double* f(StokesLevel& L) { return L.f; }
+  static double* r(StokesLevel& L) { return L.r; }
+  static double* p(StokesLevel& L) { return L.p; }
+  static const double* A(StokesLevel& L) { return L.A_val; }
+  static const double* P(StokesLevel& L) { return L.P_val; }
+  static const double* R(StokesLevel& L) { return L.R_val; }
+  static const double* Linv(StokesLevel& L) { return L.Linv; }
+  static const double* Ninv(StokesLevel& L) { return L.Ninv; }
+};
+template <>
+struct SV<float> {
+  static float* x(StokesLevel& L) { return L.x32; }
+  static float* f(StokesLevel& L) { return L.f32; }
+  static float* r(StokesLevel& L) { return L.r32; }
+  static float* p(StokesLevel& L) { return L.p32; }
+  static const float* A(StokesLevel& L) { return L.A_val32; }
+  static const float* P(StokesLevel& L) { return L.P_val32; }
+  static const float* R(StokesLevel& L) { return L.R_val32; }
+  static const float* Linv(StokesLevel& L) { return L.Linv32; }
+  static const float* Ninv(StokesLevel& L) { return L.Ninv32; }
+};
+
+template <typename T>
+hipError_t s_resid(StokesLevel& L, const T* f, const T* x, T* r, hipStream_t s) {
+  hipLaunchKernelGGL((ks_resid<T, 0>), dim3(blocks_for(L.ndof)), dim3(kSNT), 0, s, L.ndof, L.A_rp, L.A_col,
+                     SV<T>::A(L), f, x, r, (const double*)nullptr, (double*)nullptr);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t s_smooth(Stokes* S, StokesLevel& L, T* x, T* r, int steps, hipStream_t s) {
+  const T* A = SV<T>::A(L);
+  for (int it = 0; it < steps; it++) {
+    switch (S->smoother) {
+      case MG_NE:
+        hipLaunchKernelGGL((ks_ne_p<T>), dim3(blocks_for(L.ndof)), dim3(kSNT), 0, s, L.ndof, L.A_rp, L.A_col, A,
+                           SV<T>::Linv(L), (T)S->tau, (const T*)r, x, SV<T>::p(L));
+        hipLaunchKernelGGL((ks_ne_r<T>), dim3(blocks_for(L.ndof)), dim3(kSNT), 0, s, L.ndof, L.A_rp, L.A_col, A,
+                           (const T*)SV<T>::p(L), r);
+        break;
+      case MG_LSGS:
+      case MG_SLSGS: {
+        const int nph = (int)L.gph.size() - 1;
+        const int sweeps = S->smoother == MG_SLSGS ? 2 : 1;
+        for (int sw = 0; sw < sweeps; sw++)
+          for (int k = 0; k < nph; k++) {
+            const int ph = sw == 0 ? k : nph - 1 - k;
+            const int g0 = L.gph[ph], ng = L.gph[ph + 1] - g0;
+            hipLaunchKernelGGL((ks_lsgs<T>), dim3(blocks_for(ng)), dim3(kSNT), 0, s, g0, ng,
+                               (const int2*)L.groups, L.A_rp, L.A_col, A, SV<T>::Linv(L), SV<T>::Ninv(L), x, r);
+          }
+        break;
+      }
+      case MG_VANKA:
+        for (int ph = 0; ph + 1 < (int)L.vph.size(); ph++) {
+          const int p0 = L.vph[ph], npch = L.vph[ph + 1] - p0;
+          hipLaunchKernelGGL((ks_vanka<T>), dim3(blocks_for(npch, 64)), dim3(64), 0, s, p0, npch, L.v_order,
+                             L.v_dptr, L.v_dof, L.v_luptr, L.v_lu, L.v_piv, L.A_rp, L.A_col, A, S->tau, x, r);
+        }
+        break;
+    }
+  }
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t s_project(Stokes* S, StokesLevel& L, T* x, hipStream_t s) {
+  const int nb = blocks_for(L.np);
+  T* vp = x + 2 * L.nv;
+  T* vm = x + 4 * L.nv + L.np;
+  hipLaunchKernelGGL((ks_wsum<T>), dim3(nb), dim3(kSNT), 0, s, L.np, (const double*)L.w, (const T*)vp, (const T*)vm,
+                     S->part);
+  hipLaunchKernelGGL(ks_means, dim3(1), dim3(kSNT), 0, s, (const double*)S->part, nb, 1.0 / L.wsum, S->means);
+  hipLaunchKernelGGL((ks_shift<T>), dim3(nb), dim3(kSNT), 0, s, L.np, (const double*)S->means, vp, vm);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t s_coarse(Stokes* S, const T* f, T* x, hipStream_t s) {
+  hipLaunchKernelGGL((ks_coarse<T>), dim3(1), dim3(256), 0, s, S->ncoarse, S->nlu, (const double*)S->lu,
+                     (const int*)S->piv, f, x);
+  return hipGetLastError();
+}
+
+// one iterate on level l (section 2): smoothing, restriction of the defect,
+// gamma coarse iterates from zero (exact bordered solve on k0), prolongation,
+// residual, smoothing; r is current on entry when `current`
+template <typename T>
+hipError_t s_cycle(Stokes* S, int l, const T* f, T* x, T* r, bool current, hipStream_t s) {
+  if (l == S->k0) return s_coarse<T>(S, f, x, s);
+  StokesLevel& L = S->L(l);
+  StokesLevel& C = S->L(l - 1);
+  if (!current) SCHK(s_resid<T>(L, f, x, r, s));
+  SCHK(s_smooth<T>(S, L, x, r, S->nu1, s));
+  const bool to_k0 = (l - 1 == S->k0);
+  hipLaunchKernelGGL((ks_spmv<T, 0>), dim3(blocks_for(C.ndof)), dim3(kSNT), 0, s, C.ndof, L.R_rp, L.R_col,
+                     SV<T>::R(L), (const T*)r, SV<T>::f(C), to_k0 ? (T*)nullptr : SV<T>::x(C),
+                     to_k0 ? (T*)nullptr : SV<T>::r(C));
+  SCHK(hipGetLastError());
+  for (int g = 0; g < S->gamma; g++)
+    SCHK(s_cycle<T>(S, l - 1, SV<T>::f(C), SV<T>::x(C), SV<T>::r(C), g == 0, s));
+  hipLaunchKernelGGL((ks_spmv<T, 1>), dim3(blocks_for(L.ndof)), dim3(kSNT), 0, s, L.ndof, L.P_rp, L.P_col,
+                     SV<T>::P(L), (const T*)SV<T>::x(C), x, (T*)nullptr, (T*)nullptr);
+  SCHK(hipGetLastError());
+  SCHK(s_resid<T>(L, f, x, r, s));
+  return s_smooth<T>(S, L, x, r, S->nu2, s);
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------- interface
+
+int stokes_create(int level, int k0, double alpha, const mg_opts& o, Stokes** out, std::string* err) {
+  Stokes* S = new Stokes;
+  S->level = level;
+  S->k0 = k0;
+  S->alpha = alpha;
+  S->smoother = o.smoother;
+  S->nu1 = o.nu1;
+  S->nu2 = o.nu2;
+  S->gamma = o.gamma;
+  S->tau = o.tau;
+  S->fp32 = o.precision == MG_FP32_IR;
+  S->lv.resize(level - k0 + 1);
+  for (int l = k0; l <= level; l++) {
+    const hipError_t e = build_level(S, l, l == level, err);
+    if (e != hipSuccess) {
+      if (err->empty()) *err = std::string("stokes setup: ") + hipGetErrorString(e);
+      stokes_destroy(S);
+      return e == hipErrorOutOfMemory ? MG_ENOMEM : (e == hipErrorInvalidValue ? MG_EINVAL : MG_EHIP);
+    }
+  }
+  S->npart = 2 * (size_t)blocks_for(S->L(level).np) + 2;
+  if (zalloc(S, &S->part, S->npart) != hipSuccess || zalloc(S, &S->means, 2) != hipSuccess) {
+    stokes_destroy(S);
+    return MG_ENOMEM;
+  }
+  *out = S;
+  return MG_OK;
+}
+
+void stokes_destroy(Stokes* S) {
+  if (!S) return;
+  for (void* p : S->owned) (void)hipFree(p);
+  delete S;
+}
+
+size_t stokes_len(const Stokes* S, int level) {
+  if (!S || level < S->k0 || level > S->level) return 0;
+  return (size_t)S->lv[level - S->k0].ndof;
+}
+
+size_t stokes_partials(const Stokes* S) { return (size_t)blocks_for(S->lv.back().ndof); }
+
+void stokes_set(Stokes* S, const mg_opts& o) {
+  S->nu1 = o.nu1;
+  S->nu2 = o.nu2;
+  S->gamma = o.gamma;
+  S->tau = o.tau;
+}
+
+hipError_t stokes_rhs(Stokes* S, const double* vd, double* f, hipStream_t s) {
+  StokesLevel& L = S->lv.back();
+  hipLaunchKernelGGL(ks_rhs, dim3(blocks_for(L.ndof)), dim3(kSNT), 0, s, L.nv, L.ndof, (const int*)S->M_rp,
+                     (const int*)S->M_col, (const double*)S->M_val, vd, f);
+  return hipGetLastError();
+}
+
+hipError_t stokes_apply(Stokes* S, int l, const double* x, double* y, hipStream_t s) {
+  StokesLevel& L = S->L(l);
+  hipLaunchKernelGGL((ks_resid<double, 0>), dim3(blocks_for(L.ndof)), dim3(kSNT), 0, s, L.ndof, L.A_rp, L.A_col,
+                     (const double*)L.A_val, (const double*)nullptr, x, y, (const double*)nullptr, (double*)nullptr);
+  return hipGetLastError();
+}
+
+hipError_t stokes_residual(Stokes* S, int l, const double* f, const double* x, double* r, double* part,
+                           int norm_mode, int* nparts, hipStream_t s) {
+  StokesLevel& L = S->L(l);
+  const int nb = blocks_for(L.ndof);
+  if (nparts) *nparts = nb;
+  if (!part)
+    hipLaunchKernelGGL((ks_resid<double, 0>), dim3(nb), dim3(kSNT), 0, s, L.ndof, L.A_rp, L.A_col,
+                       (const double*)L.A_val, f, x, r, (const double*)L.Ld, part);
+  else if (norm_mode == 2)
+    hipLaunchKernelGGL((ks_resid<double, 2>), dim3(nb), dim3(kSNT), 0, s, L.ndof, L.A_rp, L.A_col,
+                       (const double*)L.A_val, f, x, r, (const double*)L.Ld, part);
+  else
+    hipLaunchKernelGGL((ks_resid<double, 1>), dim3(nb), dim3(kSNT), 0, s, L.ndof, L.A_rp, L.A_col,
+                       (const double*)L.A_val, f, x, r, (const double*)L.Ld, part);
+  return hipGetLastError();
+}
+
+hipError_t stokes_vnorm(Stokes* S, const double* v, double* part, int norm_mode, int* nparts, hipStream_t s) {
+  StokesLevel& L = S->lv.back();
+  const int nb = blocks_for(L.ndof);
+  *nparts = nb;
+  if (norm_mode == 2)
+    hipLaunchKernelGGL((ks_vnorm<2>), dim3(nb), dim3(kSNT), 0, s, L.ndof, v, (const double*)L.Ld, part);
+  else
+    hipLaunchKernelGGL((ks_vnorm<1>), dim3(nb), dim3(kSNT), 0, s, L.ndof, v, (const double*)L.Ld, part);
+  return hipGetLastError();
+}
+
+hipError_t stokes_smooth(Stokes* S, int l, double* x, double* r, int steps, hipStream_t s) {
+  return s_smooth<double>(S, S->L(l), x, r, steps, s);
+}
+
+hipError_t stokes_restrict(Stokes* S, int l, const double* r, double* fc, hipStream_t s) {
+  StokesLevel& L = S->L(l);
+  StokesLevel& C = S->L(l - 1);
+  hipLaunchKernelGGL((ks_spmv<double, 0>), dim3(blocks_for(C.ndof)), dim3(kSNT), 0, s, C.ndof, L.R_rp, L.R_col,
+                     (const double*)L.R_val, r, fc, (double*)nullptr, (double*)nullptr);
+  return hipGetLastError();
+}
+
+hipError_t stokes_prolong_add(Stokes* S, int l, const double* xc, double* x, hipStream_t s) {
+  StokesLevel& L = S->L(l);
+  hipLaunchKernelGGL((ks_spmv<double, 1>), dim3(blocks_for(L.ndof)), dim3(kSNT), 0, s, L.ndof, L.P_rp, L.P_col,
+                     (const double*)L.P_val, xc, x, (double*)nullptr, (double*)nullptr);
+  return hipGetLastError();
+}
+
+hipError_t stokes_coarse_solve(Stokes* S, const double* f, double* x, hipStream_t s) {
+  return s_coarse<double>(S, f, x, s);
+}
+
+hipError_t stokes_project(Stokes* S, int l, double* x, hipStream_t s) { return s_project<double>(S, S->L(l), x, s); }
+
+// one FP64 cycle on the finest level with r current, then the mean projection
+hipError_t stokes_cycle(Stokes* S, const double* f, double* x, double* r, bool current, hipStream_t s) {
+  SCHK(s_cycle<double>(S, S->level, f, x, r, current, s));
+  return s_project<double>(S, S->lv.back(), x, s);
+}
+
+double* stokes_fine_r(Stokes* S) { return S->lv.back().r; }
+
+// one refinement step: FP32 cycle from zero on the scaled FP64 residual r
+// (||r||^2 in nrm2 on the device), x += s c in FP64, then the mean
+// projection of the FP64 iterate
+hipError_t stokes_ir_step(Stokes* S, double* x, hipStream_t s, const double* nrm2) {
+  StokesLevel& L = S->lv.back();
+  const size_t n = L.ndof;
+  SCHK(launch_to_f32_scaled(L.r, n, nrm2, L.f32, L.r32, s));
+  SCHK(launch_zero_f32(L.x32, n, s));
+  SCHK(s_cycle<float>(S, S->level, L.f32, L.x32, L.r32, true, s));
+  SCHK(launch_axpy_f32(L.x32, n, nrm2, x, s));
+  return s_project<double>(S, L, x, s);
+}
+
+}  // namespace mgk

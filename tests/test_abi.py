@@ -56,12 +56,19 @@ def test_setup_rejects_alpha(alpha):
     assert st == mg.MG_EINVAL and not h.value
 
 
-@pytest.mark.parametrize("field,value", [("smoother", 4), ("smoother", -1), ("gamma", 0), ("gamma", 3),
+@pytest.mark.parametrize("field,value", [("smoother", 5), ("smoother", -1), ("gamma", 0), ("gamma", 3),
                                          ("tau", 2.5), ("tau", math.nan), ("coarse_level", 0),
                                          ("coarse_level", 4), ("precision", 2), ("nu1", -1), ("max_cycles", -5),
                                          ("inner_cycles", 0), ("norm", 2), ("norm", -1)])
 def test_setup_rejects_options(field, value):
     assert _setup(**{field: value})[0] == mg.MG_EINVAL
+
+
+@pytest.mark.parametrize("problem,field,value", [(0, "smoother", 4), (1, "smoother", 3), (1, "coarse_level", 3)])
+def test_setup_unsupported_combinations(problem, field, value):
+    # patch smoother is Stokes-only, collective point smoother Poisson-only; the
+    # bordered Stokes coarse solve holds at most 248 unknowns (coarse level <= 2)
+    assert _setup(level=5, problem=problem, **{field: value})[0] == mg.MG_EUNSUPPORTED
 
 
 def test_setup_rejects_level_not_above_coarse():
