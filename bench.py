@@ -29,6 +29,9 @@ METRIC = "V-cycles/s and HBM GB/s at 2049^2 Poisson control; time to rel. residu
 # (FETCH_SIZE, WRITE_SIZE) in separate profiler runs and recorded, together
 # with a hash of the sources the kernel is built from, in TRAFFIC_RECORD; the
 # figure is reported only while those sources are unchanged.
+# what the sweep kernel is built from: its source, the level descriptors of
+# the internal header (the part before the launcher declarations) and the
+# compiler flags
 SWEEP_SOURCES = ("paper_1502_03917_amd/csrc/sweep.hip", "paper_1502_03917_amd/csrc/mg_internal.hpp",
                  "paper_1502_03917_amd/build.py")
 TRAFFIC_RECORD = os.path.join(ROOT, "profiles", "lsgs_sweep_2049sq_traffic.txt")
@@ -56,8 +59,14 @@ def words_per_cycle(level: int, coarse: int, nu1: int, nu2: int, sweep_words: fl
 def sweep_source_hash() -> str:
     h = hashlib.sha256()
     for rel in SWEEP_SOURCES:
-        with open(os.path.join(ROOT, rel), "rb") as fh:
-            h.update(fh.read())
+        with open(os.path.join(ROOT, rel)) as fh:
+            text = fh.read()
+        if rel.endswith("mg_internal.hpp"):
+            text = text.split("// ---- batched launches")[0]
+        elif rel.endswith("build.py"):
+            text = text[text.index("FLAGS = ["):]
+            text = text[: text.index("]") + 1]
+        h.update(text.encode())
     return h.hexdigest()[:16]
 
 
@@ -117,18 +126,12 @@ def counter_summary(directory: str):
     return {k: (n, v / n) for k, (n, v) in agg.items()}
 
 
-def finest_sweep_grid(level: int, precision: str, cus: int = 256) -> int:
-    """Work-items launched by the finest-level sweep (512-wide workgroups,
-    48 x 48 tiles): FP64 with two or more full rounds of tiles runs persistent
-    with balanced rounds, otherwise one workgroup per tile; grids are rounded
-    up to a multiple of 8."""
+def finest_sweep_grid(level: int, precision: str) -> int:
+    """Work-items launched by the finest-level sweep: one workgroup per
+    48 x 48 tile (1024 threads in FP64, 512 in FP32), the workgroup count
+    rounded up to a multiple of 8."""
     side = -(-((1 << level) + 1) // 48)
-    tiles = side * side
-    r8 = lambda v: -(-v // 8) * 8
-    if precision == "fp64" and tiles >= 2 * cus:
-        rounds = -(-tiles // cus)
-        return 512 * r8(-(-tiles // rounds))
-    return 512 * r8(tiles)
+    return (1024 if precision == "fp64" else 512) * (-(-side * side // 8) * 8)
 
 
 def print_summary(args) -> int:
@@ -250,6 +253,44 @@ def batch_measure(steps: int, tol: float):
     return out
 
 
+def stokes_measure(steps: int, tol: float, level: int = 9):
+    """Stokes control (Taylor-Hood) on 513^2 vertices (4,712,454 unknowns),
+    desired velocity from a seeded stream function (seed 7), V(2,2) cycles
+    from x = 0 to relative residual tol: LSGS in FP64 and FP32 refinement for
+    alpha in {1e-2, 1e-6}, and the patch smoother (FP64, alpha = 1e-2)."""
+    import torch
+
+    import paper_1502_03917_amd as mg
+    import workloads
+
+    vd = torch.from_numpy(workloads.desired_velocity(level, 7)).cuda()
+    out = {"workload": f"Stokes control, {(1 << level) + 1}^2 vertices, Taylor-Hood, V(2,2), tol {tol:g}"}
+    runs = [("lsgs", "fp64", 1e-2), ("lsgs", "fp32_ir", 1e-2), ("lsgs", "fp64", 1e-6), ("lsgs", "fp32_ir", 1e-6),
+            ("vanka", "fp64", 1e-2)]
+    for sm, pr, al in runs:
+        t0 = time.perf_counter()
+        s = mg.Solver(level, al, problem="stokes", smoother=sm, precision=pr)
+        setup = time.perf_counter() - t0
+        n = s.vec_len()
+        x = torch.zeros(n, dtype=torch.float64, device="cuda")
+        f = s.rhs(vd)
+        s.solve(f, x, tol=tol, raise_on_error=False)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        cyc = 0
+        for _ in range(steps):
+            x.zero_()
+            _, it, rel, st = s.solve(f, x, tol=tol, raise_on_error=False)
+            cyc += it
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / steps
+        s.close()
+        out[f"{sm}/{pr}/alpha={al:g}"] = {
+            "unknowns": n, "cycles": cyc / steps, "ms_per_solve": 1e3 * dt, "vcycles_per_s": cyc / steps / dt,
+            "final_relres": rel, "status": mg.lib().mg_strerror(st).decode(), "setup_s": setup}
+    return out
+
+
 def cpu_baseline(level: int, alpha: float, seed: int, smoother: str, cycles: int):
     import numpy as np
 
@@ -283,6 +324,8 @@ def main() -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batch", action="store_true", help="skip the 64-instance batched solve")
     ap.add_argument("--batch-only", action="store_true", help="run only the 64-instance batched solve")
+    ap.add_argument("--no-stokes", action="store_true", help="skip the Stokes-control solves")
+    ap.add_argument("--stokes-only", action="store_true", help="run only the Stokes-control solves")
     ap.add_argument("--variants", action="store_true", help="also time the other smoother/precision/alpha variants")
     ap.add_argument("--copy-probe", action="store_true", help="run only the plain copy that calibrates the counters")
     ap.add_argument("--trace", help="summarise a rocprofv3 kernel-trace CSV directory and exit")
@@ -310,6 +353,9 @@ def main() -> int:
     torch.cuda.set_device(0)
     if args.copy_probe:
         return copy_probe()
+    if args.stokes_only:
+        print(json.dumps(stokes_measure(max(1, args.steps // 5), args.tol)), flush=True)
+        return 0
     if args.batch_only:
         print(json.dumps(batch_measure(max(2, args.steps // 3), args.tol)), flush=True)
         return 0
@@ -408,6 +454,9 @@ def main() -> int:
     if not args.no_batch:
         log("bench: batched solve of 64 instances (fp32_ir)")
         result["batch"] = batch_measure(max(2, args.steps // 3), args.tol)
+    if not args.no_stokes:
+        log("bench: Stokes-control solves (513^2 vertices)")
+        result["stokes"] = stokes_measure(max(1, args.steps // 5), args.tol)
     if not args.no_cpu_baseline:
         log(f"bench: CPU oracle baseline ({args.cpu_cycles} cycles)")
         result["cpu_baseline"] = cpu_baseline(args.level, args.alpha, args.seed, args.smoother, args.cpu_cycles)

@@ -392,8 +392,9 @@ void colour_groups(int n, std::vector<int2>& grp, std::vector<int>& ph) {
 }
 
 // Patches of the patch smoother (one per vertex) with the LU factors of their
-// matrices; patches listed by colour (i mod 3) + 3 (j mod 3), phase k spans
-// order[ph[k] .. ph[k+1]).
+// matrices and the row permutation of the pivoting (piv[dptr[q] + k] = the
+// patch row that ends in position k); patches listed by colour
+// (i mod 3) + 3 (j mod 3), phase k spans order[ph[k] .. ph[k+1]).
 bool build_patches(int n, const HCsr& A, std::vector<int>& dptr, std::vector<int>& dof, std::vector<int>& piv,
                    std::vector<long long>& luptr, std::vector<double>& lu, std::vector<int>& order,
                    std::vector<int>& ph, std::string* err) {
@@ -454,6 +455,12 @@ bool build_patches(int n, const HCsr& A, std::vector<int>& dptr, std::vector<int
         *err = "stokes: singular patch matrix";
         return false;
       }
+      // the row swaps of the factorisation as one permutation: after them,
+      // position k holds the entry that started at pm[k]
+      std::vector<int> pm(msz);
+      for (int k = 0; k < msz; k++) pm[k] = k;
+      for (int k = 0; k < msz; k++) std::swap(pm[k], pm[pv[k]]);
+      pv = pm;
       dptr[q + 1] = dptr[q] + msz;
       luptr[q + 1] = luptr[q] + (long long)msz * msz;
       dof.insert(dof.end(), d.begin(), d.end());
@@ -490,27 +497,44 @@ __device__ inline void block_store(double v, double* out) {
   }
 }
 
-// r = f - A x (MODE 0), with per-block partial sums of ||r||_2^2 (1) or
-// r^T L^-1 r (2); f == nullptr gives r = A x
+// Row kernels: 16 lanes per CSR row (16 rows per 256-thread block), each lane
+// taking every 16th entry, partial sums combined by shuffles.
+constexpr int kRL = 16;
+constexpr int kRows = kSNT / kRL;
+
+template <typename T>
+__device__ inline T row_sum(T v) {
+#pragma unroll
+  for (int o = kRL / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, kRL);
+  return v;
+}
+
+// r = f - A x, with per-block partial sums of ||r||_2^2 (MODE 1) or
+// r^T L^-1 r (MODE 2); f == nullptr gives r = A x
 template <typename T, int MODE>
 __global__ __launch_bounds__(kSNT) void ks_resid(int n, const int* __restrict__ rp, const int* __restrict__ col,
                                                  const T* __restrict__ val, const T* __restrict__ f,
                                                  const T* __restrict__ x, T* __restrict__ r,
                                                  const double* __restrict__ Ld, double* __restrict__ part) {
-  const int i = blockIdx.x * kSNT + threadIdx.x;
+  const int ln = threadIdx.x % kRL;
   double s2 = 0.0;
-  if (i < n) {
+  for (int i0 = blockIdx.x * kRows; i0 < n; i0 += gridDim.x * kRows) {  // uniform per block
+    const int i = i0 + threadIdx.x / kRL;
     T s = 0;
-    for (int k = rp[i]; k < rp[i + 1]; k++) s += val[k] * x[col[k]];
-    const T ri = f ? f[i] - s : s;
-    r[i] = ri;
-    if (MODE == 1) s2 = (double)ri * (double)ri;
-    if (MODE == 2) s2 = (double)ri * (double)ri / Ld[i];
+    if (i < n)
+      for (int k = rp[i] + ln; k < rp[i + 1]; k += kRL) s += val[k] * x[col[k]];
+    s = row_sum(s);
+    if (i < n && ln == 0) {
+      const T ri = f ? f[i] - s : s;
+      r[i] = ri;
+      if (MODE == 1) s2 += (double)ri * (double)ri;
+      if (MODE == 2) s2 += (double)ri * (double)ri / Ld[i];
+    }
   }
   if (MODE) block_store(s2, &part[blockIdx.x]);
 }
 
-// per-block partial sums of ||v||^2 (MODE 1) or v^T L^-1 v (MODE 2)
+// per-block partial sums of ||v||^2 (MODE 1) or v^T L^-1 v (MODE 2), one thread per entry
 template <int MODE>
 __global__ __launch_bounds__(kSNT) void ks_vnorm(int n, const double* __restrict__ v, const double* __restrict__ Ld,
                                                  double* __restrict__ part) {
@@ -525,16 +549,21 @@ template <typename T, int ADD>
 __global__ __launch_bounds__(kSNT) void ks_spmv(int n, const int* __restrict__ rp, const int* __restrict__ col,
                                                 const T* __restrict__ val, const T* __restrict__ x, T* __restrict__ y,
                                                 T* __restrict__ zero_out, T* __restrict__ copy_out) {
-  const int i = blockIdx.x * kSNT + threadIdx.x;
-  if (i >= n) return;
-  T s = 0;
-  for (int k = rp[i]; k < rp[i + 1]; k++) s += val[k] * x[col[k]];
-  if (ADD) {
-    y[i] += s;
-  } else {
-    y[i] = s;
-    if (zero_out) zero_out[i] = (T)0;
-    if (copy_out) copy_out[i] = s;
+  const int ln = threadIdx.x % kRL;
+  for (int i0 = blockIdx.x * kRows; i0 < n; i0 += gridDim.x * kRows) {
+    const int i = i0 + threadIdx.x / kRL;
+    T s = 0;
+    if (i < n)
+      for (int k = rp[i] + ln; k < rp[i + 1]; k += kRL) s += val[k] * x[col[k]];
+    s = row_sum(s);
+    if (i >= n || ln != 0) continue;
+    if (ADD) {
+      y[i] += s;
+    } else {
+      y[i] = s;
+      if (zero_out) zero_out[i] = (T)0;
+      if (copy_out) copy_out[i] = s;
+    }
   }
 }
 
@@ -543,81 +572,121 @@ template <typename T>
 __global__ __launch_bounds__(kSNT) void ks_ne_p(int n, const int* __restrict__ rp, const int* __restrict__ col,
                                                 const T* __restrict__ val, const T* __restrict__ Linv, T tau,
                                                 const T* __restrict__ r, T* __restrict__ x, T* __restrict__ p) {
-  const int i = blockIdx.x * kSNT + threadIdx.x;
-  if (i >= n) return;
-  T q = 0;
-  for (int k = rp[i]; k < rp[i + 1]; k++) q += val[k] * Linv[col[k]] * r[col[k]];
-  const T pi = tau * q * Linv[i];
-  p[i] = pi;
-  x[i] += pi;
+  const int ln = threadIdx.x % kRL;
+  for (int i0 = blockIdx.x * kRows; i0 < n; i0 += gridDim.x * kRows) {
+    const int i = i0 + threadIdx.x / kRL;
+    T q = 0;
+    if (i < n)
+      for (int k = rp[i] + ln; k < rp[i + 1]; k += kRL) q += val[k] * Linv[col[k]] * r[col[k]];
+    q = row_sum(q);
+    if (i >= n || ln != 0) continue;
+    const T pi = tau * q * Linv[i];
+    p[i] = pi;
+    x[i] += pi;
+  }
 }
 
 // Alg. 1, second loop: r -= A p (A symmetric: row i holds the column)
 template <typename T>
 __global__ __launch_bounds__(kSNT) void ks_ne_r(int n, const int* __restrict__ rp, const int* __restrict__ col,
                                                 const T* __restrict__ val, const T* __restrict__ p, T* __restrict__ r) {
-  const int i = blockIdx.x * kSNT + threadIdx.x;
-  if (i >= n) return;
-  T s = 0;
-  for (int k = rp[i]; k < rp[i + 1]; k++) s += val[k] * p[col[k]];
-  r[i] -= s;
+  const int ln = threadIdx.x % kRL;
+  for (int i0 = blockIdx.x * kRows; i0 < n; i0 += gridDim.x * kRows) {
+    const int i = i0 + threadIdx.x / kRL;
+    T s = 0;
+    if (i < n)
+      for (int k = rp[i] + ln; k < rp[i + 1]; k += kRL) s += val[k] * p[col[k]];
+    s = row_sum(s);
+    if (i < n && ln == 0) r[i] -= s;
+  }
 }
 
 // One colour phase of Alg. 2: every group (two unknowns whose entry of
 // N = A^T L^-1 A is zero) takes both q from the residual, updates x, and
 // subtracts A_ji p_i from r; groups of a phase share no residual entry.
+// One wave per group: each half-wave gathers one row (32 lanes), then the two
+// rows are scattered one after the other (they touch the same entries of r).
+constexpr int kHalf = 32;
+
+template <typename T>
+__device__ inline T half_sum(T v) {
+#pragma unroll
+  for (int o = kHalf / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, kHalf);
+  return v;
+}
+
 template <typename T>
 __global__ __launch_bounds__(kSNT) void ks_lsgs(int g0, int ng, const int2* __restrict__ grp,
                                                 const int* __restrict__ rp, const int* __restrict__ col,
                                                 const T* __restrict__ val, const T* __restrict__ Linv,
                                                 const T* __restrict__ Ninv, T* __restrict__ x, T* __restrict__ r) {
-  const int g = blockIdx.x * kSNT + threadIdx.x;
-  if (g >= ng) return;
+  const int g = blockIdx.x * (kSNT / 64) + threadIdx.x / 64;
+  if (g >= ng) return;  // uniform per wave
+  const int lane = threadIdx.x % 64, half = lane / kHalf, ln = lane % kHalf;
   const int2 u = grp[g0 + g];
-  T q1 = 0, q2 = 0;
-  for (int k = rp[u.x]; k < rp[u.x + 1]; k++) q1 += val[k] * Linv[col[k]] * r[col[k]];
-  for (int k = rp[u.y]; k < rp[u.y + 1]; k++) q2 += val[k] * Linv[col[k]] * r[col[k]];
-  const T p1 = q1 * Ninv[u.x], p2 = q2 * Ninv[u.y];
-  x[u.x] += p1;
-  x[u.y] += p2;
-  for (int k = rp[u.x]; k < rp[u.x + 1]; k++) r[col[k]] -= val[k] * p1;
-  for (int k = rp[u.y]; k < rp[u.y + 1]; k++) r[col[k]] -= val[k] * p2;
+  const int row = half ? u.y : u.x;
+  const int kb = rp[row], ke = rp[row + 1];
+  T q = 0;
+  for (int k = kb + ln; k < ke; k += kHalf) q += val[k] * Linv[col[k]] * r[col[k]];
+  q = half_sum(q);
+  const T pv = q * Ninv[row];
+  if (ln == 0) x[row] += pv;
+  if (half == 0)
+    for (int k = kb + ln; k < ke; k += kHalf) r[col[k]] -= val[k] * pv;
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+  if (half == 1)
+    for (int k = kb + ln; k < ke; k += kHalf) r[col[k]] -= val[k] * pv;
 }
 
 // One colour phase of the patch smoother: x_P += tau A_PP^-1 r_P,
-// r -= tau A_{:,P} A_PP^-1 r_P (LU factors of A_PP with row pivots, FP64)
+// r -= tau A_{:,P} A_PP^-1 r_P, with the LU factors of A_PP (row-major,
+// FP64) and the row permutation of its pivoting.  One wave per patch: lane c
+// keeps column c of the factors in registers and entry c of the vector; the
+// substitutions reduce over the wave; the patch rows are then subtracted from
+// r one after the other (rows of one patch share entries of r).
 template <typename T>
-__global__ __launch_bounds__(64) void ks_vanka(int p0, int npatch, const int* __restrict__ order,
-                                               const int* __restrict__ dptr, const int* __restrict__ dof,
-                                               const long long* __restrict__ luptr, const double* __restrict__ lu,
-                                               const int* __restrict__ piv, const int* __restrict__ rp,
-                                               const int* __restrict__ col, const T* __restrict__ val, double tau,
-                                               T* __restrict__ x, T* __restrict__ r) {
-  const int t = blockIdx.x * 64 + threadIdx.x;
-  if (t >= npatch) return;
+__global__ __launch_bounds__(kSNT) void ks_vanka(int p0, int npatch, const int* __restrict__ order,
+                                                 const int* __restrict__ dptr, const int* __restrict__ dof,
+                                                 const long long* __restrict__ luptr, const double* __restrict__ lu,
+                                                 const int* __restrict__ perm, const int* __restrict__ rp,
+                                                 const int* __restrict__ col, const T* __restrict__ val, double tau,
+                                                 T* __restrict__ x, T* __restrict__ r) {
+  const int t = blockIdx.x * (kSNT / 64) + threadIdx.x / 64;
+  if (t >= npatch) return;  // uniform per wave
+  const int c = threadIdx.x % 64;
   const int q = order[p0 + t];
   const int b = dptr[q], m = dptr[q + 1] - b;
   const double* a = lu + luptr[q];
-  const int* pv = piv + b;
-  double y[kMaxPatch];
-  for (int u = 0; u < m; u++) y[u] = (double)r[dof[b + u]];
-  for (int k = 0; k < m; k++)
-    if (pv[k] != k) {
-      const double s = y[k];
-      y[k] = y[pv[k]];
-      y[pv[k]] = s;
-    }
-  for (int i = 1; i < m; i++)
-    for (int c = 0; c < i; c++) y[i] -= a[i * m + c] * y[c];
-  for (int i = m - 1; i >= 0; i--) {
-    for (int c = i + 1; c < m; c++) y[i] -= a[i * m + c] * y[c];
-    y[i] /= a[i * m + i];
+  const bool on = c < m;
+  double acol[kMaxPatch];
+#pragma unroll
+  for (int i = 0; i < kMaxPatch; i++) acol[i] = (on && i < m) ? a[i * m + c] : 0.0;
+  // permuted right-hand side: entry c = r at the patch unknown perm[c]
+  double y = on ? (double)r[dof[b + perm[b + c]]] : 0.0;
+  // forward substitution with the unit lower factor (rows i >= m are inert)
+#pragma unroll
+  for (int i = 1; i < kMaxPatch; i++) {
+    double v = (c < i && i < m) ? acol[i] * y : 0.0;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    if (c == i && i < m) y -= v;
   }
+  // back substitution with the upper factor
+#pragma unroll
+  for (int i = kMaxPatch - 1; i >= 0; i--) {
+    double v = (c > i && c < m && i < m) ? acol[i] * y : 0.0;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    const double di = __shfl(acol[i], i, 64);  // diagonal entry a_ii (held by lane i)
+    if (c == i && i < m) y = (y - v) / di;
+  }
+  const T du = (T)(tau * y);
+  if (on) x[dof[b + c]] += du;
   for (int u = 0; u < m; u++) {
+    const T d = __shfl(du, u, 64);
     const int i = dof[b + u];
-    const T du = (T)(tau * y[u]);
-    x[i] += du;
-    for (int k = rp[i]; k < rp[i + 1]; k++) r[col[k]] -= val[k] * du;
+    for (int k = rp[i] + c; k < rp[i + 1]; k += 64) r[col[k]] -= val[k] * d;
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
   }
 }
 
@@ -707,6 +776,8 @@ __global__ __launch_bounds__(kSNT) void ks_rhs(int nv, int ndof, const int* __re
 }
 
 inline int blocks_for(int n, int nt = kSNT) { return (n + nt - 1) / nt; }
+// blocks of the row kernels (grid-stride over groups of kRows rows)
+inline int row_blocks(int n) { return std::min(blocks_for(n, kRows), 4096); }
 
 template <typename T>
 struct Dev {
@@ -949,7 +1020,7 @@ struct SV<float> {
 
 template <typename T>
 hipError_t s_resid(StokesLevel& L, const T* f, const T* x, T* r, hipStream_t s) {
-  hipLaunchKernelGGL((ks_resid<T, 0>), dim3(blocks_for(L.ndof)), dim3(kSNT), 0, s, L.ndof, L.A_rp, L.A_col,
+  hipLaunchKernelGGL((ks_resid<T, 0>), dim3(row_blocks(L.ndof)), dim3(kSNT), 0, s, L.ndof, L.A_rp, L.A_col,
                      SV<T>::A(L), f, x, r, (const double*)nullptr, (double*)nullptr);
   return hipGetLastError();
 }
@@ -960,9 +1031,9 @@ hipError_t s_smooth(Stokes* S, StokesLevel& L, T* x, T* r, int steps, hipStream_
   for (int it = 0; it < steps; it++) {
     switch (S->smoother) {
       case MG_NE:
-        hipLaunchKernelGGL((ks_ne_p<T>), dim3(blocks_for(L.ndof)), dim3(kSNT), 0, s, L.ndof, L.A_rp, L.A_col, A,
+        hipLaunchKernelGGL((ks_ne_p<T>), dim3(row_blocks(L.ndof)), dim3(kSNT), 0, s, L.ndof, L.A_rp, L.A_col, A,
                            SV<T>::Linv(L), (T)S->tau, (const T*)r, x, SV<T>::p(L));
-        hipLaunchKernelGGL((ks_ne_r<T>), dim3(blocks_for(L.ndof)), dim3(kSNT), 0, s, L.ndof, L.A_rp, L.A_col, A,
+        hipLaunchKernelGGL((ks_ne_r<T>), dim3(row_blocks(L.ndof)), dim3(kSNT), 0, s, L.ndof, L.A_rp, L.A_col, A,
                            (const T*)SV<T>::p(L), r);
         break;
       case MG_LSGS:
@@ -973,7 +1044,7 @@ hipError_t s_smooth(Stokes* S, StokesLevel& L, T* x, T* r, int steps, hipStream_
           for (int k = 0; k < nph; k++) {
             const int ph = sw == 0 ? k : nph - 1 - k;
             const int g0 = L.gph[ph], ng = L.gph[ph + 1] - g0;
-            hipLaunchKernelGGL((ks_lsgs<T>), dim3(blocks_for(ng)), dim3(kSNT), 0, s, g0, ng,
+            hipLaunchKernelGGL((ks_lsgs<T>), dim3(blocks_for(ng, kSNT / 64)), dim3(kSNT), 0, s, g0, ng,
                                (const int2*)L.groups, L.A_rp, L.A_col, A, SV<T>::Linv(L), SV<T>::Ninv(L), x, r);
           }
         break;
@@ -981,7 +1052,7 @@ hipError_t s_smooth(Stokes* S, StokesLevel& L, T* x, T* r, int steps, hipStream_
       case MG_VANKA:
         for (int ph = 0; ph + 1 < (int)L.vph.size(); ph++) {
           const int p0 = L.vph[ph], npch = L.vph[ph + 1] - p0;
-          hipLaunchKernelGGL((ks_vanka<T>), dim3(blocks_for(npch, 64)), dim3(64), 0, s, p0, npch, L.v_order,
+          hipLaunchKernelGGL((ks_vanka<T>), dim3(blocks_for(npch, kSNT / 64)), dim3(kSNT), 0, s, p0, npch, L.v_order,
                              L.v_dptr, L.v_dof, L.v_luptr, L.v_lu, L.v_piv, L.A_rp, L.A_col, A, S->tau, x, r);
         }
         break;
@@ -1020,13 +1091,13 @@ hipError_t s_cycle(Stokes* S, int l, const T* f, T* x, T* r, bool current, hipSt
   if (!current) SCHK(s_resid<T>(L, f, x, r, s));
   SCHK(s_smooth<T>(S, L, x, r, S->nu1, s));
   const bool to_k0 = (l - 1 == S->k0);
-  hipLaunchKernelGGL((ks_spmv<T, 0>), dim3(blocks_for(C.ndof)), dim3(kSNT), 0, s, C.ndof, L.R_rp, L.R_col,
+  hipLaunchKernelGGL((ks_spmv<T, 0>), dim3(row_blocks(C.ndof)), dim3(kSNT), 0, s, C.ndof, L.R_rp, L.R_col,
                      SV<T>::R(L), (const T*)r, SV<T>::f(C), to_k0 ? (T*)nullptr : SV<T>::x(C),
                      to_k0 ? (T*)nullptr : SV<T>::r(C));
   SCHK(hipGetLastError());
   for (int g = 0; g < S->gamma; g++)
     SCHK(s_cycle<T>(S, l - 1, SV<T>::f(C), SV<T>::x(C), SV<T>::r(C), g == 0, s));
-  hipLaunchKernelGGL((ks_spmv<T, 1>), dim3(blocks_for(L.ndof)), dim3(kSNT), 0, s, L.ndof, L.P_rp, L.P_col,
+  hipLaunchKernelGGL((ks_spmv<T, 1>), dim3(row_blocks(L.ndof)), dim3(kSNT), 0, s, L.ndof, L.P_rp, L.P_col,
                      SV<T>::P(L), (const T*)SV<T>::x(C), x, (T*)nullptr, (T*)nullptr);
   SCHK(hipGetLastError());
   SCHK(s_resid<T>(L, f, x, r, s));
@@ -1077,7 +1148,10 @@ size_t stokes_len(const Stokes* S, int level) {
   return (size_t)S->lv[level - S->k0].ndof;
 }
 
-size_t stokes_partials(const Stokes* S) { return (size_t)blocks_for(S->lv.back().ndof); }
+size_t stokes_partials(const Stokes* S) {
+  const int n = S->lv.back().ndof;
+  return (size_t)std::max(blocks_for(n), row_blocks(n));
+}
 
 void stokes_set(Stokes* S, const mg_opts& o) {
   S->nu1 = o.nu1;
@@ -1095,7 +1169,7 @@ hipError_t stokes_rhs(Stokes* S, const double* vd, double* f, hipStream_t s) {
 
 hipError_t stokes_apply(Stokes* S, int l, const double* x, double* y, hipStream_t s) {
   StokesLevel& L = S->L(l);
-  hipLaunchKernelGGL((ks_resid<double, 0>), dim3(blocks_for(L.ndof)), dim3(kSNT), 0, s, L.ndof, L.A_rp, L.A_col,
+  hipLaunchKernelGGL((ks_resid<double, 0>), dim3(row_blocks(L.ndof)), dim3(kSNT), 0, s, L.ndof, L.A_rp, L.A_col,
                      (const double*)L.A_val, (const double*)nullptr, x, y, (const double*)nullptr, (double*)nullptr);
   return hipGetLastError();
 }
@@ -1103,7 +1177,7 @@ hipError_t stokes_apply(Stokes* S, int l, const double* x, double* y, hipStream_
 hipError_t stokes_residual(Stokes* S, int l, const double* f, const double* x, double* r, double* part,
                            int norm_mode, int* nparts, hipStream_t s) {
   StokesLevel& L = S->L(l);
-  const int nb = blocks_for(L.ndof);
+  const int nb = row_blocks(L.ndof);
   if (nparts) *nparts = nb;
   if (!part)
     hipLaunchKernelGGL((ks_resid<double, 0>), dim3(nb), dim3(kSNT), 0, s, L.ndof, L.A_rp, L.A_col,
@@ -1135,14 +1209,14 @@ hipError_t stokes_smooth(Stokes* S, int l, double* x, double* r, int steps, hipS
 hipError_t stokes_restrict(Stokes* S, int l, const double* r, double* fc, hipStream_t s) {
   StokesLevel& L = S->L(l);
   StokesLevel& C = S->L(l - 1);
-  hipLaunchKernelGGL((ks_spmv<double, 0>), dim3(blocks_for(C.ndof)), dim3(kSNT), 0, s, C.ndof, L.R_rp, L.R_col,
+  hipLaunchKernelGGL((ks_spmv<double, 0>), dim3(row_blocks(C.ndof)), dim3(kSNT), 0, s, C.ndof, L.R_rp, L.R_col,
                      (const double*)L.R_val, r, fc, (double*)nullptr, (double*)nullptr);
   return hipGetLastError();
 }
 
 hipError_t stokes_prolong_add(Stokes* S, int l, const double* xc, double* x, hipStream_t s) {
   StokesLevel& L = S->L(l);
-  hipLaunchKernelGGL((ks_spmv<double, 1>), dim3(blocks_for(L.ndof)), dim3(kSNT), 0, s, L.ndof, L.P_rp, L.P_col,
+  hipLaunchKernelGGL((ks_spmv<double, 1>), dim3(row_blocks(L.ndof)), dim3(kSNT), 0, s, L.ndof, L.P_rp, L.P_col,
                      (const double*)L.P_val, xc, x, (double*)nullptr, (double*)nullptr);
   return hipGetLastError();
 }

@@ -60,14 +60,11 @@ __device__ inline void bstore(__amdgpu_buffer_rsrc_t r, unsigned off, float v) {
 template <int TW>
 struct TileGeom {
   static constexpr int RMAX = TW + 2 * kHalo;  // widest / tallest region
-  static constexpr int RP = RMAX + 2;          // pitch with one guard cell each side
+  static constexpr int RP = RMAX + 3;          // pitch: one guard cell each side, one pad cell
   static constexpr int RN = RP * (RMAX + 2);   // region cells with guard rows
 };
 
-// PERSIST: fewer workgroups than tiles; each loops over tiles (round r takes
-// tile r * gridDim.x + its slot) and loads the next tile into registers while
-// the current one is computed.  Otherwise one tile per workgroup.
-template <typename T, int TW, int NT, bool PERSIST>
+template <typename T, int TW, int NT>
 __device__ __forceinline__ void lsgs_tile_body(const Lev& L, int ntx, int nty, int reverse, T* __restrict__ x,
                                                const T* __restrict__ rin, T* __restrict__ rout) {
   using G = TileGeom<TW>;
@@ -89,10 +86,8 @@ __device__ __forceinline__ void lsgs_tile_body(const Lev& L, int ntx, int nty, i
 
   // The workgroups of one XCD (bid % 8) take a contiguous run of tiles, which
   // share halo rows in that XCD's L2 (the grid is a multiple of 8).
-  const int slot = (nblk % 8 == 0) ? (bid % 8) * (nblk / 8) + bid / 8 : bid;
-  const int nrounds = PERSIST ? (ntiles + nblk - 1) / nblk : 1;
-  auto tile_of = [&](int round) { return round * nblk + slot; };
-  if (slot >= ntiles) return;  // padding workgroup
+  const int tile = (nblk % 8 == 0) ? (bid % 8) * (nblk / 8) + bid / 8 : bid;
+  if (tile >= ntiles) return;  // padding workgroup
   struct Box {
     int i0, i1, j0, j1, ci0, ci1, rj0, rj1;
   };
@@ -165,30 +160,17 @@ __device__ __forceinline__ void lsgs_tile_body(const Lev& L, int ntx, int nty, i
     for (int q = 0; q < NC; q++)
       if (tid + q * NT < 25 * kC5) tC[tid + q * NT] = (T)v[q];
   }
-  fetch(tile_of(0));
-  stash(tile_of(0));
+  fetch(tile);
+  stash(tile);
   lds_barrier();
 
   const T Mc = (T)L.Mc, Mo = (T)L.Mo, Kc = (T)L.Kc, Ka = (T)L.Ka, Kd = (T)L.Kd, Wi = (T)L.Winv;
   const T al = (T)L.alpha, ai = (T)L.ainv, Nyi = (T)L.Nyi, Nli = (T)L.Nli;
 
-  for (int round = 0; round < nrounds; round++) {
-    const int tile = tile_of(round);
-    const bool more = PERSIST && round + 1 < nrounds && tile_of(round + 1) < ntiles;  // uniform per block
+  {
     const Box b = box_of(tile);
     const int i0 = b.i0, i1 = b.i1, j0 = b.j0, j1 = b.j1, ci0 = b.ci0, ci1 = b.ci1, rj0 = b.rj0, rj1 = b.rj1;
     const int OW = i1 - i0, OH = j1 - j0;
-    // this tile's x (registers of the previous fetch), then the next tile's
-    // loads are put in flight
-    T cxy[NX], cxl[NX];
-#pragma unroll
-    for (int q = 0; q < NX; q++) {
-      cxy[q] = xy[q];
-      cxl[q] = xl[q];
-    }
-    if constexpr (PERSIST) {
-      if (more) fetch(tile_of(round + 1));
-    }
 
     // one update of the vertex at region cell (lr, li)
     auto update = [&](int lr, int li) {
@@ -295,20 +277,16 @@ __device__ __forceinline__ void lsgs_tile_body(const Lev& L, int ntx, int nty, i
       const unsigned o2 = ok ? o + fo : kOff;
       bstore(Rout, o, sy[a]);
       bstore(Rout, o2, sl[a]);
-      bstore(Rx, o, cxy[q] + dxy[od]);
-      bstore(Rx, o2, cxl[q] + dxl[od]);
+      bstore(Rx, o, xy[q] + dxy[od]);
+      bstore(Rx, o2, xl[q] + dxl[od]);
     }
-    if (!more) break;
-    lds_barrier();
-    stash(tile_of(round + 1));
-    lds_barrier();
   }
 }
 
-template <typename T, int TW, int NT, bool PERSIST>
+template <typename T, int TW, int NT>
 __global__ __launch_bounds__(NT) void k_lsgs_tile(Lev L, int ntx, int nty, int reverse, T* __restrict__ x,
                                                   const T* __restrict__ rin, T* __restrict__ rout) {
-  lsgs_tile_body<T, TW, NT, PERSIST>(L, ntx, nty, reverse, x, rin, rout);
+  lsgs_tile_body<T, TW, NT>(L, ntx, nty, reverse, x, rin, rout);
 }
 
 // many instances of one level: instance blockIdx.y, residual read from r
@@ -317,44 +295,36 @@ template <typename T, int TW, int NT>
 __global__ __launch_bounds__(NT) void kb_lsgs_tile(const BInst<T>* __restrict__ B, int ntx, int reverse, int sel) {
   const BInst<T>& a = B[blockIdx.y];
   if (!*a.active) return;
-  lsgs_tile_body<T, TW, NT, false>(a.L, ntx, ntx, reverse, a.x, sel ? a.r2 : a.r, sel ? a.r : a.r2);
+  lsgs_tile_body<T, TW, NT>(a.L, ntx, ntx, reverse, a.x, sel ? a.r2 : a.r, sel ? a.r : a.r2);
 }
 
 inline int tiles_along(int npts, int TW) { return (npts + TW - 1) / TW; }
 
-// Grid shape.  With one workgroup resident per CU (FP64: the tile needs
-// 139 KB of LDS) and at least two full rounds of tiles, the launch is
-// persistent: the rounds are balanced (every workgroup gets the same number
-// of tiles, up to one) and the next tile's loads overlap the current tile's
-// LDS work.  Otherwise (fewer tiles, or FP32 with two workgroups per CU that
-// overlap each other) one workgroup per tile.  Grids are multiples of 8 for
-// the XCD-aware order; spare workgroups exit at once.
+// One workgroup per tile; the grid is padded to a multiple of 8 so that the
+// XCD-aware tile order applies (spare workgroups exit at once).  Workgroup
+// size per precision: FP64 tiles need 139 KB of LDS, so one workgroup fits
+// per CU and it takes 1024 threads (16 waves) to hide LDS and FP64 latency;
+// FP32 tiles need 70 KB and run as two 512-thread workgroups per CU.  (A
+// persistent grid that prefetches the next tile measured slower: its extra
+// registers limit it to 512 threads.)
 inline int round8(int v) { return (v + 7) / 8 * 8; }
 
-int cu_count() {
-  static int cus = 0;
-  if (cus == 0) {
-    int dev = 0;
-    if (hipGetDevice(&dev) != hipSuccess ||
-        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0)
-      cus = 256;
-  }
-  return cus;
-}
+template <typename T>
+struct SweepShape;
+template <>
+struct SweepShape<double> {
+  static constexpr int NT = 1024;
+};
+template <>
+struct SweepShape<float> {
+  static constexpr int NT = 512;
+};
 
-template <typename T, int TW, int NT>
-hipError_t launch_tile_cfg(const Lev& L, bool allow_persistent, int reverse, T* x, const T* rin, T* rout,
-                           hipStream_t s) {
-  const int nt = tiles_along(L.n + 1, TW);
-  const int tiles = nt * nt, resident = cu_count();
-  if (allow_persistent && tiles >= 2 * resident) {
-    const int rounds = (tiles + resident - 1) / resident;
-    const int nblk = round8((tiles + rounds - 1) / rounds);
-    hipLaunchKernelGGL((k_lsgs_tile<T, TW, NT, true>), dim3(nblk), dim3(NT), 0, s, L, nt, nt, reverse, x, rin, rout);
-  } else {
-    hipLaunchKernelGGL((k_lsgs_tile<T, TW, NT, false>), dim3(round8(tiles)), dim3(NT), 0, s, L, nt, nt, reverse, x,
-                       rin, rout);
-  }
+template <typename T>
+hipError_t launch_tile_cfg(const Lev& L, int reverse, T* x, const T* rin, T* rout, hipStream_t s) {
+  constexpr int NT = SweepShape<T>::NT;
+  const int nt = tiles_along(L.n + 1, 48);
+  hipLaunchKernelGGL((k_lsgs_tile<T, 48, NT>), dim3(round8(nt * nt)), dim3(NT), 0, s, L, nt, nt, reverse, x, rin, rout);
   return hipGetLastError();
 }
 
@@ -362,8 +332,9 @@ hipError_t launch_tile_cfg(const Lev& L, bool allow_persistent, int reverse, T* 
 
 template <typename T>
 hipError_t launch_b_lsgs_sweep(const BInst<T>* d, int count, int n, int reverse, int sel, hipStream_t s) {
+  constexpr int NT = SweepShape<T>::NT;
   const int nt = tiles_along(n + 1, 48);
-  hipLaunchKernelGGL((kb_lsgs_tile<T, 48, 512>), dim3(round8(nt * nt), count), dim3(512), 0, s, d, nt, reverse, sel);
+  hipLaunchKernelGGL((kb_lsgs_tile<T, 48, NT>), dim3(round8(nt * nt), count), dim3(NT), 0, s, d, nt, reverse, sel);
   return hipGetLastError();
 }
 template hipError_t launch_b_lsgs_sweep<double>(const BInst<double>*, int, int, int, int, hipStream_t);
@@ -372,13 +343,13 @@ template hipError_t launch_b_lsgs_sweep<float>(const BInst<float>*, int, int, in
 template <>
 hipError_t launch_lsgs_sweep<double>(const Lev& L, int reverse, double* x, const double* rin, double* rout,
                                      hipStream_t s) {
-  return launch_tile_cfg<double, 48, 512>(L, true, reverse, x, rin, rout, s);
+  return launch_tile_cfg<double>(L, reverse, x, rin, rout, s);
 }
 
 template <>
 hipError_t launch_lsgs_sweep<float>(const Lev& L, int reverse, float* x, const float* rin, float* rout,
                                     hipStream_t s) {
-  return launch_tile_cfg<float, 48, 512>(L, false, reverse, x, rin, rout, s);
+  return launch_tile_cfg<float>(L, reverse, x, rin, rout, s);
 }
 
 }  // namespace mgk
