@@ -63,6 +63,10 @@ def sweep_source_hash() -> str:
             text = fh.read()
         if rel.endswith("mg_internal.hpp"):
             text = text.split("// ---- batched launches")[0]
+        elif rel.endswith("sweep.hip"):
+            # the batched kernel and launcher do not affect the single-instance sweep
+            text = "\n\n".join(c for c in text.split("\n\n")
+                                if "kb_lsgs_tile" not in c and "launch_b_lsgs_sweep" not in c)
         elif rel.endswith("build.py"):
             text = text[text.index("FLAGS = ["):]
             text = text[: text.index("]") + 1]
@@ -323,6 +327,7 @@ def main() -> int:
     ap.add_argument("--cpu-cycles", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batch", action="store_true", help="skip the 64-instance batched solve")
+    ap.add_argument("--no-fp32-ir", action="store_true", help="skip the FP32-refinement rerun of the main workload")
     ap.add_argument("--batch-only", action="store_true", help="run only the 64-instance batched solve")
     ap.add_argument("--no-stokes", action="store_true", help="skip the Stokes-control solves")
     ap.add_argument("--stokes-only", action="store_true", help="run only the Stokes-control solves")
@@ -442,6 +447,17 @@ def main() -> int:
                      "sweeps_timed": main_run["sweeps_timed"], "algorithmic_bytes_per_sweep": sweep_bytes,
                      "traffic_unit": "bytes per launch"},
     }
+    if args.precision == "fp64" and not args.no_fp32_ir:
+        # the same workload with FP32 cycles inside FP64 refinement (same FP64 tolerance)
+        log("bench: the same solves with FP32 cycles inside FP64 refinement")
+        ir = run(args.smoother, "fp32_ir", args.alpha, args.steps, args.warmup, timing=False)
+        ir_sweep = run(args.smoother, "fp32_ir", args.alpha, max(2, args.steps // 2), 0, timing=True)
+        ach = 8 * V * 4 / (ir_sweep["sweep_ms"] * 1e-3) / 1e9
+        result["fp32_ir"] = {"vcycles_per_s": ir["vcycles_per_s"], "ms_per_solve": ir["ms_per_solve"],
+                             "cycles_per_solve": ir["cycles_per_solve"], "final_relres": ir["relres"],
+                             "status": ir["status"], "speedup_time_to_tol_vs_fp64": main_run["ms_per_solve"] / ir["ms_per_solve"],
+                             "finest_sweep_ms": ir_sweep["sweep_ms"], "finest_sweep_GBps": ach,
+                             "finest_sweep_frac_of_8TBps": ach / HBM_PEAK_GBS}
     if args.variants:
         var = {}
         for sm in ("ne", "lsgs"):

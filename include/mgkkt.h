@@ -173,6 +173,25 @@ int mg_coarse_solve(mg_ctx *ctx, const double *f, double *x, void *stream);
  * host synchronisation. */
 int mg_cycle(mg_ctx *ctx, const double *f, double *x, void *stream);
 
+/* ---- one iterate as a replayable HIP graph (section 2's cycle) ------------
+ * mg_capture_cycle records exactly the launches of mg_cycle(ctx, f, x) with
+ * the context's current options into an executable HIP graph and returns it
+ * in *out (caller-owned; free it with mg_graph_destroy before mg_destroy of
+ * its context).  Capture runs on a private stream of the context and does not
+ * execute anything; the graph is uploaded on `stream`.  Each
+ * mg_graph_launch(g, stream) then performs one iterate in place on the x
+ * captured, reading the f captured: both device buffers must stay allocated
+ * while g is used.  A replay is bit-identical to an eager mg_cycle.  The graph
+ * uses the context's workspace, so replays, eager calls and solves on one
+ * context must be ordered on one stream.  mg_set_opts invalidates graphs
+ * captured before it: their launch then returns MG_EINVAL.  Errors: MG_EINVAL
+ * (NULL argument), MG_EHIP / MG_ENOMEM from capture or instantiation (*out =
+ * NULL). */
+typedef struct mg_graph mg_graph;
+int mg_capture_cycle(mg_ctx *ctx, const double *f, double *x, void *stream, mg_graph **out);
+int mg_graph_launch(mg_graph *graph, void *stream);
+void mg_graph_destroy(mg_graph *graph);
+
 /* Iterate from the initial guess in x until ||f - A x|| <= tol ||f|| in the
  * context's norm (mg_opts.norm).  cycles_out (may be NULL) receives the number
  * of iterates done, relres_out (may be NULL) the final relative residual.

@@ -84,6 +84,10 @@ def lib():
     L.mg_prolong_add.argtypes = [vp, ip, vp, vp, vp]
     L.mg_coarse_solve.argtypes = [vp, vp, vp, vp]
     L.mg_cycle.argtypes = [vp, vp, vp, vp]
+    L.mg_capture_cycle.argtypes = [vp, vp, vp, vp, ctypes.POINTER(vp)]
+    L.mg_graph_launch.argtypes = [vp, vp]
+    L.mg_graph_destroy.argtypes = [vp]
+    L.mg_graph_destroy.restype = None
     L.mg_solve.argtypes = [vp, vp, vp, dp, ctypes.POINTER(ip), ctypes.POINTER(dp), vp]
     L.mg_timing_enable.argtypes = [vp, ip]
     L.mg_timing_read.argtypes = [vp, ctypes.POINTER(dp), ctypes.POINTER(ctypes.c_long)]
@@ -108,7 +112,7 @@ def lib():
     L.mg_last_error.restype = ctypes.c_char_p
     L.mg_last_error.argtypes = [vp]
     for name in ("mg_setup", "mg_get_opts", "mg_set_opts", "mg_rhs", "mg_control", "mg_adjoint_grad", "mg_apply", "mg_residual", "mg_smooth",
-                 "mg_restrict", "mg_prolong_add", "mg_coarse_solve", "mg_cycle", "mg_solve", "mg_timing_enable",
+                 "mg_restrict", "mg_prolong_add", "mg_coarse_solve", "mg_cycle", "mg_capture_cycle", "mg_graph_launch", "mg_solve", "mg_timing_enable",
                  "mg_timing_read"):
         getattr(L, name).restype = ip
     _lib = L
@@ -288,6 +292,14 @@ class Solver:
         self._check(lib().mg_cycle(self._h, self._t(f, n, "f"), self._t(x, n, "x"), _stream()), "mg_cycle")
         return x
 
+    def capture_cycle(self, f, x) -> "CycleGraph":
+        """mg_cycle(f, x) recorded as a HIP graph; CycleGraph.launch() replays it."""
+        n = self.vec_len()
+        g = ctypes.c_void_p()
+        st = lib().mg_capture_cycle(self._h, self._t(f, n, "f"), self._t(x, n, "x"), _stream(), ctypes.byref(g))
+        self._check(st, "mg_capture_cycle")
+        return CycleGraph(self, g, f, x)
+
     def solve(self, f, x=None, tol: float = 1e-10, raise_on_error: bool = True):
         """Returns (x, cycles, relres, status)."""
         import torch
@@ -314,6 +326,32 @@ class Solver:
 
 
 # --- batches of independent instances ----------------------------------------------
+
+class CycleGraph:
+    """Caller-owned graph of one iterate of a Solver (mg_capture_cycle).  It
+    keeps the solver and the captured f and x alive and is destroyed before
+    them."""
+
+    def __init__(self, solver: Solver, handle, f, x):
+        self._solver, self._g, self.f, self.x = solver, handle, f, x
+
+    def launch(self):
+        if not self._g or not self._solver._h:
+            raise RuntimeError("CycleGraph.launch: graph or solver already closed")
+        self._solver._check(lib().mg_graph_launch(self._g, _stream()), "mg_graph_launch")
+        return self.x
+
+    def close(self):
+        if self._g:
+            lib().mg_graph_destroy(self._g)
+            self._g = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
 
 class Batch:
     """Independent instances (level_i, alpha_i) solved together (mg_batch_*)."""

@@ -236,6 +236,7 @@ struct mg_ctx {
   const double* g_f = nullptr;
   double* g_x = nullptr;
   bool capturing = false;
+  unsigned long opts_gen = 0;  // bumped by mg_set_opts; caller graphs record it
   // timing of the finest-level smoothing sweeps
   bool timing = false;
   std::vector<hipEvent_t> ev;  // pairs
@@ -245,6 +246,13 @@ struct mg_ctx {
   std::string err;
   // Stokes control: the CSR-based solver of stokes.hip (nullptr for Poisson)
   mgk::Stokes* st = nullptr;
+};
+
+// caller-owned executable graph of one mg_cycle
+struct mg_graph {
+  hipGraphExec_t exec;
+  mg_ctx* ctx;
+  unsigned long gen;  // ctx->opts_gen at capture
 };
 
 namespace {
@@ -446,7 +454,9 @@ void tail_ops(const mg_ctx* c, int l, std::vector<int4>& ops) {
   if (c->o.nu2) ops.push_back(make_int4(mgk::kTailSmooth, l, c->o.nu2, 0));
 }
 
-// (Re)build the tail for the context's options; tail level min(5, level - 1)
+// (Re)build the tail for the context's options; tail level min(5, level - 1).
+// k0 <= 2: the tail solves the coarsest system with one lane per unknown
+// (2 (2^k0 + 1)^2 <= 64).
 int setup_tail(mg_ctx* c) {
   (void)hipFree(c->d_tail_ops);
   c->d_tail_ops = nullptr;
@@ -591,15 +601,16 @@ void drop_graph(mg_ctx* c) {
   c->g_x = nullptr;
 }
 
-// graph of iterate() for (f, x) and the current options / timing state
-int ensure_graph(mg_ctx* c, const double* f, double* x) {
-  if (c->gexec && c->g_f == f && c->g_x == x) return MG_OK;
-  drop_graph(c);
+// records body(stream) on the context's capture stream (no execution) and
+// instantiates the graph into *out
+template <class Body>
+int capture_graph(mg_ctx* c, Body&& body, hipGraphExec_t* out) {
+  *out = nullptr;
   if (!c->cap_stream) HIPCHK(c, hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
   hipGraph_t g = nullptr;
   HIPCHK(c, hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
   c->capturing = true;
-  int st = iterate(c, f, x, c->cap_stream);
+  int st = body(c->cap_stream);
   c->capturing = false;
   hipError_t e = hipStreamEndCapture(c->cap_stream, &g);
   if (st != MG_OK) {
@@ -607,12 +618,22 @@ int ensure_graph(mg_ctx* c, const double* f, double* x) {
     return st;
   }
   if (e != hipSuccess) return fail(c, MG_EHIP, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
-  e = hipGraphInstantiate(&c->gexec, g, nullptr, nullptr, 0);
+  e = hipGraphInstantiate(out, g, nullptr, nullptr, 0);
   (void)hipGraphDestroy(g);
   if (e != hipSuccess) {
-    c->gexec = nullptr;
-    return fail(c, MG_EHIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
+    *out = nullptr;
+    return fail(c, e == hipErrorOutOfMemory ? MG_ENOMEM : MG_EHIP,
+                std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
   }
+  return MG_OK;
+}
+
+// graph of iterate() for (f, x) and the current options / timing state
+int ensure_graph(mg_ctx* c, const double* f, double* x) {
+  if (c->gexec && c->g_f == f && c->g_x == x) return MG_OK;
+  drop_graph(c);
+  int st = capture_graph(c, [&](hipStream_t cs) { return iterate(c, f, x, cs); }, &c->gexec);
+  if (st != MG_OK) return st;
   c->g_f = f;
   c->g_x = x;
   return MG_OK;
@@ -776,6 +797,11 @@ int mg_setup(int level, double alpha, int problem, const mg_opts* opts, mg_ctx**
     const int N = 2 * ((1 << c->k0) + 1) * ((1 << c->k0) + 1);
     if (!lu_factor(N, A, piv)) return bail(fail(c, MG_EINVAL, "singular coarsest matrix"));
     c->ncoarse = N;
+    // d_piv holds the row interchanges (N entries) followed by the permutation
+    // they compose to: entry i of the permuted right-hand side is b[perm[i]]
+    piv.resize(2 * N);
+    for (int i = 0; i < N; i++) piv[N + i] = i;
+    for (int k = 0; k < N; k++) std::swap(piv[N + k], piv[N + piv[k]]);
     if (hipMalloc(&c->d_lu, A.size() * sizeof(double)) != hipSuccess) return bail(MG_ENOMEM);
     if (hipMalloc(&c->d_piv, piv.size() * sizeof(int)) != hipSuccess) return bail(MG_ENOMEM);
     if (hipMemcpy(c->d_lu, A.data(), A.size() * sizeof(double), hipMemcpyHostToDevice) != hipSuccess ||
@@ -808,6 +834,7 @@ int mg_set_opts(mg_ctx* ctx, const mg_opts* opts) {
     ctx->o = o;
     mgk::stokes_set(ctx->st, o);
     drop_graph(ctx);
+    ctx->opts_gen++;
     return MG_OK;
   }
   if (hipSetDevice(ctx->device) != hipSuccess) return MG_EHIP;
@@ -818,6 +845,7 @@ int mg_set_opts(mg_ctx* ctx, const mg_opts* opts) {
   ctx->o = o;
   for (auto& b : ctx->lv) b.lev.tau = o.tau;
   drop_graph(ctx);
+  ctx->opts_gen++;
   return setup_tail(ctx);
 }
 
@@ -949,6 +977,36 @@ int mg_cycle(mg_ctx* ctx, const double* f, double* x, void* stream) {
     return ir_step(ctx, x, s);
   }
   return cycle_body<double>(ctx, ctx->level, f, x, b.r, false, s);
+}
+
+int mg_capture_cycle(mg_ctx* ctx, const double* f, double* x, void* stream, mg_graph** out) {
+  if (out) *out = nullptr;
+  if (!ctx || !f || !x || !out) return MG_EINVAL;
+  HIPCHK(ctx, hipSetDevice(ctx->device));
+  hipGraphExec_t exec = nullptr;
+  int st = capture_graph(ctx, [&](hipStream_t cs) { return mg_cycle(ctx, f, x, cs); }, &exec);
+  if (st != MG_OK) return st;
+  hipError_t e = hipGraphUpload(exec, (hipStream_t)stream);
+  if (e != hipSuccess) {
+    (void)hipGraphExecDestroy(exec);
+    return fail(ctx, MG_EHIP, std::string("hipGraphUpload: ") + hipGetErrorString(e));
+  }
+  *out = new mg_graph{exec, ctx, ctx->opts_gen};
+  return MG_OK;
+}
+
+int mg_graph_launch(mg_graph* graph, void* stream) {
+  if (!graph) return MG_EINVAL;
+  mg_ctx* c = graph->ctx;
+  if (graph->gen != c->opts_gen) return fail(c, MG_EINVAL, "mg_graph_launch: options changed since capture");
+  HIPCHK(c, hipGraphLaunch(graph->exec, (hipStream_t)stream));
+  return MG_OK;
+}
+
+void mg_graph_destroy(mg_graph* graph) {
+  if (!graph) return;
+  (void)hipGraphExecDestroy(graph->exec);
+  delete graph;
 }
 
 int mg_solve(mg_ctx* ctx, const double* f, double* x, double tol, int* cycles_out, double* relres_out,

@@ -484,19 +484,36 @@ __global__ __launch_bounds__(256) void k_coarse_solve(int N, const double* __res
   for (int i = tid; i < N; i += blockDim.x) x[i] = (T)b[i];
 }
 
+// *out = scale * sum of part[0..n) by one workgroup of NT threads, in a fixed
+// order (four independent accumulators per thread keep loads in flight)
+template <int NT>
 __device__ __forceinline__ void sum_body(const double* __restrict__ part, int n, double scale,
-                                             double* __restrict__ out) {
-  __shared__ double sh[4];
+                                         double* __restrict__ out) {
+  __shared__ double sh[NT / 64];
   const int tid = threadIdx.x;
-  double s = 0.0;
-  for (int k = tid; k < n; k += 256) s += part[k];
-  s = wave_sum(s);
+  double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+  int k = tid;
+  for (; k + 3 * NT < n; k += 4 * NT) {
+    a0 += part[k];
+    a1 += part[k + NT];
+    a2 += part[k + 2 * NT];
+    a3 += part[k + 3 * NT];
+  }
+  for (; k < n; k += NT) a0 += part[k];
+  double s = wave_sum((a0 + a1) + (a2 + a3));
   if ((tid & 63) == 0) sh[tid >> 6] = s;
   __syncthreads();
-  if (tid == 0) *out = scale * ((sh[0] + sh[1]) + (sh[2] + sh[3]));
+  if (tid == 0) {
+    double t = 0.0;
+#pragma unroll
+    for (int w = 0; w < NT / 64; w++) t += sh[w];
+    *out = scale * t;
+  }
 }
-__global__ __launch_bounds__(256) void k_sum(const double* __restrict__ part, int n, double scale,
-                                             double* __restrict__ out) { sum_body(part, n, scale, out); }
+__global__ __launch_bounds__(1024) void k_sum(const double* __restrict__ part, int n, double scale,
+                                              double* __restrict__ out) {
+  sum_body<1024>(part, n, scale, out);
+}
 
 __global__ __launch_bounds__(256) void k_sumsq(const double* __restrict__ v, size_t n, double* __restrict__ part) {
   __shared__ double sh[4];
@@ -611,7 +628,7 @@ __global__ __launch_bounds__(kNT) void kb_vnorm(const BFine* __restrict__ B) {
 __global__ __launch_bounds__(256) void kb_sum(const BFine* __restrict__ B, int nparts, int slot) {
   const BFine& a = B[blockIdx.x];
   if (!*a.active) return;
-  sum_body(a.part, nparts, 1.0, a.norm + slot);
+  sum_body<256>(a.part, nparts, 1.0, a.norm + slot);
 }
 
 __global__ void kb_to_f32_scaled(const BFine* __restrict__ B, size_t len) {
@@ -723,7 +740,7 @@ hipError_t launch_coarse_solve(int N, const double* lu, const int* piv, const T*
 }
 
 hipError_t launch_sum(const double* part, int n, double* out, hipStream_t s, double scale) {
-  hipLaunchKernelGGL(k_sum, dim3(1), dim3(256), 0, s, part, n, scale, out);
+  hipLaunchKernelGGL(k_sum, dim3(1), dim3(1024), 0, s, part, n, scale, out);
   return hipGetLastError();
 }
 

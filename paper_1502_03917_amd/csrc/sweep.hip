@@ -254,7 +254,13 @@ __device__ __forceinline__ void lsgs_tile_body(const Lev& L, int ntx, int nty, i
       const int d = kHalo - 1 - 2 * ph;  // Chebyshev radius of the phase window around the tile
       const int wl = max(ci0, i0 - d), wh = min(ci1, i1 + d);
       const int wb = max(rj0, j0 - d), wt = min(rj1, j1 + d);
-      const int S = (wh - wl + 6) / 7 + 1;  // colour slots per row (first slot within [wl, wl+7))
+      // colour slots per row: the first slot lies in [wl, wl + 7).  When one
+      // pass of the workgroup covers the widest phase, a fixed count that
+      // covers the widest window keeps the item decode free of divisions by
+      // run-time values (slots past wh are skipped)
+      constexpr int SMAX = (G::RMAX + 6) / 7 + 1;
+      constexpr bool kFixed = (G::RMAX - 2) * SMAX <= NT;
+      const int S = kFixed ? SMAX : (wh - wl + 6) / 7 + 1;
       const int nitems = (wt - wb) * S;
       for (int k = tid; k < nitems; k += NT) {
         const int rr = k / S, t = k - rr * S;
@@ -301,11 +307,15 @@ __global__ __launch_bounds__(NT) void kb_lsgs_tile(const BInst<T>* __restrict__ 
 inline int tiles_along(int npts, int TW) { return (npts + TW - 1) / TW; }
 
 // One workgroup per tile; the grid is padded to a multiple of 8 so that the
-// XCD-aware tile order applies (spare workgroups exit at once).  Workgroup
-// size per precision: FP64 tiles need 139 KB of LDS, so one workgroup fits
-// per CU and it takes 1024 threads (16 waves) to hide LDS and FP64 latency;
-// FP32 tiles need 70 KB and run as two 512-thread workgroups per CU.  (A
-// persistent grid that prefetches the next tile measured slower: its extra
+// XCD-aware tile order applies (spare workgroups exit at once).
+//
+// Tile shapes (measured on gfx950).  Large levels: 48 x 48 tiles; FP64 tiles
+// need 140 KB of LDS, so one workgroup fits per CU and it takes 1024 threads
+// (16 waves) to hide LDS and FP64 latency; FP32 tiles need 70 KB and run as
+// two 512-thread workgroups per CU.  Small levels (up to 257^2 vertices in
+// FP64, 513^2 in FP32) are latency-bound (one round of tiles): 16 x 16 tiles
+// with 256 threads take about 15 us per sweep there instead of about 25 us.
+// (A persistent grid that prefetches the next tile measured slower: its extra
 // registers limit it to 512 threads.)
 inline int round8(int v) { return (v + 7) / 8 * 8; }
 
@@ -314,22 +324,35 @@ struct SweepShape;
 template <>
 struct SweepShape<double> {
   static constexpr int NT = 1024;
+  static constexpr int kSmallMaxN = 256;  // n of the largest level swept with small tiles
 };
 template <>
 struct SweepShape<float> {
   static constexpr int NT = 512;
+  static constexpr int kSmallMaxN = 512;
 };
+constexpr int kSmallTW = 16, kSmallNT = 256;
 
 template <typename T>
 hipError_t launch_tile_cfg(const Lev& L, int reverse, T* x, const T* rin, T* rout, hipStream_t s) {
-  constexpr int NT = SweepShape<T>::NT;
-  const int nt = tiles_along(L.n + 1, 48);
-  hipLaunchKernelGGL((k_lsgs_tile<T, 48, NT>), dim3(round8(nt * nt)), dim3(NT), 0, s, L, nt, nt, reverse, x, rin, rout);
+  if (L.n <= SweepShape<T>::kSmallMaxN) {
+    const int nt = tiles_along(L.n + 1, kSmallTW);
+    hipLaunchKernelGGL((k_lsgs_tile<T, kSmallTW, kSmallNT>), dim3(round8(nt * nt)), dim3(kSmallNT), 0, s, L, nt, nt,
+                       reverse, x, rin, rout);
+  } else {
+    constexpr int NT = SweepShape<T>::NT;
+    const int nt = tiles_along(L.n + 1, 48);
+    hipLaunchKernelGGL((k_lsgs_tile<T, 48, NT>), dim3(round8(nt * nt)), dim3(NT), 0, s, L, nt, nt, reverse, x, rin,
+                       rout);
+  }
   return hipGetLastError();
 }
 
 }  // namespace
 
+// Batched sweeps keep the 48 x 48 tiles on every level: a launch over many
+// instances has enough workgroups to fill the chip, where the smaller tiles'
+// wider halo share would cost bandwidth.
 template <typename T>
 hipError_t launch_b_lsgs_sweep(const BInst<T>* d, int count, int n, int reverse, int sel, hipStream_t s) {
   constexpr int NT = SweepShape<T>::NT;

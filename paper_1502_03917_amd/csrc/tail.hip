@@ -19,6 +19,14 @@ namespace {
 
 __device__ inline void bar() { __syncthreads(); }
 
+// value of v in lane k of the wave (k uniform across the wave)
+__device__ inline double lane_bcast(double v, int k) {
+  const unsigned long long u = __builtin_bit_cast(unsigned long long, v);
+  const unsigned lo = __builtin_amdgcn_readlane((unsigned)u, k);
+  const unsigned hi = __builtin_amdgcn_readlane((unsigned)(u >> 32), k);
+  return __builtin_bit_cast(double, ((unsigned long long)hi << 32) | lo);
+}
+
 // bytes of the shared scratch: NE corrections of level T (2 V_T entries) or
 // the FP64 right-hand side of the coarsest solve, whichever is larger
 template <typename T>
@@ -39,8 +47,8 @@ struct TailArgs {
   int k0, tlev, nops, smoother;  // tlev: the top level of the tail
   double tau;
   const int4* ops;       // device op list
-  const double* lu;      // coarsest LU factors (row pivots piv)
-  const int* piv;
+  const double* lu;      // coarsest LU factors
+  const int* piv;        // row interchanges (ncoarse), then the permutation they compose to (ncoarse)
   int ncoarse;
   const T* fT;           // f on level T (global)
   T* xT;                 // x on level T (global): in (if !first) / out
@@ -265,31 +273,24 @@ __device__ __forceinline__ void tail_body(const TailArgs<T>& A) {
         break;
       }
       case kTailCoarse: {  // x_k0 = A_k0^{-1} f_k0, FP64 LU with row pivots
+        // one wave, one row per lane (N0 <= 64): the permuted right-hand side,
+        // then forward (unit lower) and back substitution with the pivot
+        // entry of each step broadcast from its lane; no workgroup barriers
         const TailLevel& Lc = A.lv[k0];
-        double* b = reinterpret_cast<double*>(sp);  // NE scratch is free here
-        for (int e = tid; e < N0; e += NT) b[e] = (double)sm[Lc.of + e];
-        bar();
-        if (tid == 0)
-          for (int k = 0; k < N0; k++)
-            if (A.piv[k] != k) {
-              const double t = b[k];
-              b[k] = b[A.piv[k]];
-              b[A.piv[k]] = t;
-            }
-        bar();
-        for (int k = 0; k < N0; k++) {
-          const double bk = b[k];
-          for (int i = k + 1 + tid; i < N0; i += NT) b[i] -= slu[i * N0 + k] * bk;
-          bar();
+        if (tid < 64) {
+          const int* perm = A.piv + N0;
+          double v = tid < N0 ? (double)sm[Lc.of + perm[tid]] : 0.0;
+          for (int k = 0; k + 1 < N0; k++) {
+            const double bk = lane_bcast(v, k);
+            if (tid > k && tid < N0) v -= slu[tid * N0 + k] * bk;
+          }
+          for (int k = N0 - 1; k >= 0; k--) {
+            if (tid == k) v /= slu[k * N0 + k];
+            const double bk = lane_bcast(v, k);
+            if (tid < k) v -= slu[tid * N0 + k] * bk;
+          }
+          if (tid < N0) sm[Lc.ox + tid] = (T)v;
         }
-        for (int k = N0 - 1; k >= 0; k--) {
-          if (tid == 0) b[k] /= slu[k * N0 + k];
-          bar();
-          const double bk = b[k];
-          for (int i = tid; i < k; i += NT) b[i] -= slu[i * N0 + k] * bk;
-          bar();
-        }
-        for (int e = tid; e < N0; e += NT) sm[Lc.ox + e] = (T)b[e];
         bar();
         break;
       }

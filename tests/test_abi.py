@@ -87,6 +87,12 @@ def test_null_context_calls():
     assert L.mg_level_len(None, 3) == 0
     assert L.mg_last_error(None) == b"no context"
     assert L.mg_cycle(None, None, None, None) == mg.MG_EINVAL
+    g = ctypes.c_void_p(1)
+    assert L.mg_capture_cycle(None, None, None, None, ctypes.byref(g)) == mg.MG_EINVAL
+    assert g.value is None  # *out cleared on error
+    assert L.mg_capture_cycle(None, None, None, None, None) == mg.MG_EINVAL
+    assert L.mg_graph_launch(None, None) == mg.MG_EINVAL
+    L.mg_graph_destroy(None)
     assert L.mg_solve(None, None, None, 1e-10, None, None, None) == mg.MG_EINVAL
     assert L.mg_rhs(None, None, None, None) == mg.MG_EINVAL
     assert L.mg_smooth(None, 3, None, None, 1, None) == mg.MG_EINVAL

@@ -185,6 +185,46 @@ def test_graph_replays_match_eager(torch_cuda, monkeypatch, precision):
     torch.cuda.synchronize()
 
 
+@pytest.mark.parametrize("problem,precision", [("poisson", "fp64"), ("poisson", "fp32_ir"), ("stokes", "fp64")])
+def test_capture_cycle_replays_match_eager(torch_cuda, problem, precision):
+    # mg_capture_cycle: capturing executes nothing; each replay equals one
+    # eager mg_cycle bit for bit, with eager work of the same context
+    # (residual norms, which share its workspace) between the replays;
+    # mg_set_opts invalidates the graph
+    torch = torch_cuda
+    mg = _mg()
+    level, alpha = (8, 1e-3) if problem == "poisson" else (5, 1e-2)
+    se = mg.Solver(level, alpha, problem=problem, precision=precision)
+    sg = mg.Solver(level, alpha, problem=problem, precision=precision)
+    data = workloads.desired_state(level, 2) if problem == "poisson" else workloads.desired_velocity(level, 7)
+    f = se.rhs(_dev(torch, data))
+    xe = torch.zeros_like(f)
+    xg = torch.zeros_like(f)
+    other = _dev(torch, workloads.uniform(f.numel(), 5))
+    g = sg.capture_cycle(f, xg)
+    torch.cuda.synchronize()
+    assert not xg.any()
+    for k in range(1, 5):
+        se.cycle(f, xe)
+        g.launch()
+        _, nrm = sg.residual(f, other, norm=True)
+        assert nrm > 0
+        assert torch.equal(xe, xg), k
+    if problem == "poisson" and precision == "fp64":
+        h = oracle.Hierarchy(level, alpha, coarse=1)
+        xo = np.zeros(h.ndof())
+        fo = h.rhs(workloads.desired_state(level, 2))
+        for _ in range(4):
+            h.cycle(fo, xo, smoother="lsgs", order="col7")
+        assert np.linalg.norm(_host(xg) - xo) <= 1e-12 * np.linalg.norm(xo)
+    sg.set_opts(nu1=1)
+    with pytest.raises(mg.MGError) as e:
+        g.launch()
+    assert e.value.status == mg.MG_EINVAL
+    g.close()
+    torch.cuda.synchronize()
+
+
 CYCLE_CASES = [
     (5, 1e-2, "lsgs", 1),
     (5, 1e-2, "ne", 1),
