@@ -64,17 +64,32 @@ struct TileGeom {
   static constexpr int RN = RP * (RMAX + 2);   // region cells with guard rows
 };
 
+// the two fields of one vertex side by side (one 16-byte LDS access in FP64)
+template <typename T>
+struct Pair;
+template <>
+struct Pair<double> {
+  typedef double type __attribute__((ext_vector_type(2)));
+};
+template <>
+struct Pair<float> {
+  typedef float type __attribute__((ext_vector_type(2)));
+};
+
 template <typename T, int TW, int NT>
 __device__ __forceinline__ void lsgs_tile_body(const Lev& L, int ntx, int nty, int reverse, T* __restrict__ x,
                                                const T* __restrict__ rin, T* __restrict__ rout) {
   using G = TileGeom<TW>;
+  using T2 = typename Pair<T>::type;
   constexpr int NR = (G::RMAX * G::RMAX + NT - 1) / NT;  // region cells per thread
   constexpr int NX = (TW * TW + NT - 1) / NT;            // owned cells per thread
-  __shared__ T sy[G::RN];
-  __shared__ T sl[G::RN];
-  __shared__ T dxy[TW * TW];
-  __shared__ T dxl[TW * TW];
-  __shared__ T tC[25 * kC5];  // per-class coefficient blocks for vertices near the boundary
+  // residual (y, lambda) of the region; the guard ring and the cells of the
+  // region that lie outside the square hold zeros, so the neighbours of a
+  // boundary vertex can be read and written without bounds checks (their
+  // coefficients in the class blocks are zero)
+  __shared__ T2 s2[G::RN];
+  __shared__ T2 dx2[TW * TW];               // corrections of the owned x
+  __shared__ __align__(16) T tC[25 * kC5];  // per-class coefficient blocks
 
   const int n = L.n, ld = L.ld, V = L.V;
   const int ntiles = ntx * nty;
@@ -88,204 +103,158 @@ __device__ __forceinline__ void lsgs_tile_body(const Lev& L, int ntx, int nty, i
   // share halo rows in that XCD's L2 (the grid is a multiple of 8).
   const int tile = (nblk % 8 == 0) ? (bid % 8) * (nblk / 8) + bid / 8 : bid;
   if (tile >= ntiles) return;  // padding workgroup
-  struct Box {
-    int i0, i1, j0, j1, ci0, ci1, rj0, rj1;
-  };
-  auto box_of = [&](int tile) -> Box {
-    Box b;
-    const int tx = tile % ntx, ty = tile / ntx;
-    b.i0 = tx * TW;
-    b.i1 = min(n + 1, b.i0 + TW);
-    b.j0 = ty * TW;
-    b.j1 = min(n + 1, b.j0 + TW);
-    b.ci0 = max(0, b.i0 - kHalo);
-    b.ci1 = min(n + 1, b.i1 + kHalo);
-    b.rj0 = max(0, b.j0 - kHalo);
-    b.rj1 = min(n + 1, b.j1 + kHalo);
-    return b;
-  };
+  const int tx = tile % ntx, ty = tile / ntx;
+  const int i0 = tx * TW, i1 = min(n + 1, i0 + TW);
+  const int j0 = ty * TW, j1 = min(n + 1, j0 + TW);
+  const int ci0 = max(0, i0 - kHalo), ci1 = min(n + 1, i1 + kHalo);
+  const int rj0 = max(0, j0 - kHalo), rj1 = min(n + 1, j1 + kHalo);
+  const int RW = ci1 - ci0, RH = rj1 - rj0, OW = i1 - i0, OH = j1 - j0;
 
   // the tile's region of r and its owned x, loaded into registers first so
-  // that every load is in flight before the first LDS store
+  // that every load is in flight before the first LDS store; cells outside
+  // the square load as zero (masked offset)
   T ry[NR], rl[NR], xy[NX], xl[NX];
-  auto fetch = [&](int tile) {
-    const Box b = box_of(tile);
-    const int RW = b.ci1 - b.ci0, RH = b.rj1 - b.rj0, OW = b.i1 - b.i0, OH = b.j1 - b.j0;
 #pragma unroll
-    for (int q = 0; q < NX; q++) {
-      const int e = tid + q * NT;
-      const int oj = e / TW, oi = e - oj * TW;
-      const bool ok = e < TW * TW && oi < OW && oj < OH;
-      const unsigned o = ok ? (unsigned)(((b.j0 + oj) * ld + b.i0 + oi) * sizeof(T)) : kOff;
-      xy[q] = bload(Rx, o, (T*)nullptr);
-      xl[q] = bload(Rx, ok ? o + fo : kOff, (T*)nullptr);
-    }
+  for (int q = 0; q < NX; q++) {
+    const int e = tid + q * NT;
+    const int oj = e / TW, oi = e - oj * TW;
+    const bool ok = e < TW * TW && oi < OW && oj < OH;
+    const unsigned o = ok ? (unsigned)(((j0 + oj) * ld + i0 + oi) * sizeof(T)) : kOff;
+    xy[q] = bload(Rx, o, (T*)nullptr);
+    xl[q] = bload(Rx, ok ? o + fo : kOff, (T*)nullptr);
+  }
 #pragma unroll
-    for (int q = 0; q < NR; q++) {
-      const int e = tid + q * NT;
-      const int lr = e / G::RMAX, li = e - lr * G::RMAX;
-      const bool ok = e < G::RMAX * G::RMAX && li < RW && lr < RH;
-      const unsigned o = ok ? (unsigned)(((b.rj0 + lr) * ld + b.ci0 + li) * sizeof(T)) : kOff;
-      ry[q] = bload(Rin, o, (T*)nullptr);
-      rl[q] = bload(Rin, ok ? o + fo : kOff, (T*)nullptr);
-    }
-  };
-  // region r into LDS, corrections cleared
-  auto stash = [&](int tile) {
-    const Box b = box_of(tile);
-    const int RW = b.ci1 - b.ci0, RH = b.rj1 - b.rj0;
-#pragma unroll
-    for (int q = 0; q < NR; q++) {
-      const int e = tid + q * NT;
-      const int lr = e / G::RMAX, li = e - lr * G::RMAX;
-      if (e < G::RMAX * G::RMAX && li < RW && lr < RH) {
-        const int a = (lr + 1) * G::RP + li + 1;
-        sy[a] = ry[q];
-        sl[a] = rl[q];
-      }
-    }
-    for (int e = tid; e < TW * TW; e += NT) {
-      dxy[e] = (T)0;
-      dxl[e] = (T)0;
-    }
-  };
-
+  for (int q = 0; q < NR; q++) {
+    const int e = tid + q * NT;
+    const int lr = e / G::RMAX, li = e - lr * G::RMAX;
+    const bool ok = e < G::RMAX * G::RMAX && li < RW && lr < RH;
+    const unsigned o = ok ? (unsigned)(((rj0 + lr) * ld + ci0 + li) * sizeof(T)) : kOff;
+    ry[q] = bload(Rin, o, (T*)nullptr);
+    rl[q] = bload(Rin, ok ? o + fo : kOff, (T*)nullptr);
+  }
   {
     constexpr int NC = (25 * kC5 + NT - 1) / NT;
     const double* src = &L.tab->C5[0][0];
-    double v[NC];
-#pragma unroll
-    for (int q = 0; q < NC; q++) v[q] = src[min(tid + q * NT, 25 * kC5 - 1)];
 #pragma unroll
     for (int q = 0; q < NC; q++)
-      if (tid + q * NT < 25 * kC5) tC[tid + q * NT] = (T)v[q];
+      if (tid + q * NT < 25 * kC5) tC[tid + q * NT] = (T)src[tid + q * NT];
   }
-  fetch(tile);
-  stash(tile);
+  // guard ring: rows 0 and RMAX + 1, columns 0 and RMAX + 1
+  for (int e = tid; e < 4 * (G::RMAX + 2); e += NT) {
+    const int side = e / (G::RMAX + 2), t = e - side * (G::RMAX + 2);
+    const int a = side == 0 ? t : side == 1 ? (G::RMAX + 1) * G::RP + t : side == 2 ? t * G::RP
+                                                                                   : t * G::RP + G::RMAX + 1;
+    s2[a] = (T2){(T)0, (T)0};
+  }
+  for (int e = tid; e < TW * TW; e += NT) dx2[e] = (T2){(T)0, (T)0};
+#pragma unroll
+  for (int q = 0; q < NR; q++) {
+    const int e = tid + q * NT;
+    const int lr = e / G::RMAX, li = e - lr * G::RMAX;
+    if (e < G::RMAX * G::RMAX) s2[(lr + 1) * G::RP + li + 1] = (T2){ry[q], rl[q]};
+  }
   lds_barrier();
 
   const T Mc = (T)L.Mc, Mo = (T)L.Mo, Kc = (T)L.Kc, Ka = (T)L.Ka, Kd = (T)L.Kd, Wi = (T)L.Winv;
   const T al = (T)L.alpha, ai = (T)L.ainv, Nyi = (T)L.Nyi, Nli = (T)L.Nli;
 
-  {
-    const Box b = box_of(tile);
-    const int i0 = b.i0, i1 = b.i1, j0 = b.j0, j1 = b.j1, ci0 = b.ci0, ci1 = b.ci1, rj0 = b.rj0, rj1 = b.rj1;
-    const int OW = i1 - i0, OH = j1 - j0;
-
-    // one update of the vertex at region cell (lr, li)
-    auto update = [&](int lr, int li) {
-      const int gi = ci0 + li, gj = rj0 + lr;
-      const int b0 = (lr + 1) * G::RP + li + 1;
-      const int bu = b0 + G::RP, bd = b0 - G::RP;
-      T py, pl;
-      // the 14 residual entries are read once; the scatter writes the gathered
-      // values minus the update (no other vertex of the phase touches them)
-      if (gi >= 2 && gi <= n - 2 && gj >= 2 && gj <= n - 2) {
-        const T yc = sy[b0], ye = sy[b0 + 1], yw = sy[b0 - 1], yn = sy[bu], ys = sy[bd], yne = sy[bu + 1],
-                ysw = sy[bd - 1];
-        const T lc = sl[b0], le = sl[b0 + 1], lw = sl[b0 - 1], ln = sl[bu], ls = sl[bd], lne = sl[bu + 1],
-                lsw = sl[bd - 1];
-        const T ya = ye + yw + yn + ys;
-        const T yg = yne + ysw;
-        const T la = le + lw + ln + ls;
-        const T lg = lne + lsw;
-        const T qy = Wi * (Mc * yc + Mo * (ya + yg) + al * (Kc * lc + Ka * la + Kd * lg));
-        const T ql = Wi * ((Kc * yc + Ka * ya + Kd * yg) - (Mc * lc + Mo * (la + lg)));
-        py = qy * Nyi;
-        pl = ql * Nli;
-        const T dyc = Mc * py + Kc * pl, dya = Mo * py + Ka * pl, dyg = Mo * py + Kd * pl;
-        const T dlc = Kc * py - ai * (Mc * pl), dla = Ka * py - ai * (Mo * pl), dlg = Kd * py - ai * (Mo * pl);
-        sy[b0] = yc - dyc;
-        sl[b0] = lc - dlc;
-        sy[b0 + 1] = ye - dya;
-        sl[b0 + 1] = le - dla;
-        sy[b0 - 1] = yw - dya;
-        sl[b0 - 1] = lw - dla;
-        sy[bu] = yn - dya;
-        sl[bu] = ln - dla;
-        sy[bd] = ys - dya;
-        sl[bd] = ls - dla;
-        sy[bu + 1] = yne - dyg;
-        sl[bu + 1] = lne - dlg;
-        sy[bd - 1] = ysw - dyg;
-        sl[bd - 1] = lsw - dlg;
-      } else {
-        // near the domain boundary: the class block gives all coefficients;
-        // neighbours outside the square have zero coefficients and are neither
-        // read nor written
-        const T* cb = &tC[(cls5(gi, n) * 5 + cls5(gj, n)) * kC5];
-        int ad[kNDir];
-        bool in[kNDir];
-        T va[kNDir], vb[kNDir];
+  // vertices at least 2 steps from the boundary share one stencil (the
+  // constants above); the others take their class block.  The choice is
+  // made per wave, so a wave runs one of the two paths: a wave holding any
+  // near-boundary vertex runs the class-block path for all its lanes (the
+  // interior class block holds the interior stencil).
+  auto update_interior = [&](int b0, T& py, T& pl) {
+    const int bu = b0 + G::RP, bd = b0 - G::RP;
+    // the 7 residual pairs are read once; the scatter writes the gathered
+    // values minus the update (no other vertex of the phase touches them)
+    const T2 c = s2[b0], e = s2[b0 + 1], w = s2[b0 - 1], nn = s2[bu], ss = s2[bd], ne = s2[bu + 1], sw = s2[bd - 1];
+    const T ya = e.x + w.x + nn.x + ss.x;
+    const T yg = ne.x + sw.x;
+    const T la = e.y + w.y + nn.y + ss.y;
+    const T lg = ne.y + sw.y;
+    const T qy = Wi * (Mc * c.x + Mo * (ya + yg) + al * (Kc * c.y + Ka * la + Kd * lg));
+    const T ql = Wi * ((Kc * c.x + Ka * ya + Kd * yg) - (Mc * c.y + Mo * (la + lg)));
+    py = qy * Nyi;
+    pl = ql * Nli;
+    const T dyc = Mc * py + Kc * pl, dya = Mo * py + Ka * pl, dyg = Mo * py + Kd * pl;
+    const T dlc = Kc * py - ai * (Mc * pl), dla = Ka * py - ai * (Mo * pl), dlg = Kd * py - ai * (Mo * pl);
+    s2[b0] = (T2){c.x - dyc, c.y - dlc};
+    s2[b0 + 1] = (T2){e.x - dya, e.y - dla};
+    s2[b0 - 1] = (T2){w.x - dya, w.y - dla};
+    s2[bu] = (T2){nn.x - dya, nn.y - dla};
+    s2[bd] = (T2){ss.x - dya, ss.y - dla};
+    s2[bu + 1] = (T2){ne.x - dyg, ne.y - dlg};
+    s2[bd - 1] = (T2){sw.x - dyg, sw.y - dlg};
+  };
+  auto update_class = [&](int b0, int gi, int gj, T& py, T& pl) {
+    const T* cb = &tC[(cls5(gi, n) * 5 + cls5(gj, n)) * kC5];
+    T2 v[kNDir];
 #pragma unroll
-        for (int d = 0; d < kNDir; d++) {
-          const int ii = gi + kDI[d], jj = gj + kDJ[d];
-          in[d] = ii >= 0 && ii <= n && jj >= 0 && jj <= n;
-          ad[d] = in[d] ? b0 + kDJ[d] * G::RP + kDI[d] : b0;
-          va[d] = sy[ad[d]];
-          vb[d] = sl[ad[d]];
-        }
-        T qy = 0, ql = 0;
+    for (int d = 0; d < kNDir; d++) v[d] = s2[b0 + kDJ[d] * G::RP + kDI[d]];
+    T qy = 0, ql = 0;
 #pragma unroll
-        for (int d = 0; d < kNDir; d++) {
-          const T m = cb[d], k = cb[kNDir + d], wi = cb[2 * kNDir + d];
-          qy += (m * va[d] + al * k * vb[d]) * wi;
-          ql += (k * va[d] - m * vb[d]) * wi;
-        }
-        py = qy * cb[3 * kNDir];
-        pl = ql * cb[3 * kNDir + 1];
-#pragma unroll
-        for (int d = 0; d < kNDir; d++) {
-          if (!in[d]) continue;
-          const T m = cb[d], k = cb[kNDir + d];
-          sy[ad[d]] = va[d] - (m * py + k * pl);
-          sl[ad[d]] = vb[d] - (k * py - ai * (m * pl));
-        }
-      }
-      if (gi >= i0 && gi < i1 && gj >= j0 && gj < j1) {
-        const int o = (gj - j0) * TW + (gi - i0);
-        dxy[o] = py;
-        dxl[o] = pl;
-      }
-    };
-
-    for (int ph = 0; ph < 7; ph++) {
-      const int colour = reverse ? 6 - ph : ph;
-      const int d = kHalo - 1 - 2 * ph;  // Chebyshev radius of the phase window around the tile
-      const int wl = max(ci0, i0 - d), wh = min(ci1, i1 + d);
-      const int wb = max(rj0, j0 - d), wt = min(rj1, j1 + d);
-      // colour slots per row: the first slot lies in [wl, wl + 7).  When one
-      // pass of the workgroup covers the widest phase, a fixed count that
-      // covers the widest window keeps the item decode free of divisions by
-      // run-time values (slots past wh are skipped)
-      constexpr int SMAX = (G::RMAX + 6) / 7 + 1;
-      constexpr bool kFixed = (G::RMAX - 2) * SMAX <= NT;
-      const int S = kFixed ? SMAX : (wh - wl + 6) / 7 + 1;
-      const int nitems = (wt - wb) * S;
-      for (int k = tid; k < nitems; k += NT) {
-        const int rr = k / S, t = k - rr * S;
-        const int gj = wb + rr;
-        const int gi = wl + ((colour - 2 * gj - wl) % 7 + 7) % 7 + 7 * t;
-        if (gi < wh) update(gj - rj0, gi - ci0);
-      }
-      lds_barrier();
+    for (int d = 0; d < kNDir; d++) {
+      const T m = cb[d], k = cb[kNDir + d], wi = cb[2 * kNDir + d];
+      qy += (m * v[d].x + al * k * v[d].y) * wi;
+      ql += (k * v[d].x - m * v[d].y) * wi;
     }
-
-    // owned tile out: r to r_out, x + corrections to x
+    py = qy * cb[3 * kNDir];
+    pl = ql * cb[3 * kNDir + 1];
 #pragma unroll
-    for (int q = 0; q < NX; q++) {
-      const int e = tid + q * NT;
-      const int oj = e / TW, oi = e - oj * TW;
-      const bool ok = e < TW * TW && oi < OW && oj < OH;
-      const int a = ok ? (oj + j0 - rj0 + 1) * G::RP + (oi + i0 - ci0) + 1 : 0;
-      const int od = ok ? e : 0;
-      const unsigned o = ok ? (unsigned)(((j0 + oj) * ld + i0 + oi) * sizeof(T)) : kOff;
-      const unsigned o2 = ok ? o + fo : kOff;
-      bstore(Rout, o, sy[a]);
-      bstore(Rout, o2, sl[a]);
-      bstore(Rx, o, xy[q] + dxy[od]);
-      bstore(Rx, o2, xl[q] + dxl[od]);
+    for (int d = 0; d < kNDir; d++) {
+      const T m = cb[d], k = cb[kNDir + d];
+      s2[b0 + kDJ[d] * G::RP + kDI[d]] = (T2){v[d].x - (m * py + k * pl), v[d].y - (k * py - ai * (m * pl))};
     }
+  };
+
+  for (int ph = 0; ph < 7; ph++) {
+    const int colour = reverse ? 6 - ph : ph;
+    const int d = kHalo - 1 - 2 * ph;  // Chebyshev radius of the phase window around the tile
+    const int wl = max(ci0, i0 - d), wh = min(ci1, i1 + d);
+    const int wb = max(rj0, j0 - d), wt = min(rj1, j1 + d);
+    // colour slots per row: the first slot lies in [wl, wl + 7).  When one
+    // pass of the workgroup covers the widest phase, a fixed count that
+    // covers the widest window keeps the item decode free of divisions by
+    // run-time values (slots past wh are skipped) and the phase a single pass
+    constexpr int SMAX = (G::RMAX + 6) / 7 + 1;
+    constexpr bool kFixed = (G::RMAX - 2) * SMAX <= NT;
+    const int S = kFixed ? SMAX : (wh - wl + 6) / 7 + 1;
+    const int nitems = (wt - wb) * S;
+    for (int k = tid; k < (kFixed ? NT : nitems); k += NT) {
+      const int rr = k / S, t = k - rr * S;
+      const int gj = wb + rr;
+      const int gi = wl + ((colour - 2 * gj - wl) % 7 + 7) % 7 + 7 * t;
+      const bool act = k < nitems && gi < wh;
+      const bool inner = gi >= 2 && gi <= n - 2 && gj >= 2 && gj <= n - 2;
+      const bool wave_inner = __builtin_amdgcn_ballot_w64(act && !inner) == 0;
+      if (act) {
+        const int b0 = (gj - rj0 + 1) * G::RP + (gi - ci0) + 1;
+        T py, pl;
+        if (wave_inner)
+          update_interior(b0, py, pl);
+        else
+          update_class(b0, gi, gj, py, pl);
+        if (gi >= i0 && gi < i1 && gj >= j0 && gj < j1) dx2[(gj - j0) * TW + (gi - i0)] = (T2){py, pl};
+      }
+    }
+    lds_barrier();
+  }
+
+  // owned tile out: r to r_out, x + corrections to x
+#pragma unroll
+  for (int q = 0; q < NX; q++) {
+    const int e = tid + q * NT;
+    const int oj = e / TW, oi = e - oj * TW;
+    const bool ok = e < TW * TW && oi < OW && oj < OH;
+    const int a = ok ? (oj + j0 - rj0 + 1) * G::RP + (oi + i0 - ci0) + 1 : 0;
+    const int od = ok ? e : 0;
+    const unsigned o = ok ? (unsigned)(((j0 + oj) * ld + i0 + oi) * sizeof(T)) : kOff;
+    const unsigned o2 = ok ? o + fo : kOff;
+    const T2 rv = s2[a], dv = dx2[od];
+    bstore(Rout, o, rv.x);
+    bstore(Rout, o2, rv.y);
+    bstore(Rx, o, xy[q] + dv.x);
+    bstore(Rx, o2, xl[q] + dv.y);
   }
 }
 
