@@ -130,12 +130,16 @@ def counter_summary(directory: str):
     return {k: (n, v / n) for k, (n, v) in agg.items()}
 
 
+# finest-level tile shape (tile width, threads per workgroup) per precision
+SWEEP_TILE = {"fp64": (48, 1024), "fp32_ir": (48, 512)}
+
+
 def finest_sweep_grid(level: int, precision: str) -> int:
     """Work-items launched by the finest-level sweep: one workgroup per
-    48 x 48 tile (1024 threads in FP64, 512 in FP32), the workgroup count
-    rounded up to a multiple of 8."""
-    side = -(-((1 << level) + 1) // 48)
-    return (1024 if precision == "fp64" else 512) * (-(-side * side // 8) * 8)
+    TW x TW tile, the workgroup count rounded up to a multiple of 8."""
+    tw, nt = SWEEP_TILE[precision]
+    side = -(-((1 << level) + 1) // tw)
+    return nt * (-(-side * side // 8) * 8)
 
 
 def print_summary(args) -> int:

@@ -76,6 +76,15 @@ struct Pair<float> {
   typedef float type __attribute__((ext_vector_type(2)));
 };
 
+// Work items of a colour phase are (row, slot) pairs: slot t of a row is its
+// t-th vertex of the phase's colour inside the window.  A window row of width
+// w holds at most ceil(w / 7) of them.
+template <int TW>
+struct PhaseItems {
+  static constexpr int W0 = TW + 2 * kHalo - 2;  // width and height of the widest (first) window
+  static constexpr int SMAX = (W0 + 6) / 7;      // slots per row that cover every window
+};
+
 template <typename T, int TW, int NT>
 __device__ __forceinline__ void lsgs_tile_body(const Lev& L, int ntx, int nty, int reverse, T* __restrict__ x,
                                                const T* __restrict__ rin, T* __restrict__ rout) {
@@ -83,13 +92,19 @@ __device__ __forceinline__ void lsgs_tile_body(const Lev& L, int ntx, int nty, i
   using T2 = typename Pair<T>::type;
   constexpr int NR = (G::RMAX * G::RMAX + NT - 1) / NT;  // region cells per thread
   constexpr int NX = (TW * TW + NT - 1) / NT;            // owned cells per thread
+  constexpr int SMAX = PhaseItems<TW>::SMAX;
+  // One pass of the workgroup covers every phase: each thread then has at
+  // most one vertex per phase, known in advance, and updates its x directly
+  // (x prefetched at the start, x + p stored in the phase).  Otherwise the
+  // corrections of the owned vertices collect in LDS and x is written at the end.
+  constexpr bool kOnePass = PhaseItems<TW>::W0 * SMAX <= NT;
   // residual (y, lambda) of the region; the guard ring and the cells of the
   // region that lie outside the square hold zeros, so the neighbours of a
   // boundary vertex can be read and written without bounds checks (their
   // coefficients in the class blocks are zero)
   __shared__ T2 s2[G::RN];
-  __shared__ T2 dx2[TW * TW];               // corrections of the owned x
-  __shared__ __align__(16) T tC[25 * kC5];  // per-class coefficient blocks
+  __shared__ T2 dx2[kOnePass ? 1 : TW * TW];  // corrections of the owned x (multi-pass phases)
+  __shared__ __align__(16) T tC[25 * kC5];    // per-class coefficient blocks
 
   const int n = L.n, ld = L.ld, V = L.V;
   const int ntiles = ntx * nty;
@@ -110,19 +125,55 @@ __device__ __forceinline__ void lsgs_tile_body(const Lev& L, int ntx, int nty, i
   const int rj0 = max(0, j0 - kHalo), rj1 = min(n + 1, j1 + kHalo);
   const int RW = ci1 - ci0, RH = rj1 - rj0, OW = i1 - i0, OH = j1 - j0;
 
-  // the tile's region of r and its owned x, loaded into registers first so
-  // that every load is in flight before the first LDS store; cells outside
-  // the square load as zero (masked offset)
-  T ry[NR], rl[NR], xy[NX], xl[NX];
+  // the vertex of work item k in phase ph (gi >= wh or k >= nitems: none)
+  struct Item {
+    int gi, gj;
+    bool act;
+  };
+  auto item_of = [&](int ph, int k) {
+    const int colour = reverse ? 6 - ph : ph;
+    const int d = kHalo - 1 - 2 * ph;  // Chebyshev radius of the phase window around the tile
+    const int wl = max(ci0, i0 - d), wh = min(ci1, i1 + d);
+    const int wb = max(rj0, j0 - d), wt = min(rj1, j1 + d);
+    // a fixed slot count (covering the widest window) keeps the decode free of
+    // divisions by run-time values; slots past wh are skipped
+    const int S = kOnePass ? SMAX : (wh - wl + 6) / 7;
+    const int rr = k / S, t = k - rr * S;
+    Item it;
+    it.gj = wb + rr;
+    it.gi = wl + ((colour - 2 * it.gj - wl) % 7 + 7) % 7 + 7 * t;
+    it.act = k < (wt - wb) * S && it.gi < wh;
+    return it;
+  };
+  auto owned = [&](const Item& it) { return it.act && it.gi >= i0 && it.gi < i1 && it.gj >= j0 && it.gj < j1; };
+
+  // Loads first, so that all of them are in flight before the first LDS store:
+  // x of the owned vertices this thread updates (one-pass) or of the owned
+  // cells it writes at the end, then the region of r.  Cells outside the
+  // square load as zero (masked offset).
+  constexpr int NXP = kOnePass ? 7 : NX;
+  T xy[NXP], xl[NXP];
+  unsigned xo[kOnePass ? 7 : 1];
+  if constexpr (kOnePass) {
 #pragma unroll
-  for (int q = 0; q < NX; q++) {
-    const int e = tid + q * NT;
-    const int oj = e / TW, oi = e - oj * TW;
-    const bool ok = e < TW * TW && oi < OW && oj < OH;
-    const unsigned o = ok ? (unsigned)(((j0 + oj) * ld + i0 + oi) * sizeof(T)) : kOff;
-    xy[q] = bload(Rx, o, (T*)nullptr);
-    xl[q] = bload(Rx, ok ? o + fo : kOff, (T*)nullptr);
+    for (int ph = 0; ph < 7; ph++) {
+      const Item it = item_of(ph, tid);
+      xo[ph] = owned(it) ? (unsigned)((it.gj * ld + it.gi) * sizeof(T)) : kOff;
+      xy[ph] = bload(Rx, xo[ph], (T*)nullptr);
+      xl[ph] = bload(Rx, xo[ph] == kOff ? kOff : xo[ph] + fo, (T*)nullptr);
+    }
+  } else {
+#pragma unroll
+    for (int q = 0; q < NX; q++) {
+      const int e = tid + q * NT;
+      const int oj = e / TW, oi = e - oj * TW;
+      const bool ok = e < TW * TW && oi < OW && oj < OH;
+      const unsigned o = ok ? (unsigned)(((j0 + oj) * ld + i0 + oi) * sizeof(T)) : kOff;
+      xy[q] = bload(Rx, o, (T*)nullptr);
+      xl[q] = bload(Rx, ok ? o + fo : kOff, (T*)nullptr);
+    }
   }
+  T ry[NR], rl[NR];
 #pragma unroll
   for (int q = 0; q < NR; q++) {
     const int e = tid + q * NT;
@@ -146,7 +197,8 @@ __device__ __forceinline__ void lsgs_tile_body(const Lev& L, int ntx, int nty, i
                                                                                    : t * G::RP + G::RMAX + 1;
     s2[a] = (T2){(T)0, (T)0};
   }
-  for (int e = tid; e < TW * TW; e += NT) dx2[e] = (T2){(T)0, (T)0};
+  if constexpr (!kOnePass)
+    for (int e = tid; e < TW * TW; e += NT) dx2[e] = (T2){(T)0, (T)0};
 #pragma unroll
   for (int q = 0; q < NR; q++) {
     const int e = tid + q * NT;
@@ -206,55 +258,64 @@ __device__ __forceinline__ void lsgs_tile_body(const Lev& L, int ntx, int nty, i
       s2[b0 + kDJ[d] * G::RP + kDI[d]] = (T2){v[d].x - (m * py + k * pl), v[d].y - (k * py - ai * (m * pl))};
     }
   };
-
-  for (int ph = 0; ph < 7; ph++) {
-    const int colour = reverse ? 6 - ph : ph;
-    const int d = kHalo - 1 - 2 * ph;  // Chebyshev radius of the phase window around the tile
-    const int wl = max(ci0, i0 - d), wh = min(ci1, i1 + d);
-    const int wb = max(rj0, j0 - d), wt = min(rj1, j1 + d);
-    // colour slots per row: the first slot lies in [wl, wl + 7).  When one
-    // pass of the workgroup covers the widest phase, a fixed count that
-    // covers the widest window keeps the item decode free of divisions by
-    // run-time values (slots past wh are skipped) and the phase a single pass
-    constexpr int SMAX = (G::RMAX + 6) / 7 + 1;
-    constexpr bool kFixed = (G::RMAX - 2) * SMAX <= NT;
-    const int S = kFixed ? SMAX : (wh - wl + 6) / 7 + 1;
-    const int nitems = (wt - wb) * S;
-    for (int k = tid; k < (kFixed ? NT : nitems); k += NT) {
-      const int rr = k / S, t = k - rr * S;
-      const int gj = wb + rr;
-      const int gi = wl + ((colour - 2 * gj - wl) % 7 + 7) % 7 + 7 * t;
-      const bool act = k < nitems && gi < wh;
-      const bool inner = gi >= 2 && gi <= n - 2 && gj >= 2 && gj <= n - 2;
-      const bool wave_inner = __builtin_amdgcn_ballot_w64(act && !inner) == 0;
-      if (act) {
-        const int b0 = (gj - rj0 + 1) * G::RP + (gi - ci0) + 1;
-        T py, pl;
-        if (wave_inner)
-          update_interior(b0, py, pl);
-        else
-          update_class(b0, gi, gj, py, pl);
-        if (gi >= i0 && gi < i1 && gj >= j0 && gj < j1) dx2[(gj - j0) * TW + (gi - i0)] = (T2){py, pl};
-      }
+  // update of item it (all lanes of the wave call this: the path choice is a ballot)
+  auto update = [&](const Item& it, T& py, T& pl) {
+    const bool inner = it.gi >= 2 && it.gi <= n - 2 && it.gj >= 2 && it.gj <= n - 2;
+    const bool wave_inner = __builtin_amdgcn_ballot_w64(it.act && !inner) == 0;
+    if (it.act) {
+      const int b0 = (it.gj - rj0 + 1) * G::RP + (it.gi - ci0) + 1;
+      if (wave_inner)
+        update_interior(b0, py, pl);
+      else
+        update_class(b0, it.gi, it.gj, py, pl);
     }
-    lds_barrier();
+  };
+
+  if constexpr (kOnePass) {
+#pragma unroll
+    for (int ph = 0; ph < 7; ph++) {
+      const Item it = item_of(ph, tid);
+      T py = 0, pl = 0;
+      update(it, py, pl);
+      // x of an owned vertex: the prefetched value plus its correction
+      // (masked store for other items)
+      bstore(Rx, xo[ph], xy[ph] + py);
+      bstore(Rx, xo[ph] == kOff ? kOff : xo[ph] + fo, xl[ph] + pl);
+      lds_barrier();
+    }
+  } else {
+    for (int ph = 0; ph < 7; ph++) {
+      const int d = kHalo - 1 - 2 * ph;
+      const int wl = max(ci0, i0 - d), wh = min(ci1, i1 + d);
+      const int wb = max(rj0, j0 - d), wt = min(rj1, j1 + d);
+      const int nitems = (wt - wb) * ((wh - wl + 6) / 7);
+      for (int k = tid; k < nitems; k += NT) {
+        const Item it = item_of(ph, k);
+        T py = 0, pl = 0;
+        update(it, py, pl);
+        if (owned(it)) dx2[(it.gj - j0) * TW + (it.gi - i0)] = (T2){py, pl};
+      }
+      lds_barrier();
+    }
   }
 
-  // owned tile out: r to r_out, x + corrections to x
+  // owned tile out: r to r_out (and x + corrections to x for multi-pass phases)
 #pragma unroll
   for (int q = 0; q < NX; q++) {
     const int e = tid + q * NT;
     const int oj = e / TW, oi = e - oj * TW;
     const bool ok = e < TW * TW && oi < OW && oj < OH;
     const int a = ok ? (oj + j0 - rj0 + 1) * G::RP + (oi + i0 - ci0) + 1 : 0;
-    const int od = ok ? e : 0;
     const unsigned o = ok ? (unsigned)(((j0 + oj) * ld + i0 + oi) * sizeof(T)) : kOff;
     const unsigned o2 = ok ? o + fo : kOff;
-    const T2 rv = s2[a], dv = dx2[od];
+    const T2 rv = s2[a];
     bstore(Rout, o, rv.x);
     bstore(Rout, o2, rv.y);
-    bstore(Rx, o, xy[q] + dv.x);
-    bstore(Rx, o2, xl[q] + dv.y);
+    if constexpr (!kOnePass) {
+      const T2 dv = dx2[ok ? e : 0];
+      bstore(Rx, o, xy[q] + dv.x);
+      bstore(Rx, o2, xl[q] + dv.y);
+    }
   }
 }
 
@@ -292,12 +353,12 @@ template <typename T>
 struct SweepShape;
 template <>
 struct SweepShape<double> {
-  static constexpr int NT = 1024;
+  static constexpr int TW = 48, NT = 1024;
   static constexpr int kSmallMaxN = 256;  // n of the largest level swept with small tiles
 };
 template <>
 struct SweepShape<float> {
-  static constexpr int NT = 512;
+  static constexpr int TW = 48, NT = 512;
   static constexpr int kSmallMaxN = 512;
 };
 constexpr int kSmallTW = 16, kSmallNT = 256;
@@ -309,9 +370,9 @@ hipError_t launch_tile_cfg(const Lev& L, int reverse, T* x, const T* rin, T* rou
     hipLaunchKernelGGL((k_lsgs_tile<T, kSmallTW, kSmallNT>), dim3(round8(nt * nt)), dim3(kSmallNT), 0, s, L, nt, nt,
                        reverse, x, rin, rout);
   } else {
-    constexpr int NT = SweepShape<T>::NT;
-    const int nt = tiles_along(L.n + 1, 48);
-    hipLaunchKernelGGL((k_lsgs_tile<T, 48, NT>), dim3(round8(nt * nt)), dim3(NT), 0, s, L, nt, nt, reverse, x, rin,
+    constexpr int TW = SweepShape<T>::TW, NT = SweepShape<T>::NT;
+    const int nt = tiles_along(L.n + 1, TW);
+    hipLaunchKernelGGL((k_lsgs_tile<T, TW, NT>), dim3(round8(nt * nt)), dim3(NT), 0, s, L, nt, nt, reverse, x, rin,
                        rout);
   }
   return hipGetLastError();
@@ -324,9 +385,9 @@ hipError_t launch_tile_cfg(const Lev& L, int reverse, T* x, const T* rin, T* rou
 // wider halo share would cost bandwidth.
 template <typename T>
 hipError_t launch_b_lsgs_sweep(const BInst<T>* d, int count, int n, int reverse, int sel, hipStream_t s) {
-  constexpr int NT = SweepShape<T>::NT;
-  const int nt = tiles_along(n + 1, 48);
-  hipLaunchKernelGGL((kb_lsgs_tile<T, 48, NT>), dim3(round8(nt * nt), count), dim3(NT), 0, s, d, nt, reverse, sel);
+  constexpr int TW = SweepShape<T>::TW, NT = SweepShape<T>::NT;
+  const int nt = tiles_along(n + 1, TW);
+  hipLaunchKernelGGL((kb_lsgs_tile<T, TW, NT>), dim3(round8(nt * nt), count), dim3(NT), 0, s, d, nt, reverse, sel);
   return hipGetLastError();
 }
 template hipError_t launch_b_lsgs_sweep<double>(const BInst<double>*, int, int, int, int, hipStream_t);

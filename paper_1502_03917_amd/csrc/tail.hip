@@ -90,11 +90,32 @@ __device__ __forceinline__ void tail_body(const TailArgs<T>& A) {
   }
   bar();
 
-  // (A x) at vertex (i, j) of level l from LDS array xa (both rows)
-  auto apply_v = [&](int l, const T* xa, int i, int j, T& ay, T& al) {
-    const TailLevel& L = A.lv[l];
-    const T* cb = &tC[(l * 25 + cls5(i, L.n) * 5 + cls5(j, L.n)) * kC5];
-    const T ainv = (T)A.lev[l].ainv;
+  // Level parameters are copied into registers once per operation: read
+  // from the argument block inside the vertex loops they would be fetched
+  // again after every barrier, each fetch waiting for all LDS traffic.
+  struct LP {
+    int n, ld, V, ox, or_, of;
+    T alpha, ainv;
+    const T* cb0;  // the level's class blocks
+  };
+  auto level_params = [&](int l) {
+    const TailLevel& g = A.lv[l];
+    LP p;
+    p.n = g.n;
+    p.ld = g.ld;
+    p.V = g.V;
+    p.ox = g.ox;
+    p.or_ = g.or_;
+    p.of = g.of;
+    p.alpha = (T)A.lev[l].alpha;
+    p.ainv = (T)A.lev[l].ainv;
+    p.cb0 = tC + l * 25 * kC5;
+    return p;
+  };
+
+  // (A x) at vertex (i, j) from LDS array xa (both rows)
+  auto apply_v = [&](const LP& L, const T* xa, int i, int j, T& ay, T& al) {
+    const T* cb = L.cb0 + (cls5(i, L.n) * 5 + cls5(j, L.n)) * kC5;
     ay = 0;
     al = 0;
 #pragma unroll
@@ -104,25 +125,23 @@ __device__ __forceinline__ void tail_body(const TailArgs<T>& A) {
       const int m = jj * L.ld + ii;
       const T a = xa[m], b = xa[L.V + m];
       ay += cb[d] * a + cb[kNDir + d] * b;
-      al += cb[kNDir + d] * a - ainv * cb[d] * b;
+      al += cb[kNDir + d] * a - L.ainv * cb[d] * b;
     }
   };
-  // r = f - A x on level l
-  auto residual = [&](int l) {  // no barrier inside
-    const TailLevel& L = A.lv[l];
+  // r = f - A x on one level
+  auto residual = [&](const LP& L) {  // no barrier inside
     for (int v = tid; v < L.V; v += NT) {
       const int j = v / L.ld, i = v - j * L.ld;
       T ay, al;
-      apply_v(l, sm + L.ox, i, j, ay, al);
+      apply_v(L, sm + L.ox, i, j, ay, al);
       sm[L.or_ + v] = sm[L.of + v] - ay;
       sm[L.or_ + L.V + v] = sm[L.of + L.V + v] - al;
     }
   };
   // one vertex of a Gauss-Seidel-like phase: LSGS (Alg. 2) or collective GS
-  auto gs_vertex = [&](int l, int i, int j, bool collective) {
-    const TailLevel& L = A.lv[l];
-    const T* cb = &tC[(l * 25 + cls5(i, L.n) * 5 + cls5(j, L.n)) * kC5];
-    const T al = (T)A.lev[l].alpha, ainv = (T)A.lev[l].ainv;
+  auto gs_vertex = [&](const LP& L, int i, int j, bool collective) {
+    const T* cb = L.cb0 + (cls5(i, L.n) * 5 + cls5(j, L.n)) * kC5;
+    const T al = L.alpha, ainv = L.ainv;
     T* ry = sm + L.or_;
     T* rl = ry + L.V;
     int m[kNDir];
@@ -163,28 +182,29 @@ __device__ __forceinline__ void tail_body(const TailArgs<T>& A) {
       rl[m[d]] = vb[d] - (cb[kNDir + d] * py - ainv * (cb[d] * pl));
     }
   };
-  auto gs_sweep = [&](int l, bool reverse, bool collective) {
-    const TailLevel& L = A.lv[l];
+  // one sweep in the colour order c = (i + 2j) mod 7 (reverse: c = 6..0);
+  // work item k of a phase is slot t = k mod S of row j = k / S
+  auto gs_sweep = [&](const LP& L, bool reverse, bool collective) {
     const int S = (L.ld + 6) / 7;
+    const int nit = L.ld * S;
     for (int ph = 0; ph < 7; ph++) {
       const int c = reverse ? 6 - ph : ph;
-      for (int k = tid; k < L.ld * S; k += NT) {
+      for (int k = tid; k < nit; k += NT) {
         const int j = k / S, t = k - j * S;
         const int i = ((c - 2 * j) % 7 + 7) % 7 + 7 * t;
-        if (i <= L.n) gs_vertex(l, i, j, collective);
+        if (i <= L.n) gs_vertex(L, i, j, collective);
       }
       bar();
     }
   };
   // normal-equation step (Alg. 1): p = tau L^-1 A^T L^-1 r for all unknowns, x += p, r -= A p
-  auto ne_step = [&](int l) {
-    const TailLevel& L = A.lv[l];
-    const T al = (T)A.lev[l].alpha, tau = (T)A.tau;
+  auto ne_step = [&](const LP& L) {
+    const T al = L.alpha, tau = (T)A.tau;
     const T* ry = sm + L.or_;
     const T* rl = ry + L.V;
     for (int v = tid; v < L.V; v += NT) {
       const int j = v / L.ld, i = v - j * L.ld;
-      const T* cb = &tC[(l * 25 + cls5(i, L.n) * 5 + cls5(j, L.n)) * kC5];
+      const T* cb = L.cb0 + (cls5(i, L.n) * 5 + cls5(j, L.n)) * kC5;
       T qy = 0, ql = 0, wv = 0;
 #pragma unroll
       for (int d = 0; d < kNDir; d++) {
@@ -206,7 +226,7 @@ __device__ __forceinline__ void tail_body(const TailArgs<T>& A) {
     for (int v = tid; v < L.V; v += NT) {
       const int j = v / L.ld, i = v - j * L.ld;
       T ay, alv;
-      apply_v(l, sp, i, j, ay, alv);
+      apply_v(L, sp, i, j, ay, alv);
       sm[L.or_ + v] -= ay;
       sm[L.or_ + L.V + v] -= alv;
     }
@@ -218,7 +238,7 @@ __device__ __forceinline__ void tail_body(const TailArgs<T>& A) {
     const TailLevel& L = A.lv[Tl];
     for (int e = tid; e < 2 * L.V; e += NT) sm[L.or_ + e] = sm[L.of + e];
   } else {
-    residual(Tl);
+    residual(level_params(Tl));
   }
   bar();
 
@@ -226,26 +246,29 @@ __device__ __forceinline__ void tail_body(const TailArgs<T>& A) {
     const int4 op = A.ops[o];
     const int l = op.y;
     switch (op.x) {
-      case kTailSmooth:
+      case kTailSmooth: {
+        const LP P = level_params(l);
+        const int sm_kind = A.smoother;
         for (int s = 0; s < op.z; s++) {
-          if (A.smoother == MG_TAIL_NE)
-            ne_step(l);
-          else if (A.smoother == MG_TAIL_LSGS)
-            gs_sweep(l, false, false);
-          else if (A.smoother == MG_TAIL_SLSGS) {
-            gs_sweep(l, false, false);
-            gs_sweep(l, true, false);
+          if (sm_kind == MG_TAIL_NE)
+            ne_step(P);
+          else if (sm_kind == MG_TAIL_LSGS)
+            gs_sweep(P, false, false);
+          else if (sm_kind == MG_TAIL_SLSGS) {
+            gs_sweep(P, false, false);
+            gs_sweep(P, true, false);
           } else
-            gs_sweep(l, false, true);
+            gs_sweep(P, false, true);
         }
         break;
+      }
       case kTailResidual:
-        residual(l);
+        residual(level_params(l));
         bar();
         break;
       case kTailRestrict: {  // f_{l-1} = P^T r_l; if l-1 > k0: x_{l-1} = 0, r_{l-1} = f_{l-1}
-        const TailLevel& Lf = A.lv[l];
-        const TailLevel& Lc = A.lv[l - 1];
+        const TailLevel Lf = A.lv[l];
+        const TailLevel Lc = A.lv[l - 1];
         for (int w = tid; w < Lc.V; w += NT) {
           const int J = w / Lc.ld, I = w - J * Lc.ld;
           const int a = 2 * I, b = 2 * J;
@@ -276,7 +299,7 @@ __device__ __forceinline__ void tail_body(const TailArgs<T>& A) {
         // one wave, one row per lane (N0 <= 64): the permuted right-hand side,
         // then forward (unit lower) and back substitution with the pivot
         // entry of each step broadcast from its lane; no workgroup barriers
-        const TailLevel& Lc = A.lv[k0];
+        const TailLevel Lc = A.lv[k0];
         if (tid < 64) {
           const int* perm = A.piv + N0;
           double v = tid < N0 ? (double)sm[Lc.of + perm[tid]] : 0.0;
@@ -295,8 +318,8 @@ __device__ __forceinline__ void tail_body(const TailArgs<T>& A) {
         break;
       }
       case kTailProlongResidual: {  // x_l += P x_{l-1}, then r_l = f_l - A x_l
-        const TailLevel& Lf = A.lv[l];
-        const TailLevel& Lc = A.lv[l - 1];
+        const TailLevel Lf = A.lv[l];
+        const TailLevel Lc = A.lv[l - 1];
         for (int u = tid; u < Lf.V; u += NT) {
           const int b = u / Lf.ld, a = u - b * Lf.ld;
           const int w0 = (b >> 1) * Lc.ld + (a >> 1), w1 = ((b + 1) >> 1) * Lc.ld + ((a + 1) >> 1);
@@ -312,7 +335,7 @@ __device__ __forceinline__ void tail_body(const TailArgs<T>& A) {
           sm[Lf.ox + Lf.V + u] += vl;
         }
         bar();
-        residual(l);
+        residual(level_params(l));
         bar();
         break;
       }
