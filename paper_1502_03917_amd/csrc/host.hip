@@ -229,6 +229,11 @@ struct mg_ctx {
   bool tail_allowed = true;
   int4* d_tail_ops = nullptr;
   mgk::TailLaunch tail{};
+  // precomputed coarse map of the tail (the sub-cycle on level kTailMapLevel
+  // and below as a dense matrix); map_allowed: MGKKT_NO_MAP unset
+  bool map_allowed = true;
+  double* d_map64 = nullptr;
+  float* d_map32 = nullptr;
   // HIP graph of one solver iterate (cycle + residual norm) for fixed f, x
   hipStream_t cap_stream = nullptr;  // capture stream (default priority)
   bool graphs = true;
@@ -321,6 +326,8 @@ void destroy_impl(mg_ctx* c) {
   (void)hipFree(c->d_lu);
   (void)hipFree(c->d_piv);
   (void)hipFree(c->d_tail_ops);
+  (void)hipFree(c->d_map64);
+  (void)hipFree(c->d_map32);
   (void)hipFree(c->d_part);
   (void)hipFree(c->d_norm);
   if (c->h_norm) (void)hipHostFree(c->h_norm);
@@ -438,20 +445,79 @@ int coarse_solve_T(mg_ctx* c, const T* f, T* x, hipStream_t s) {
 // Op list of one iterate on level l of the tail (same steps as cycle_body):
 // nu1 smoothing steps, restriction (x_{l-1} = 0, r_{l-1} = f_{l-1}), gamma
 // coarse iterates (a fresh residual before the second), prolongation with the
-// new residual, nu2 smoothing steps; the coarsest level is the LU solve.
-void tail_ops(const mg_ctx* c, int l, std::vector<int4>& ops) {
+// new residual, nu2 smoothing steps; the coarsest level is the LU solve.  On
+// level map_level (0: none) an iterate is x += B r with the precomputed map B
+// of the sub-cycle from zero (an iterate of a linear method from x equals
+// x + B (f - A x)).
+void tail_ops(const mg_ctx* c, int l, std::vector<int4>& ops, int map_level) {
   if (l == c->k0) {
     ops.push_back(make_int4(mgk::kTailCoarse, l, 0, 0));
+    return;
+  }
+  if (l == map_level) {
+    ops.push_back(make_int4(mgk::kTailApplyMap, l, 0, 0));
     return;
   }
   if (c->o.nu1) ops.push_back(make_int4(mgk::kTailSmooth, l, c->o.nu1, 0));
   ops.push_back(make_int4(mgk::kTailRestrict, l, 0, 0));
   for (int g = 0; g < c->o.gamma; g++) {
     if (g > 0 && l - 1 > c->k0) ops.push_back(make_int4(mgk::kTailResidual, l - 1, 0, 0));
-    tail_ops(c, l - 1, ops);
+    tail_ops(c, l - 1, ops, map_level);
   }
   ops.push_back(make_int4(mgk::kTailProlongResidual, l, 0, 0));
   if (c->o.nu2) ops.push_back(make_int4(mgk::kTailSmooth, l, c->o.nu2, 0));
+}
+
+// The coarse map B of level kTailMapLevel: column i is the tail's sub-cycle on
+// that level (with everything below it) applied to the unit vector e_i, all
+// columns computed by one batched tail launch.  Stored column-major in FP64
+// and as an FP32 copy for the FP32 cycles.
+int build_coarse_map(mg_ctx* c, const mgk::TailLaunch& base, size_t lds_bytes) {
+  constexpr int ML = mgk::kTailMapLevel;
+  const int N = 2 * ((1 << ML) + 1) * ((1 << ML) + 1);
+  std::vector<int4> ops;
+  tail_ops(c, ML, ops, 0);
+  mgk::TailLaunch t = base;
+  t.T = ML;
+  t.nops = (int)ops.size();
+  t.map64 = nullptr;
+  t.map32 = nullptr;
+  t.nmap = 0;
+  int4* d_ops = nullptr;
+  double* d_id = nullptr;
+  void* d_args = nullptr;
+  auto done = [&](int st) {
+    (void)hipFree(d_ops);
+    (void)hipFree(d_id);
+    (void)hipFree(d_args);
+    return st;
+  };
+  if (hipMalloc(&d_ops, ops.size() * sizeof(int4)) != hipSuccess ||
+      hipMalloc(&d_id, (size_t)N * N * sizeof(double)) != hipSuccess ||
+      hipMalloc(&c->d_map64, (size_t)N * N * sizeof(double)) != hipSuccess ||
+      hipMalloc(&c->d_map32, (size_t)N * N * sizeof(float)) != hipSuccess)
+    return done(fail(c, MG_ENOMEM, "coarse map: device allocation failed"));
+  std::vector<double> id((size_t)N * N, 0.0);
+  for (int i = 0; i < N; i++) id[(size_t)i * N + i] = 1.0;
+  t.ops = d_ops;
+  const size_t sz = mgk::tail_args_bytes<double>();
+  std::vector<unsigned char> args((size_t)N * sz);
+  for (int i = 0; i < N; i++)
+    mgk::make_tail_args<double>(t, d_id + (size_t)i * N, c->d_map64 + (size_t)i * N, 1, nullptr, args.data() + i * sz);
+  if (hipMalloc(&d_args, args.size()) != hipSuccess) return done(fail(c, MG_ENOMEM, "coarse map: device allocation failed"));
+  hipError_t e = hipMemcpy(d_ops, ops.data(), ops.size() * sizeof(int4), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(d_id, id.data(), id.size() * sizeof(double), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(d_args, args.data(), args.size(), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = mgk::launch_b_tail<double>(d_args, N, lds_bytes, nullptr);
+  if (e == hipSuccess) e = hipDeviceSynchronize();
+  std::vector<double> m64((size_t)N * N);
+  if (e == hipSuccess) e = hipMemcpy(m64.data(), c->d_map64, m64.size() * sizeof(double), hipMemcpyDeviceToHost);
+  std::vector<float> m32(m64.begin(), m64.end());
+  if (e == hipSuccess) e = hipMemcpy(c->d_map32, m32.data(), m32.size() * sizeof(float), hipMemcpyHostToDevice);
+  if (e != hipSuccess) return done(fail(c, MG_EHIP, std::string("coarse map: ") + hipGetErrorString(e)));
+  for (double v : m64)
+    if (!std::isfinite(v)) return done(fail(c, MG_EHIP, "coarse map: non-finite entry"));
+  return done(MG_OK);
 }
 
 // (Re)build the tail for the context's options; tail level min(5, level - 1).
@@ -459,22 +525,21 @@ void tail_ops(const mg_ctx* c, int l, std::vector<int4>& ops) {
 // (2 (2^k0 + 1)^2 <= 64).
 int setup_tail(mg_ctx* c) {
   (void)hipFree(c->d_tail_ops);
+  (void)hipFree(c->d_map64);
+  (void)hipFree(c->d_map32);
   c->d_tail_ops = nullptr;
+  c->d_map64 = nullptr;
+  c->d_map32 = nullptr;
   c->tail_T = 0;
   const int T = c->level - 1 < 5 ? c->level - 1 : 5;
   if (!c->tail_allowed || T <= c->k0 || c->k0 > 2 || c->problem != MG_POISSON) return MG_OK;
-  std::vector<int4> ops;
-  tail_ops(c, T, ops);
-  HIPCHK(c, hipMalloc(&c->d_tail_ops, ops.size() * sizeof(int4)));
-  HIPCHK(c, hipMemcpy(c->d_tail_ops, ops.data(), ops.size() * sizeof(int4), hipMemcpyHostToDevice));
   mgk::TailLaunch& t = c->tail;
+  t = mgk::TailLaunch{};
   t.k0 = c->k0;
   t.T = T;
-  t.nops = (int)ops.size();
   static const int map[4] = {mgk::MG_TAIL_NE, mgk::MG_TAIL_LSGS, mgk::MG_TAIL_SLSGS, mgk::MG_TAIL_CGS};
   t.smoother = map[c->o.smoother];
   t.tau = c->o.tau;
-  t.ops = c->d_tail_ops;
   t.lu = c->d_lu;
   t.piv = c->d_piv;
   t.ncoarse = c->ncoarse;
@@ -486,6 +551,23 @@ int setup_tail(mg_ctx* c) {
   t.max_lds = (size_t)maxlds;
   if (need > t.max_lds) return MG_OK;  // does not fit: no tail
   HIPCHK(c, mgk::tail_allow_lds(need));
+  // the coarse map replaces the sub-cycle on level kTailMapLevel when the
+  // tail reaches above it
+  int map_level = 0;
+  if (c->map_allowed && T > mgk::kTailMapLevel && c->k0 < mgk::kTailMapLevel) {
+    int st = build_coarse_map(c, t, mgk::tail_lds_bytes<double>(c->k0, mgk::kTailMapLevel));
+    if (st != MG_OK) return st;
+    map_level = mgk::kTailMapLevel;
+    t.map64 = c->d_map64;
+    t.map32 = c->d_map32;
+    t.nmap = 2 * ((1 << map_level) + 1) * ((1 << map_level) + 1);
+  }
+  std::vector<int4> ops;
+  tail_ops(c, T, ops, map_level);
+  HIPCHK(c, hipMalloc(&c->d_tail_ops, ops.size() * sizeof(int4)));
+  HIPCHK(c, hipMemcpy(c->d_tail_ops, ops.data(), ops.size() * sizeof(int4), hipMemcpyHostToDevice));
+  t.nops = (int)ops.size();
+  t.ops = c->d_tail_ops;
   c->tail_T = T;
   return MG_OK;
 }
@@ -748,6 +830,9 @@ int mg_setup(int level, double alpha, int problem, const mg_opts* opts, mg_ctx**
     // MGKKT_NO_TAIL=1 runs the coarse levels with the per-level kernels
     const char* t = std::getenv("MGKKT_NO_TAIL");
     c->tail_allowed = !(t && t[0] == '1');
+    // MGKKT_NO_MAP=1 runs the tail's sub-cycle on every level instead of the coarse map
+    const char* m = std::getenv("MGKKT_NO_MAP");
+    c->map_allowed = !(m && m[0] == '1');
     // MGKKT_NO_GRAPH=1 makes mg_solve launch every kernel eagerly
     const char* g = std::getenv("MGKKT_NO_GRAPH");
     c->graphs = !(g && g[0] == '1');

@@ -52,7 +52,11 @@ struct Lev {
 // levels k0..T from a host-built op list
 constexpr int kTailMaxLevels = 6;  // highest tail level supported
 constexpr int kTailThreads = 256;  // a few waves: the tail is a chain of small barrier-separated steps
-enum { kTailSmooth = 1, kTailResidual = 2, kTailRestrict = 3, kTailCoarse = 4, kTailProlongResidual = 5 };
+enum { kTailSmooth = 1, kTailResidual = 2, kTailRestrict = 3, kTailCoarse = 4, kTailProlongResidual = 5, kTailApplyMap = 6 };
+// Level of the precomputed coarse map: from x = 0 the sub-cycle on this level
+// (and everything below it) is a fixed linear map of the level's residual,
+// kept as a dense matrix (2 (2^3 + 1)^2 = 162 unknowns)
+constexpr int kTailMapLevel = 3;
 enum { MG_TAIL_NE = 0, MG_TAIL_LSGS = 1, MG_TAIL_SLSGS = 2, MG_TAIL_CGS = 3 };
 struct TailLaunch {
   int k0, T, nops, smoother, ncoarse;
@@ -60,6 +64,11 @@ struct TailLaunch {
   const int4* ops;  // device op list (x = op, y = level, z = count)
   const double* lu;
   const int* piv;
+  // coarse map of level kTailMapLevel: column-major N x N (entry (r, c) at
+  // c * N + r), FP64 and FP32 copies; nullptr: not used
+  const double* map64;
+  const float* map32;
+  int nmap;
   Lev lev[kTailMaxLevels + 1];
   size_t max_lds;
 };

@@ -10,6 +10,7 @@
 // vertices use the per-class coefficient blocks of the level table, so
 // boundary and interior vertices take the same path.
 #include <cstring>
+#include <type_traits>
 
 #include "mg_internal.hpp"
 
@@ -50,6 +51,8 @@ struct TailArgs {
   const double* lu;      // coarsest LU factors
   const int* piv;        // row interchanges (ncoarse), then the permutation they compose to (ncoarse)
   int ncoarse;
+  const T* map;          // coarse map of level kTailMapLevel (column-major, nmap x nmap), or nullptr
+  int nmap;
   const T* fT;           // f on level T (global)
   T* xT;                 // x on level T (global): in (if !first) / out
   int first;             // 1: x_T starts at zero and r_T = f_T
@@ -69,17 +72,27 @@ __device__ __forceinline__ void tail_body(const TailArgs<T>& A) {
   const int Tl = A.tlev, k0 = A.k0;
   int off_end = 0;
   for (int l = k0; l <= Tl; l++) off_end = max(off_end, A.lv[l].of + 2 * A.lv[l].V);
-  T* tC = sm + off_end;                                 // 25 * kC5 per level l in (k0, T]
-  // NE scratch (2 V_T entries, also the coarse right-hand side in FP64), 16-byte aligned
-  T* sp = reinterpret_cast<T*>((reinterpret_cast<size_t>(tC + (kTailMaxLevels + 1) * 25 * kC5) + 15) & ~size_t(15));
-  double* slu = reinterpret_cast<double*>(
-      (reinterpret_cast<size_t>(sp) + tail_scratch_bytes<T>(A.lv[Tl].V, A.ncoarse) + 15) & ~size_t(15));
+  // All shared pointers are byte offsets from the LDS base: a pointer that
+  // went through an integer would lose its address space and every access
+  // through it would become a flat (generic) memory operation.
+  auto align16 = [](size_t b) { return (b + 15) & ~size_t(15); };
+  const size_t off_sp =
+      align16((size_t)off_end * sizeof(T) + (size_t)(kTailMaxLevels + 1) * 25 * kC5 * sizeof(T));
+  const size_t off_lu = align16(off_sp + tail_scratch_bytes<T>(A.lv[Tl].V, A.ncoarse));
   const int N0 = A.ncoarse;
+  T* tC = sm + off_end;                                   // 25 * kC5 per level l in (k0, T]
+  T* sp = reinterpret_cast<T*>(smem_raw + off_sp);        // NE scratch (2 V_T), also the coarse rhs in FP64
+  double* slu = reinterpret_cast<double*>(smem_raw + off_lu);  // coarsest LU factors
+  // two zero cells (one per field): neighbours outside the square are read
+  // from and written to them, so every access of a vertex update is
+  // unconditional (their coefficients are zero, so they stay zero)
+  T* zs = reinterpret_cast<T*>(smem_raw + off_lu + (size_t)N0 * N0 * sizeof(double));
 
   // ---- load tables, LU, f_T and x_T
   for (int l = k0 + 1; l <= Tl; l++)
     for (int e = tid; e < 25 * kC5; e += NT) tC[l * 25 * kC5 + e] = (T)(&A.lev[l].tab->C5[0][0])[e];
   for (int e = tid; e < N0 * N0; e += NT) slu[e] = A.lu[e];
+  if (tid < 2) zs[tid] = (T)0;
   {
     const TailLevel& L = A.lv[Tl];
     for (int e = tid; e < 2 * L.V; e += NT) {
@@ -121,9 +134,9 @@ __device__ __forceinline__ void tail_body(const TailArgs<T>& A) {
 #pragma unroll
     for (int d = 0; d < kNDir; d++) {
       const int ii = i + kDI[d], jj = j + kDJ[d];
-      if (ii < 0 || jj < 0 || ii > L.n || jj > L.n) continue;
+      const bool in = ii >= 0 && jj >= 0 && ii <= L.n && jj <= L.n;
       const int m = jj * L.ld + ii;
-      const T a = xa[m], b = xa[L.V + m];
+      const T a = *(in ? xa + m : zs), b = *(in ? xa + L.V + m : zs + 1);
       ay += cb[d] * a + cb[kNDir + d] * b;
       al += cb[kNDir + d] * a - L.ainv * cb[d] * b;
     }
@@ -144,43 +157,55 @@ __device__ __forceinline__ void tail_body(const TailArgs<T>& A) {
     const T al = L.alpha, ainv = L.ainv;
     T* ry = sm + L.or_;
     T* rl = ry + L.V;
-    int m[kNDir];
-    bool in[kNDir];
+    // the class block in registers before any store: all shared arrays live
+    // in one LDS block, so a store could alias it as far as the compiler knows
+    T cm[kNDir], ck[kNDir], cw[kNDir];
+#pragma unroll
+    for (int d = 0; d < kNDir; d++) {
+      cm[d] = cb[d];
+      ck[d] = cb[kNDir + d];
+      cw[d] = cb[2 * kNDir + d];
+    }
+    const T nyi = cb[3 * kNDir], nli = cb[3 * kNDir + 1];
+    T* pa[kNDir];
+    T* pb[kNDir];
     T va[kNDir], vb[kNDir];
 #pragma unroll
     for (int d = 0; d < kNDir; d++) {
       const int ii = i + kDI[d], jj = j + kDJ[d];
-      in[d] = ii >= 0 && jj >= 0 && ii <= L.n && jj <= L.n;
-      m[d] = in[d] ? jj * L.ld + ii : j * L.ld + i;
-      va[d] = ry[m[d]];
-      vb[d] = rl[m[d]];
+      const bool in = ii >= 0 && jj >= 0 && ii <= L.n && jj <= L.n;
+      const int m = jj * L.ld + ii;
+      pa[d] = in ? ry + m : zs;
+      pb[d] = in ? rl + m : zs + 1;
+      va[d] = *pa[d];
+      vb[d] = *pb[d];
     }
     T py, pl;
     if (!collective) {
       T qy = 0, ql = 0;
 #pragma unroll
       for (int d = 0; d < kNDir; d++) {
-        const T mm = cb[d], k = cb[kNDir + d], wi = cb[2 * kNDir + d];
-        qy += (mm * va[d] + al * k * vb[d]) * wi;
-        ql += (k * va[d] - mm * vb[d]) * wi;
+        qy += (cm[d] * va[d] + al * ck[d] * vb[d]) * cw[d];
+        ql += (ck[d] * va[d] - cm[d] * vb[d]) * cw[d];
       }
-      py = qy * cb[3 * kNDir];
-      pl = ql * cb[3 * kNDir + 1];
+      py = qy * nyi;
+      pl = ql * nli;
     } else {
-      const T b11 = cb[0], b12 = cb[kNDir], b21 = cb[kNDir], b22 = -ainv * cb[0];
+      const T b11 = cm[0], b12 = ck[0], b21 = ck[0], b22 = -ainv * cm[0];
       const T det = b11 * b22 - b12 * b21;
       py = (b22 * va[0] - b12 * vb[0]) / det;
       pl = (b11 * vb[0] - b21 * va[0]) / det;
     }
     const int v = j * L.ld + i;
-    sm[L.ox + v] += py;
-    sm[L.ox + L.V + v] += pl;
+    T* xy = sm + L.ox + v;
+    const T x0 = xy[0], x1 = xy[L.V];
 #pragma unroll
     for (int d = 0; d < kNDir; d++) {
-      if (!in[d]) continue;
-      ry[m[d]] = va[d] - (cb[d] * py + cb[kNDir + d] * pl);
-      rl[m[d]] = vb[d] - (cb[kNDir + d] * py - ainv * (cb[d] * pl));
+      *pa[d] = va[d] - (cm[d] * py + ck[d] * pl);
+      *pb[d] = vb[d] - (ck[d] * py - ainv * (cm[d] * pl));
     }
+    xy[0] = x0 + py;
+    xy[L.V] = x1 + pl;
   };
   // one sweep in the colour order c = (i + 2j) mod 7 (reverse: c = 6..0);
   // work item k of a phase is slot t = k mod S of row j = k / S
@@ -209,11 +234,12 @@ __device__ __forceinline__ void tail_body(const TailArgs<T>& A) {
 #pragma unroll
       for (int d = 0; d < kNDir; d++) {
         const int ii = i + kDI[d], jj = j + kDJ[d];
-        if (ii < 0 || jj < 0 || ii > L.n || jj > L.n) continue;
+        const bool in = ii >= 0 && jj >= 0 && ii <= L.n && jj <= L.n;
         const int m = jj * L.ld + ii;
+        const T a = *(in ? ry + m : zs), b = *(in ? rl + m : zs + 1);
         const T mm = cb[d], k = cb[kNDir + d], wi = cb[2 * kNDir + d];
-        qy += (mm * ry[m] + al * k * rl[m]) * wi;
-        ql += (k * ry[m] - mm * rl[m]) * wi;
+        qy += (mm * a + al * k * b) * wi;
+        ql += (k * a - mm * b) * wi;
         if (d == 0) wv = wi;
       }
       const T py = tau * qy * wv, pl = tau * ql * (al * wv);
@@ -339,6 +365,23 @@ __device__ __forceinline__ void tail_body(const TailArgs<T>& A) {
         bar();
         break;
       }
+      case kTailApplyMap: {  // x_l += B r_l: the whole sub-cycle on level l and below, from zero
+        const LP P = level_params(l);
+        const int N = A.nmap;
+        if (tid < N) {
+          const T* rv = sm + P.or_;
+          T acc0 = 0, acc1 = 0;
+          int c = 0;
+          for (; c + 1 < N; c += 2) {
+            acc0 += A.map[(size_t)c * N + tid] * rv[c];
+            acc1 += A.map[(size_t)(c + 1) * N + tid] * rv[c + 1];
+          }
+          if (c < N) acc0 += A.map[(size_t)c * N + tid] * rv[c];
+          sm[P.ox + tid] += acc0 + acc1;
+        }
+        bar();
+        break;
+      }
       default:
         break;
     }
@@ -382,7 +425,7 @@ size_t tail_layout(int k0, int Tl, TailLevel* lv) {
   }
   const int N0 = 2 * ((1 << k0) + 1) * ((1 << k0) + 1);
   return (size_t)at * sizeof(T) + (size_t)(kTailMaxLevels + 1) * 25 * kC5 * sizeof(T) + 16 +
-         tail_scratch_bytes<T>(lv[Tl].V, N0) + 16 + (size_t)N0 * N0 * sizeof(double);
+         tail_scratch_bytes<T>(lv[Tl].V, N0) + 16 + (size_t)N0 * N0 * sizeof(double) + 2 * sizeof(T);
 }
 
 template <typename T>
@@ -399,6 +442,11 @@ size_t fill_tail_args(const TailLaunch& tl, const T* fT, T* xT, int first, const
   a.lu = tl.lu;
   a.piv = tl.piv;
   a.ncoarse = tl.ncoarse;
+  if constexpr (std::is_same<T, double>::value)
+    a.map = tl.map64;
+  else
+    a.map = tl.map32;
+  a.nmap = tl.nmap;
   a.fT = fT;
   a.xT = xT;
   a.first = first;

@@ -225,6 +225,33 @@ def test_capture_cycle_replays_match_eager(torch_cuda, problem, precision):
     torch.cuda.synchronize()
 
 
+@pytest.mark.parametrize("smoother,gamma", [("lsgs", 1), ("ne", 1), ("slsgs", 2), ("lsgs", 2)])
+def test_coarse_map_equals_subcycle(torch_cuda, monkeypatch, smoother, gamma):
+    # the tail's precomputed map of the level-3 sub-cycle gives the same
+    # iterates as running that sub-cycle (MGKKT_NO_MAP=1), to rounding, for
+    # V- and W-cycles, in FP64 and in FP32 refinement
+    torch = torch_cuda
+    mg = _mg()
+    level, alpha = 7, 1e-3
+    nu = 1 if smoother == "slsgs" else 2
+    yd = _dev(torch, workloads.desired_state(level, 3))
+    for precision, bound in (("fp64", 1e-13), ("fp32_ir", 1e-5)):
+        xs = []
+        for env in (None, "1"):
+            if env:
+                monkeypatch.setenv("MGKKT_NO_MAP", env)
+            else:
+                monkeypatch.delenv("MGKKT_NO_MAP", raising=False)
+            s = mg.Solver(level, alpha, smoother=smoother, gamma=gamma, nu1=nu, nu2=nu, precision=precision)
+            f = s.rhs(yd)
+            x = torch.zeros_like(f)
+            for _ in range(3):
+                s.cycle(f, x)
+            xs.append(_host(x))
+        monkeypatch.delenv("MGKKT_NO_MAP", raising=False)
+        assert np.linalg.norm(xs[0] - xs[1]) <= bound * np.linalg.norm(xs[1]), precision
+
+
 CYCLE_CASES = [
     (5, 1e-2, "lsgs", 1),
     (5, 1e-2, "ne", 1),
