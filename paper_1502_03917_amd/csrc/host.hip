@@ -232,6 +232,8 @@ struct mg_ctx {
   // precomputed coarse map of the tail (the sub-cycle on level kTailMapLevel
   // and below as a dense matrix); map_allowed: MGKKT_NO_MAP unset
   bool map_allowed = true;
+  // the last post-smoothing sweep supplies the residual norm (MGKKT_NO_SWEEP_NORM unset)
+  bool sweep_norm_allowed = true;
   double* d_map64 = nullptr;
   float* d_map32 = nullptr;
   // HIP graph of one solver iterate (cycle + residual norm) for fixed f, x
@@ -391,13 +393,36 @@ hipEvent_t timing_begin(mg_ctx* c, hipStream_t s, size_t* slot) {
 // `steps` smoothing steps on level l.  r holds f - A x on entry; the fused
 // LSGS sweeps alternate between r and alt, and r is updated to the buffer
 // holding the current residual on return.
+// Residual norm of the last sweep (FP64 tile sweeps only): when part is
+// given, the last sweep also stores per-tile partial sums of ||r||^2 of the
+// residual it leaves (norm mode `mode`) and *nb receives their number.
+struct SweepNorm {
+  double* part = nullptr;
+  int mode = 0;
+  int* nb = nullptr;
+};
+
 template <typename T>
-int smooth_steps(mg_ctx* c, int l, T* x, T*& r, T* alt, T* p, int steps, hipStream_t s) {
+hipError_t last_sweep(const Lev& L, int reverse, const T* xin, T* x, const T* rin, T* rout, const SweepNorm& sn,
+                      hipStream_t s) {
+  if constexpr (std::is_same<T, double>::value) {
+    if (sn.part) return mgk::launch_lsgs_sweep_norm(L, reverse, xin, x, rin, rout, sn.part, sn.mode, sn.nb, s);
+  }
+  return mgk::launch_lsgs_sweep_from<T>(L, reverse, xin, x, rin, rout, s);
+}
+
+template <typename T>
+int smooth_steps(mg_ctx* c, int l, T* x, T*& r, T* alt, T* p, int steps, hipStream_t s, const T* xin0 = nullptr,
+                 const SweepNorm& sn = SweepNorm{}) {
   LevelBuf& b = L_(c, l);
   const Lev& L = b.lev;
   const bool timed = c->timing && l == c->level && !c->capturing;
   const bool fused = c->fused && alt != nullptr;
   for (int it = 0; it < steps; it++) {
+    // the first tile sweep may take the iterate from xin0 (fused prolongation)
+    const T* xin = (it == 0 && xin0) ? xin0 : x;
+    const SweepNorm none{};
+    const SweepNorm& snl = (it == steps - 1) ? sn : none;
     size_t slot = 0;
     hipEvent_t stop = nullptr;
     if (timed) stop = timing_begin(c, s, &slot);
@@ -407,7 +432,7 @@ int smooth_steps(mg_ctx* c, int l, T* x, T*& r, T* alt, T* p, int steps, hipStre
         break;
       case MG_LSGS:
         if (fused) {
-          HIPCHK(c, mgk::launch_lsgs_sweep<T>(L, 0, x, r, alt, s));
+          HIPCHK(c, last_sweep<T>(L, 0, xin, x, r, alt, snl, s));
           std::swap(r, alt);
         } else {
           for (int col = 0; col < 7; col++) HIPCHK(c, mgk::launch_lsgs_phase<T>(L, col, x, r, s));
@@ -415,8 +440,8 @@ int smooth_steps(mg_ctx* c, int l, T* x, T*& r, T* alt, T* p, int steps, hipStre
         break;
       case MG_SLSGS:
         if (fused) {
-          HIPCHK(c, mgk::launch_lsgs_sweep<T>(L, 0, x, r, alt, s));
-          HIPCHK(c, mgk::launch_lsgs_sweep<T>(L, 1, x, alt, r, s));
+          HIPCHK(c, mgk::launch_lsgs_sweep_from<T>(L, 0, xin, x, r, alt, s));
+          HIPCHK(c, last_sweep<T>(L, 1, x, x, alt, r, snl, s));
         } else {
           for (int col = 0; col < 7; col++) HIPCHK(c, mgk::launch_lsgs_phase<T>(L, col, x, r, s));
           for (int col = 6; col >= 0; col--) HIPCHK(c, mgk::launch_lsgs_phase<T>(L, col, x, r, s));
@@ -575,7 +600,8 @@ int setup_tail(mg_ctx* c) {
 // One iterate on level l for A_l x = f; r is level-l workspace (one of the
 // level's two residual buffers).  If residual_current, r already holds f - A_l x.
 template <typename T>
-int cycle_body(mg_ctx* c, int l, const T* f, T* x, T* r, bool residual_current, hipStream_t s) {
+int cycle_body(mg_ctx* c, int l, const T* f, T* x, T* r, bool residual_current, hipStream_t s,
+               const SweepNorm& sn = SweepNorm{}) {
   if (l == c->k0) return coarse_solve_T<T>(c, f, x, s);
   LevelBuf& b = L_(c, l);
   LevelBuf& bc = L_(c, l - 1);
@@ -596,6 +622,14 @@ int cycle_body(mg_ctx* c, int l, const T* f, T* x, T* r, bool residual_current, 
       HIPCHK(c, mgk::launch_tail<T>(c->tail, wc.f, wc.x, g == 0 ? 1 : 0, s));
     else if ((st = cycle_body<T>(c, l - 1, wc.f, wc.x, wc.r, g == 0, s)) != MG_OK)
       return st;
+  }
+  // x += P x_c and r = f - A x.  Before a tile-sweep post-smoother both go in
+  // one kernel that writes the corrected iterate to the level's scratch p
+  // (unused by LSGS); the first sweep reads it from there and writes x.
+  const bool fuse = c->fused && c->o.nu2 > 0 && (c->o.smoother == MG_LSGS || c->o.smoother == MG_SLSGS);
+  if (fuse) {
+    HIPCHK(c, mgk::launch_prolong_residual<T>(b.lev, bc.lev, wc.x, x, f, wb.p, r, s));
+    return smooth_steps<T>(c, l, x, r, alt, wb.p, c->o.nu2, s, wb.p, sn);
   }
   HIPCHK(c, mgk::launch_prolong_add<T>(b.lev, bc.lev, wc.x, x, s));
   HIPCHK(c, mgk::launch_residual<T>(b.lev, f, x, r, nullptr, 0, nullptr, s));
@@ -662,6 +696,16 @@ int ir_step(mg_ctx* c, double* x, hipStream_t s) {
 // the residual buffer of the finest level
 double* fine_r(mg_ctx* c) { return c->st ? mgk::stokes_fine_r(c->st) : L_(c, c->level).r; }
 
+// FP64 Poisson iterates whose last post-smoothing step is a tile sweep that
+// leaves the residual in the finest level's first buffer (an even number of
+// LSGS sweeps per cycle, or sLSGS) take the residual norm from that sweep.
+bool sweep_norm(const mg_ctx* c) {
+  if (c->st || !c->sweep_norm_allowed || c->o.precision != MG_FP64 || !c->fused || c->o.nu2 < 1 || c->timing)
+    return false;
+  if (c->o.smoother == MG_SLSGS) return true;
+  return c->o.smoother == MG_LSGS && (c->o.nu1 + c->o.nu2) % 2 == 0;
+}
+
 int iterate(mg_ctx* c, const double* f, double* x, hipStream_t s) {
   if (c->st) {
     if (c->o.precision == MG_FP32_IR)
@@ -671,6 +715,19 @@ int iterate(mg_ctx* c, const double* f, double* x, hipStream_t s) {
     return residual_norm(c, f, x, fine_r(c), 0, s);
   }
   LevelBuf& b = L_(c, c->level);
+  if (sweep_norm(c)) {
+    // the last post-smoothing sweep leaves r = f - A x (maintained by the
+    // smoother) in b.r and sums its squared norm: no separate residual pass
+    int nb = 0;
+    SweepNorm sn;
+    sn.part = c->d_part;
+    sn.mode = norm_mode(c);
+    sn.nb = &nb;
+    int st = cycle_body<double>(c, c->level, f, x, b.r, true, s, sn);
+    if (st != MG_OK) return st;
+    HIPCHK(c, mgk::launch_sum(c->d_part, nb, c->d_norm, s));
+    return MG_OK;
+  }
   int st = c->o.precision == MG_FP32_IR ? ir_step(c, x, s) : cycle_body<double>(c, c->level, f, x, b.r, true, s);
   if (st != MG_OK) return st;
   return residual_norm(c, f, x, b.r, 0, s);
@@ -833,6 +890,9 @@ int mg_setup(int level, double alpha, int problem, const mg_opts* opts, mg_ctx**
     // MGKKT_NO_MAP=1 runs the tail's sub-cycle on every level instead of the coarse map
     const char* m = std::getenv("MGKKT_NO_MAP");
     c->map_allowed = !(m && m[0] == '1');
+    // MGKKT_NO_SWEEP_NORM=1 recomputes f - A x for the norm after every iterate
+    const char* q = std::getenv("MGKKT_NO_SWEEP_NORM");
+    c->sweep_norm_allowed = !(q && q[0] == '1');
     // MGKKT_NO_GRAPH=1 makes mg_solve launch every kernel eagerly
     const char* g = std::getenv("MGKKT_NO_GRAPH");
     c->graphs = !(g && g[0] == '1');
@@ -1114,8 +1174,20 @@ int mg_solve(mg_ctx* ctx, const double* f, double* x, double tol, int* cycles_ou
     const int verdict = mon.check(ctx->h_norm[0], ctx->h_norm[1], tol, it, ctx->o.max_cycles, &why);
     if (cycles_out) *cycles_out = it;
     if (relres_out) *relres_out = mon.rel;
-    if (verdict == MG_OK) return MG_OK;
-    if (verdict != kContinue) return fail(ctx, verdict, why);
+    if (verdict == MG_OK && it > 0 && sweep_norm(ctx)) {
+      // the norm came from the residual the smoother maintains: confirm with
+      // the recomputed residual f - A x (which then replaces it)
+      if ((st = residual_norm(ctx, f, x, fine_r(ctx), 0, s)) != MG_OK) return st;
+      HIPCHK(ctx, hipMemcpyAsync(ctx->h_norm, ctx->d_norm, sizeof(double), hipMemcpyDeviceToHost, s));
+      HIPCHK(ctx, hipStreamSynchronize(s));
+      const double rel = std::sqrt(ctx->h_norm[0]) / mon.nf;
+      if (relres_out) *relres_out = rel;
+      if (rel <= tol) return MG_OK;
+      if (!std::isfinite(rel)) return fail(ctx, MG_ENAN, "non-finite residual norm");
+    } else if (verdict == MG_OK) {
+      return MG_OK;
+    }
+    if (verdict != kContinue && verdict != MG_OK) return fail(ctx, verdict, why);
     if (ctx->graphs && !ctx->timing) {
       if ((st = ensure_graph(ctx, f, x)) != MG_OK) return st;
       HIPCHK(ctx, hipGraphLaunch(ctx->gexec, s));

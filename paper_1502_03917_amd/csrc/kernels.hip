@@ -453,6 +453,86 @@ __device__ __forceinline__ void prolong_add_body(Lev Lf, Lev Lc, const T* __rest
 template <typename T>
 __global__ __launch_bounds__(kNT) void k_prolong_add(Lev Lf, Lev Lc, const T* __restrict__ xc, T* __restrict__ x) { prolong_add_body<T>(Lf, Lc, xc, x); }
 
+// (P x_c) at fine vertex (a, b): the coarse value at a coarse vertex, the mean
+// of the endpoints on a coarse edge (same expression as prolong_add_body)
+template <typename T>
+__device__ __forceinline__ void prolong_at(const Lev& Lf, const Lev& Lc, const T* __restrict__ xc, int a, int b,
+                                           T& vy, T& vl) {
+  const int w0 = (b >> 1) * Lc.ld + (a >> 1), w1 = ((b + 1) >> 1) * Lc.ld + ((a + 1) >> 1);
+  if (w0 == w1) {
+    vy = xc[w0];
+    vl = xc[Lc.V + w0];
+  } else {
+    vy = (T)0.5 * (xc[w0] + xc[w1]);
+    vl = (T)0.5 * (xc[Lc.V + w0] + xc[Lc.V + w1]);
+  }
+  (void)Lf;
+}
+
+// x_out = x_in + P x_c and r = f - A x_out in one pass (section 2: coarse-grid
+// correction followed by the fine residual).  The block first forms the
+// corrected iterate on its vertices plus a one-vertex ring in LDS (one
+// interpolation per vertex), then applies the stencil from there.  x_out must
+// not alias x_in.  Same arithmetic as k_prolong_add followed by k_residual.
+template <typename T>
+__global__ __launch_bounds__(kNT) void k_prolong_residual(Lev Lf, Lev Lc, const T* __restrict__ xc,
+                                                          const T* __restrict__ xin, const T* __restrict__ f,
+                                                          T* __restrict__ xout, T* __restrict__ r) {
+  constexpr int PX = kBX + 2, PY = kBY + 2;
+  __shared__ T sy[PX * PY], sl[PX * PY];
+  const int n = Lf.n, V = Lf.V, ld = Lf.ld;
+  const int ib = blockIdx.x * kBX - 1, jb = blockIdx.y * kBY - 1;
+  const int tid = threadIdx.y * kBX + threadIdx.x;
+  for (int e = tid; e < PX * PY; e += kNT) {
+    const int lj = e / PX, li = e - lj * PX;
+    const int a = ib + li, b = jb + lj;
+    T y = 0, l = 0;
+    if (a >= 0 && a <= n && b >= 0 && b <= n) {
+      T vy, vl;
+      prolong_at(Lf, Lc, xc, a, b, vy, vl);
+      const int u = b * ld + a;
+      y = xin[u] + vy;
+      l = xin[V + u] + vl;
+    }
+    sy[e] = y;
+    sl[e] = l;
+  }
+  __syncthreads();
+  const int i = blockIdx.x * kBX + threadIdx.x;
+  const int j = blockIdx.y * kBY + threadIdx.y;
+  if (i > n || j > n) return;
+  const int c = (threadIdx.y + 1) * PX + threadIdx.x + 1;
+  const T ai = (T)Lf.ainv;
+  const T yc = sy[c], lc = sl[c];
+  T ay, al;
+  if (i >= 1 && i < n && j >= 1 && j < n) {
+    const T ya = sy[c + 1] + sy[c - 1] + sy[c + PX] + sy[c - PX];
+    const T yg = sy[c + PX + 1] + sy[c - PX - 1];
+    const T la = sl[c + 1] + sl[c - 1] + sl[c + PX] + sl[c - PX];
+    const T lg = sl[c + PX + 1] + sl[c - PX - 1];
+    const T Mc = (T)Lf.Mc, Mo = (T)Lf.Mo, Kc = (T)Lf.Kc, Ka = (T)Lf.Ka, Kd = (T)Lf.Kd;
+    ay = Mc * yc + Mo * (ya + yg) + (Kc * lc + Ka * la + Kd * lg);
+    al = (Kc * yc + Ka * ya + Kd * yg) - ai * (Mc * lc + Mo * (la + lg));
+  } else {
+    T M[kNDir], K[kNDir];
+    coef_MK(Lf, i, j, M, K);
+    ay = 0;
+    al = 0;
+#pragma unroll
+    for (int d = 0; d < kNDir; d++) {
+      if (!inside(Lf, i + kDI[d], j + kDJ[d])) continue;
+      const int m = c + kDJ[d] * PX + kDI[d];
+      ay += M[d] * sy[m] + K[d] * sl[m];
+      al += K[d] * sy[m] - ai * M[d] * sl[m];
+    }
+  }
+  const int v = j * ld + i;
+  xout[v] = yc;
+  xout[V + v] = lc;
+  r[v] = f[v] - ay;
+  r[V + v] = f[V + v] - al;
+}
+
 // x = A_{k0}^{-1} f with the FP64 LU factors (row pivots piv) of A_{k0}
 template <typename T>
 __global__ __launch_bounds__(256) void k_coarse_solve(int N, const double* __restrict__ lu, const int* __restrict__ piv,
@@ -733,6 +813,14 @@ hipError_t launch_prolong_add(const Lev& Lf, const Lev& Lc, const T* xc, T* x, h
 }
 
 template <typename T>
+hipError_t launch_prolong_residual(const Lev& Lf, const Lev& Lc, const T* xc, const T* xin, const T* f, T* xout, T* r,
+                                   hipStream_t s) {
+  if (xin == xout) return hipErrorInvalidValue;
+  hipLaunchKernelGGL((k_prolong_residual<T>), grid_vertices(Lf.n), kBlock, 0, s, Lf, Lc, xc, xin, f, xout, r);
+  return hipGetLastError();
+}
+
+template <typename T>
 hipError_t launch_coarse_solve(int N, const double* lu, const int* piv, const T* f, T* x, hipStream_t s) {
   if (N > 512) return hipErrorInvalidValue;
   hipLaunchKernelGGL((k_coarse_solve<T>), dim3(1), dim3(256), 0, s, N, lu, piv, f, x);
@@ -881,6 +969,8 @@ hipError_t launch_b_gather_norms(const double* const* d, int count, double* out,
   template hipError_t launch_cgs_phase<T>(const Lev&, int, T*, T*, hipStream_t);                                   \
   template hipError_t launch_restrict<T>(const Lev&, const Lev&, const T*, T*, T*, T*, hipStream_t);              \
   template hipError_t launch_prolong_add<T>(const Lev&, const Lev&, const T*, T*, hipStream_t);                    \
+  template hipError_t launch_prolong_residual<T>(const Lev&, const Lev&, const T*, const T*, const T*, T*, T*,      \
+                                                 hipStream_t);                                                    \
   template hipError_t launch_coarse_solve<T>(int, const double*, const int*, const T*, T*, hipStream_t);         \
   template hipError_t launch_b_residual<T>(const BInst<T>*, int, int, int, hipStream_t);                          \
   template hipError_t launch_b_ne<T>(const BInst<T>*, int, int, int, hipStream_t);                                \

@@ -118,12 +118,23 @@ hipError_t launch_lsgs_phase(const Lev& L, int colour, T* x, T* r, hipStream_t s
 // and writing r_out (distinct buffers), x updated in place
 template <typename T>
 hipError_t launch_lsgs_sweep(const Lev& L, int reverse, T* x, const T* rin, T* rout, hipStream_t s);
+// the same sweep reading the iterate from xin and writing it to x
+template <typename T>
+hipError_t launch_lsgs_sweep_from(const Lev& L, int reverse, const T* xin, T* x, const T* rin, T* rout, hipStream_t s);
+// an FP64 sweep that also stores per-tile partial sums of ||r_out||^2
+// (norm_mode 1: Euclidean, 2: L^{-1}) in part; *nparts = number of tiles
+hipError_t launch_lsgs_sweep_norm(const Lev& L, int reverse, const double* xin, double* x, const double* rin,
+                                  double* rout, double* part, int norm_mode, int* nparts, hipStream_t s);
 template <typename T>
 hipError_t launch_cgs_phase(const Lev& L, int colour, T* x, T* r, hipStream_t s);
 template <typename T>
 hipError_t launch_restrict(const Lev& Lf, const Lev& Lc, const T* r, T* fc, T* xc_zero, T* rc_copy, hipStream_t s);
 template <typename T>
 hipError_t launch_prolong_add(const Lev& Lf, const Lev& Lc, const T* xc, T* x, hipStream_t s);
+// x_out = x_in + P x_c and r = f - A x_out in one pass (x_out != x_in)
+template <typename T>
+hipError_t launch_prolong_residual(const Lev& Lf, const Lev& Lc, const T* xc, const T* xin, const T* f, T* xout, T* r,
+                                   hipStream_t s);
 template <typename T>
 hipError_t launch_coarse_solve(int N, const double* lu, const int* piv, const T* f, T* x, hipStream_t s);
 

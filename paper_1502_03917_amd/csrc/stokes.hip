@@ -626,16 +626,37 @@ __global__ __launch_bounds__(kSNT) void ks_lsgs(int g0, int ng, const int2* __re
   const int2 u = grp[g0 + g];
   const int row = half ? u.y : u.x;
   const int kb = rp[row], ke = rp[row + 1];
+  // the first two entries of each lane (rows of this discretisation have at
+  // most 2 kHalf entries) are gathered in one round and their column indices
+  // and values kept in registers; longer rows continue in the loops below
+  // (same summation order)
+  const int k0 = kb + ln, k1 = k0 + kHalf;
+  const bool h0 = k0 < ke, h1 = k1 < ke;
+  const int c0 = h0 ? col[k0] : 0, c1 = h1 ? col[k1] : 0;
+  const T v0 = h0 ? val[k0] : (T)0, v1 = h1 ? val[k1] : (T)0;
   T q = 0;
-  for (int k = kb + ln; k < ke; k += kHalf) q += val[k] * Linv[col[k]] * r[col[k]];
+  if (h0) q += v0 * Linv[c0] * r[c0];
+  if (h1) q += v1 * Linv[c1] * r[c1];
+  for (int k = k1 + kHalf; k < ke; k += kHalf) q += val[k] * Linv[col[k]] * r[col[k]];
   q = half_sum(q);
   const T pv = q * Ninv[row];
   if (ln == 0) x[row] += pv;
-  if (half == 0)
-    for (int k = kb + ln; k < ke; k += kHalf) r[col[k]] -= val[k] * pv;
+  // The two rows of the group share residual entries: each half re-reads
+  // every entry before its update.  The halves' branches may run in either
+  // order (they are exclusive per lane), so neither may reuse the gathered
+  // values; the volatile reads keep the compiler from substituting them.
+  volatile T* rc = r;
+  if (half == 0) {
+    if (h0) r[c0] = rc[c0] - v0 * pv;
+    if (h1) r[c1] = rc[c1] - v1 * pv;
+    for (int k = k1 + kHalf; k < ke; k += kHalf) r[col[k]] = rc[col[k]] - val[k] * pv;
+  }
   __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
-  if (half == 1)
-    for (int k = kb + ln; k < ke; k += kHalf) r[col[k]] -= val[k] * pv;
+  if (half == 1) {
+    if (h0) r[c0] = rc[c0] - v0 * pv;
+    if (h1) r[c1] = rc[c1] - v1 * pv;
+    for (int k = k1 + kHalf; k < ke; k += kHalf) r[col[k]] = rc[col[k]] - val[k] * pv;
+  }
 }
 
 // One colour phase of the patch smoother: x_P += tau A_PP^-1 r_P,

@@ -85,9 +85,13 @@ struct PhaseItems {
   static constexpr int SMAX = (W0 + 6) / 7;      // slots per row that cover every window
 };
 
+// The iterate is read from xin and written to x (the same buffer, or a
+// distinct one when the sweep also moves x: xin is read only before x is
+// written, per owned vertex).
 template <typename T, int TW, int NT>
-__device__ __forceinline__ void lsgs_tile_body(const Lev& L, int ntx, int nty, int reverse, T* __restrict__ x,
-                                               const T* __restrict__ rin, T* __restrict__ rout) {
+__device__ __forceinline__ void lsgs_tile_body(const Lev& L, int ntx, int nty, int reverse, const T* xin, T* x,
+                                               const T* __restrict__ rin, T* __restrict__ rout,
+                                               double* __restrict__ part = nullptr, int norm_mode = 0) {
   using G = TileGeom<TW>;
   using T2 = typename Pair<T>::type;
   constexpr int NR = (G::RMAX * G::RMAX + NT - 1) / NT;  // region cells per thread
@@ -111,7 +115,8 @@ __device__ __forceinline__ void lsgs_tile_body(const Lev& L, int ntx, int nty, i
   const int nblk = gridDim.x, bid = blockIdx.x;
   const int tid = threadIdx.x;
   const size_t vbytes = (size_t)2 * V * sizeof(T);
-  const __amdgpu_buffer_rsrc_t Rin = make_rsrc(rin, vbytes), Rout = make_rsrc(rout, vbytes), Rx = make_rsrc(x, vbytes);
+  const __amdgpu_buffer_rsrc_t Rin = make_rsrc(rin, vbytes), Rout = make_rsrc(rout, vbytes), Rx = make_rsrc(x, vbytes),
+                              Rxi = make_rsrc(xin, vbytes);
   const unsigned fo = (unsigned)(V * sizeof(T));  // byte offset of the lambda field
 
   // The workgroups of one XCD (bid % 8) take a contiguous run of tiles, which
@@ -159,8 +164,8 @@ __device__ __forceinline__ void lsgs_tile_body(const Lev& L, int ntx, int nty, i
     for (int ph = 0; ph < 7; ph++) {
       const Item it = item_of(ph, tid);
       xo[ph] = owned(it) ? (unsigned)((it.gj * ld + it.gi) * sizeof(T)) : kOff;
-      xy[ph] = bload(Rx, xo[ph], (T*)nullptr);
-      xl[ph] = bload(Rx, xo[ph] == kOff ? kOff : xo[ph] + fo, (T*)nullptr);
+      xy[ph] = bload(Rxi, xo[ph], (T*)nullptr);
+      xl[ph] = bload(Rxi, xo[ph] == kOff ? kOff : xo[ph] + fo, (T*)nullptr);
     }
   } else {
 #pragma unroll
@@ -169,8 +174,8 @@ __device__ __forceinline__ void lsgs_tile_body(const Lev& L, int ntx, int nty, i
       const int oj = e / TW, oi = e - oj * TW;
       const bool ok = e < TW * TW && oi < OW && oj < OH;
       const unsigned o = ok ? (unsigned)(((j0 + oj) * ld + i0 + oi) * sizeof(T)) : kOff;
-      xy[q] = bload(Rx, o, (T*)nullptr);
-      xl[q] = bload(Rx, ok ? o + fo : kOff, (T*)nullptr);
+      xy[q] = bload(Rxi, o, (T*)nullptr);
+      xl[q] = bload(Rxi, ok ? o + fo : kOff, (T*)nullptr);
     }
   }
   T ry[NR], rl[NR];
@@ -299,7 +304,11 @@ __device__ __forceinline__ void lsgs_tile_body(const Lev& L, int ntx, int nty, i
     }
   }
 
-  // owned tile out: r to r_out (and x + corrections to x for multi-pass phases)
+  // owned tile out: r to r_out (and x + corrections to x for multi-pass
+  // phases); with norm_mode 1 / 2 also the tile's share of ||r_out||^2,
+  // Euclidean or weighted by L^{-1} = blockdiag(W^{-1}, alpha W^{-1}), in
+  // part[tile]
+  double s2sum = 0.0;
 #pragma unroll
   for (int q = 0; q < NX; q++) {
     const int e = tid + q * NT;
@@ -316,13 +325,40 @@ __device__ __forceinline__ void lsgs_tile_body(const Lev& L, int ntx, int nty, i
       bstore(Rx, o, xy[q] + dv.x);
       bstore(Rx, o2, xl[q] + dv.y);
     }
+    if (norm_mode && ok) {
+      const double ry = (double)rv.x, rl = (double)rv.y;
+      if (norm_mode == 1) {
+        s2sum += ry * ry + rl * rl;
+      } else {
+        const int gi = i0 + oi, gj = j0 + oj;
+        const double wi = (gi >= 1 && gi < n && gj >= 1 && gj < n)
+                              ? L.Winv
+                              : (double)tC[(cls5(gi, n) * 5 + cls5(gj, n)) * kC5 + 2 * kNDir];
+        s2sum += wi * (ry * ry + L.alpha * (rl * rl));
+      }
+    }
+  }
+  if (norm_mode) {
+    // fixed-order workgroup sum: within each wave, then over the waves
+    __shared__ double wsum[NT / 64];
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) s2sum += __shfl_xor(s2sum, o, 64);
+    if ((tid & 63) == 0) wsum[tid >> 6] = s2sum;
+    lds_barrier();
+    if (tid == 0) {
+      double t = 0.0;
+#pragma unroll
+      for (int w = 0; w < NT / 64; w++) t += wsum[w];
+      part[tile] = t;
+    }
   }
 }
 
 template <typename T, int TW, int NT>
-__global__ __launch_bounds__(NT) void k_lsgs_tile(Lev L, int ntx, int nty, int reverse, T* __restrict__ x,
-                                                  const T* __restrict__ rin, T* __restrict__ rout) {
-  lsgs_tile_body<T, TW, NT>(L, ntx, nty, reverse, x, rin, rout);
+__global__ __launch_bounds__(NT) void k_lsgs_tile(Lev L, int ntx, int nty, int reverse, const T* xin, T* x,
+                                                  const T* __restrict__ rin, T* __restrict__ rout,
+                                                  double* __restrict__ part, int norm_mode) {
+  lsgs_tile_body<T, TW, NT>(L, ntx, nty, reverse, xin, x, rin, rout, part, norm_mode);
 }
 
 // many instances of one level: instance blockIdx.y, residual read from r
@@ -331,7 +367,7 @@ template <typename T, int TW, int NT>
 __global__ __launch_bounds__(NT) void kb_lsgs_tile(const BInst<T>* __restrict__ B, int ntx, int reverse, int sel) {
   const BInst<T>& a = B[blockIdx.y];
   if (!*a.active) return;
-  lsgs_tile_body<T, TW, NT>(a.L, ntx, ntx, reverse, a.x, sel ? a.r2 : a.r, sel ? a.r : a.r2);
+  lsgs_tile_body<T, TW, NT>(a.L, ntx, ntx, reverse, a.x, a.x, sel ? a.r2 : a.r, sel ? a.r : a.r2);
 }
 
 inline int tiles_along(int npts, int TW) { return (npts + TW - 1) / TW; }
@@ -364,16 +400,19 @@ struct SweepShape<float> {
 constexpr int kSmallTW = 16, kSmallNT = 256;
 
 template <typename T>
-hipError_t launch_tile_cfg(const Lev& L, int reverse, T* x, const T* rin, T* rout, hipStream_t s) {
+hipError_t launch_tile_cfg(const Lev& L, int reverse, const T* xin, T* x, const T* rin, T* rout, hipStream_t s,
+                           double* part = nullptr, int norm_mode = 0, int* nparts = nullptr) {
   if (L.n <= SweepShape<T>::kSmallMaxN) {
     const int nt = tiles_along(L.n + 1, kSmallTW);
+    if (nparts) *nparts = nt * nt;
     hipLaunchKernelGGL((k_lsgs_tile<T, kSmallTW, kSmallNT>), dim3(round8(nt * nt)), dim3(kSmallNT), 0, s, L, nt, nt,
-                       reverse, x, rin, rout);
+                       reverse, xin, x, rin, rout, part, norm_mode);
   } else {
     constexpr int TW = SweepShape<T>::TW, NT = SweepShape<T>::NT;
     const int nt = tiles_along(L.n + 1, TW);
-    hipLaunchKernelGGL((k_lsgs_tile<T, TW, NT>), dim3(round8(nt * nt)), dim3(NT), 0, s, L, nt, nt, reverse, x, rin,
-                       rout);
+    if (nparts) *nparts = nt * nt;
+    hipLaunchKernelGGL((k_lsgs_tile<T, TW, NT>), dim3(round8(nt * nt)), dim3(NT), 0, s, L, nt, nt, reverse, xin, x,
+                       rin, rout, part, norm_mode);
   }
   return hipGetLastError();
 }
@@ -396,13 +435,31 @@ template hipError_t launch_b_lsgs_sweep<float>(const BInst<float>*, int, int, in
 template <>
 hipError_t launch_lsgs_sweep<double>(const Lev& L, int reverse, double* x, const double* rin, double* rout,
                                      hipStream_t s) {
-  return launch_tile_cfg<double>(L, reverse, x, rin, rout, s);
+  return launch_tile_cfg<double>(L, reverse, x, x, rin, rout, s);
 }
 
 template <>
 hipError_t launch_lsgs_sweep<float>(const Lev& L, int reverse, float* x, const float* rin, float* rout,
                                     hipStream_t s) {
-  return launch_tile_cfg<float>(L, reverse, x, rin, rout, s);
+  return launch_tile_cfg<float>(L, reverse, x, x, rin, rout, s);
+}
+
+template <>
+hipError_t launch_lsgs_sweep_from<double>(const Lev& L, int reverse, const double* xin, double* x, const double* rin,
+                                          double* rout, hipStream_t s) {
+  return launch_tile_cfg<double>(L, reverse, xin, x, rin, rout, s);
+}
+
+template <>
+hipError_t launch_lsgs_sweep_from<float>(const Lev& L, int reverse, const float* xin, float* x, const float* rin,
+                                         float* rout, hipStream_t s) {
+  return launch_tile_cfg<float>(L, reverse, xin, x, rin, rout, s);
+}
+
+hipError_t launch_lsgs_sweep_norm(const Lev& L, int reverse, const double* xin, double* x, const double* rin,
+                                  double* rout, double* part, int norm_mode, int* nparts, hipStream_t s) {
+  if (!part || (norm_mode != 1 && norm_mode != 2)) return hipErrorInvalidValue;
+  return launch_tile_cfg<double>(L, reverse, xin, x, rin, rout, s, part, norm_mode, nparts);
 }
 
 }  // namespace mgk

@@ -88,17 +88,51 @@ __device__ __forceinline__ void tail_body(const TailArgs<T>& A) {
   // unconditional (their coefficients are zero, so they stay zero)
   T* zs = reinterpret_cast<T*>(smem_raw + off_lu + (size_t)N0 * N0 * sizeof(double));
 
-  // ---- load tables, LU, f_T and x_T
-  for (int l = k0 + 1; l <= Tl; l++)
-    for (int e = tid; e < 25 * kC5; e += NT) tC[l * 25 * kC5 + e] = (T)(&A.lev[l].tab->C5[0][0])[e];
-  for (int e = tid; e < N0 * N0; e += NT) slu[e] = A.lu[e];
+  // ---- load tables, LU, f_T and x_T.  Global loads are issued in unrolled
+  // batches before the LDS stores that consume them, so a batch costs one
+  // memory round trip (a loop of load-then-store would wait on every load).
+  auto copy_in = [&](T* dst, const auto* src, int n) {  // dst[e] = (T)src[e], e < n
+    constexpr int B = 8;
+    for (int base = 0; base < n; base += B * NT) {
+      T v[B];
+#pragma unroll
+      for (int u = 0; u < B; u++) {
+        const int e = base + u * NT + tid;
+        v[u] = e < n ? (T)src[e] : (T)0;
+      }
+#pragma unroll
+      for (int u = 0; u < B; u++) {
+        const int e = base + u * NT + tid;
+        if (e < n) dst[e] = v[u];
+      }
+    }
+  };
+  for (int l = k0 + 1; l <= Tl; l++) copy_in(tC + l * 25 * kC5, &A.lev[l].tab->C5[0][0], 25 * kC5);
+  {
+    // the LU stays FP64
+    constexpr int B = 8;
+    for (int base = 0; base < N0 * N0; base += B * NT) {
+      double v[B];
+#pragma unroll
+      for (int u = 0; u < B; u++) {
+        const int e = base + u * NT + tid;
+        v[u] = e < N0 * N0 ? A.lu[e] : 0.0;
+      }
+#pragma unroll
+      for (int u = 0; u < B; u++) {
+        const int e = base + u * NT + tid;
+        if (e < N0 * N0) slu[e] = v[u];
+      }
+    }
+  }
   if (tid < 2) zs[tid] = (T)0;
   {
     const TailLevel& L = A.lv[Tl];
-    for (int e = tid; e < 2 * L.V; e += NT) {
-      const T fv = A.fT[e];
-      sm[L.of + e] = fv;
-      sm[L.ox + e] = A.first ? (T)0 : A.xT[e];
+    copy_in(sm + L.of, A.fT, 2 * L.V);
+    if (A.first) {
+      for (int e = tid; e < 2 * L.V; e += NT) sm[L.ox + e] = (T)0;
+    } else {
+      copy_in(sm + L.ox, A.xT, 2 * L.V);
     }
   }
   bar();
@@ -366,17 +400,24 @@ __device__ __forceinline__ void tail_body(const TailArgs<T>& A) {
         break;
       }
       case kTailApplyMap: {  // x_l += B r_l: the whole sub-cycle on level l and below, from zero
+        // row tid of B (column-major, so a batch of columns is one coalesced
+        // load per column); the loads of a batch are issued together
         const LP P = level_params(l);
         const int N = A.nmap;
         if (tid < N) {
           const T* rv = sm + P.or_;
+          constexpr int B = 18;
           T acc0 = 0, acc1 = 0;
-          int c = 0;
-          for (; c + 1 < N; c += 2) {
-            acc0 += A.map[(size_t)c * N + tid] * rv[c];
-            acc1 += A.map[(size_t)(c + 1) * N + tid] * rv[c + 1];
+          for (int c0 = 0; c0 < N; c0 += B) {
+            T v[B];
+#pragma unroll
+            for (int u = 0; u < B; u++) v[u] = c0 + u < N ? A.map[(size_t)(c0 + u) * N + tid] : (T)0;
+#pragma unroll
+            for (int u = 0; u < B; u += 2) {
+              if (c0 + u < N) acc0 += v[u] * rv[c0 + u];
+              if (c0 + u + 1 < N) acc1 += v[u + 1] * rv[c0 + u + 1];
+            }
           }
-          if (c < N) acc0 += A.map[(size_t)c * N + tid] * rv[c];
           sm[P.ox + tid] += acc0 + acc1;
         }
         bar();

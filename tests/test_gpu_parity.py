@@ -252,6 +252,41 @@ def test_coarse_map_equals_subcycle(torch_cuda, monkeypatch, smoother, gamma):
         assert np.linalg.norm(xs[0] - xs[1]) <= bound * np.linalg.norm(xs[1]), precision
 
 
+@pytest.mark.parametrize("smoother,nu", [("lsgs", 2), ("slsgs", 1)])
+def test_sweep_norm_solve(torch_cuda, monkeypatch, smoother, nu):
+    # FP64 solves take each iterate's norm from the residual the last sweep
+    # leaves; at convergence the recomputed f - A x is checked.  Against the
+    # path that recomputes the residual after every iterate: same cycle count
+    # (to one) and solution, and the reported relative residual is the true
+    # one (Euclidean norm, recomputed here)
+    torch = torch_cuda
+    mg = _mg()
+    level, alpha = 9, 1e-4
+    yd = _dev(torch, workloads.desired_state(level, 2))
+    out = []
+    for env in (None, "1"):
+        if env:
+            monkeypatch.setenv("MGKKT_NO_SWEEP_NORM", env)
+        s = mg.Solver(level, alpha, smoother=smoother, nu1=nu, nu2=nu, norm="l2")
+        monkeypatch.delenv("MGKKT_NO_SWEEP_NORM", raising=False)
+        f = s.rhs(yd)
+        x, it, rel, st = s.solve(f, tol=1e-10)
+        assert st == mg.MG_OK and rel <= 1e-10
+        _, nrm = s.residual(f, x, norm=True)
+        fn = float(torch.linalg.norm(f))
+        assert rel == pytest.approx(nrm / fn, rel=1e-12)
+        out.append((_host(x), it))
+    assert abs(out[0][1] - out[1][1]) <= 1
+    assert np.linalg.norm(out[0][0] - out[1][0]) <= 1e-8 * np.linalg.norm(out[1][0])
+    # a tolerance close to rounding still ends on the recomputed residual
+    s = mg.Solver(level, alpha, smoother=smoother, nu1=nu, nu2=nu, norm="l2", max_cycles=80)
+    f = s.rhs(yd)
+    x, it, rel, st = s.solve(f, tol=1e-14, raise_on_error=False)
+    if st == mg.MG_OK:
+        _, nrm = s.residual(f, x, norm=True)
+        assert nrm / float(torch.linalg.norm(f)) <= 1e-14
+
+
 CYCLE_CASES = [
     (5, 1e-2, "lsgs", 1),
     (5, 1e-2, "ne", 1),
