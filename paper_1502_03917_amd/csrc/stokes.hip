@@ -515,7 +515,7 @@ template <typename T, int MODE>
 __global__ __launch_bounds__(kSNT) void ks_resid(int n, const int* __restrict__ rp, const int* __restrict__ col,
                                                  const T* __restrict__ val, const T* __restrict__ f,
                                                  const T* __restrict__ x, T* __restrict__ r,
-                                                 const double* __restrict__ Ld, double* __restrict__ part) {
+                                                 const double* __restrict__ Ldi, double* __restrict__ part) {
   const int ln = threadIdx.x % kRL;
   double s2 = 0.0;
   for (int i0 = blockIdx.x * kRows; i0 < n; i0 += gridDim.x * kRows) {  // uniform per block
@@ -528,7 +528,7 @@ __global__ __launch_bounds__(kSNT) void ks_resid(int n, const int* __restrict__ 
       const T ri = f ? f[i] - s : s;
       r[i] = ri;
       if (MODE == 1) s2 += (double)ri * (double)ri;
-      if (MODE == 2) s2 += (double)ri * (double)ri / Ld[i];
+      if (MODE == 2) s2 += (double)ri * (double)ri * Ldi[i];
     }
   }
   if (MODE) block_store(s2, &part[blockIdx.x]);
@@ -536,11 +536,11 @@ __global__ __launch_bounds__(kSNT) void ks_resid(int n, const int* __restrict__ 
 
 // per-block partial sums of ||v||^2 (MODE 1) or v^T L^-1 v (MODE 2), one thread per entry
 template <int MODE>
-__global__ __launch_bounds__(kSNT) void ks_vnorm(int n, const double* __restrict__ v, const double* __restrict__ Ld,
+__global__ __launch_bounds__(kSNT) void ks_vnorm(int n, const double* __restrict__ v, const double* __restrict__ Ldi,
                                                  double* __restrict__ part) {
   const int i = blockIdx.x * kSNT + threadIdx.x;
   double s2 = 0.0;
-  if (i < n) s2 = MODE == 1 ? v[i] * v[i] : v[i] * v[i] / Ld[i];
+  if (i < n) s2 = MODE == 1 ? v[i] * v[i] : v[i] * v[i] * Ldi[i];
   block_store(s2, &part[blockIdx.x]);
 }
 
@@ -644,18 +644,19 @@ __global__ __launch_bounds__(kSNT) void ks_lsgs(int g0, int ng, const int2* __re
   // The two rows of the group share residual entries: each half re-reads
   // every entry before its update.  The halves' branches may run in either
   // order (they are exclusive per lane), so neither may reuse the gathered
-  // values; the volatile reads keep the compiler from substituting them.
-  volatile T* rc = r;
+  // values; the re-reads are relaxed atomic loads, which the compiler does
+  // not replace by earlier plain loads of the same address.
+  auto fresh = [&](int c) { return __hip_atomic_load(r + c, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP); };
   if (half == 0) {
-    if (h0) r[c0] = rc[c0] - v0 * pv;
-    if (h1) r[c1] = rc[c1] - v1 * pv;
-    for (int k = k1 + kHalf; k < ke; k += kHalf) r[col[k]] = rc[col[k]] - val[k] * pv;
+    if (h0) r[c0] = fresh(c0) - v0 * pv;
+    if (h1) r[c1] = fresh(c1) - v1 * pv;
+    for (int k = k1 + kHalf; k < ke; k += kHalf) r[col[k]] = fresh(col[k]) - val[k] * pv;
   }
   __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
   if (half == 1) {
-    if (h0) r[c0] = rc[c0] - v0 * pv;
-    if (h1) r[c1] = rc[c1] - v1 * pv;
-    for (int k = k1 + kHalf; k < ke; k += kHalf) r[col[k]] = rc[col[k]] - val[k] * pv;
+    if (h0) r[c0] = fresh(c0) - v0 * pv;
+    if (h1) r[c1] = fresh(c1) - v1 * pv;
+    for (int k = k1 + kHalf; k < ke; k += kHalf) r[col[k]] = fresh(col[k]) - val[k] * pv;
   }
 }
 
@@ -1202,13 +1203,13 @@ hipError_t stokes_residual(Stokes* S, int l, const double* f, const double* x, d
   if (nparts) *nparts = nb;
   if (!part)
     hipLaunchKernelGGL((ks_resid<double, 0>), dim3(nb), dim3(kSNT), 0, s, L.ndof, L.A_rp, L.A_col,
-                       (const double*)L.A_val, f, x, r, (const double*)L.Ld, part);
+                       (const double*)L.A_val, f, x, r, (const double*)L.Linv, part);
   else if (norm_mode == 2)
     hipLaunchKernelGGL((ks_resid<double, 2>), dim3(nb), dim3(kSNT), 0, s, L.ndof, L.A_rp, L.A_col,
-                       (const double*)L.A_val, f, x, r, (const double*)L.Ld, part);
+                       (const double*)L.A_val, f, x, r, (const double*)L.Linv, part);
   else
     hipLaunchKernelGGL((ks_resid<double, 1>), dim3(nb), dim3(kSNT), 0, s, L.ndof, L.A_rp, L.A_col,
-                       (const double*)L.A_val, f, x, r, (const double*)L.Ld, part);
+                       (const double*)L.A_val, f, x, r, (const double*)L.Linv, part);
   return hipGetLastError();
 }
 
@@ -1217,9 +1218,9 @@ hipError_t stokes_vnorm(Stokes* S, const double* v, double* part, int norm_mode,
   const int nb = blocks_for(L.ndof);
   *nparts = nb;
   if (norm_mode == 2)
-    hipLaunchKernelGGL((ks_vnorm<2>), dim3(nb), dim3(kSNT), 0, s, L.ndof, v, (const double*)L.Ld, part);
+    hipLaunchKernelGGL((ks_vnorm<2>), dim3(nb), dim3(kSNT), 0, s, L.ndof, v, (const double*)L.Linv, part);
   else
-    hipLaunchKernelGGL((ks_vnorm<1>), dim3(nb), dim3(kSNT), 0, s, L.ndof, v, (const double*)L.Ld, part);
+    hipLaunchKernelGGL((ks_vnorm<1>), dim3(nb), dim3(kSNT), 0, s, L.ndof, v, (const double*)L.Linv, part);
   return hipGetLastError();
 }
 
