@@ -137,13 +137,25 @@ def counter_summary(directory: str):
 
 
 # finest-level tile shape (tile width, threads per workgroup) per precision
-SWEEP_TILE = {"fp64": (48, 1024), "fp32_ir": (48, 512)}
+def sweep_tile(level: int, precision: str) -> tuple[int, int]:
+    """(tile edge, threads) of the sweep on a level: the per-level table of
+    the sweep launcher (csrc/sweep.hip, launch_tile_cfg)."""
+    n = 1 << level
+    if precision == "fp64":
+        if n <= 256:
+            return 16, 256
+        if n in (1024, 2048):
+            return 65, 1024
+        return (56, 1024) if n >= 4096 else (48, 1024)
+    if n <= 512:
+        return 16, 256
+    return (46, 512) if n == 2048 else (48, 512)
 
 
 def finest_sweep_grid(level: int, precision: str) -> int:
     """Work-items launched by the finest-level sweep: one workgroup per
     TW x TW tile, the workgroup count rounded up to a multiple of 8."""
-    tw, nt = SWEEP_TILE[precision]
+    tw, nt = sweep_tile(level, precision)
     side = -(-((1 << level) + 1) // tw)
     return nt * (-(-side * side // 8) * 8)
 

@@ -236,6 +236,13 @@ struct mg_ctx {
   bool sweep_norm_allowed = true;
   double* d_map64 = nullptr;
   float* d_map32 = nullptr;
+  // dense map of the tail's top level (kDenseMapLevel), row-major: one
+  // matrix-vector product replaces the tail launch in single-instance cycles;
+  // dmap_allowed: MGKKT_NO_DENSE_MAP unset
+  bool dmap_allowed = true;
+  int dmap_n = 0;  // 0: not built
+  double* d_dmap64 = nullptr;
+  float* d_dmap32 = nullptr;
   // HIP graph of one solver iterate (cycle + residual norm) for fixed f, x
   hipStream_t cap_stream = nullptr;  // capture stream (default priority)
   bool graphs = true;
@@ -330,6 +337,8 @@ void destroy_impl(mg_ctx* c) {
   (void)hipFree(c->d_tail_ops);
   (void)hipFree(c->d_map64);
   (void)hipFree(c->d_map32);
+  (void)hipFree(c->d_dmap64);
+  (void)hipFree(c->d_dmap32);
   (void)hipFree(c->d_part);
   (void)hipFree(c->d_norm);
   if (c->h_norm) (void)hipHostFree(c->h_norm);
@@ -545,6 +554,60 @@ int build_coarse_map(mg_ctx* c, const mgk::TailLaunch& base, size_t lds_bytes) {
   return done(MG_OK);
 }
 
+// The dense map B of the tail's top level T = kDenseMapLevel: from x_T = 0 the
+// tail computes x_T = B f_T (every step is linear in f_T), so column i is the
+// tail applied to the unit vector e_i.  All columns come from one batched tail
+// launch; B is stored row-major (one row per wave in the product) in FP64 and
+// as an FP32 copy for the FP32 cycles.
+int build_dense_map(mg_ctx* c) {
+  const int T = c->tail_T;
+  const int N = 2 * ((1 << T) + 1) * ((1 << T) + 1);
+  if (N > mgk::kDenseMapMaxN) return MG_OK;
+  const size_t lds = mgk::tail_lds_bytes<double>(c->k0, T);
+  double* d_id = nullptr;
+  double* d_cols = nullptr;
+  void* d_args = nullptr;
+  auto done = [&](int st) {
+    (void)hipFree(d_id);
+    (void)hipFree(d_cols);
+    (void)hipFree(d_args);
+    return st;
+  };
+  const size_t nn = (size_t)N * N;
+  if (hipMalloc(&d_id, nn * sizeof(double)) != hipSuccess || hipMalloc(&d_cols, nn * sizeof(double)) != hipSuccess ||
+      hipMalloc(&c->d_dmap64, nn * sizeof(double)) != hipSuccess ||
+      hipMalloc(&c->d_dmap32, nn * sizeof(float)) != hipSuccess)
+    return done(fail(c, MG_ENOMEM, "dense map: device allocation failed"));
+  std::vector<double> h(nn, 0.0);
+  for (int i = 0; i < N; i++) h[(size_t)i * N + i] = 1.0;
+  const size_t sz = mgk::tail_args_bytes<double>();
+  std::vector<unsigned char> args((size_t)N * sz);
+  for (int i = 0; i < N; i++)
+    mgk::make_tail_args<double>(c->tail, d_id + (size_t)i * N, d_cols + (size_t)i * N, 1, nullptr, args.data() + i * sz);
+  if (hipMalloc(&d_args, args.size()) != hipSuccess) return done(fail(c, MG_ENOMEM, "dense map: device allocation failed"));
+  hipError_t e = hipMemcpy(d_id, h.data(), nn * sizeof(double), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(d_args, args.data(), args.size(), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = mgk::launch_b_tail<double>(d_args, N, lds, nullptr);
+  if (e == hipSuccess) e = hipDeviceSynchronize();
+  std::vector<double> cols(nn);
+  if (e == hipSuccess) e = hipMemcpy(cols.data(), d_cols, nn * sizeof(double), hipMemcpyDeviceToHost);
+  if (e != hipSuccess) return done(fail(c, MG_EHIP, std::string("dense map: ") + hipGetErrorString(e)));
+  // column i (contiguous in cols) becomes column i of the row-major matrix
+  std::vector<float> h32(nn);
+  for (int i = 0; i < N; i++)
+    for (int r = 0; r < N; r++) {
+      const double v = cols[(size_t)i * N + r];
+      if (!std::isfinite(v)) return done(fail(c, MG_EHIP, "dense map: non-finite entry"));
+      h[(size_t)r * N + i] = v;
+      h32[(size_t)r * N + i] = (float)v;
+    }
+  e = hipMemcpy(c->d_dmap64, h.data(), nn * sizeof(double), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(c->d_dmap32, h32.data(), nn * sizeof(float), hipMemcpyHostToDevice);
+  if (e != hipSuccess) return done(fail(c, MG_EHIP, std::string("dense map: ") + hipGetErrorString(e)));
+  c->dmap_n = N;
+  return done(MG_OK);
+}
+
 // (Re)build the tail for the context's options; tail level min(5, level - 1).
 // k0 <= 2: the tail solves the coarsest system with one lane per unknown
 // (2 (2^k0 + 1)^2 <= 64).
@@ -555,6 +618,11 @@ int setup_tail(mg_ctx* c) {
   c->d_tail_ops = nullptr;
   c->d_map64 = nullptr;
   c->d_map32 = nullptr;
+  (void)hipFree(c->d_dmap64);
+  (void)hipFree(c->d_dmap32);
+  c->d_dmap64 = nullptr;
+  c->d_dmap32 = nullptr;
+  c->dmap_n = 0;
   c->tail_T = 0;
   const int T = c->level - 1 < 5 ? c->level - 1 : 5;
   if (!c->tail_allowed || T <= c->k0 || c->k0 > 2 || c->problem != MG_POISSON) return MG_OK;
@@ -594,8 +662,16 @@ int setup_tail(mg_ctx* c) {
   t.nops = (int)ops.size();
   t.ops = c->d_tail_ops;
   c->tail_T = T;
+  if (c->dmap_allowed && T == mgk::kDenseMapLevel) return build_dense_map(c);
   return MG_OK;
 }
+
+// set while mg_batch_setup creates its instances: batched cycles launch the
+// tail for all instances at once and never use a dense map
+thread_local bool t_batch_instance = false;
+
+const double* dmap(const mg_ctx* c, double*) { return c->d_dmap64; }
+const float* dmap(const mg_ctx* c, float*) { return c->d_dmap32; }
 
 // One iterate on level l for A_l x = f; r is level-l workspace (one of the
 // level's two residual buffers).  If residual_current, r already holds f - A_l x.
@@ -618,7 +694,15 @@ int cycle_body(mg_ctx* c, int l, const T* f, T* x, T* r, bool residual_current, 
   HIPCHK(c, mgk::launch_restrict<T>(b.lev, bc.lev, r, wc.f, (coarse_is_k0 || tail) ? nullptr : wc.x,
                                     (coarse_is_k0 || tail) ? nullptr : wc.r, s));
   for (int g = 0; g < c->o.gamma; g++) {
-    if (tail)
+    if (tail && c->dmap_n) {
+      // x_c = B f_c from zero; a further iterate x_c += B (f_c - A x_c)
+      if (g == 0) {
+        HIPCHK(c, mgk::launch_dense_map<T>(dmap(c, (T*)nullptr), c->dmap_n, wc.f, wc.x, 0, s));
+      } else {
+        HIPCHK(c, mgk::launch_residual<T>(bc.lev, wc.f, wc.x, wc.r, nullptr, 0, nullptr, s));
+        HIPCHK(c, mgk::launch_dense_map<T>(dmap(c, (T*)nullptr), c->dmap_n, wc.r, wc.x, 1, s));
+      }
+    } else if (tail)
       HIPCHK(c, mgk::launch_tail<T>(c->tail, wc.f, wc.x, g == 0 ? 1 : 0, s));
     else if ((st = cycle_body<T>(c, l - 1, wc.f, wc.x, wc.r, g == 0, s)) != MG_OK)
       return st;
@@ -890,6 +974,9 @@ int mg_setup(int level, double alpha, int problem, const mg_opts* opts, mg_ctx**
     // MGKKT_NO_MAP=1 runs the tail's sub-cycle on every level instead of the coarse map
     const char* m = std::getenv("MGKKT_NO_MAP");
     c->map_allowed = !(m && m[0] == '1');
+    // MGKKT_NO_DENSE_MAP=1 launches the tail instead of the dense map of its top level
+    const char* dm = std::getenv("MGKKT_NO_DENSE_MAP");
+    c->dmap_allowed = !(dm && dm[0] == '1') && !t_batch_instance;
     // MGKKT_NO_SWEEP_NORM=1 recomputes f - A x for the norm after every iterate
     const char* q = std::getenv("MGKKT_NO_SWEEP_NORM");
     c->sweep_norm_allowed = !(q && q[0] == '1');
@@ -1522,7 +1609,9 @@ int mg_batch_setup(int count, const int* levels, const double* alphas, int probl
   };
   for (int i = 0; i < count; i++) {
     mg_ctx* c = nullptr;
+    t_batch_instance = true;
     int st = mg_setup(levels[i], alphas[i], problem, &o, &c);
+    t_batch_instance = false;
     if (st != MG_OK) return bail(st);
     b->inst.push_back(c);
     b->level.push_back(levels[i]);

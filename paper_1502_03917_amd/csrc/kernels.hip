@@ -960,6 +960,71 @@ hipError_t launch_b_gather_norms(const double* const* d, int count, double* out,
   return hipGetLastError();
 }
 
+// ---- dense coarse map: x = B r (accumulate 0) or x += B r (accumulate 1),
+// B row-major N x N with N even.  One wave per row and 8 rows per workgroup;
+// r is staged in LDS; a lane reads pairs of entries (one 16- or 8-byte load),
+// all of a row's loads in flight at once, and the wave sums its lanes in a
+// fixed order.
+namespace {
+constexpr int kDenseRows = 8;
+template <typename T>
+struct Pair2;
+template <>
+struct Pair2<double> {
+  typedef double type __attribute__((ext_vector_type(2)));
+};
+template <>
+struct Pair2<float> {
+  typedef float type __attribute__((ext_vector_type(2)));
+};
+
+template <typename T>
+__global__ __launch_bounds__(64 * kDenseRows) void k_dense_map(const T* __restrict__ B, int N, const T* __restrict__ r,
+                                                             T* __restrict__ x, int accumulate) {
+  using T2 = typename Pair2<T>::type;
+  __shared__ __align__(16) T rs[kDenseMapMaxN];
+  const int tid = threadIdx.x, lane = tid & 63;
+  for (int e = tid; e < N; e += 64 * kDenseRows) rs[e] = r[e];
+  __syncthreads();
+  const int row = blockIdx.x * kDenseRows + (tid >> 6);
+  if (row >= N) return;
+  const T2* b2 = reinterpret_cast<const T2*>(B + (size_t)row * N);
+  const T2* r2 = reinterpret_cast<const T2*>(rs);
+  const int np = N / 2;
+  constexpr int U = (kDenseMapMaxN / 2 + 63) / 64;  // pairs per lane: the whole row in one batch
+  T2 v[U];
+#pragma unroll
+  for (int u = 0; u < U; u++) {
+    const int q = lane + 64 * u;
+    v[u] = q < np ? b2[q] : (T2){(T)0, (T)0};
+  }
+  T a0 = 0, a1 = 0;
+#pragma unroll
+  for (int u = 0; u < U; u++) {
+    const int q = lane + 64 * u;
+    if (q < np) {
+      const T2 rv = r2[q];
+      a0 += v[u].x * rv.x;
+      a1 += v[u].y * rv.y;
+    }
+  }
+  T acc = a0 + a1;
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
+  if (lane == 0) x[row] = accumulate ? x[row] + acc : acc;
+}
+}  // namespace
+
+template <typename T>
+hipError_t launch_dense_map(const T* B, int N, const T* r, T* x, int accumulate, hipStream_t s) {
+  if (N <= 0 || N > kDenseMapMaxN || (N & 1)) return hipErrorInvalidValue;
+  hipLaunchKernelGGL((k_dense_map<T>), dim3((N + kDenseRows - 1) / kDenseRows), dim3(64 * kDenseRows), 0, s, B, N, r,
+                     x, accumulate);
+  return hipGetLastError();
+}
+template hipError_t launch_dense_map<double>(const double*, int, const double*, double*, int, hipStream_t);
+template hipError_t launch_dense_map<float>(const float*, int, const float*, float*, int, hipStream_t);
+
 #define MGK_INSTANTIATE(T)                                                                                          \
   template hipError_t launch_residual<T>(const Lev&, const T*, const T*, T*, double*, int, int*, hipStream_t);         \
   template hipError_t launch_apply<T>(const Lev&, const T*, T*, hipStream_t);                                      \

@@ -57,6 +57,11 @@ enum { kTailSmooth = 1, kTailResidual = 2, kTailRestrict = 3, kTailCoarse = 4, k
 // (and everything below it) is a fixed linear map of the level's residual,
 // kept as a dense matrix (2 (2^3 + 1)^2 = 162 unknowns)
 constexpr int kTailMapLevel = 3;
+// dense coarse map of the tail's top level kDenseMapLevel: the whole
+// sub-cycle on that level and below (a linear map of the level's right-hand
+// side) as one N x N matrix, N = 2 (2^5 + 1)^2
+constexpr int kDenseMapLevel = 5;
+constexpr int kDenseMapMaxN = 2 * ((1 << kDenseMapLevel) + 1) * ((1 << kDenseMapLevel) + 1);
 enum { MG_TAIL_NE = 0, MG_TAIL_LSGS = 1, MG_TAIL_SLSGS = 2, MG_TAIL_CGS = 3 };
 struct TailLaunch {
   int k0, T, nops, smoother, ncoarse;
@@ -147,6 +152,9 @@ hipError_t tail_allow_lds(size_t bytes);
 
 // *out = scale * (sum of the n partials)
 hipError_t launch_sum(const double* part, int n, double* out, hipStream_t s, double scale = 1.0);
+// x = B r (accumulate 0) or x += B r (accumulate 1), B row-major N x N (N even, <= kDenseMapMaxN)
+template <typename T>
+hipError_t launch_dense_map(const T* B, int N, const T* r, T* x, int accumulate, hipStream_t s);
 // gyd = M xa^y; part = per-block partial sums of (xa^lambda)^T M lambda
 hipError_t launch_adjoint_grad(const Lev& L, const double* x, const double* xa, double* gyd, double* part,
                                int* nblocks, hipStream_t s);

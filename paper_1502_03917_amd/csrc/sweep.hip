@@ -17,6 +17,8 @@
 // Global traffic per owned vertex: x read and written once, r written once,
 // r read once plus the halo share (neighbouring tiles re-read each other's
 // borders, mostly from L2 because consecutive tiles run on the same XCD).
+#include <type_traits>
+
 #include "mg_internal.hpp"
 
 namespace mgk {
@@ -97,11 +99,17 @@ __device__ __forceinline__ void lsgs_tile_body(const Lev& L, int ntx, int nty, i
   constexpr int NR = (G::RMAX * G::RMAX + NT - 1) / NT;  // region cells per thread
   constexpr int NX = (TW * TW + NT - 1) / NT;            // owned cells per thread
   constexpr int SMAX = PhaseItems<TW>::SMAX;
-  // One pass of the workgroup covers every phase: each thread then has at
-  // most one vertex per phase, known in advance, and updates its x directly
-  // (x prefetched at the start, x + p stored in the phase).  Otherwise the
+  // The rows of a phase window are enumerated from the tile's first row on,
+  // wrapping round to the halo rows above it.  When the first pass of the
+  // workgroup (NT / SMAX rows) spans the tile's height, every owned vertex of a
+  // phase falls in it: each thread then has at most one owned vertex per
+  // phase, known in advance, and updates its x directly (x prefetched at the
+  // start, x + p stored in the phase); window rows beyond the first pass are
+  // halo rows and give some threads a second vertex (kSecond).  Otherwise the
   // corrections of the owned vertices collect in LDS and x is written at the end.
-  constexpr bool kOnePass = PhaseItems<TW>::W0 * SMAX <= NT;
+  constexpr bool kOnePass = TW <= NT / SMAX;
+  constexpr bool kSecond = kOnePass && PhaseItems<TW>::W0 * SMAX > NT;
+  static_assert(PhaseItems<TW>::W0 * SMAX <= 2 * NT || !kOnePass, "at most two vertices per thread and phase");
   // residual (y, lambda) of the region; the guard ring and the cells of the
   // region that lie outside the square hold zeros, so the neighbours of a
   // boundary vertex can be read and written without bounds checks (their
@@ -145,7 +153,12 @@ __device__ __forceinline__ void lsgs_tile_body(const Lev& L, int ntx, int nty, i
     const int S = kOnePass ? SMAX : (wh - wl + 6) / 7;
     const int rr = k / S, t = k - rr * S;
     Item it;
-    it.gj = wb + rr;
+    if constexpr (kOnePass) {
+      it.gj = j0 + rr;  // wb <= j0 < j1 <= wt
+      if (it.gj >= wt) it.gj -= wt - wb;
+    } else {
+      it.gj = wb + rr;
+    }
     it.gi = wl + ((colour - 2 * it.gj - wl) % 7 + 7) % 7 + 7 * t;
     it.act = k < (wt - wb) * S && it.gi < wh;
     return it;
@@ -286,6 +299,12 @@ __device__ __forceinline__ void lsgs_tile_body(const Lev& L, int ntx, int nty, i
       // (masked store for other items)
       bstore(Rx, xo[ph], xy[ph] + py);
       bstore(Rx, xo[ph] == kOff ? kOff : xo[ph] + fo, xl[ph] + pl);
+      if constexpr (kSecond) {
+        // a halo vertex of the rows past the first pass (no x)
+        const Item it2 = item_of(ph, tid + NT);
+        T qy = 0, ql = 0;
+        update(it2, qy, ql);
+      }
       lds_barrier();
     }
   } else {
@@ -375,22 +394,29 @@ inline int tiles_along(int npts, int TW) { return (npts + TW - 1) / TW; }
 // One workgroup per tile; the grid is padded to a multiple of 8 so that the
 // XCD-aware tile order applies (spare workgroups exit at once).
 //
-// Tile shapes (measured on gfx950).  Large levels: 48 x 48 tiles; FP64 tiles
-// need 140 KB of LDS, so one workgroup fits per CU and it takes 1024 threads
-// (16 waves) to hide LDS and FP64 latency; FP32 tiles need 70 KB and run as
-// two 512-thread workgroups per CU.  Small levels (up to 257^2 vertices in
-// FP64, 513^2 in FP32) are latency-bound (one round of tiles): 16 x 16 tiles
-// with 256 threads take about 15 us per sweep there instead of about 25 us.
-// (A persistent grid that prefetches the next tile measured slower: its extra
-// registers limit it to 512 threads.)
+// Tile shapes per level (measured on gfx950, us per sweep).  A tile of
+// 1024 threads holds one CU (FP64 regions need 100-150 KB of LDS), so a sweep
+// runs in rounds of 256 tiles and the tile edge is picked for whole rounds:
+//   FP64  1025^2: 48 x 48 (484 tiles, 2 rounds) 33.1, 65 x 65 (256, 1) 28.7
+//         2049^2: 48 x 48 (1849, 8 rounds) 108.9, 65 x 65 (1024, 4) 102.7
+//         4097^2: 48 x 48 467.5, 56 x 56 439.1, 65 x 65 484.0
+//          513^2: 48 x 48 18.1 (65 x 65: 24.8)
+//   FP32 (512-thread tiles, 70 KB, two per CU): 48 x 48 except at 2049^2,
+//         where 46 x 46 tiles (2025 tiles, 4 rounds of 512) take 55.9 against 58.8.
+// Levels up to 257^2 vertices (FP64) or 513^2 (FP32) run one round of small
+// tiles and are latency-bound: 16 x 16 tiles with 256 threads take about
+// 10-15 us per sweep there instead of about 25 us.  (A persistent grid that
+// keeps a workgroup per CU and prefetches the next tile's region measured
+// slower at every size: 123 against 110 us at 2049^2 with 44 x 44 tiles and
+// 768 threads, since its extra registers cap the threads per CU.)
 inline int round8(int v) { return (v + 7) / 8 * 8; }
 
 template <typename T>
 struct SweepShape;
 template <>
 struct SweepShape<double> {
-  static constexpr int TW = 48, NT = 1024;
-  static constexpr int kSmallMaxN = 256;  // n of the largest level swept with small tiles
+  static constexpr int TW = 48, NT = 1024;  // batched launches, 513^2
+  static constexpr int kSmallMaxN = 256;    // n of the largest level swept with small tiles
 };
 template <>
 struct SweepShape<float> {
@@ -399,22 +425,30 @@ struct SweepShape<float> {
 };
 constexpr int kSmallTW = 16, kSmallNT = 256;
 
+template <typename T, int TW, int NT>
+hipError_t launch_tile(const Lev& L, int reverse, const T* xin, T* x, const T* rin, T* rout, hipStream_t s,
+                       double* part, int norm_mode, int* nparts) {
+  const int nt = tiles_along(L.n + 1, TW);
+  if (nparts) *nparts = nt * nt;
+  hipLaunchKernelGGL((k_lsgs_tile<T, TW, NT>), dim3(round8(nt * nt)), dim3(NT), 0, s, L, nt, nt, reverse, xin, x, rin,
+                     rout, part, norm_mode);
+  return hipGetLastError();
+}
+
 template <typename T>
 hipError_t launch_tile_cfg(const Lev& L, int reverse, const T* xin, T* x, const T* rin, T* rout, hipStream_t s,
                            double* part = nullptr, int norm_mode = 0, int* nparts = nullptr) {
-  if (L.n <= SweepShape<T>::kSmallMaxN) {
-    const int nt = tiles_along(L.n + 1, kSmallTW);
-    if (nparts) *nparts = nt * nt;
-    hipLaunchKernelGGL((k_lsgs_tile<T, kSmallTW, kSmallNT>), dim3(round8(nt * nt)), dim3(kSmallNT), 0, s, L, nt, nt,
-                       reverse, xin, x, rin, rout, part, norm_mode);
+  if (L.n <= SweepShape<T>::kSmallMaxN)
+    return launch_tile<T, kSmallTW, kSmallNT>(L, reverse, xin, x, rin, rout, s, part, norm_mode, nparts);
+  if constexpr (std::is_same<T, double>::value) {
+    if (L.n == 1024 || L.n == 2048)
+      return launch_tile<T, 65, 1024>(L, reverse, xin, x, rin, rout, s, part, norm_mode, nparts);
+    if (L.n >= 4096) return launch_tile<T, 56, 1024>(L, reverse, xin, x, rin, rout, s, part, norm_mode, nparts);
   } else {
-    constexpr int TW = SweepShape<T>::TW, NT = SweepShape<T>::NT;
-    const int nt = tiles_along(L.n + 1, TW);
-    if (nparts) *nparts = nt * nt;
-    hipLaunchKernelGGL((k_lsgs_tile<T, TW, NT>), dim3(round8(nt * nt)), dim3(NT), 0, s, L, nt, nt, reverse, xin, x,
-                       rin, rout, part, norm_mode);
+    if (L.n == 2048) return launch_tile<T, 46, 512>(L, reverse, xin, x, rin, rout, s, part, norm_mode, nparts);
   }
-  return hipGetLastError();
+  return launch_tile<T, SweepShape<T>::TW, SweepShape<T>::NT>(L, reverse, xin, x, rin, rout, s, part, norm_mode,
+                                                              nparts);
 }
 
 }  // namespace

@@ -28,12 +28,21 @@ __device__ inline double lane_bcast(double v, int k) {
   return __builtin_bit_cast(double, ((unsigned long long)hi << 32) | lo);
 }
 
-// bytes of the shared scratch: NE corrections of level T (2 V_T entries) or
-// the FP64 right-hand side of the coarsest solve, whichever is larger
+// unknowns of the level that the coarse map covers, and the waves that split
+// its columns
+constexpr int kTailMapN = 2 * ((1 << kTailMapLevel) + 1) * ((1 << kTailMapLevel) + 1);
+constexpr int kTailWaves = kTailThreads / 64;
+static_assert(kTailMapN <= 3 * 64, "map rows: three per lane");
+
+// bytes of the shared scratch: NE corrections of level T (2 V_T entries), the
+// FP64 right-hand side of the coarsest solve, or the per-wave partial sums of
+// the coarse map product (tails above the map level), whichever is largest
 template <typename T>
-__host__ __device__ inline size_t tail_scratch_bytes(int VT, int ncoarse) {
+__host__ __device__ inline size_t tail_scratch_bytes(int VT, int ncoarse, int Tl) {
   const size_t a = (size_t)2 * VT * sizeof(T), b = (size_t)ncoarse * sizeof(double);
-  return a > b ? a : b;
+  const size_t c = Tl > kTailMapLevel ? (size_t)kTailWaves * kTailMapN * sizeof(T) : 0;
+  const size_t ab = a > b ? a : b;
+  return ab > c ? ab : c;
 }
 
 struct TailLevel {
@@ -53,6 +62,8 @@ struct TailArgs {
   int ncoarse;
   const T* map;          // coarse map of level kTailMapLevel (column-major, nmap x nmap), or nullptr
   int nmap;
+  int tab_lo;            // lowest level whose class blocks are used (below the map level: none)
+  int use_lu;            // 0: no coarsest solve in the op list (the map covers it)
   const T* fT;           // f on level T (global)
   T* xT;                 // x on level T (global): in (if !first) / out
   int first;             // 1: x_T starts at zero and r_T = f_T
@@ -78,7 +89,7 @@ __device__ __forceinline__ void tail_body(const TailArgs<T>& A) {
   auto align16 = [](size_t b) { return (b + 15) & ~size_t(15); };
   const size_t off_sp =
       align16((size_t)off_end * sizeof(T) + (size_t)(kTailMaxLevels + 1) * 25 * kC5 * sizeof(T));
-  const size_t off_lu = align16(off_sp + tail_scratch_bytes<T>(A.lv[Tl].V, A.ncoarse));
+  const size_t off_lu = align16(off_sp + tail_scratch_bytes<T>(A.lv[Tl].V, A.ncoarse, Tl));
   const int N0 = A.ncoarse;
   T* tC = sm + off_end;                                   // 25 * kC5 per level l in (k0, T]
   T* sp = reinterpret_cast<T*>(smem_raw + off_sp);        // NE scratch (2 V_T), also the coarse rhs in FP64
@@ -107,8 +118,8 @@ __device__ __forceinline__ void tail_body(const TailArgs<T>& A) {
       }
     }
   };
-  for (int l = k0 + 1; l <= Tl; l++) copy_in(tC + l * 25 * kC5, &A.lev[l].tab->C5[0][0], 25 * kC5);
-  {
+  for (int l = A.tab_lo; l <= Tl; l++) copy_in(tC + l * 25 * kC5, &A.lev[l].tab->C5[0][0], 25 * kC5);
+  if (A.use_lu) {
     // the LU stays FP64
     constexpr int B = 8;
     for (int base = 0; base < N0 * N0; base += B * NT) {
@@ -214,6 +225,9 @@ __device__ __forceinline__ void tail_body(const TailArgs<T>& A) {
       va[d] = *pa[d];
       vb[d] = *pb[d];
     }
+    // all 14 loads in flight before the first use (left to itself the
+    // scheduler interleaves them with the sums, one LDS round trip per pair)
+    __builtin_amdgcn_sched_barrier(0);
     T py, pl;
     if (!collective) {
       T qy = 0, ql = 0;
@@ -400,25 +414,42 @@ __device__ __forceinline__ void tail_body(const TailArgs<T>& A) {
         break;
       }
       case kTailApplyMap: {  // x_l += B r_l: the whole sub-cycle on level l and below, from zero
-        // row tid of B (column-major, so a batch of columns is one coalesced
-        // load per column); the loads of a batch are issued together
+        // B is column-major: for one column, the lanes of a wave read
+        // consecutive rows.  Each wave takes a quarter of the columns and each
+        // lane three rows (lane, lane + 64, lane + 128), so a thread has
+        // 3 x 14 loads in flight per batch; the per-wave partial sums meet in
+        // the scratch and are added in wave order.
         const LP P = level_params(l);
-        const int N = A.nmap;
-        if (tid < N) {
-          const T* rv = sm + P.or_;
-          constexpr int B = 18;
-          T acc0 = 0, acc1 = 0;
-          for (int c0 = 0; c0 < N; c0 += B) {
-            T v[B];
+        const int N = A.nmap;  // <= kTailMapN
+        const int w = tid >> 6, lane = tid & 63;
+        const int q = (N + kTailWaves - 1) / kTailWaves, cb0 = w * q, cb1 = min(N, cb0 + q);
+        const T* rv = sm + P.or_;
+        T acc[3] = {(T)0, (T)0, (T)0};
+        constexpr int B = 14;
+        for (int cb = cb0; cb < cb1; cb += B) {
+          T v[3][B];
 #pragma unroll
-            for (int u = 0; u < B; u++) v[u] = c0 + u < N ? A.map[(size_t)(c0 + u) * N + tid] : (T)0;
+          for (int u = 0; u < B; u++)
 #pragma unroll
-            for (int u = 0; u < B; u += 2) {
-              if (c0 + u < N) acc0 += v[u] * rv[c0 + u];
-              if (c0 + u + 1 < N) acc1 += v[u + 1] * rv[c0 + u + 1];
+            for (int k = 0; k < 3; k++) {
+              const int row = lane + 64 * k, c = cb + u;
+              v[k][u] = (c < cb1 && row < N) ? A.map[(size_t)c * N + row] : (T)0;
             }
+#pragma unroll
+          for (int u = 0; u < B; u++) {
+            const T rc = cb + u < cb1 ? rv[cb + u] : (T)0;
+#pragma unroll
+            for (int k = 0; k < 3; k++) acc[k] += v[k][u] * rc;
           }
-          sm[P.ox + tid] += acc0 + acc1;
+        }
+#pragma unroll
+        for (int k = 0; k < 3; k++)
+          if (lane + 64 * k < N) sp[w * N + lane + 64 * k] = acc[k];
+        bar();
+        if (tid < N) {
+          T sum = sp[tid];
+          for (int ww = 1; ww < kTailWaves; ww++) sum += sp[ww * N + tid];
+          sm[P.ox + tid] += sum;
         }
         bar();
         break;
@@ -466,7 +497,7 @@ size_t tail_layout(int k0, int Tl, TailLevel* lv) {
   }
   const int N0 = 2 * ((1 << k0) + 1) * ((1 << k0) + 1);
   return (size_t)at * sizeof(T) + (size_t)(kTailMaxLevels + 1) * 25 * kC5 * sizeof(T) + 16 +
-         tail_scratch_bytes<T>(lv[Tl].V, N0) + 16 + (size_t)N0 * N0 * sizeof(double) + 2 * sizeof(T);
+         tail_scratch_bytes<T>(lv[Tl].V, N0, Tl) + 16 + (size_t)N0 * N0 * sizeof(double) + 2 * sizeof(T);
 }
 
 template <typename T>
@@ -488,6 +519,8 @@ size_t fill_tail_args(const TailLaunch& tl, const T* fT, T* xT, int first, const
   else
     a.map = tl.map32;
   a.nmap = tl.nmap;
+  a.tab_lo = a.map ? kTailMapLevel : tl.k0 + 1;  // a W-cycle takes a residual on the map level
+  a.use_lu = a.map ? 0 : 1;
   a.fT = fT;
   a.xT = xT;
   a.first = first;

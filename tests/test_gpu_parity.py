@@ -252,6 +252,34 @@ def test_coarse_map_equals_subcycle(torch_cuda, monkeypatch, smoother, gamma):
         assert np.linalg.norm(xs[0] - xs[1]) <= bound * np.linalg.norm(xs[1]), precision
 
 
+@pytest.mark.parametrize("smoother,gamma", [("lsgs", 1), ("ne", 1), ("slsgs", 2), ("lsgs", 2)])
+@pytest.mark.parametrize("level", [6, 8])
+def test_dense_map_equals_tail(torch_cuda, monkeypatch, smoother, gamma, level):
+    # the dense map of the level-5 sub-cycle (one matrix-vector product per
+    # coarse iterate) against the tail launch it replaces (MGKKT_NO_DENSE_MAP=1):
+    # same iterates to rounding, for V- and W-cycles, in FP64 and FP32 refinement
+    torch = torch_cuda
+    mg = _mg()
+    alpha = 1e-3
+    nu = 1 if smoother == "slsgs" else 2
+    yd = _dev(torch, workloads.desired_state(level, 3))
+    for precision, bound in (("fp64", 1e-13), ("fp32_ir", 1e-5)):
+        xs = []
+        for env in (None, "1"):
+            if env:
+                monkeypatch.setenv("MGKKT_NO_DENSE_MAP", env)
+            else:
+                monkeypatch.delenv("MGKKT_NO_DENSE_MAP", raising=False)
+            s = mg.Solver(level, alpha, smoother=smoother, gamma=gamma, nu1=nu, nu2=nu, precision=precision)
+            f = s.rhs(yd)
+            x = torch.zeros_like(f)
+            for _ in range(3):
+                s.cycle(f, x)
+            xs.append(_host(x))
+        monkeypatch.delenv("MGKKT_NO_DENSE_MAP", raising=False)
+        assert np.linalg.norm(xs[0] - xs[1]) <= bound * np.linalg.norm(xs[1]), precision
+
+
 @pytest.mark.parametrize("smoother,nu", [("lsgs", 2), ("slsgs", 1)])
 def test_sweep_norm_solve(torch_cuda, monkeypatch, smoother, nu):
     # FP64 solves take each iterate's norm from the residual the last sweep
@@ -407,3 +435,22 @@ def test_full_size_cycle_parity(torch_cuda):
     xo = np.zeros(h.ndof())
     h.cycle(f, xo, smoother="lsgs", order="col7")
     assert np.linalg.norm(xgh - xo) <= 1e-12 * np.linalg.norm(xo)
+
+
+@pytest.mark.parametrize("alpha", [1e-4])
+def test_fp32_refinement_full_size(torch_cuda, alpha):
+    # the benchmark's size (2049^2 vertices): FP32 cycles inside FP64
+    # refinement reach the FP64 tolerance (the outer residual is the FP64
+    # residual kernel's) and the iterate agrees with the plain FP64 solve,
+    # whose cycle matches the oracle at this size
+    torch = torch_cuda
+    mg = _mg()
+    level = 11
+    yd = _dev(torch, workloads.desired_state(level, 2))
+    s32 = mg.Solver(level, alpha, precision="fp32_ir")
+    s64 = mg.Solver(level, alpha)
+    f = s64.rhs(yd)
+    x32, it32, rel32, st32 = s32.solve(f, tol=1e-10)
+    x64, it64, rel64, st64 = s64.solve(f, tol=1e-10)
+    assert st32 == mg.MG_OK and st64 == mg.MG_OK and rel32 <= 1e-10 and rel64 <= 1e-10
+    assert torch.linalg.vector_norm(x32 - x64).item() <= 1e-8 * torch.linalg.vector_norm(x64).item()
