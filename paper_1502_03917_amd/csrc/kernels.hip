@@ -984,29 +984,46 @@ __global__ __launch_bounds__(64 * kDenseRows) void k_dense_map(const T* __restri
   using T2 = typename Pair2<T>::type;
   __shared__ __align__(16) T rs[kDenseMapMaxN];
   const int tid = threadIdx.x, lane = tid & 63;
-  for (int e = tid; e < N; e += 64 * kDenseRows) rs[e] = r[e];
-  __syncthreads();
   const int row = blockIdx.x * kDenseRows + (tid >> 6);
-  if (row >= N) return;
-  const T2* b2 = reinterpret_cast<const T2*>(B + (size_t)row * N);
-  const T2* r2 = reinterpret_cast<const T2*>(rs);
   const int np = N / 2;
+  // loads in issue order: this thread's share of r, then the whole row (in
+  // flight while r is staged in LDS: the wait for r does not wait for them)
+  constexpr int RU = (kDenseMapMaxN + 64 * kDenseRows - 1) / (64 * kDenseRows);
+  T rv0[RU];
+#pragma unroll
+  for (int u = 0; u < RU; u++) {
+    const int e = tid + u * 64 * kDenseRows;
+    rv0[u] = r[e < N ? e : N - 1];  // unconditional loads keep the wait counts exact
+  }
   constexpr int U = (kDenseMapMaxN / 2 + 63) / 64;  // pairs per lane: the whole row in one batch
   T2 v[U];
+  const T2* b2 = reinterpret_cast<const T2*>(B + (size_t)(row < N ? row : 0) * N);
 #pragma unroll
   for (int u = 0; u < U; u++) {
     const int q = lane + 64 * u;
-    v[u] = q < np ? b2[q] : (T2){(T)0, (T)0};
+    // clamped index and a zero weight past the row's end: the load itself
+    // stays unconditional (a guarded load would be moved under a branch)
+    const T w = q < np ? (T)1 : (T)0;
+    v[u] = b2[q < np ? q : np - 1] * w;
   }
+#pragma unroll
+  for (int u = 0; u < RU; u++) {
+    const int e = tid + u * 64 * kDenseRows;
+    if (e < N) rs[e] = rv0[u];
+  }
+  // a barrier that orders the LDS stores only (the row's loads stay in flight)
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+  if (row >= N) return;
+  const T2* r2 = reinterpret_cast<const T2*>(rs);
   T a0 = 0, a1 = 0;
 #pragma unroll
   for (int u = 0; u < U; u++) {
     const int q = lane + 64 * u;
-    if (q < np) {
-      const T2 rv = r2[q];
-      a0 += v[u].x * rv.x;
-      a1 += v[u].y * rv.y;
-    }
+    const T2 rv = r2[q < np ? q : 0];
+    a0 += v[u].x * rv.x;
+    a1 += v[u].y * rv.y;
   }
   T acc = a0 + a1;
 #pragma unroll
