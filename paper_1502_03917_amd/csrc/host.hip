@@ -224,6 +224,7 @@ struct mg_ctx {
   double* h_norm = nullptr;  // pinned host copy
   bool fp32_ready = false;
   bool fused = true;  // one kernel per LSGS sweep (else one kernel per colour phase)
+  bool sweep2 = true;  // two sweeps per launch on small coarse levels (MGKKT_NO_SWEEP2 unset)
   // coarse-level tail: one workgroup runs the sub-cycle on levels k0..tail_T
   int tail_T = 0;       // 0: no tail
   bool tail_allowed = true;
@@ -427,6 +428,9 @@ int smooth_steps(mg_ctx* c, int l, T* x, T*& r, T* alt, T* p, int steps, hipStre
   const Lev& L = b.lev;
   const bool timed = c->timing && l == c->level && !c->capturing;
   const bool fused = c->fused && alt != nullptr;
+  // below the finest level, small levels run two sweeps per launch (an
+  // LSGS pair, or the forward and backward sweep of an sLSGS step)
+  const bool pairs = fused && c->sweep2 && l < c->level && L.n <= mgk::lsgs_sweep2_max_n();
   for (int it = 0; it < steps; it++) {
     // the first tile sweep may take the iterate from xin0 (fused prolongation)
     const T* xin = (it == 0 && xin0) ? xin0 : x;
@@ -440,7 +444,11 @@ int smooth_steps(mg_ctx* c, int l, T* x, T*& r, T* alt, T* p, int steps, hipStre
         HIPCHK(c, mgk::launch_ne<T>(L, x, r, p, s));
         break;
       case MG_LSGS:
-        if (fused) {
+        if (pairs && it + 1 < steps) {
+          HIPCHK(c, mgk::launch_lsgs_sweep2<T>(L, 0, xin, x, r, alt, s));
+          std::swap(r, alt);
+          it++;
+        } else if (fused) {
           HIPCHK(c, last_sweep<T>(L, 0, xin, x, r, alt, snl, s));
           std::swap(r, alt);
         } else {
@@ -448,7 +456,10 @@ int smooth_steps(mg_ctx* c, int l, T* x, T*& r, T* alt, T* p, int steps, hipStre
         }
         break;
       case MG_SLSGS:
-        if (fused) {
+        if (pairs) {
+          HIPCHK(c, mgk::launch_lsgs_sweep2<T>(L, 2, xin, x, r, alt, s));
+          std::swap(r, alt);
+        } else if (fused) {
           HIPCHK(c, mgk::launch_lsgs_sweep_from<T>(L, 0, xin, x, r, alt, s));
           HIPCHK(c, last_sweep<T>(L, 1, x, x, alt, r, snl, s));
         } else {
@@ -968,6 +979,9 @@ int mg_setup(int level, double alpha, int problem, const mg_opts* opts, mg_ctx**
     // MGKKT_PHASE_KERNELS=1 selects one launch per colour phase (comparison and testing)
     const char* e = std::getenv("MGKKT_PHASE_KERNELS");
     c->fused = !(e && e[0] == '1');
+    // MGKKT_NO_SWEEP2=1 runs one sweep per launch on every level
+    const char* e2 = std::getenv("MGKKT_NO_SWEEP2");
+    c->sweep2 = !(e2 && e2[0] == '1');
     // MGKKT_NO_TAIL=1 runs the coarse levels with the per-level kernels
     const char* t = std::getenv("MGKKT_NO_TAIL");
     c->tail_allowed = !(t && t[0] == '1');

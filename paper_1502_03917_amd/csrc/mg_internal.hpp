@@ -128,6 +128,12 @@ template <typename T>
 hipError_t launch_lsgs_sweep_from(const Lev& L, int reverse, const T* xin, T* x, const T* rin, T* rout, hipStream_t s);
 // an FP64 sweep that also stores per-tile partial sums of ||r_out||^2
 // (norm_mode 1: Euclidean, 2: L^{-1}) in part; *nparts = number of tiles
+// two LSGS sweeps in one launch on levels with n <= lsgs_sweep2_max_n()
+// (bit s of revmask: sweep s in reverse colour order); r from rin, the
+// residual after both sweeps to rout
+template <typename T>
+hipError_t launch_lsgs_sweep2(const Lev& L, int revmask, const T* xin, T* x, const T* rin, T* rout, hipStream_t s);
+int lsgs_sweep2_max_n();
 hipError_t launch_lsgs_sweep_norm(const Lev& L, int reverse, const double* xin, double* x, const double* rin,
                                   double* rout, double* part, int norm_mode, int* nparts, hipStream_t s);
 template <typename T>

@@ -59,9 +59,9 @@ __device__ inline void bstore(__amdgpu_buffer_rsrc_t r, unsigned off, float v) {
   __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, off, 0, 0);
 }
 
-template <int TW>
+template <int TW, int H = kHalo>
 struct TileGeom {
-  static constexpr int RMAX = TW + 2 * kHalo;  // widest / tallest region
+  static constexpr int RMAX = TW + 2 * H;  // widest / tallest region (halo H)
   static constexpr int RP = RMAX + 3;          // pitch: one guard cell each side, one pad cell
   static constexpr int RN = RP * (RMAX + 2);   // region cells with guard rows
 };
@@ -81,24 +81,27 @@ struct Pair<float> {
 // Work items of a colour phase are (row, slot) pairs: slot t of a row is its
 // t-th vertex of the phase's colour inside the window.  A window row of width
 // w holds at most ceil(w / 7) of them.
-template <int TW>
+template <int TW, int H = kHalo>
 struct PhaseItems {
-  static constexpr int W0 = TW + 2 * kHalo - 2;  // width and height of the widest (first) window
+  static constexpr int W0 = TW + 2 * H - 2;  // width and height of the widest (first) window
   static constexpr int SMAX = (W0 + 6) / 7;      // slots per row that cover every window
 };
 
 // The iterate is read from xin and written to x (the same buffer, or a
 // distinct one when the sweep also moves x: xin is read only before x is
-// written, per owned vertex).
-template <typename T, int TW, int NT>
+// written, per owned vertex).  NSW sweeps run in one pass over the tile
+// (halo 14 NSW, 7 NSW colour phases); bit s of reverse gives the order of
+// sweep s.
+template <typename T, int TW, int NT, int NSW = 1>
 __device__ __forceinline__ void lsgs_tile_body(const Lev& L, int ntx, int nty, int reverse, const T* xin, T* x,
                                                const T* __restrict__ rin, T* __restrict__ rout,
                                                double* __restrict__ part = nullptr, int norm_mode = 0) {
-  using G = TileGeom<TW>;
+  constexpr int H = kHalo * NSW;
+  using G = TileGeom<TW, H>;
   using T2 = typename Pair<T>::type;
   constexpr int NR = (G::RMAX * G::RMAX + NT - 1) / NT;  // region cells per thread
   constexpr int NX = (TW * TW + NT - 1) / NT;            // owned cells per thread
-  constexpr int SMAX = PhaseItems<TW>::SMAX;
+  constexpr int SMAX = PhaseItems<TW, H>::SMAX;
   // The rows of a phase window are enumerated from the tile's first row on,
   // wrapping round to the halo rows above it.  When the first pass of the
   // workgroup (NT / SMAX rows) spans the tile's height, every owned vertex of a
@@ -107,9 +110,11 @@ __device__ __forceinline__ void lsgs_tile_body(const Lev& L, int ntx, int nty, i
   // start, x + p stored in the phase); window rows beyond the first pass are
   // halo rows and give some threads a second vertex (kSecond).  Otherwise the
   // corrections of the owned vertices collect in LDS and x is written at the end.
-  constexpr bool kOnePass = TW <= NT / SMAX;
-  constexpr bool kSecond = kOnePass && PhaseItems<TW>::W0 * SMAX > NT;
-  static_assert(PhaseItems<TW>::W0 * SMAX <= 2 * NT || !kOnePass, "at most two vertices per thread and phase");
+  // (Several sweeps in one pass update an owned vertex once per sweep, so
+  // their corrections always collect in LDS.)
+  constexpr bool kOnePass = NSW == 1 && TW <= NT / SMAX;
+  constexpr bool kSecond = kOnePass && PhaseItems<TW, H>::W0 * SMAX > NT;
+  static_assert(PhaseItems<TW, H>::W0 * SMAX <= 2 * NT || !kOnePass, "at most two vertices per thread and phase");
   // residual (y, lambda) of the region; the guard ring and the cells of the
   // region that lie outside the square hold zeros, so the neighbours of a
   // boundary vertex can be read and written without bounds checks (their
@@ -134,8 +139,8 @@ __device__ __forceinline__ void lsgs_tile_body(const Lev& L, int ntx, int nty, i
   const int tx = tile % ntx, ty = tile / ntx;
   const int i0 = tx * TW, i1 = min(n + 1, i0 + TW);
   const int j0 = ty * TW, j1 = min(n + 1, j0 + TW);
-  const int ci0 = max(0, i0 - kHalo), ci1 = min(n + 1, i1 + kHalo);
-  const int rj0 = max(0, j0 - kHalo), rj1 = min(n + 1, j1 + kHalo);
+  const int ci0 = max(0, i0 - H), ci1 = min(n + 1, i1 + H);
+  const int rj0 = max(0, j0 - H), rj1 = min(n + 1, j1 + H);
   const int RW = ci1 - ci0, RH = rj1 - rj0, OW = i1 - i0, OH = j1 - j0;
 
   // the vertex of work item k in phase ph (gi >= wh or k >= nitems: none)
@@ -144,8 +149,9 @@ __device__ __forceinline__ void lsgs_tile_body(const Lev& L, int ntx, int nty, i
     bool act;
   };
   auto item_of = [&](int ph, int k) {
-    const int colour = reverse ? 6 - ph : ph;
-    const int d = kHalo - 1 - 2 * ph;  // Chebyshev radius of the phase window around the tile
+    const int c7 = ph % 7;
+    const int colour = ((reverse >> (ph / 7)) & 1) ? 6 - c7 : c7;
+    const int d = H - 1 - 2 * ph;  // Chebyshev radius of the phase window around the tile
     const int wl = max(ci0, i0 - d), wh = min(ci1, i1 + d);
     const int wb = max(rj0, j0 - d), wt = min(rj1, j1 + d);
     // a fixed slot count (covering the widest window) keeps the decode free of
@@ -308,8 +314,8 @@ __device__ __forceinline__ void lsgs_tile_body(const Lev& L, int ntx, int nty, i
       lds_barrier();
     }
   } else {
-    for (int ph = 0; ph < 7; ph++) {
-      const int d = kHalo - 1 - 2 * ph;
+    for (int ph = 0; ph < 7 * NSW; ph++) {
+      const int d = H - 1 - 2 * ph;
       const int wl = max(ci0, i0 - d), wh = min(ci1, i1 + d);
       const int wb = max(rj0, j0 - d), wt = min(rj1, j1 + d);
       const int nitems = (wt - wb) * ((wh - wl + 6) / 7);
@@ -317,7 +323,13 @@ __device__ __forceinline__ void lsgs_tile_body(const Lev& L, int ntx, int nty, i
         const Item it = item_of(ph, k);
         T py = 0, pl = 0;
         update(it, py, pl);
-        if (owned(it)) dx2[(it.gj - j0) * TW + (it.gi - i0)] = (T2){py, pl};
+        if (owned(it)) {
+          T2& dv = dx2[(it.gj - j0) * TW + (it.gi - i0)];
+          if constexpr (NSW == 1)
+            dv = (T2){py, pl};
+          else
+            dv += (T2){py, pl};
+        }
       }
       lds_barrier();
     }
@@ -373,11 +385,11 @@ __device__ __forceinline__ void lsgs_tile_body(const Lev& L, int ntx, int nty, i
   }
 }
 
-template <typename T, int TW, int NT>
+template <typename T, int TW, int NT, int NSW = 1>
 __global__ __launch_bounds__(NT) void k_lsgs_tile(Lev L, int ntx, int nty, int reverse, const T* xin, T* x,
                                                   const T* __restrict__ rin, T* __restrict__ rout,
                                                   double* __restrict__ part, int norm_mode) {
-  lsgs_tile_body<T, TW, NT>(L, ntx, nty, reverse, xin, x, rin, rout, part, norm_mode);
+  lsgs_tile_body<T, TW, NT, NSW>(L, ntx, nty, reverse, xin, x, rin, rout, part, norm_mode);
 }
 
 // many instances of one level: instance blockIdx.y, residual read from r
@@ -489,6 +501,33 @@ hipError_t launch_lsgs_sweep_from<float>(const Lev& L, int reverse, const float*
                                          float* rout, hipStream_t s) {
   return launch_tile_cfg<float>(L, reverse, xin, x, rin, rout, s);
 }
+
+// Two sweeps in one launch (bit s of revmask: sweep s in reverse colour
+// order) on the coarse levels up to 513^2, where a sweep is about one
+// latency-bound round of tiles: a 28-vertex halo, 14 colour phases, the
+// corrections of both sweeps collected in LDS; 17 x 17 tiles up to 257^2,
+// 33 x 33 tiles (256 of them) on 513^2.  r is read from rin and the residual
+// after both sweeps written to rout.
+constexpr int kSweep2MaxN = 512;
+template <typename T>
+hipError_t launch_lsgs_sweep2(const Lev& L, int revmask, const T* xin, T* x, const T* rin, T* rout, hipStream_t s) {
+  if (L.n > kSweep2MaxN) return hipErrorInvalidValue;
+  if (L.n <= 256) {
+    const int nt = tiles_along(L.n + 1, 17);
+    hipLaunchKernelGGL((k_lsgs_tile<T, 17, 1024, 2>), dim3(round8(nt * nt)), dim3(1024), 0, s, L, nt, nt, revmask,
+                       xin, x, rin, rout, (double*)nullptr, 0);
+  } else {
+    const int nt = tiles_along(L.n + 1, 33);
+    hipLaunchKernelGGL((k_lsgs_tile<T, 33, 1024, 2>), dim3(round8(nt * nt)), dim3(1024), 0, s, L, nt, nt, revmask,
+                       xin, x, rin, rout, (double*)nullptr, 0);
+  }
+  return hipGetLastError();
+}
+template hipError_t launch_lsgs_sweep2<double>(const Lev&, int, const double*, double*, const double*, double*,
+                                               hipStream_t);
+template hipError_t launch_lsgs_sweep2<float>(const Lev&, int, const float*, float*, const float*, float*,
+                                              hipStream_t);
+int lsgs_sweep2_max_n() { return kSweep2MaxN; }
 
 hipError_t launch_lsgs_sweep_norm(const Lev& L, int reverse, const double* xin, double* x, const double* rin,
                                   double* rout, double* part, int norm_mode, int* nparts, hipStream_t s) {

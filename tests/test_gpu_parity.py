@@ -280,6 +280,33 @@ def test_dense_map_equals_tail(torch_cuda, monkeypatch, smoother, gamma, level):
         assert np.linalg.norm(xs[0] - xs[1]) <= bound * np.linalg.norm(xs[1]), precision
 
 
+@pytest.mark.parametrize("smoother,nu,gamma", [("lsgs", 2, 1), ("lsgs", 3, 1), ("slsgs", 1, 1), ("slsgs", 2, 2)])
+@pytest.mark.parametrize("level", [9, 10])
+def test_sweep_pairs_match_single_sweeps(torch_cuda, monkeypatch, smoother, nu, gamma, level):
+    # two sweeps per launch on the coarse levels up to 513^2 (halo 28,
+    # corrections of both sweeps in LDS; 17 x 17 and 33 x 33 tiles) against
+    # one launch per sweep (MGKKT_NO_SWEEP2=1)
+    torch = torch_cuda
+    mg = _mg()
+    alpha = 1e-3
+    yd = _dev(torch, workloads.desired_state(level, 4))
+    for precision, bound in (("fp64", 1e-13), ("fp32_ir", 1e-5)):
+        xs = []
+        for env in (None, "1"):
+            if env:
+                monkeypatch.setenv("MGKKT_NO_SWEEP2", env)
+            else:
+                monkeypatch.delenv("MGKKT_NO_SWEEP2", raising=False)
+            s = mg.Solver(level, alpha, smoother=smoother, gamma=gamma, nu1=nu, nu2=nu, precision=precision)
+            f = s.rhs(yd)
+            x = torch.zeros_like(f)
+            for _ in range(3):
+                s.cycle(f, x)
+            xs.append(_host(x))
+        monkeypatch.delenv("MGKKT_NO_SWEEP2", raising=False)
+        assert np.linalg.norm(xs[0] - xs[1]) <= bound * np.linalg.norm(xs[1]), precision
+
+
 @pytest.mark.parametrize("smoother,nu", [("lsgs", 2), ("slsgs", 1)])
 def test_sweep_norm_solve(torch_cuda, monkeypatch, smoother, nu):
     # FP64 solves take each iterate's norm from the residual the last sweep
