@@ -17,6 +17,7 @@
 #include <cmath>
 #include <cstring>
 #include <string>
+#include <unordered_map>
 #include <vector>
 
 #include "mg_internal.hpp"
@@ -192,6 +193,93 @@ inline int node_of(int n, int a, int b) {
   const int m = 2 * n - 1;
   if (a < 1 || b < 1 || a > m || b > m) return -1;
   return (b - 1) * m + (a - 1);
+}
+
+// Position of an unknown on the half-step lattice.  Unknowns are field-major:
+// v1, v2 (interior P2 nodes), p (P1 vertices), lambda1, lambda2, mu; a P2
+// node (a, b) has index (b - 1) m + (a - 1), a vertex (2I, 2J) index J (n + 1) + I.
+struct SGeo {
+  int n, m, nv, np;
+};
+__host__ __device__ inline int sbase(const SGeo& g, int f) {
+  return f == 0 ? 0 : f == 1 ? g.nv : f == 2 ? 2 * g.nv : f == 3 ? 2 * g.nv + g.np : f == 4 ? 3 * g.nv + g.np
+                                                                                          : 4 * g.nv + g.np;
+}
+__host__ __device__ inline bool sp1(int f) { return f == 2 || f == 5; }
+// field of unknown i and its lattice position
+__host__ __device__ inline int sfield(const SGeo& g, int i) {
+  return i < g.nv ? 0 : i < 2 * g.nv ? 1 : i < 2 * g.nv + g.np ? 2 : i < 3 * g.nv + g.np ? 3 : i < 4 * g.nv + g.np ? 4 : 5;
+}
+__host__ __device__ inline void spos(const SGeo& g, int i, int& hx, int& hy) {
+  const int f = sfield(g, i), a = i - sbase(g, f);
+  if (sp1(f)) {
+    const int J = a / (g.n + 1);
+    hx = 2 * (a - J * (g.n + 1));
+    hy = 2 * J;
+  } else {
+    const int b = a / g.m;
+    hx = a - b * g.m + 1;
+    hy = b + 1;
+  }
+}
+__host__ __device__ inline int sindex(const SGeo& g, int f, int hx, int hy) {
+  return sbase(g, f) + (sp1(f) ? (hy >> 1) * (g.n + 1) + (hx >> 1) : (hy - 1) * g.m + (hx - 1));
+}
+
+// A with its rows grouped into stencil classes: rows whose entries agree in
+// column field, lattice offset and value share one class (the mesh is
+// uniform, so a level has a few hundred classes for millions of rows).  An
+// entry packs the column field and its offset (dx, dy) from the row on the
+// half-step lattice; the column is recomputed from the row's position.
+struct ClassA {
+  std::vector<int> row_cls, ptr, ent;
+  std::vector<double> val;
+};
+constexpr int kEntOff = 16;  // offsets are stored + 16 in 8 bits
+__host__ __device__ inline int sent_col(const SGeo& g, int e, int hx, int hy) {
+  return sindex(g, e & 0xFF, hx + ((e >> 8) & 0xFF) - kEntOff, hy + ((e >> 16) & 0xFF) - kEntOff);
+}
+
+bool build_classes(const HCsr& A, const SGeo& g, ClassA& C, std::string* err) {
+  std::unordered_map<std::string, int> seen;
+  C.row_cls.assign(A.nrows, 0);
+  C.ptr.assign(1, 0);
+  std::string key;
+  std::vector<int> ents;
+  for (int i = 0; i < A.nrows; i++) {
+    int hx, hy;
+    spos(g, i, hx, hy);
+    ents.clear();
+    key.clear();
+    for (int k = A.rp[i]; k < A.rp[i + 1]; k++) {
+      const int c = A.col[k], fc = sfield(g, c);
+      int cx, cy;
+      spos(g, c, cx, cy);
+      const int dx = cx - hx, dy = cy - hy;
+      if (dx < -kEntOff || dx >= 256 - kEntOff || dy < -kEntOff || dy >= 256 - kEntOff) {
+        *err = "stokes: stencil offset out of range";
+        return false;
+      }
+      const int e = fc | ((dx + kEntOff) << 8) | ((dy + kEntOff) << 16);
+      if (sent_col(g, e, hx, hy) != c) {
+        *err = "stokes: stencil class does not reproduce a column";
+        return false;
+      }
+      ents.push_back(e);
+      key.append(reinterpret_cast<const char*>(&e), sizeof(e));
+      key.append(reinterpret_cast<const char*>(&A.val[k]), sizeof(double));
+    }
+    auto it = seen.find(key);
+    if (it == seen.end()) {
+      const int id = (int)C.ptr.size() - 1;
+      it = seen.emplace(key, id).first;
+      for (int k = A.rp[i]; k < A.rp[i + 1]; k++) C.val.push_back(A.val[k]);
+      C.ent.insert(C.ent.end(), ents.begin(), ents.end());
+      C.ptr.push_back((int)C.ent.size());
+    }
+    C.row_cls[i] = it->second;
+  }
+  return true;
 }
 
 struct Blocks {
@@ -497,7 +585,42 @@ __device__ inline void block_store(double v, double* out) {
   }
 }
 
-// Row kernels: 16 lanes per CSR row (16 rows per 256-thread block), each lane
+// Rows of a sparse operator: a CSR matrix (the transfers) or the stencil
+// classes of A.  row() gives the entry range and the row's lattice position
+// (classes) from which col_of() forms the column.
+template <typename T>
+struct CsrRows {
+  const int* rp;
+  const int* col;
+  const T* val;
+  __device__ void row(int i, int& kb, int& ke, int& pos) const {
+    kb = rp[i];
+    ke = rp[i + 1];
+    pos = 0;
+  }
+  __device__ int col_of(int k, int) const { return col[k]; }
+  __device__ T val_of(int k) const { return val[k]; }
+};
+template <typename T>
+struct ClassRows {
+  const int* cls;
+  const int* ptr;
+  const int* ent;
+  const T* val;
+  SGeo g;
+  __device__ void row(int i, int& kb, int& ke, int& pos) const {
+    const int c = cls[i];
+    kb = ptr[c];
+    ke = ptr[c + 1];
+    int hx, hy;
+    spos(g, i, hx, hy);
+    pos = hx | (hy << 16);
+  }
+  __device__ int col_of(int k, int pos) const { return sent_col(g, ent[k], pos & 0xFFFF, pos >> 16); }
+  __device__ T val_of(int k) const { return val[k]; }
+};
+
+// Row kernels: 16 lanes per row (16 rows per 256-thread block), each lane
 // taking every 16th entry, partial sums combined by shuffles.
 constexpr int kRL = 16;
 constexpr int kRows = kSNT / kRL;
@@ -511,18 +634,20 @@ __device__ inline T row_sum(T v) {
 
 // r = f - A x, with per-block partial sums of ||r||_2^2 (MODE 1) or
 // r^T L^-1 r (MODE 2); f == nullptr gives r = A x
-template <typename T, int MODE>
-__global__ __launch_bounds__(kSNT) void ks_resid(int n, const int* __restrict__ rp, const int* __restrict__ col,
-                                                 const T* __restrict__ val, const T* __restrict__ f,
-                                                 const T* __restrict__ x, T* __restrict__ r,
-                                                 const double* __restrict__ Ldi, double* __restrict__ part) {
+template <typename T, int MODE, typename AT>
+__global__ __launch_bounds__(kSNT) void ks_resid(int n, AT A, const T* __restrict__ f, const T* __restrict__ x,
+                                                 T* __restrict__ r, const double* __restrict__ Ldi,
+                                                 double* __restrict__ part) {
   const int ln = threadIdx.x % kRL;
   double s2 = 0.0;
   for (int i0 = blockIdx.x * kRows; i0 < n; i0 += gridDim.x * kRows) {  // uniform per block
     const int i = i0 + threadIdx.x / kRL;
     T s = 0;
-    if (i < n)
-      for (int k = rp[i] + ln; k < rp[i + 1]; k += kRL) s += val[k] * x[col[k]];
+    if (i < n) {
+      int kb, ke, pos;
+      A.row(i, kb, ke, pos);
+      for (int k = kb + ln; k < ke; k += kRL) s += A.val_of(k) * x[A.col_of(k, pos)];
+    }
     s = row_sum(s);
     if (i < n && ln == 0) {
       const T ri = f ? f[i] - s : s;
@@ -545,16 +670,18 @@ __global__ __launch_bounds__(kSNT) void ks_vnorm(int n, const double* __restrict
 }
 
 // y = A x (ADD 0) or y += A x (ADD 1); restriction variant also writes x_c = 0, r_c = f_c
-template <typename T, int ADD>
-__global__ __launch_bounds__(kSNT) void ks_spmv(int n, const int* __restrict__ rp, const int* __restrict__ col,
-                                                const T* __restrict__ val, const T* __restrict__ x, T* __restrict__ y,
+template <typename T, int ADD, typename AT>
+__global__ __launch_bounds__(kSNT) void ks_spmv(int n, AT A, const T* __restrict__ x, T* __restrict__ y,
                                                 T* __restrict__ zero_out, T* __restrict__ copy_out) {
   const int ln = threadIdx.x % kRL;
   for (int i0 = blockIdx.x * kRows; i0 < n; i0 += gridDim.x * kRows) {
     const int i = i0 + threadIdx.x / kRL;
     T s = 0;
-    if (i < n)
-      for (int k = rp[i] + ln; k < rp[i + 1]; k += kRL) s += val[k] * x[col[k]];
+    if (i < n) {
+      int kb, ke, pos;
+      A.row(i, kb, ke, pos);
+      for (int k = kb + ln; k < ke; k += kRL) s += A.val_of(k) * x[A.col_of(k, pos)];
+    }
     s = row_sum(s);
     if (i >= n || ln != 0) continue;
     if (ADD) {
@@ -568,16 +695,21 @@ __global__ __launch_bounds__(kSNT) void ks_spmv(int n, const int* __restrict__ r
 }
 
 // Alg. 1, first loop with x += p: p_i = tau (sum_j A_ij r_j / L_jj) / L_ii
-template <typename T>
-__global__ __launch_bounds__(kSNT) void ks_ne_p(int n, const int* __restrict__ rp, const int* __restrict__ col,
-                                                const T* __restrict__ val, const T* __restrict__ Linv, T tau,
+template <typename T, typename AT>
+__global__ __launch_bounds__(kSNT) void ks_ne_p(int n, AT A, const T* __restrict__ Linv, T tau,
                                                 const T* __restrict__ r, T* __restrict__ x, T* __restrict__ p) {
   const int ln = threadIdx.x % kRL;
   for (int i0 = blockIdx.x * kRows; i0 < n; i0 += gridDim.x * kRows) {
     const int i = i0 + threadIdx.x / kRL;
     T q = 0;
-    if (i < n)
-      for (int k = rp[i] + ln; k < rp[i + 1]; k += kRL) q += val[k] * Linv[col[k]] * r[col[k]];
+    if (i < n) {
+      int kb, ke, pos;
+      A.row(i, kb, ke, pos);
+      for (int k = kb + ln; k < ke; k += kRL) {
+        const int c = A.col_of(k, pos);
+        q += A.val_of(k) * Linv[c] * r[c];
+      }
+    }
     q = row_sum(q);
     if (i >= n || ln != 0) continue;
     const T pi = tau * q * Linv[i];
@@ -587,15 +719,17 @@ __global__ __launch_bounds__(kSNT) void ks_ne_p(int n, const int* __restrict__ r
 }
 
 // Alg. 1, second loop: r -= A p (A symmetric: row i holds the column)
-template <typename T>
-__global__ __launch_bounds__(kSNT) void ks_ne_r(int n, const int* __restrict__ rp, const int* __restrict__ col,
-                                                const T* __restrict__ val, const T* __restrict__ p, T* __restrict__ r) {
+template <typename T, typename AT>
+__global__ __launch_bounds__(kSNT) void ks_ne_r(int n, AT A, const T* __restrict__ p, T* __restrict__ r) {
   const int ln = threadIdx.x % kRL;
   for (int i0 = blockIdx.x * kRows; i0 < n; i0 += gridDim.x * kRows) {
     const int i = i0 + threadIdx.x / kRL;
     T s = 0;
-    if (i < n)
-      for (int k = rp[i] + ln; k < rp[i + 1]; k += kRL) s += val[k] * p[col[k]];
+    if (i < n) {
+      int kb, ke, pos;
+      A.row(i, kb, ke, pos);
+      for (int k = kb + ln; k < ke; k += kRL) s += A.val_of(k) * p[A.col_of(k, pos)];
+    }
     s = row_sum(s);
     if (i < n && ln == 0) r[i] -= s;
   }
@@ -615,29 +749,32 @@ __device__ inline T half_sum(T v) {
   return v;
 }
 
-template <typename T>
-__global__ __launch_bounds__(kSNT) void ks_lsgs(int g0, int ng, const int2* __restrict__ grp,
-                                                const int* __restrict__ rp, const int* __restrict__ col,
-                                                const T* __restrict__ val, const T* __restrict__ Linv,
-                                                const T* __restrict__ Ninv, T* __restrict__ x, T* __restrict__ r) {
+template <typename T, typename AT>
+__global__ __launch_bounds__(kSNT) void ks_lsgs(int g0, int ng, const int2* __restrict__ grp, AT A,
+                                                const T* __restrict__ Linv, const T* __restrict__ Ninv,
+                                                T* __restrict__ x, T* __restrict__ r) {
   const int g = blockIdx.x * (kSNT / 64) + threadIdx.x / 64;
   if (g >= ng) return;  // uniform per wave
   const int lane = threadIdx.x % 64, half = lane / kHalf, ln = lane % kHalf;
   const int2 u = grp[g0 + g];
   const int row = half ? u.y : u.x;
-  const int kb = rp[row], ke = rp[row + 1];
+  int kb, ke, pos;
+  A.row(row, kb, ke, pos);
   // the first two entries of each lane (rows of this discretisation have at
   // most 2 kHalf entries) are gathered in one round and their column indices
   // and values kept in registers; longer rows continue in the loops below
   // (same summation order)
   const int k0 = kb + ln, k1 = k0 + kHalf;
   const bool h0 = k0 < ke, h1 = k1 < ke;
-  const int c0 = h0 ? col[k0] : 0, c1 = h1 ? col[k1] : 0;
-  const T v0 = h0 ? val[k0] : (T)0, v1 = h1 ? val[k1] : (T)0;
+  const int c0 = h0 ? A.col_of(k0, pos) : 0, c1 = h1 ? A.col_of(k1, pos) : 0;
+  const T v0 = h0 ? A.val_of(k0) : (T)0, v1 = h1 ? A.val_of(k1) : (T)0;
   T q = 0;
   if (h0) q += v0 * Linv[c0] * r[c0];
   if (h1) q += v1 * Linv[c1] * r[c1];
-  for (int k = k1 + kHalf; k < ke; k += kHalf) q += val[k] * Linv[col[k]] * r[col[k]];
+  for (int k = k1 + kHalf; k < ke; k += kHalf) {
+    const int c = A.col_of(k, pos);
+    q += A.val_of(k) * Linv[c] * r[c];
+  }
   q = half_sum(q);
   const T pv = q * Ninv[row];
   if (ln == 0) x[row] += pv;
@@ -650,13 +787,19 @@ __global__ __launch_bounds__(kSNT) void ks_lsgs(int g0, int ng, const int2* __re
   if (half == 0) {
     if (h0) r[c0] = fresh(c0) - v0 * pv;
     if (h1) r[c1] = fresh(c1) - v1 * pv;
-    for (int k = k1 + kHalf; k < ke; k += kHalf) r[col[k]] = fresh(col[k]) - val[k] * pv;
+    for (int k = k1 + kHalf; k < ke; k += kHalf) {
+      const int c = A.col_of(k, pos);
+      r[c] = fresh(c) - A.val_of(k) * pv;
+    }
   }
   __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
   if (half == 1) {
     if (h0) r[c0] = fresh(c0) - v0 * pv;
     if (h1) r[c1] = fresh(c1) - v1 * pv;
-    for (int k = k1 + kHalf; k < ke; k += kHalf) r[col[k]] = fresh(col[k]) - val[k] * pv;
+    for (int k = k1 + kHalf; k < ke; k += kHalf) {
+      const int c = A.col_of(k, pos);
+      r[c] = fresh(c) - A.val_of(k) * pv;
+    }
   }
 }
 
@@ -666,12 +809,11 @@ __global__ __launch_bounds__(kSNT) void ks_lsgs(int g0, int ng, const int2* __re
 // keeps column c of the factors in registers and entry c of the vector; the
 // substitutions reduce over the wave; the patch rows are then subtracted from
 // r one after the other (rows of one patch share entries of r).
-template <typename T>
+template <typename T, typename AT>
 __global__ __launch_bounds__(kSNT) void ks_vanka(int p0, int npatch, const int* __restrict__ order,
                                                  const int* __restrict__ dptr, const int* __restrict__ dof,
                                                  const long long* __restrict__ luptr, const double* __restrict__ lu,
-                                                 const int* __restrict__ perm, const int* __restrict__ rp,
-                                                 const int* __restrict__ col, const T* __restrict__ val, double tau,
+                                                 const int* __restrict__ perm, AT A, double tau,
                                                  T* __restrict__ x, T* __restrict__ r) {
   const int t = blockIdx.x * (kSNT / 64) + threadIdx.x / 64;
   if (t >= npatch) return;  // uniform per wave
@@ -707,7 +849,9 @@ __global__ __launch_bounds__(kSNT) void ks_vanka(int p0, int npatch, const int* 
   for (int u = 0; u < m; u++) {
     const T d = __shfl(du, u, 64);
     const int i = dof[b + u];
-    for (int k = rp[i] + c; k < rp[i + 1]; k += 64) r[col[k]] -= val[k] * d;
+    int kb, ke, pos;
+    A.row(i, kb, ke, pos);
+    for (int k = kb + c; k < ke; k += 64) r[A.col_of(k, pos)] -= A.val_of(k) * d;
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
   }
 }
@@ -823,9 +967,13 @@ hipError_t upload(T** d, const T* h, size_t n) {
 
 struct StokesLevel {
   int l = 0, n = 0, nv = 0, np = 0, ndof = 0;
-  int *A_rp = nullptr, *A_col = nullptr;
+  SGeo geo{};
+  // A by stencil classes: class of each row, entry range of each class,
+  // packed (field, offset) entries and their values
+  int *A_cls = nullptr, *A_ptr = nullptr, *A_ent = nullptr;
   double* A_val = nullptr;
   float* A_val32 = nullptr;
+  int nclass = 0;
   double *Ld = nullptr, *Linv = nullptr, *Ninv = nullptr;
   float *Linv32 = nullptr, *Ninv32 = nullptr;
   // prolongation from level l-1 and restriction to it (its transpose)
@@ -903,9 +1051,14 @@ hipError_t build_level(Stokes* S, int l, bool finest, std::string* err) {
     return hipErrorInvalidValue;
   }
   const HCsr A = assemble_kkt(n, S->alpha, B);
-  SCHK(up(S, &L.A_rp, A.rp));
-  SCHK(up(S, &L.A_col, A.col));
-  SCHK(up(S, &L.A_val, A.val));
+  L.geo = SGeo{n, m, L.nv, L.np};
+  ClassA CA;
+  if (!build_classes(A, L.geo, CA, err)) return hipErrorInvalidValue;
+  L.nclass = (int)CA.ptr.size() - 1;
+  SCHK(up(S, &L.A_cls, CA.row_cls));
+  SCHK(up(S, &L.A_ptr, CA.ptr));
+  SCHK(up(S, &L.A_ent, CA.ent));
+  SCHK(up(S, &L.A_val, CA.val));
   // L = (W^, W^, P^, W^/alpha, W^/alpha, P^/alpha), W^ = diag(M + alpha^1/2 K), P^ = alpha diag(D W^-1 D^T)
   std::vector<double> Ld(L.ndof), W(L.nv);
   for (int a = 0; a < L.nv; a++) W[a] = entry(B.Ms, a, a) + std::sqrt(S->alpha) * entry(B.Ks, a, a);
@@ -935,7 +1088,7 @@ hipError_t build_level(Stokes* S, int l, bool finest, std::string* err) {
   L.wsum = 0.0;
   for (double v : B.w) L.wsum += v;
   if (S->fp32) {
-    SCHK(up(S, &L.A_val32, to32(A.val)));
+    SCHK(up(S, &L.A_val32, to32(CA.val)));
     SCHK(up(S, &L.Linv32, to32(Linv)));
     SCHK(up(S, &L.Ninv32, to32(Ninv)));
   }
@@ -1040,22 +1193,36 @@ struct SV<float> {
   static const float* Ninv(StokesLevel& L) { return L.Ninv32; }
 };
 
+// A of level L by stencil classes; the transfers P (from level l-1) and R (to it) as CSR
+template <typename T>
+ClassRows<T> a_rows(StokesLevel& L) {
+  return ClassRows<T>{L.A_cls, L.A_ptr, L.A_ent, SV<T>::A(L), L.geo};
+}
+template <typename T>
+CsrRows<T> p_rows(StokesLevel& L) {
+  return CsrRows<T>{L.P_rp, L.P_col, SV<T>::P(L)};
+}
+template <typename T>
+CsrRows<T> r_rows(StokesLevel& L) {
+  return CsrRows<T>{L.R_rp, L.R_col, SV<T>::R(L)};
+}
+
 template <typename T>
 hipError_t s_resid(StokesLevel& L, const T* f, const T* x, T* r, hipStream_t s) {
-  hipLaunchKernelGGL((ks_resid<T, 0>), dim3(row_blocks(L.ndof)), dim3(kSNT), 0, s, L.ndof, L.A_rp, L.A_col,
-                     SV<T>::A(L), f, x, r, (const double*)nullptr, (double*)nullptr);
+  hipLaunchKernelGGL((ks_resid<T, 0, ClassRows<T>>), dim3(row_blocks(L.ndof)), dim3(kSNT), 0, s, L.ndof, a_rows<T>(L),
+                     f, x, r, (const double*)nullptr, (double*)nullptr);
   return hipGetLastError();
 }
 
 template <typename T>
 hipError_t s_smooth(Stokes* S, StokesLevel& L, T* x, T* r, int steps, hipStream_t s) {
-  const T* A = SV<T>::A(L);
+  const ClassRows<T> A = a_rows<T>(L);
   for (int it = 0; it < steps; it++) {
     switch (S->smoother) {
       case MG_NE:
-        hipLaunchKernelGGL((ks_ne_p<T>), dim3(row_blocks(L.ndof)), dim3(kSNT), 0, s, L.ndof, L.A_rp, L.A_col, A,
+        hipLaunchKernelGGL((ks_ne_p<T, ClassRows<T>>), dim3(row_blocks(L.ndof)), dim3(kSNT), 0, s, L.ndof, A,
                            SV<T>::Linv(L), (T)S->tau, (const T*)r, x, SV<T>::p(L));
-        hipLaunchKernelGGL((ks_ne_r<T>), dim3(row_blocks(L.ndof)), dim3(kSNT), 0, s, L.ndof, L.A_rp, L.A_col, A,
+        hipLaunchKernelGGL((ks_ne_r<T, ClassRows<T>>), dim3(row_blocks(L.ndof)), dim3(kSNT), 0, s, L.ndof, A,
                            (const T*)SV<T>::p(L), r);
         break;
       case MG_LSGS:
@@ -1066,16 +1233,16 @@ hipError_t s_smooth(Stokes* S, StokesLevel& L, T* x, T* r, int steps, hipStream_
           for (int k = 0; k < nph; k++) {
             const int ph = sw == 0 ? k : nph - 1 - k;
             const int g0 = L.gph[ph], ng = L.gph[ph + 1] - g0;
-            hipLaunchKernelGGL((ks_lsgs<T>), dim3(blocks_for(ng, kSNT / 64)), dim3(kSNT), 0, s, g0, ng,
-                               (const int2*)L.groups, L.A_rp, L.A_col, A, SV<T>::Linv(L), SV<T>::Ninv(L), x, r);
+            hipLaunchKernelGGL((ks_lsgs<T, ClassRows<T>>), dim3(blocks_for(ng, kSNT / 64)), dim3(kSNT), 0, s, g0, ng,
+                               (const int2*)L.groups, A, SV<T>::Linv(L), SV<T>::Ninv(L), x, r);
           }
         break;
       }
       case MG_VANKA:
         for (int ph = 0; ph + 1 < (int)L.vph.size(); ph++) {
           const int p0 = L.vph[ph], npch = L.vph[ph + 1] - p0;
-          hipLaunchKernelGGL((ks_vanka<T>), dim3(blocks_for(npch, kSNT / 64)), dim3(kSNT), 0, s, p0, npch, L.v_order,
-                             L.v_dptr, L.v_dof, L.v_luptr, L.v_lu, L.v_piv, L.A_rp, L.A_col, A, S->tau, x, r);
+          hipLaunchKernelGGL((ks_vanka<T, ClassRows<T>>), dim3(blocks_for(npch, kSNT / 64)), dim3(kSNT), 0, s, p0,
+                             npch, L.v_order, L.v_dptr, L.v_dof, L.v_luptr, L.v_lu, L.v_piv, A, S->tau, x, r);
         }
         break;
     }
@@ -1113,14 +1280,13 @@ hipError_t s_cycle(Stokes* S, int l, const T* f, T* x, T* r, bool current, hipSt
   if (!current) SCHK(s_resid<T>(L, f, x, r, s));
   SCHK(s_smooth<T>(S, L, x, r, S->nu1, s));
   const bool to_k0 = (l - 1 == S->k0);
-  hipLaunchKernelGGL((ks_spmv<T, 0>), dim3(row_blocks(C.ndof)), dim3(kSNT), 0, s, C.ndof, L.R_rp, L.R_col,
-                     SV<T>::R(L), (const T*)r, SV<T>::f(C), to_k0 ? (T*)nullptr : SV<T>::x(C),
-                     to_k0 ? (T*)nullptr : SV<T>::r(C));
+  hipLaunchKernelGGL((ks_spmv<T, 0, CsrRows<T>>), dim3(row_blocks(C.ndof)), dim3(kSNT), 0, s, C.ndof, r_rows<T>(L),
+                     (const T*)r, SV<T>::f(C), to_k0 ? (T*)nullptr : SV<T>::x(C), to_k0 ? (T*)nullptr : SV<T>::r(C));
   SCHK(hipGetLastError());
   for (int g = 0; g < S->gamma; g++)
     SCHK(s_cycle<T>(S, l - 1, SV<T>::f(C), SV<T>::x(C), SV<T>::r(C), g == 0, s));
-  hipLaunchKernelGGL((ks_spmv<T, 1>), dim3(row_blocks(L.ndof)), dim3(kSNT), 0, s, L.ndof, L.P_rp, L.P_col,
-                     SV<T>::P(L), (const T*)SV<T>::x(C), x, (T*)nullptr, (T*)nullptr);
+  hipLaunchKernelGGL((ks_spmv<T, 1, CsrRows<T>>), dim3(row_blocks(L.ndof)), dim3(kSNT), 0, s, L.ndof, p_rows<T>(L),
+                     (const T*)SV<T>::x(C), x, (T*)nullptr, (T*)nullptr);
   SCHK(hipGetLastError());
   SCHK(s_resid<T>(L, f, x, r, s));
   return s_smooth<T>(S, L, x, r, S->nu2, s);
@@ -1191,8 +1357,8 @@ hipError_t stokes_rhs(Stokes* S, const double* vd, double* f, hipStream_t s) {
 
 hipError_t stokes_apply(Stokes* S, int l, const double* x, double* y, hipStream_t s) {
   StokesLevel& L = S->L(l);
-  hipLaunchKernelGGL((ks_resid<double, 0>), dim3(row_blocks(L.ndof)), dim3(kSNT), 0, s, L.ndof, L.A_rp, L.A_col,
-                     (const double*)L.A_val, (const double*)nullptr, x, y, (const double*)nullptr, (double*)nullptr);
+  hipLaunchKernelGGL((ks_resid<double, 0, ClassRows<double>>), dim3(row_blocks(L.ndof)), dim3(kSNT), 0, s, L.ndof,
+                     a_rows<double>(L), (const double*)nullptr, x, y, (const double*)nullptr, (double*)nullptr);
   return hipGetLastError();
 }
 
@@ -1201,15 +1367,16 @@ hipError_t stokes_residual(Stokes* S, int l, const double* f, const double* x, d
   StokesLevel& L = S->L(l);
   const int nb = row_blocks(L.ndof);
   if (nparts) *nparts = nb;
+  const ClassRows<double> A = a_rows<double>(L);
   if (!part)
-    hipLaunchKernelGGL((ks_resid<double, 0>), dim3(nb), dim3(kSNT), 0, s, L.ndof, L.A_rp, L.A_col,
-                       (const double*)L.A_val, f, x, r, (const double*)L.Linv, part);
+    hipLaunchKernelGGL((ks_resid<double, 0, ClassRows<double>>), dim3(nb), dim3(kSNT), 0, s, L.ndof, A, f, x, r,
+                       (const double*)L.Linv, part);
   else if (norm_mode == 2)
-    hipLaunchKernelGGL((ks_resid<double, 2>), dim3(nb), dim3(kSNT), 0, s, L.ndof, L.A_rp, L.A_col,
-                       (const double*)L.A_val, f, x, r, (const double*)L.Linv, part);
+    hipLaunchKernelGGL((ks_resid<double, 2, ClassRows<double>>), dim3(nb), dim3(kSNT), 0, s, L.ndof, A, f, x, r,
+                       (const double*)L.Linv, part);
   else
-    hipLaunchKernelGGL((ks_resid<double, 1>), dim3(nb), dim3(kSNT), 0, s, L.ndof, L.A_rp, L.A_col,
-                       (const double*)L.A_val, f, x, r, (const double*)L.Linv, part);
+    hipLaunchKernelGGL((ks_resid<double, 1, ClassRows<double>>), dim3(nb), dim3(kSNT), 0, s, L.ndof, A, f, x, r,
+                       (const double*)L.Linv, part);
   return hipGetLastError();
 }
 
@@ -1231,15 +1398,15 @@ hipError_t stokes_smooth(Stokes* S, int l, double* x, double* r, int steps, hipS
 hipError_t stokes_restrict(Stokes* S, int l, const double* r, double* fc, hipStream_t s) {
   StokesLevel& L = S->L(l);
   StokesLevel& C = S->L(l - 1);
-  hipLaunchKernelGGL((ks_spmv<double, 0>), dim3(row_blocks(C.ndof)), dim3(kSNT), 0, s, C.ndof, L.R_rp, L.R_col,
-                     (const double*)L.R_val, r, fc, (double*)nullptr, (double*)nullptr);
+  hipLaunchKernelGGL((ks_spmv<double, 0, CsrRows<double>>), dim3(row_blocks(C.ndof)), dim3(kSNT), 0, s, C.ndof,
+                     r_rows<double>(L), r, fc, (double*)nullptr, (double*)nullptr);
   return hipGetLastError();
 }
 
 hipError_t stokes_prolong_add(Stokes* S, int l, const double* xc, double* x, hipStream_t s) {
   StokesLevel& L = S->L(l);
-  hipLaunchKernelGGL((ks_spmv<double, 1>), dim3(row_blocks(L.ndof)), dim3(kSNT), 0, s, L.ndof, L.P_rp, L.P_col,
-                     (const double*)L.P_val, xc, x, (double*)nullptr, (double*)nullptr);
+  hipLaunchKernelGGL((ks_spmv<double, 1, CsrRows<double>>), dim3(row_blocks(L.ndof)), dim3(kSNT), 0, s, L.ndof,
+                     p_rows<double>(L), xc, x, (double*)nullptr, (double*)nullptr);
   return hipGetLastError();
 }
 
