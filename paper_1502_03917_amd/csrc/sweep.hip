@@ -59,11 +59,25 @@ __device__ inline void bstore(__amdgpu_buffer_rsrc_t r, unsigned off, float v) {
   __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, off, 0, 0);
 }
 
-template <int TW, int H = kHalo>
+// Row pitch of the LDS region beyond its RMAX + 2 cells (a guard cell each
+// side).  A 16-byte (FP64) or 8-byte (FP32) access is served a few lanes at a
+// time, and the lanes of a phase step through a row at a stride of 7 cells
+// and then on into the next row; the padding is chosen, per tile shape, so
+// that the cells of the lanes served together fall into distinct banks as
+// often as possible (a bank-conflict model of the phases' access pattern, for
+// 32 and 64 four-byte banks).
+constexpr int pitch_pad(int TW, int H, int cell) {
+  return cell == 16 ? (H == kHalo ? (TW == 65 ? 7 : TW == 56 ? 9 : TW == 48 ? 10 : TW == 16 ? 7 : 1)
+                                  : (TW == 17 ? 13 : TW == 33 ? 4 : 1))
+                    : (H == kHalo ? (TW == 46 ? 3 : TW == 48 ? 12 : TW == 16 ? 8 : 1)
+                                  : (TW == 17 ? 15 : TW == 33 ? 13 : 1));
+}
+
+template <int TW, int H = kHalo, int CELL = 16>
 struct TileGeom {
-  static constexpr int RMAX = TW + 2 * H;  // widest / tallest region (halo H)
-  static constexpr int RP = RMAX + 3;          // pitch: one guard cell each side, one pad cell
-  static constexpr int RN = RP * (RMAX + 2);   // region cells with guard rows
+  static constexpr int RMAX = TW + 2 * H;                           // widest / tallest region (halo H)
+  static constexpr int RP = RMAX + 2 + pitch_pad(TW, H, CELL);      // pitch: a guard cell each side, padding
+  static constexpr int RN = RP * (RMAX + 2);                        // region cells with guard rows
 };
 
 // the two fields of one vertex side by side (one 16-byte LDS access in FP64)
@@ -97,7 +111,7 @@ __device__ __forceinline__ void lsgs_tile_body(const Lev& L, int ntx, int nty, i
                                                const T* __restrict__ rin, T* __restrict__ rout,
                                                double* __restrict__ part = nullptr, int norm_mode = 0) {
   constexpr int H = kHalo * NSW;
-  using G = TileGeom<TW, H>;
+  using G = TileGeom<TW, H, 2 * sizeof(T)>;
   using T2 = typename Pair<T>::type;
   constexpr int NR = (G::RMAX * G::RMAX + NT - 1) / NT;  // region cells per thread
   constexpr int NX = (TW * TW + NT - 1) / NT;            // owned cells per thread
