@@ -241,16 +241,21 @@ __host__ __device__ inline int sent_col(const SGeo& g, int e, int hx, int hy) {
 }
 
 bool build_classes(const HCsr& A, const SGeo& g, ClassA& C, std::string* err) {
-  std::unordered_map<std::string, int> seen;
+  // rows are looked up by a 64-bit hash of their entries and compared in
+  // full with the class the hash points to
+  std::unordered_map<unsigned long long, std::vector<int>> seen;
   C.row_cls.assign(A.nrows, 0);
   C.ptr.assign(1, 0);
-  std::string key;
   std::vector<int> ents;
   for (int i = 0; i < A.nrows; i++) {
     int hx, hy;
     spos(g, i, hx, hy);
     ents.clear();
-    key.clear();
+    unsigned long long h = 0x243F6A8885A308D3ull;  // multiply-xorshift hash of the entries and value bits
+    auto mix = [&](unsigned long long v) {
+      h = (h ^ v) * 0x9E3779B97F4A7C15ull;
+      h ^= h >> 29;
+    };
     for (int k = A.rp[i]; k < A.rp[i + 1]; k++) {
       const int c = A.col[k], fc = sfield(g, c);
       int cx, cy;
@@ -266,18 +271,32 @@ bool build_classes(const HCsr& A, const SGeo& g, ClassA& C, std::string* err) {
         return false;
       }
       ents.push_back(e);
-      key.append(reinterpret_cast<const char*>(&e), sizeof(e));
-      key.append(reinterpret_cast<const char*>(&A.val[k]), sizeof(double));
+      unsigned long long vb;
+      std::memcpy(&vb, &A.val[k], sizeof(vb));
+      mix((unsigned long long)(unsigned)e);
+      mix(vb);
     }
-    auto it = seen.find(key);
-    if (it == seen.end()) {
-      const int id = (int)C.ptr.size() - 1;
-      it = seen.emplace(key, id).first;
-      for (int k = A.rp[i]; k < A.rp[i + 1]; k++) C.val.push_back(A.val[k]);
+    const int len = A.rp[i + 1] - A.rp[i];
+    int id = -1;
+    std::vector<int>& cand = seen[h];
+    for (int c : cand) {
+      if (C.ptr[c + 1] - C.ptr[c] != len) continue;
+      bool same = true;
+      for (int q = 0; q < len && same; q++)
+        same = C.ent[C.ptr[c] + q] == ents[q] && C.val[C.ptr[c] + q] == A.val[A.rp[i] + q];
+      if (same) {
+        id = c;
+        break;
+      }
+    }
+    if (id < 0) {
+      id = (int)C.ptr.size() - 1;
+      cand.push_back(id);
       C.ent.insert(C.ent.end(), ents.begin(), ents.end());
+      C.val.insert(C.val.end(), A.val.begin() + A.rp[i], A.val.begin() + A.rp[i + 1]);
       C.ptr.push_back((int)C.ent.size());
     }
-    C.row_cls[i] = it->second;
+    C.row_cls[i] = id;
   }
   return true;
 }
