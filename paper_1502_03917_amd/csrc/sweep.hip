@@ -431,7 +431,9 @@ inline int tiles_along(int npts, int TW) { return (npts + TW - 1) / TW; }
 //         where 46 x 46 tiles (2025 tiles, 4 rounds of 512) take 55.9 against 58.8.
 // Levels up to 257^2 vertices (FP64) or 513^2 (FP32) run one round of small
 // tiles and are latency-bound: 16 x 16 tiles with 256 threads take about
-// 10-15 us per sweep there instead of about 25 us.  (A persistent grid that
+// 10-15 us per sweep there instead of about 25 us (inside a cycle, the coarse
+// levels up to 513^2 run two sweeps per launch instead, launch_lsgs_sweep2).
+// (A persistent grid that
 // keeps a workgroup per CU and prefetches the next tile's region measured
 // slower at every size: 123 against 110 us at 2049^2 with 44 x 44 tiles and
 // 768 threads, since its extra registers cap the threads per CU.)
