@@ -15,6 +15,7 @@ import csv
 import hashlib
 import json
 import os
+import re
 import sys
 import time
 
@@ -76,6 +77,10 @@ def sweep_source_hash() -> str:
         elif rel.endswith("build.py"):
             text = text[text.index("FLAGS = ["):]
             text = text[: text.index("]") + 1]
+        if not rel.endswith("build.py"):
+            # comments and blank lines do not change the kernels
+            lines = (re.sub(r"//.*$", "", ln).rstrip() for ln in text.splitlines())
+            text = "\n".join(ln for ln in lines if ln)
         h.update(text.encode())
     return h.hexdigest()[:16]
 
