@@ -393,7 +393,7 @@ def main() -> int:
         return 0
     yd = torch.from_numpy(workloads.desired_state(args.level, args.seed)).cuda()
 
-    def run(smoother, precision, alpha, steps, warmup, timing=False):
+    def run(smoother, precision, alpha, steps, warmup, timing=False, keep=False):
         s = mg.Solver(args.level, alpha, smoother=smoother, precision=precision)
         inner = s.opts().inner_cycles
         x = torch.zeros(s.vec_len(), dtype=torch.float64, device="cuda")
@@ -422,6 +422,8 @@ def main() -> int:
             s.timing_enable(False)
             out["sweep_ms"] = ms / max(n, 1)
             out["sweeps_timed"] = n
+        if keep:
+            out["x"] = x.clone()
         s.close()
         return out
 
@@ -486,13 +488,20 @@ def main() -> int:
                              "finest_sweep_ms": ir_sweep["sweep_ms"], "finest_sweep_GBps": ach,
                              "finest_sweep_frac_of_8TBps": ach / HBM_PEAK_GBS}
     if args.variants:
+        # NE and LSGS, FP64 and FP32 refinement, alpha 1e-8 / 1e-4 / 1 on the same
+        # workload; the FP32-refinement iterate is compared with the FP64 one
+        # (whose cycles match the oracle's at this size)
         var = {}
         for sm in ("ne", "lsgs"):
-            for pr in ("fp64", "fp32_ir"):
-                for al in (1e-8, 1e-4, 1.0):
-                    key = f"{sm}/{pr}/alpha={al:g}"
-                    log(f"bench: variant {key}")
-                    var[key] = run(sm, pr, al, 2, 1)
+            for al in (1e-8, 1e-4, 1.0):
+                log(f"bench: variants {sm}, alpha {al:g}")
+                r64 = run(sm, "fp64", al, 2, 1, keep=True)
+                r32 = run(sm, "fp32_ir", al, 2, 1, keep=True)
+                x64, x32 = r64.pop("x"), r32.pop("x")
+                r32["rel_diff_vs_fp64"] = float(torch.linalg.vector_norm(x32 - x64) / torch.linalg.vector_norm(x64))
+                r32["speedup_time_to_tol_vs_fp64"] = r64["ms_per_solve"] / r32["ms_per_solve"]
+                var[f"{sm}/fp64/alpha={al:g}"] = r64
+                var[f"{sm}/fp32_ir/alpha={al:g}"] = r32
         result["variants"] = var
     if not args.no_batch:
         log("bench: batched solve of 64 instances (fp32_ir)")
