@@ -268,11 +268,13 @@ def batch_measure(steps: int, tol: float):
             cyc_total += sum(cyc)
         torch.cuda.synchronize()
         dt = (time.perf_counter() - t0) / steps
+        tiles = {str(l): b.sweep_tile(l) for l in sorted(set(levels))}
         b.close()
-        return dt, cyc_total / steps, cyc, rel, st
+        return dt, cyc_total / steps, cyc, rel, st, tiles
 
-    dt, cyc_sum, cyc, rel, st = timed(True)
-    dt_eager, _, _, _, _ = timed(False)
+    dt, cyc_sum, cyc, rel, st, tiles = timed(True)
+    dt_eager, _, _, _, _, _ = timed(False)
+    out["sweep_tiles_autotuned"] = tiles
     nbytes = 0.0
     for l, c in zip(levels, cyc):
         V = ((1 << l) + 1) ** 2

@@ -233,6 +233,13 @@ void mg_batch_destroy(mg_batch *batch);
 int mg_batch_count(const mg_batch *batch);
 /* unknowns of instance i, 2 (2^levels[i]+1)^2 (0 if out of range) */
 size_t mg_batch_vec_len(const mg_batch *batch, int i);
+/* Tile edge of the batched LSGS sweep on `level` (vertices 2^level+1 per
+ * side).  For an LSGS or sLSGS batch, mg_batch_setup times every candidate
+ * tile shape of that level on the batch's own buffers and keeps the fastest
+ * (an addition to the method: the tile shape changes no result beyond
+ * rounding); MGKKT_NO_AUTOTUNE=1 keeps the default shape.  0 for NULL or a
+ * level that no instance reaches above the coarse tail. */
+int mg_batch_sweep_tile(const mg_batch *batch, int level);
 /* f_i = (M y_D,i; 0) for every instance: yd and f are HOST arrays of count
  * DEVICE pointers (instance i: (2^l+1)^2 and 2 (2^l+1)^2 entries). */
 int mg_batch_rhs(mg_batch *batch, const double *const *yd, double *const *f, void *stream);

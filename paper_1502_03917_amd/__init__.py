@@ -100,6 +100,8 @@ def lib():
     L.mg_batch_count.restype = ip
     L.mg_batch_vec_len.argtypes = [vp, ip]
     L.mg_batch_vec_len.restype = sz
+    L.mg_batch_sweep_tile.argtypes = [vp, ip]
+    L.mg_batch_sweep_tile.restype = ip
     L.mg_batch_rhs.argtypes = [vp, ctypes.POINTER(vp), ctypes.POINTER(vp), vp]
     L.mg_batch_rhs.restype = ip
     L.mg_batch_solve.argtypes = [vp, ctypes.POINTER(vp), ctypes.POINTER(vp), dp, ctypes.POINTER(ip),
@@ -387,6 +389,10 @@ class Batch:
 
     def vec_len(self, i: int) -> int:
         return lib().mg_batch_vec_len(self._h, i)
+
+    def sweep_tile(self, level: int) -> int:
+        """Tile edge the setup's autotuner picked for the batched sweep on `level`."""
+        return lib().mg_batch_sweep_tile(self._h, level)
 
     def _ptrs(self, ts, lens, name):
         import torch

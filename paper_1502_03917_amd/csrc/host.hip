@@ -1351,6 +1351,7 @@ struct mg_batch {
   double** d_normptr = nullptr;
   struct Group {
     int L = 0;
+    int shape = 0;  // tile shape of the batched sweep on this level (picked at setup)
     std::vector<int> members;
     mgk::BInst<double>* d64 = nullptr;
     mgk::BInst<float>* d32 = nullptr;
@@ -1499,12 +1500,12 @@ int batch_smooth(mg_batch* b, const mg_batch::Group& g, int steps, int& sel, hip
         BCHK(b, mgk::launch_b_ne<T>(d, cnt, n, sel, s));
         break;
       case MG_LSGS:
-        BCHK(b, mgk::launch_b_lsgs_sweep<T>(d, cnt, n, 0, sel, s));
+        BCHK(b, mgk::launch_b_lsgs_sweep<T>(d, cnt, n, 0, sel, s, g.shape));
         sel ^= 1;
         break;
       case MG_SLSGS:
-        BCHK(b, mgk::launch_b_lsgs_sweep<T>(d, cnt, n, 0, sel, s));
-        BCHK(b, mgk::launch_b_lsgs_sweep<T>(d, cnt, n, 1, sel ^ 1, s));
+        BCHK(b, mgk::launch_b_lsgs_sweep<T>(d, cnt, n, 0, sel, s, g.shape));
+        BCHK(b, mgk::launch_b_lsgs_sweep<T>(d, cnt, n, 1, sel ^ 1, s, g.shape));
         break;
       case MG_CGS:
         for (int col = 0; col < 7; col++) BCHK(b, mgk::launch_b_cgs_phase<T>(d, cnt, n, col, sel, s));
@@ -1589,6 +1590,62 @@ int batch_graph(mg_batch* b) {
   if (e != hipSuccess) {
     b->gexec = nullptr;
     return bfail(b, MG_EHIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
+  }
+  return MG_OK;
+}
+
+// Autotuner of the batched sweep's tile shape: per level, every candidate
+// of launch_b_lsgs_sweep is timed on the batch's own level buffers (x, r and
+// r2 of every instance; FP64 cycles use the level scratch p as x, since the
+// caller's iterate is bound only at solve time), after zeroing them, and the
+// fastest is kept.  One warm-up launch, then the median of 3 timed launches.
+template <typename T>
+int batch_autotune(mg_batch* b, hipStream_t s) {
+  for (auto& g : b->groups) {
+    const int n = 1 << g.L, cnt = (int)g.members.size();
+    std::vector<mgk::BInst<T>> h;
+    for (int i : g.members) {
+      mgk::BInst<T> a = make_binst<T>(b, i, g.L, nullptr, nullptr);
+      if constexpr (std::is_same<T, double>::value) a.x = a.p;
+      const size_t len = L_(b->inst[i], g.L).len;
+      BCHK(b, hipMemsetAsync(a.x, 0, len * sizeof(T), s));
+      BCHK(b, hipMemsetAsync(a.r, 0, len * sizeof(T), s));
+      BCHK(b, hipMemsetAsync(a.r2, 0, len * sizeof(T), s));
+      h.push_back(a);
+    }
+    mgk::BInst<T>* d = nullptr;
+    if (hipMalloc(&d, h.size() * sizeof(h[0])) != hipSuccess) return bfail(b, MG_ENOMEM, "autotune: allocation failed");
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    auto done = [&](int st) {
+      if (e0) (void)hipEventDestroy(e0);
+      if (e1) (void)hipEventDestroy(e1);
+      (void)hipFree(d);
+      return st;
+    };
+    if (hipMemcpyAsync(d, h.data(), h.size() * sizeof(h[0]), hipMemcpyHostToDevice, s) != hipSuccess ||
+        hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
+      return done(bfail(b, MG_EHIP, "autotune: HIP setup failed"));
+    float best = 0.0f;
+    int best_shape = 0;
+    for (int shape = 0; shape < mgk::b_sweep_shapes(); shape++) {
+      if (mgk::launch_b_lsgs_sweep<T>(d, cnt, n, 0, 0, s, shape) != hipSuccess)
+        return done(bfail(b, MG_EHIP, "autotune: sweep launch failed"));
+      float t[3];
+      for (int rep = 0; rep < 3; rep++) {
+        if (hipEventRecord(e0, s) != hipSuccess ||
+            mgk::launch_b_lsgs_sweep<T>(d, cnt, n, 0, rep & 1, s, shape) != hipSuccess ||
+            hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+            hipEventElapsedTime(&t[rep], e0, e1) != hipSuccess)
+          return done(bfail(b, MG_EHIP, "autotune: timing failed"));
+      }
+      std::sort(t, t + 3);
+      if (shape == 0 || t[1] < best) {
+        best = t[1];
+        best_shape = shape;
+      }
+    }
+    g.shape = best_shape;
+    done(MG_OK);
   }
   return MG_OK;
 }
@@ -1691,11 +1748,30 @@ int mg_batch_setup(int count, const int* levels, const double* alphas, int probl
     b->tail_lds = std::max(mgk::tail_lds_bytes<double>(b->k0, b->T),
                            o.precision == MG_FP32_IR ? mgk::tail_lds_bytes<float>(b->k0, b->T) : size_t(0));
   }
+  // tile shapes of the batched LSGS sweeps (MGKKT_NO_AUTOTUNE=1: the default shape)
+  if (o.smoother == MG_LSGS || o.smoother == MG_SLSGS) {
+    const char* nt = std::getenv("MGKKT_NO_AUTOTUNE");
+    if (!(nt && nt[0] == '1')) {
+      for (int i = 0; i < count; i++) b->h_active[i] = 1;
+      if (hipMemcpy(b->d_active, b->h_active, count * sizeof(int), hipMemcpyHostToDevice) != hipSuccess)
+        return bail(MG_EHIP);
+      const int st = o.precision == MG_FP32_IR ? batch_autotune<float>(b, nullptr) : batch_autotune<double>(b, nullptr);
+      if (st != MG_OK) return bail(st);
+      if (hipDeviceSynchronize() != hipSuccess) return bail(MG_EHIP);
+    }
+  }
   *out = b;
   return MG_OK;
 }
 
 void mg_batch_destroy(mg_batch* b) { batch_free(b); }
+
+int mg_batch_sweep_tile(const mg_batch* b, int level) {
+  if (!b) return 0;
+  for (const auto& g : b->groups)
+    if (g.L == level) return mgk::b_sweep_tile(b->o.precision == MG_FP32_IR ? 1 : 0, g.shape);
+  return 0;
+}
 
 int mg_batch_count(const mg_batch* b) { return b ? b->count : 0; }
 

@@ -178,7 +178,9 @@ template <typename T>
 hipError_t launch_b_cgs_phase(const BInst<T>* d, int count, int n, int colour, int sel, hipStream_t s);
 // one LSGS sweep reading the `sel` buffer and writing the other
 template <typename T>
-hipError_t launch_b_lsgs_sweep(const BInst<T>* d, int count, int n, int reverse, int sel, hipStream_t s);
+hipError_t launch_b_lsgs_sweep(const BInst<T>* d, int count, int n, int reverse, int sel, hipStream_t s, int shape = 0);
+int b_sweep_shapes();                              // tile-shape candidates of launch_b_lsgs_sweep
+int b_sweep_tile(int precision_fp32, int shape);   // their tile edges
 // f_c = P^T r (the `sel` buffer); with zero_coarse also x_c = 0, r_c = f_c
 template <typename T>
 hipError_t launch_b_restrict(const BInst<T>* d, int count, int nc, int sel, int zero_coarse, hipStream_t s);

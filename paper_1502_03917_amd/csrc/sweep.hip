@@ -481,18 +481,37 @@ hipError_t launch_tile_cfg(const Lev& L, int reverse, const T* xin, T* x, const 
 
 }  // namespace
 
-// Batched sweeps keep the 48 x 48 tiles on every level: a launch over many
-// instances has enough workgroups to fill the chip, where the smaller tiles'
-// wider halo share would cost bandwidth.
+// Batched sweeps (launch_b_lsgs_sweep): one launch over every instance of a
+// level, instance blockIdx.y.  The tile shape of each level is picked at batch
+// setup by timing the candidates below on the batch's own buffers
+// (b_sweep_shapes: their count; shape 0 is the default).
+//   FP64: 48 x 48, 65 x 65, 56 x 56 (1024 threads, one tile per CU)
+//   FP32: 48 x 48 (512 threads, corrections in LDS), 46 x 46 (512 threads,
+//         one vertex per thread and phase), 65 x 65 (1024 threads)
 template <typename T>
-hipError_t launch_b_lsgs_sweep(const BInst<T>* d, int count, int n, int reverse, int sel, hipStream_t s) {
-  constexpr int TW = SweepShape<T>::TW, NT = SweepShape<T>::NT;
-  const int nt = tiles_along(n + 1, TW);
-  hipLaunchKernelGGL((kb_lsgs_tile<T, TW, NT>), dim3(round8(nt * nt), count), dim3(NT), 0, s, d, nt, reverse, sel);
-  return hipGetLastError();
+hipError_t launch_b_lsgs_sweep(const BInst<T>* d, int count, int n, int reverse, int sel, hipStream_t s, int shape) {
+  auto go = [&](auto kern, int TW, int NT) {
+    const int nt = tiles_along(n + 1, TW);
+    hipLaunchKernelGGL(kern, dim3(round8(nt * nt), count), dim3(NT), 0, s, d, nt, reverse, sel);
+    return hipGetLastError();
+  };
+  if constexpr (std::is_same<T, double>::value) {
+    if (shape == 1) return go(kb_lsgs_tile<T, 65, 1024>, 65, 1024);
+    if (shape == 2) return go(kb_lsgs_tile<T, 56, 1024>, 56, 1024);
+    return go(kb_lsgs_tile<T, 48, 1024>, 48, 1024);
+  } else {
+    if (shape == 1) return go(kb_lsgs_tile<T, 46, 512>, 46, 512);
+    if (shape == 2) return go(kb_lsgs_tile<T, 65, 1024>, 65, 1024);
+    return go(kb_lsgs_tile<T, 48, 512>, 48, 512);
+  }
 }
-template hipError_t launch_b_lsgs_sweep<double>(const BInst<double>*, int, int, int, int, hipStream_t);
-template hipError_t launch_b_lsgs_sweep<float>(const BInst<float>*, int, int, int, int, hipStream_t);
+template hipError_t launch_b_lsgs_sweep<double>(const BInst<double>*, int, int, int, int, hipStream_t, int);
+template hipError_t launch_b_lsgs_sweep<float>(const BInst<float>*, int, int, int, int, hipStream_t, int);
+int b_sweep_shapes() { return 3; }  // candidates of launch_b_lsgs_sweep per precision
+int b_sweep_tile(int precision_fp32, int shape) {  // tile edge of a launch_b_lsgs_sweep shape
+  static const int t64[3] = {48, 65, 56}, t32[3] = {48, 46, 65};
+  return (shape < 0 || shape > 2) ? 0 : precision_fp32 ? t32[shape] : t64[shape];
+}
 
 template <>
 hipError_t launch_lsgs_sweep<double>(const Lev& L, int reverse, double* x, const double* rin, double* rout,

@@ -150,3 +150,35 @@ def test_batch_64_instances_fp32_refinement(torch_cuda):
         assert st1 in (mg.MG_OK, mg.MG_ESTALL)
         x1h = _host(x1)
         assert np.linalg.norm(_host(xs[i]) - x1h) <= 1e-8 * np.linalg.norm(x1h), i
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32_ir"])
+def test_batch_autotuned_tiles_match_default(torch_cuda, monkeypatch, precision):
+    """The setup's autotuner picks a tile shape per level for the batched
+    sweep; its solves equal those with the default shape (MGKKT_NO_AUTOTUNE=1)
+    to rounding, with the same cycle counts, and every picked edge is one of
+    the candidates."""
+    import paper_1502_03917_amd as mg
+
+    torch = torch_cuda
+    levels, alphas = [9, 7, 10, 8], [1e-4, 1.0, 1e-8, 1e-2]
+    yds = _batch_inputs(torch, levels)
+    out = []
+    for env in (None, "1"):
+        if env:
+            monkeypatch.setenv("MGKKT_NO_AUTOTUNE", env)
+        else:
+            monkeypatch.delenv("MGKKT_NO_AUTOTUNE", raising=False)
+        b = mg.Batch(levels, alphas, precision=precision)
+        tiles = {l: b.sweep_tile(l) for l in range(6, 11)}
+        fs = b.rhs(yds)
+        xs, cyc, rel, sts, st = b.solve(fs, tol=1e-10)
+        out.append(([_host(x) for x in xs], cyc, tiles))
+        b.close()
+    monkeypatch.delenv("MGKKT_NO_AUTOTUNE", raising=False)
+    (xa, ca, ta), (xb, cb, tb) = out
+    cand = {48, 65, 56} if precision == "fp64" else {48, 46, 65}
+    assert all(t in cand for t in ta.values()) and all(t == 48 for t in tb.values()), (ta, tb)
+    assert ca == cb
+    for a, bb in zip(xa, xb):
+        assert np.linalg.norm(a - bb) <= 1e-9 * np.linalg.norm(bb)
