@@ -481,3 +481,26 @@ def test_fp32_refinement_full_size(torch_cuda, alpha):
     x64, it64, rel64, st64 = s64.solve(f, tol=1e-10)
     assert st32 == mg.MG_OK and st64 == mg.MG_OK and rel32 <= 1e-10 and rel64 <= 1e-10
     assert torch.linalg.vector_norm(x32 - x64).item() <= 1e-8 * torch.linalg.vector_norm(x64).item()
+
+
+@pytest.mark.parametrize("smoother,gamma", [("lsgs", 1), ("slsgs", 2)])
+def test_cycle_parity_coarse_level_2(torch_cuda, smoother, gamma):
+    # coarsest level k0 = 2 (50 unknowns): the tail, its level-3 map and the
+    # dense level-5 map are all built on the k0 = 2 hierarchy; four cycles
+    # against the oracle on the same hierarchy
+    torch = torch_cuda
+    mg = _mg()
+    level, alpha = 7, 1e-3
+    nu = 1 if smoother == "slsgs" else 2
+    s = mg.Solver(level, alpha, smoother=smoother, gamma=gamma, nu1=nu, nu2=nu, coarse_level=2)
+    h = oracle.Hierarchy(level, alpha, coarse=2)
+    yd = workloads.desired_state(level, 5)
+    f = h.rhs(yd)
+    fg = s.rhs(_dev(torch, yd))
+    xg = torch.zeros(h.ndof(), dtype=torch.float64, device="cuda")
+    xo = np.zeros(h.ndof())
+    for m in range(4):
+        s.cycle(fg, xg)
+        h.cycle(f, xo, smoother=smoother, order="col7", gamma=gamma, nu1=nu, nu2=nu)
+        err = np.linalg.norm(_host(xg) - xo) / np.linalg.norm(xo)
+        assert err <= 1e-12, (m, err)
