@@ -15,6 +15,7 @@
 // one thread per patch for a colour phase of the patch (Vanka-type) smoother.
 #include <algorithm>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <string>
 #include <unordered_map>
@@ -236,6 +237,7 @@ struct ClassA {
   std::vector<double> val;
 };
 constexpr int kEntOff = 16;  // offsets are stored + 16 in 8 bits
+constexpr int kMaxRowEntries = 64;  // the LSGS kernel holds up to 64 entries of a row in registers
 __host__ __device__ inline int sent_col(const SGeo& g, int e, int hx, int hy) {
   return sindex(g, e & 0xFF, hx + ((e >> 8) & 0xFF) - kEntOff, hy + ((e >> 16) & 0xFF) - kEntOff);
 }
@@ -298,6 +300,11 @@ bool build_classes(const HCsr& A, const SGeo& g, ClassA& C, std::string* err) {
     }
     C.row_cls[i] = id;
   }
+  for (size_t c = 0; c + 1 < C.ptr.size(); c++)
+    if (C.ptr[c + 1] - C.ptr[c] > kMaxRowEntries) {
+      *err = "stokes: a row has more entries than the LSGS kernel takes";
+      return false;
+    }
   return true;
 }
 
@@ -757,14 +764,18 @@ __global__ __launch_bounds__(kSNT) void ks_ne_r(int n, AT A, const T* __restrict
 // One colour phase of Alg. 2: every group (two unknowns whose entry of
 // N = A^T L^-1 A is zero) takes both q from the residual, updates x, and
 // subtracts A_ji p_i from r; groups of a phase share no residual entry.
-// One wave per group: each half-wave gathers one row (32 lanes), then the two
-// rows are scattered one after the other (they touch the same entries of r).
-constexpr int kHalf = 32;
+// A wave takes kGroups groups (the phase's cost is the dependent chain of
+// gathers of each wave, so fewer, fuller waves finish sooner): each row of a
+// group has kLR lanes, each lane holds up to kNE of the row's entries (rows
+// of this discretisation have at most 64) in registers; the two rows of a
+// group are scattered one after the other (they touch the same entries of r).
+constexpr int kGroups = 2, kLR = 32 / kGroups, kNE = 64 / kLR;
+static_assert(kLR * kNE == kMaxRowEntries, "entries held per row");
 
 template <typename T>
-__device__ inline T half_sum(T v) {
+__device__ inline T lr_sum(T v) {
 #pragma unroll
-  for (int o = kHalf / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, kHalf);
+  for (int o = kLR / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, kLR);
   return v;
 }
 
@@ -772,53 +783,184 @@ template <typename T, typename AT>
 __global__ __launch_bounds__(kSNT) void ks_lsgs(int g0, int ng, const int2* __restrict__ grp, AT A,
                                                 const T* __restrict__ Linv, const T* __restrict__ Ninv,
                                                 T* __restrict__ x, T* __restrict__ r) {
-  const int g = blockIdx.x * (kSNT / 64) + threadIdx.x / 64;
-  if (g >= ng) return;  // uniform per wave
-  const int lane = threadIdx.x % 64, half = lane / kHalf, ln = lane % kHalf;
-  const int2 u = grp[g0 + g];
+  const int wave = blockIdx.x * (kSNT / 64) + threadIdx.x / 64;
+  if (wave * kGroups >= ng) return;  // uniform per wave
+  const int lane = threadIdx.x % 64;
+  const int gw = lane / (2 * kLR), half = (lane / kLR) & 1, ln = lane % kLR;
+  const int g = wave * kGroups + gw;
+  const bool live = g < ng;
+  const int2 u = live ? grp[g0 + g] : make_int2(0, 0);
   const int row = half ? u.y : u.x;
-  int kb, ke, pos;
-  A.row(row, kb, ke, pos);
-  // the first two entries of each lane (rows of this discretisation have at
-  // most 2 kHalf entries) are gathered in one round and their column indices
-  // and values kept in registers; longer rows continue in the loops below
-  // (same summation order)
-  const int k0 = kb + ln, k1 = k0 + kHalf;
-  const bool h0 = k0 < ke, h1 = k1 < ke;
-  const int c0 = h0 ? A.col_of(k0, pos) : 0, c1 = h1 ? A.col_of(k1, pos) : 0;
-  const T v0 = h0 ? A.val_of(k0) : (T)0, v1 = h1 ? A.val_of(k1) : (T)0;
-  T q = 0;
-  if (h0) q += v0 * Linv[c0] * r[c0];
-  if (h1) q += v1 * Linv[c1] * r[c1];
-  for (int k = k1 + kHalf; k < ke; k += kHalf) {
-    const int c = A.col_of(k, pos);
-    q += A.val_of(k) * Linv[c] * r[c];
+  int kb = 0, ke = 0, pos = 0;
+  if (live) A.row(row, kb, ke, pos);
+  int c[kNE];
+  T v[kNE];
+#pragma unroll
+  for (int e = 0; e < kNE; e++) {
+    const int k = kb + ln + e * kLR;
+    const bool h = k < ke;
+    c[e] = h ? A.col_of(k, pos) : 0;
+    v[e] = h ? A.val_of(k) : (T)0;
   }
-  q = half_sum(q);
-  const T pv = q * Ninv[row];
-  if (ln == 0) x[row] += pv;
-  // The two rows of the group share residual entries: each half re-reads
+  T q = 0;
+#pragma unroll
+  for (int e = 0; e < kNE; e++)
+    if (kb + ln + e * kLR < ke) q += v[e] * Linv[c[e]] * r[c[e]];
+  q = lr_sum(q);
+  const T pv = live ? q * Ninv[row] : (T)0;
+  if (live && ln == 0) x[row] += pv;
+  // The two rows of a group share residual entries: each half re-reads
   // every entry before its update.  The halves' branches may run in either
   // order (they are exclusive per lane), so neither may reuse the gathered
   // values; the re-reads are relaxed atomic loads, which the compiler does
   // not replace by earlier plain loads of the same address.
-  auto fresh = [&](int c) { return __hip_atomic_load(r + c, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP); };
+  auto fresh = [&](int cc) { return __hip_atomic_load(r + cc, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP); };
   if (half == 0) {
-    if (h0) r[c0] = fresh(c0) - v0 * pv;
-    if (h1) r[c1] = fresh(c1) - v1 * pv;
-    for (int k = k1 + kHalf; k < ke; k += kHalf) {
-      const int c = A.col_of(k, pos);
-      r[c] = fresh(c) - A.val_of(k) * pv;
-    }
+#pragma unroll
+    for (int e = 0; e < kNE; e++)
+      if (kb + ln + e * kLR < ke) r[c[e]] = fresh(c[e]) - v[e] * pv;
   }
   __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
   if (half == 1) {
-    if (h0) r[c0] = fresh(c0) - v0 * pv;
-    if (h1) r[c1] = fresh(c1) - v1 * pv;
-    for (int k = k1 + kHalf; k < ke; k += kHalf) {
-      const int c = A.col_of(k, pos);
-      r[c] = fresh(c) - A.val_of(k) * pv;
+#pragma unroll
+    for (int e = 0; e < kNE; e++)
+      if (kb + ln + e * kLR < ke) r[c[e]] = fresh(c[e]) - v[e] * pv;
+  }
+}
+
+// Every smoothing step of Alg. 2 on a small level in one workgroup.  On
+// these levels a colour phase has few groups, so a launch per phase costs
+// far more than the work: here the residual, x and L^-1 stay in LDS, phases
+// are separated by workgroup barriers, and each lane's part of the matrix
+// (which does not depend on the residual) comes from phase-ordered arrays
+// built at setup, loaded one phase ahead of its use (the row and entry
+// count two phases ahead).  Lane t of phase ph: meta[ph][t] = (row, count),
+// entry e at col/val[ph][e][t]; row -1 and count 0 mark an idle lane.
+constexpr int kWT = 1024, kWG = 4, kWLR = 32 / kWG, kWNE = 64 / kWLR;
+constexpr int kWSlots = kWT / 64 * kWG;  // largest phase (in groups) the kernel takes
+constexpr int kWLdsBytes = 150 * 1024;   // residual, x and L^-1 of the level
+static_assert(kWLR * kWNE == kMaxRowEntries, "entries held per row");
+
+template <typename T>
+__device__ inline T wlr_sum(T v) {
+#pragma unroll
+  for (int o = kWLR / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, kWLR);
+  return v;
+}
+
+// orders LDS accesses only: the kernel's global stores are its last act
+__device__ inline void lds_barrier() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
+// Global loads of the kernel below are buffer loads issued unconditionally:
+// an unused one takes an offset past the end of its buffer, which the
+// hardware answers with zero and no memory access.  With a fixed sequence of
+// loads the compiler waits only for the data about to be used, so the loads
+// for the next phase stay in flight through the current one.
+constexpr unsigned kOff = 0x80000000u;  // past the end of every buffer (< 2 GiB each)
+
+__device__ inline __amdgpu_buffer_rsrc_t rsrc(const void* p, int bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), 0, bytes, 0x00020000);
+}
+__device__ inline int bld_i(__amdgpu_buffer_rsrc_t r, unsigned off) {
+  return __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0);
+}
+__device__ inline double bld(__amdgpu_buffer_rsrc_t r, unsigned off, double*) {
+  return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0));
+}
+__device__ inline float bld(__amdgpu_buffer_rsrc_t r, unsigned off, float*) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0));
+}
+
+template <typename T>
+__global__ __launch_bounds__(kWT) void ks_lsgs_wg(int ndof, int nph, int nseq, int sweeps,
+                                                  const int2* __restrict__ meta, const int* __restrict__ col,
+                                                  const T* __restrict__ val, const T* __restrict__ Linv,
+                                                  const T* __restrict__ Ninv, T* __restrict__ x, T* __restrict__ r) {
+  __shared__ T lds[kWLdsBytes / sizeof(T)];
+  T* rs = lds;
+  T* ls = lds + ndof;
+  T* xs = lds + 2 * ndof;
+  const int t = threadIdx.x, ln = t % kWLR, half = (t / kWLR) & 1;
+  for (int i = t; i < ndof; i += kWT) {
+    rs[i] = r[i];
+    ls[i] = Linv[i];
+    xs[i] = x[i];
+  }
+  const int nent = nph * kWNE * kWT;
+  const __amdgpu_buffer_rsrc_t Rm = rsrc(meta, nph * kWT * 8), Rc = rsrc(col, nent * 4),
+                               Rv = rsrc(val, nent * (int)sizeof(T)), Rn = rsrc(Ninv, ndof * (int)sizeof(T));
+  // phase of step s: sweeps alternate forward and backward colour order
+  auto phase = [&](int s) {
+    const int k = s % nph;
+    return (s / nph) % sweeps ? nph - 1 - k : k;
+  };
+  // (row, count) of this lane at step s; steps past the end read (0, 0)
+  auto ld_meta = [&](int s, int& row, int& cnt) {
+    const unsigned o = s < nseq ? (unsigned)((phase(s) * kWT + t) * 8) : kOff;
+    row = bld_i(Rm, o);
+    cnt = bld_i(Rm, o + 4);
+  };
+  // entries (absent ones read column 0, value 0) and N_ii^-1 at step s
+  auto ld_ent = [&](int s, int row, int cnt, int* c, T* v, T& ni) {
+    const int ph = s < nseq ? phase(s) : 0;
+#pragma unroll
+    for (int e = 0; e < kWNE; e++) {
+      const int i = (ph * kWNE + e) * kWT + t;
+      c[e] = bld_i(Rc, e < cnt ? (unsigned)i * 4u : kOff);
+      v[e] = bld(Rv, e < cnt ? (unsigned)(i * (int)sizeof(T)) : kOff, (T*)nullptr);
     }
+    ni = bld(Rn, row >= 0 && cnt > 0 ? (unsigned)(row * (int)sizeof(T)) : kOff, (T*)nullptr);
+  };
+  // one step: q = sum_j A_ij L_jj^-1 r_j over each row of the group, then
+  // x_i += p_i and r_j -= A_ji p_i
+  auto step = [&](int row, int cnt, const int* c, const T* v, T ni) {
+    T q = 0;
+#pragma unroll
+    for (int e = 0; e < kWNE; e++) q += v[e] * ls[c[e]] * rs[c[e]];
+    q = wlr_sum(q);
+    const T pv = q * ni;
+    if (cnt > 0 && ln == 0) xs[row] += pv;
+    // the group's two rows share residual entries: the second row's lanes
+    // update after the first's (a wave's LDS accesses complete in order;
+    // the empty asm keeps the compiler from reordering or reusing loads)
+    if (half == 0) {
+#pragma unroll
+      for (int e = 0; e < kWNE; e++)
+        if (e < cnt) rs[c[e]] -= v[e] * pv;
+    }
+    asm volatile("" ::: "memory");
+    if (half == 1) {
+#pragma unroll
+      for (int e = 0; e < kWNE; e++)
+        if (e < cnt) rs[c[e]] -= v[e] * pv;
+    }
+  };
+  // two register sets, used in turn (unrolled by two so that neither is
+  // copied into the other, which would wait for the loads in flight)
+  int rowA, cntA, rowB, cntB, cA[kWNE], cB[kWNE];
+  T vA[kWNE], vB[kWNE], nA, nB;
+  ld_meta(0, rowA, cntA);
+  ld_ent(0, rowA, cntA, cA, vA, nA);
+  ld_meta(1, rowB, cntB);
+  lds_barrier();
+  for (int s = 0; s < nseq; s += 2) {
+    ld_ent(s + 1, rowB, cntB, cB, vB, nB);
+    step(rowA, cntA, cA, vA, nA);
+    ld_meta(s + 2, rowA, cntA);
+    lds_barrier();
+    if (s + 1 == nseq) break;
+    ld_ent(s + 2, rowA, cntA, cA, vA, nA);
+    step(rowB, cntB, cB, vB, nB);
+    ld_meta(s + 3, rowB, cntB);
+    lds_barrier();
+  }
+  for (int i = t; i < ndof; i += kWT) {
+    r[i] = rs[i];
+    x[i] = xs[i];
   }
 }
 
@@ -1002,6 +1144,11 @@ struct StokesLevel {
   // LSGS colour phases: groups of two unknowns, phase g spans groups [gph[g], gph[g+1])
   int2* groups = nullptr;
   std::vector<int> gph;
+  // the same phases laid out for the one-workgroup sweep (small levels only)
+  int2* w_meta = nullptr;
+  int* w_col = nullptr;
+  double* w_val = nullptr;
+  float* w_val32 = nullptr;
   // patch smoother: patches (one per vertex) ordered by colour, phase spans vph
   int *v_order = nullptr, *v_dptr = nullptr, *v_dof = nullptr, *v_piv = nullptr;
   long long* v_luptr = nullptr;
@@ -1019,6 +1166,7 @@ struct Stokes {
   int level = 0, k0 = 1, smoother = 1, nu1 = 2, nu2 = 2, gamma = 1;
   double alpha = 1.0, tau = 0.35;
   bool fp32 = false;
+  bool wg_sweep = true;  // one-workgroup LSGS sweeps on small levels (MGKKT_NO_WG_SWEEP unset)
   std::vector<StokesLevel> lv;  // lv[l - k0]
   int *M_rp = nullptr, *M_col = nullptr;  // scalar P2 mass of the finest level (right-hand side)
   double* M_val = nullptr;
@@ -1055,6 +1203,43 @@ hipError_t zalloc(Stokes* S, T** d, size_t n) {
   } while (0)
 
 std::vector<float> to32(const std::vector<double>& v) { return std::vector<float>(v.begin(), v.end()); }
+
+// Lanes of the one-workgroup sweep: group slot k of a phase goes to wave
+// k / kWG, its two rows to consecutive runs of kWLR lanes, and entry e of a
+// row to lane e % kWLR, register e / kWLR.  Levels whose residual, x and
+// L^-1 exceed the kernel's LDS, or with a phase of more than kWSlots groups,
+// keep the launch per phase.
+hipError_t build_wg_phases(Stokes* S, StokesLevel& L, const HCsr& A, const std::vector<int2>& grp) {
+  const int nph = (int)L.gph.size() - 1;
+  if (3 * (size_t)L.ndof * sizeof(double) > (size_t)kWLdsBytes) return hipSuccess;
+  for (int ph = 0; ph < nph; ph++)
+    if (L.gph[ph + 1] - L.gph[ph] > kWSlots) return hipSuccess;
+  std::vector<int2> meta((size_t)nph * kWT, make_int2(-1, 0));
+  std::vector<int> col((size_t)nph * kWNE * kWT, 0);
+  std::vector<double> val(col.size(), 0.0);
+  for (int ph = 0; ph < nph; ph++)
+    for (int g = L.gph[ph]; g < L.gph[ph + 1]; g++) {
+      const int k = g - L.gph[ph];
+      for (int h = 0; h < 2; h++) {
+        const int row = h ? grp[g].y : grp[g].x, kb = A.rp[row], len = A.rp[row + 1] - kb;
+        for (int ln = 0; ln < kWLR; ln++) {
+          const int t = (k / kWG) * 64 + (k % kWG) * 2 * kWLR + h * kWLR + ln;
+          const int cnt = len > ln ? (len - ln + kWLR - 1) / kWLR : 0;
+          meta[(size_t)ph * kWT + t] = make_int2(row, cnt);
+          for (int e = 0; e < cnt; e++) {
+            const size_t o = ((size_t)ph * kWNE + e) * kWT + t;
+            col[o] = A.col[kb + ln + e * kWLR];
+            val[o] = A.val[kb + ln + e * kWLR];
+          }
+        }
+      }
+    }
+  SCHK(up(S, &L.w_meta, meta));
+  SCHK(up(S, &L.w_col, col));
+  SCHK(up(S, &L.w_val, val));
+  if (S->fp32) SCHK(up(S, &L.w_val32, to32(val)));
+  return hipSuccess;
+}
 
 hipError_t build_level(Stokes* S, int l, bool finest, std::string* err) {
   StokesLevel& L = S->L(l);
@@ -1114,6 +1299,7 @@ hipError_t build_level(Stokes* S, int l, bool finest, std::string* err) {
   std::vector<int2> grp;
   colour_groups(n, grp, L.gph);
   SCHK(up(S, &L.groups, grp));
+  if (S->wg_sweep && (S->smoother == MG_LSGS || S->smoother == MG_SLSGS)) SCHK(build_wg_phases(S, L, A, grp));
   // patches of the patch smoother
   if (S->smoother == MG_VANKA) {
     std::vector<int> dptr, dof, piv, order;
@@ -1198,6 +1384,7 @@ struct SV<double> {
   static const double* R(StokesLevel& L) { return L.R_val; }
   static const double* Linv(StokesLevel& L) { return L.Linv; }
   static const double* Ninv(StokesLevel& L) { return L.Ninv; }
+  static const double* W(StokesLevel& L) { return L.w_val; }
 };
 template <>
 struct SV<float> {
@@ -1210,6 +1397,7 @@ struct SV<float> {
   static const float* R(StokesLevel& L) { return L.R_val32; }
   static const float* Linv(StokesLevel& L) { return L.Linv32; }
   static const float* Ninv(StokesLevel& L) { return L.Ninv32; }
+  static const float* W(StokesLevel& L) { return L.w_val32; }
 };
 
 // A of level L by stencil classes; the transfers P (from level l-1) and R (to it) as CSR
@@ -1248,11 +1436,18 @@ hipError_t s_smooth(Stokes* S, StokesLevel& L, T* x, T* r, int steps, hipStream_
       case MG_SLSGS: {
         const int nph = (int)L.gph.size() - 1;
         const int sweeps = S->smoother == MG_SLSGS ? 2 : 1;
+        if (L.w_meta) {  // every step in one workgroup
+          if (steps > 0)
+            hipLaunchKernelGGL((ks_lsgs_wg<T>), dim3(1), dim3(kWT), 0, s, L.ndof, nph, steps * sweeps * nph, sweeps,
+                               (const int2*)L.w_meta, (const int*)L.w_col, SV<T>::W(L), SV<T>::Linv(L),
+                               SV<T>::Ninv(L), x, r);
+          return hipGetLastError();
+        }
         for (int sw = 0; sw < sweeps; sw++)
           for (int k = 0; k < nph; k++) {
             const int ph = sw == 0 ? k : nph - 1 - k;
             const int g0 = L.gph[ph], ng = L.gph[ph + 1] - g0;
-            hipLaunchKernelGGL((ks_lsgs<T, ClassRows<T>>), dim3(blocks_for(ng, kSNT / 64)), dim3(kSNT), 0, s, g0, ng,
+            hipLaunchKernelGGL((ks_lsgs<T, ClassRows<T>>), dim3(blocks_for(ng, kSNT / 64 * kGroups)), dim3(kSNT), 0, s, g0, ng,
                                (const int2*)L.groups, A, SV<T>::Linv(L), SV<T>::Ninv(L), x, r);
           }
         break;
@@ -1326,6 +1521,7 @@ int stokes_create(int level, int k0, double alpha, const mg_opts& o, Stokes** ou
   S->gamma = o.gamma;
   S->tau = o.tau;
   S->fp32 = o.precision == MG_FP32_IR;
+  S->wg_sweep = std::getenv("MGKKT_NO_WG_SWEEP") == nullptr;
   S->lv.resize(level - k0 + 1);
   for (int l = k0; l <= level; l++) {
     const hipError_t e = build_level(S, l, l == level, err);

@@ -91,6 +91,48 @@ def test_stokes_smoothing_step(torch_cuda, smoother, order, alpha):
     assert _rel(_host(rg), ro) < 1e-11
 
 
+@pytest.mark.parametrize("smoother", ["lsgs", "slsgs"])
+@pytest.mark.parametrize("level", [2, 4, 5])
+def test_stokes_lsgs_steps(torch_cuda, smoother, level):
+    """Two smoothing steps: levels up to 4 run every phase of both steps in one
+    workgroup (an odd number of phases for LSGS, even for sLSGS), level 5
+    launches each colour phase."""
+    torch = torch_cuda
+    s = _solver(level, 1e-2, smoother=smoother)
+    h = oracle.Hierarchy(level, 1e-2, coarse=1, problem="stokes")
+    n = h.ndof()
+    x0 = workloads.uniform(n, 91)
+    f = workloads.uniform(n, 92)
+    r0 = f - h.matrix("A") @ x0
+    xo, ro = x0.copy(), r0.copy()
+    for _ in range(2):
+        h.smooth(xo, ro, smoother=smoother, order="col7")
+    xg, rg = _dev(torch, x0), _dev(torch, r0)
+    s.smooth(xg, rg, steps=2)
+    assert _rel(_host(xg), xo) < 1e-12
+    assert _rel(_host(rg), ro) < 1e-11
+
+
+def test_stokes_wg_sweep_matches_phase_launches(torch_cuda, monkeypatch):
+    """The one-workgroup sweep of a small level against a launch per colour
+    phase (MGKKT_NO_WG_SWEEP=1) on the same input, three sLSGS steps."""
+    torch = torch_cuda
+    monkeypatch.setenv("MGKKT_NO_WG_SWEEP", "1")
+    s_ph = _solver(4, 1e-4, smoother="slsgs")
+    monkeypatch.delenv("MGKKT_NO_WG_SWEEP")
+    s_wg = _solver(4, 1e-4, smoother="slsgs")
+    n = s_wg.vec_len()
+    x0 = workloads.uniform(n, 93)
+    r0 = workloads.uniform(n, 94)
+    out = []
+    for s in (s_ph, s_wg):
+        xg, rg = _dev(torch, x0), _dev(torch, r0)
+        s.smooth(xg, rg, steps=3)
+        out.append((_host(xg), _host(rg)))
+    assert _rel(out[1][0], out[0][0]) < 1e-13
+    assert _rel(out[1][1], out[0][1]) < 1e-13
+
+
 STOKES_CYCLES = [
     (3, 1e-2, "lsgs", 1),
     (3, 1.0, "ne", 1),
