@@ -7,12 +7,16 @@
 // (2n-1)^2 interior nodes (a, b) of the half-step lattice (index
 // (b-1)(2n-1)+(a-1)), p and mu on the (n+1)^2 vertices (index j(n+1)+i).
 //
-// The operator has six coupled fields and two element types, so it is kept
-// as one CSR matrix per level (assembled here on the host from element
-// matrices computed by Gauss quadrature), and the kernels walk its rows:
-// one thread per row for the residual and the normal-equation smoother, one
-// thread per group of unknowns for a colour phase of the LSGS sweep (Alg. 2),
-// one thread per patch for a colour phase of the patch (Vanka-type) smoother.
+// The operator has six coupled fields and two element types.  It is
+// assembled on the host (element matrices by Gauss quadrature) and kept on
+// the device by stencil classes: the mesh is uniform, so rows that agree in
+// column fields, lattice offsets and values share one entry list, and a
+// level's matrix takes a few hundred classes instead of a CSR array.  The
+// kernels walk rows through the classes: 16 lanes per row for the residual
+// and the normal-equation smoother; for a colour phase of the LSGS sweep
+// (Alg. 2), 32 lanes per group of two unknowns with the two rows merged (on
+// small levels, every phase of every step in one workgroup with the
+// residual in LDS); a wave per patch for the patch (Vanka-type) smoother.
 #include <algorithm>
 #include <cmath>
 #include <cstdlib>
@@ -237,7 +241,7 @@ struct ClassA {
   std::vector<double> val;
 };
 constexpr int kEntOff = 16;  // offsets are stored + 16 in 8 bits
-constexpr int kMaxRowEntries = 64;  // the LSGS kernel holds up to 64 entries of a row in registers
+constexpr int kMaxRowEntries = 64;  // the one-workgroup LSGS kernel holds up to 64 entries of a row in registers
 __host__ __device__ inline int sent_col(const SGeo& g, int e, int hx, int hy) {
   return sindex(g, e & 0xFF, hx + ((e >> 8) & 0xFF) - kEntOff, hy + ((e >> 16) & 0xFF) - kEntOff);
 }
@@ -302,7 +306,7 @@ bool build_classes(const HCsr& A, const SGeo& g, ClassA& C, std::string* err) {
   }
   for (size_t c = 0; c + 1 < C.ptr.size(); c++)
     if (C.ptr[c + 1] - C.ptr[c] > kMaxRowEntries) {
-      *err = "stokes: a row has more entries than the LSGS kernel takes";
+      *err = "stokes: a row has more entries than the one-workgroup LSGS kernel takes";
       return false;
     }
   return true;
@@ -761,71 +765,92 @@ __global__ __launch_bounds__(kSNT) void ks_ne_r(int n, AT A, const T* __restrict
   }
 }
 
-// One colour phase of Alg. 2: every group (two unknowns whose entry of
-// N = A^T L^-1 A is zero) takes both q from the residual, updates x, and
-// subtracts A_ji p_i from r; groups of a phase share no residual entry.
-// A wave takes kGroups groups (the phase's cost is the dependent chain of
-// gathers of each wave, so fewer, fuller waves finish sooner): each row of a
-// group has kLR lanes, each lane holds up to kNE of the row's entries (rows
-// of this discretisation have at most 64) in registers; the two rows of a
-// group are scattered one after the other (they touch the same entries of r).
-constexpr int kGroups = 2, kLR = 32 / kGroups, kNE = 64 / kLR;
-static_assert(kLR * kNE == kMaxRowEntries, "entries held per row");
+// One colour phase of Alg. 2.  A group is two unknowns whose entry of
+// N = A^T L^-1 A is zero (a velocity component and its multiplier at one
+// node, or the pressure and its multiplier at one vertex), so both take q
+// from the same residual; groups of a phase share no residual entry.  A group
+// (i, j) keeps the union of its two rows' columns, each entry with both
+// coefficients (A_ik, A_jk), in a group class (groups whose merged entries
+// agree in field, lattice offset from row i and values share one).  One
+// gather of L^-1 r over the union gives q_i and q_j; since no other group of
+// the phase touches these residual entries, the gathered values are still
+// current and each is written once, r_k - A_ik p_i - A_jk p_j.  The class
+// also fixes L_kk^-1 of every merged column and N_ii^-1, N_jj^-1 (stored at
+// the class's first entry), so the phase gathers nothing but r.  A group
+// record is (i, j, first entry, end).
+constexpr int kMaxGroupEntries = 96;
 
 template <typename T>
-__device__ inline T lr_sum(T v) {
-#pragma unroll
-  for (int o = kLR / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, kLR);
-  return v;
-}
+struct T2of;
+template <>
+struct T2of<double> {
+  typedef double2 type;
+};
+template <>
+struct T2of<float> {
+  typedef float2 type;
+};
 
-template <typename T, typename AT>
-__global__ __launch_bounds__(kSNT) void ks_lsgs(int g0, int ng, const int2* __restrict__ grp, AT A,
-                                                const T* __restrict__ Linv, const T* __restrict__ Ninv,
-                                                T* __restrict__ x, T* __restrict__ r) {
+// A group per kGLR lanes, kGNE merged entries per lane in registers.  The
+// phase's cost is the chain of dependent loads of each wave (record, entries,
+// gathers), not bandwidth.
+constexpr int kGLR = 32, kGNE = kMaxGroupEntries / kGLR;
+
+template <typename T>
+__global__ __launch_bounds__(kSNT) void ks_lsgs_grp(int g0, int ng, const int4* __restrict__ grp,
+                                                    const int* __restrict__ gent,
+                                                    const typename T2of<T>::type* __restrict__ gval,
+                                                    const T* __restrict__ glinv,
+                                                    const typename T2of<T>::type* __restrict__ gninv, SGeo geo,
+                                                    T* __restrict__ x, T* __restrict__ r) {
+  constexpr int LR = kGLR, G = 64 / LR, NE = kGNE;
   const int wave = blockIdx.x * (kSNT / 64) + threadIdx.x / 64;
-  if (wave * kGroups >= ng) return;  // uniform per wave
-  const int lane = threadIdx.x % 64;
-  const int gw = lane / (2 * kLR), half = (lane / kLR) & 1, ln = lane % kLR;
-  const int g = wave * kGroups + gw;
+  if (wave * G >= ng) return;  // uniform per wave
+  const int lane = threadIdx.x % 64, ln = lane % LR;
+  const int g = wave * G + lane / LR;
   const bool live = g < ng;
-  const int2 u = live ? grp[g0 + g] : make_int2(0, 0);
-  const int row = half ? u.y : u.x;
-  int kb = 0, ke = 0, pos = 0;
-  if (live) A.row(row, kb, ke, pos);
-  int c[kNE];
-  T v[kNE];
+  const int4 u = live ? grp[g0 + g] : make_int4(0, 0, 0, 0);
+  int hx, hy;
+  spos(geo, u.x, hx, hy);
+  int c[NE];
+  typename T2of<T>::type a[NE];
+  T l[NE], rc[NE];
 #pragma unroll
-  for (int e = 0; e < kNE; e++) {
-    const int k = kb + ln + e * kLR;
-    const bool h = k < ke;
-    c[e] = h ? A.col_of(k, pos) : 0;
-    v[e] = h ? A.val_of(k) : (T)0;
+  for (int e = 0; e < NE; e++) {
+    const int k = u.z + ln + e * LR;
+    const bool h = k < u.w;
+    c[e] = h ? sent_col(geo, gent[k], hx, hy) : 0;
+    if (h) {
+      a[e] = gval[k];
+      l[e] = glinv[k];
+    } else {
+      a[e].x = a[e].y = l[e] = 0;
+    }
   }
-  T q = 0;
+  typename T2of<T>::type nn;
+  if (live) nn = gninv[u.z];
+  else nn.x = nn.y = 0;
+  T qi = 0, qj = 0;
 #pragma unroll
-  for (int e = 0; e < kNE; e++)
-    if (kb + ln + e * kLR < ke) q += v[e] * Linv[c[e]] * r[c[e]];
-  q = lr_sum(q);
-  const T pv = live ? q * Ninv[row] : (T)0;
-  if (live && ln == 0) x[row] += pv;
-  // The two rows of a group share residual entries: each half re-reads
-  // every entry before its update.  The halves' branches may run in either
-  // order (they are exclusive per lane), so neither may reuse the gathered
-  // values; the re-reads are relaxed atomic loads, which the compiler does
-  // not replace by earlier plain loads of the same address.
-  auto fresh = [&](int cc) { return __hip_atomic_load(r + cc, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP); };
-  if (half == 0) {
-#pragma unroll
-    for (int e = 0; e < kNE; e++)
-      if (kb + ln + e * kLR < ke) r[c[e]] = fresh(c[e]) - v[e] * pv;
+  for (int e = 0; e < NE; e++) {
+    rc[e] = u.z + ln + e * LR < u.w ? r[c[e]] : (T)0;
+    const T w = l[e] * rc[e];
+    qi += a[e].x * w;
+    qj += a[e].y * w;
   }
-  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
-  if (half == 1) {
 #pragma unroll
-    for (int e = 0; e < kNE; e++)
-      if (kb + ln + e * kLR < ke) r[c[e]] = fresh(c[e]) - v[e] * pv;
+  for (int o = LR / 2; o > 0; o >>= 1) {
+    qi += __shfl_xor(qi, o, LR);
+    qj += __shfl_xor(qj, o, LR);
   }
+  const T pi = qi * nn.x, pj = qj * nn.y;
+  if (live && ln == 0) {
+    x[u.x] += pi;
+    x[u.y] += pj;
+  }
+#pragma unroll
+  for (int e = 0; e < NE; e++)
+    if (u.z + ln + e * LR < u.w) r[c[e]] = (rc[e] - a[e].x * pi) - a[e].y * pj;
 }
 
 // Every smoothing step of Alg. 2 on a small level in one workgroup.  On
@@ -1142,8 +1167,14 @@ struct StokesLevel {
   double *P_val = nullptr, *R_val = nullptr;
   float *P_val32 = nullptr, *R_val32 = nullptr;
   // LSGS colour phases: groups of two unknowns, phase g spans groups [gph[g], gph[g+1])
-  int2* groups = nullptr;
   std::vector<int> gph;
+  // merged groups: records (i, j, first entry, end), group-class entries and coefficient pairs
+  int4* mgroups = nullptr;
+  int* g_ent = nullptr;
+  double2 *g_val = nullptr, *g_ninv = nullptr;
+  double* g_linv = nullptr;
+  float2 *g_val32 = nullptr, *g_ninv32 = nullptr;
+  float* g_linv32 = nullptr;
   // the same phases laid out for the one-workgroup sweep (small levels only)
   int2* w_meta = nullptr;
   int* w_col = nullptr;
@@ -1203,6 +1234,105 @@ hipError_t zalloc(Stokes* S, T** d, size_t n) {
   } while (0)
 
 std::vector<float> to32(const std::vector<double>& v) { return std::vector<float>(v.begin(), v.end()); }
+
+// Merged groups (see ks_lsgs_grp): entries of row i in its order, then those
+// of row j that row i lacks.  Both unknowns of a group sit at one lattice
+// position, so the merged entries follow from the two rows' stencil classes;
+// the group class adds L^-1 of the merged columns and the two N^-1 (equal
+// for all groups of the class, up to the hash's full comparison).
+bool build_group_classes(const ClassA& C, const SGeo& g, const std::vector<int2>& grp,
+                         const std::vector<double>& Linv, const std::vector<double>& Ninv, std::vector<int4>& rec,
+                         std::vector<int>& ent, std::vector<double2>& val, std::vector<double>& lv,
+                         std::vector<double2>& nv, std::string* err) {
+  std::unordered_map<unsigned long long, std::vector<int>> pair_union;  // (class i, class j) -> merged entries
+  std::unordered_map<unsigned long long, std::vector<int2>> seen;       // hash -> classes
+  std::vector<std::vector<double2>> pair_vals;
+  rec.resize(grp.size());
+  ent.clear();
+  val.clear();
+  lv.clear();
+  nv.clear();
+  std::vector<double> lk;
+  for (size_t q = 0; q < grp.size(); q++) {
+    const int i = grp[q].x, j = grp[q].y;
+    int hx, hy, jx, jy;
+    spos(g, i, hx, hy);
+    spos(g, j, jx, jy);
+    if (jx != hx || jy != hy) {
+      *err = "stokes: the two unknowns of a group sit at different lattice positions";
+      return false;
+    }
+    const int ci = C.row_cls[i], cj = C.row_cls[j];
+    const unsigned long long key = ((unsigned long long)(unsigned)ci << 32) | (unsigned)cj;
+    auto pu = pair_union.find(key);
+    if (pu == pair_union.end()) {
+      std::vector<int> u;
+      std::vector<double2> uv;
+      for (int k = C.ptr[ci]; k < C.ptr[ci + 1]; k++) {
+        u.push_back(C.ent[k]);
+        uv.push_back(make_double2(C.val[k], 0.0));
+      }
+      for (int k = C.ptr[cj]; k < C.ptr[cj + 1]; k++) {
+        size_t t = 0;
+        while (t < u.size() && u[t] != C.ent[k]) t++;
+        if (t == u.size()) {
+          u.push_back(C.ent[k]);
+          uv.push_back(make_double2(0.0, C.val[k]));
+        } else {
+          uv[t].y = C.val[k];
+        }
+      }
+      if ((int)u.size() > kMaxGroupEntries) {
+        *err = "stokes: a group has more entries than the LSGS kernel takes";
+        return false;
+      }
+      u.push_back((int)pair_vals.size());  // index of the values, after the entries
+      pair_vals.push_back(uv);
+      pu = pair_union.emplace(key, u).first;
+    }
+    const std::vector<int>& u = pu->second;
+    const int len = (int)u.size() - 1;
+    const std::vector<double2>& uv = pair_vals[u[len]];
+    lk.resize(len);
+    unsigned long long h = key * 0x9E3779B97F4A7C15ull;
+    auto mix = [&](double v) {
+      unsigned long long b;
+      std::memcpy(&b, &v, 8);
+      h = (h ^ b) * 0x9E3779B97F4A7C15ull;
+      h ^= h >> 29;
+    };
+    for (int t = 0; t < len; t++) {
+      lk[t] = Linv[sent_col(g, u[t], hx, hy)];
+      mix(lk[t]);
+    }
+    mix(Ninv[i]);
+    mix(Ninv[j]);
+    int id = -1;
+    std::vector<int2>& cand = seen[h];  // (first entry, length) of the classes with this hash
+    for (const int2 bl : cand) {
+      const int b = bl.x;
+      bool same = bl.y == len && nv[b].x == Ninv[i] && nv[b].y == Ninv[j];
+      for (int t = 0; t < len && same; t++)
+        same = ent[b + t] == u[t] && val[b + t].x == uv[t].x && val[b + t].y == uv[t].y && lv[b + t] == lk[t];
+      if (same) {
+        id = b;
+        break;
+      }
+    }
+    if (id < 0) {
+      id = (int)ent.size();
+      cand.push_back(make_int2(id, len));
+      for (int t = 0; t < len; t++) {
+        ent.push_back(u[t]);
+        val.push_back(uv[t]);
+        lv.push_back(lk[t]);
+        nv.push_back(t == 0 ? make_double2(Ninv[i], Ninv[j]) : make_double2(0.0, 0.0));
+      }
+    }
+    rec[q] = make_int4(i, j, id, id + len);
+  }
+  return true;
+}
 
 // Lanes of the one-workgroup sweep: group slot k of a phase goes to wave
 // k / kWG, its two rows to consecutive runs of kWLR lanes, and entry e of a
@@ -1298,7 +1428,28 @@ hipError_t build_level(Stokes* S, int l, bool finest, std::string* err) {
   }
   std::vector<int2> grp;
   colour_groups(n, grp, L.gph);
-  SCHK(up(S, &L.groups, grp));
+  {
+    std::vector<int4> rec;
+    std::vector<int> gent;
+    std::vector<double2> gval, gni;
+    std::vector<double> glv;
+    if (!build_group_classes(CA, L.geo, grp, Linv, Ninv, rec, gent, gval, glv, gni, err)) return hipErrorInvalidValue;
+    SCHK(up(S, &L.mgroups, rec));
+    SCHK(up(S, &L.g_ent, gent));
+    SCHK(up(S, &L.g_val, gval));
+    SCHK(up(S, &L.g_linv, glv));
+    SCHK(up(S, &L.g_ninv, gni));
+    if (S->fp32) {
+      auto f2 = [](const std::vector<double2>& v) {
+        std::vector<float2> o(v.size());
+        for (size_t t = 0; t < v.size(); t++) o[t] = make_float2((float)v[t].x, (float)v[t].y);
+        return o;
+      };
+      SCHK(up(S, &L.g_val32, f2(gval)));
+      SCHK(up(S, &L.g_ninv32, f2(gni)));
+      SCHK(up(S, &L.g_linv32, to32(glv)));
+    }
+  }
   if (S->wg_sweep && (S->smoother == MG_LSGS || S->smoother == MG_SLSGS)) SCHK(build_wg_phases(S, L, A, grp));
   // patches of the patch smoother
   if (S->smoother == MG_VANKA) {
@@ -1385,6 +1536,9 @@ struct SV<double> {
   static const double* Linv(StokesLevel& L) { return L.Linv; }
   static const double* Ninv(StokesLevel& L) { return L.Ninv; }
   static const double* W(StokesLevel& L) { return L.w_val; }
+  static const double2* G(StokesLevel& L) { return L.g_val; }
+  static const double* GL(StokesLevel& L) { return L.g_linv; }
+  static const double2* GN(StokesLevel& L) { return L.g_ninv; }
 };
 template <>
 struct SV<float> {
@@ -1398,6 +1552,9 @@ struct SV<float> {
   static const float* Linv(StokesLevel& L) { return L.Linv32; }
   static const float* Ninv(StokesLevel& L) { return L.Ninv32; }
   static const float* W(StokesLevel& L) { return L.w_val32; }
+  static const float2* G(StokesLevel& L) { return L.g_val32; }
+  static const float* GL(StokesLevel& L) { return L.g_linv32; }
+  static const float2* GN(StokesLevel& L) { return L.g_ninv32; }
 };
 
 // A of level L by stencil classes; the transfers P (from level l-1) and R (to it) as CSR
@@ -1447,8 +1604,9 @@ hipError_t s_smooth(Stokes* S, StokesLevel& L, T* x, T* r, int steps, hipStream_
           for (int k = 0; k < nph; k++) {
             const int ph = sw == 0 ? k : nph - 1 - k;
             const int g0 = L.gph[ph], ng = L.gph[ph + 1] - g0;
-            hipLaunchKernelGGL((ks_lsgs<T, ClassRows<T>>), dim3(blocks_for(ng, kSNT / 64 * kGroups)), dim3(kSNT), 0, s, g0, ng,
-                               (const int2*)L.groups, A, SV<T>::Linv(L), SV<T>::Ninv(L), x, r);
+            hipLaunchKernelGGL((ks_lsgs_grp<T>), dim3(blocks_for(ng, kSNT / kGLR)), dim3(kSNT), 0, s, g0, ng,
+                               (const int4*)L.mgroups, (const int*)L.g_ent, SV<T>::G(L), SV<T>::GL(L), SV<T>::GN(L),
+                               L.geo, x, r);
           }
         break;
       }
