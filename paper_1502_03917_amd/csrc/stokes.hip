@@ -989,30 +989,49 @@ __global__ __launch_bounds__(kWT) void ks_lsgs_wg(int ndof, int nph, int nseq, i
   }
 }
 
+// value of lane u (u uniform), read as scalars: independent of the exec mask
+__device__ inline double bcast(double v, int u) {
+  const unsigned long long b = __builtin_bit_cast(unsigned long long, v);
+  const unsigned lo = __builtin_amdgcn_readlane((unsigned)b, u), hi = __builtin_amdgcn_readlane((unsigned)(b >> 32), u);
+  return __builtin_bit_cast(double, (unsigned long long)lo | ((unsigned long long)hi << 32));
+}
+__device__ inline float bcast(float v, int u) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(unsigned, v), u));
+}
+
 // One colour phase of the patch smoother: x_P += tau A_PP^-1 r_P,
-// r -= tau A_{:,P} A_PP^-1 r_P, with the LU factors of A_PP (row-major,
-// FP64) and the row permutation of its pivoting.  One wave per patch: lane c
-// keeps column c of the factors in registers and entry c of the vector; the
-// substitutions reduce over the wave; the patch rows are then subtracted from
-// r one after the other (rows of one patch share entries of r).
-template <typename T, typename AT>
+// r -= tau A_{:,P} A_PP^-1 r_P.  Patches (one per vertex) come in patch
+// classes: patches whose unknowns sit at the same lattice offsets from the
+// vertex and whose rows agree share the LU factors of A_PP (row-major, FP64,
+// with the row permutation of the pivoting) and the union U of their rows'
+// columns with the dense block A_{P,U} (stored [u][k]).  Class record:
+// (m, first unknown code, first LU entry, first union code), (|U|, first
+// coefficient).  One wave per patch: lane c keeps column c of the factors in
+// registers and entry c of the vector; the substitutions reduce over the
+// wave.  Patches of one colour share no residual entry, so each lane gathers
+// its union entries of r once and writes r_k - sum_u A_uk du_u once (du_u
+// broadcast from lane u by a scalar read).
+template <typename T>
 __global__ __launch_bounds__(kSNT) void ks_vanka(int p0, int npatch, const int* __restrict__ order,
-                                                 const int* __restrict__ dptr, const int* __restrict__ dof,
-                                                 const long long* __restrict__ luptr, const double* __restrict__ lu,
-                                                 const int* __restrict__ perm, AT A, double tau,
-                                                 T* __restrict__ x, T* __restrict__ r) {
+                                                 const int* __restrict__ pcls, const int4* __restrict__ cinfo,
+                                                 const int2* __restrict__ cun, const int* __restrict__ pcode,
+                                                 const int* __restrict__ perm, const double* __restrict__ lu,
+                                                 const int* __restrict__ ucode, const T* __restrict__ coef,
+                                                 SGeo geo, double tau, T* __restrict__ x, T* __restrict__ r) {
   const int t = blockIdx.x * (kSNT / 64) + threadIdx.x / 64;
   if (t >= npatch) return;  // uniform per wave
   const int c = threadIdx.x % 64;
   const int q = order[p0 + t];
-  const int b = dptr[q], m = dptr[q + 1] - b;
-  const double* a = lu + luptr[q];
+  const int4 ci = cinfo[pcls[q]];
+  const int2 cu = cun[pcls[q]];
+  const int m = ci.x, hx = 2 * (q % (geo.n + 1)), hy = 2 * (q / (geo.n + 1));
   const bool on = c < m;
+  const double* a = lu + ci.z;
   double acol[kMaxPatch];
 #pragma unroll
   for (int i = 0; i < kMaxPatch; i++) acol[i] = (on && i < m) ? a[i * m + c] : 0.0;
   // permuted right-hand side: entry c = r at the patch unknown perm[c]
-  double y = on ? (double)r[dof[b + perm[b + c]]] : 0.0;
+  double y = on ? (double)r[sent_col(geo, pcode[ci.y + perm[ci.y + c]], hx, hy)] : 0.0;
   // forward substitution with the unit lower factor (rows i >= m are inert)
 #pragma unroll
   for (int i = 1; i < kMaxPatch; i++) {
@@ -1030,15 +1049,23 @@ __global__ __launch_bounds__(kSNT) void ks_vanka(int p0, int npatch, const int* 
     const double di = __shfl(acol[i], i, 64);  // diagonal entry a_ii (held by lane i)
     if (c == i && i < m) y = (y - v) / di;
   }
-  const T du = (T)(tau * y);
-  if (on) x[dof[b + c]] += du;
-  for (int u = 0; u < m; u++) {
-    const T d = __shfl(du, u, 64);
-    const int i = dof[b + u];
-    int kb, ke, pos;
-    A.row(i, kb, ke, pos);
-    for (int k = kb + c; k < ke; k += 64) r[A.col_of(k, pos)] -= A.val_of(k) * d;
-    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+  const T du = on ? (T)(tau * y) : (T)0;
+  if (on) x[sent_col(geo, pcode[ci.y + c], hx, hy)] += du;
+  // union entries c and c + 64 of U: loads at clamped indices (a lane past
+  // |U| stores nothing), coefficients of unknowns u >= m meet du_u = 0
+  const int nu = cu.x;
+#pragma unroll
+  for (int sl = 0; sl < 2; sl++) {
+    const int k = c + 64 * sl, kk = k < nu ? k : nu - 1;
+    const int col = sent_col(geo, ucode[ci.w + kk], hx, hy);
+    const T rk = r[col];
+    T upd = 0;
+#pragma unroll
+    for (int u = 0; u < kMaxPatch; u++) {
+      const T d = bcast(du, u);
+      upd += coef[cu.y + (u < m ? u : m - 1) * nu + kk] * d;
+    }
+    if (k < nu) r[col] = rk - upd;
   }
 }
 
@@ -1181,9 +1208,13 @@ struct StokesLevel {
   double* w_val = nullptr;
   float* w_val32 = nullptr;
   // patch smoother: patches (one per vertex) ordered by colour, phase spans vph
-  int *v_order = nullptr, *v_dptr = nullptr, *v_dof = nullptr, *v_piv = nullptr;
-  long long* v_luptr = nullptr;
-  double* v_lu = nullptr;
+  // patch smoother: patches (one per vertex) ordered by colour, phase spans vph;
+  // patch classes (see ks_vanka)
+  int *v_order = nullptr, *v_cls = nullptr, *v_code = nullptr, *v_perm = nullptr, *v_ucode = nullptr;
+  int4* v_info = nullptr;
+  int2* v_un = nullptr;
+  double *v_lu = nullptr, *v_coef = nullptr;
+  float* v_coef32 = nullptr;
   std::vector<int> vph;
   // pressure-mean weights
   double* w = nullptr;
@@ -1234,6 +1265,109 @@ hipError_t zalloc(Stokes* S, T** d, size_t n) {
   } while (0)
 
 std::vector<float> to32(const std::vector<double>& v) { return std::vector<float>(v.begin(), v.end()); }
+
+// Patch classes (see ks_vanka) from the per-patch unknowns, pivots and LU
+// factors: the class key is the whole record (unknown offsets, permutation,
+// factors, union offsets and coefficients), looked up by hash and compared
+// in full.
+struct PatchClasses {
+  std::vector<int> cls, code, perm, ucode;
+  std::vector<int4> info;
+  std::vector<int2> un;
+  std::vector<double> lu, coef;
+};
+bool build_patch_classes(const HCsr& A, const SGeo& g, const std::vector<int>& dptr, const std::vector<int>& dof,
+                         const std::vector<int>& piv, const std::vector<long long>& luptr,
+                         const std::vector<double>& lu, PatchClasses& P, std::string* err) {
+  const int np = (int)dptr.size() - 1;
+  std::unordered_map<unsigned long long, std::vector<int>> seen;
+  P.cls.assign(np, 0);
+  std::vector<int> code, ucode;
+  std::vector<double> coef;
+  std::unordered_map<int, int> upos;
+  auto enc = [&](int i, int hx, int hy, int& e) {
+    int cx, cy;
+    spos(g, i, cx, cy);
+    const int dx = cx - hx, dy = cy - hy;
+    if (dx < -kEntOff || dx >= 256 - kEntOff || dy < -kEntOff || dy >= 256 - kEntOff) return false;
+    e = sfield(g, i) | ((dx + kEntOff) << 8) | ((dy + kEntOff) << 16);
+    return sent_col(g, e, hx, hy) == i;
+  };
+  for (int q = 0; q < np; q++) {
+    const int b = dptr[q], m = dptr[q + 1] - b;
+    const int hx = 2 * (q % (g.n + 1)), hy = 2 * (q / (g.n + 1));
+    code.resize(m);
+    ucode.clear();
+    upos.clear();
+    bool ok = true;
+    for (int u = 0; u < m && ok; u++) ok = enc(dof[b + u], hx, hy, code[u]);
+    for (int u = 0; u < m && ok; u++)
+      for (int k = A.rp[dof[b + u]]; k < A.rp[dof[b + u] + 1] && ok; k++)
+        if (!upos.count(A.col[k])) {
+          int e;
+          ok = enc(A.col[k], hx, hy, e);
+          upos[A.col[k]] = (int)ucode.size();
+          ucode.push_back(e);
+        }
+    if (!ok) {
+      *err = "stokes: a patch unknown or column is not a lattice offset of its vertex";
+      return false;
+    }
+    const int nu = (int)ucode.size();
+    if (nu > 128) {
+      *err = "stokes: a patch couples to more than 128 unknowns";
+      return false;
+    }
+    coef.assign((size_t)m * nu, 0.0);
+    for (int u = 0; u < m; u++)
+      for (int k = A.rp[dof[b + u]]; k < A.rp[dof[b + u] + 1]; k++) coef[(size_t)u * nu + upos[A.col[k]]] = A.val[k];
+    const double* f = lu.data() + luptr[q];
+    unsigned long long h = 0x243F6A8885A308D3ull;
+    auto mix = [&](unsigned long long v) {
+      h = (h ^ v) * 0x9E3779B97F4A7C15ull;
+      h ^= h >> 29;
+    };
+    auto mixd = [&](double v) {
+      unsigned long long bb;
+      std::memcpy(&bb, &v, 8);
+      mix(bb);
+    };
+    mix((unsigned)m);
+    mix((unsigned)nu);
+    for (int u = 0; u < m; u++) mix(((unsigned long long)(unsigned)code[u] << 32) | (unsigned)piv[b + u]);
+    for (int k = 0; k < nu; k++) mix((unsigned)ucode[k]);
+    for (int k = 0; k < m * m; k++) mixd(f[k]);
+    for (double v : coef) mixd(v);
+    int id = -1;
+    for (int c : seen[h]) {
+      const int4 ci = P.info[c];
+      const int2 cu = P.un[c];
+      if (ci.x != m || cu.x != nu) continue;
+      bool same = std::equal(code.begin(), code.end(), P.code.begin() + ci.y) &&
+                  std::equal(piv.begin() + b, piv.begin() + b + m, P.perm.begin() + ci.y) &&
+                  std::equal(f, f + (size_t)m * m, P.lu.begin() + ci.z) &&
+                  std::equal(ucode.begin(), ucode.end(), P.ucode.begin() + ci.w) &&
+                  std::equal(coef.begin(), coef.end(), P.coef.begin() + cu.y);
+      if (same) {
+        id = c;
+        break;
+      }
+    }
+    if (id < 0) {
+      id = (int)P.info.size();
+      seen[h].push_back(id);
+      P.info.push_back(make_int4(m, (int)P.code.size(), (int)P.lu.size(), (int)P.ucode.size()));
+      P.un.push_back(make_int2(nu, (int)P.coef.size()));
+      P.code.insert(P.code.end(), code.begin(), code.end());
+      P.perm.insert(P.perm.end(), piv.begin() + b, piv.begin() + b + m);
+      P.lu.insert(P.lu.end(), f, f + (size_t)m * m);
+      P.ucode.insert(P.ucode.end(), ucode.begin(), ucode.end());
+      P.coef.insert(P.coef.end(), coef.begin(), coef.end());
+    }
+    P.cls[q] = id;
+  }
+  return true;
+}
 
 // Merged groups (see ks_lsgs_grp): entries of row i in its order, then those
 // of row j that row i lacks.  Both unknowns of a group sit at one lattice
@@ -1457,12 +1591,18 @@ hipError_t build_level(Stokes* S, int l, bool finest, std::string* err) {
     std::vector<long long> luptr;
     std::vector<double> lu;
     if (!build_patches(n, A, dptr, dof, piv, luptr, lu, order, L.vph, err)) return hipErrorInvalidValue;
+    PatchClasses P;
+    if (!build_patch_classes(A, L.geo, dptr, dof, piv, luptr, lu, P, err)) return hipErrorInvalidValue;
     SCHK(up(S, &L.v_order, order));
-    SCHK(up(S, &L.v_dptr, dptr));
-    SCHK(up(S, &L.v_dof, dof));
-    SCHK(up(S, &L.v_piv, piv));
-    SCHK(up(S, &L.v_luptr, luptr));
-    SCHK(up(S, &L.v_lu, lu));
+    SCHK(up(S, &L.v_cls, P.cls));
+    SCHK(up(S, &L.v_info, P.info));
+    SCHK(up(S, &L.v_un, P.un));
+    SCHK(up(S, &L.v_code, P.code));
+    SCHK(up(S, &L.v_perm, P.perm));
+    SCHK(up(S, &L.v_lu, P.lu));
+    SCHK(up(S, &L.v_ucode, P.ucode));
+    SCHK(up(S, &L.v_coef, P.coef));
+    if (S->fp32) SCHK(up(S, &L.v_coef32, to32(P.coef)));
   }
   // transfers from / to level l-1
   if (l > S->k0) {
@@ -1537,6 +1677,7 @@ struct SV<double> {
   static const double* Ninv(StokesLevel& L) { return L.Ninv; }
   static const double* W(StokesLevel& L) { return L.w_val; }
   static const double2* G(StokesLevel& L) { return L.g_val; }
+  static const double* VC(StokesLevel& L) { return L.v_coef; }
   static const double* GL(StokesLevel& L) { return L.g_linv; }
   static const double2* GN(StokesLevel& L) { return L.g_ninv; }
 };
@@ -1553,6 +1694,7 @@ struct SV<float> {
   static const float* Ninv(StokesLevel& L) { return L.Ninv32; }
   static const float* W(StokesLevel& L) { return L.w_val32; }
   static const float2* G(StokesLevel& L) { return L.g_val32; }
+  static const float* VC(StokesLevel& L) { return L.v_coef32; }
   static const float* GL(StokesLevel& L) { return L.g_linv32; }
   static const float2* GN(StokesLevel& L) { return L.g_ninv32; }
 };
@@ -1613,8 +1755,10 @@ hipError_t s_smooth(Stokes* S, StokesLevel& L, T* x, T* r, int steps, hipStream_
       case MG_VANKA:
         for (int ph = 0; ph + 1 < (int)L.vph.size(); ph++) {
           const int p0 = L.vph[ph], npch = L.vph[ph + 1] - p0;
-          hipLaunchKernelGGL((ks_vanka<T, ClassRows<T>>), dim3(blocks_for(npch, kSNT / 64)), dim3(kSNT), 0, s, p0,
-                             npch, L.v_order, L.v_dptr, L.v_dof, L.v_luptr, L.v_lu, L.v_piv, A, S->tau, x, r);
+          hipLaunchKernelGGL((ks_vanka<T>), dim3(blocks_for(npch, kSNT / 64)), dim3(kSNT), 0, s, p0, npch,
+                             (const int*)L.v_order, (const int*)L.v_cls, (const int4*)L.v_info, (const int2*)L.v_un,
+                             (const int*)L.v_code, (const int*)L.v_perm, (const double*)L.v_lu,
+                             (const int*)L.v_ucode, SV<T>::VC(L), L.geo, S->tau, x, r);
         }
         break;
     }
