@@ -1006,9 +1006,9 @@ __device__ inline float bcast(float v, int u) {
 // with the row permutation of the pivoting) and the union U of their rows'
 // columns with the dense block A_{P,U} (stored [u][k]).  Class record:
 // (m, first unknown code, first LU entry, first union code), (|U|, first
-// coefficient).  One wave per patch: lane c keeps column c of the factors in
-// registers and entry c of the vector; the substitutions reduce over the
-// wave.  Patches of one colour share no residual entry, so each lane gathers
+// coefficient).  One wave per patch: lane c keeps row c of the factors in
+// registers and entry c of the vector; the substitutions go by columns, each
+// finished entry broadcast by a scalar read.  Patches of one colour share no residual entry, so each lane gathers
 // its union entries of r once and writes r_k - sum_u A_uk du_u once (du_u
 // broadcast from lane u by a scalar read).
 template <typename T>
@@ -1027,27 +1027,29 @@ __global__ __launch_bounds__(kSNT) void ks_vanka(int p0, int npatch, const int* 
   const int m = ci.x, hx = 2 * (q % (geo.n + 1)), hy = 2 * (q / (geo.n + 1));
   const bool on = c < m;
   const double* a = lu + ci.z;
-  double acol[kMaxPatch];
+  double arow[kMaxPatch];  // row c of the factors
 #pragma unroll
-  for (int i = 0; i < kMaxPatch; i++) acol[i] = (on && i < m) ? a[i * m + c] : 0.0;
+  for (int j = 0; j < kMaxPatch; j++) arow[j] = (on && j < m) ? a[c * m + j] : 0.0;
   // permuted right-hand side: entry c = r at the patch unknown perm[c]
   double y = on ? (double)r[sent_col(geo, pcode[ci.y + perm[ci.y + c]], hx, hy)] : 0.0;
-  // forward substitution with the unit lower factor (rows i >= m are inert)
+  // forward substitution with the unit lower factor, by columns: y_j is
+  // final once columns < j are done; it is broadcast and the rows below
+  // subtract L_cj y_j (m is uniform per wave)
 #pragma unroll
-  for (int i = 1; i < kMaxPatch; i++) {
-    double v = (c < i && i < m) ? acol[i] * y : 0.0;
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-    if (c == i && i < m) y -= v;
+  for (int j = 0; j + 1 < kMaxPatch; j++) {
+    if (j + 1 < m) {
+      const double yj = bcast(y, j);
+      if (c > j) y -= arow[j] * yj;
+    }
   }
-  // back substitution with the upper factor
+  // back substitution with the upper factor, by columns from the last
 #pragma unroll
-  for (int i = kMaxPatch - 1; i >= 0; i--) {
-    double v = (c > i && c < m && i < m) ? acol[i] * y : 0.0;
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-    const double di = __shfl(acol[i], i, 64);  // diagonal entry a_ii (held by lane i)
-    if (c == i && i < m) y = (y - v) / di;
+  for (int j = kMaxPatch - 1; j >= 0; j--) {
+    if (j < m) {
+      if (c == j) y /= arow[j];
+      const double yj = bcast(y, j);
+      if (c < j) y -= arow[j] * yj;
+    }
   }
   const T du = on ? (T)(tau * y) : (T)0;
   if (on) x[sent_col(geo, pcode[ci.y + c], hx, hy)] += du;
