@@ -1012,18 +1012,19 @@ __device__ inline float bcast(float v, int u) {
 // its union entries of r once and writes r_k - sum_u A_uk du_u once (du_u
 // broadcast from lane u by a scalar read).
 template <typename T>
-__global__ __launch_bounds__(kSNT) void ks_vanka(int p0, int npatch, const int* __restrict__ order,
-                                                 const int* __restrict__ pcls, const int4* __restrict__ cinfo,
-                                                 const int2* __restrict__ cun, const int* __restrict__ pcode,
+__global__ __launch_bounds__(kSNT) void ks_vanka(int p0, int npatch, const int2* __restrict__ order,
+                                                 const int4* __restrict__ cinfo, const int2* __restrict__ cun,
+                                                 const int* __restrict__ pcode,
                                                  const int* __restrict__ perm, const double* __restrict__ lu,
                                                  const int* __restrict__ ucode, const T* __restrict__ coef,
                                                  SGeo geo, double tau, T* __restrict__ x, T* __restrict__ r) {
   const int t = blockIdx.x * (kSNT / 64) + threadIdx.x / 64;
   if (t >= npatch) return;  // uniform per wave
   const int c = threadIdx.x % 64;
-  const int q = order[p0 + t];
-  const int4 ci = cinfo[pcls[q]];
-  const int2 cu = cun[pcls[q]];
+  const int2 qc = order[p0 + t];  // (vertex, patch class)
+  const int q = qc.x;
+  const int4 ci = cinfo[qc.y];
+  const int2 cu = cun[qc.y];
   const int m = ci.x, hx = 2 * (q % (geo.n + 1)), hy = 2 * (q / (geo.n + 1));
   const bool on = c < m;
   const double* a = lu + ci.z;
@@ -1212,7 +1213,8 @@ struct StokesLevel {
   // patch smoother: patches (one per vertex) ordered by colour, phase spans vph
   // patch smoother: patches (one per vertex) ordered by colour, phase spans vph;
   // patch classes (see ks_vanka)
-  int *v_order = nullptr, *v_cls = nullptr, *v_code = nullptr, *v_perm = nullptr, *v_ucode = nullptr;
+  int2* v_order = nullptr;  // (vertex, patch class) in colour order
+  int *v_code = nullptr, *v_perm = nullptr, *v_ucode = nullptr;
   int4* v_info = nullptr;
   int2* v_un = nullptr;
   double *v_lu = nullptr, *v_coef = nullptr;
@@ -1595,8 +1597,9 @@ hipError_t build_level(Stokes* S, int l, bool finest, std::string* err) {
     if (!build_patches(n, A, dptr, dof, piv, luptr, lu, order, L.vph, err)) return hipErrorInvalidValue;
     PatchClasses P;
     if (!build_patch_classes(A, L.geo, dptr, dof, piv, luptr, lu, P, err)) return hipErrorInvalidValue;
-    SCHK(up(S, &L.v_order, order));
-    SCHK(up(S, &L.v_cls, P.cls));
+    std::vector<int2> oc(order.size());
+    for (size_t t = 0; t < order.size(); t++) oc[t] = make_int2(order[t], P.cls[order[t]]);
+    SCHK(up(S, &L.v_order, oc));
     SCHK(up(S, &L.v_info, P.info));
     SCHK(up(S, &L.v_un, P.un));
     SCHK(up(S, &L.v_code, P.code));
@@ -1758,7 +1761,7 @@ hipError_t s_smooth(Stokes* S, StokesLevel& L, T* x, T* r, int steps, hipStream_
         for (int ph = 0; ph + 1 < (int)L.vph.size(); ph++) {
           const int p0 = L.vph[ph], npch = L.vph[ph + 1] - p0;
           hipLaunchKernelGGL((ks_vanka<T>), dim3(blocks_for(npch, kSNT / 64)), dim3(kSNT), 0, s, p0, npch,
-                             (const int*)L.v_order, (const int*)L.v_cls, (const int4*)L.v_info, (const int2*)L.v_un,
+                             (const int2*)L.v_order, (const int4*)L.v_info, (const int2*)L.v_un,
                              (const int*)L.v_code, (const int*)L.v_perm, (const double*)L.v_lu,
                              (const int*)L.v_ucode, SV<T>::VC(L), L.geo, S->tau, x, r);
         }
