@@ -509,20 +509,15 @@ void colour_groups(int n, std::vector<int2>& grp, std::vector<int>& ph) {
   }
 }
 
-// Patches of the patch smoother (one per vertex) with the LU factors of their
-// matrices and the row permutation of the pivoting (piv[dptr[q] + k] = the
-// patch row that ends in position k); patches listed by colour
+// Patches of the patch smoother (one per vertex): the unknowns of patch q
+// are dof[dptr[q] .. dptr[q+1]); patches listed by colour
 // (i mod 3) + 3 (j mod 3), phase k spans order[ph[k] .. ph[k+1]).
-bool build_patches(int n, const HCsr& A, std::vector<int>& dptr, std::vector<int>& dof, std::vector<int>& piv,
-                   std::vector<long long>& luptr, std::vector<double>& lu, std::vector<int>& order,
+bool build_patches(int n, std::vector<int>& dptr, std::vector<int>& dof, std::vector<int>& order,
                    std::vector<int>& ph, std::string* err) {
   const int m = 2 * n - 1, nv = m * m, np = (n + 1) * (n + 1);
   const int op = 2 * nv, ol = 2 * nv + np, om = 4 * nv + np;
   dptr.assign(np + 1, 0);
-  luptr.assign(np + 1, 0);
   dof.clear();
-  piv.clear();
-  lu.clear();
   order.clear();
   auto vel = [&](int node, std::vector<int>& d) {
     d.push_back(node);
@@ -563,27 +558,8 @@ bool build_patches(int n, const HCsr& A, std::vector<int>& dptr, std::vector<int
         *err = "stokes: patch larger than 30 unknowns";
         return false;
       }
-      std::vector<double> a((size_t)msz * msz);
-      for (int u = 0; u < msz; u++)
-        for (int v = 0; v < msz; v++) a[(size_t)u * msz + v] = entry(A, d[u], d[v]);
-      std::vector<int> pv;
-      bool ok;
-      lu_dense(msz, a, pv, ok);
-      if (!ok) {
-        *err = "stokes: singular patch matrix";
-        return false;
-      }
-      // the row swaps of the factorisation as one permutation: after them,
-      // position k holds the entry that started at pm[k]
-      std::vector<int> pm(msz);
-      for (int k = 0; k < msz; k++) pm[k] = k;
-      for (int k = 0; k < msz; k++) std::swap(pm[k], pm[pv[k]]);
-      pv = pm;
       dptr[q + 1] = dptr[q] + msz;
-      luptr[q + 1] = luptr[q] + (long long)msz * msz;
       dof.insert(dof.end(), d.begin(), d.end());
-      piv.insert(piv.end(), pv.begin(), pv.end());
-      lu.insert(lu.end(), a.begin(), a.end());
     }
   ph.assign(1, 0);
   for (int col = 0; col < 9; col++) {
@@ -1270,10 +1246,10 @@ hipError_t zalloc(Stokes* S, T** d, size_t n) {
 
 std::vector<float> to32(const std::vector<double>& v) { return std::vector<float>(v.begin(), v.end()); }
 
-// Patch classes (see ks_vanka) from the per-patch unknowns, pivots and LU
-// factors: the class key is the whole record (unknown offsets, permutation,
-// factors, union offsets and coefficients), looked up by hash and compared
-// in full.
+// Patch classes (see ks_vanka): the class key is the unknown offsets, the
+// union offsets and the coefficient block, looked up by hash and compared in
+// full; A_PP is a sub-block of the block, so the LU factors (partial
+// pivoting) are computed once per class.
 struct PatchClasses {
   std::vector<int> cls, code, perm, ucode;
   std::vector<int4> info;
@@ -1281,8 +1257,7 @@ struct PatchClasses {
   std::vector<double> lu, coef;
 };
 bool build_patch_classes(const HCsr& A, const SGeo& g, const std::vector<int>& dptr, const std::vector<int>& dof,
-                         const std::vector<int>& piv, const std::vector<long long>& luptr,
-                         const std::vector<double>& lu, PatchClasses& P, std::string* err) {
+                         PatchClasses& P, std::string* err) {
   const int np = (int)dptr.size() - 1;
   std::unordered_map<unsigned long long, std::vector<int>> seen;
   P.cls.assign(np, 0);
@@ -1325,7 +1300,6 @@ bool build_patch_classes(const HCsr& A, const SGeo& g, const std::vector<int>& d
     coef.assign((size_t)m * nu, 0.0);
     for (int u = 0; u < m; u++)
       for (int k = A.rp[dof[b + u]]; k < A.rp[dof[b + u] + 1]; k++) coef[(size_t)u * nu + upos[A.col[k]]] = A.val[k];
-    const double* f = lu.data() + luptr[q];
     unsigned long long h = 0x243F6A8885A308D3ull;
     auto mix = [&](unsigned long long v) {
       h = (h ^ v) * 0x9E3779B97F4A7C15ull;
@@ -1338,9 +1312,8 @@ bool build_patch_classes(const HCsr& A, const SGeo& g, const std::vector<int>& d
     };
     mix((unsigned)m);
     mix((unsigned)nu);
-    for (int u = 0; u < m; u++) mix(((unsigned long long)(unsigned)code[u] << 32) | (unsigned)piv[b + u]);
+    for (int u = 0; u < m; u++) mix((unsigned)code[u]);
     for (int k = 0; k < nu; k++) mix((unsigned)ucode[k]);
-    for (int k = 0; k < m * m; k++) mixd(f[k]);
     for (double v : coef) mixd(v);
     int id = -1;
     for (int c : seen[h]) {
@@ -1348,8 +1321,6 @@ bool build_patch_classes(const HCsr& A, const SGeo& g, const std::vector<int>& d
       const int2 cu = P.un[c];
       if (ci.x != m || cu.x != nu) continue;
       bool same = std::equal(code.begin(), code.end(), P.code.begin() + ci.y) &&
-                  std::equal(piv.begin() + b, piv.begin() + b + m, P.perm.begin() + ci.y) &&
-                  std::equal(f, f + (size_t)m * m, P.lu.begin() + ci.z) &&
                   std::equal(ucode.begin(), ucode.end(), P.ucode.begin() + ci.w) &&
                   std::equal(coef.begin(), coef.end(), P.coef.begin() + cu.y);
       if (same) {
@@ -1358,13 +1329,33 @@ bool build_patch_classes(const HCsr& A, const SGeo& g, const std::vector<int>& d
       }
     }
     if (id < 0) {
+      // A_PP from the block: A(d_u, d_v) is the coefficient at d_v's union
+      // position (zero where d_v is no column of any patch row)
+      std::vector<double> a((size_t)m * m, 0.0);
+      for (int v = 0; v < m; v++) {
+        auto it = upos.find(dof[b + v]);
+        if (it == upos.end()) continue;
+        for (int u = 0; u < m; u++) a[(size_t)u * m + v] = coef[(size_t)u * nu + it->second];
+      }
+      std::vector<int> pv;
+      bool okf;
+      lu_dense(m, a, pv, okf);
+      if (!okf) {
+        *err = "stokes: singular patch matrix";
+        return false;
+      }
+      // the row swaps of the factorisation as one permutation: after them,
+      // position k holds the entry that started at pm[k]
+      std::vector<int> pm(m);
+      for (int k = 0; k < m; k++) pm[k] = k;
+      for (int k = 0; k < m; k++) std::swap(pm[k], pm[pv[k]]);
       id = (int)P.info.size();
       seen[h].push_back(id);
       P.info.push_back(make_int4(m, (int)P.code.size(), (int)P.lu.size(), (int)P.ucode.size()));
       P.un.push_back(make_int2(nu, (int)P.coef.size()));
       P.code.insert(P.code.end(), code.begin(), code.end());
-      P.perm.insert(P.perm.end(), piv.begin() + b, piv.begin() + b + m);
-      P.lu.insert(P.lu.end(), f, f + (size_t)m * m);
+      P.perm.insert(P.perm.end(), pm.begin(), pm.end());
+      P.lu.insert(P.lu.end(), a.begin(), a.end());
       P.ucode.insert(P.ucode.end(), ucode.begin(), ucode.end());
       P.coef.insert(P.coef.end(), coef.begin(), coef.end());
     }
@@ -1591,12 +1582,10 @@ hipError_t build_level(Stokes* S, int l, bool finest, std::string* err) {
   if (S->wg_sweep && (S->smoother == MG_LSGS || S->smoother == MG_SLSGS)) SCHK(build_wg_phases(S, L, A, grp));
   // patches of the patch smoother
   if (S->smoother == MG_VANKA) {
-    std::vector<int> dptr, dof, piv, order;
-    std::vector<long long> luptr;
-    std::vector<double> lu;
-    if (!build_patches(n, A, dptr, dof, piv, luptr, lu, order, L.vph, err)) return hipErrorInvalidValue;
+    std::vector<int> dptr, dof, order;
+    if (!build_patches(n, dptr, dof, order, L.vph, err)) return hipErrorInvalidValue;
     PatchClasses P;
-    if (!build_patch_classes(A, L.geo, dptr, dof, piv, luptr, lu, P, err)) return hipErrorInvalidValue;
+    if (!build_patch_classes(A, L.geo, dptr, dof, P, err)) return hipErrorInvalidValue;
     std::vector<int2> oc(order.size());
     for (size_t t = 0; t < order.size(); t++) oc[t] = make_int2(order[t], P.cls[order[t]]);
     SCHK(up(S, &L.v_order, oc));
