@@ -982,9 +982,10 @@ __device__ inline float bcast(float v, int u) {
 // with the row permutation of the pivoting) and the union U of their rows'
 // columns with the dense block A_{P,U} (stored [u][k]).  Class record:
 // (m, first unknown code, first LU entry, first union code), (|U|, first
-// coefficient).  One wave per patch: lane c keeps row c of the factors in
-// registers and entry c of the vector; the substitutions go by columns, each
-// finished entry broadcast by a scalar read.  Patches of one colour share no residual entry, so each lane gathers
+// coefficient).  Two patches per wave (a patch has at most 30 unknowns),
+// one per half: lane c of a half keeps row c of the factors in registers and
+// entry c of the vector; the substitutions go by columns, each finished
+// entry broadcast by a scalar read.  Patches of one colour share no residual entry, so each lane gathers
 // its union entries of r once and writes r_k - sum_u A_uk du_u once (du_u
 // broadcast from lane u by a scalar read).
 template <typename T>
@@ -994,15 +995,22 @@ __global__ __launch_bounds__(kSNT) void ks_vanka(int p0, int npatch, const int2*
                                                  const int* __restrict__ perm, const double* __restrict__ lu,
                                                  const int* __restrict__ ucode, const T* __restrict__ coef,
                                                  SGeo geo, double tau, T* __restrict__ x, T* __restrict__ r) {
-  const int t = blockIdx.x * (kSNT / 64) + threadIdx.x / 64;
-  if (t >= npatch) return;  // uniform per wave
-  const int c = threadIdx.x % 64;
-  const int2 qc = order[p0 + t];  // (vertex, patch class)
+  const int w = blockIdx.x * (kSNT / 64) + threadIdx.x / 64;
+  if (2 * w >= npatch) return;  // uniform per wave
+  const int h = (threadIdx.x % 64) / 32, c = threadIdx.x % 32;  // half-wave h takes patch 2w + h
+  const int t = 2 * w + h;
+  const bool live = t < npatch;
+  const int2 qc = live ? order[p0 + t] : make_int2(0, 0);  // (vertex, patch class)
   const int q = qc.x;
   const int4 ci = cinfo[qc.y];
   const int2 cu = cun[qc.y];
-  const int m = ci.x, hx = 2 * (q % (geo.n + 1)), hy = 2 * (q / (geo.n + 1));
+  const int m = live ? ci.x : 0, hx = 2 * (q % (geo.n + 1)), hy = 2 * (q / (geo.n + 1));
   const bool on = c < m;
+  // entry j of this half's patch, broadcast from lane j of the half
+  auto bc = [&](double v, int j) {
+    const double v0 = bcast(v, j), v1 = bcast(v, 32 + j);
+    return h ? v1 : v0;
+  };
   const double* a = lu + ci.z;
   double arow[kMaxPatch];  // row c of the factors
 #pragma unroll
@@ -1011,40 +1019,36 @@ __global__ __launch_bounds__(kSNT) void ks_vanka(int p0, int npatch, const int2*
   double y = on ? (double)r[sent_col(geo, pcode[ci.y + perm[ci.y + c]], hx, hy)] : 0.0;
   // forward substitution with the unit lower factor, by columns: y_j is
   // final once columns < j are done; it is broadcast and the rows below
-  // subtract L_cj y_j (m is uniform per wave)
+  // subtract L_cj y_j
 #pragma unroll
   for (int j = 0; j + 1 < kMaxPatch; j++) {
-    if (j + 1 < m) {
-      const double yj = bcast(y, j);
-      if (c > j) y -= arow[j] * yj;
-    }
+    const double yj = bc(y, j);
+    if (c > j && j + 1 < m) y -= arow[j] * yj;
   }
   // back substitution with the upper factor, by columns from the last
 #pragma unroll
   for (int j = kMaxPatch - 1; j >= 0; j--) {
-    if (j < m) {
-      if (c == j) y /= arow[j];
-      const double yj = bcast(y, j);
-      if (c < j) y -= arow[j] * yj;
-    }
+    if (c == j && j < m) y /= arow[j];
+    const double yj = bc(y, j);
+    if (c < j && j < m) y -= arow[j] * yj;
   }
   const T du = on ? (T)(tau * y) : (T)0;
   if (on) x[sent_col(geo, pcode[ci.y + c], hx, hy)] += du;
-  // union entries c and c + 64 of U: loads at clamped indices (a lane past
-  // |U| stores nothing), coefficients of unknowns u >= m meet du_u = 0
-  const int nu = cu.x;
+  // union entries c, c + 32, c + 64 of U: loads at clamped indices (a lane
+  // past |U| stores nothing), coefficients of unknowns u >= m meet du_u = 0
+  const int nu = live ? cu.x : 1, mc = m > 0 ? m : 1;
 #pragma unroll
-  for (int sl = 0; sl < 2; sl++) {
-    const int k = c + 64 * sl, kk = k < nu ? k : nu - 1;
+  for (int sl = 0; sl < 3; sl++) {
+    const int k = c + 32 * sl, kk = k < nu ? k : nu - 1;
     const int col = sent_col(geo, ucode[ci.w + kk], hx, hy);
     const T rk = r[col];
     T upd = 0;
 #pragma unroll
     for (int u = 0; u < kMaxPatch; u++) {
-      const T d = bcast(du, u);
-      upd += coef[cu.y + (u < m ? u : m - 1) * nu + kk] * d;
+      const T d0 = bcast(du, u), d1 = bcast(du, 32 + u);
+      upd += coef[cu.y + (u < mc ? u : mc - 1) * nu + kk] * (h ? d1 : d0);
     }
-    if (k < nu) r[col] = rk - upd;
+    if (live && k < nu) r[col] = rk - upd;
   }
 }
 
@@ -1293,8 +1297,8 @@ bool build_patch_classes(const HCsr& A, const SGeo& g, const std::vector<int>& d
       return false;
     }
     const int nu = (int)ucode.size();
-    if (nu > 128) {
-      *err = "stokes: a patch couples to more than 128 unknowns";
+    if (nu > 96) {
+      *err = "stokes: a patch couples to more than 96 unknowns";
       return false;
     }
     coef.assign((size_t)m * nu, 0.0);
@@ -1749,7 +1753,7 @@ hipError_t s_smooth(Stokes* S, StokesLevel& L, T* x, T* r, int steps, hipStream_
       case MG_VANKA:
         for (int ph = 0; ph + 1 < (int)L.vph.size(); ph++) {
           const int p0 = L.vph[ph], npch = L.vph[ph + 1] - p0;
-          hipLaunchKernelGGL((ks_vanka<T>), dim3(blocks_for(npch, kSNT / 64)), dim3(kSNT), 0, s, p0, npch,
+          hipLaunchKernelGGL((ks_vanka<T>), dim3(blocks_for(npch, kSNT / 32)), dim3(kSNT), 0, s, p0, npch,
                              (const int2*)L.v_order, (const int4*)L.v_info, (const int2*)L.v_un,
                              (const int*)L.v_code, (const int*)L.v_perm, (const double*)L.v_lu,
                              (const int*)L.v_ucode, SV<T>::VC(L), L.geo, S->tau, x, r);
