@@ -980,8 +980,8 @@ __device__ inline float bcast(float v, int u) {
 // One colour phase of the patch smoother: x_P += tau A_PP^-1 r_P,
 // r -= tau A_{:,P} A_PP^-1 r_P.  Patches (one per vertex) come in patch
 // classes: patches whose unknowns sit at the same lattice offsets from the
-// vertex and whose rows agree share the LU factors of A_PP (row-major, FP64,
-// with the row permutation of the pivoting) and the union U of their rows'
+// vertex and whose rows agree share the LU factors of A_PP (row-major, FP64;
+// the unknown codes also in the row order of the pivoting) and the union U of their rows'
 // columns with the dense block A_{P,U} (stored [u][k]).  Class record:
 // (m, first unknown code, first LU entry, first union code), (|U|, first
 // coefficient).  Two patches per wave (a patch has at most 30 unknowns),
@@ -994,7 +994,7 @@ template <typename T>
 __global__ __launch_bounds__(kSNT) void ks_vanka(int p0, int npatch, const int2* __restrict__ order,
                                                  const int4* __restrict__ cinfo, const int2* __restrict__ cun,
                                                  const int* __restrict__ pcode,
-                                                 const int* __restrict__ perm, const double* __restrict__ lu,
+                                                 const int* __restrict__ pcodep, const double* __restrict__ lu,
                                                  const int* __restrict__ ucode, const T* __restrict__ coef,
                                                  SGeo geo, double tau, T* __restrict__ x, T* __restrict__ r) {
   const int w = blockIdx.x * (kSNT / 64) + threadIdx.x / 64;
@@ -1017,8 +1017,8 @@ __global__ __launch_bounds__(kSNT) void ks_vanka(int p0, int npatch, const int2*
   double arow[kMaxPatch];  // row c of the factors
 #pragma unroll
   for (int j = 0; j < kMaxPatch; j++) arow[j] = (on && j < m) ? a[c * m + j] : 0.0;
-  // permuted right-hand side: entry c = r at the patch unknown perm[c]
-  double y = on ? (double)r[sent_col(geo, pcode[ci.y + perm[ci.y + c]], hx, hy)] : 0.0;
+  // permuted right-hand side: entry c = r at the patch unknown in pivot position c
+  double y = on ? (double)r[sent_col(geo, pcodep[ci.y + c], hx, hy)] : 0.0;
   // forward substitution with the unit lower factor, by columns: y_j is
   // final once columns < j are done; it is broadcast and the rows below
   // subtract L_cj y_j
@@ -1196,7 +1196,7 @@ struct StokesLevel {
   // patch smoother: patches (one per vertex) ordered by colour, phase spans vph;
   // patch classes (see ks_vanka)
   int2* v_order = nullptr;  // (vertex, patch class) in colour order
-  int *v_code = nullptr, *v_perm = nullptr, *v_ucode = nullptr;
+  int *v_code = nullptr, *v_pcodep = nullptr, *v_ucode = nullptr;
   int4* v_info = nullptr;
   int2* v_un = nullptr;
   double *v_lu = nullptr, *v_coef = nullptr;
@@ -1257,7 +1257,7 @@ std::vector<float> to32(const std::vector<double>& v) { return std::vector<float
 // full; A_PP is a sub-block of the block, so the LU factors (partial
 // pivoting) are computed once per class.
 struct PatchClasses {
-  std::vector<int> cls, code, perm, ucode;
+  std::vector<int> cls, code, pcodep, ucode;  // pcodep: the unknown codes in pivot order
   std::vector<int4> info;
   std::vector<int2> un;
   std::vector<double> lu, coef;
@@ -1360,7 +1360,7 @@ bool build_patch_classes(const HCsr& A, const SGeo& g, const std::vector<int>& d
       P.info.push_back(make_int4(m, (int)P.code.size(), (int)P.lu.size(), (int)P.ucode.size()));
       P.un.push_back(make_int2(nu, (int)P.coef.size()));
       P.code.insert(P.code.end(), code.begin(), code.end());
-      P.perm.insert(P.perm.end(), pm.begin(), pm.end());
+      for (int k = 0; k < m; k++) P.pcodep.push_back(code[pm[k]]);
       P.lu.insert(P.lu.end(), a.begin(), a.end());
       P.ucode.insert(P.ucode.end(), ucode.begin(), ucode.end());
       P.coef.insert(P.coef.end(), coef.begin(), coef.end());
@@ -1598,7 +1598,7 @@ hipError_t build_level(Stokes* S, int l, bool finest, std::string* err) {
     SCHK(up(S, &L.v_info, P.info));
     SCHK(up(S, &L.v_un, P.un));
     SCHK(up(S, &L.v_code, P.code));
-    SCHK(up(S, &L.v_perm, P.perm));
+    SCHK(up(S, &L.v_pcodep, P.pcodep));
     SCHK(up(S, &L.v_lu, P.lu));
     SCHK(up(S, &L.v_ucode, P.ucode));
     SCHK(up(S, &L.v_coef, P.coef));
@@ -1757,7 +1757,7 @@ hipError_t s_smooth(Stokes* S, StokesLevel& L, T* x, T* r, int steps, hipStream_
           const int p0 = L.vph[ph], npch = L.vph[ph + 1] - p0;
           hipLaunchKernelGGL((ks_vanka<T>), dim3(blocks_for(npch, kSNT / 32)), dim3(kSNT), 0, s, p0, npch,
                              (const int2*)L.v_order, (const int4*)L.v_info, (const int2*)L.v_un,
-                             (const int*)L.v_code, (const int*)L.v_perm, (const double*)L.v_lu,
+                             (const int*)L.v_code, (const int*)L.v_pcodep, (const double*)L.v_lu,
                              (const int*)L.v_ucode, SV<T>::VC(L), L.geo, S->tau, x, r);
         }
         break;

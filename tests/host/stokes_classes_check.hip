@@ -102,7 +102,7 @@ static long check_patches(int n, const HCsr& A, const SGeo& g) {
     for (int k = 0; k < mm; k++) pm[k] = k;
     for (int k = 0; k < mm; k++) std::swap(pm[k], pm[pv[k]]);
     for (int u = 0; u < mm; u++)
-      if (sent_col(g, P.code[ci.y + u], hx, hy) != dof[b + u] || P.perm[ci.y + u] != pm[u]) bad++;
+      if (sent_col(g, P.code[ci.y + u], hx, hy) != dof[b + u] || sent_col(g, P.pcodep[ci.y + u], hx, hy) != dof[b + pm[u]]) bad++;
     for (int k = 0; k < mm * mm; k++)
       if (P.lu[ci.z + k] != a[k]) bad++;
     std::map<int, int> kofcol;
