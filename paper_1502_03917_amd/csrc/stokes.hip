@@ -980,8 +980,9 @@ __device__ inline float bcast(float v, int u) {
 // One colour phase of the patch smoother: x_P += tau A_PP^-1 r_P,
 // r -= tau A_{:,P} A_PP^-1 r_P.  Patches (one per vertex) come in patch
 // classes: patches whose unknowns sit at the same lattice offsets from the
-// vertex and whose rows agree share the LU factors of A_PP (row-major, FP64;
-// the unknown codes also in the row order of the pivoting) and the union U of their rows'
+// vertex and whose rows agree share the LU factors of A_PP (row-major, FP64,
+// then the reciprocals of U's diagonal; the unknown codes also in the row
+// order of the pivoting) and the union U of their rows'
 // columns with the dense block A_{P,U} (stored [u][k]).  Class record:
 // (m, first unknown code, first LU entry, first union code), (|U|, first
 // coefficient).  Two patches per wave (a patch has at most 30 unknowns),
@@ -1017,6 +1018,7 @@ __global__ __launch_bounds__(kSNT) void ks_vanka(int p0, int npatch, const int2*
   double arow[kMaxPatch];  // row c of the factors
 #pragma unroll
   for (int j = 0; j < kMaxPatch; j++) arow[j] = (on && j < m) ? a[c * m + j] : 0.0;
+  const double dinv = on ? a[m * m + c] : 0.0;  // 1 / u_cc
   // permuted right-hand side: entry c = r at the patch unknown in pivot position c
   double y = on ? (double)r[sent_col(geo, pcodep[ci.y + c], hx, hy)] : 0.0;
   // forward substitution with the unit lower factor, by columns: y_j is
@@ -1030,7 +1032,7 @@ __global__ __launch_bounds__(kSNT) void ks_vanka(int p0, int npatch, const int2*
   // back substitution with the upper factor, by columns from the last
 #pragma unroll
   for (int j = kMaxPatch - 1; j >= 0; j--) {
-    if (c == j && j < m) y /= arow[j];
+    if (c == j && j < m) y *= dinv;
     const double yj = bc(y, j);
     if (c < j && j < m) y -= arow[j] * yj;
   }
@@ -1362,6 +1364,7 @@ bool build_patch_classes(const HCsr& A, const SGeo& g, const std::vector<int>& d
       P.code.insert(P.code.end(), code.begin(), code.end());
       for (int k = 0; k < m; k++) P.pcodep.push_back(code[pm[k]]);
       P.lu.insert(P.lu.end(), a.begin(), a.end());
+      for (int k = 0; k < m; k++) P.lu.push_back(1.0 / a[(size_t)k * m + k]);  // 1 / u_kk after the factors
       P.ucode.insert(P.ucode.end(), ucode.begin(), ucode.end());
       P.coef.insert(P.coef.end(), coef.begin(), coef.end());
     }

@@ -105,6 +105,8 @@ static long check_patches(int n, const HCsr& A, const SGeo& g) {
       if (sent_col(g, P.code[ci.y + u], hx, hy) != dof[b + u] || sent_col(g, P.pcodep[ci.y + u], hx, hy) != dof[b + pm[u]]) bad++;
     for (int k = 0; k < mm * mm; k++)
       if (P.lu[ci.z + k] != a[k]) bad++;
+    for (int k = 0; k < mm; k++)
+      if (P.lu[ci.z + mm * mm + k] != 1.0 / a[(size_t)k * mm + k]) bad++;
     std::map<int, int> kofcol;
     for (int k = 0; k < cu.x; k++) {
       const int c = sent_col(g, P.ucode[ci.w + k], hx, hy);
