@@ -1041,19 +1041,28 @@ __global__ __launch_bounds__(kSNT) void ks_vanka(int p0, int npatch, const int2*
   // union entries c, c + 32, c + 64 of U: loads at clamped indices (a lane
   // past |U| stores nothing), coefficients of unknowns u >= m meet du_u = 0
   const int nu = live ? cu.x : 1, mc = m > 0 ? m : 1;
+  int col[3], kk[3];
+  T rk[3], upd[3];
 #pragma unroll
   for (int sl = 0; sl < 3; sl++) {
-    const int k = c + 32 * sl, kk = k < nu ? k : nu - 1;
-    const int col = sent_col(geo, ucode[ci.w + kk], hx, hy);
-    const T rk = r[col];
-    T upd = 0;
-#pragma unroll
-    for (int u = 0; u < kMaxPatch; u++) {
-      const T d0 = bcast(du, u), d1 = bcast(du, 32 + u);
-      upd += coef[cu.y + (u < mc ? u : mc - 1) * nu + kk] * (h ? d1 : d0);
-    }
-    if (live && k < nu) r[col] = rk - upd;
+    const int k = c + 32 * sl;
+    kk[sl] = k < nu ? k : nu - 1;
+    col[sl] = sent_col(geo, ucode[ci.w + kk[sl]], hx, hy);
+    rk[sl] = r[col[sl]];
+    upd[sl] = 0;
   }
+  // du_u broadcast once per u, used by the three slots (unrolled by 5: full
+  // unrolling hoists all 90 coefficient loads and needs 258 registers)
+#pragma unroll 5
+  for (int u = 0; u < kMaxPatch; u++) {
+    const T d0 = bcast(du, u), d1 = bcast(du, 32 + u), d = h ? d1 : d0;
+    const int row = cu.y + (u < mc ? u : mc - 1) * nu;
+#pragma unroll
+    for (int sl = 0; sl < 3; sl++) upd[sl] += coef[row + kk[sl]] * d;
+  }
+#pragma unroll
+  for (int sl = 0; sl < 3; sl++)
+    if (live && c + 32 * sl < nu) r[col[sl]] = rk[sl] - upd[sl];
 }
 
 // pressure and multiplier means: per-block partial sums of w.p and w.mu
