@@ -9,12 +9,33 @@
  *
  * on the unit square, P1 (Courant) elements on the uniform mesh with n = 2^k
  * cells per side, every square split along its (i,j)-(i+1,j+1) diagonal,
- * K_k = stiffness matrix of -Laplace(y) + y with natural boundary conditions.
+ * K_k = stiffness matrix of -Laplace(y) + y with natural boundary conditions;
+ * and of the Stokes-control KKT system of section 1 eq. mp3,
+ *
+ *      [ M_k    0     K_k        D_k^T ] [ v_k      ]   [ M_k v_D ]
+ *      [ 0      0     D_k        0     ] [ p_k      ] = [    0    ]
+ *      [ K_k  D_k^T  -alpha^-1 M_k  0  ] [ lambda_k ]   [    0    ]
+ *      [ D_k    0     0          0     ] [ mu_k     ]   [    0    ]
+ *
+ * with Taylor-Hood elements on the same mesh: P2 velocity and multiplier
+ * lambda (zero on the boundary; M_k, K_k the vector P2 mass and Laplacian
+ * stiffness matrices), P1 pressure p and multiplier mu, D_k the divergence
+ * (D_k q-row = -int q div phi).  The constant p and mu span the kernel of
+ * A_k: iterates are shifted to zero mean (weights int phi_q) after every
+ * finest-level iterate.
  *
  * Conventions shared by every entry point:
  *  - Vectors are contiguous FP64 arrays in DEVICE memory of the context's GPU.
- *    A level-l vector has 2 (2^l+1)^2 entries, field-major [ y | lambda ];
- *    vertex (i,j) (x = i h, y = j h) has index j (2^l+1) + i within a field.
+ *  - Poisson control: a level-l vector has 2 (2^l+1)^2 entries, field-major
+ *    [ y | lambda ]; vertex (i,j) (x = i h, y = j h, h = 2^-l) has index
+ *    j (2^l+1) + i within a field.
+ *  - Stokes control: a level-l vector (n = 2^l, m = 2n - 1) has
+ *    4 m^2 + 2 (n+1)^2 entries, field-major [ v1 | v2 | p | lambda1 | lambda2 | mu ]:
+ *    v1, v2, lambda1, lambda2 have one entry per interior P2 node, the node at
+ *    (a h/2, b h/2), 1 <= a, b <= m, at index (b-1) m + (a-1) within the field;
+ *    p and mu have one entry per vertex (i,j), index j (n+1) + i.  Field
+ *    offsets: v1 0, v2 m^2, p 2 m^2, lambda1 2 m^2 + (n+1)^2, lambda2
+ *    3 m^2 + (n+1)^2, mu 4 m^2 + (n+1)^2.
  *  - Caller-owned buffers are never freed, retained or resized by the library.
  *    The context owns its level workspace (allocated in mg_setup).
  *  - `stream` is a hipStream_t (NULL = default stream).  Work is enqueued in
@@ -65,7 +86,7 @@ typedef enum mg_status {
   MG_OK = 0,
   MG_EINVAL = -1,      /* invalid argument (checked before any HIP call)     */
   MG_EHIP = -2,        /* a HIP runtime call failed; see mg_last_error        */
-  MG_ENOMEM = -3,      /* device allocation failed                            */
+  MG_ENOMEM = -3,      /* device or host allocation failed                    */
   MG_ENOTCONV = -4,    /* max_cycles reached; x holds the last iterate        */
   MG_ENAN = -5,        /* non-finite residual norm                            */
   MG_EDIVERGE = -6,    /* residual grew above 1e3 times its initial value     */
@@ -88,7 +109,8 @@ typedef struct {
   int smoother;     /* mg_smoother; default MG_LSGS                                  */
   int nu1, nu2;     /* pre-/post-smoothing steps; default 2, 2 (section 3)           */
   int gamma;        /* recursive coarse iterates: 1 = V-cycle (default), 2 = W-cycle */
-  double tau;       /* NE damping; <= 0 selects 0.4 (Poisson) / 0.35 (Stokes), section 3 */
+  double tau;       /* NE / patch-smoother damping; <= 0 (default -1) selects section 3's
+                       0.4 (Poisson NE, Stokes patch smoother) or 0.35 (Stokes NE)      */
   int coarse_level; /* k0: level solved exactly by FP64 LU; 1..3, default 1           */
   int precision;    /* mg_precision; default MG_FP64                                */
   int max_cycles;   /* cap of mg_solve; default 200                                  */
@@ -100,27 +122,42 @@ typedef struct {
 mg_opts mg_default_opts(int problem);
 
 /* Build a solver context for level `level` (n = 2^level cells per side),
- * regularisation `alpha` (> 0, finite) and problem MG_POISSON.  opts may be
- * NULL (defaults).  Requires coarse_level+1 <= level <= 12.  Computes the
- * per-level stencil tables, the FP64 LU factors of the coarsest matrix and
- * allocates the level hierarchy on the current HIP device.
- * Errors: MG_EINVAL, MG_EUNSUPPORTED (problem), MG_ENOMEM, MG_EHIP. */
+ * regularisation `alpha` (> 0, finite) and problem MG_POISSON (eq. mp2) or
+ * MG_STOKES (eq. mp3), with the scaling L_k of section 2 (Poisson:
+ * diag(Q_k) = blockdiag(W, W / alpha), W = diag(M + alpha^1/2 K); Stokes:
+ * blockdiag(W^, P^, W^ / alpha, P^ / alpha), W^ = diag(M + alpha^1/2 K),
+ * P^ = alpha diag(D W^-1 D^T)) and one exact FP64 LU solve on the coarsest
+ * level of section 2's cycle.  opts may be NULL (defaults).
+ * Requires coarse_level+1 <= level <= 12 (Poisson) or <= 10 (Stokes: its
+ * host assembly uses 32-bit row pointers).  Computes the per-level stencil
+ * tables, the FP64 LU factors of the coarsest matrix and allocates the level
+ * hierarchy on the current HIP device; *out is NULL on every error.
+ * Errors: MG_EINVAL (argument), MG_EUNSUPPORTED (Stokes above level 10, the
+ * patch smoother for Poisson, the collective smoother or coarse_level > 2 for
+ * Stokes), MG_ENOMEM (device or host allocation), MG_EHIP. */
 int mg_setup(int level, double alpha, int problem, const mg_opts *opts, mg_ctx **out);
 
 /* Release the context and its device memory (NULL is allowed). */
 void mg_destroy(mg_ctx *ctx);
 
-/* Number of unknowns on the finest level, 2 (2^level+1)^2 (0 for NULL). */
+/* Number of unknowns on the finest level: 2 (2^level+1)^2 (Poisson) or
+ * 4 (2^(level+1)-1)^2 + 2 (2^level+1)^2 (Stokes); 0 for NULL. */
 size_t mg_vec_len(const mg_ctx *ctx);
 /* Number of unknowns on level l (0 if l is outside [coarse_level, level]). */
 size_t mg_level_len(const mg_ctx *ctx, int level);
 
-/* Read / replace the options (the level and alpha are fixed at setup). */
+/* Read / replace the options (the level, alpha and coarse_level are fixed at
+ * setup; for Stokes also the smoother and the precision).  mg_set_opts
+ * returns MG_EUNSUPPORTED for the problem / smoother pairs mg_setup rejects. */
 int mg_get_opts(const mg_ctx *ctx, mg_opts *out);
 int mg_set_opts(mg_ctx *ctx, const mg_opts *opts);
 
-/* f = (M_k y_D; 0): yd holds the nodal values of the desired state (V
- * entries), f the fine-level right-hand side (2V entries), eq. mp2. */
+/* Right-hand side of the finest level (device buffers, caller-owned).
+ * Poisson (eq. mp2): f = (M_k y_D; 0); yd holds the nodal values of the
+ * desired state ((2^l+1)^2 entries), f has 2 (2^l+1)^2 entries.
+ * Stokes (eq. mp3): f = (M_k v_D; 0; 0; 0); yd holds [ v_D1 | v_D2 ] at the
+ * interior P2 nodes (2 m^2 entries, the node order of the vector layout
+ * above), f has mg_vec_len entries. */
 int mg_rhs(mg_ctx *ctx, const double *yd, double *f, void *stream);
 
 /* Control u = alpha^-1 lambda recovered from a solution x = (y; lambda) of
@@ -142,7 +179,7 @@ int mg_control(mg_ctx *ctx, const double *x, double *u, void *stream);
 int mg_adjoint_grad(mg_ctx *ctx, const double *x, const double *xadj, double *grad_yd, double *grad_alpha,
                     void *stream);
 
-/* y = A_l x on level l (section 1, eq. mp2). */
+/* y = A_l x on level l (section 1: eq. mp2, or eq. mp3 for Stokes). */
 int mg_apply(mg_ctx *ctx, int level, const double *x, double *y, void *stream);
 
 /* r = f - A_l x on level l; if norm_out is not NULL the Euclidean norm of r
@@ -155,13 +192,17 @@ int mg_residual(mg_ctx *ctx, int level, const double *f, const double *x, double
 int mg_smooth(mg_ctx *ctx, int level, double *x, double *r, int steps, void *stream);
 
 /* f_c = I_l^{l-1} r: restriction = transpose of the canonical embedding, scale 1
- * (section 2); r on level l, f_c on level l-1, both fields. */
+ * (section 2); r on level l, f_c on level l-1, every field (Stokes: P2
+ * interpolation for v and lambda, P1 for p and mu). */
 int mg_restrict(mg_ctx *ctx, int level, const double *r, double *fc, void *stream);
 
-/* x += I_{l-1}^l x_c: canonical embedding (P1 interpolation), section 2. */
+/* x += I_{l-1}^l x_c: canonical embedding (P1 interpolation; Stokes: P2 for v
+ * and lambda, P1 for p and mu), section 2. */
 int mg_prolong_add(mg_ctx *ctx, int level, const double *xc, double *x, void *stream);
 
-/* x = A_{k0}^{-1} f on the coarsest level by FP64 LU with partial pivoting. */
+/* x = A_{k0}^{-1} f on the coarsest level by FP64 LU with partial pivoting
+ * (section 2; Stokes: LU of A_{k0} bordered by the two zero-mean constraints
+ * on p and mu). */
 int mg_coarse_solve(mg_ctx *ctx, const double *f, double *x, void *stream);
 
 /* One multigrid iterate on the finest level, in place on x (section 2):
@@ -192,8 +233,11 @@ int mg_capture_cycle(mg_ctx *ctx, const double *f, double *x, void *stream, mg_g
 int mg_graph_launch(mg_graph *graph, void *stream);
 void mg_graph_destroy(mg_graph *graph);
 
-/* Iterate from the initial guess in x until ||f - A x|| <= tol ||f|| in the
- * context's norm (mg_opts.norm).  cycles_out (may be NULL) receives the number
+/* Iterate section 2's multigrid cycle (or, with MG_FP32_IR, FP64 refinement
+ * steps around FP32 cycles) from the initial guess in x until
+ * ||f - A x|| <= tol ||f|| in the context's norm (mg_opts.norm; section 3
+ * stops on a reduction of the error in the L_k norm, whose dual on residuals
+ * is MG_NORM_LINV).  cycles_out (may be NULL) receives the number
  * of iterates done, relres_out (may be NULL) the final relative residual.
  * Synchronises on one norm per iterate.  Returns MG_OK, MG_ENOTCONV (x = last
  * iterate), MG_ESTALL (x = last iterate), MG_ENAN, MG_EDIVERGE, or an argument /

@@ -4,8 +4,10 @@
  * check and the CPU-baseline leg of the benchmark, never by the product path.
  *
  * Plain, slow, obviously correct: matrices are assembled element by element
- * into CSR, the smoothers walk the sparse rows exactly as the paper's
- * algorithms describe, and the coarsest level is solved by dense LU.
+ * into CSR, the smoothers are written from their defining formulas in
+ * section 2 (whole-vector products for the normal-equation step, exact
+ * coordinate descent for the Gauss-Seidel-like step), and the coarsest level
+ * is solved by dense LU.
  * The Poisson-control parts are pinned by the tests in tests/test_oracle_*.py;
  * see the header mgo.h for the discretisation readings.
  */
@@ -328,14 +330,13 @@ static void build_L_poisson(mgo_level *L, double alpha) {
   }
 }
 
-/* N_ii = sum_j A_ij^2 / L_jj (Alg. 2, prepared once) */
+/* diagonal of N = A^T L^-1 A: N_ii = a_i^T L^-1 a_i over column a_i of A
+ * (row i of A^T); computed once per level */
 static void build_Ndiag(mgo_level *L) {
+  const mgo_csr *At = &L->At;
   for (int i = 0; i < L->ndof; i++) {
     double s = 0.0;
-    for (int k = L->A.rowptr[i]; k < L->A.rowptr[i + 1]; k++) {
-      double a = L->A.val[k];
-      s += a * a / L->L[L->A.col[k]];
-    }
+    for (int k = At->rowptr[i]; k < At->rowptr[i + 1]; k++) s += At->val[k] * At->val[k] / L->L[At->col[k]];
     L->Nd[i] = s;
   }
 }
@@ -1092,45 +1093,59 @@ void mgo_residual(const mgo_hier *h, int level, const double *f, const double *x
   for (int i = 0; i < L->ndof; i++) r[i] = f[i] - r[i];
 }
 
-/* Normal-equation smoother, Alg. 1: p_i = tau (sum_j A_ij r_j / L_jj) / L_ii
- * for all i from the old residual, then x_i += p_i and r_j -= A_ji p_i. */
+/* Normal-equation smoother (section 2): the damped Richardson step on the
+ * normal equation A^T L^-1 A x = A^T L^-1 f with the preconditioner L,
+ *   x <- x + tau L^-1 A^T L^-1 (f - A x),
+ * written with whole-vector products: s = L^-1 r, t = A^T s, p = tau L^-1 t,
+ * then x += p and r -= A p, so that r stays f - A x (the cost unit of Alg. 1:
+ * one product with A^T and one with A per step). */
 static void ne_step(const mgo_level *L, double tau, double *x, double *r) {
-  const mgo_csr *A = &L->A, *At = &L->At;
+  int n = L->ndof;
+  double *s = (double *)xmalloc((size_t)n * sizeof(double));
+  double *t = (double *)xmalloc((size_t)n * sizeof(double));
   double *p = L->p;
-  for (int i = 0; i < L->ndof; i++) {
-    double q = 0.0;
-    for (int k = A->rowptr[i]; k < A->rowptr[i + 1]; k++) q += A->val[k] / L->L[A->col[k]] * r[A->col[k]];
-    p[i] = tau * q / L->L[i];
-  }
-  for (int i = 0; i < L->ndof; i++) {
+  for (int i = 0; i < n; i++) s[i] = r[i] / L->L[i];
+  csr_mv(&L->At, s, t);
+  for (int i = 0; i < n; i++) p[i] = tau * t[i] / L->L[i];
+  csr_mv(&L->A, p, t);
+  for (int i = 0; i < n; i++) {
     x[i] += p[i];
-    /* row i of At lists the entries A_ji of column i */
-    for (int k = At->rowptr[i]; k < At->rowptr[i + 1]; k++) r[At->col[k]] -= At->val[k] * p[i];
+    r[i] -= t[i];
   }
+  free(s);
+  free(t);
 }
 
-/* Least-squares Gauss-Seidel, Alg. 2, over the groups of an ordering: every
- * unknown i of a group takes q = sum_j A_ij r_j / L_jj from the same residual,
- * p = q / N_ii, x_i += p, r_j -= A_ji p.  Groups of one unknown are Alg. 2
- * verbatim; a group {y_v, lambda_v} is equivalent because the (y_v, lambda_v)
- * entry of N_k = A^T L^{-1} A is zero. */
+/* Least-squares Gauss-Seidel (section 2): Gauss-Seidel on the normal
+ * equation N x = A^T L^-1 f, N = A^T L^-1 A, i.e. exact coordinate descent on
+ * the functional 1/2 ||f - A x||^2_{L^-1}.  Along coordinate i (column a_i of
+ * A, stored as row i of A^T) the functional is minimised by the step
+ *   p = a_i^T L^-1 r / N_ii,  N_ii = a_i^T L^-1 a_i,
+ * after which x_i += p and r -= p a_i.  The coordinates are taken in the
+ * order `ord`; the coordinates of one group are stepped from the same
+ * residual, which equals stepping them one after the other exactly when
+ * their mutual entries of N vanish (the pair {y_v, lambda_v} in the Poisson
+ * problem, a velocity component and its multiplier at one node or p and mu
+ * at one vertex in the Stokes problem). */
 static void lsgs_groups(const mgo_level *L, const int *ord, const int *gptr, int ngroup, int reverse, double *x,
                         double *r) {
-  const mgo_csr *A = &L->A, *At = &L->At;
-  double p[8];
+  const mgo_csr *At = &L->At;
+  double step[8];
   for (int gg = 0; gg < ngroup; gg++) {
     int g = reverse ? ngroup - 1 - gg : gg;
-    int b = gptr[g], e = gptr[g + 1];
-    for (int a = b; a < e; a++) {
-      int i = ord[a];
-      double q = 0.0;
-      for (int k = A->rowptr[i]; k < A->rowptr[i + 1]; k++) q += A->val[k] / L->L[A->col[k]] * r[A->col[k]];
-      p[a - b] = q / L->Nd[i];
+    int first = gptr[g], count = gptr[g + 1] - gptr[g];
+    /* the steps of the group, all from the current residual */
+    for (int u = 0; u < count; u++) {
+      int i = ord[first + u];
+      double dot = 0.0;
+      for (int k = At->rowptr[i]; k < At->rowptr[i + 1]; k++) dot += At->val[k] * (r[At->col[k]] / L->L[At->col[k]]);
+      step[u] = dot / L->Nd[i];
     }
-    for (int a = b; a < e; a++) {
-      int i = ord[a];
-      x[i] += p[a - b];
-      for (int k = At->rowptr[i]; k < At->rowptr[i + 1]; k++) r[At->col[k]] -= At->val[k] * p[a - b];
+    /* then the coordinate moves and the residual update r -= p a_i */
+    for (int u = 0; u < count; u++) {
+      int i = ord[first + u];
+      x[i] += step[u];
+      for (int k = At->rowptr[i]; k < At->rowptr[i + 1]; k++) r[At->col[k]] -= step[u] * At->val[k];
     }
   }
 }

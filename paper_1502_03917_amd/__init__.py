@@ -436,16 +436,29 @@ class Batch:
 
 # --- differentiable solve ---------------------------------------------------------
 
-_ACCEPT = (MG_OK, MG_ESTALL)  # a stall is convergence to the rounding floor
+# A stall (MG_ESTALL: no factor 2 gained over 10 iterates) is accepted as
+# convergence only when the relative residual reached is at the FP64 rounding
+# floor of the solve, at most STALL_FLOOR (or tol, if larger); above it the
+# differentiable solve raises instead of returning an unconverged x.
+STALL_FLOOR = 1e-11
+
+
+def check_solve_status(status: int, relres: float, tol: float) -> None:
+    """Raise MGError unless a solve ended in success, or in a stall at or below
+    max(tol, STALL_FLOOR)."""
+    if status == MG_OK:
+        return
+    if status == MG_ESTALL and relres <= max(tol, STALL_FLOOR):
+        return
+    raise MGError(status, "mg_solve", f"relative residual {relres:.3e} (tol {tol:.1e})")
 
 
 def _solve_or_raise(solver: "Solver", f, tol: float):
     import torch
 
     x = torch.zeros(solver.vec_len(), dtype=torch.float64, device="cuda")
-    x, _, _, st = solver.solve(f, x, tol=tol, raise_on_error=False)
-    if st not in _ACCEPT:
-        solver._check(st, "mg_solve")
+    x, _, rel, st = solver.solve(f, x, tol=tol, raise_on_error=False)
+    check_solve_status(st, rel, tol)
     return x
 
 
@@ -478,7 +491,10 @@ def _make_function():
 
 
 _MGSolve = None
-_SOLVERS: dict = {}
+# solver contexts of solve(), most recently used last; at most MAX_SOLVERS are
+# kept (a context holds the level workspace, hundreds of MB at 1025^2)
+MAX_SOLVERS = 4
+_SOLVERS: "collections.OrderedDict" = None
 
 
 def mg_solve_fn():
@@ -494,15 +510,36 @@ def solve(yd, alpha, level: int, tol: float = 1e-12, **opts):
     nodal values, FP64 CUDA tensor) and alpha (float or 0-d/1-element FP64
     tensor).  Returns (y, lam, u): y and lam are differentiable views of the
     solution; u = lam / alpha is computed by the library and carries no
-    gradient (differentiate lam / alpha instead).  Solvers are cached per
-    (level, alpha, options)."""
+    gradient (differentiate lam / alpha instead).  Solver contexts are cached
+    per (level, alpha, options), the MAX_SOLVERS most recently used; the
+    solves raise MGError unless they converge (a stall is accepted only at
+    the rounding floor, see check_solve_status)."""
+    import collections
+
     import torch
 
-    a = alpha if isinstance(alpha, torch.Tensor) else torch.tensor(float(alpha), dtype=torch.float64, device="cuda")
-    key = (level, float(a.detach().cpu()), tuple(sorted(opts.items())))
+    global _SOLVERS
+    if _SOLVERS is None:
+        _SOLVERS = collections.OrderedDict()
+    if isinstance(alpha, torch.Tensor):
+        a = alpha
+        # the context is built for alpha's value: a CUDA tensor costs one
+        # device-to-host read here, a float or a CPU tensor none
+        aval = float(a.detach().cpu()) if a.is_cuda else float(a.detach())
+        if not a.is_cuda:
+            a = a.to(dtype=torch.float64, device="cuda")
+    else:
+        aval = float(alpha)
+        a = torch.tensor(aval, dtype=torch.float64, device="cuda")
+    key = (level, aval, tuple(sorted(opts.items())))
     s = _SOLVERS.get(key)
     if s is None:
-        s = _SOLVERS[key] = Solver(level, key[1], **opts)
+        s = _SOLVERS[key] = Solver(level, aval, **opts)
+        while len(_SOLVERS) > MAX_SOLVERS:
+            _, old = _SOLVERS.popitem(last=False)
+            old.close()
+    else:
+        _SOLVERS.move_to_end(key)
     x = mg_solve_fn().apply(yd, a, s, tol)
     V = s.nvert()
     with torch.no_grad():

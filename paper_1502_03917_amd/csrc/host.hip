@@ -7,6 +7,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <exception>
 #include <new>
 #include <algorithm>
 #include <string>
@@ -23,6 +24,10 @@ using mgk::Tab;
 namespace {
 
 constexpr int kMaxLevel = 12;
+// Stokes control: the host assembles the level's KKT matrix (eq. mp3) in CSR
+// with 32-bit row pointers before compressing it into stencil classes; level
+// 10 (1025^2 vertices, about 5.4e8 nonzeros) is the largest that fits them.
+constexpr int kMaxStokesLevel = 10;
 constexpr int kMaxCoarse = 3;  // coarsest LU of 2 (2^k0+1)^2 <= 162 unknowns
 // mg_solve reports a stall when the best relative residual of the last 10
 // iterates is not below half the best of the 10 before them
@@ -302,6 +307,15 @@ double default_tau(int problem, int smoother) {
   return (problem == MG_STOKES && smoother != MG_VANKA) ? 0.35 : 0.4;
 }
 
+// problem / smoother pairs that the build does not provide: the patch
+// smoother is defined for Stokes only, the collective point smoother for
+// Poisson only; Stokes solves the coarsest level k0 <= 2
+bool unsupported_pair(int problem, const mg_opts& q) {
+  if (problem == MG_POISSON && q.smoother == MG_VANKA) return true;
+  if (problem == MG_STOKES && (q.smoother == MG_CGS || q.coarse_level > 2)) return true;
+  return false;
+}
+
 bool valid_opts(const mg_opts* o, int level) {
   if (!o) return true;
   if (o->smoother < MG_NE || o->smoother > MG_VANKA) return false;
@@ -470,6 +484,8 @@ int smooth_steps(mg_ctx* c, int l, T* x, T*& r, T* alt, T* p, int steps, hipStre
       case MG_CGS:
         for (int col = 0; col < 7; col++) HIPCHK(c, mgk::launch_cgs_phase<T>(L, col, x, r, s));
         break;
+      default:
+        return fail(c, MG_EUNSUPPORTED, "smoother not provided for Poisson control");
     }
     if (timed && stop) {
       (void)hipEventRecord(stop, s);
@@ -642,6 +658,8 @@ int setup_tail(mg_ctx* c) {
   t.k0 = c->k0;
   t.T = T;
   static const int map[4] = {mgk::MG_TAIL_NE, mgk::MG_TAIL_LSGS, mgk::MG_TAIL_SLSGS, mgk::MG_TAIL_CGS};
+  if (c->o.smoother < MG_NE || c->o.smoother > MG_CGS)
+    return fail(c, MG_EUNSUPPORTED, "coarse tail: smoother not provided for Poisson control");
   t.smoother = map[c->o.smoother];
   t.tau = c->o.tau;
   t.lu = c->d_lu;
@@ -918,7 +936,7 @@ mg_opts mg_default_opts(int problem) {
   o.nu1 = 2;
   o.nu2 = 2;
   o.gamma = 1;
-  o.tau = problem == MG_STOKES ? 0.35 : 0.4;
+  o.tau = -1.0;  // resolved at setup: 0.4 (Poisson NE, patch smoother) or 0.35 (Stokes NE)
   o.coarse_level = 1;
   o.precision = MG_FP64;
   o.max_cycles = 200;
@@ -948,26 +966,35 @@ size_t mg_level_len(const mg_ctx* ctx, int level) {
   return ctx->lv[level - ctx->k0].len;
 }
 
-int mg_get_opts(const mg_ctx* ctx, mg_opts* out) {
+static int impl_mg_get_opts(const mg_ctx* ctx, mg_opts* out) {
   if (!ctx || !out) return MG_EINVAL;
   *out = ctx->o;
   return MG_OK;
 }
 
-int mg_setup(int level, double alpha, int problem, const mg_opts* opts, mg_ctx** out) {
+static int setup_body(mg_ctx* c, int level, double alpha, int problem, const mg_opts* opts, mg_ctx** out);
+
+static int impl_mg_setup(int level, double alpha, int problem, const mg_opts* opts, mg_ctx** out) {
   if (!out) return MG_EINVAL;
   *out = nullptr;
   if (problem != MG_POISSON && problem != MG_STOKES) return MG_EINVAL;
   if (!(alpha > 0.0) || !std::isfinite(alpha)) return MG_EINVAL;
   if (level < 2 || level > kMaxLevel) return MG_EINVAL;
   if (!valid_opts(opts, level)) return MG_EINVAL;
-  {
-    const mg_opts& q = opts ? *opts : mg_default_opts(problem);
-    if (problem == MG_POISSON && q.smoother == MG_VANKA) return MG_EUNSUPPORTED;
-    if (problem == MG_STOKES && (q.smoother == MG_CGS || q.coarse_level > 2)) return MG_EUNSUPPORTED;
-  }
+  if (unsupported_pair(problem, opts ? *opts : mg_default_opts(problem))) return MG_EUNSUPPORTED;
+  if (problem == MG_STOKES && level > kMaxStokesLevel) return MG_EUNSUPPORTED;
   mg_ctx* c = new (std::nothrow) mg_ctx();
   if (!c) return MG_ENOMEM;
+  try {
+    return setup_body(c, level, alpha, problem, opts, out);
+  } catch (...) {
+    // every path that releases c returns at once, so c is still alive here
+    destroy_impl(c);
+    throw;
+  }
+}
+
+static int setup_body(mg_ctx* c, int level, double alpha, int problem, const mg_opts* opts, mg_ctx** out) {
   c->problem = problem;
   c->level = level;
   c->alpha = alpha;
@@ -1068,10 +1095,12 @@ int mg_setup(int level, double alpha, int problem, const mg_opts* opts, mg_ctx**
 
 void mg_destroy(mg_ctx* ctx) { destroy_impl(ctx); }
 
-int mg_set_opts(mg_ctx* ctx, const mg_opts* opts) {
+static int impl_mg_set_opts(mg_ctx* ctx, const mg_opts* opts) {
   if (!ctx || !opts) return MG_EINVAL;
   if (!valid_opts(opts, ctx->level)) return MG_EINVAL;
   if (opts->coarse_level != ctx->k0) return fail(ctx, MG_EINVAL, "coarse_level is fixed at setup");
+  if (unsupported_pair(ctx->problem, *opts))
+    return fail(ctx, MG_EUNSUPPORTED, "mg_set_opts: smoother not provided for this problem");
   mg_opts o = *opts;
   if (o.tau <= 0.0) o.tau = default_tau(ctx->problem, o.smoother);
   if (ctx->st) {
@@ -1095,7 +1124,7 @@ int mg_set_opts(mg_ctx* ctx, const mg_opts* opts) {
   return setup_tail(ctx);
 }
 
-int mg_rhs(mg_ctx* ctx, const double* yd, double* f, void* stream) {
+static int impl_mg_rhs(mg_ctx* ctx, const double* yd, double* f, void* stream) {
   if (!ctx || !yd || !f) return MG_EINVAL;
   if (ctx->st) {
     HIPCHK(ctx, mgk::stokes_rhs(ctx->st, yd, f, (hipStream_t)stream));
@@ -1105,14 +1134,14 @@ int mg_rhs(mg_ctx* ctx, const double* yd, double* f, void* stream) {
   return MG_OK;
 }
 
-int mg_control(mg_ctx* ctx, const double* x, double* u, void* stream) {
+static int impl_mg_control(mg_ctx* ctx, const double* x, double* u, void* stream) {
   if (!ctx || !x || !u) return MG_EINVAL;
   if (ctx->problem != MG_POISSON) return fail(ctx, MG_EUNSUPPORTED, "mg_control: Poisson control only");
   HIPCHK(ctx, mgk::launch_control(L_(ctx, ctx->level).lev, x, u, (hipStream_t)stream));
   return MG_OK;
 }
 
-int mg_adjoint_grad(mg_ctx* ctx, const double* x, const double* xadj, double* grad_yd, double* grad_alpha,
+static int impl_mg_adjoint_grad(mg_ctx* ctx, const double* x, const double* xadj, double* grad_yd, double* grad_alpha,
                     void* stream) {
   if (!ctx || !x || !xadj || !grad_yd || !grad_alpha) return MG_EINVAL;
   if (ctx->problem != MG_POISSON) return fail(ctx, MG_EUNSUPPORTED, "mg_adjoint_grad: Poisson control only");
@@ -1124,7 +1153,7 @@ int mg_adjoint_grad(mg_ctx* ctx, const double* x, const double* xadj, double* gr
   return MG_OK;
 }
 
-int mg_apply(mg_ctx* ctx, int level, const double* x, double* y, void* stream) {
+static int impl_mg_apply(mg_ctx* ctx, int level, const double* x, double* y, void* stream) {
   if (!ctx || !x || !y || !check_level(ctx, level, false)) return MG_EINVAL;
   if (ctx->st) {
     HIPCHK(ctx, mgk::stokes_apply(ctx->st, level, x, y, (hipStream_t)stream));
@@ -1134,7 +1163,7 @@ int mg_apply(mg_ctx* ctx, int level, const double* x, double* y, void* stream) {
   return MG_OK;
 }
 
-int mg_residual(mg_ctx* ctx, int level, const double* f, const double* x, double* r, double* norm_out,
+static int impl_mg_residual(mg_ctx* ctx, int level, const double* f, const double* x, double* r, double* norm_out,
                 void* stream) {
   if (!ctx || !f || !x || !r || !check_level(ctx, level, false)) return MG_EINVAL;
   hipStream_t s = (hipStream_t)stream;
@@ -1157,7 +1186,7 @@ int mg_residual(mg_ctx* ctx, int level, const double* f, const double* x, double
   return MG_OK;
 }
 
-int mg_smooth(mg_ctx* ctx, int level, double* x, double* r, int steps, void* stream) {
+static int impl_mg_smooth(mg_ctx* ctx, int level, double* x, double* r, int steps, void* stream) {
   if (!ctx || !x || !r || steps < 0 || !check_level(ctx, level, false)) return MG_EINVAL;
   hipStream_t s = (hipStream_t)stream;
   if (ctx->st) {
@@ -1172,7 +1201,7 @@ int mg_smooth(mg_ctx* ctx, int level, double* x, double* r, int steps, void* str
   return MG_OK;
 }
 
-int mg_restrict(mg_ctx* ctx, int level, const double* r, double* fc, void* stream) {
+static int impl_mg_restrict(mg_ctx* ctx, int level, const double* r, double* fc, void* stream) {
   if (!ctx || !r || !fc || !check_level(ctx, level, false)) return MG_EINVAL;
   if (ctx->st) {
     HIPCHK(ctx, mgk::stokes_restrict(ctx->st, level, r, fc, (hipStream_t)stream));
@@ -1183,7 +1212,7 @@ int mg_restrict(mg_ctx* ctx, int level, const double* r, double* fc, void* strea
   return MG_OK;
 }
 
-int mg_prolong_add(mg_ctx* ctx, int level, const double* xc, double* x, void* stream) {
+static int impl_mg_prolong_add(mg_ctx* ctx, int level, const double* xc, double* x, void* stream) {
   if (!ctx || !xc || !x || !check_level(ctx, level, false)) return MG_EINVAL;
   if (ctx->st) {
     HIPCHK(ctx, mgk::stokes_prolong_add(ctx->st, level, xc, x, (hipStream_t)stream));
@@ -1194,7 +1223,7 @@ int mg_prolong_add(mg_ctx* ctx, int level, const double* xc, double* x, void* st
   return MG_OK;
 }
 
-int mg_coarse_solve(mg_ctx* ctx, const double* f, double* x, void* stream) {
+static int impl_mg_coarse_solve(mg_ctx* ctx, const double* f, double* x, void* stream) {
   if (!ctx || !f || !x) return MG_EINVAL;
   if (ctx->st) {
     HIPCHK(ctx, mgk::stokes_coarse_solve(ctx->st, f, x, (hipStream_t)stream));
@@ -1203,7 +1232,7 @@ int mg_coarse_solve(mg_ctx* ctx, const double* f, double* x, void* stream) {
   return coarse_solve_T<double>(ctx, f, x, (hipStream_t)stream);
 }
 
-int mg_cycle(mg_ctx* ctx, const double* f, double* x, void* stream) {
+static int impl_mg_cycle(mg_ctx* ctx, const double* f, double* x, void* stream) {
   if (!ctx || !f || !x) return MG_EINVAL;
   hipStream_t s = (hipStream_t)stream;
   if (ctx->st) {
@@ -1225,7 +1254,7 @@ int mg_cycle(mg_ctx* ctx, const double* f, double* x, void* stream) {
   return cycle_body<double>(ctx, ctx->level, f, x, b.r, false, s);
 }
 
-int mg_capture_cycle(mg_ctx* ctx, const double* f, double* x, void* stream, mg_graph** out) {
+static int impl_mg_capture_cycle(mg_ctx* ctx, const double* f, double* x, void* stream, mg_graph** out) {
   if (out) *out = nullptr;
   if (!ctx || !f || !x || !out) return MG_EINVAL;
   HIPCHK(ctx, hipSetDevice(ctx->device));
@@ -1241,7 +1270,7 @@ int mg_capture_cycle(mg_ctx* ctx, const double* f, double* x, void* stream, mg_g
   return MG_OK;
 }
 
-int mg_graph_launch(mg_graph* graph, void* stream) {
+static int impl_mg_graph_launch(mg_graph* graph, void* stream) {
   if (!graph) return MG_EINVAL;
   mg_ctx* c = graph->ctx;
   if (graph->gen != c->opts_gen) return fail(c, MG_EINVAL, "mg_graph_launch: options changed since capture");
@@ -1255,7 +1284,7 @@ void mg_graph_destroy(mg_graph* graph) {
   delete graph;
 }
 
-int mg_solve(mg_ctx* ctx, const double* f, double* x, double tol, int* cycles_out, double* relres_out,
+static int impl_mg_solve(mg_ctx* ctx, const double* f, double* x, double tol, int* cycles_out, double* relres_out,
              void* stream) {
   if (!ctx || !f || !x || !(tol > 0.0) || !std::isfinite(tol)) return MG_EINVAL;
   hipStream_t s = (hipStream_t)stream;
@@ -1298,7 +1327,7 @@ int mg_solve(mg_ctx* ctx, const double* f, double* x, double tol, int* cycles_ou
   }
 }
 
-int mg_timing_enable(mg_ctx* ctx, int enable) {
+static int impl_mg_timing_enable(mg_ctx* ctx, int enable) {
   if (!ctx) return MG_EINVAL;
   drop_graph(ctx);
   if (ctx->ev_used) (void)hipEventSynchronize(ctx->ev[ctx->ev_used - 1]);
@@ -1309,7 +1338,7 @@ int mg_timing_enable(mg_ctx* ctx, int enable) {
   return MG_OK;
 }
 
-int mg_timing_read(mg_ctx* ctx, double* total_ms, long* launches) {
+static int impl_mg_timing_read(mg_ctx* ctx, double* total_ms, long* launches) {
   if (!ctx || !total_ms || !launches) return MG_EINVAL;
   if (ctx->ev_used) {
     HIPCHK(ctx, hipEventSynchronize(ctx->ev[ctx->ev_used - 1]));
@@ -1654,8 +1683,11 @@ int batch_autotune(mg_batch* b, hipStream_t s) {
 
 extern "C" {
 
-int mg_batch_setup(int count, const int* levels, const double* alphas, int problem, const mg_opts* opts,
-                   mg_batch** out) {
+static int batch_setup_body(mg_batch* b, int count, const int* levels, const double* alphas, int problem,
+                            const mg_opts& o, mg_batch** out);
+
+static int impl_mg_batch_setup(int count, const int* levels, const double* alphas, int problem, const mg_opts* opts,
+                               mg_batch** out) {
   if (!out) return MG_EINVAL;
   *out = nullptr;
   if (count < 1 || count > kMaxBatch || !levels || !alphas) return MG_EINVAL;
@@ -1669,6 +1701,16 @@ int mg_batch_setup(int count, const int* levels, const double* alphas, int probl
   }
   if (problem != MG_POISSON || o.gamma != 1 || o.inner_cycles != 1 || o.coarse_level > 2) return MG_EUNSUPPORTED;
   mg_batch* b = new mg_batch;
+  try {
+    return batch_setup_body(b, count, levels, alphas, problem, o, out);
+  } catch (...) {
+    batch_free(b);
+    throw;
+  }
+}
+
+static int batch_setup_body(mg_batch* b, int count, const int* levels, const double* alphas, int problem,
+                            const mg_opts& o, mg_batch** out) {
   b->count = count;
   b->o = o;
   b->k0 = o.coarse_level;
@@ -1781,7 +1823,7 @@ size_t mg_batch_vec_len(const mg_batch* b, int i) {
 
 const char* mg_batch_last_error(const mg_batch* b) { return b ? b->err.c_str() : "no batch"; }
 
-int mg_batch_rhs(mg_batch* b, const double* const* yd, double* const* f, void* stream) {
+static int impl_mg_batch_rhs(mg_batch* b, const double* const* yd, double* const* f, void* stream) {
   if (!b || !yd || !f) return MG_EINVAL;
   for (int i = 0; i < b->count; i++)
     if (!yd[i] || !f[i]) return MG_EINVAL;
@@ -1792,7 +1834,7 @@ int mg_batch_rhs(mg_batch* b, const double* const* yd, double* const* f, void* s
   return MG_OK;
 }
 
-int mg_batch_solve(mg_batch* b, const double* const* f, double* const* x, double tol, int* cycles_out,
+static int impl_mg_batch_solve(mg_batch* b, const double* const* f, double* const* x, double tol, int* cycles_out,
                    double* relres_out, int* status_out, void* stream) {
   if (!b || !f || !x || !(tol > 0.0) || !std::isfinite(tol)) return MG_EINVAL;
   for (int i = 0; i < b->count; i++)
@@ -1848,6 +1890,127 @@ int mg_batch_solve(mg_batch* b, const double* const* f, double* const* x, double
   }
   if (result != MG_OK) b->err = why0;
   return result;
+}
+
+}  // extern "C"
+
+// ============================================================ exception guard
+//
+// Every int-returning entry point runs its body through guarded(): a host
+// exception (std::bad_alloc from a std::vector of the setup or of the solve
+// loop's bookkeeping, std::length_error from an oversized assembly) becomes a
+// status code instead of crossing the C ABI.
+namespace {
+template <class F>
+int guarded(std::string* err, F&& body) noexcept {
+  try {
+    return body();
+  } catch (const std::bad_alloc&) {
+    try {
+      if (err) *err = "host memory allocation failed";
+    } catch (...) {
+    }
+    return MG_ENOMEM;
+  } catch (const std::exception& e) {
+    try {
+      if (err) *err = std::string("host exception: ") + e.what();
+    } catch (...) {
+    }
+    return MG_EUNSUPPORTED;
+  } catch (...) {
+    return MG_EHIP;
+  }
+}
+std::string* err_of(mg_ctx* c) { return c ? &c->err : nullptr; }
+std::string* err_of(const mg_ctx*) { return nullptr; }
+std::string* err_of(mg_batch* b) { return b ? &b->err : nullptr; }
+std::string* err_of(mg_graph* g) { return g ? &g->ctx->err : nullptr; }
+}  // namespace
+
+extern "C" {
+
+int mg_get_opts(const mg_ctx* ctx, mg_opts* out) {
+  return guarded(err_of(ctx), [&] { return impl_mg_get_opts(ctx, out); });
+}
+
+int mg_setup(int level, double alpha, int problem, const mg_opts* opts, mg_ctx** out) {
+  return guarded(nullptr, [&] { return impl_mg_setup(level, alpha, problem, opts, out); });
+}
+
+int mg_set_opts(mg_ctx* ctx, const mg_opts* opts) {
+  return guarded(err_of(ctx), [&] { return impl_mg_set_opts(ctx, opts); });
+}
+
+int mg_rhs(mg_ctx* ctx, const double* yd, double* f, void* stream) {
+  return guarded(err_of(ctx), [&] { return impl_mg_rhs(ctx, yd, f, stream); });
+}
+
+int mg_control(mg_ctx* ctx, const double* x, double* u, void* stream) {
+  return guarded(err_of(ctx), [&] { return impl_mg_control(ctx, x, u, stream); });
+}
+
+int mg_adjoint_grad(mg_ctx* ctx, const double* x, const double* xadj, double* grad_yd, double* grad_alpha, void* stream) {
+  return guarded(err_of(ctx), [&] { return impl_mg_adjoint_grad(ctx, x, xadj, grad_yd, grad_alpha, stream); });
+}
+
+int mg_apply(mg_ctx* ctx, int level, const double* x, double* y, void* stream) {
+  return guarded(err_of(ctx), [&] { return impl_mg_apply(ctx, level, x, y, stream); });
+}
+
+int mg_residual(mg_ctx* ctx, int level, const double* f, const double* x, double* r, double* norm_out, void* stream) {
+  return guarded(err_of(ctx), [&] { return impl_mg_residual(ctx, level, f, x, r, norm_out, stream); });
+}
+
+int mg_smooth(mg_ctx* ctx, int level, double* x, double* r, int steps, void* stream) {
+  return guarded(err_of(ctx), [&] { return impl_mg_smooth(ctx, level, x, r, steps, stream); });
+}
+
+int mg_restrict(mg_ctx* ctx, int level, const double* r, double* fc, void* stream) {
+  return guarded(err_of(ctx), [&] { return impl_mg_restrict(ctx, level, r, fc, stream); });
+}
+
+int mg_prolong_add(mg_ctx* ctx, int level, const double* xc, double* x, void* stream) {
+  return guarded(err_of(ctx), [&] { return impl_mg_prolong_add(ctx, level, xc, x, stream); });
+}
+
+int mg_coarse_solve(mg_ctx* ctx, const double* f, double* x, void* stream) {
+  return guarded(err_of(ctx), [&] { return impl_mg_coarse_solve(ctx, f, x, stream); });
+}
+
+int mg_cycle(mg_ctx* ctx, const double* f, double* x, void* stream) {
+  return guarded(err_of(ctx), [&] { return impl_mg_cycle(ctx, f, x, stream); });
+}
+
+int mg_capture_cycle(mg_ctx* ctx, const double* f, double* x, void* stream, mg_graph** out) {
+  return guarded(err_of(ctx), [&] { return impl_mg_capture_cycle(ctx, f, x, stream, out); });
+}
+
+int mg_graph_launch(mg_graph* graph, void* stream) {
+  return guarded(err_of(graph), [&] { return impl_mg_graph_launch(graph, stream); });
+}
+
+int mg_solve(mg_ctx* ctx, const double* f, double* x, double tol, int* cycles_out, double* relres_out, void* stream) {
+  return guarded(err_of(ctx), [&] { return impl_mg_solve(ctx, f, x, tol, cycles_out, relres_out, stream); });
+}
+
+int mg_timing_enable(mg_ctx* ctx, int enable) {
+  return guarded(err_of(ctx), [&] { return impl_mg_timing_enable(ctx, enable); });
+}
+
+int mg_timing_read(mg_ctx* ctx, double* total_ms, long* launches) {
+  return guarded(err_of(ctx), [&] { return impl_mg_timing_read(ctx, total_ms, launches); });
+}
+
+int mg_batch_setup(int count, const int* levels, const double* alphas, int problem, const mg_opts* opts, mg_batch** out) {
+  return guarded(nullptr, [&] { return impl_mg_batch_setup(count, levels, alphas, problem, opts, out); });
+}
+
+int mg_batch_rhs(mg_batch* b, const double* const* yd, double* const* f, void* stream) {
+  return guarded(err_of(b), [&] { return impl_mg_batch_rhs(b, yd, f, stream); });
+}
+
+int mg_batch_solve(mg_batch* b, const double* const* f, double* const* x, double tol, int* cycles_out, double* relres_out, int* status_out, void* stream) {
+  return guarded(err_of(b), [&] { return impl_mg_batch_solve(b, f, x, tol, cycles_out, relres_out, status_out, stream); });
 }
 
 }  // extern "C"

@@ -18,9 +18,11 @@
 // small levels, every phase of every step in one workgroup with the
 // residual in LDS); a wave per patch for the patch (Vanka-type) smoother.
 #include <algorithm>
+#include <climits>
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
+#include <stdexcept>
 #include <string>
 #include <unordered_map>
 #include <vector>
@@ -148,7 +150,12 @@ struct RowAcc {
     A.nrows = nrows;
     A.ncols = ncols;
     A.rp.assign(nrows + 1, 0);
-    for (int r = 0; r < nrows; r++) A.rp[r + 1] = A.rp[r] + cnt[r];
+    long long nnz = 0;
+    for (int r = 0; r < nrows; r++) {
+      nnz += cnt[r];
+      if (nnz > INT_MAX) throw std::length_error("Stokes assembly: more than 2^31-1 nonzeros");
+      A.rp[r + 1] = (int)nnz;
+    }
     A.col.resize(A.rp[nrows]);
     A.val.resize(A.rp[nrows]);
     std::vector<std::pair<int, double>> row;
@@ -372,7 +379,10 @@ HCsr assemble_kkt(int n, double alpha, const Blocks& B) {
       A.val.push_back(scale * S.val[k]);
     }
   };
-  auto endrow = [&]() { A.rp.push_back((int)A.col.size()); };
+  auto endrow = [&]() {
+    if (A.col.size() > (size_t)INT_MAX) throw std::length_error("Stokes KKT matrix: more than 2^31-1 nonzeros");
+    A.rp.push_back((int)A.col.size());
+  };
   for (int c = 0; c < 2; c++)  // v_c: M v_c + K lambda_c + D_c^T mu
     for (int a = 0; a < nv; a++) {
       put(B.Ms, a, ov[c], 1.0);
@@ -1824,8 +1834,22 @@ hipError_t s_cycle(Stokes* S, int l, const T* f, T* x, T* r, bool current, hipSt
 
 // ---------------------------------------------------------------- interface
 
+static int stokes_create_body(Stokes* S, int level, int k0, double alpha, const mg_opts& o, Stokes** out, std::string* err);
+
+// A host exception in the assembly (allocation, or a matrix too large for its
+// 32-bit row pointers) releases the partly built solver and propagates to the
+// C ABI's guard, which turns it into a status code.
 int stokes_create(int level, int k0, double alpha, const mg_opts& o, Stokes** out, std::string* err) {
   Stokes* S = new Stokes;
+  try {
+    return stokes_create_body(S, level, k0, alpha, o, out, err);
+  } catch (...) {
+    stokes_destroy(S);
+    throw;
+  }
+}
+
+static int stokes_create_body(Stokes* S, int level, int k0, double alpha, const mg_opts& o, Stokes** out, std::string* err) {
   S->level = level;
   S->k0 = k0;
   S->alpha = alpha;

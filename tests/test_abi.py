@@ -30,9 +30,10 @@ def test_library_exports_every_declared_symbol():
 def test_default_opts():
     o = mg.default_opts("poisson")
     assert (o.smoother, o.nu1, o.nu2, o.gamma, o.coarse_level, o.precision) == (mg.MG_LSGS, 2, 2, 1, 1, mg.MG_FP64)
-    assert o.tau == pytest.approx(0.4) and o.max_cycles == 200 and o.inner_cycles == 1
+    # tau <= 0: the context picks section 3's damping for its problem and smoother
+    assert o.tau < 0 and o.max_cycles == 200 and o.inner_cycles == 1
     assert o.norm == mg.MG_NORM_LINV
-    assert mg.default_opts("stokes").tau == pytest.approx(0.35)
+    assert mg.default_opts("stokes").tau < 0
 
 
 def _setup(level=5, alpha=1e-2, problem=0, **kw):
@@ -69,6 +70,46 @@ def test_setup_unsupported_combinations(problem, field, value):
     # patch smoother is Stokes-only, collective point smoother Poisson-only; the
     # bordered Stokes coarse solve holds at most 248 unknowns (coarse level <= 2)
     assert _setup(level=5, problem=problem, **{field: value})[0] == mg.MG_EUNSUPPORTED
+
+
+@pytest.mark.parametrize("level", [11, 12])
+def test_setup_stokes_level_cap(level):
+    # the Stokes host assembly keeps 32-bit row pointers: levels above 10 are
+    # refused before any allocation
+    st, h = _setup(level=level, problem=mg.MG_STOKES)
+    assert st == mg.MG_EUNSUPPORTED and not h.value
+
+
+def test_host_allocation_failure_is_a_status(tmp_path):
+    """A std::bad_alloc inside an entry point comes back as MG_ENOMEM with the
+    output handle cleared (program tests/host/abi_alloc_check.cpp replaces
+    operator new; no GPU is touched)."""
+    import shutil
+    import subprocess
+
+    gxx = shutil.which("g++")
+    if not gxx:
+        pytest.skip("g++ not available")
+    mg.lib()  # built library
+    libdir = os.path.join(ROOT, "paper_1502_03917_amd")
+    exe = tmp_path / "abi_alloc_check"
+    subprocess.run([gxx, "-O1", "-std=c++17", "-I" + os.path.join(ROOT, "include"),
+                    os.path.join(ROOT, "tests", "host", "abi_alloc_check.cpp"), "-L" + libdir, "-lmgkkt",
+                    "-Wl,-rpath," + libdir, "-Wl,--allow-shlib-undefined", "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], capture_output=True, text=True, timeout=120)
+    assert out.returncode == 0, out.stdout + out.stderr
+    assert out.stdout.strip().endswith("ok")
+
+
+def test_solve_status_check():
+    # success passes; a stall passes only at the rounding floor; anything else raises
+    mg.check_solve_status(mg.MG_OK, 1e-3, 1e-12)
+    mg.check_solve_status(mg.MG_ESTALL, 4e-12, 1e-12)
+    mg.check_solve_status(mg.MG_ESTALL, 5e-9, 1e-8)
+    for st, rel in [(mg.MG_ESTALL, 2e-11), (mg.MG_ESTALL, 0.5), (mg.MG_ENOTCONV, 1e-13), (mg.MG_ENAN, math.nan),
+                    (mg.MG_EDIVERGE, 1e4)]:
+        with pytest.raises(mg.MGError):
+            mg.check_solve_status(st, rel, 1e-12)
 
 
 def test_setup_rejects_level_not_above_coarse():
