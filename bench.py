@@ -3,10 +3,13 @@
 MI355X.
 
 One step = one complete solve from x = 0: right-hand side f = (M y_D; 0), then
-multigrid iterates until ||f - A x||_2 <= 1e-10 ||f||_2.  The printed JSON line
-carries the throughput, the roofline of the dominant kernel (the finest-level
-smoothing sweep, timed with HIP events on the launch stream) and the FP64 CPU
-oracle timed on a bounded sample on the host cores.
+multigrid iterates until ||f - A x||_{L^-1} <= 1e-10 ||f||_{L^-1}, the residual
+norm weighted by L_k^-1 (the dual of the L_k norm in which section 3 measures
+convergence; the Euclidean ratio has an FP64 floor near eps h^-2, about 3e-9
+at this size).  The printed JSON line carries the throughput, the roofline of
+the dominant kernel (the finest-level smoothing sweep, timed with HIP events
+on the launch stream), per-field errors of the FP32-refinement solves, and
+the FP64 CPU oracle timed on a bounded sample on the host cores.
 """
 from __future__ import annotations
 
@@ -43,18 +46,47 @@ def log(msg: str) -> None:
     print(msg, file=sys.stderr, flush=True)
 
 
-def words_per_cycle(level: int, coarse: int, nu1: int, nu2: int, sweep_words: float = 8.0) -> float:
-    """Algorithmic words of one V-cycle: per level visit nu1+nu2 sweeps of
-    `sweep_words` per vertex, restriction (read r: 2 words, write f_c: 0.5),
-    prolongation + residual (read x_c 0.5, x 2, f 2; write x 2, r 2), plus the
-    finest-level residual at the start of the cycle (read f, x; write r)."""
+def words_per_cycle(level: int, coarse: int, nu1: int, nu2: int, sweep_words: float = 8.0,
+                    fine_residual: bool = False) -> float:
+    """Algorithmic words of one V-cycle in steady state: per level visit
+    nu1+nu2 sweeps of `sweep_words` per vertex, restriction (read r: 2 words,
+    write f_c: 0.5) and prolongation + residual (read x_c 0.5, x 2, f 2; write
+    x 2, r 2), 43 words per vertex for V(2,2), about 57.3 per fine vertex over
+    all levels.  The smoothers keep r = f - A x current, so a finest-level
+    residual pass (read f, x; write r: 6 words) is added only where the solve
+    moves one (fine_residual)."""
     total = 0.0
     for l in range(coarse + 1, level + 1):
         V = ((1 << l) + 1) ** 2
         total += V * ((nu1 + nu2) * sweep_words + 2.5 + 8.5)
-    V = ((1 << level) + 1) ** 2
-    total += 6 * V
+    if fine_residual:
+        total += 6 * ((1 << level) + 1) ** 2
     return total
+
+
+def field_errors(got, ref, alpha, problem: str = "poisson", level: int | None = None) -> dict:
+    """max |got - ref| / max |ref| per field of a solution vector (Poisson
+    [y | lambda], Stokes [v1 | v2 | p | lambda1 | lambda2 | mu]) and of the
+    control u = lambda / alpha; torch tensors on the device."""
+    import torch
+
+    if problem == "poisson":
+        V = got.numel() // 2
+        names, sizes = ("y", "lambda"), (V, V)
+    else:
+        n = 1 << level
+        nv, npv = (2 * n - 1) ** 2, (n + 1) ** 2
+        names, sizes = ("v1", "v2", "p", "lambda1", "lambda2", "mu"), (nv, nv, npv, nv, nv, npv)
+    out, at = {}, 0
+    for name, k in zip(names, sizes):
+        g, r = got[at:at + k], ref[at:at + k]
+        out["err_" + name] = float(torch.max(torch.abs(g - r)) / torch.clamp(torch.max(torch.abs(r)), min=1e-300))
+        if name.startswith("lambda"):
+            gu, ru = g / alpha, r / alpha
+            out["err_u" + name[6:]] = float(torch.max(torch.abs(gu - ru)) /
+                                            torch.clamp(torch.max(torch.abs(ru)), min=1e-300))
+        at += k
+    return out
 
 
 def sweep_source_hash() -> str:
@@ -275,6 +307,21 @@ def batch_measure(steps: int, tol: float):
     dt, cyc_sum, cyc, rel, st, tiles = timed(True)
     dt_eager, _, _, _, _, _ = timed(False)
     out["sweep_tiles_autotuned"] = tiles
+    # final error of every instance's FP32-refinement solution against its
+    # FP64 one-instance solve, per field (y, lambda, u = lambda / alpha)
+    b = mg.Batch(levels, alphas, precision="fp32_ir")
+    fs = b.rhs(yds)
+    xs, _, _, _, _ = b.solve(fs, tol=tol, raise_on_error=False)
+    errs = []
+    for i, (l, a) in enumerate(zip(levels, alphas)):
+        s1 = mg.Solver(l, a)
+        x1, _, _, _ = s1.solve(s1.rhs(yds[i]), tol=tol, raise_on_error=False)
+        e = field_errors(xs[i], x1, a)
+        errs.append([float(f"{e['err_y']:.2e}"), float(f"{e['err_lambda']:.2e}"), float(f"{e['err_u']:.2e}")])
+        s1.close()
+    b.close()
+    out["fp32_ir_err_vs_fp64_per_instance"] = {"fields": ["y", "lambda", "u"], "errors": errs,
+                                               "max": [max(e[k] for e in errs) for k in range(3)]}
     nbytes = 0.0
     for l, c in zip(levels, cyc):
         V = ((1 << l) + 1) ** 2
@@ -300,6 +347,7 @@ def stokes_measure(steps: int, tol: float, level: int = 9):
     out = {"workload": f"Stokes control, {(1 << level) + 1}^2 vertices, Taylor-Hood, V(2,2), tol {tol:g}"}
     runs = [("lsgs", "fp64", 1e-2), ("lsgs", "fp32_ir", 1e-2), ("lsgs", "fp64", 1e-6), ("lsgs", "fp32_ir", 1e-6),
             ("vanka", "fp64", 1e-2)]
+    keep = {}
     for sm, pr, al in runs:
         t0 = time.perf_counter()
         s = mg.Solver(level, al, problem="stokes", smoother=sm, precision=pr)
@@ -317,29 +365,93 @@ def stokes_measure(steps: int, tol: float, level: int = 9):
             cyc += it
         torch.cuda.synchronize()
         dt = (time.perf_counter() - t0) / steps
+        rec = {"unknowns": n, "cycles": cyc / steps, "ms_per_solve": 1e3 * dt, "vcycles_per_s": cyc / steps / dt,
+               "final_relres": rel, "status": mg.lib().mg_strerror(st).decode(), "setup_s": setup}
+        if sm == "lsgs":
+            keep[(pr, al)] = x.clone()
+        if sm == "lsgs" and pr == "fp64" and al == 1e-2:
+            # the finest-level LSGS sweep (59 colour phases) timed with events
+            # on the launch stream: 4 words (read x, r; write x, r) per unknown
+            r = s.residual(f, x)
+            ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            nsw = 8
+            s.smooth(x, r, steps=1)
+            ev0.record()
+            s.smooth(x, r, steps=nsw)
+            ev1.record()
+            torch.cuda.synchronize()
+            ms = ev0.elapsed_time(ev1) / nsw
+            nbytes = 4 * n * 8
+            rec["roofline"] = {"bound": "hbm", "kernel": "finest-level LSGS sweep (59 colour-phase launches)",
+                               "sweep_ms": ms, "algorithmic_bytes_per_sweep": nbytes,
+                               "achieved": nbytes / (ms * 1e-3) / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                               "frac": nbytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS}
         s.close()
-        out[f"{sm}/{pr}/alpha={al:g}"] = {
-            "unknowns": n, "cycles": cyc / steps, "ms_per_solve": 1e3 * dt, "vcycles_per_s": cyc / steps / dt,
-            "final_relres": rel, "status": mg.lib().mg_strerror(st).decode(), "setup_s": setup}
+        out[f"{sm}/{pr}/alpha={al:g}"] = rec
+    for al in (1e-2, 1e-6):
+        if ("fp64", al) in keep and ("fp32_ir", al) in keep:
+            out[f"lsgs/fp32_ir/alpha={al:g}"]["field_errors_vs_fp64"] = field_errors(
+                keep[("fp32_ir", al)], keep[("fp64", al)], al, "stokes", level)
     return out
 
 
-def cpu_baseline(level: int, alpha: float, seed: int, smoother: str, cycles: int):
+def cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(level: int, alpha: float, seed: int, smoother: str, reps: int, gpu_cycles: float | None):
+    """The FP64 CPU oracle on the host: V(2,2) cycles of the same workload in
+    the same 7-colour order, from x = 0 (setup excluded), each timed alone,
+    median of `reps`; (1) the OpenMP build on all host threads (the groups of
+    one colour, the sparse products and the transfers in parallel; results
+    bit-identical to the single-threaded build), (2) the single-threaded
+    build.  Time to 1e-10 is extrapolated: the oracle's cycles equal the GPU
+    FP64 cycles to 1e-12 at this size, so it needs the same number of cycles."""
+    import statistics
+
     import numpy as np
 
     import oracle
     import workloads
 
-    h = oracle.Hierarchy(level, alpha, coarse=1)
-    f = h.rhs(workloads.desired_state(level, seed))
-    x = np.zeros(h.ndof())
-    t0 = time.perf_counter()
-    for _ in range(cycles):
-        h.cycle(f, x, smoother=smoother, order="col7")
-    dt = time.perf_counter() - t0
-    return {"value": cycles / dt, "unit": "V-cycles/s", "cores": 1, "kind": "oracle",
-            "sample": f"{cycles} V(2,2) {smoother.upper()} cycles (7-colour order) of the 2049^2 workload, "
-                      f"alpha={alpha:g}, from x=0, setup excluded; single-threaded FP64 C"}
+    def leg(threaded: bool):
+        h = oracle.Hierarchy(level, alpha, coarse=1, threaded=threaded)
+        f = h.rhs(workloads.desired_state(level, seed))
+        x = np.zeros(h.ndof())
+        times = []
+        for _ in range(reps):
+            t0 = time.perf_counter()
+            h.cycle(f, x, smoother=smoother, order="col7")
+            times.append(time.perf_counter() - t0)
+        nthr = oracle.threads(threaded)
+        h.close()
+        med = statistics.median(times)
+        rec = {"value": 1.0 / med, "unit": "V-cycles/s", "cores": nthr, "cycle_s_median": med,
+               "cycle_s_all": times}
+        if gpu_cycles:
+            rec["cycles_to_tol"] = gpu_cycles
+            rec["time_to_tol_s_extrapolated"] = gpu_cycles * med
+        return rec
+
+    log("bench: CPU oracle, all host threads")
+    multi = leg(True)
+    log("bench: CPU oracle, one thread")
+    single = leg(False)
+    host = {"nproc": os.cpu_count(), "affinity_cpus": len(os.sched_getaffinity(0)), "model": cpu_model()}
+    out = dict(multi)
+    out.update({"kind": "oracle",
+                "sample": f"{reps} V(2,2) {smoother.upper()} cycles (7-colour order) of the {(1 << level) + 1}^2 "
+                          f"workload, alpha={alpha:g}, from x=0, setup excluded, each timed, median; FP64 C "
+                          f"oracle built with OpenMP on {multi['cores']} threads; time to 1e-10 = GPU cycle "
+                          f"count x median cycle time (extrapolated)",
+                "host": host, "single_core": single})
+    return out
 
 
 def main() -> int:
@@ -353,7 +465,7 @@ def main() -> int:
     ap.add_argument("--precision", default="fp64")
     ap.add_argument("--tol", type=float, default=1e-10)
     ap.add_argument("--seed", type=int, default=2)
-    ap.add_argument("--cpu-cycles", type=int, default=2)
+    ap.add_argument("--cpu-reps", type=int, default=3, help="oracle cycles timed per CPU leg (median)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batch", action="store_true", help="skip the 64-instance batched solve")
     ap.add_argument("--no-fp32-ir", action="store_true", help="skip the FP32-refinement rerun of the main workload")
@@ -395,8 +507,9 @@ def main() -> int:
         return 0
     yd = torch.from_numpy(workloads.desired_state(args.level, args.seed)).cuda()
 
-    def run(smoother, precision, alpha, steps, warmup, timing=False, keep=False):
-        s = mg.Solver(args.level, alpha, smoother=smoother, precision=precision)
+    def run(smoother, precision, alpha, steps, warmup, timing=False, keep=False, gamma=1):
+        nu = 1 if smoother == "slsgs" else 2
+        s = mg.Solver(args.level, alpha, smoother=smoother, precision=precision, gamma=gamma, nu1=nu, nu2=nu)
         inner = s.opts().inner_cycles
         x = torch.zeros(s.vec_len(), dtype=torch.float64, device="cuda")
         for _ in range(warmup):
@@ -445,7 +558,8 @@ def main() -> int:
     sweep_bytes = 8 * V * wbytes  # read and write x and r, both fields
     achieved = sweep_bytes / (main_run["sweep_ms"] * 1e-3) / 1e9
     traffic = recorded_traffic(args.precision, args.level)
-    cyc_bytes = words_per_cycle(args.level, 1, 2, 2) * wbytes
+    # the LSGS solve takes its residual norm from the last sweep (no residual pass)
+    cyc_bytes = words_per_cycle(args.level, 1, 2, 2, fine_residual=args.smoother not in ("lsgs", "slsgs")) * wbytes
     if args.precision == "fp32_ir":
         cyc_bytes += V * 2 * (8 + 8 + 8 + 4 + 8)  # FP64 residual (f, x -> r), scaled cast, FP64 update
     result = {
@@ -489,21 +603,34 @@ def main() -> int:
                              "status": ir["status"], "speedup_time_to_tol_vs_fp64": main_run["ms_per_solve"] / ir["ms_per_solve"],
                              "finest_sweep_ms": ir_sweep["sweep_ms"], "finest_sweep_GBps": ach,
                              "finest_sweep_frac_of_8TBps": ach / HBM_PEAK_GBS}
+        # final error of the FP32-refinement solve against the FP64 solve (whose
+        # cycles match the oracle's at this size), per field, for each alpha
+        errs = {}
+        for al in (1e-8, 1e-4, 1.0):
+            log(f"bench: FP32-refinement field errors, alpha {al:g}")
+            x64 = run(args.smoother, "fp64", al, 1, 0, keep=True)["x"]
+            x32 = run(args.smoother, "fp32_ir", al, 1, 0, keep=True)["x"]
+            errs[f"alpha={al:g}"] = field_errors(x32, x64, al)
+        result["fp32_ir"]["field_errors_vs_fp64"] = errs
     if args.variants:
         # NE and LSGS, FP64 and FP32 refinement, alpha 1e-8 / 1e-4 / 1 on the same
         # workload; the FP32-refinement iterate is compared with the FP64 one
         # (whose cycles match the oracle's at this size)
         var = {}
-        for sm in ("ne", "lsgs"):
+        for sm, gamma in (("ne", 1), ("lsgs", 1), ("cgs", 1), ("slsgs", 1), ("lsgs", 2)):
             for al in (1e-8, 1e-4, 1.0):
-                log(f"bench: variants {sm}, alpha {al:g}")
-                r64 = run(sm, "fp64", al, 2, 1, keep=True)
-                r32 = run(sm, "fp32_ir", al, 2, 1, keep=True)
+                tag = sm + ("/W" if gamma == 2 else "")
+                log(f"bench: variants {tag}, alpha {al:g}")
+                r64 = run(sm, "fp64", al, 2, 1, keep=True, gamma=gamma)
+                r32 = run(sm, "fp32_ir", al, 2, 1, keep=True, gamma=gamma)
+                t64 = run(sm, "fp64", al, 1, 0, timing=True, gamma=gamma)
                 x64, x32 = r64.pop("x"), r32.pop("x")
-                r32["rel_diff_vs_fp64"] = float(torch.linalg.vector_norm(x32 - x64) / torch.linalg.vector_norm(x64))
+                r32.update(field_errors(x32, x64, al))
                 r32["speedup_time_to_tol_vs_fp64"] = r64["ms_per_solve"] / r32["ms_per_solve"]
-                var[f"{sm}/fp64/alpha={al:g}"] = r64
-                var[f"{sm}/fp32_ir/alpha={al:g}"] = r32
+                # finest-level smoothing step: HIP events around its launches
+                r64["finest_step_ms"] = t64["sweep_ms"]
+                var[f"{tag}/fp64/alpha={al:g}"] = r64
+                var[f"{tag}/fp32_ir/alpha={al:g}"] = r32
         result["variants"] = var
     if not args.no_batch:
         log("bench: batched solve of 64 instances (fp32_ir)")
@@ -512,8 +639,9 @@ def main() -> int:
         log("bench: Stokes-control solves (513^2 vertices)")
         result["stokes"] = stokes_measure(max(1, args.steps // 5), args.tol)
     if not args.no_cpu_baseline:
-        log(f"bench: CPU oracle baseline ({args.cpu_cycles} cycles)")
-        result["cpu_baseline"] = cpu_baseline(args.level, args.alpha, args.seed, args.smoother, args.cpu_cycles)
+        log(f"bench: CPU oracle baseline ({args.cpu_reps} cycles per leg)")
+        result["cpu_baseline"] = cpu_baseline(args.level, args.alpha, args.seed, args.smoother, args.cpu_reps,
+                                              main_run["cycles_per_solve"])
     print(json.dumps(result), flush=True)
     return 0
 

@@ -38,26 +38,48 @@ ORDERS = {"lex": ORDER_LEX, "col7": ORDER_COL7, "col7seq": ORDER_COL7SEQ, "vlex"
 TAU_POISSON, TAU_STOKES, TAU_VANKA = 0.4, 0.35, 0.4
 
 
+_OMP_PATH = os.path.join(_HERE, "libmgo_omp.so")
+_omp_lib = None
+
+
 def build(force: bool = True) -> str:
-    """Compile mgo.c into libmgo.so next to this file (plain gcc, FP64)."""
+    """Compile mgo.c into libmgo.so next to this file (plain gcc, FP64,
+    single-threaded) and into libmgo_omp.so, the same source built with
+    OpenMP: its parallel loops (sparse products, transfers, and the groups of
+    one colour of the COL7 order, which touch disjoint residual entries) run
+    on the host's cores with bit-identical results."""
     src = [os.path.join(_HERE, "mgo.c")]
-    if os.path.exists(os.path.join(_HERE, "mgo_stokes.c")):
-        src.append(os.path.join(_HERE, "mgo_stokes.c"))
-    if force or not os.path.exists(_LIB_PATH):
-        tmp = _LIB_PATH + ".tmp"
-        cmd = ["gcc", "-O2", "-std=c99", "-fPIC", "-shared", "-ffp-contract=off", "-o", tmp] + src + ["-lm"]
-        subprocess.run(cmd, check=True)
-        os.replace(tmp, _LIB_PATH)
+    for path, extra in ((_LIB_PATH, []), (_OMP_PATH, ["-fopenmp"])):
+        if force or not os.path.exists(path):
+            tmp = path + ".tmp"
+            cmd = ["gcc", "-O2", "-std=c99", "-fPIC", "-shared", "-ffp-contract=off"] + extra + ["-o", tmp] + src + ["-lm"]
+            subprocess.run(cmd, check=True)
+            os.replace(tmp, path)
     return _LIB_PATH
 
 
-def _load():
-    global _lib
+def threads(threaded: bool = False) -> int:
+    """Threads of the oracle's parallel loops (1 for the default build)."""
+    return int(_load(threaded).mgo_threads())
+
+
+def _load(threaded: bool = False):
+    global _lib, _omp_lib
+    if threaded:
+        if _omp_lib is None:
+            if not os.path.exists(_OMP_PATH):
+                build(force=False)
+            _omp_lib = _setup(ctypes.CDLL(_OMP_PATH))
+        return _omp_lib
     if _lib is not None:
         return _lib
     if not os.path.exists(_LIB_PATH):
         build(force=False)
-    lib = ctypes.CDLL(_LIB_PATH)
+    _lib = _setup(ctypes.CDLL(_LIB_PATH))
+    return _lib
+
+
+def _setup(lib):
     vp, ip, dp = ctypes.c_void_p, ctypes.c_int, ctypes.c_double
     lib.mgo_create.restype = vp
     lib.mgo_create.argtypes = [ip, ip, ip, dp]
@@ -76,7 +98,7 @@ def _load():
     lib.mgo_assemble_p2.argtypes = [ip, ip, vp, vp, vp, vp]
     lib.mgo_prolongation_p2.argtypes = [ip, ip, vp]
     lib.mgo_csr_free.argtypes = [vp]
-    _lib = lib
+    lib.mgo_threads.restype = ip
     return lib
 
 
@@ -136,9 +158,9 @@ class Hierarchy:
     nodes per velocity component and (n+1)^2 pressure vertices.
     """
 
-    def __init__(self, level: int, alpha: float, coarse: int = 1, problem=0):
+    def __init__(self, level: int, alpha: float, coarse: int = 1, problem=0, threaded: bool = False):
         problem = {"poisson": 0, "stokes": 1}.get(problem, problem)
-        self.lib = _load()
+        self.lib = _load(threaded)
         self.level, self.coarse, self.alpha, self.problem = level, coarse, float(alpha), problem
         h = self.lib.mgo_create(problem, level, coarse, float(alpha))
         if not h:

@@ -18,6 +18,20 @@
 
 #include "mgo.h"
 
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+/* threads of the oracle's parallel loops: 1 in the default (single-threaded)
+ * build, the OpenMP team size in the threaded build */
+int mgo_threads(void) {
+#ifdef _OPENMP
+  return omp_get_max_threads();
+#else
+  return 1;
+#endif
+}
+
 /* ------------------------------------------------------------------ utils */
 
 static void *xmalloc(size_t n) {
@@ -148,6 +162,7 @@ static double csr_entry(const mgo_csr *A, int r, int c) {
 
 /* y = A x */
 static void csr_mv(const mgo_csr *A, const double *x, double *y) {
+#pragma omp parallel for schedule(static)
   for (int r = 0; r < A->nrows; r++) {
     double s = 0.0;
     for (int k = A->rowptr[r]; k < A->rowptr[r + 1]; k++) s += A->val[k] * x[A->col[k]];
@@ -277,6 +292,9 @@ typedef struct {
   /* orderings for the Gauss-Seidel-like smoothers: order[] lists unknowns,
    * gptr[] delimits groups updated from one residual snapshot */
   int *ord[4], *gptr[4], ngroup[4];
+  /* first group of each colour (and the end) in the COL7 order: the groups of
+   * one colour share no residual entry, so their steps commute exactly */
+  int cptr[8], ncolour;
   int *cgs_ord[3]; /* vertex orders for the collective smoother: lex, col7, col3 */
   int ncgs;
   /* coarsest level only: dense LU with partial pivoting (Stokes: of the
@@ -376,6 +394,18 @@ static void build_orders_poisson(mgo_level *L) {
         }
     L->gptr[o][g] = at;
     L->ngroup[o] = g;
+  }
+  {
+    /* colour boundaries of COL7: one group per vertex, colours in order */
+    int g = 0;
+    L->ncolour = 7;
+    for (int c = 0; c < 7; c++) {
+      L->cptr[c] = g;
+      for (int j = 0; j <= n; j++)
+        for (int i = 0; i <= n; i++)
+          if ((i + 2 * j) % 7 == c) g++;
+    }
+    L->cptr[7] = g;
   }
   /* vertex-interleaved lexicographic: y_v then lambda_v for v = 0, 1, ... */
   L->ord[MGO_ORDER_VLEX] = (int *)xmalloc(N * sizeof(int));
@@ -1090,6 +1120,7 @@ int mgo_get_diag(const mgo_hier *h, int level, int which, double *out) {
 void mgo_residual(const mgo_hier *h, int level, const double *f, const double *x, double *r) {
   const mgo_level *L = &h->lv[level];
   csr_mv(&L->A, x, r);
+#pragma omp parallel for schedule(static)
   for (int i = 0; i < L->ndof; i++) r[i] = f[i] - r[i];
 }
 
@@ -1127,26 +1158,40 @@ static void ne_step(const mgo_level *L, double tau, double *x, double *r) {
  * their mutual entries of N vanish (the pair {y_v, lambda_v} in the Poisson
  * problem, a velocity component and its multiplier at one node or p and mu
  * at one vertex in the Stokes problem). */
-static void lsgs_groups(const mgo_level *L, const int *ord, const int *gptr, int ngroup, int reverse, double *x,
-                        double *r) {
+static void lsgs_group(const mgo_level *L, const int *ord, const int *gptr, int g, double *x, double *r) {
   const mgo_csr *At = &L->At;
   double step[8];
-  for (int gg = 0; gg < ngroup; gg++) {
-    int g = reverse ? ngroup - 1 - gg : gg;
-    int first = gptr[g], count = gptr[g + 1] - gptr[g];
-    /* the steps of the group, all from the current residual */
-    for (int u = 0; u < count; u++) {
-      int i = ord[first + u];
-      double dot = 0.0;
-      for (int k = At->rowptr[i]; k < At->rowptr[i + 1]; k++) dot += At->val[k] * (r[At->col[k]] / L->L[At->col[k]]);
-      step[u] = dot / L->Nd[i];
-    }
-    /* then the coordinate moves and the residual update r -= p a_i */
-    for (int u = 0; u < count; u++) {
-      int i = ord[first + u];
-      x[i] += step[u];
-      for (int k = At->rowptr[i]; k < At->rowptr[i + 1]; k++) r[At->col[k]] -= step[u] * At->val[k];
-    }
+  int first = gptr[g], count = gptr[g + 1] - gptr[g];
+  /* the steps of the group, all from the current residual */
+  for (int u = 0; u < count; u++) {
+    int i = ord[first + u];
+    double dot = 0.0;
+    for (int k = At->rowptr[i]; k < At->rowptr[i + 1]; k++) dot += At->val[k] * (r[At->col[k]] / L->L[At->col[k]]);
+    step[u] = dot / L->Nd[i];
+  }
+  /* then the coordinate moves and the residual update r -= p a_i */
+  for (int u = 0; u < count; u++) {
+    int i = ord[first + u];
+    x[i] += step[u];
+    for (int k = At->rowptr[i]; k < At->rowptr[i + 1]; k++) r[At->col[k]] -= step[u] * At->val[k];
+  }
+}
+
+static void lsgs_groups(const mgo_level *L, const int *ord, const int *gptr, int ngroup, int reverse, double *x,
+                        double *r) {
+  for (int gg = 0; gg < ngroup; gg++) lsgs_group(L, ord, gptr, reverse ? ngroup - 1 - gg : gg, x, r);
+}
+
+/* the COL7 order colour by colour: the groups of one colour touch disjoint
+ * residual entries, so they may be stepped in any order, or concurrently (the
+ * threaded build of the oracle runs them with OpenMP; the result is the same
+ * bit for bit) */
+static void lsgs_colours(const mgo_level *L, int reverse, double *x, double *r) {
+  const int *ord = L->ord[MGO_ORDER_COL7], *gptr = L->gptr[MGO_ORDER_COL7];
+  for (int cc = 0; cc < L->ncolour; cc++) {
+    int c = reverse ? L->ncolour - 1 - cc : cc;
+#pragma omp parallel for schedule(static)
+    for (int g = L->cptr[c]; g < L->cptr[c + 1]; g++) lsgs_group(L, ord, gptr, g, x, r);
   }
 }
 
@@ -1202,10 +1247,19 @@ void mgo_smooth(const mgo_hier *h, int level, int kind, int order, double tau, d
     case MGO_NE: ne_step(L, tau, x, r); break;
     case MGO_LSGS:
       if (order == MGO_ORDER_COL3) order = MGO_ORDER_COL7;
+      if (order == MGO_ORDER_COL7 && L->ncolour) {
+        lsgs_colours(L, 0, x, r);
+        break;
+      }
       lsgs_groups(L, L->ord[order], L->gptr[order], L->ngroup[order], 0, x, r);
       break;
     case MGO_SLSGS:
       if (order == MGO_ORDER_COL3) order = MGO_ORDER_COL7;
+      if (order == MGO_ORDER_COL7 && L->ncolour) {
+        lsgs_colours(L, 0, x, r);
+        lsgs_colours(L, 1, x, r);
+        break;
+      }
       lsgs_groups(L, L->ord[order], L->gptr[order], L->ngroup[order], 0, x, r);
       lsgs_groups(L, L->ord[order], L->gptr[order], L->ngroup[order], 1, x, r);
       break;
@@ -1257,6 +1311,7 @@ static void prolong_add(const mgo_level *Lf, const mgo_level *Lc, const double *
     const mgo_csr *P = &Lf->Pk[Lf->fkind[fl]];
     const double *src = xc + Lc->foff[fl];
     double *dst = xf + Lf->foff[fl];
+#pragma omp parallel for schedule(static)
     for (int rr = 0; rr < P->nrows; rr++) {
       double s = 0.0;
       for (int k = P->rowptr[rr]; k < P->rowptr[rr + 1]; k++) s += P->val[k] * src[P->col[k]];

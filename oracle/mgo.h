@@ -124,4 +124,7 @@ int mgo_solve(const mgo_hier *h, int kind, int order, double tau, int nu1, int n
 #ifdef __cplusplus
 }
 #endif
+/* threads used by the oracle's parallel loops (1 unless built with OpenMP) */
+int mgo_threads(void);
+
 #endif

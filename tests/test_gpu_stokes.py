@@ -10,6 +10,7 @@ import scipy.sparse as sp
 
 import oracle
 import workloads
+from fieldwise import assert_fields
 
 pytestmark = pytest.mark.gpu
 
@@ -158,8 +159,8 @@ def test_stokes_cycle_parity(torch_cuda, level, alpha, smoother, gamma):
     for m in range(5):
         s.cycle(fg, xg)
         h.cycle(f, xo, smoother=smoother, order="col7", gamma=gamma, nu1=nu, nu2=nu)
-        err = np.linalg.norm(_host(xg) - xo) / np.linalg.norm(xo)
-        assert err <= 1e-12, (m, err)
+        # v1, v2, p, lambda1, lambda2, mu and the control u = lambda / alpha
+        assert_fields(_host(xg), xo, 1e-12, "stokes", level, alpha, what=f"cycle {m}")
 
 
 @pytest.mark.parametrize("precision", ["fp64", "fp32_ir"])
@@ -176,7 +177,8 @@ def test_stokes_solve(torch_cuda, precision, alpha):
     xg, it, rel, st = s.solve(s.rhs(_dev(torch, vd)), tol=1e-10)
     assert st == mg.MG_OK and rel <= 1e-10
     bound = 1e-9 if precision == "fp64" else 1e-8
-    assert np.linalg.norm(_host(xg) - xo) <= bound * np.linalg.norm(xo)
+    err = assert_fields(_host(xg), xo, bound, "stokes", level, alpha)
+    print(f"Stokes {precision} alpha {alpha} vs oracle: {err}", flush=True)
     # pressure and multiplier have zero mean
     w = np.asarray(h.matrix("Mp").sum(axis=1)).ravel()
     fl = h.fields()
@@ -203,17 +205,51 @@ def test_stokes_graph_replays_match_eager(torch_cuda):
     assert np.array_equal(out[0][0], out[1][0])
 
 
-def test_stokes_513_one_cycle_sampled(torch_cuda):
-    """513^2 vertices (4,712,454 unknowns): after one V-cycle from zero the
-    iterate's residual, computed by the oracle's own matrix on the GPU result,
-    equals the GPU residual, and the solve reaches 1e-10 in the L^-1 norm."""
+@pytest.mark.timeout(900)
+def test_stokes_513_against_oracle(torch_cuda):
+    """513^2 vertices (level 9, 4,712,454 unknowns, alpha = 1e-2).
+    (1) One LSGS V-cycle from zero on the GPU equals the oracle's cycle per
+    field to 1e-12, and the GPU residual of that iterate equals f - A x with
+    the oracle's level-9 matrix.  (2) One patch-smoother V-cycle from zero
+    against the oracle's.  (3) FP64 solves to 1e-10 and, for both alpha of the
+    workload (1e-2, 1e-6), FP32 cycles inside FP64 refinement against the
+    FP64 solve, per field."""
     import paper_1502_03917_amd as mg
 
     torch = torch_cuda
-    level, alpha = 9, 1e-2
-    s = _solver(level, alpha)
-    assert s.vec_len() == 4 * 1023**2 + 2 * 513**2
+    level = 9
     vd = workloads.desired_velocity(level, 7)
+    print("Stokes 513^2: oracle hierarchy", flush=True)
+    h = oracle.Hierarchy(level, 1e-2, coarse=1, problem="stokes")
+    f = h.rhs(vd)
+    s = _solver(level, 1e-2)
+    assert s.vec_len() == 4 * 1023**2 + 2 * 513**2 == h.ndof()
     fg = s.rhs(_dev(torch, vd))
-    xg, it, rel, st = s.solve(fg, tol=1e-10)
-    assert st == mg.MG_OK and rel <= 1e-10 and it <= 40
+    assert _rel(_host(fg), f) < 1e-14
+    xg = torch.zeros(h.ndof(), dtype=torch.float64, device="cuda")
+    s.cycle(fg, xg)
+    xo = np.zeros(h.ndof())
+    h.cycle(f, xo, smoother="lsgs", order="col7")
+    assert_fields(_host(xg), xo, 1e-12, "stokes", level, 1e-2, what="lsgs cycle")
+    rg = s.residual(fg, xg)
+    ro = f - h.matrix("A") @ _host(xg)
+    assert _rel(_host(rg), ro) < 1e-12
+    print("Stokes 513^2: patch smoother cycle", flush=True)
+    sv = _solver(level, 1e-2, smoother="vanka")
+    xv = torch.zeros(h.ndof(), dtype=torch.float64, device="cuda")
+    sv.cycle(fg, xv)
+    xvo = np.zeros(h.ndof())
+    h.cycle(f, xvo, smoother="vanka", order="col7")
+    assert_fields(_host(xv), xvo, 1e-12, "stokes", level, 1e-2, what="patch cycle")
+    del h
+    for alpha in (1e-2, 1e-6):
+        print(f"Stokes 513^2: solves at alpha {alpha}", flush=True)
+        s64 = _solver(level, alpha)
+        s32 = _solver(level, alpha, precision="fp32_ir")
+        fa = s64.rhs(_dev(torch, vd))
+        x64, it64, rel64, st64 = s64.solve(fa, tol=1e-10)
+        x32, it32, rel32, st32 = s32.solve(fa, tol=1e-10)
+        assert st64 == mg.MG_OK and st32 == mg.MG_OK and rel64 <= 1e-10 and rel32 <= 1e-10
+        assert it64 <= 40 and it32 <= 40
+        err = assert_fields(_host(x32), _host(x64), 1e-8, "stokes", level, alpha)
+        print(f"Stokes 513^2 alpha {alpha}: FP32 refinement vs FP64 solve {err}", flush=True)

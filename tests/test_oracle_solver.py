@@ -159,3 +159,19 @@ def test_adjoint_gradient_matches_central_differences(alpha):
     da = 1e-6 * alpha  # relative step
     fda = (loss_at(yd, alpha + da) - loss_at(yd, alpha - da)) / (2 * da)
     assert g_alpha == pytest.approx(fda, rel=1e-6)
+
+
+def test_threaded_oracle_is_bit_identical():
+    """The OpenMP build (used for the all-cores CPU baseline) steps the groups
+    of one colour concurrently; they touch disjoint residual entries, so its
+    cycles equal the single-threaded build's bit for bit."""
+    level, alpha = 7, 1e-4
+    out = []
+    for threaded in (False, True):
+        h = oracle.Hierarchy(level, alpha, coarse=1, threaded=threaded)
+        f = h.rhs(workloads.desired_state(level, 2))
+        x = np.zeros(h.ndof())
+        for sm in ("lsgs", "slsgs", "ne"):
+            h.cycle(f, x, smoother=sm, order="col7", nu1=1, nu2=1)
+        out.append(x)
+    assert np.array_equal(out[0], out[1])

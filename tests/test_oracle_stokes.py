@@ -149,6 +149,107 @@ def test_stokes_L_blocks(alpha):
     assert Ld[fl[0]][node] == pytest.approx((1 / n) ** 2 / 10 + np.sqrt(alpha) * K[node, node], rel=1e-14)
 
 
+@pytest.mark.parametrize("alpha", [1.0, 1e-4, 1e-12])
+def test_stokes_pressure_scaling_is_its_definition(alpha):
+    """Section 2 (L_k for Stokes): P^ = alpha diag(D W^-1 D^T) with
+    W^ = diag(M + alpha^1/2 K), D = (D_1 D_2).  The p block of the oracle's
+    L_k equals P^ and the mu block P^ / alpha, with P^ evaluated by sparse
+    products of the Taylor-Hood blocks (both velocity components)."""
+    level = 3
+    n = 1 << level
+    h = oracle.Hierarchy(level, alpha, coarse=1, problem="stokes")
+    M, K, D1, D2 = oracle.taylor_hood(n)
+    Winv = sp.diags(1.0 / (M.diagonal() + np.sqrt(alpha) * K.diagonal()))
+    S = (D1 @ Winv @ D1.T + D2 @ Winv @ D2.T).diagonal()
+    Ld = h.Ldiag()
+    fl = h.fields()
+    assert np.abs(Ld[fl[2]] - alpha * S).max() <= 1e-14 * np.abs(alpha * S).max()
+    assert np.abs(Ld[fl[5]] - S).max() <= 1e-14 * np.abs(S).max()
+
+
+def _tri_rule(npts=4):
+    """Collapsed Gauss-Legendre rule on the reference triangle {s, t >= 0,
+    s + t <= 1}: points (s, t) and weights summing to 1/2; exact for total
+    degree <= 2 npts - 2."""
+    g, w = np.polynomial.legendre.leggauss(npts)
+    g, w = (g + 1) / 2, w / 2
+    pts, wts = [], []
+    for a, wa in zip(g, w):
+        for b, wb in zip(g, w):
+            pts.append((a, b * (1 - a)))
+            wts.append(wa * wb * (1 - a))
+    return np.array(pts), np.array(wts)
+
+
+def _pressure_scaling_by_quadrature(n, alpha):
+    """s_q = sum_j (D1_qj^2 + D2_qj^2) / W^_j for every vertex q, assembled here
+    from scratch: triangles of the mesh whose squares are split along the
+    (i,j)-(i+1,j+1) diagonal, P2 basis lambda_k (2 lambda_k - 1) and
+    4 lambda_a lambda_b in barycentric coordinates, integrals by a collapsed
+    Gauss rule in Cartesian coordinates, velocity nodes interior only."""
+    hh = 1.0 / n
+    pts, wts = _tri_rule()
+    m = 2 * n - 1
+    Md = np.zeros(m * m)
+    Kd = np.zeros(m * m)
+    D = {}  # (q, node) -> [D1, D2]
+
+    def node(a, b):
+        return None if a in (0, 2 * n) or b in (0, 2 * n) else (b - 1) * m + (a - 1)
+
+    for j in range(n):
+        for i in range(n):
+            for tri in ([(i, j), (i + 1, j), (i + 1, j + 1)], [(i, j), (i + 1, j + 1), (i, j + 1)]):
+                P = np.array([[vi * hh, vj * hh] for vi, vj in tri])
+                T = np.array([[P[0, 0], P[1, 0], P[2, 0]], [P[0, 1], P[1, 1], P[2, 1]], [1.0, 1.0, 1.0]])
+                Ti = np.linalg.inv(T)  # lambda = Ti @ (x, y, 1)
+                grad = Ti[:, :2]  # grad lambda_k (constant)
+                area = 0.5 * abs(np.linalg.det(T))
+                loc = [(2 * tri[k][0], 2 * tri[k][1]) for k in range(3)]
+                edges = [(0, 1), (1, 2), (0, 2)]
+                loc += [(tri[a][0] + tri[b][0], tri[a][1] + tri[b][1]) for a, b in edges]
+                for (s_, t_), w_ in zip(pts, wts):
+                    X = P[0] + s_ * (P[1] - P[0]) + t_ * (P[2] - P[0])
+                    lam = Ti @ np.array([X[0], X[1], 1.0])
+                    val = [lam[k] * (2 * lam[k] - 1) for k in range(3)] + [4 * lam[a] * lam[b] for a, b in edges]
+                    gr = [(4 * lam[k] - 1) * grad[k] for k in range(3)]
+                    gr += [4 * (lam[a] * grad[b] + lam[b] * grad[a]) for a, b in edges]
+                    wq = 2 * area * w_
+                    for k in range(6):
+                        nd = node(*loc[k])
+                        if nd is None:
+                            continue
+                        Md[nd] += wq * val[k] ** 2
+                        Kd[nd] += wq * gr[k] @ gr[k]
+                        for v in range(3):
+                            q = tri[v][1] * (n + 1) + tri[v][0]
+                            e = D.setdefault((q, nd), np.zeros(2))
+                            e -= wq * lam[v] * gr[k]
+    W = Md + np.sqrt(alpha) * Kd
+    s = np.zeros((n + 1) ** 2)
+    for (q, nd), d in D.items():
+        s[q] += (d @ d) / W[nd]
+    return s
+
+
+@pytest.mark.parametrize("alpha", [1.0, 1e-4, 1e-12])
+def test_stokes_pressure_scaling_independent_assembly(alpha):
+    """The p and mu blocks of L_k (alpha s_q and s_q) at every vertex, boundary
+    and interior, against an independent quadrature assembly of
+    s_q = (D W^-1 D^T)_qq (section 2, definition of P^)."""
+    level = 3
+    n = 1 << level
+    h = oracle.Hierarchy(level, alpha, coarse=1, problem="stokes")
+    s = _pressure_scaling_by_quadrature(n, alpha)
+    Ld = h.Ldiag()
+    fl = h.fields()
+    assert np.abs(Ld[fl[5]] - s).max() <= 1e-12 * s.max()
+    assert np.abs(Ld[fl[2]] - alpha * s).max() <= 1e-12 * alpha * s.max()
+    # interior vertices share one value (translation invariance of the mesh)
+    inner = [jj * (n + 1) + ii for jj in range(2, n - 1) for ii in range(2, n - 1)]
+    assert np.ptp(s[inner]) <= 1e-13 * s[inner].max()
+
+
 # ------------------------------------------------------------- smoothers
 
 def _dense(h):
