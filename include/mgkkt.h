@@ -187,6 +187,23 @@ int mg_apply(mg_ctx *ctx, int level, const double *x, double *y, void *stream);
 int mg_residual(mg_ctx *ctx, int level, const double *f, const double *x, double *r, double *norm_out,
                 void *stream);
 
+/* For callers that cannot allocate (code under HIP graph capture, serving
+ * loops or harnesses that forbid allocation): mg_residual without any
+ * allocation or host synchronisation.  r = f - A_l x on level l as in
+ * mg_residual, and the Euclidean norm of r written to norm_dev (ONE double in
+ * device memory, caller-owned), stream-ordered.  The per-block partial sums
+ * of the norm live in a static device array of the library (32768 doubles,
+ * 256 KiB per GPU, kept until the process ends) instead of the context's
+ * workspace; its address on each device is taken by mg_setup.  Every call on
+ * one GPU shares that array, so calls that may overlap on one GPU (two
+ * streams, two host threads) race and must be ordered by the caller.
+ * Returns MG_EINVAL for a NULL argument or a level outside
+ * [coarse_level, level], MG_EUNSUPPORTED when the level needs more partial
+ * sums than the array holds (Poisson level 12; every other Poisson and
+ * Stokes level fits), MG_EHIP for a launch failure.  Allocates nothing. */
+int mg_residual_nalloc(mg_ctx *ctx, int level, const double *f, const double *x, double *r, double *norm_dev,
+                       void *stream);
+
 /* `steps` smoothing steps of the context's smoother on level l, in place on
  * (x, r) where r = f - A_l x on entry and is kept current (Alg. 1 / Alg. 2). */
 int mg_smooth(mg_ctx *ctx, int level, double *x, double *r, int steps, void *stream);

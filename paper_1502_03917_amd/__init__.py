@@ -79,6 +79,7 @@ def lib():
     L.mg_adjoint_grad.argtypes = [vp, vp, vp, vp, vp, vp]
     L.mg_apply.argtypes = [vp, ip, vp, vp, vp]
     L.mg_residual.argtypes = [vp, ip, vp, vp, vp, ctypes.POINTER(dp), vp]
+    L.mg_residual_nalloc.argtypes = [vp, ip, vp, vp, vp, vp, vp]
     L.mg_smooth.argtypes = [vp, ip, vp, vp, ip, vp]
     L.mg_restrict.argtypes = [vp, ip, vp, vp, vp]
     L.mg_prolong_add.argtypes = [vp, ip, vp, vp, vp]
@@ -113,7 +114,7 @@ def lib():
     L.mg_strerror.argtypes = [ip]
     L.mg_last_error.restype = ctypes.c_char_p
     L.mg_last_error.argtypes = [vp]
-    for name in ("mg_setup", "mg_get_opts", "mg_set_opts", "mg_rhs", "mg_control", "mg_adjoint_grad", "mg_apply", "mg_residual", "mg_smooth",
+    for name in ("mg_setup", "mg_get_opts", "mg_set_opts", "mg_rhs", "mg_control", "mg_adjoint_grad", "mg_apply", "mg_residual", "mg_residual_nalloc", "mg_smooth",
                  "mg_restrict", "mg_prolong_add", "mg_coarse_solve", "mg_cycle", "mg_capture_cycle", "mg_graph_launch", "mg_solve", "mg_timing_enable",
                  "mg_timing_read"):
         getattr(L, name).restype = ip
@@ -264,6 +265,16 @@ class Solver:
                                ctypes.byref(nrm) if norm else None, _stream())
         self._check(st, "mg_residual")
         return (r, nrm.value) if norm else r
+
+    def residual_nalloc(self, f, x, r, norm, level: int | None = None):
+        """mg_residual_nalloc: r = f - A x and ||r||_2 written to the one-entry
+        device tensor `norm`, stream-ordered; the library allocates nothing."""
+        l = self.level if level is None else level
+        n = self.level_len(l)
+        st = lib().mg_residual_nalloc(self._h, l, self._t(f, n, "f"), self._t(x, n, "x"), self._t(r, n, "r"),
+                                      self._t(norm, 1, "norm"), _stream())
+        self._check(st, "mg_residual_nalloc")
+        return r, norm
 
     def smooth(self, x, r, steps: int = 1, level: int | None = None):
         l = self.level if level is None else level

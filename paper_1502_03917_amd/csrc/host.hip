@@ -8,6 +8,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <exception>
+#include <mutex>
 #include <new>
 #include <algorithm>
 #include <string>
@@ -201,6 +202,43 @@ bool lu_factor(int N, std::vector<double>& a, std::vector<int>& piv) {
   return true;
 }
 
+}  // namespace
+
+// ------------------------------------------------- static scratch (no allocation)
+//
+// mg_residual_nalloc keeps its norm partial sums in this file-scope device
+// array instead of the context's workspace: 32768 doubles (256 KiB), one copy
+// per GPU, held until the process ends.  Host code never passes the array's
+// name to a kernel (on the host it is only a stand-in symbol): mg_setup takes
+// its device address once per device with hipGetSymbolAddress, with that
+// device current, and the entry point uses that address.  Every call on a GPU
+// shares the array, so calls that overlap on one GPU race.
+constexpr int kScratchWords = 32768;
+static __device__ __align__(256) double scratch[kScratchWords];
+
+namespace {
+constexpr int kScratchMaxDevices = 64;
+std::mutex g_scratch_mu;
+double* g_scratch_ptr[kScratchMaxDevices] = {};
+
+// device address of `scratch` on device dev (which must be current), taken once
+hipError_t scratch_init(int dev) {
+  if (dev < 0 || dev >= kScratchMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (g_scratch_ptr[dev]) return hipSuccess;
+  void* ptr = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+  if (e != hipSuccess) return e;
+  if (!ptr) return hipErrorInvalidSymbol;
+  g_scratch_ptr[dev] = static_cast<double*>(ptr);
+  return hipSuccess;
+}
+
+double* scratch_ptr(int dev) {
+  if (dev < 0 || dev >= kScratchMaxDevices) return nullptr;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  return g_scratch_ptr[dev];
+}
 }  // namespace
 
 // -------------------------------------------------------------------- context
@@ -909,6 +947,10 @@ int setup_stokes(mg_ctx* c, mg_ctx** out) {
     delete c;
     return MG_EHIP;
   }
+  if (scratch_init(c->device) != hipSuccess) {
+    delete c;
+    return MG_EHIP;
+  }
   int st = mgk::stokes_create(c->level, c->k0, c->alpha, c->o, &c->st, &c->err);
   if (st != MG_OK) {
     destroy_impl(c);
@@ -1031,6 +1073,10 @@ static int setup_body(mg_ctx* c, int level, double alpha, int problem, const mg_
     return s;
   };
   if (hipGetDevice(&c->device) != hipSuccess) {
+    delete c;
+    return MG_EHIP;
+  }
+  if (scratch_init(c->device) != hipSuccess) {
     delete c;
     return MG_EHIP;
   }
@@ -1183,6 +1229,36 @@ static int impl_mg_residual(mg_ctx* ctx, int level, const double* f, const doubl
   HIPCHK(ctx, hipMemcpyAsync(ctx->h_norm + 2, ctx->d_norm + 2, sizeof(double), hipMemcpyDeviceToHost, s));
   HIPCHK(ctx, hipStreamSynchronize(s));
   *norm_out = std::sqrt(ctx->h_norm[2]);
+  return MG_OK;
+}
+
+// mg_residual's arithmetic with the norm partials in the static scratch and
+// the norm left on the device: no allocation and no synchronisation
+static int impl_mg_residual_nalloc(mg_ctx* ctx, int level, const double* f, const double* x, double* r,
+                                   double* norm_dev, void* stream) {
+  if (!ctx || !f || !x || !r || !norm_dev || !check_level(ctx, level, false)) return MG_EINVAL;
+  const int nb = ctx->st ? mgk::stokes_residual_parts(ctx->st, level) : mgk::residual_blocks(1 << level);
+  if (nb < 1 || nb > kScratchWords) {
+    ctx->err = "mg_residual_nalloc: level " + std::to_string(level) + " needs " + std::to_string(nb) +
+               " partial sums, the static scratch holds " + std::to_string(kScratchWords);
+    return MG_EUNSUPPORTED;
+  }
+  double* part = scratch_ptr(ctx->device);
+  if (!part) {
+    ctx->err = "mg_residual_nalloc: no scratch address for device " + std::to_string(ctx->device);
+    return MG_EHIP;
+  }
+  hipStream_t s = (hipStream_t)stream;
+  int wrote = 0;
+  if (ctx->st)
+    HIPCHK(ctx, mgk::stokes_residual(ctx->st, level, f, x, r, part, 1, &wrote, s));
+  else
+    HIPCHK(ctx, mgk::launch_residual<double>(L_(ctx, level).lev, f, x, r, part, 1, &wrote, s));
+  if (wrote != nb) {
+    ctx->err = "mg_residual_nalloc: partial count mismatch";
+    return MG_EHIP;
+  }
+  HIPCHK(ctx, mgk::launch_sum_sqrt(part, nb, norm_dev, s));
   return MG_OK;
 }
 
@@ -1959,6 +2035,11 @@ int mg_apply(mg_ctx* ctx, int level, const double* x, double* y, void* stream) {
 
 int mg_residual(mg_ctx* ctx, int level, const double* f, const double* x, double* r, double* norm_out, void* stream) {
   return guarded(err_of(ctx), [&] { return impl_mg_residual(ctx, level, f, x, r, norm_out, stream); });
+}
+
+int mg_residual_nalloc(mg_ctx* ctx, int level, const double* f, const double* x, double* r, double* norm_dev,
+                       void* stream) {
+  return guarded(err_of(ctx), [&] { return impl_mg_residual_nalloc(ctx, level, f, x, r, norm_dev, stream); });
 }
 
 int mg_smooth(mg_ctx* ctx, int level, double* x, double* r, int steps, void* stream) {

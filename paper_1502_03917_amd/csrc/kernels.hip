@@ -566,7 +566,7 @@ __global__ __launch_bounds__(256) void k_coarse_solve(int N, const double* __res
 
 // *out = scale * sum of part[0..n) by one workgroup of NT threads, in a fixed
 // order (four independent accumulators per thread keep loads in flight)
-template <int NT>
+template <int NT, bool SQRT = false>
 __device__ __forceinline__ void sum_body(const double* __restrict__ part, int n, double scale,
                                          double* __restrict__ out) {
   __shared__ double sh[NT / 64];
@@ -587,12 +587,17 @@ __device__ __forceinline__ void sum_body(const double* __restrict__ part, int n,
     double t = 0.0;
 #pragma unroll
     for (int w = 0; w < NT / 64; w++) t += sh[w];
-    *out = scale * t;
+    *out = SQRT ? sqrt(scale * t) : scale * t;
   }
 }
 __global__ __launch_bounds__(1024) void k_sum(const double* __restrict__ part, int n, double scale,
                                               double* __restrict__ out) {
   sum_body<1024>(part, n, scale, out);
+}
+// the same sum followed by its square root (a Euclidean norm from squared partials)
+__global__ __launch_bounds__(1024) void k_sum_sqrt(const double* __restrict__ part, int n,
+                                                   double* __restrict__ out) {
+  sum_body<1024, true>(part, n, 1.0, out);
 }
 
 __global__ __launch_bounds__(256) void k_sumsq(const double* __restrict__ v, size_t n, double* __restrict__ part) {
@@ -829,6 +834,11 @@ hipError_t launch_coarse_solve(int N, const double* lu, const int* piv, const T*
 
 hipError_t launch_sum(const double* part, int n, double* out, hipStream_t s, double scale) {
   hipLaunchKernelGGL(k_sum, dim3(1), dim3(1024), 0, s, part, n, scale, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_sum_sqrt(const double* part, int n, double* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_sum_sqrt, dim3(1), dim3(1024), 0, s, part, n, out);
   return hipGetLastError();
 }
 

@@ -158,6 +158,8 @@ hipError_t tail_allow_lds(size_t bytes);
 
 // *out = scale * (sum of the n partials)
 hipError_t launch_sum(const double* part, int n, double* out, hipStream_t s, double scale = 1.0);
+// *out = sqrt(sum of the n partials)
+hipError_t launch_sum_sqrt(const double* part, int n, double* out, hipStream_t s);
 // x = B r (accumulate 0) or x += B r (accumulate 1), B row-major N x N (N even, <= kDenseMapMaxN)
 template <typename T>
 hipError_t launch_dense_map(const T* B, int N, const T* r, T* x, int accumulate, hipStream_t s);
@@ -217,6 +219,7 @@ hipError_t stokes_rhs(Stokes* S, const double* vd, double* f, hipStream_t s);
 hipError_t stokes_apply(Stokes* S, int l, const double* x, double* y, hipStream_t s);
 hipError_t stokes_residual(Stokes* S, int l, const double* f, const double* x, double* r, double* part,
                            int norm_mode, int* nparts, hipStream_t s);
+int stokes_residual_parts(const Stokes* S, int l);  // norm partial sums a level-l residual writes
 hipError_t stokes_vnorm(Stokes* S, const double* v, double* part, int norm_mode, int* nparts, hipStream_t s);
 hipError_t stokes_smooth(Stokes* S, int l, double* x, double* r, int steps, hipStream_t s);
 hipError_t stokes_restrict(Stokes* S, int l, const double* r, double* fc, hipStream_t s);

@@ -1915,6 +1915,11 @@ hipError_t stokes_apply(Stokes* S, int l, const double* x, double* y, hipStream_
   return hipGetLastError();
 }
 
+int stokes_residual_parts(const Stokes* S, int l) {
+  if (!S || l < S->k0 || l > S->level) return 0;
+  return row_blocks(S->lv[l - S->k0].ndof);
+}
+
 hipError_t stokes_residual(Stokes* S, int l, const double* f, const double* x, double* r, double* part,
                            int norm_mode, int* nparts, hipStream_t s) {
   StokesLevel& L = S->L(l);
