@@ -453,8 +453,8 @@ hipEvent_t timing_begin(mg_ctx* c, hipStream_t s, size_t* slot) {
 }
 
 // `steps` smoothing steps on level l.  r holds f - A x on entry; the fused
-// LSGS sweeps alternate between r and alt, and r is updated to the buffer
-// holding the current residual on return.
+// LSGS and collective-smoother sweeps alternate between r and alt, and r is
+// updated to the buffer holding the current residual on return.
 // Residual norm of the last sweep (FP64 tile sweeps only): when part is
 // given, the last sweep also stores per-tile partial sums of ||r||^2 of the
 // residual it leaves (norm mode `mode`) and *nb receives their number.
@@ -466,11 +466,14 @@ struct SweepNorm {
 
 template <typename T>
 hipError_t last_sweep(const Lev& L, int reverse, const T* xin, T* x, const T* rin, T* rout, const SweepNorm& sn,
-                      hipStream_t s) {
+                      hipStream_t s, bool cgs = false) {
   if constexpr (std::is_same<T, double>::value) {
-    if (sn.part) return mgk::launch_lsgs_sweep_norm(L, reverse, xin, x, rin, rout, sn.part, sn.mode, sn.nb, s);
+    if (sn.part)
+      return cgs ? mgk::launch_cgs_sweep_norm(L, xin, x, rin, rout, sn.part, sn.mode, sn.nb, s)
+                 : mgk::launch_lsgs_sweep_norm(L, reverse, xin, x, rin, rout, sn.part, sn.mode, sn.nb, s);
   }
-  return mgk::launch_lsgs_sweep_from<T>(L, reverse, xin, x, rin, rout, s);
+  return cgs ? mgk::launch_cgs_sweep_from<T>(L, xin, x, rin, rout, s)
+             : mgk::launch_lsgs_sweep_from<T>(L, reverse, xin, x, rin, rout, s);
 }
 
 template <typename T>
@@ -481,7 +484,8 @@ int smooth_steps(mg_ctx* c, int l, T* x, T*& r, T* alt, T* p, int steps, hipStre
   const bool timed = c->timing && l == c->level && !c->capturing;
   const bool fused = c->fused && alt != nullptr;
   // below the finest level, small levels run two sweeps per launch (an
-  // LSGS pair, or the forward and backward sweep of an sLSGS step)
+  // LSGS or collective-smoother pair, or the forward and backward sweep of
+  // an sLSGS step)
   const bool pairs = fused && c->sweep2 && l < c->level && L.n <= mgk::lsgs_sweep2_max_n();
   for (int it = 0; it < steps; it++) {
     // the first tile sweep may take the iterate from xin0 (fused prolongation)
@@ -520,7 +524,16 @@ int smooth_steps(mg_ctx* c, int l, T* x, T*& r, T* alt, T* p, int steps, hipStre
         }
         break;
       case MG_CGS:
-        for (int col = 0; col < 7; col++) HIPCHK(c, mgk::launch_cgs_phase<T>(L, col, x, r, s));
+        if (pairs && it + 1 < steps) {
+          HIPCHK(c, mgk::launch_cgs_sweep2<T>(L, xin, x, r, alt, s));
+          std::swap(r, alt);
+          it++;
+        } else if (fused) {
+          HIPCHK(c, last_sweep<T>(L, 0, xin, x, r, alt, snl, s, true));
+          std::swap(r, alt);
+        } else {
+          for (int col = 0; col < 7; col++) HIPCHK(c, mgk::launch_cgs_phase<T>(L, col, x, r, s));
+        }
         break;
       default:
         return fail(c, MG_EUNSUPPORTED, "smoother not provided for Poisson control");
@@ -777,7 +790,8 @@ int cycle_body(mg_ctx* c, int l, const T* f, T* x, T* r, bool residual_current, 
   // x += P x_c and r = f - A x.  Before a tile-sweep post-smoother both go in
   // one kernel that writes the corrected iterate to the level's scratch p
   // (unused by LSGS); the first sweep reads it from there and writes x.
-  const bool fuse = c->fused && c->o.nu2 > 0 && (c->o.smoother == MG_LSGS || c->o.smoother == MG_SLSGS);
+  const bool fuse = c->fused && c->o.nu2 > 0 &&
+                    (c->o.smoother == MG_LSGS || c->o.smoother == MG_SLSGS || c->o.smoother == MG_CGS);
   if (fuse) {
     HIPCHK(c, mgk::launch_prolong_residual<T>(b.lev, bc.lev, wc.x, x, f, wb.p, r, s));
     return smooth_steps<T>(c, l, x, r, alt, wb.p, c->o.nu2, s, wb.p, sn);
@@ -849,12 +863,13 @@ double* fine_r(mg_ctx* c) { return c->st ? mgk::stokes_fine_r(c->st) : L_(c, c->
 
 // FP64 Poisson iterates whose last post-smoothing step is a tile sweep that
 // leaves the residual in the finest level's first buffer (an even number of
-// LSGS sweeps per cycle, or sLSGS) take the residual norm from that sweep.
+// LSGS or collective-smoother sweeps per cycle, or sLSGS) take the residual
+// norm from that sweep.
 bool sweep_norm(const mg_ctx* c) {
   if (c->st || !c->sweep_norm_allowed || c->o.precision != MG_FP64 || !c->fused || c->o.nu2 < 1 || c->timing)
     return false;
   if (c->o.smoother == MG_SLSGS) return true;
-  return c->o.smoother == MG_LSGS && (c->o.nu1 + c->o.nu2) % 2 == 0;
+  return (c->o.smoother == MG_LSGS || c->o.smoother == MG_CGS) && (c->o.nu1 + c->o.nu2) % 2 == 0;
 }
 
 int iterate(mg_ctx* c, const double* f, double* x, hipStream_t s) {

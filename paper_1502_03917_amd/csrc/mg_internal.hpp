@@ -138,6 +138,16 @@ hipError_t launch_lsgs_sweep_norm(const Lev& L, int reverse, const double* xin, 
                                   double* rout, double* part, int norm_mode, int* nparts, hipStream_t s);
 template <typename T>
 hipError_t launch_cgs_phase(const Lev& L, int colour, T* x, T* r, hipStream_t s);
+// fused sweeps of the collective point smoother (7 colours, one launch per
+// sweep; two sweeps per launch on levels with n <= lsgs_sweep2_max_n()); r
+// read from rin and written to rout, the iterate read from xin and written
+// to x; the _norm form also stores per-tile partial sums of ||r_out||^2
+template <typename T>
+hipError_t launch_cgs_sweep_from(const Lev& L, const T* xin, T* x, const T* rin, T* rout, hipStream_t s);
+template <typename T>
+hipError_t launch_cgs_sweep2(const Lev& L, const T* xin, T* x, const T* rin, T* rout, hipStream_t s);
+hipError_t launch_cgs_sweep_norm(const Lev& L, const double* xin, double* x, const double* rin, double* rout,
+                                 double* part, int norm_mode, int* nparts, hipStream_t s);
 template <typename T>
 hipError_t launch_restrict(const Lev& Lf, const Lev& Lc, const T* r, T* fc, T* xc_zero, T* rc_copy, hipStream_t s);
 template <typename T>

@@ -1,5 +1,7 @@
 // One fused kernel per LSGS sweep (Alg. 2 of Takacs, arXiv 1502.03917, with
-// the unknowns ordered by the colours c(i,j) = (i + 2j) mod 7) for gfx950.
+// the unknowns ordered by the colours c(i,j) = (i + 2j) mod 7) for gfx950,
+// and the same kernel for a sweep of the collective point smoother (section
+// 2: a 2x2 solve of (y_v, lambda_v) per vertex, in the same 7 colours).
 //
 // A colour phase updates the vertices of one colour; each of them reads and
 // writes r on its closed neighbourhood, so after 7 phases the residual at a
@@ -17,6 +19,12 @@
 // Global traffic per owned vertex: x read and written once, r written once,
 // r read once plus the halo share (neighbouring tiles re-read each other's
 // borders, mostly from L2 because consecutive tiles run on the same XCD).
+//
+// The collective smoother reads only its own vertex's residual and scatters
+// to the closed neighbourhood, so a phase widens the dependence by one step
+// instead of two: a 7-vertex halo per sweep, and phase c visits the vertices
+// of colour c within distance 7 - c of the tile.  Its scatters from the
+// outermost window reach the guard ring, which nothing reads.
 #include <type_traits>
 
 #include "mg_internal.hpp"
@@ -25,7 +33,8 @@ namespace mgk {
 
 namespace {
 
-constexpr int kHalo = 14;
+constexpr int kHalo = 14;     // LSGS: halo of one sweep
+constexpr int kHaloCgs = 7;   // collective smoother: halo of one sweep
 
 // Workgroup barrier that orders LDS accesses only; global memory needs no
 // ordering inside a sweep (r_in is read-only, r_out and x are per owned vertex).
@@ -66,17 +75,22 @@ __device__ inline void bstore(__amdgpu_buffer_rsrc_t r, unsigned off, float v) {
 // that the cells of the lanes served together fall into distinct banks as
 // often as possible (a bank-conflict model of the phases' access pattern, for
 // 32 and 64 four-byte banks).
-constexpr int pitch_pad(int TW, int H, int cell) {
+constexpr int pitch_pad(int TW, int H, int cell, bool cgs = false) {
+  if (cgs)
+    return cell == 16 ? (H == kHaloCgs ? (TW == 65 ? 14 : TW == 48 ? 10 : TW == 16 ? 14 : 1)
+                                       : (TW == 17 ? 13 : TW == 33 ? 11 : 1))
+                      : (H == kHaloCgs ? (TW == 46 ? 12 : TW == 48 ? 10 : TW == 16 ? 6 : 1)
+                                       : (TW == 17 ? 13 : TW == 33 ? 11 : 1));
   return cell == 16 ? (H == kHalo ? (TW == 65 ? 7 : TW == 56 ? 9 : TW == 48 ? 10 : TW == 16 ? 7 : 1)
                                   : (TW == 17 ? 13 : TW == 33 ? 4 : 1))
                     : (H == kHalo ? (TW == 46 ? 3 : TW == 48 ? 12 : TW == 16 ? 8 : 1)
                                   : (TW == 17 ? 15 : TW == 33 ? 13 : 1));
 }
 
-template <int TW, int H = kHalo, int CELL = 16>
+template <int TW, int H = kHalo, int CELL = 16, bool CGS = false>
 struct TileGeom {
   static constexpr int RMAX = TW + 2 * H;                           // widest / tallest region (halo H)
-  static constexpr int RP = RMAX + 2 + pitch_pad(TW, H, CELL);      // pitch: a guard cell each side, padding
+  static constexpr int RP = RMAX + 2 + pitch_pad(TW, H, CELL, CGS); // pitch: a guard cell each side, padding
   static constexpr int RN = RP * (RMAX + 2);                        // region cells with guard rows
 };
 
@@ -94,28 +108,30 @@ struct Pair<float> {
 
 // Work items of a colour phase are (row, slot) pairs: slot t of a row is its
 // t-th vertex of the phase's colour inside the window.  A window row of width
-// w holds at most ceil(w / 7) of them.
-template <int TW, int H = kHalo>
+// w holds at most ceil(w / 7) of them.  The first window reaches H - 1 steps
+// beyond the tile (LSGS) or H steps (collective smoother).
+template <int TW, int H = kHalo, bool CGS = false>
 struct PhaseItems {
-  static constexpr int W0 = TW + 2 * H - 2;  // width and height of the widest (first) window
-  static constexpr int SMAX = (W0 + 6) / 7;      // slots per row that cover every window
+  static constexpr int W0 = TW + 2 * (CGS ? H : H - 1);  // width and height of the widest (first) window
+  static constexpr int SMAX = (W0 + 6) / 7;                // slots per row that cover every window
 };
 
 // The iterate is read from xin and written to x (the same buffer, or a
 // distinct one when the sweep also moves x: xin is read only before x is
 // written, per owned vertex).  NSW sweeps run in one pass over the tile
-// (halo 14 NSW, 7 NSW colour phases); bit s of reverse gives the order of
-// sweep s.
-template <typename T, int TW, int NT, int NSW = 1>
+// (halo 14 NSW, or 7 NSW for the collective smoother (CGS); 7 NSW colour
+// phases); bit s of reverse gives the order of sweep s.
+template <typename T, int TW, int NT, int NSW = 1, bool CGS = false>
 __device__ __forceinline__ void lsgs_tile_body(const Lev& L, int ntx, int nty, int reverse, const T* xin, T* x,
                                                const T* __restrict__ rin, T* __restrict__ rout,
                                                double* __restrict__ part = nullptr, int norm_mode = 0) {
-  constexpr int H = kHalo * NSW;
-  using G = TileGeom<TW, H, 2 * sizeof(T)>;
+  constexpr int H = (CGS ? kHaloCgs : kHalo) * NSW;
+  using G = TileGeom<TW, H, 2 * sizeof(T), CGS>;
   using T2 = typename Pair<T>::type;
+  using PI = PhaseItems<TW, H, CGS>;
   constexpr int NR = (G::RMAX * G::RMAX + NT - 1) / NT;  // region cells per thread
   constexpr int NX = (TW * TW + NT - 1) / NT;            // owned cells per thread
-  constexpr int SMAX = PhaseItems<TW, H>::SMAX;
+  constexpr int SMAX = PI::SMAX;
   // The rows of a phase window are enumerated from the tile's first row on,
   // wrapping round to the halo rows above it.  When the first pass of the
   // workgroup (NT / SMAX rows) spans the tile's height, every owned vertex of a
@@ -127,8 +143,8 @@ __device__ __forceinline__ void lsgs_tile_body(const Lev& L, int ntx, int nty, i
   // (Several sweeps in one pass update an owned vertex once per sweep, so
   // their corrections always collect in LDS.)
   constexpr bool kOnePass = NSW == 1 && TW <= NT / SMAX;
-  constexpr bool kSecond = kOnePass && PhaseItems<TW, H>::W0 * SMAX > NT;
-  static_assert(PhaseItems<TW, H>::W0 * SMAX <= 2 * NT || !kOnePass, "at most two vertices per thread and phase");
+  constexpr bool kSecond = kOnePass && PI::W0 * SMAX > NT;
+  static_assert(PI::W0 * SMAX <= 2 * NT || !kOnePass, "at most two vertices per thread and phase");
   // residual (y, lambda) of the region; the guard ring and the cells of the
   // region that lie outside the square hold zeros, so the neighbours of a
   // boundary vertex can be read and written without bounds checks (their
@@ -165,7 +181,7 @@ __device__ __forceinline__ void lsgs_tile_body(const Lev& L, int ntx, int nty, i
   auto item_of = [&](int ph, int k) {
     const int c7 = ph % 7;
     const int colour = ((reverse >> (ph / 7)) & 1) ? 6 - c7 : c7;
-    const int d = H - 1 - 2 * ph;  // Chebyshev radius of the phase window around the tile
+    const int d = CGS ? H - ph : H - 1 - 2 * ph;  // Chebyshev radius of the phase window around the tile
     const int wl = max(ci0, i0 - d), wh = min(ci1, i1 + d);
     const int wb = max(rj0, j0 - d), wt = min(rj1, j1 + d);
     // a fixed slot count (covering the widest window) keeps the decode free of
@@ -296,16 +312,60 @@ __device__ __forceinline__ void lsgs_tile_body(const Lev& L, int ntx, int nty, i
       s2[b0 + kDJ[d] * G::RP + kDI[d]] = (T2){v[d].x - (m * py + k * pl), v[d].y - (k * py - ai * (m * pl))};
     }
   };
+  // Collective smoother (CGS): the 2x2 system [[M_vv, K_vv], [K_vv,
+  // -alpha^-1 M_vv]] d = (r^y_v, r^l_v) is solved at the vertex, x += d, and
+  // r_m -= A_mv d on the closed neighbourhood (A symmetric: A_mv is the
+  // vertex's own stencil entry towards m).  Its own row is the interior
+  // stencil from one step inside the boundary on.
+  auto cgs_interior = [&](int b0, T& py, T& pl) {
+    const int bu = b0 + G::RP, bd = b0 - G::RP;
+    const T2 c = s2[b0], e = s2[b0 + 1], w = s2[b0 - 1], nn = s2[bu], ss = s2[bd], ne = s2[bu + 1], sw = s2[bd - 1];
+    const T b22 = -ai * Mc, det = Mc * b22 - Kc * Kc;
+    py = (b22 * c.x - Kc * c.y) / det;
+    pl = (Mc * c.y - Kc * c.x) / det;
+    const T dyc = Mc * py + Kc * pl, dya = Mo * py + Ka * pl, dyg = Mo * py + Kd * pl;
+    const T dlc = Kc * py - ai * (Mc * pl), dla = Ka * py - ai * (Mo * pl), dlg = Kd * py - ai * (Mo * pl);
+    s2[b0] = (T2){c.x - dyc, c.y - dlc};
+    s2[b0 + 1] = (T2){e.x - dya, e.y - dla};
+    s2[b0 - 1] = (T2){w.x - dya, w.y - dla};
+    s2[bu] = (T2){nn.x - dya, nn.y - dla};
+    s2[bd] = (T2){ss.x - dya, ss.y - dla};
+    s2[bu + 1] = (T2){ne.x - dyg, ne.y - dlg};
+    s2[bd - 1] = (T2){sw.x - dyg, sw.y - dlg};
+  };
+  auto cgs_class = [&](int b0, int gi, int gj, T& py, T& pl) {
+    const T* cb = &tC[(cls5(gi, n) * 5 + cls5(gj, n)) * kC5];
+    T2 v[kNDir];
+#pragma unroll
+    for (int d = 0; d < kNDir; d++) v[d] = s2[b0 + kDJ[d] * G::RP + kDI[d]];
+    const T m0 = cb[0], k0 = cb[kNDir];
+    const T b22 = -ai * m0, det = m0 * b22 - k0 * k0;
+    py = (b22 * v[0].x - k0 * v[0].y) / det;
+    pl = (m0 * v[0].y - k0 * v[0].x) / det;
+#pragma unroll
+    for (int d = 0; d < kNDir; d++) {
+      const T m = cb[d], k = cb[kNDir + d];
+      s2[b0 + kDJ[d] * G::RP + kDI[d]] = (T2){v[d].x - (m * py + k * pl), v[d].y - (k * py - ai * (m * pl))};
+    }
+  };
   // update of item it (all lanes of the wave call this: the path choice is a ballot)
   auto update = [&](const Item& it, T& py, T& pl) {
-    const bool inner = it.gi >= 2 && it.gi <= n - 2 && it.gj >= 2 && it.gj <= n - 2;
+    constexpr int e = CGS ? 1 : 2;  // first index whose update takes the interior constants
+    const bool inner = it.gi >= e && it.gi <= n - e && it.gj >= e && it.gj <= n - e;
     const bool wave_inner = __builtin_amdgcn_ballot_w64(it.act && !inner) == 0;
     if (it.act) {
       const int b0 = (it.gj - rj0 + 1) * G::RP + (it.gi - ci0) + 1;
-      if (wave_inner)
-        update_interior(b0, py, pl);
-      else
-        update_class(b0, it.gi, it.gj, py, pl);
+      if constexpr (CGS) {
+        if (wave_inner)
+          cgs_interior(b0, py, pl);
+        else
+          cgs_class(b0, it.gi, it.gj, py, pl);
+      } else {
+        if (wave_inner)
+          update_interior(b0, py, pl);
+        else
+          update_class(b0, it.gi, it.gj, py, pl);
+      }
     }
   };
 
@@ -329,7 +389,7 @@ __device__ __forceinline__ void lsgs_tile_body(const Lev& L, int ntx, int nty, i
     }
   } else {
     for (int ph = 0; ph < 7 * NSW; ph++) {
-      const int d = H - 1 - 2 * ph;
+      const int d = CGS ? H - ph : H - 1 - 2 * ph;
       const int wl = max(ci0, i0 - d), wh = min(ci1, i1 + d);
       const int wb = max(rj0, j0 - d), wt = min(rj1, j1 + d);
       const int nitems = (wt - wb) * ((wh - wl + 6) / 7);
@@ -406,6 +466,15 @@ __global__ __launch_bounds__(NT) void k_lsgs_tile(Lev L, int ntx, int nty, int r
   lsgs_tile_body<T, TW, NT, NSW>(L, ntx, nty, reverse, xin, x, rin, rout, part, norm_mode);
 }
 
+// NSW sweeps of the collective point smoother (the colour order of every
+// sweep is 0..6; reverse is unused)
+template <typename T, int TW, int NT, int NSW = 1>
+__global__ __launch_bounds__(NT) void k_cgs_tile(Lev L, int ntx, int nty, int reverse, const T* xin, T* x,
+                                                 const T* __restrict__ rin, T* __restrict__ rout,
+                                                 double* __restrict__ part, int norm_mode) {
+  lsgs_tile_body<T, TW, NT, NSW, true>(L, ntx, nty, 0, xin, x, rin, rout, part, norm_mode);
+}
+
 // many instances of one level: instance blockIdx.y, residual read from r
 // (sel 0) or r2 (sel 1) and written to the other
 template <typename T, int TW, int NT>
@@ -453,30 +522,35 @@ struct SweepShape<float> {
 };
 constexpr int kSmallTW = 16, kSmallNT = 256;
 
-template <typename T, int TW, int NT>
+template <typename T, int TW, int NT, bool CGS>
 hipError_t launch_tile(const Lev& L, int reverse, const T* xin, T* x, const T* rin, T* rout, hipStream_t s,
                        double* part, int norm_mode, int* nparts) {
   const int nt = tiles_along(L.n + 1, TW);
   if (nparts) *nparts = nt * nt;
-  hipLaunchKernelGGL((k_lsgs_tile<T, TW, NT>), dim3(round8(nt * nt)), dim3(NT), 0, s, L, nt, nt, reverse, xin, x, rin,
-                     rout, part, norm_mode);
+  if constexpr (CGS)
+    hipLaunchKernelGGL((k_cgs_tile<T, TW, NT>), dim3(round8(nt * nt)), dim3(NT), 0, s, L, nt, nt, 0, xin, x, rin,
+                       rout, part, norm_mode);
+  else
+    hipLaunchKernelGGL((k_lsgs_tile<T, TW, NT>), dim3(round8(nt * nt)), dim3(NT), 0, s, L, nt, nt, reverse, xin, x,
+                       rin, rout, part, norm_mode);
   return hipGetLastError();
 }
 
-template <typename T>
+// the collective smoother (CGS = true) takes the LSGS tile shapes
+template <typename T, bool CGS = false>
 hipError_t launch_tile_cfg(const Lev& L, int reverse, const T* xin, T* x, const T* rin, T* rout, hipStream_t s,
                            double* part = nullptr, int norm_mode = 0, int* nparts = nullptr) {
   if (L.n <= SweepShape<T>::kSmallMaxN)
-    return launch_tile<T, kSmallTW, kSmallNT>(L, reverse, xin, x, rin, rout, s, part, norm_mode, nparts);
+    return launch_tile<T, kSmallTW, kSmallNT, CGS>(L, reverse, xin, x, rin, rout, s, part, norm_mode, nparts);
   if constexpr (std::is_same<T, double>::value) {
     if (L.n == 1024 || L.n == 2048)
-      return launch_tile<T, 65, 1024>(L, reverse, xin, x, rin, rout, s, part, norm_mode, nparts);
-    if (L.n >= 4096) return launch_tile<T, 56, 1024>(L, reverse, xin, x, rin, rout, s, part, norm_mode, nparts);
+      return launch_tile<T, 65, 1024, CGS>(L, reverse, xin, x, rin, rout, s, part, norm_mode, nparts);
+    if (L.n >= 4096) return launch_tile<T, 56, 1024, CGS>(L, reverse, xin, x, rin, rout, s, part, norm_mode, nparts);
   } else {
-    if (L.n == 2048) return launch_tile<T, 46, 512>(L, reverse, xin, x, rin, rout, s, part, norm_mode, nparts);
+    if (L.n == 2048) return launch_tile<T, 46, 512, CGS>(L, reverse, xin, x, rin, rout, s, part, norm_mode, nparts);
   }
-  return launch_tile<T, SweepShape<T>::TW, SweepShape<T>::NT>(L, reverse, xin, x, rin, rout, s, part, norm_mode,
-                                                              nparts);
+  return launch_tile<T, SweepShape<T>::TW, SweepShape<T>::NT, CGS>(L, reverse, xin, x, rin, rout, s, part, norm_mode,
+                                                                   nparts);
 }
 
 }  // namespace
@@ -544,19 +618,24 @@ hipError_t launch_lsgs_sweep_from<float>(const Lev& L, int reverse, const float*
 // 33 x 33 tiles (256 of them) on 513^2.  r is read from rin and the residual
 // after both sweeps written to rout.
 constexpr int kSweep2MaxN = 512;
+template <typename T, bool CGS>
+hipError_t sweep2(const Lev& L, int revmask, const T* xin, T* x, const T* rin, T* rout, hipStream_t s) {
+  if (L.n > kSweep2MaxN) return hipErrorInvalidValue;
+  auto go = [&](auto kern, int TW) {
+    const int nt = tiles_along(L.n + 1, TW);
+    hipLaunchKernelGGL(kern, dim3(round8(nt * nt)), dim3(1024), 0, s, L, nt, nt, revmask, xin, x, rin, rout,
+                       (double*)nullptr, 0);
+    return hipGetLastError();
+  };
+  if constexpr (CGS)
+    return L.n <= 256 ? go(k_cgs_tile<T, 17, 1024, 2>, 17) : go(k_cgs_tile<T, 33, 1024, 2>, 33);
+  else
+    return L.n <= 256 ? go(k_lsgs_tile<T, 17, 1024, 2>, 17) : go(k_lsgs_tile<T, 33, 1024, 2>, 33);
+}
+
 template <typename T>
 hipError_t launch_lsgs_sweep2(const Lev& L, int revmask, const T* xin, T* x, const T* rin, T* rout, hipStream_t s) {
-  if (L.n > kSweep2MaxN) return hipErrorInvalidValue;
-  if (L.n <= 256) {
-    const int nt = tiles_along(L.n + 1, 17);
-    hipLaunchKernelGGL((k_lsgs_tile<T, 17, 1024, 2>), dim3(round8(nt * nt)), dim3(1024), 0, s, L, nt, nt, revmask,
-                       xin, x, rin, rout, (double*)nullptr, 0);
-  } else {
-    const int nt = tiles_along(L.n + 1, 33);
-    hipLaunchKernelGGL((k_lsgs_tile<T, 33, 1024, 2>), dim3(round8(nt * nt)), dim3(1024), 0, s, L, nt, nt, revmask,
-                       xin, x, rin, rout, (double*)nullptr, 0);
-  }
-  return hipGetLastError();
+  return sweep2<T, false>(L, revmask, xin, x, rin, rout, s);
 }
 template hipError_t launch_lsgs_sweep2<double>(const Lev&, int, const double*, double*, const double*, double*,
                                                hipStream_t);
@@ -568,6 +647,29 @@ hipError_t launch_lsgs_sweep_norm(const Lev& L, int reverse, const double* xin, 
                                   double* rout, double* part, int norm_mode, int* nparts, hipStream_t s) {
   if (!part || (norm_mode != 1 && norm_mode != 2)) return hipErrorInvalidValue;
   return launch_tile_cfg<double>(L, reverse, xin, x, rin, rout, s, part, norm_mode, nparts);
+}
+
+// ---- collective point smoother: one or two fused sweeps per launch
+template <typename T>
+hipError_t launch_cgs_sweep_from(const Lev& L, const T* xin, T* x, const T* rin, T* rout, hipStream_t s) {
+  return launch_tile_cfg<T, true>(L, 0, xin, x, rin, rout, s);
+}
+template hipError_t launch_cgs_sweep_from<double>(const Lev&, const double*, double*, const double*, double*,
+                                                  hipStream_t);
+template hipError_t launch_cgs_sweep_from<float>(const Lev&, const float*, float*, const float*, float*, hipStream_t);
+
+template <typename T>
+hipError_t launch_cgs_sweep2(const Lev& L, const T* xin, T* x, const T* rin, T* rout, hipStream_t s) {
+  return sweep2<T, true>(L, 0, xin, x, rin, rout, s);
+}
+template hipError_t launch_cgs_sweep2<double>(const Lev&, const double*, double*, const double*, double*,
+                                              hipStream_t);
+template hipError_t launch_cgs_sweep2<float>(const Lev&, const float*, float*, const float*, float*, hipStream_t);
+
+hipError_t launch_cgs_sweep_norm(const Lev& L, const double* xin, double* x, const double* rin, double* rout,
+                                 double* part, int norm_mode, int* nparts, hipStream_t s) {
+  if (!part || (norm_mode != 1 && norm_mode != 2)) return hipErrorInvalidValue;
+  return launch_tile_cfg<double, true>(L, 0, xin, x, rin, rout, s, part, norm_mode, nparts);
 }
 
 }  // namespace mgk

@@ -110,10 +110,11 @@ def test_coarse_solve(torch_cuda, alpha, coarse):
     assert np.linalg.norm(got - ref) <= 1e-11 * np.linalg.norm(ref)
 
 
-@pytest.mark.parametrize("smoother", ["lsgs", "slsgs"])
+@pytest.mark.parametrize("smoother", ["lsgs", "slsgs", "cgs"])
 @pytest.mark.parametrize("level", [7, 10])
 def test_fused_sweep_matches_phase_kernels(torch_cuda, monkeypatch, level, smoother):
     # one fused kernel per sweep vs one launch per colour phase: same arithmetic
+    # (LSGS: 14-vertex halo; collective smoother: 7-vertex halo)
     torch = torch_cuda
     mg = _mg()
     alpha = 1e-3
@@ -281,12 +282,13 @@ def test_dense_map_equals_tail(torch_cuda, monkeypatch, smoother, gamma, level):
         assert np.linalg.norm(xs[0] - xs[1]) <= bound * np.linalg.norm(xs[1]), precision
 
 
-@pytest.mark.parametrize("smoother,nu,gamma", [("lsgs", 2, 1), ("lsgs", 3, 1), ("slsgs", 1, 1), ("slsgs", 2, 2)])
+@pytest.mark.parametrize("smoother,nu,gamma", [("lsgs", 2, 1), ("lsgs", 3, 1), ("slsgs", 1, 1), ("slsgs", 2, 2),
+                                               ("cgs", 2, 1), ("cgs", 3, 2)])
 @pytest.mark.parametrize("level", [9, 10])
 def test_sweep_pairs_match_single_sweeps(torch_cuda, monkeypatch, smoother, nu, gamma, level):
-    # two sweeps per launch on the coarse levels up to 513^2 (halo 28,
-    # corrections of both sweeps in LDS; 17 x 17 and 33 x 33 tiles) against
-    # one launch per sweep (MGKKT_NO_SWEEP2=1)
+    # two sweeps per launch on the coarse levels up to 513^2 (halo 28, or 14
+    # for the collective smoother; corrections of both sweeps in LDS; 17 x 17
+    # and 33 x 33 tiles) against one launch per sweep (MGKKT_NO_SWEEP2=1)
     torch = torch_cuda
     mg = _mg()
     alpha = 1e-3
@@ -308,7 +310,7 @@ def test_sweep_pairs_match_single_sweeps(torch_cuda, monkeypatch, smoother, nu, 
         assert np.linalg.norm(xs[0] - xs[1]) <= bound * np.linalg.norm(xs[1]), precision
 
 
-@pytest.mark.parametrize("smoother,nu", [("lsgs", 2), ("slsgs", 1)])
+@pytest.mark.parametrize("smoother,nu", [("lsgs", 2), ("slsgs", 1), ("cgs", 2)])
 def test_sweep_norm_solve(torch_cuda, monkeypatch, smoother, nu):
     # FP64 solves take each iterate's norm from the residual the last sweep
     # leaves; at convergence the recomputed f - A x is checked.  Against the
@@ -352,6 +354,8 @@ CYCLE_CASES = [
     (7, 1e-4, "ne", 1),
     (7, 1.0, "slsgs", 1),
     (7, 1e-8, "cgs", 1),
+    (8, 1.0, "cgs", 2),
+    (10, 1e-3, "cgs", 1),
     (8, 1e-6, "lsgs", 2),
     (10, 1e-2, "lsgs", 1),
     (10, 1e-5, "slsgs", 1),
@@ -379,7 +383,7 @@ def test_cycle_parity(torch_cuda, level, alpha, smoother, gamma):
 
 @pytest.mark.parametrize("norm", ["l2", "linv"])
 @pytest.mark.parametrize("alpha", ALPHAS)
-@pytest.mark.parametrize("smoother", ["ne", "lsgs"])
+@pytest.mark.parametrize("smoother", ["ne", "lsgs", "cgs"])
 def test_solve_parity(torch_cuda, alpha, smoother, norm):
     torch = torch_cuda
     mg = _mg()
@@ -451,15 +455,16 @@ def test_error_paths(torch_cuda):
     assert st in (mg.MG_EDIVERGE, mg.MG_ENAN, mg.MG_ENOTCONV)
 
 
+@pytest.mark.parametrize("smoother", ["lsgs", "cgs"])
 @pytest.mark.parametrize("alpha", [1e-8, 1e-4, 1.0])
-def test_fp32_refinement_reaches_tolerance(torch_cuda, alpha):
+def test_fp32_refinement_reaches_tolerance(torch_cuda, alpha, smoother):
     torch = torch_cuda
     mg = _mg()
     level = 8
     h = oracle.Hierarchy(level, alpha, coarse=1)
     yd = workloads.desired_state(level, 2)
-    xo, _, _ = h.solve(h.rhs(yd), tol=1e-12, smoother="lsgs", order="col7")
-    s = mg.Solver(level, alpha, precision="fp32_ir")
+    xo, _, _ = h.solve(h.rhs(yd), tol=1e-12, smoother=smoother, order="col7")
+    s = mg.Solver(level, alpha, precision="fp32_ir", smoother=smoother)
     xg, it, rel, st = s.solve(s.rhs(_dev(torch, yd)), tol=1e-10)
     assert st == mg.MG_OK and rel <= 1e-10
     # final error of FP32 cycles + FP64 refinement against the FP64 oracle,
@@ -468,13 +473,14 @@ def test_fp32_refinement_reaches_tolerance(torch_cuda, alpha):
     print(f"fp32 refinement vs FP64 oracle, level {level}, alpha {alpha}: {err}")
 
 
-def test_full_size_cycle_parity(torch_cuda):
-    # the benchmark's size (2049^2 vertices), one V(2,2) LSGS cycle from zero
+@pytest.mark.parametrize("smoother", ["lsgs", "cgs"])
+def test_full_size_cycle_parity(torch_cuda, smoother):
+    # the benchmark's size (2049^2 vertices), one V(2,2) cycle from zero
     torch = torch_cuda
     mg = _mg()
     level, alpha = 11, 1e-4
     yd = workloads.desired_state(level, 2)
-    s = mg.Solver(level, alpha)
+    s = mg.Solver(level, alpha, smoother=smoother)
     fg = s.rhs(_dev(torch, yd))
     xg = torch.zeros(s.vec_len(), dtype=torch.float64, device="cuda")
     s.cycle(fg, xg)
@@ -483,7 +489,7 @@ def test_full_size_cycle_parity(torch_cuda):
     f = h.rhs(yd)
     assert _relmax(_host(fg), f) < 1e-14
     xo = np.zeros(h.ndof())
-    h.cycle(f, xo, smoother="lsgs", order="col7")
+    h.cycle(f, xo, smoother=smoother, order="col7")
     assert_fields(xgh, xo, 1e-12, alpha=alpha)
 
 
