@@ -469,6 +469,7 @@ def main() -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batch", action="store_true", help="skip the 64-instance batched solve")
     ap.add_argument("--no-fp32-ir", action="store_true", help="skip the FP32-refinement rerun of the main workload")
+    ap.add_argument("--no-cgs", action="store_true", help="skip the collective-smoother solves of the main workload")
     ap.add_argument("--batch-only", action="store_true", help="run only the 64-instance batched solve")
     ap.add_argument("--no-stokes", action="store_true", help="skip the Stokes-control solves")
     ap.add_argument("--stokes-only", action="store_true", help="run only the Stokes-control solves")
@@ -612,6 +613,23 @@ def main() -> int:
             x32 = run(args.smoother, "fp32_ir", al, 1, 0, keep=True)["x"]
             errs[f"alpha={al:g}"] = field_errors(x32, x64, al)
         result["fp32_ir"]["field_errors_vs_fp64"] = errs
+    if args.smoother == "lsgs" and not args.no_cgs:
+        # the collective point smoother (section 2) on the same workload: the
+        # paper's fastest smoother for Poisson control (Table 1), one fused
+        # tile kernel per sweep moving the same 8 words per vertex
+        log("bench: the same solves with the collective point smoother")
+        cg = {}
+        for pr in ("fp64", "fp32_ir"):
+            rr = run("cgs", pr, args.alpha, max(2, args.steps // 2), max(1, args.warmup // 2))
+            rt = run("cgs", pr, args.alpha, 2, 0, timing=True)
+            wb = 4 if pr == "fp32_ir" else 8
+            ach = 8 * V * wb / (rt["sweep_ms"] * 1e-3) / 1e9
+            cg[pr] = {"vcycles_per_s": rr["vcycles_per_s"], "ms_per_solve": rr["ms_per_solve"],
+                      "cycles_per_solve": rr["cycles_per_solve"], "final_relres": rr["relres"], "status": rr["status"],
+                      "finest_sweep_ms": rt["sweep_ms"], "finest_sweep_GBps": ach,
+                      "finest_sweep_frac_of_8TBps": ach / HBM_PEAK_GBS,
+                      "time_to_tol_speedup_vs_lsgs_fp64": main_run["ms_per_solve"] / rr["ms_per_solve"]}
+        result["cgs"] = cg
     if args.variants:
         # NE and LSGS, FP64 and FP32 refinement, alpha 1e-8 / 1e-4 / 1 on the same
         # workload; the FP32-refinement iterate is compared with the FP64 one

@@ -12,8 +12,9 @@
 // the device by stencil classes: the mesh is uniform, so rows that agree in
 // column fields, lattice offsets and values share one entry list, and a
 // level's matrix takes a few hundred classes instead of a CSR array.  The
-// kernels walk rows through the classes: 16 lanes per row for the residual
-// and the normal-equation smoother; for a colour phase of the LSGS sweep
+// kernels walk rows through the classes: one thread per row for the
+// residual and the prolongation, 16 lanes per row for the restriction and
+// the normal-equation smoother; for a colour phase of the LSGS sweep
 // (Alg. 2), 32 lanes per group of two unknowns with the two rows merged (on
 // small levels, every phase of every step in one workgroup with the
 // residual in LDS); a wave per patch for the patch (Vanka-type) smoother.
@@ -636,8 +637,9 @@ struct ClassRows {
   __device__ T val_of(int k) const { return val[k]; }
 };
 
-// Row kernels: 16 lanes per row (16 rows per 256-thread block), each lane
-// taking every 16th entry, partial sums combined by shuffles.
+// Row kernels with 16 lanes per row (16 rows per 256-thread block), each
+// lane taking every 16th entry, partial sums combined by shuffles: the
+// restriction (rows of 10 to 25 entries) and the normal-equation smoother.
 constexpr int kRL = 16;
 constexpr int kRows = kSNT / kRL;
 
@@ -649,28 +651,25 @@ __device__ inline T row_sum(T v) {
 }
 
 // r = f - A x, with per-block partial sums of ||r||_2^2 (MODE 1) or
-// r^T L^-1 r (MODE 2); f == nullptr gives r = A x
+// r^T L^-1 r (MODE 2); f == nullptr gives r = A x.  One thread per row,
+// grid-stride: consecutive threads take consecutive rows of one field, i.e.
+// neighbouring lattice positions, which mostly share a stencil class, so the
+// class entries a wave reads are common to its lanes and the x of one entry
+// are contiguous.
 template <typename T, int MODE, typename AT>
 __global__ __launch_bounds__(kSNT) void ks_resid(int n, AT A, const T* __restrict__ f, const T* __restrict__ x,
                                                  T* __restrict__ r, const double* __restrict__ Ldi,
                                                  double* __restrict__ part) {
-  const int ln = threadIdx.x % kRL;
   double s2 = 0.0;
-  for (int i0 = blockIdx.x * kRows; i0 < n; i0 += gridDim.x * kRows) {  // uniform per block
-    const int i = i0 + threadIdx.x / kRL;
+  for (int i = blockIdx.x * kSNT + threadIdx.x; i < n; i += gridDim.x * kSNT) {
+    int kb, ke, pos;
+    A.row(i, kb, ke, pos);
     T s = 0;
-    if (i < n) {
-      int kb, ke, pos;
-      A.row(i, kb, ke, pos);
-      for (int k = kb + ln; k < ke; k += kRL) s += A.val_of(k) * x[A.col_of(k, pos)];
-    }
-    s = row_sum(s);
-    if (i < n && ln == 0) {
-      const T ri = f ? f[i] - s : s;
-      r[i] = ri;
-      if (MODE == 1) s2 += (double)ri * (double)ri;
-      if (MODE == 2) s2 += (double)ri * (double)ri * Ldi[i];
-    }
+    for (int k = kb; k < ke; k++) s += A.val_of(k) * x[A.col_of(k, pos)];
+    const T ri = f ? f[i] - s : s;
+    r[i] = ri;
+    if (MODE == 1) s2 += (double)ri * (double)ri;
+    if (MODE == 2) s2 += (double)ri * (double)ri * Ldi[i];
   }
   if (MODE) block_store(s2, &part[blockIdx.x]);
 }
@@ -683,6 +682,19 @@ __global__ __launch_bounds__(kSNT) void ks_vnorm(int n, const double* __restrict
   double s2 = 0.0;
   if (i < n) s2 = MODE == 1 ? v[i] * v[i] : v[i] * v[i] * Ldi[i];
   block_store(s2, &part[blockIdx.x]);
+}
+
+// y += A x with one thread per row (grid-stride), for operators with a few
+// entries per row (the prolongation: 1 to 3)
+template <typename T, typename AT>
+__global__ __launch_bounds__(kSNT) void ks_spmv_add1(int n, AT A, const T* __restrict__ x, T* __restrict__ y) {
+  for (int i = blockIdx.x * kSNT + threadIdx.x; i < n; i += gridDim.x * kSNT) {
+    int kb, ke, pos;
+    A.row(i, kb, ke, pos);
+    T s = 0;
+    for (int k = kb; k < ke; k++) s += A.val_of(k) * x[A.col_of(k, pos)];
+    y[i] += s;
+  }
 }
 
 // y = A x (ADD 0) or y += A x (ADD 1); restriction variant also writes x_c = 0, r_c = f_c
@@ -1163,6 +1175,8 @@ __global__ __launch_bounds__(kSNT) void ks_rhs(int nv, int ndof, const int* __re
 inline int blocks_for(int n, int nt = kSNT) { return (n + nt - 1) / nt; }
 // blocks of the row kernels (grid-stride over groups of kRows rows)
 inline int row_blocks(int n) { return std::min(blocks_for(n, kRows), 4096); }
+// blocks of the one-thread-per-row kernels (grid-stride over kSNT rows)
+inline int thread_blocks(int n) { return std::min(blocks_for(n), 4096); }
 
 template <typename T>
 struct Dev {
@@ -1737,7 +1751,7 @@ CsrRows<T> r_rows(StokesLevel& L) {
 
 template <typename T>
 hipError_t s_resid(StokesLevel& L, const T* f, const T* x, T* r, hipStream_t s) {
-  hipLaunchKernelGGL((ks_resid<T, 0, ClassRows<T>>), dim3(row_blocks(L.ndof)), dim3(kSNT), 0, s, L.ndof, a_rows<T>(L),
+  hipLaunchKernelGGL((ks_resid<T, 0, ClassRows<T>>), dim3(thread_blocks(L.ndof)), dim3(kSNT), 0, s, L.ndof, a_rows<T>(L),
                      f, x, r, (const double*)nullptr, (double*)nullptr);
   return hipGetLastError();
 }
@@ -1768,6 +1782,7 @@ hipError_t s_smooth(Stokes* S, StokesLevel& L, T* x, T* r, int steps, hipStream_
           for (int k = 0; k < nph; k++) {
             const int ph = sw == 0 ? k : nph - 1 - k;
             const int g0 = L.gph[ph], ng = L.gph[ph + 1] - g0;
+            if (ng == 0) continue;  // a colour without nodes on a small level
             hipLaunchKernelGGL((ks_lsgs_grp<T>), dim3(blocks_for(ng, kGNT / kGLR)), dim3(kGNT), 0, s, g0, ng,
                                (const int4*)L.mgroups, (const int*)L.g_ent, SV<T>::G(L), SV<T>::GL(L), SV<T>::GN(L),
                                L.geo, x, r);
@@ -1823,8 +1838,8 @@ hipError_t s_cycle(Stokes* S, int l, const T* f, T* x, T* r, bool current, hipSt
   SCHK(hipGetLastError());
   for (int g = 0; g < S->gamma; g++)
     SCHK(s_cycle<T>(S, l - 1, SV<T>::f(C), SV<T>::x(C), SV<T>::r(C), g == 0, s));
-  hipLaunchKernelGGL((ks_spmv<T, 1, CsrRows<T>>), dim3(row_blocks(L.ndof)), dim3(kSNT), 0, s, L.ndof, p_rows<T>(L),
-                     (const T*)SV<T>::x(C), x, (T*)nullptr, (T*)nullptr);
+  hipLaunchKernelGGL((ks_spmv_add1<T, CsrRows<T>>), dim3(thread_blocks(L.ndof)), dim3(kSNT), 0, s, L.ndof,
+                     p_rows<T>(L), (const T*)SV<T>::x(C), x);
   SCHK(hipGetLastError());
   SCHK(s_resid<T>(L, f, x, r, s));
   return s_smooth<T>(S, L, x, r, S->nu2, s);
@@ -1910,20 +1925,20 @@ hipError_t stokes_rhs(Stokes* S, const double* vd, double* f, hipStream_t s) {
 
 hipError_t stokes_apply(Stokes* S, int l, const double* x, double* y, hipStream_t s) {
   StokesLevel& L = S->L(l);
-  hipLaunchKernelGGL((ks_resid<double, 0, ClassRows<double>>), dim3(row_blocks(L.ndof)), dim3(kSNT), 0, s, L.ndof,
+  hipLaunchKernelGGL((ks_resid<double, 0, ClassRows<double>>), dim3(thread_blocks(L.ndof)), dim3(kSNT), 0, s, L.ndof,
                      a_rows<double>(L), (const double*)nullptr, x, y, (const double*)nullptr, (double*)nullptr);
   return hipGetLastError();
 }
 
 int stokes_residual_parts(const Stokes* S, int l) {
   if (!S || l < S->k0 || l > S->level) return 0;
-  return row_blocks(S->lv[l - S->k0].ndof);
+  return thread_blocks(S->lv[l - S->k0].ndof);
 }
 
 hipError_t stokes_residual(Stokes* S, int l, const double* f, const double* x, double* r, double* part,
                            int norm_mode, int* nparts, hipStream_t s) {
   StokesLevel& L = S->L(l);
-  const int nb = row_blocks(L.ndof);
+  const int nb = thread_blocks(L.ndof);
   if (nparts) *nparts = nb;
   const ClassRows<double> A = a_rows<double>(L);
   if (!part)
@@ -1963,8 +1978,8 @@ hipError_t stokes_restrict(Stokes* S, int l, const double* r, double* fc, hipStr
 
 hipError_t stokes_prolong_add(Stokes* S, int l, const double* xc, double* x, hipStream_t s) {
   StokesLevel& L = S->L(l);
-  hipLaunchKernelGGL((ks_spmv<double, 1, CsrRows<double>>), dim3(row_blocks(L.ndof)), dim3(kSNT), 0, s, L.ndof,
-                     p_rows<double>(L), xc, x, (double*)nullptr, (double*)nullptr);
+  hipLaunchKernelGGL((ks_spmv_add1<double, CsrRows<double>>), dim3(thread_blocks(L.ndof)), dim3(kSNT), 0, s, L.ndof,
+                     p_rows<double>(L), xc, x);
   return hipGetLastError();
 }
 
