@@ -314,6 +314,31 @@ def _colour_phases(level):
     return phases
 
 
+@pytest.mark.parametrize("level", [3, 4])
+def test_patch_colours_are_independent(level):
+    """The patch smoother's 9 colours (i mod 3) + 3 (j mod 3): patches of one
+    colour share no column of their rows (so their updates commute), for
+    patches written from their definition."""
+    h = oracle.Hierarchy(level, 1e-2, coarse=1, problem="stokes")
+    A = h.matrix("A").tocsr()
+    n = 1 << level
+    pats = _patches(level)
+    assert len(pats) == (n + 1) ** 2
+    by_colour = {}
+    for q, dofs in enumerate(pats):
+        i, j = q % (n + 1), q // (n + 1)
+        cols = set()
+        for d in dofs:
+            cols.update(A.indices[A.indptr[d]:A.indptr[d + 1]].tolist())
+        by_colour.setdefault(i % 3 + 3 * (j % 3), []).append(cols)
+    assert len(by_colour) == 9
+    for colour, lst in by_colour.items():
+        seen = set()
+        for cols in lst:
+            assert not (cols & seen), colour
+            seen |= cols
+
+
 @pytest.mark.parametrize("alpha", [1.0, 1e-6])
 def test_stokes_colour_phases_are_independent(alpha):
     """Within a phase no two groups share a residual entry (no structural
