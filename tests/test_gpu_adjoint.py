@@ -123,3 +123,27 @@ def test_gradient_matches_central_differences_1025(torch_cuda):
     print(f"directional y_D: adjoint {g_dir:.12e} fd {fd_dir:.12e} rel {err_dir:.2e}; "
           f"alpha: adjoint {g_al:.12e} fd {fd_al:.12e} rel {err_al:.2e}", flush=True)
     assert err_dir <= 1e-6 and err_al <= 1e-6
+
+
+def test_differentiable_solve_raises_on_stall_above_floor(torch_cuda):
+    """A multigrid whose NE smoother is damped to tau = 1e-3 gains far less
+    than a factor 2 over 10 cycles: the solve stalls near the initial residual.
+    The C ABI reports MG_ESTALL; the differentiable solve must raise rather
+    than hand back the unconverged state (and a gradient with no signal)."""
+    import paper_1502_03917_amd as mg
+
+    level, alpha, tol = 5, 1e-2, 1e-10
+    opts = dict(smoother="ne", tau=1e-3)
+    yd = _dev(torch_cuda, workloads.desired_state(level, 1))
+    s = mg.Solver(level, alpha, **opts)
+    try:
+        _, it, rel, st = s.solve(s.rhs(yd), tol=tol, raise_on_error=False)
+    finally:
+        s.close()
+    assert st == mg.MG_ESTALL and it < 40 and rel > max(tol, mg.STALL_FLOOR)
+    with pytest.raises(mg.MGError) as e:
+        mg.solve(yd.clone().requires_grad_(True), alpha, level, tol=tol, **opts)
+    assert e.value.status == mg.MG_ESTALL
+    # the default smoother on the same data converges and returns
+    y, lam, u = mg.solve(yd, alpha, level, tol=tol)
+    assert bool(torch_cuda.isfinite(y).all())
