@@ -220,8 +220,13 @@ def print_summary(args) -> int:
     f_fetch = copy_bytes / (copy_kib(cfetch, "FETCH_SIZE") * 1024.0)
     f_write = copy_bytes / (copy_kib(cwrite, "WRITE_SIZE") * 1024.0)
     grid = finest_sweep_grid(args.level, args.precision)
-    sweep = [(k, v) for k, v in fetch.items() if "k_lsgs_tile" in k[0] and k[1] == grid]
-    wsweep = [(k, v) for k, v in write.items() if "k_lsgs_tile" in k[0] and k[1] == grid]
+    # the plain sweep (transfer argument IO = 0), not the launches that carry
+    # the prolongation or the restriction
+    def plain(name):
+        return "k_lsgs_tile<" in name and ", 0>(" in name
+
+    sweep = [(k, v) for k, v in fetch.items() if plain(k[0]) and k[1] == grid]
+    wsweep = [(k, v) for k, v in write.items() if plain(k[0]) and k[1] == grid]
     if len(sweep) != 1 or len(wsweep) != 1:
         print("expected one finest-level sweep entry per counter run", sweep, wsweep, file=sys.stderr)
         return 1

@@ -228,7 +228,12 @@ int mg_coarse_solve(mg_ctx *ctx, const double *f, double *x, void *stream);
  * prolongation and correction, r = f - A x, nu2 smoothing steps.  With
  * precision MG_FP32_IR the iterate is one refinement step: FP64 residual,
  * inner_cycles FP32 cycles from zero on it, FP64 update.  Stream-ordered, no
- * host synchronisation. */
+ * host synchronisation.  With the tile-sweep smoothers (MG_LSGS, MG_SLSGS,
+ * MG_CGS) and nu1, nu2 >= 1 the restriction runs inside the last
+ * pre-smoothing launch and the prolongation with the new residual inside the
+ * first post-smoothing launch of each level (the same arithmetic; the
+ * environment variable MGKKT_NO_FUSED_TRANSFERS=1 at mg_setup, or timing
+ * enabled with mg_timing_enable, launches them as kernels of their own). */
 int mg_cycle(mg_ctx *ctx, const double *f, double *x, void *stream);
 
 /* ---- one iterate as a replayable HIP graph (section 2's cycle) ------------
@@ -264,7 +269,9 @@ int mg_solve(mg_ctx *ctx, const double *f, double *x, double tol, int *cycles_ou
 
 /* Per-launch timing of the finest-level smoothing kernels with HIP events on
  * the launch stream: enable (1) / disable (0) and reset; read the total time in
- * milliseconds and the number of timed launches. */
+ * milliseconds and the number of timed launches.  While timing is enabled the
+ * cycles launch the grid transfers as kernels of their own, so that every
+ * timed launch is a plain smoothing step. */
 int mg_timing_enable(mg_ctx *ctx, int enable);
 int mg_timing_read(mg_ctx *ctx, double *total_ms, long *launches);
 

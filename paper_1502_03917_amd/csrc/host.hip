@@ -268,6 +268,10 @@ struct mg_ctx {
   bool fp32_ready = false;
   bool fused = true;  // one kernel per LSGS sweep (else one kernel per colour phase)
   bool sweep2 = true;  // two sweeps per launch on small coarse levels (MGKKT_NO_SWEEP2 unset)
+  // the restriction runs in the last pre-smoothing launch and the
+  // prolongation with the new residual in the first post-smoothing launch
+  // (MGKKT_NO_FUSED_TRANSFERS unset)
+  bool xfer_allowed = true;
   // coarse-level tail: one workgroup runs the sub-cycle on levels k0..tail_T
   int tail_T = 0;       // 0: no tail
   bool tail_allowed = true;
@@ -466,19 +470,29 @@ struct SweepNorm {
 
 template <typename T>
 hipError_t last_sweep(const Lev& L, int reverse, const T* xin, T* x, const T* rin, T* rout, const SweepNorm& sn,
-                      hipStream_t s, bool cgs = false) {
+                      hipStream_t s, bool cgs = false, const mgk::SweepIO<T>* io = nullptr) {
   if constexpr (std::is_same<T, double>::value) {
     if (sn.part)
-      return cgs ? mgk::launch_cgs_sweep_norm(L, xin, x, rin, rout, sn.part, sn.mode, sn.nb, s)
-                 : mgk::launch_lsgs_sweep_norm(L, reverse, xin, x, rin, rout, sn.part, sn.mode, sn.nb, s);
+      return cgs ? mgk::launch_cgs_sweep_norm(L, xin, x, rin, rout, sn.part, sn.mode, sn.nb, s, io)
+                 : mgk::launch_lsgs_sweep_norm(L, reverse, xin, x, rin, rout, sn.part, sn.mode, sn.nb, s, io);
   }
-  return cgs ? mgk::launch_cgs_sweep_from<T>(L, xin, x, rin, rout, s)
-             : mgk::launch_lsgs_sweep_from<T>(L, reverse, xin, x, rin, rout, s);
+  return cgs ? mgk::launch_cgs_sweep_from<T>(L, xin, x, rin, rout, s, io)
+             : mgk::launch_lsgs_sweep_from<T>(L, reverse, xin, x, rin, rout, s, io);
 }
+
+// Grid transfers carried by the tile-sweep launches of one smooth_steps call:
+// the first launch may form the prolongation with the new residual (first),
+// the last may write the restriction (last) and its iterate to last_x.
+template <typename T>
+struct SweepXfer {
+  const mgk::SweepIO<T>* first = nullptr;
+  const mgk::SweepIO<T>* last = nullptr;
+  T* last_x = nullptr;
+};
 
 template <typename T>
 int smooth_steps(mg_ctx* c, int l, T* x, T*& r, T* alt, T* p, int steps, hipStream_t s, const T* xin0 = nullptr,
-                 const SweepNorm& sn = SweepNorm{}) {
+                 const SweepNorm& sn = SweepNorm{}, const SweepXfer<T>& xf = SweepXfer<T>{}) {
   LevelBuf& b = L_(c, l);
   const Lev& L = b.lev;
   const bool timed = c->timing && l == c->level && !c->capturing;
@@ -492,6 +506,13 @@ int smooth_steps(mg_ctx* c, int l, T* x, T*& r, T* alt, T* p, int steps, hipStre
     const T* xin = (it == 0 && xin0) ? xin0 : x;
     const SweepNorm none{};
     const SweepNorm& snl = (it == steps - 1) ? sn : none;
+    // transfers of this step's launches: the prolongation on the first
+    // launch of the call, the restriction (with the iterate written to
+    // xf.last_x) on the last
+    const bool first = it == 0;
+    const bool last_single = it == steps - 1;          // a one-sweep launch ending the call
+    const bool last_pair = pairs && it + 2 == steps;  // a two-sweep launch ending the call
+    const mgk::SweepIO<T>* io1 = first ? xf.first : nullptr;
     size_t slot = 0;
     hipEvent_t stop = nullptr;
     if (timed) stop = timing_begin(c, s, &slot);
@@ -501,11 +522,15 @@ int smooth_steps(mg_ctx* c, int l, T* x, T*& r, T* alt, T* p, int steps, hipStre
         break;
       case MG_LSGS:
         if (pairs && it + 1 < steps) {
-          HIPCHK(c, mgk::launch_lsgs_sweep2<T>(L, 0, xin, x, r, alt, s));
+          const mgk::SweepIO<T>* io = last_pair && xf.last ? xf.last : io1;
+          T* xo = last_pair && xf.last ? xf.last_x : x;
+          HIPCHK(c, mgk::launch_lsgs_sweep2<T>(L, 0, xin, xo, r, alt, s, io));
           std::swap(r, alt);
           it++;
         } else if (fused) {
-          HIPCHK(c, last_sweep<T>(L, 0, xin, x, r, alt, snl, s));
+          const mgk::SweepIO<T>* io = last_single && xf.last ? xf.last : io1;
+          T* xo = last_single && xf.last ? xf.last_x : x;
+          HIPCHK(c, last_sweep<T>(L, 0, xin, xo, r, alt, snl, s, false, io));
           std::swap(r, alt);
         } else {
           for (int col = 0; col < 7; col++) HIPCHK(c, mgk::launch_lsgs_phase<T>(L, col, x, r, s));
@@ -513,11 +538,15 @@ int smooth_steps(mg_ctx* c, int l, T* x, T*& r, T* alt, T* p, int steps, hipStre
         break;
       case MG_SLSGS:
         if (pairs) {
-          HIPCHK(c, mgk::launch_lsgs_sweep2<T>(L, 2, xin, x, r, alt, s));
+          const mgk::SweepIO<T>* io = last_single && xf.last ? xf.last : io1;
+          T* xo = last_single && xf.last ? xf.last_x : x;
+          HIPCHK(c, mgk::launch_lsgs_sweep2<T>(L, 2, xin, xo, r, alt, s, io));
           std::swap(r, alt);
         } else if (fused) {
-          HIPCHK(c, mgk::launch_lsgs_sweep_from<T>(L, 0, xin, x, r, alt, s));
-          HIPCHK(c, last_sweep<T>(L, 1, x, x, alt, r, snl, s));
+          HIPCHK(c, mgk::launch_lsgs_sweep_from<T>(L, 0, xin, x, r, alt, s, io1));
+          const mgk::SweepIO<T>* io = last_single && xf.last ? xf.last : nullptr;
+          T* xo = last_single && xf.last ? xf.last_x : x;
+          HIPCHK(c, last_sweep<T>(L, 1, x, xo, alt, r, snl, s, false, io));
         } else {
           for (int col = 0; col < 7; col++) HIPCHK(c, mgk::launch_lsgs_phase<T>(L, col, x, r, s));
           for (int col = 6; col >= 0; col--) HIPCHK(c, mgk::launch_lsgs_phase<T>(L, col, x, r, s));
@@ -525,11 +554,15 @@ int smooth_steps(mg_ctx* c, int l, T* x, T*& r, T* alt, T* p, int steps, hipStre
         break;
       case MG_CGS:
         if (pairs && it + 1 < steps) {
-          HIPCHK(c, mgk::launch_cgs_sweep2<T>(L, xin, x, r, alt, s));
+          const mgk::SweepIO<T>* io = last_pair && xf.last ? xf.last : io1;
+          T* xo = last_pair && xf.last ? xf.last_x : x;
+          HIPCHK(c, mgk::launch_cgs_sweep2<T>(L, xin, xo, r, alt, s, io));
           std::swap(r, alt);
           it++;
         } else if (fused) {
-          HIPCHK(c, last_sweep<T>(L, 0, xin, x, r, alt, snl, s, true));
+          const mgk::SweepIO<T>* io = last_single && xf.last ? xf.last : io1;
+          T* xo = last_single && xf.last ? xf.last_x : x;
+          HIPCHK(c, last_sweep<T>(L, 0, xin, xo, r, alt, snl, s, true, io));
           std::swap(r, alt);
         } else {
           for (int col = 0; col < 7; col++) HIPCHK(c, mgk::launch_cgs_phase<T>(L, col, x, r, s));
@@ -766,13 +799,36 @@ int cycle_body(mg_ctx* c, int l, const T* f, T* x, T* r, bool residual_current, 
   T* alt = (r == wb.r) ? wb.r2 : wb.r;
   int st;
   if (!residual_current) HIPCHK(c, mgk::launch_residual<T>(b.lev, f, x, r, nullptr, 0, nullptr, s));
-  if ((st = smooth_steps<T>(c, l, x, r, alt, wb.p, c->o.nu1, s)) != MG_OK) return st;
-  alt = (r == wb.r) ? wb.r2 : wb.r;
   // defect restriction; the coarse iterate starts from zero with r_c = f_c
   const bool coarse_is_k0 = (l - 1 == c->k0);
   const bool tail = (l - 1 == c->tail_T);
-  HIPCHK(c, mgk::launch_restrict<T>(b.lev, bc.lev, r, wc.f, (coarse_is_k0 || tail) ? nullptr : wc.x,
-                                    (coarse_is_k0 || tail) ? nullptr : wc.r, s));
+  T* xc0 = (coarse_is_k0 || tail) ? nullptr : wc.x;
+  T* rc = (coarse_is_k0 || tail) ? nullptr : wc.r;
+  // With tile-sweep smoothers on both sides the restriction runs in the last
+  // pre-smoothing launch, which writes the smoothed iterate to the level's
+  // scratch p; the post-smoothing then starts from p (x + P x_c and its
+  // residual formed by the first sweep launch, or by the separate kernel
+  // reading p and writing x).
+  // Timed solves (mg_timing_enable) keep the transfers apart, so that every
+  // timed finest-level step is a plain smoothing step.
+  const bool tile_smoother =
+      c->fused && (c->o.smoother == MG_LSGS || c->o.smoother == MG_SLSGS || c->o.smoother == MG_CGS);
+  const bool xfer = tile_smoother && c->xfer_allowed && !c->timing && c->o.nu1 > 0 && c->o.nu2 > 0;
+  if (xfer) {
+    mgk::SweepIO<T> rio;
+    rio.fc = wc.f;
+    rio.xc0 = xc0;
+    rio.rc = rc;
+    rio.Lc = bc.lev;
+    SweepXfer<T> xf;
+    xf.last = &rio;
+    xf.last_x = wb.p;
+    if ((st = smooth_steps<T>(c, l, x, r, alt, wb.p, c->o.nu1, s, nullptr, SweepNorm{}, xf)) != MG_OK) return st;
+  } else {
+    if ((st = smooth_steps<T>(c, l, x, r, alt, wb.p, c->o.nu1, s)) != MG_OK) return st;
+    HIPCHK(c, mgk::launch_restrict<T>(b.lev, bc.lev, r, wc.f, xc0, rc, s));
+  }
+  alt = (r == wb.r) ? wb.r2 : wb.r;
   for (int g = 0; g < c->o.gamma; g++) {
     if (tail && c->dmap_n) {
       // x_c = B f_c from zero; a further iterate x_c += B (f_c - A x_c)
@@ -787,11 +843,29 @@ int cycle_body(mg_ctx* c, int l, const T* f, T* x, T* r, bool residual_current, 
     else if ((st = cycle_body<T>(c, l - 1, wc.f, wc.x, wc.r, g == 0, s)) != MG_OK)
       return st;
   }
+  // the prolongation with the residual pays inside the first post-smoothing
+  // launch only on the levels swept one sweep per launch (above 513^2): it
+  // reads the iterate and f on the whole tile region, where the separate
+  // kernel reads each vertex once; on the two-sweep levels the launch of its
+  // own is cheaper
+  if (xfer && b.lev.n > mgk::lsgs_sweep2_max_n()) {
+    mgk::SweepIO<T> pio;
+    pio.xc = wc.x;
+    pio.f = f;
+    pio.Lc = bc.lev;
+    SweepXfer<T> xf;
+    xf.first = &pio;
+    return smooth_steps<T>(c, l, x, r, alt, wb.p, c->o.nu2, s, wb.p, sn, xf);
+  }
   // x += P x_c and r = f - A x.  Before a tile-sweep post-smoother both go in
   // one kernel that writes the corrected iterate to the level's scratch p
   // (unused by LSGS); the first sweep reads it from there and writes x.
-  const bool fuse = c->fused && c->o.nu2 > 0 &&
-                    (c->o.smoother == MG_LSGS || c->o.smoother == MG_SLSGS || c->o.smoother == MG_CGS);
+  const bool fuse = tile_smoother && c->o.nu2 > 0;
+  if (fuse && xfer) {
+    // the pre-smoothed iterate is in p
+    HIPCHK(c, mgk::launch_prolong_residual<T>(b.lev, bc.lev, wc.x, wb.p, f, x, r, s));
+    return smooth_steps<T>(c, l, x, r, alt, wb.p, c->o.nu2, s, nullptr, sn);
+  }
   if (fuse) {
     HIPCHK(c, mgk::launch_prolong_residual<T>(b.lev, bc.lev, wc.x, x, f, wb.p, r, s));
     return smooth_steps<T>(c, l, x, r, alt, wb.p, c->o.nu2, s, wb.p, sn);
@@ -1066,6 +1140,10 @@ static int setup_body(mg_ctx* c, int level, double alpha, int problem, const mg_
     // MGKKT_NO_SWEEP2=1 runs one sweep per launch on every level
     const char* e2 = std::getenv("MGKKT_NO_SWEEP2");
     c->sweep2 = !(e2 && e2[0] == '1');
+    // MGKKT_NO_FUSED_TRANSFERS=1 launches the restriction and the
+    // prolongation with the residual as kernels of their own
+    const char* e3 = std::getenv("MGKKT_NO_FUSED_TRANSFERS");
+    c->xfer_allowed = !(e3 && e3[0] == '1');
     // MGKKT_NO_TAIL=1 runs the coarse levels with the per-level kernels
     const char* t = std::getenv("MGKKT_NO_TAIL");
     c->tail_allowed = !(t && t[0] == '1');

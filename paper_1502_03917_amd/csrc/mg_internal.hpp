@@ -119,23 +119,46 @@ template <typename T>
 hipError_t launch_ne(const Lev& L, T* x, T* r, T* p, hipStream_t s);
 template <typename T>
 hipError_t launch_lsgs_phase(const Lev& L, int colour, T* x, T* r, hipStream_t s);
+// Grid transfers folded into a tile-sweep launch (section 2: the defect
+// restriction after the pre-smoothing, the coarse-grid correction and the new
+// residual before the post-smoothing).
+//  - prolongation (xc set; the first post-smoothing launch): the launch forms
+//    x + P xc and r = f - A (x + P xc) on each tile's region from xin, xc and
+//    f instead of reading r_in, and sweeps from there; xin is read on whole
+//    regions, so it must not alias x;
+//  - restriction (fc set; the last pre-smoothing launch): the tiles keep one
+//    more ring of final residuals and write f_c = P^T r of the residual the
+//    launch leaves (x_c = 0 and r_c = f_c as well where xc0 / rc are given)
+//    instead of r_out.
+template <typename T>
+struct SweepIO {
+  const T* xc = nullptr;
+  const T* f = nullptr;
+  T* fc = nullptr;
+  T* xc0 = nullptr;
+  T* rc = nullptr;
+  Lev Lc{};  // the coarse level
+};
 // one full LSGS sweep (all 7 colours; reverse = colours 6..0) reading r_in
 // and writing r_out (distinct buffers), x updated in place
 template <typename T>
 hipError_t launch_lsgs_sweep(const Lev& L, int reverse, T* x, const T* rin, T* rout, hipStream_t s);
 // the same sweep reading the iterate from xin and writing it to x
 template <typename T>
-hipError_t launch_lsgs_sweep_from(const Lev& L, int reverse, const T* xin, T* x, const T* rin, T* rout, hipStream_t s);
+hipError_t launch_lsgs_sweep_from(const Lev& L, int reverse, const T* xin, T* x, const T* rin, T* rout, hipStream_t s,
+                                  const SweepIO<T>* io = nullptr);
 // an FP64 sweep that also stores per-tile partial sums of ||r_out||^2
 // (norm_mode 1: Euclidean, 2: L^{-1}) in part; *nparts = number of tiles
 // two LSGS sweeps in one launch on levels with n <= lsgs_sweep2_max_n()
 // (bit s of revmask: sweep s in reverse colour order); r from rin, the
 // residual after both sweeps to rout
 template <typename T>
-hipError_t launch_lsgs_sweep2(const Lev& L, int revmask, const T* xin, T* x, const T* rin, T* rout, hipStream_t s);
+hipError_t launch_lsgs_sweep2(const Lev& L, int revmask, const T* xin, T* x, const T* rin, T* rout, hipStream_t s,
+                              const SweepIO<T>* io = nullptr);
 int lsgs_sweep2_max_n();
 hipError_t launch_lsgs_sweep_norm(const Lev& L, int reverse, const double* xin, double* x, const double* rin,
-                                  double* rout, double* part, int norm_mode, int* nparts, hipStream_t s);
+                                  double* rout, double* part, int norm_mode, int* nparts, hipStream_t s,
+                                  const SweepIO<double>* io = nullptr);
 template <typename T>
 hipError_t launch_cgs_phase(const Lev& L, int colour, T* x, T* r, hipStream_t s);
 // fused sweeps of the collective point smoother (7 colours, one launch per
@@ -143,11 +166,14 @@ hipError_t launch_cgs_phase(const Lev& L, int colour, T* x, T* r, hipStream_t s)
 // read from rin and written to rout, the iterate read from xin and written
 // to x; the _norm form also stores per-tile partial sums of ||r_out||^2
 template <typename T>
-hipError_t launch_cgs_sweep_from(const Lev& L, const T* xin, T* x, const T* rin, T* rout, hipStream_t s);
+hipError_t launch_cgs_sweep_from(const Lev& L, const T* xin, T* x, const T* rin, T* rout, hipStream_t s,
+                                 const SweepIO<T>* io = nullptr);
 template <typename T>
-hipError_t launch_cgs_sweep2(const Lev& L, const T* xin, T* x, const T* rin, T* rout, hipStream_t s);
+hipError_t launch_cgs_sweep2(const Lev& L, const T* xin, T* x, const T* rin, T* rout, hipStream_t s,
+                             const SweepIO<T>* io = nullptr);
 hipError_t launch_cgs_sweep_norm(const Lev& L, const double* xin, double* x, const double* rin, double* rout,
-                                 double* part, int norm_mode, int* nparts, hipStream_t s);
+                                 double* part, int norm_mode, int* nparts, hipStream_t s,
+                                 const SweepIO<double>* io = nullptr);
 template <typename T>
 hipError_t launch_restrict(const Lev& Lf, const Lev& Lc, const T* r, T* fc, T* xc_zero, T* rc_copy, hipStream_t s);
 template <typename T>

@@ -36,6 +36,10 @@ namespace {
 constexpr int kHalo = 14;     // LSGS: halo of one sweep
 constexpr int kHaloCgs = 7;   // collective smoother: halo of one sweep
 
+// transfers folded into a launch (SweepIO): none, the prolongation with the
+// new residual before the sweeps, the restriction of the residual after them
+constexpr int kIoNone = 0, kIoProlong = 1, kIoRestrict = 2;
+
 // Workgroup barrier that orders LDS accesses only; global memory needs no
 // ordering inside a sweep (r_in is read-only, r_out and x are per owned vertex).
 __device__ inline void lds_barrier() {
@@ -81,8 +85,9 @@ constexpr int pitch_pad(int TW, int H, int cell, bool cgs = false) {
                                        : (TW == 17 ? 13 : TW == 33 ? 11 : 1))
                       : (H == kHaloCgs ? (TW == 46 ? 12 : TW == 48 ? 10 : TW == 16 ? 6 : 1)
                                        : (TW == 17 ? 13 : TW == 33 ? 11 : 1));
+  // (33 x 33 pair tiles with the restriction's extra ring: 1, to fit the LDS)
   return cell == 16 ? (H == kHalo ? (TW == 65 ? 7 : TW == 56 ? 9 : TW == 48 ? 10 : TW == 16 ? 7 : 1)
-                                  : (TW == 17 ? 13 : TW == 33 ? 4 : 1))
+                                  : (TW == 17 ? 13 : TW == 33 ? (H == 2 * kHalo ? 4 : 1) : 1))
                     : (H == kHalo ? (TW == 46 ? 3 : TW == 48 ? 12 : TW == 16 ? 8 : 1)
                                   : (TW == 17 ? 15 : TW == 33 ? 13 : 1));
 }
@@ -121,11 +126,19 @@ struct PhaseItems {
 // written, per owned vertex).  NSW sweeps run in one pass over the tile
 // (halo 14 NSW, or 7 NSW for the collective smoother (CGS); 7 NSW colour
 // phases); bit s of reverse gives the order of sweep s.
-template <typename T, int TW, int NT, int NSW = 1, bool CGS = false>
+//
+// Transfers (IO): with kIoProlong the tile forms x + P x_c on its region and
+// the ring around it, then r = f - A (x + P x_c) on the region, in LDS,
+// instead of reading r (xin is read on the whole region: it must not alias
+// x).  With kIoRestrict the halo is one vertex wider, so that the residual
+// is also final on the ring around the tile, and the tile writes f_c = P^T r
+// for the coarse vertices (I, J) with (2I, 2J) in the tile instead of r.
+template <typename T, int TW, int NT, int NSW = 1, bool CGS = false, int IO = kIoNone>
 __device__ __forceinline__ void lsgs_tile_body(const Lev& L, int ntx, int nty, int reverse, const T* xin, T* x,
                                                const T* __restrict__ rin, T* __restrict__ rout,
-                                               double* __restrict__ part = nullptr, int norm_mode = 0) {
-  constexpr int H = (CGS ? kHaloCgs : kHalo) * NSW;
+                                               double* __restrict__ part = nullptr, int norm_mode = 0,
+                                               const SweepIO<T>* io = nullptr) {
+  constexpr int H = (CGS ? kHaloCgs : kHalo) * NSW + (IO == kIoRestrict ? 1 : 0);
   using G = TileGeom<TW, H, 2 * sizeof(T), CGS>;
   using T2 = typename Pair<T>::type;
   using PI = PhaseItems<TW, H, CGS>;
@@ -213,10 +226,12 @@ __device__ __forceinline__ void lsgs_tile_body(const Lev& L, int ntx, int nty, i
     for (int ph = 0; ph < 7; ph++) {
       const Item it = item_of(ph, tid);
       xo[ph] = owned(it) ? (unsigned)((it.gj * ld + it.gi) * sizeof(T)) : kOff;
-      xy[ph] = bload(Rxi, xo[ph], (T*)nullptr);
-      xl[ph] = bload(Rxi, xo[ph] == kOff ? kOff : xo[ph] + fo, (T*)nullptr);
+      if constexpr (IO != kIoProlong) {
+        xy[ph] = bload(Rxi, xo[ph], (T*)nullptr);
+        xl[ph] = bload(Rxi, xo[ph] == kOff ? kOff : xo[ph] + fo, (T*)nullptr);
+      }
     }
-  } else {
+  } else if constexpr (IO != kIoProlong) {
 #pragma unroll
     for (int q = 0; q < NX; q++) {
       const int e = tid + q * NT;
@@ -228,14 +243,16 @@ __device__ __forceinline__ void lsgs_tile_body(const Lev& L, int ntx, int nty, i
     }
   }
   T ry[NR], rl[NR];
+  if constexpr (IO != kIoProlong) {
 #pragma unroll
-  for (int q = 0; q < NR; q++) {
-    const int e = tid + q * NT;
-    const int lr = e / G::RMAX, li = e - lr * G::RMAX;
-    const bool ok = e < G::RMAX * G::RMAX && li < RW && lr < RH;
-    const unsigned o = ok ? (unsigned)(((rj0 + lr) * ld + ci0 + li) * sizeof(T)) : kOff;
-    ry[q] = bload(Rin, o, (T*)nullptr);
-    rl[q] = bload(Rin, ok ? o + fo : kOff, (T*)nullptr);
+    for (int q = 0; q < NR; q++) {
+      const int e = tid + q * NT;
+      const int lr = e / G::RMAX, li = e - lr * G::RMAX;
+      const bool ok = e < G::RMAX * G::RMAX && li < RW && lr < RH;
+      const unsigned o = ok ? (unsigned)(((rj0 + lr) * ld + ci0 + li) * sizeof(T)) : kOff;
+      ry[q] = bload(Rin, o, (T*)nullptr);
+      rl[q] = bload(Rin, ok ? o + fo : kOff, (T*)nullptr);
+    }
   }
   {
     constexpr int NC = (25 * kC5 + NT - 1) / NT;
@@ -243,6 +260,121 @@ __device__ __forceinline__ void lsgs_tile_body(const Lev& L, int ntx, int nty, i
 #pragma unroll
     for (int q = 0; q < NC; q++)
       if (tid + q * NT < 25 * kC5) tC[tid + q * NT] = (T)src[tid + q * NT];
+  }
+  if constexpr (IO == kIoProlong) {
+    // (1) x + P x_c on every cell of the region and of the ring around it
+    // (the guard positions), zero outside the square: a coarse vertex takes
+    // the coarse value, a vertex on a coarse edge (horizontal, vertical or
+    // the (I,J)-(I+1,J+1) diagonal) the mean of its two endpoints (for a
+    // coarse vertex both endpoints are the vertex itself, and the mean is
+    // its value exactly).  The loads of a batch of cells are all issued
+    // before any of them is used.
+    const Lev& Lc = io->Lc;
+    const __amdgpu_buffer_rsrc_t Rxc = make_rsrc(io->xc, (size_t)2 * Lc.V * sizeof(T));
+    const unsigned foc = (unsigned)(Lc.V * sizeof(T));
+    const __amdgpu_buffer_rsrc_t Rf = make_rsrc(io->f, vbytes);
+#pragma unroll
+    for (int q = 0; q < NR; q++) {  // f of the region, in flight through (1)
+      const int e = tid + q * NT;
+      const int lr = e / G::RMAX, li = e - lr * G::RMAX;
+      const bool ok = e < G::RMAX * G::RMAX && li < RW && lr < RH;
+      const unsigned o = ok ? (unsigned)(((rj0 + lr) * ld + ci0 + li) * sizeof(T)) : kOff;
+      ry[q] = bload(Rf, o, (T*)nullptr);
+      rl[q] = bload(Rf, ok ? o + fo : kOff, (T*)nullptr);
+    }
+    constexpr int RA = G::RMAX + 2;
+    constexpr int NA = (RA * RA + NT - 1) / NT;  // cells per thread
+    constexpr int BA = 3;                        // cells per batch
+#pragma unroll
+    for (int q0 = 0; q0 < NA; q0 += BA) {
+      T xv[BA], xw[BA], a0[BA], b0[BA], a1[BA], b1[BA];
+#pragma unroll
+      for (int u = 0; u < BA; u++) {
+        const int e = tid + (q0 + u) * NT;
+        const int lr = e / RA - 1, li = e - (lr + 1) * RA - 1;
+        const int gi = ci0 + li, gj = rj0 + lr;
+        const bool ok = q0 + u < NA && e < RA * RA && li <= RW && lr <= RH && gi >= 0 && gi <= n && gj >= 0 &&
+                        gj <= n;
+        const unsigned o = ok ? (unsigned)((gj * ld + gi) * sizeof(T)) : kOff;
+        const unsigned c0 = ok ? (unsigned)(((gj >> 1) * Lc.ld + (gi >> 1)) * sizeof(T)) : kOff;
+        const unsigned c1 = ok ? (unsigned)((((gj + 1) >> 1) * Lc.ld + ((gi + 1) >> 1)) * sizeof(T)) : kOff;
+        xv[u] = bload(Rxi, o, (T*)nullptr);
+        xw[u] = bload(Rxi, ok ? o + fo : kOff, (T*)nullptr);
+        a0[u] = bload(Rxc, c0, (T*)nullptr);
+        b0[u] = bload(Rxc, ok ? c0 + foc : kOff, (T*)nullptr);
+        a1[u] = bload(Rxc, c1, (T*)nullptr);
+        b1[u] = bload(Rxc, ok ? c1 + foc : kOff, (T*)nullptr);
+      }
+#pragma unroll
+      for (int u = 0; u < BA; u++) {
+        const int e = tid + (q0 + u) * NT;
+        if (q0 + u < NA && e < RA * RA) {
+          // masked loads returned zeros outside the square
+          const T vy = (T)0.5 * (a0[u] + a1[u]), vl = (T)0.5 * (b0[u] + b1[u]);
+          s2[e / RA * G::RP + e % RA] = (T2){xv[u] + vy, xw[u] + vl};
+        }
+      }
+    }
+    lds_barrier();
+    // (2) r = f - A (x + P x_c) on the region, into registers (f loaded
+    // before (1)); the corrected iterate of the owned vertices for the x
+    // stores
+    const T ai = (T)L.ainv;
+#pragma unroll
+    for (int q = 0; q < NR; q++) {
+      const int e = tid + q * NT;
+      const int lr = e / G::RMAX, li = e - lr * G::RMAX;
+      const bool ok = e < G::RMAX * G::RMAX && li < RW && lr < RH;
+      const int gi = ci0 + li, gj = rj0 + lr;
+      T ay = 0, al = 0;
+      if (ok) {
+        const int c = (lr + 1) * G::RP + li + 1;
+        const T2 xc2 = s2[c];
+        if (gi >= 1 && gi < n && gj >= 1 && gj < n) {
+          const T2 e2 = s2[c + 1], w2 = s2[c - 1], n2 = s2[c + G::RP], s2_ = s2[c - G::RP];
+          const T2 ne2 = s2[c + G::RP + 1], sw2 = s2[c - G::RP - 1];
+          const T ya = e2.x + w2.x + n2.x + s2_.x;
+          const T yg = ne2.x + sw2.x;
+          const T la = e2.y + w2.y + n2.y + s2_.y;
+          const T lg = ne2.y + sw2.y;
+          const T Mc = (T)L.Mc, Mo = (T)L.Mo, Kc = (T)L.Kc, Ka = (T)L.Ka, Kd = (T)L.Kd;
+          ay = Mc * xc2.x + Mo * (ya + yg) + (Kc * xc2.y + Ka * la + Kd * lg);
+          al = (Kc * xc2.x + Ka * ya + Kd * yg) - ai * (Mc * xc2.y + Mo * (la + lg));
+        } else {
+          const T* cb = &tC[(cls5(gi, n) * 5 + cls5(gj, n)) * kC5];
+#pragma unroll
+          for (int d = 0; d < kNDir; d++) {
+            const int ii = gi + kDI[d], jj = gj + kDJ[d];
+            if (ii < 0 || ii > n || jj < 0 || jj > n) continue;
+            const T2 v = s2[c + kDJ[d] * G::RP + kDI[d]];
+            ay += cb[d] * v.x + cb[kNDir + d] * v.y;
+            al += cb[kNDir + d] * v.x - ai * cb[d] * v.y;
+          }
+        }
+      }
+      ry[q] = ok ? ry[q] - ay : (T)0;
+      rl[q] = ok ? rl[q] - al : (T)0;
+    }
+    if constexpr (kOnePass) {
+#pragma unroll
+      for (int ph = 0; ph < 7; ph++) {
+        const Item it = item_of(ph, tid);
+        const T2 v = s2[xo[ph] == kOff ? 0 : (it.gj - rj0 + 1) * G::RP + (it.gi - ci0) + 1];
+        xy[ph] = v.x;
+        xl[ph] = v.y;
+      }
+    } else {
+#pragma unroll
+      for (int q = 0; q < NX; q++) {
+        const int e = tid + q * NT;
+        const int oj = e / TW, oi = e - oj * TW;
+        const bool ok = e < TW * TW && oi < OW && oj < OH;
+        const T2 v = s2[ok ? (j0 + oj - rj0 + 1) * G::RP + (i0 + oi - ci0) + 1 : 0];
+        xy[q] = v.x;
+        xl[q] = v.y;
+      }
+    }
+    lds_barrier();
   }
   // guard ring: rows 0 and RMAX + 1, columns 0 and RMAX + 1
   for (int e = tid; e < 4 * (G::RMAX + 2); e += NT) {
@@ -423,8 +555,10 @@ __device__ __forceinline__ void lsgs_tile_body(const Lev& L, int ntx, int nty, i
     const unsigned o = ok ? (unsigned)(((j0 + oj) * ld + i0 + oi) * sizeof(T)) : kOff;
     const unsigned o2 = ok ? o + fo : kOff;
     const T2 rv = s2[a];
-    bstore(Rout, o, rv.x);
-    bstore(Rout, o2, rv.y);
+    if constexpr (IO != kIoRestrict) {
+      bstore(Rout, o, rv.x);
+      bstore(Rout, o2, rv.y);
+    }
     if constexpr (!kOnePass) {
       const T2 dv = dx2[ok ? e : 0];
       bstore(Rx, o, xy[q] + dv.x);
@@ -440,6 +574,48 @@ __device__ __forceinline__ void lsgs_tile_body(const Lev& L, int ntx, int nty, i
                               ? L.Winv
                               : (double)tC[(cls5(gi, n) * 5 + cls5(gj, n)) * kC5 + 2 * kNDir];
         s2sum += wi * (ry * ry + L.alpha * (rl * rl));
+      }
+    }
+  }
+  if constexpr (IO == kIoRestrict) {
+    // f_c = P^T r: coarse vertex (I, J) collects the residual at (2I, 2J) with
+    // weight 1 and at its six lattice neighbours with weight 1/2 (the ring
+    // around the tile holds final values); x_c = 0 and r_c = f_c when asked
+    const Lev& Lc = io->Lc;
+    const int I0 = (i0 + 1) >> 1, J0 = (j0 + 1) >> 1;
+    const int CW = ((i1 + 1) >> 1) - I0, CH = ((j1 + 1) >> 1) - J0;
+    for (int e = tid; e < CW * CH; e += NT) {
+      const int cj = e / CW, ci = e - cj * CW;
+      const int I = I0 + ci, J = J0 + cj, a = 2 * I, b = 2 * J;
+      const int c = (b - rj0 + 1) * G::RP + (a - ci0) + 1;
+      const T2 r0 = s2[c];
+      T hy = 0, hl = 0;
+      if (a >= 1 && a < n && b >= 1 && b < n) {
+        const T2 e2 = s2[c + 1], w2 = s2[c - 1], n2 = s2[c + G::RP], s2_ = s2[c - G::RP];
+        const T2 ne2 = s2[c + G::RP + 1], sw2 = s2[c - G::RP - 1];
+        hy = (e2.x + w2.x + n2.x + s2_.x) + (ne2.x + sw2.x);
+        hl = (e2.y + w2.y + n2.y + s2_.y) + (ne2.y + sw2.y);
+      } else {
+#pragma unroll
+        for (int d = 1; d < kNDir; d++) {
+          const int aa = a + kDI[d], bb = b + kDJ[d];
+          if (aa < 0 || aa > n || bb < 0 || bb > n) continue;
+          const T2 v = s2[c + kDJ[d] * G::RP + kDI[d]];
+          hy += v.x;
+          hl += v.y;
+        }
+      }
+      const int w = J * Lc.ld + I;
+      const T gy = r0.x + (T)0.5 * hy, gl = r0.y + (T)0.5 * hl;
+      io->fc[w] = gy;
+      io->fc[Lc.V + w] = gl;
+      if (io->xc0) {
+        io->xc0[w] = (T)0;
+        io->xc0[Lc.V + w] = (T)0;
+      }
+      if (io->rc) {
+        io->rc[w] = gy;
+        io->rc[Lc.V + w] = gl;
       }
     }
   }
@@ -459,20 +635,20 @@ __device__ __forceinline__ void lsgs_tile_body(const Lev& L, int ntx, int nty, i
   }
 }
 
-template <typename T, int TW, int NT, int NSW = 1>
+template <typename T, int TW, int NT, int NSW = 1, int IO = kIoNone>
 __global__ __launch_bounds__(NT) void k_lsgs_tile(Lev L, int ntx, int nty, int reverse, const T* xin, T* x,
                                                   const T* __restrict__ rin, T* __restrict__ rout,
-                                                  double* __restrict__ part, int norm_mode) {
-  lsgs_tile_body<T, TW, NT, NSW>(L, ntx, nty, reverse, xin, x, rin, rout, part, norm_mode);
+                                                  double* __restrict__ part, int norm_mode, SweepIO<T> io) {
+  lsgs_tile_body<T, TW, NT, NSW, false, IO>(L, ntx, nty, reverse, xin, x, rin, rout, part, norm_mode, &io);
 }
 
 // NSW sweeps of the collective point smoother (the colour order of every
 // sweep is 0..6; reverse is unused)
-template <typename T, int TW, int NT, int NSW = 1>
+template <typename T, int TW, int NT, int NSW = 1, int IO = kIoNone>
 __global__ __launch_bounds__(NT) void k_cgs_tile(Lev L, int ntx, int nty, int reverse, const T* xin, T* x,
                                                  const T* __restrict__ rin, T* __restrict__ rout,
-                                                 double* __restrict__ part, int norm_mode) {
-  lsgs_tile_body<T, TW, NT, NSW, true>(L, ntx, nty, 0, xin, x, rin, rout, part, norm_mode);
+                                                 double* __restrict__ part, int norm_mode, SweepIO<T> io) {
+  lsgs_tile_body<T, TW, NT, NSW, true, IO>(L, ntx, nty, 0, xin, x, rin, rout, part, norm_mode, &io);
 }
 
 // many instances of one level: instance blockIdx.y, residual read from r
@@ -522,35 +698,62 @@ struct SweepShape<float> {
 };
 constexpr int kSmallTW = 16, kSmallNT = 256;
 
+// transfers of a launch: kIoProlong, kIoRestrict or kIoNone
+template <typename T>
+int io_kind(const SweepIO<T>* io) {
+  return !io ? kIoNone : io->xc ? kIoProlong : io->fc ? kIoRestrict : kIoNone;
+}
+
+// the kernel of a tile shape with the launch's transfers (IO picked at run time)
+template <typename T, int TW, int NT, int NSW, bool CGS>
+hipError_t launch_tile_io(int nblocks, const Lev& L, int ntx, int reverse, const T* xin, T* x, const T* rin, T* rout,
+                          hipStream_t s, double* part, int norm_mode, const SweepIO<T>* io) {
+  const SweepIO<T> a = io ? *io : SweepIO<T>{};
+  auto go = [&](auto kern) {
+    hipLaunchKernelGGL(kern, dim3(nblocks), dim3(NT), 0, s, L, ntx, ntx, reverse, xin, x, rin, rout, part, norm_mode,
+                       a);
+    return hipGetLastError();
+  };
+  switch (io_kind(io)) {
+    case kIoProlong:
+      if constexpr (CGS) return go(k_cgs_tile<T, TW, NT, NSW, kIoProlong>);
+      else return go(k_lsgs_tile<T, TW, NT, NSW, kIoProlong>);
+    case kIoRestrict:
+      if constexpr (CGS) return go(k_cgs_tile<T, TW, NT, NSW, kIoRestrict>);
+      else return go(k_lsgs_tile<T, TW, NT, NSW, kIoRestrict>);
+    default:
+      if constexpr (CGS) return go(k_cgs_tile<T, TW, NT, NSW>);
+      else return go(k_lsgs_tile<T, TW, NT, NSW>);
+  }
+}
+
 template <typename T, int TW, int NT, bool CGS>
 hipError_t launch_tile(const Lev& L, int reverse, const T* xin, T* x, const T* rin, T* rout, hipStream_t s,
-                       double* part, int norm_mode, int* nparts) {
+                       double* part, int norm_mode, int* nparts, const SweepIO<T>* io) {
   const int nt = tiles_along(L.n + 1, TW);
   if (nparts) *nparts = nt * nt;
-  if constexpr (CGS)
-    hipLaunchKernelGGL((k_cgs_tile<T, TW, NT>), dim3(round8(nt * nt)), dim3(NT), 0, s, L, nt, nt, 0, xin, x, rin,
-                       rout, part, norm_mode);
-  else
-    hipLaunchKernelGGL((k_lsgs_tile<T, TW, NT>), dim3(round8(nt * nt)), dim3(NT), 0, s, L, nt, nt, reverse, xin, x,
-                       rin, rout, part, norm_mode);
-  return hipGetLastError();
+  return launch_tile_io<T, TW, NT, 1, CGS>(round8(nt * nt), L, nt, CGS ? 0 : reverse, xin, x, rin, rout, s, part,
+                                           norm_mode, io);
 }
 
 // the collective smoother (CGS = true) takes the LSGS tile shapes
 template <typename T, bool CGS = false>
 hipError_t launch_tile_cfg(const Lev& L, int reverse, const T* xin, T* x, const T* rin, T* rout, hipStream_t s,
-                           double* part = nullptr, int norm_mode = 0, int* nparts = nullptr) {
+                           double* part = nullptr, int norm_mode = 0, int* nparts = nullptr,
+                           const SweepIO<T>* io = nullptr) {
   if (L.n <= SweepShape<T>::kSmallMaxN)
-    return launch_tile<T, kSmallTW, kSmallNT, CGS>(L, reverse, xin, x, rin, rout, s, part, norm_mode, nparts);
+    return launch_tile<T, kSmallTW, kSmallNT, CGS>(L, reverse, xin, x, rin, rout, s, part, norm_mode, nparts, io);
   if constexpr (std::is_same<T, double>::value) {
     if (L.n == 1024 || L.n == 2048)
-      return launch_tile<T, 65, 1024, CGS>(L, reverse, xin, x, rin, rout, s, part, norm_mode, nparts);
-    if (L.n >= 4096) return launch_tile<T, 56, 1024, CGS>(L, reverse, xin, x, rin, rout, s, part, norm_mode, nparts);
+      return launch_tile<T, 65, 1024, CGS>(L, reverse, xin, x, rin, rout, s, part, norm_mode, nparts, io);
+    if (L.n >= 4096)
+      return launch_tile<T, 56, 1024, CGS>(L, reverse, xin, x, rin, rout, s, part, norm_mode, nparts, io);
   } else {
-    if (L.n == 2048) return launch_tile<T, 46, 512, CGS>(L, reverse, xin, x, rin, rout, s, part, norm_mode, nparts);
+    if (L.n == 2048)
+      return launch_tile<T, 46, 512, CGS>(L, reverse, xin, x, rin, rout, s, part, norm_mode, nparts, io);
   }
   return launch_tile<T, SweepShape<T>::TW, SweepShape<T>::NT, CGS>(L, reverse, xin, x, rin, rout, s, part, norm_mode,
-                                                                   nparts);
+                                                                   nparts, io);
 }
 
 }  // namespace
@@ -601,14 +804,14 @@ hipError_t launch_lsgs_sweep<float>(const Lev& L, int reverse, float* x, const f
 
 template <>
 hipError_t launch_lsgs_sweep_from<double>(const Lev& L, int reverse, const double* xin, double* x, const double* rin,
-                                          double* rout, hipStream_t s) {
-  return launch_tile_cfg<double>(L, reverse, xin, x, rin, rout, s);
+                                          double* rout, hipStream_t s, const SweepIO<double>* io) {
+  return launch_tile_cfg<double>(L, reverse, xin, x, rin, rout, s, nullptr, 0, nullptr, io);
 }
 
 template <>
 hipError_t launch_lsgs_sweep_from<float>(const Lev& L, int reverse, const float* xin, float* x, const float* rin,
-                                         float* rout, hipStream_t s) {
-  return launch_tile_cfg<float>(L, reverse, xin, x, rin, rout, s);
+                                         float* rout, hipStream_t s, const SweepIO<float>* io) {
+  return launch_tile_cfg<float>(L, reverse, xin, x, rin, rout, s, nullptr, 0, nullptr, io);
 }
 
 // Two sweeps in one launch (bit s of revmask: sweep s in reverse colour
@@ -619,57 +822,62 @@ hipError_t launch_lsgs_sweep_from<float>(const Lev& L, int reverse, const float*
 // after both sweeps written to rout.
 constexpr int kSweep2MaxN = 512;
 template <typename T, bool CGS>
-hipError_t sweep2(const Lev& L, int revmask, const T* xin, T* x, const T* rin, T* rout, hipStream_t s) {
+hipError_t sweep2(const Lev& L, int revmask, const T* xin, T* x, const T* rin, T* rout, hipStream_t s,
+                  const SweepIO<T>* io) {
   if (L.n > kSweep2MaxN) return hipErrorInvalidValue;
-  auto go = [&](auto kern, int TW) {
-    const int nt = tiles_along(L.n + 1, TW);
-    hipLaunchKernelGGL(kern, dim3(round8(nt * nt)), dim3(1024), 0, s, L, nt, nt, revmask, xin, x, rin, rout,
-                       (double*)nullptr, 0);
-    return hipGetLastError();
-  };
-  if constexpr (CGS)
-    return L.n <= 256 ? go(k_cgs_tile<T, 17, 1024, 2>, 17) : go(k_cgs_tile<T, 33, 1024, 2>, 33);
-  else
-    return L.n <= 256 ? go(k_lsgs_tile<T, 17, 1024, 2>, 17) : go(k_lsgs_tile<T, 33, 1024, 2>, 33);
+  if (L.n <= 256) {
+    const int nt = tiles_along(L.n + 1, 17);
+    return launch_tile_io<T, 17, 1024, 2, CGS>(round8(nt * nt), L, nt, CGS ? 0 : revmask, xin, x, rin, rout, s,
+                                               nullptr, 0, io);
+  }
+  const int nt = tiles_along(L.n + 1, 33);
+  return launch_tile_io<T, 33, 1024, 2, CGS>(round8(nt * nt), L, nt, CGS ? 0 : revmask, xin, x, rin, rout, s, nullptr,
+                                             0, io);
 }
 
 template <typename T>
-hipError_t launch_lsgs_sweep2(const Lev& L, int revmask, const T* xin, T* x, const T* rin, T* rout, hipStream_t s) {
-  return sweep2<T, false>(L, revmask, xin, x, rin, rout, s);
+hipError_t launch_lsgs_sweep2(const Lev& L, int revmask, const T* xin, T* x, const T* rin, T* rout, hipStream_t s,
+                              const SweepIO<T>* io) {
+  return sweep2<T, false>(L, revmask, xin, x, rin, rout, s, io);
 }
 template hipError_t launch_lsgs_sweep2<double>(const Lev&, int, const double*, double*, const double*, double*,
-                                               hipStream_t);
+                                               hipStream_t, const SweepIO<double>*);
 template hipError_t launch_lsgs_sweep2<float>(const Lev&, int, const float*, float*, const float*, float*,
-                                              hipStream_t);
+                                              hipStream_t, const SweepIO<float>*);
 int lsgs_sweep2_max_n() { return kSweep2MaxN; }
 
 hipError_t launch_lsgs_sweep_norm(const Lev& L, int reverse, const double* xin, double* x, const double* rin,
-                                  double* rout, double* part, int norm_mode, int* nparts, hipStream_t s) {
-  if (!part || (norm_mode != 1 && norm_mode != 2)) return hipErrorInvalidValue;
-  return launch_tile_cfg<double>(L, reverse, xin, x, rin, rout, s, part, norm_mode, nparts);
+                                  double* rout, double* part, int norm_mode, int* nparts, hipStream_t s,
+                                  const SweepIO<double>* io) {
+  if (!part || (norm_mode != 1 && norm_mode != 2) || io_kind(io) == kIoRestrict) return hipErrorInvalidValue;
+  return launch_tile_cfg<double>(L, reverse, xin, x, rin, rout, s, part, norm_mode, nparts, io);
 }
 
 // ---- collective point smoother: one or two fused sweeps per launch
 template <typename T>
-hipError_t launch_cgs_sweep_from(const Lev& L, const T* xin, T* x, const T* rin, T* rout, hipStream_t s) {
-  return launch_tile_cfg<T, true>(L, 0, xin, x, rin, rout, s);
+hipError_t launch_cgs_sweep_from(const Lev& L, const T* xin, T* x, const T* rin, T* rout, hipStream_t s,
+                                 const SweepIO<T>* io) {
+  return launch_tile_cfg<T, true>(L, 0, xin, x, rin, rout, s, nullptr, 0, nullptr, io);
 }
 template hipError_t launch_cgs_sweep_from<double>(const Lev&, const double*, double*, const double*, double*,
-                                                  hipStream_t);
-template hipError_t launch_cgs_sweep_from<float>(const Lev&, const float*, float*, const float*, float*, hipStream_t);
+                                                  hipStream_t, const SweepIO<double>*);
+template hipError_t launch_cgs_sweep_from<float>(const Lev&, const float*, float*, const float*, float*, hipStream_t,
+                                                 const SweepIO<float>*);
 
 template <typename T>
-hipError_t launch_cgs_sweep2(const Lev& L, const T* xin, T* x, const T* rin, T* rout, hipStream_t s) {
-  return sweep2<T, true>(L, 0, xin, x, rin, rout, s);
+hipError_t launch_cgs_sweep2(const Lev& L, const T* xin, T* x, const T* rin, T* rout, hipStream_t s,
+                             const SweepIO<T>* io) {
+  return sweep2<T, true>(L, 0, xin, x, rin, rout, s, io);
 }
 template hipError_t launch_cgs_sweep2<double>(const Lev&, const double*, double*, const double*, double*,
-                                              hipStream_t);
-template hipError_t launch_cgs_sweep2<float>(const Lev&, const float*, float*, const float*, float*, hipStream_t);
+                                              hipStream_t, const SweepIO<double>*);
+template hipError_t launch_cgs_sweep2<float>(const Lev&, const float*, float*, const float*, float*, hipStream_t,
+                                             const SweepIO<float>*);
 
 hipError_t launch_cgs_sweep_norm(const Lev& L, const double* xin, double* x, const double* rin, double* rout,
-                                 double* part, int norm_mode, int* nparts, hipStream_t s) {
-  if (!part || (norm_mode != 1 && norm_mode != 2)) return hipErrorInvalidValue;
-  return launch_tile_cfg<double, true>(L, 0, xin, x, rin, rout, s, part, norm_mode, nparts);
+                                 double* part, int norm_mode, int* nparts, hipStream_t s, const SweepIO<double>* io) {
+  if (!part || (norm_mode != 1 && norm_mode != 2) || io_kind(io) == kIoRestrict) return hipErrorInvalidValue;
+  return launch_tile_cfg<double, true>(L, 0, xin, x, rin, rout, s, part, norm_mode, nparts, io);
 }
 
 }  // namespace mgk

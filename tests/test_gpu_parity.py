@@ -310,6 +310,41 @@ def test_sweep_pairs_match_single_sweeps(torch_cuda, monkeypatch, smoother, nu, 
         assert np.linalg.norm(xs[0] - xs[1]) <= bound * np.linalg.norm(xs[1]), precision
 
 
+@pytest.mark.parametrize("smoother,nu1,nu2,gamma", [("lsgs", 2, 2, 1), ("lsgs", 1, 1, 1), ("lsgs", 3, 2, 2),
+                                                    ("lsgs", 2, 1, 1), ("slsgs", 1, 1, 1), ("slsgs", 2, 2, 2),
+                                                    ("cgs", 2, 2, 1), ("cgs", 1, 3, 2)])
+@pytest.mark.parametrize("level", [6, 10, 11])
+def test_fused_transfers_match_separate_kernels(torch_cuda, monkeypatch, smoother, nu1, nu2, gamma, level):
+    # the restriction in the last pre-smoothing launch (one more ring of
+    # final residuals, f_c written from LDS) and the prolongation with the new
+    # residual in the first post-smoothing launch (x + P x_c and f - A (x + P
+    # x_c) formed on the tile's region) against the separate restriction and
+    # prolongation-residual kernels (MGKKT_NO_FUSED_TRANSFERS=1)
+    torch = torch_cuda
+    mg = _mg()
+    if level == 11 and (nu1, nu2, gamma) not in ((2, 2, 1), (1, 3, 2)):
+        pytest.skip("2049^2: the default V(2,2) and one W-cycle case")
+    alpha = 1e-4
+    yd = _dev(torch, workloads.desired_state(level, 6))
+    for precision, bound in (("fp64", 1e-13), ("fp32_ir", 1e-5)):
+        xs = []
+        for env in (None, "1"):
+            if env:
+                monkeypatch.setenv("MGKKT_NO_FUSED_TRANSFERS", env)
+            else:
+                monkeypatch.delenv("MGKKT_NO_FUSED_TRANSFERS", raising=False)
+            s = mg.Solver(level, alpha, smoother=smoother, gamma=gamma, nu1=nu1, nu2=nu2, precision=precision)
+            monkeypatch.delenv("MGKKT_NO_FUSED_TRANSFERS", raising=False)
+            f = s.rhs(yd)
+            x = torch.zeros_like(f)
+            for _ in range(3):
+                s.cycle(f, x)
+            xs.append(_host(x))
+            s.close()
+        assert np.all(np.isfinite(xs[0]))
+        assert np.linalg.norm(xs[0] - xs[1]) <= bound * np.linalg.norm(xs[1]), precision
+
+
 @pytest.mark.parametrize("smoother,nu", [("lsgs", 2), ("slsgs", 1), ("cgs", 2)])
 def test_sweep_norm_solve(torch_cuda, monkeypatch, smoother, nu):
     # FP64 solves take each iterate's norm from the residual the last sweep
