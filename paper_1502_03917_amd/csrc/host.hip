@@ -930,6 +930,33 @@ int ir_step(mg_ctx* c, double* x, hipStream_t s) {
   return MG_OK;
 }
 
+// Poisson solves with FP32 refinement keep the fine residual only as the
+// right-hand side of the next step's FP32 cycles, r / ||f|| in FP32 (its
+// squared norm from the same pass into d_norm[0]; ||f||^2 in d_norm[1]), and
+// the step's update is x += ||f|| c.  Any fixed scale keeps the FP32 values
+// in range, and the FP32 arithmetic is relative to them.
+bool ir_fused(const mg_ctx* c) { return !c->st && c->o.precision == MG_FP32_IR; }
+
+int residual_norm_f32(mg_ctx* c, const double* f, const double* x, hipStream_t s) {
+  LevelBuf& b = L_(c, c->level);
+  int nb = 0;
+  HIPCHK(c, mgk::launch_residual_f32(b.lev, f, x, c->d_norm + 1, b.f32, b.r32, c->d_part, norm_mode(c), &nb, s));
+  HIPCHK(c, mgk::launch_sum(c->d_part, nb, c->d_norm, s));
+  return MG_OK;
+}
+
+// the refinement step of a solve: FP32 cycles from zero on the right-hand
+// side left by residual_norm_f32, then x += ||f|| c
+int ir_step_solve(mg_ctx* c, double* x, hipStream_t s) {
+  LevelBuf& b = L_(c, c->level);
+  HIPCHK(c, mgk::launch_zero_f32(b.x32, b.len, s));
+  int st;
+  for (int k = 0; k < c->o.inner_cycles; k++)
+    if ((st = cycle_body<float>(c, c->level, b.f32, b.x32, b.r32, k == 0, s)) != MG_OK) return st;
+  HIPCHK(c, mgk::launch_axpy_f32(b.x32, b.len, c->d_norm + 1, x, s));
+  return MG_OK;
+}
+
 // one solver iterate for fixed (f, x): cycle (FP64) or refinement step
 // (FP32 cycles), then the fine residual and its squared norm in d_norm[0]
 // the residual buffer of the finest level
@@ -955,6 +982,10 @@ int iterate(mg_ctx* c, const double* f, double* x, hipStream_t s) {
     return residual_norm(c, f, x, fine_r(c), 0, s);
   }
   LevelBuf& b = L_(c, c->level);
+  if (ir_fused(c)) {
+    const int st = ir_step_solve(c, x, s);
+    return st != MG_OK ? st : residual_norm_f32(c, f, x, s);
+  }
   if (sweep_norm(c)) {
     // the last post-smoothing sweep leaves r = f - A x (maintained by the
     // smoother) in b.r and sums its squared norm: no separate residual pass
@@ -1465,7 +1496,8 @@ static int impl_mg_solve(mg_ctx* ctx, const double* f, double* x, double tol, in
   HIPCHK(ctx, mgk::launch_sum(ctx->d_part, nb, ctx->d_norm + 1, s));
   Monitor mon;
   int st = MG_OK;
-  if ((st = residual_norm(ctx, f, x, fine_r(ctx), 0, s)) != MG_OK) return st;
+  st = ir_fused(ctx) ? residual_norm_f32(ctx, f, x, s) : residual_norm(ctx, f, x, fine_r(ctx), 0, s);
+  if (st != MG_OK) return st;
   for (int it = 0;; it++) {
     HIPCHK(ctx, hipMemcpyAsync(ctx->h_norm, ctx->d_norm, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
     HIPCHK(ctx, hipStreamSynchronize(s));

@@ -628,6 +628,33 @@ __device__ __forceinline__ void to_f32_scaled_body(const double* __restrict__ r,
 __global__ void k_to_f32_scaled(const double* __restrict__ r, size_t n, const double* __restrict__ nrm2,
                                 float* __restrict__ out, float* __restrict__ out2) { to_f32_scaled_body(r, n, nrm2, out, out2); }
 
+// r = f - A x (FP64) with the norm partials of r (MODE 1 / 2), written as r / s
+// in FP32 to out and out2 (s from its square at nrm2, 1 if zero) and not in
+// FP64: the residual of a refinement step and the right-hand side of its
+// FP32 cycles in one pass
+template <int MODE>
+__global__ __launch_bounds__(kNT) void k_residual_f32(Lev L, const double* __restrict__ f, const double* __restrict__ x,
+                                                      const double* __restrict__ nrm2, float* __restrict__ out,
+                                                      float* __restrict__ out2, double* __restrict__ part) {
+  const int i = blockIdx.x * kBX + threadIdx.x;
+  const int j = blockIdx.y * kBY + threadIdx.y;
+  const double inv = 1.0 / ir_scale(nrm2);
+  double s2 = 0.0;
+  if (i <= L.n && j <= L.n) {
+    const int v = j * L.ld + i;
+    double ay, al;
+    apply_at(L, i, j, x, ay, al);
+    const double ry = f[v] - ay, rl = f[L.V + v] - al;
+    const float vy = (float)(ry * inv), vl = (float)(rl * inv);
+    out[v] = vy;
+    out[L.V + v] = vl;
+    out2[v] = vy;
+    out2[L.V + v] = vl;
+    s2 = norm_term<MODE>(L, i, j, ry, rl);
+  }
+  block_sum_store(s2, &part[blockIdx.y * gridDim.x + blockIdx.x]);
+}
+
 __device__ __forceinline__ void axpy_f32_body(const float* __restrict__ c, size_t n, const double* __restrict__ nrm2,
                            double* __restrict__ x) {
   const double scale = ir_scale(nrm2);
@@ -872,6 +899,18 @@ static int grid1d(size_t n) {
 
 hipError_t launch_to_f32_scaled(const double* r, size_t n, const double* nrm2, float* out, float* out2, hipStream_t s) {
   hipLaunchKernelGGL(k_to_f32_scaled, dim3(grid1d(n)), dim3(256), 0, s, r, n, nrm2, out, out2);
+  return hipGetLastError();
+}
+
+hipError_t launch_residual_f32(const Lev& L, const double* f, const double* x, const double* nrm2, float* out,
+                               float* out2, double* part, int norm_mode, int* nblocks, hipStream_t s) {
+  if (!part || (norm_mode != 1 && norm_mode != 2)) return hipErrorInvalidValue;
+  const dim3 g = grid_vertices(L.n);
+  if (nblocks) *nblocks = (int)(g.x * g.y);
+  if (norm_mode == 2)
+    hipLaunchKernelGGL(k_residual_f32<2>, g, kBlock, 0, s, L, f, x, nrm2, out, out2, part);
+  else
+    hipLaunchKernelGGL(k_residual_f32<1>, g, kBlock, 0, s, L, f, x, nrm2, out, out2, part);
   return hipGetLastError();
 }
 

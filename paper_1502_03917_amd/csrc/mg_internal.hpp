@@ -269,6 +269,10 @@ hipError_t stokes_ir_step(Stokes* S, double* x, hipStream_t s, const double* nrm
 // FP32-preconditioned iterative refinement glue
 // refinement scale s = sqrt(*nrm2) read on the device (1 if the norm is zero)
 hipError_t launch_to_f32_scaled(const double* r, size_t n, const double* nrm2, float* out, float* out2, hipStream_t s);
+// r = f - A x with norm partials (norm_mode 1 / 2), stored only as r / s in
+// FP32 to out and out2 (s = sqrt(*nrm2), 1 if zero)
+hipError_t launch_residual_f32(const Lev& L, const double* f, const double* x, const double* nrm2, float* out,
+                               float* out2, double* part, int norm_mode, int* nblocks, hipStream_t s);
 hipError_t launch_axpy_f32(const float* c, size_t n, const double* nrm2, double* x, hipStream_t s);
 hipError_t launch_zero_f32(float* v, size_t n, hipStream_t s);
 
