@@ -483,11 +483,13 @@ hipError_t last_sweep(const Lev& L, int reverse, const T* xin, T* x, const T* ri
 // Grid transfers carried by the tile-sweep launches of one smooth_steps call:
 // the first launch may form the prolongation with the new residual (first),
 // the last may write the restriction (last) and its iterate to last_x.
+// first_xzero: the first launch takes the iterate as zero (reads no x).
 template <typename T>
 struct SweepXfer {
   const mgk::SweepIO<T>* first = nullptr;
   const mgk::SweepIO<T>* last = nullptr;
   T* last_x = nullptr;
+  bool first_xzero = false;
 };
 
 template <typename T>
@@ -508,11 +510,19 @@ int smooth_steps(mg_ctx* c, int l, T* x, T*& r, T* alt, T* p, int steps, hipStre
     const SweepNorm& snl = (it == steps - 1) ? sn : none;
     // transfers of this step's launches: the prolongation on the first
     // launch of the call, the restriction (with the iterate written to
-    // xf.last_x) on the last
+    // xf.last_x) on the last; a zero iterate on the first
     const bool first = it == 0;
     const bool last_single = it == steps - 1;          // a one-sweep launch ending the call
     const bool last_pair = pairs && it + 2 == steps;  // a two-sweep launch ending the call
-    const mgk::SweepIO<T>* io1 = first ? xf.first : nullptr;
+    mgk::SweepIO<T> zio;
+    auto io_for = [&](bool f, bool l) -> const mgk::SweepIO<T>* {
+      const mgk::SweepIO<T>* a = (l && xf.last) ? xf.last : (f ? xf.first : nullptr);
+      if (!(f && xf.first_xzero)) return a;
+      if (a) zio = *a;
+      zio.xin_zero = true;
+      return &zio;
+    };
+    auto x_for = [&](bool l) { return (l && xf.last) ? xf.last_x : x; };
     size_t slot = 0;
     hipEvent_t stop = nullptr;
     if (timed) stop = timing_begin(c, s, &slot);
@@ -522,15 +532,11 @@ int smooth_steps(mg_ctx* c, int l, T* x, T*& r, T* alt, T* p, int steps, hipStre
         break;
       case MG_LSGS:
         if (pairs && it + 1 < steps) {
-          const mgk::SweepIO<T>* io = last_pair && xf.last ? xf.last : io1;
-          T* xo = last_pair && xf.last ? xf.last_x : x;
-          HIPCHK(c, mgk::launch_lsgs_sweep2<T>(L, 0, xin, xo, r, alt, s, io));
+          HIPCHK(c, mgk::launch_lsgs_sweep2<T>(L, 0, xin, x_for(last_pair), r, alt, s, io_for(first, last_pair)));
           std::swap(r, alt);
           it++;
         } else if (fused) {
-          const mgk::SweepIO<T>* io = last_single && xf.last ? xf.last : io1;
-          T* xo = last_single && xf.last ? xf.last_x : x;
-          HIPCHK(c, last_sweep<T>(L, 0, xin, xo, r, alt, snl, s, false, io));
+          HIPCHK(c, last_sweep<T>(L, 0, xin, x_for(last_single), r, alt, snl, s, false, io_for(first, last_single)));
           std::swap(r, alt);
         } else {
           for (int col = 0; col < 7; col++) HIPCHK(c, mgk::launch_lsgs_phase<T>(L, col, x, r, s));
@@ -538,15 +544,11 @@ int smooth_steps(mg_ctx* c, int l, T* x, T*& r, T* alt, T* p, int steps, hipStre
         break;
       case MG_SLSGS:
         if (pairs) {
-          const mgk::SweepIO<T>* io = last_single && xf.last ? xf.last : io1;
-          T* xo = last_single && xf.last ? xf.last_x : x;
-          HIPCHK(c, mgk::launch_lsgs_sweep2<T>(L, 2, xin, xo, r, alt, s, io));
+          HIPCHK(c, mgk::launch_lsgs_sweep2<T>(L, 2, xin, x_for(last_single), r, alt, s, io_for(first, last_single)));
           std::swap(r, alt);
         } else if (fused) {
-          HIPCHK(c, mgk::launch_lsgs_sweep_from<T>(L, 0, xin, x, r, alt, s, io1));
-          const mgk::SweepIO<T>* io = last_single && xf.last ? xf.last : nullptr;
-          T* xo = last_single && xf.last ? xf.last_x : x;
-          HIPCHK(c, last_sweep<T>(L, 1, x, xo, alt, r, snl, s, false, io));
+          HIPCHK(c, mgk::launch_lsgs_sweep_from<T>(L, 0, xin, x, r, alt, s, io_for(first, false)));
+          HIPCHK(c, last_sweep<T>(L, 1, x, x_for(last_single), alt, r, snl, s, false, io_for(false, last_single)));
         } else {
           for (int col = 0; col < 7; col++) HIPCHK(c, mgk::launch_lsgs_phase<T>(L, col, x, r, s));
           for (int col = 6; col >= 0; col--) HIPCHK(c, mgk::launch_lsgs_phase<T>(L, col, x, r, s));
@@ -554,15 +556,11 @@ int smooth_steps(mg_ctx* c, int l, T* x, T*& r, T* alt, T* p, int steps, hipStre
         break;
       case MG_CGS:
         if (pairs && it + 1 < steps) {
-          const mgk::SweepIO<T>* io = last_pair && xf.last ? xf.last : io1;
-          T* xo = last_pair && xf.last ? xf.last_x : x;
-          HIPCHK(c, mgk::launch_cgs_sweep2<T>(L, xin, xo, r, alt, s, io));
+          HIPCHK(c, mgk::launch_cgs_sweep2<T>(L, xin, x_for(last_pair), r, alt, s, io_for(first, last_pair)));
           std::swap(r, alt);
           it++;
         } else if (fused) {
-          const mgk::SweepIO<T>* io = last_single && xf.last ? xf.last : io1;
-          T* xo = last_single && xf.last ? xf.last_x : x;
-          HIPCHK(c, last_sweep<T>(L, 0, xin, xo, r, alt, snl, s, true, io));
+          HIPCHK(c, last_sweep<T>(L, 0, xin, x_for(last_single), r, alt, snl, s, true, io_for(first, last_single)));
           std::swap(r, alt);
         } else {
           for (int col = 0; col < 7; col++) HIPCHK(c, mgk::launch_cgs_phase<T>(L, col, x, r, s));
@@ -790,7 +788,7 @@ const float* dmap(const mg_ctx* c, float*) { return c->d_dmap32; }
 // level's two residual buffers).  If residual_current, r already holds f - A_l x.
 template <typename T>
 int cycle_body(mg_ctx* c, int l, const T* f, T* x, T* r, bool residual_current, hipStream_t s,
-               const SweepNorm& sn = SweepNorm{}) {
+               const SweepNorm& sn = SweepNorm{}, bool x_zero = false) {
   if (l == c->k0) return coarse_solve_T<T>(c, f, x, s);
   LevelBuf& b = L_(c, l);
   LevelBuf& bc = L_(c, l - 1);
@@ -823,9 +821,12 @@ int cycle_body(mg_ctx* c, int l, const T* f, T* x, T* r, bool residual_current, 
     SweepXfer<T> xf;
     xf.last = &rio;
     xf.last_x = wb.p;
+    xf.first_xzero = x_zero;
     if ((st = smooth_steps<T>(c, l, x, r, alt, wb.p, c->o.nu1, s, nullptr, SweepNorm{}, xf)) != MG_OK) return st;
   } else {
-    if ((st = smooth_steps<T>(c, l, x, r, alt, wb.p, c->o.nu1, s)) != MG_OK) return st;
+    SweepXfer<T> xf;
+    xf.first_xzero = x_zero;
+    if ((st = smooth_steps<T>(c, l, x, r, alt, wb.p, c->o.nu1, s, nullptr, SweepNorm{}, xf)) != MG_OK) return st;
     HIPCHK(c, mgk::launch_restrict<T>(b.lev, bc.lev, r, wc.f, xc0, rc, s));
   }
   alt = (r == wb.r) ? wb.r2 : wb.r;
@@ -946,13 +947,18 @@ int residual_norm_f32(mg_ctx* c, const double* f, const double* x, hipStream_t s
 }
 
 // the refinement step of a solve: FP32 cycles from zero on the right-hand
-// side left by residual_norm_f32, then x += ||f|| c
+// side left by residual_norm_f32, then x += ||f|| c.  With a tile-sweep
+// pre-smoother the first launch takes the zero iterate as zero (and writes
+// every vertex of x32), so x32 is not cleared.
 int ir_step_solve(mg_ctx* c, double* x, hipStream_t s) {
   LevelBuf& b = L_(c, c->level);
-  HIPCHK(c, mgk::launch_zero_f32(b.x32, b.len, s));
+  const bool xz = c->fused && c->o.nu1 > 0 &&
+                  (c->o.smoother == MG_LSGS || c->o.smoother == MG_SLSGS || c->o.smoother == MG_CGS);
+  if (!xz) HIPCHK(c, mgk::launch_zero_f32(b.x32, b.len, s));
   int st;
   for (int k = 0; k < c->o.inner_cycles; k++)
-    if ((st = cycle_body<float>(c, c->level, b.f32, b.x32, b.r32, k == 0, s)) != MG_OK) return st;
+    if ((st = cycle_body<float>(c, c->level, b.f32, b.x32, b.r32, k == 0, s, SweepNorm{}, xz && k == 0)) != MG_OK)
+      return st;
   HIPCHK(c, mgk::launch_axpy_f32(b.x32, b.len, c->d_norm + 1, x, s));
   return MG_OK;
 }

@@ -130,6 +130,8 @@ hipError_t launch_lsgs_phase(const Lev& L, int colour, T* x, T* r, hipStream_t s
 //    more ring of final residuals and write f_c = P^T r of the residual the
 //    launch leaves (x_c = 0 and r_c = f_c as well where xc0 / rc are given)
 //    instead of r_out.
+//  - xin_zero: the launch takes the iterate it reads as zero (a refinement
+//    step's first FP32 cycle starts from x = 0) and reads nothing from xin.
 template <typename T>
 struct SweepIO {
   const T* xc = nullptr;
@@ -138,6 +140,7 @@ struct SweepIO {
   T* xc0 = nullptr;
   T* rc = nullptr;
   Lev Lc{};  // the coarse level
+  bool xin_zero = false;
 };
 // one full LSGS sweep (all 7 colours; reverse = colours 6..0) reading r_in
 // and writing r_out (distinct buffers), x updated in place

@@ -171,8 +171,11 @@ __device__ __forceinline__ void lsgs_tile_body(const Lev& L, int ntx, int nty, i
   const int nblk = gridDim.x, bid = blockIdx.x;
   const int tid = threadIdx.x;
   const size_t vbytes = (size_t)2 * V * sizeof(T);
+  // an iterate taken as zero reads through an empty buffer: every load of it
+  // returns 0 without a memory access
+  const bool xzero = io != nullptr && io->xin_zero;
   const __amdgpu_buffer_rsrc_t Rin = make_rsrc(rin, vbytes), Rout = make_rsrc(rout, vbytes), Rx = make_rsrc(x, vbytes),
-                              Rxi = make_rsrc(xin, vbytes);
+                              Rxi = make_rsrc(xin, xzero ? 0 : vbytes);
   const unsigned fo = (unsigned)(V * sizeof(T));  // byte offset of the lambda field
 
   // The workgroups of one XCD (bid % 8) take a contiguous run of tiles, which
