@@ -31,14 +31,15 @@ METRIC = "V-cycles/s and HBM GB/s at 2049^2 Poisson control; time to rel. residu
 
 # The HBM traffic of the finest-level sweep is measured with hardware counters
 # (FETCH_SIZE, WRITE_SIZE) in separate profiler runs and recorded, together
-# with a hash of the sources the kernel is built from, in TRAFFIC_RECORD; the
+# with a hash of the sources the kernel is built from, in TRAFFIC_RECORDS; the
 # figure is reported only while those sources are unchanged.
 # what the sweep kernel is built from: its source, the level descriptors of
 # the internal header (the part before the launcher declarations) and the
 # compiler flags
 SWEEP_SOURCES = ("paper_1502_03917_amd/csrc/sweep.hip", "paper_1502_03917_amd/csrc/mg_internal.hpp",
                  "paper_1502_03917_amd/build.py")
-TRAFFIC_RECORD = os.path.join(ROOT, "profiles", "lsgs_sweep_2049sq_traffic.txt")
+TRAFFIC_RECORDS = {"fp64": os.path.join(ROOT, "profiles", "lsgs_sweep_2049sq_traffic.txt"),
+                   "fp32_ir": os.path.join(ROOT, "profiles", "lsgs_sweep_2049sq_fp32_traffic.txt")}
 COPY_MIB = 512  # size of the plain copy that calibrates the counters
 
 
@@ -131,7 +132,7 @@ def recorded_traffic(precision: str, level: int):
     """HBM bytes per finest-level sweep from the counter record, or None when
     the record is missing, was taken for another configuration, or the sweep
     sources have changed since."""
-    rec = read_record(TRAFFIC_RECORD)
+    rec = read_record(TRAFFIC_RECORDS.get(precision, ""))
     key = f"traffic_bytes_per_launch_{precision}"
     if rec.get("source_hash") != sweep_source_hash() or rec.get("level") != str(level) or key not in rec:
         return None
@@ -608,7 +609,8 @@ def main() -> int:
                              "cycles_per_solve": ir["cycles_per_solve"], "final_relres": ir["relres"],
                              "status": ir["status"], "speedup_time_to_tol_vs_fp64": main_run["ms_per_solve"] / ir["ms_per_solve"],
                              "finest_sweep_ms": ir_sweep["sweep_ms"], "finest_sweep_GBps": ach,
-                             "finest_sweep_frac_of_8TBps": ach / HBM_PEAK_GBS}
+                             "finest_sweep_frac_of_8TBps": ach / HBM_PEAK_GBS,
+                             "finest_sweep_traffic": recorded_traffic("fp32_ir", args.level)}
         # final error of the FP32-refinement solve against the FP64 solve (whose
         # cycles match the oracle's at this size), per field, for each alpha
         errs = {}

@@ -528,6 +528,43 @@ def test_full_size_cycle_parity(torch_cuda, smoother):
     assert_fields(xgh, xo, 1e-12, alpha=alpha)
 
 
+def test_level12_tile_sweeps_match_phase_kernels(torch_cuda, monkeypatch):
+    # 4097^2 vertices (33.6 M unknowns, the largest level mg_setup accepts;
+    # 56 x 56 tiles on the finest level): one V(2,2) cycle from zero with the
+    # tile sweeps and the folded transfers against the same cycle with one
+    # launch per colour phase and separate transfer kernels (an independent
+    # path, checked against the oracle at the smaller levels), per field; then
+    # a solve to 1e-10 whose cycle count is mesh-independent (within 2 of the
+    # 2049^2 solve's)
+    torch = torch_cuda
+    mg = _mg()
+    level, alpha = 12, 1e-4
+    yd = _dev(torch, workloads.desired_state(level, 2))
+    xs = []
+    for env in (None, "1"):
+        if env:
+            monkeypatch.setenv("MGKKT_PHASE_KERNELS", env)
+        s = mg.Solver(level, alpha)
+        monkeypatch.delenv("MGKKT_PHASE_KERNELS", raising=False)
+        f = s.rhs(yd)
+        x = torch.zeros_like(f)
+        s.cycle(f, x)
+        xs.append(_host(x))
+        del x, f
+        s.close()
+    assert_fields(xs[0], xs[1], 1e-12, alpha=alpha)
+    s = mg.Solver(level, alpha)
+    f = s.rhs(yd)
+    x, it12, rel, st = s.solve(f, tol=1e-10)
+    assert st == mg.MG_OK and rel <= 1e-10
+    del x, f
+    s.close()
+    s11 = mg.Solver(11, alpha)
+    f11 = s11.rhs(_dev(torch, workloads.desired_state(11, 2)))
+    _, it11, rel11, st11 = s11.solve(f11, tol=1e-10)
+    assert st11 == mg.MG_OK and abs(it12 - it11) <= 2, (it12, it11)
+
+
 @pytest.mark.parametrize("alpha", [1e-8, 1e-4, 1.0])
 def test_fp32_refinement_full_size(torch_cuda, alpha):
     # the benchmark's size (2049^2 vertices): FP32 cycles inside FP64
