@@ -528,7 +528,12 @@ int smooth_steps(mg_ctx* c, int l, T* x, T*& r, T* alt, T* p, int steps, hipStre
     if (timed) stop = timing_begin(c, s, &slot);
     switch (c->o.smoother) {
       case MG_NE:
-        HIPCHK(c, mgk::launch_ne<T>(L, x, r, p, s));
+        if (fused) {  // one pass over LDS tiles, r ping-pong
+          HIPCHK(c, mgk::launch_ne_tile<T>(L, x, r, alt, s));
+          std::swap(r, alt);
+        } else {
+          HIPCHK(c, mgk::launch_ne<T>(L, x, r, p, s));
+        }
         break;
       case MG_LSGS:
         if (pairs && it + 1 < steps) {

@@ -332,6 +332,129 @@ __device__ __forceinline__ void ne_r_body(Lev L, const T* __restrict__ p, T* __r
 template <typename T>
 __global__ __launch_bounds__(kNT) void k_ne_r(Lev L, const T* __restrict__ p, T* __restrict__ r) { ne_r_body<T>(L, p, r); }
 
+// One step of Alg. 1 in one pass over a tile of kNeTX x kNeTY vertices: r on
+// the tile and a two-vertex ring is staged in LDS, p = tau L^-1 A^T L^-1 r is
+// formed on the tile and a one-vertex ring (the expressions of gather_q), then
+// x += p and r_out = r - A p (those of apply_at) on the tile.  Neighbouring
+// tiles read r_in on their rings, so r_out is a second buffer; x is read and
+// written per owned vertex.  The two-kernel form moves x, r and p through
+// HBM twice (14 words per vertex); this one moves x and r once (8 words plus
+// the ring's share of r).
+constexpr int kNeTX = 64, kNeTY = 16;
+static_assert(kNeTX * kNeTY % kNT == 0, "whole owned rows per pass");
+template <typename T>
+__global__ __launch_bounds__(kNT) void k_ne_tile(Lev L, T* __restrict__ x, const T* __restrict__ rin,
+                                                 T* __restrict__ rout) {
+  constexpr int RX = kNeTX + 4, RY = kNeTY + 4;  // r: tile + 2-vertex ring
+  constexpr int PX = kNeTX + 2, PY = kNeTY + 2;  // p: tile + 1-vertex ring
+  __shared__ T sry[RX * RY], srl[RX * RY], spy[PX * PY], spl[PX * PY];
+  const int n = L.n, ld = L.ld, V = L.V;
+  const int i0 = blockIdx.x * kNeTX, j0 = blockIdx.y * kNeTY;
+  const int tid = threadIdx.y * kBX + threadIdx.x;
+  const bool interior_tile = i0 >= 3 && i0 + kNeTX + 2 <= n - 1 && j0 >= 3 && j0 + kNeTY + 2 <= n - 1;
+  // all loads of the staged r in flight before the first LDS store
+  constexpr int NQ = (RX * RY + kNT - 1) / kNT;
+  T ly[NQ], ll[NQ];
+#pragma unroll
+  for (int q = 0; q < NQ; q++) {
+    const int e = tid + q * kNT;
+    const int lj = e / RX, li = e - lj * RX;
+    const int a = i0 - 2 + li, b = j0 - 2 + lj;
+    const bool in = e < RX * RY && a >= 0 && a <= n && b >= 0 && b <= n;
+    const int u = in ? b * ld + a : 0;
+    ly[q] = in ? rin[u] : (T)0;
+    ll[q] = in ? rin[V + u] : (T)0;
+  }
+#pragma unroll
+  for (int q = 0; q < NQ; q++) {
+    const int e = tid + q * kNT;
+    if (e < RX * RY) {
+      sry[e] = ly[q];
+      srl[e] = ll[q];
+    }
+  }
+  __syncthreads();
+  const T al = (T)L.alpha, ai = (T)L.ainv, tau = (T)L.tau;
+  const T Mc = (T)L.Mc, Mo = (T)L.Mo, Kc = (T)L.Kc, Ka = (T)L.Ka, Kd = (T)L.Kd, Wi = (T)L.Winv;
+  for (int e = tid; e < PX * PY; e += kNT) {
+    const int lj = e / PX, li = e - lj * PX;
+    const int i = i0 - 1 + li, j = j0 - 1 + lj;
+    T py = 0, pl = 0;
+    if (i >= 0 && i <= n && j >= 0 && j <= n) {
+      const int c = (lj + 1) * RX + li + 1;  // (i, j) in the r array
+      T qy, ql, wv;
+      if (interior_tile || (i >= 2 && i <= n - 2 && j >= 2 && j <= n - 2)) {
+        const T yc = sry[c], lc = srl[c];
+        const T ya = sry[c + 1] + sry[c - 1] + sry[c + RX] + sry[c - RX];
+        const T yg = sry[c + RX + 1] + sry[c - RX - 1];
+        const T la = srl[c + 1] + srl[c - 1] + srl[c + RX] + srl[c - RX];
+        const T lg = srl[c + RX + 1] + srl[c - RX - 1];
+        qy = Wi * (Mc * yc + Mo * (ya + yg) + al * (Kc * lc + Ka * la + Kd * lg));
+        ql = Wi * ((Kc * yc + Ka * ya + Kd * yg) - (Mc * lc + Mo * (la + lg)));
+        wv = Wi;
+      } else {
+        T M[kNDir], K[kNDir];
+        coef_MK(L, i, j, M, K);
+        qy = 0;
+        ql = 0;
+#pragma unroll
+        for (int d = 0; d < kNDir; d++) {
+          const int ii = i + kDI[d], jj = j + kDJ[d];
+          if (!inside(L, ii, jj)) continue;
+          const int m = c + kDJ[d] * RX + kDI[d];
+          const T wi = (T)L.tab->Winv[cls3(ii, n) * 3 + cls3(jj, n)];
+          const T a = sry[m], b = srl[m];
+          qy += (M[d] * a + al * K[d] * b) * wi;
+          ql += (K[d] * a - M[d] * b) * wi;
+        }
+        wv = (T)L.tab->Winv[cls3(i, n) * 3 + cls3(j, n)];
+      }
+      py = tau * qy * wv;
+      pl = tau * ql * (al * wv);
+    }
+    spy[e] = py;
+    spl[e] = pl;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < kNeTX * kNeTY / kNT; q++) {
+    const int e = tid + q * kNT;
+    const int lj = e / kNeTX, li = e - lj * kNeTX;
+    const int i = i0 + li, j = j0 + lj;
+    if (i > n || j > n) continue;
+    const int c = (lj + 1) * PX + li + 1;  // (i, j) in the p array
+    const int v = j * ld + i;
+    const T yc = spy[c], lc = spl[c];
+    T ay, aq;
+    if (i >= 1 && i < n && j >= 1 && j < n) {
+      const T ya = spy[c + 1] + spy[c - 1] + spy[c + PX] + spy[c - PX];
+      const T yg = spy[c + PX + 1] + spy[c - PX - 1];
+      const T la = spl[c + 1] + spl[c - 1] + spl[c + PX] + spl[c - PX];
+      const T lg = spl[c + PX + 1] + spl[c - PX - 1];
+      ay = Mc * yc + Mo * (ya + yg) + (Kc * lc + Ka * la + Kd * lg);
+      aq = (Kc * yc + Ka * ya + Kd * yg) - ai * (Mc * lc + Mo * (la + lg));
+    } else {
+      T M[kNDir], K[kNDir];
+      coef_MK(L, i, j, M, K);
+      ay = 0;
+      aq = 0;
+#pragma unroll
+      for (int d = 0; d < kNDir; d++) {
+        const int ii = i + kDI[d], jj = j + kDJ[d];
+        if (!inside(L, ii, jj)) continue;
+        const int m = c + kDJ[d] * PX + kDI[d];
+        ay += M[d] * spy[m] + K[d] * spl[m];
+        aq += K[d] * spy[m] - ai * M[d] * spl[m];
+      }
+    }
+    const int cr = (lj + 2) * RX + li + 2;  // (i, j) in the r array
+    x[v] += yc;
+    x[V + v] += lc;
+    rout[v] = sry[cr] - ay;
+    rout[V + v] = srl[cr] - aq;
+  }
+}
+
 // first vertex of colour c in row j: (i + 2 j) mod 7 == c
 __device__ inline int colour_start(int c, int j) { return ((c - 2 * j) % 7 + 7) % 7; }
 
@@ -821,6 +944,13 @@ hipError_t launch_ne(const Lev& L, T* x, T* r, T* p, hipStream_t s) {
 }
 
 template <typename T>
+hipError_t launch_ne_tile(const Lev& L, T* x, const T* rin, T* rout, hipStream_t s) {
+  const dim3 g((L.n + kNeTX) / kNeTX, (L.n + kNeTY) / kNeTY);
+  hipLaunchKernelGGL((k_ne_tile<T>), g, kBlock, 0, s, L, x, rin, rout);
+  return hipGetLastError();
+}
+
+template <typename T>
 hipError_t launch_lsgs_phase(const Lev& L, int colour, T* x, T* r, hipStream_t s) {
   hipLaunchKernelGGL((k_lsgs_phase<T>), grid_colour(L.n), kBlock, 0, s, L, colour, x, r);
   return hipGetLastError();
@@ -1096,6 +1226,7 @@ template hipError_t launch_dense_map<float>(const float*, int, const float*, flo
   template hipError_t launch_apply<T>(const Lev&, const T*, T*, hipStream_t);                                      \
   template hipError_t launch_rhs<T>(const Lev&, const double*, T*, hipStream_t);                                   \
   template hipError_t launch_ne<T>(const Lev&, T*, T*, T*, hipStream_t);                                           \
+  template hipError_t launch_ne_tile<T>(const Lev&, T*, const T*, T*, hipStream_t);                                           \
   template hipError_t launch_lsgs_phase<T>(const Lev&, int, T*, T*, hipStream_t);                                  \
   template hipError_t launch_cgs_phase<T>(const Lev&, int, T*, T*, hipStream_t);                                   \
   template hipError_t launch_restrict<T>(const Lev&, const Lev&, const T*, T*, T*, T*, hipStream_t);              \

@@ -117,6 +117,10 @@ template <typename T>
 hipError_t launch_rhs(const Lev& L, const double* yd, T* f, hipStream_t s);
 template <typename T>
 hipError_t launch_ne(const Lev& L, T* x, T* r, T* p, hipStream_t s);
+// one NE step in one pass over LDS tiles: r read from rin, written to rout
+// (distinct buffers), x updated per vertex
+template <typename T>
+hipError_t launch_ne_tile(const Lev& L, T* x, const T* rin, T* rout, hipStream_t s);
 template <typename T>
 hipError_t launch_lsgs_phase(const Lev& L, int colour, T* x, T* r, hipStream_t s);
 // Grid transfers folded into a tile-sweep launch (section 2: the defect

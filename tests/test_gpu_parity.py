@@ -110,11 +110,12 @@ def test_coarse_solve(torch_cuda, alpha, coarse):
     assert np.linalg.norm(got - ref) <= 1e-11 * np.linalg.norm(ref)
 
 
-@pytest.mark.parametrize("smoother", ["lsgs", "slsgs", "cgs"])
+@pytest.mark.parametrize("smoother", ["lsgs", "slsgs", "cgs", "ne"])
 @pytest.mark.parametrize("level", [7, 10])
 def test_fused_sweep_matches_phase_kernels(torch_cuda, monkeypatch, level, smoother):
     # one fused kernel per sweep vs one launch per colour phase: same arithmetic
-    # (LSGS: 14-vertex halo; collective smoother: 7-vertex halo)
+    # (LSGS: 14-vertex halo; collective smoother: 7-vertex halo); NE: one pass
+    # over 64 x 16 tiles with a 2-vertex ring vs the two-kernel step
     torch = torch_cuda
     mg = _mg()
     alpha = 1e-3
