@@ -509,6 +509,27 @@ def test_fp32_refinement_reaches_tolerance(torch_cuda, alpha, smoother):
     print(f"fp32 refinement vs FP64 oracle, level {level}, alpha {alpha}: {err}")
 
 
+@pytest.mark.parametrize("smoother,nu1,nu2,inner", [("lsgs", 2, 2, 2), ("lsgs", 1, 1, 1), ("slsgs", 1, 1, 1),
+                                                    ("cgs", 1, 3, 2), ("ne", 2, 2, 1), ("lsgs", 0, 2, 1)])
+def test_fp32_refinement_step_variants(torch_cuda, smoother, nu1, nu2, inner):
+    # refinement steps of a solve: the FP64 residual pass leaves r / ||f|| in
+    # FP32, the step's first FP32 pre-smoothing launch takes the iterate as
+    # zero (tile smoothers with nu1 >= 1; otherwise x32 is cleared), later
+    # inner cycles start from the current x32; against the FP64 oracle solve,
+    # per field
+    torch = torch_cuda
+    mg = _mg()
+    level, alpha = 8, 1e-4
+    h = oracle.Hierarchy(level, alpha, coarse=1)
+    yd = workloads.desired_state(level, 3)
+    xo, _, _ = h.solve(h.rhs(yd), tol=1e-12, smoother="lsgs", order="col7")
+    s = mg.Solver(level, alpha, precision="fp32_ir", smoother=smoother, nu1=nu1, nu2=nu2, inner_cycles=inner,
+                  max_cycles=400)
+    xg, it, rel, st = s.solve(s.rhs(_dev(torch, yd)), tol=1e-10)
+    assert st == mg.MG_OK and rel <= 1e-10
+    assert_fields(_host(xg), xo, 1e-8, alpha=alpha)
+
+
 @pytest.mark.parametrize("smoother", ["lsgs", "cgs"])
 def test_full_size_cycle_parity(torch_cuda, smoother):
     # the benchmark's size (2049^2 vertices), one V(2,2) cycle from zero
