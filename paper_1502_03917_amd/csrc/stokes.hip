@@ -15,14 +15,18 @@
 // kernels walk rows through the classes: one thread per row for the
 // residual and the prolongation, 16 lanes per row for the restriction and
 // the normal-equation smoother; for a colour phase of the LSGS sweep
-// (Alg. 2), 32 lanes per group of two unknowns with the two rows merged (on
-// small levels, every phase of every step in one workgroup with the
-// residual in LDS); a wave per patch for the patch (Vanka-type) smoother.
+// (Alg. 2), 32 lanes per group of two unknowns with the two rows merged, the
+// interior groups' records formed from their lattice index (on small levels,
+// every phase of every step in one workgroup with the residual in LDS); a
+// wave per patch for the patch (Vanka-type) smoother.
 #include <algorithm>
+#include <array>
 #include <climits>
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
+#include <map>
+#include <numeric>
 #include <stdexcept>
 #include <string>
 #include <unordered_map>
@@ -796,22 +800,22 @@ constexpr int kGLR = 32, kGNE = kMaxGroupEntries / kGLR;
 
 constexpr int kGNT = 512;  // threads per workgroup (measured at 513^2: 64 slower by 14%, 256 and 512 alike in FP64, 512 2% faster in FP32)
 
-template <typename T>
-__global__ __launch_bounds__(kGNT) void ks_lsgs_grp(int g0, int ng, const int4* __restrict__ grp,
-                                                    const int* __restrict__ gent,
-                                                    const typename T2of<T>::type* __restrict__ gval,
-                                                    const T* __restrict__ glinv,
-                                                    const typename T2of<T>::type* __restrict__ gninv, SGeo geo,
-                                                    T* __restrict__ x, T* __restrict__ r) {
+// The groups of one wave, each on kGLR lanes (wave-uniform early exit).  The
+// record of a group comes from rec(g) (false: no group): a load from the
+// record list, or formed from the group's index on the lattice path.
+template <typename T, typename Rec>
+__device__ __forceinline__ void grp_wave_of(int wave, int ng, Rec rec, const int* __restrict__ gent,
+                                            const typename T2of<T>::type* __restrict__ gval,
+                                            const T* __restrict__ glinv,
+                                            const typename T2of<T>::type* __restrict__ gninv, const SGeo& geo,
+                                            T* __restrict__ x, T* __restrict__ r) {
   constexpr int LR = kGLR, G = 64 / LR, NE = kGNE;
-  const int wave = blockIdx.x * (kGNT / 64) + threadIdx.x / 64;
   if (wave * G >= ng) return;  // uniform per wave
   const int lane = threadIdx.x % 64, ln = lane % LR;
   const int g = wave * G + lane / LR;
   const bool live = g < ng;
-  const int4 u = live ? grp[g0 + g] : make_int4(0, 0, 0, 0);
   int hx, hy;
-  spos(geo, u.x, hx, hy);
+  const int4 u = rec(live ? g : -1, hx, hy);
   int c[NE];
   typename T2of<T>::type a[NE];
   T l[NE], rc[NE];
@@ -851,6 +855,31 @@ __global__ __launch_bounds__(kGNT) void ks_lsgs_grp(int g0, int ng, const int4* 
 #pragma unroll
   for (int e = 0; e < NE; e++)
     if (u.z + ln + e * LR < u.w) r[c[e]] = (rc[e] - a[e].x * pi) - a[e].y * pj;
+}
+
+template <typename T>
+__device__ __forceinline__ void grp_wave(int wave, int g0, int ng, const int4* __restrict__ grp,
+                                         const int* __restrict__ gent,
+                                         const typename T2of<T>::type* __restrict__ gval,
+                                         const T* __restrict__ glinv,
+                                         const typename T2of<T>::type* __restrict__ gninv, const SGeo& geo,
+                                         T* __restrict__ x, T* __restrict__ r) {
+  auto rec = [&](int g, int& hx, int& hy) {
+    const int4 u = g >= 0 ? grp[g0 + g] : make_int4(0, 0, 0, 0);
+    spos(geo, u.x, hx, hy);
+    return u;
+  };
+  grp_wave_of<T>(wave, ng, rec, gent, gval, glinv, gninv, geo, x, r);
+}
+
+template <typename T>
+__global__ __launch_bounds__(kGNT) void ks_lsgs_grp(int g0, int ng, const int4* __restrict__ grp,
+                                                    const int* __restrict__ gent,
+                                                    const typename T2of<T>::type* __restrict__ gval,
+                                                    const T* __restrict__ glinv,
+                                                    const typename T2of<T>::type* __restrict__ gninv, SGeo geo,
+                                                    T* __restrict__ x, T* __restrict__ r) {
+  grp_wave<T>(blockIdx.x * (kGNT / 64) + threadIdx.x / 64, g0, ng, grp, gent, gval, glinv, gninv, geo, x, r);
 }
 
 // Every smoothing step of Alg. 2 on a small level in one workgroup.  On
@@ -987,6 +1016,59 @@ __global__ __launch_bounds__(kWT) void ks_lsgs_wg(int ndof, int nph, int nseq, i
     r[i] = rs[i];
     x[i] = xs[i];
   }
+}
+
+// The lattice path of an LSGS colour phase.  The groups of one colour lie on
+// a lattice (every 5th P2 node in each direction, or every 3rd vertex), and
+// on the uniform mesh every group more than a few half-steps from the
+// boundary has the group class of its node type: the class depends only on
+// the parities of the node's position (a P2 vertex node, or the midpoint of
+// a horizontal, vertical or diagonal edge; one type for the vertex groups).
+// There the group's record (its two unknowns and its class's entry range) is
+// formed from its index, so a wave's chain of dependent loads starts at the
+// class entries rather than at the record.  Groups are taken in the record
+// path's order (row by row over the whole colour lattice, all node types
+// interleaved), which keeps the residual lines that neighbouring groups share
+// in cache; the groups near the boundary take the record path in the same
+// launch.
+struct LatPhase {
+  int hx0, hy0;  // first interior group's position on the half-step lattice
+  int nx, ny;    // interior groups per row, rows
+  int step;      // lattice step between neighbouring groups (half-steps)
+  int ent[4];    // class entry range per node type t = (hx & 1) + 2 (hy & 1)
+  int len[4];
+  int nblk;      // workgroups of the interior part; the record part follows
+  int bi, bj;    // index bases of the fields of the group's two unknowns
+  int p1;        // the groups sit at P1 vertices (pressure and its multiplier)
+  int g0, ng;    // records [g0, g0 + ng) of the phase's remaining groups
+};
+
+template <typename T>
+__global__ __launch_bounds__(kGNT) void ks_lsgs_lat(LatPhase P, const int4* __restrict__ grp,
+                                                    const int* __restrict__ gent,
+                                                    const typename T2of<T>::type* __restrict__ gval,
+                                                    const T* __restrict__ glinv,
+                                                    const typename T2of<T>::type* __restrict__ gninv, SGeo geo,
+                                                    T* __restrict__ x, T* __restrict__ r) {
+  constexpr int WPB = kGNT / 64;  // waves per workgroup
+  const int blk = blockIdx.x, wave = (int)threadIdx.x / 64;
+  if (blk >= P.nblk) {  // record part
+    grp_wave<T>((blk - P.nblk) * WPB + wave, P.g0, P.ng, grp, gent, gval, glinv, gninv, geo, x, r);
+    return;
+  }
+  auto rec = [&](int g, int& hx, int& hy) {
+    const int gl = g >= 0 ? g : 0;
+    const int gy = gl / P.nx, gx = gl - gy * P.nx;
+    hx = P.hx0 + P.step * gx;
+    hy = P.hy0 + P.step * gy;
+    const int t = (hx & 1) + 2 * (hy & 1);
+    // the node type's class (selects: no indexing of the argument by a lane value)
+    const int e0 = t == 0 ? P.ent[0] : t == 1 ? P.ent[1] : t == 2 ? P.ent[2] : P.ent[3];
+    const int l0 = t == 0 ? P.len[0] : t == 1 ? P.len[1] : t == 2 ? P.len[2] : P.len[3];
+    const int b = P.p1 ? (hy >> 1) * (geo.n + 1) + (hx >> 1) : (hy - 1) * geo.m + (hx - 1);
+    return g >= 0 ? make_int4(P.bi + b, P.bj + b, e0, e0 + l0) : make_int4(0, 0, 0, 0);
+  };
+  grp_wave_of<T>(blk * WPB + wave, P.nx * P.ny, rec, gent, gval, glinv, gninv, geo, x, r);
 }
 
 // value of lane u (u uniform), read as scalars: independent of the exec mask
@@ -1222,6 +1304,10 @@ struct StokesLevel {
   double* g_linv = nullptr;
   float2 *g_val32 = nullptr, *g_ninv32 = nullptr;
   float* g_linv32 = nullptr;
+  // the lattice path of the phases (see ks_lsgs_lat): per phase its
+  // interior lattice, and the remaining groups' records (l_rec)
+  std::vector<LatPhase> lph;
+  int4* l_rec = nullptr;
   // the same phases laid out for the one-workgroup sweep (small levels only)
   int2* w_meta = nullptr;
   int* w_col = nullptr;
@@ -1250,6 +1336,7 @@ struct Stokes {
   double alpha = 1.0, tau = 0.35;
   bool fp32 = false;
   bool wg_sweep = true;  // one-workgroup LSGS sweeps on small levels (MGKKT_NO_WG_SWEEP unset)
+  bool lattice = true;   // lattice path of the LSGS phases (MGKKT_NO_STOKES_LATTICE unset)
   std::vector<StokesLevel> lv;  // lv[l - k0]
   int *M_rp = nullptr, *M_col = nullptr;  // scalar P2 mass of the finest level (right-hand side)
   double* M_val = nullptr;
@@ -1505,6 +1592,96 @@ bool build_group_classes(const ClassA& C, const SGeo& g, const std::vector<int2>
   return true;
 }
 
+// The lattice path of the LSGS phases (see ks_lsgs_lat).  Per phase: for
+// each node type the class of the group nearest the centre, and the largest
+// boundary distance of a group of that type with another class; the groups
+// farther from the boundary than all of these form the interior, which must
+// be a full rectangle of the phase's lattice (checked), and each interior
+// group's unknowns and class are checked against its record.  The other
+// groups stay records, in phase order.
+bool build_lattice(const SGeo& g, const std::vector<int4>& rec, const std::vector<int>& gph,
+                   std::vector<LatPhase>& lph, std::vector<int4>& lrec, std::string* err) {
+  const int n = g.n, m = g.m;
+  lph.assign(gph.size() - 1, LatPhase{});
+  lrec.clear();
+  auto bdist = [&](int q) {
+    int hx, hy;
+    spos(g, rec[q].x, hx, hy);
+    return std::min(std::min(hx, 2 * n - hx), std::min(hy, 2 * n - hy));
+  };
+  for (size_t p = 0; p + 1 < gph.size(); p++) {
+    LatPhase& P = lph[p];
+    const int q0 = gph[p], q1 = gph[p + 1];
+    std::vector<char> inlat(q1 - q0, 0);
+    P.g0 = (int)lrec.size();
+    if (q1 > q0) {
+      const int fi = sfield(g, rec[q0].x), fj = sfield(g, rec[q0].y);
+      P.bi = sbase(g, fi);
+      P.bj = sbase(g, fj);
+      P.p1 = sp1(fi) ? 1 : 0;
+      // per node type: the centre group's class
+      int centre[4] = {-1, -1, -1, -1};
+      long best[4] = {-1, -1, -1, -1};
+      for (int q = q0; q < q1; q++) {
+        int hx, hy;
+        spos(g, rec[q].x, hx, hy);
+        const int t = (hx & 1) + 2 * (hy & 1);
+        const long d = (long)(hx - n) * (hx - n) + (long)(hy - n) * (hy - n);
+        if (best[t] < 0 || d < best[t]) best[t] = d, centre[t] = q;
+      }
+      int margin = -1;
+      for (int q = q0; q < q1; q++) {
+        int hx, hy;
+        spos(g, rec[q].x, hx, hy);
+        const int t = (hx & 1) + 2 * (hy & 1);
+        if (rec[q].z != rec[centre[t]].z) margin = std::max(margin, bdist(q));
+      }
+      int hx0 = 1 << 30, hy0 = 1 << 30, hx1 = -1, hy1 = -1, cnt = 0, step = 0;
+      for (int q = q0; q < q1; q++)
+        if (bdist(q) > margin) {
+          int hx, hy;
+          spos(g, rec[q].x, hx, hy);
+          hx0 = std::min(hx0, hx), hx1 = std::max(hx1, hx), hy0 = std::min(hy0, hy), hy1 = std::max(hy1, hy);
+          cnt++;
+        }
+      for (int q = q0; q < q1 && cnt > 1; q++)
+        if (bdist(q) > margin) {
+          int hx, hy;
+          spos(g, rec[q].x, hx, hy);
+          step = std::gcd(step, std::gcd(hx - hx0, hy - hy0));
+        }
+      if (cnt == 1) step = 1;
+      const bool full = cnt > 0 && (long)((hx1 - hx0) / step + 1) * ((hy1 - hy0) / step + 1) == cnt;
+      if (full) {
+        P.hx0 = hx0, P.hy0 = hy0, P.step = step;
+        P.nx = (hx1 - hx0) / step + 1, P.ny = (hy1 - hy0) / step + 1;
+        for (int t = 0; t < 4; t++) {
+          P.ent[t] = centre[t] >= 0 ? rec[centre[t]].z : 0;
+          P.len[t] = centre[t] >= 0 ? rec[centre[t]].w - rec[centre[t]].z : 0;
+        }
+        for (int q = q0; q < q1; q++) {
+          if (bdist(q) <= margin) continue;
+          int hx, hy;
+          spos(g, rec[q].x, hx, hy);
+          const int t = (hx & 1) + 2 * (hy & 1);
+          const int b = P.p1 ? (hy >> 1) * (n + 1) + (hx >> 1) : (hy - 1) * m + (hx - 1);
+          if ((hx - hx0) % step || (hy - hy0) % step || rec[q].x != P.bi + b || rec[q].y != P.bj + b ||
+              rec[q].z != P.ent[t] || rec[q].w != P.ent[t] + P.len[t]) {
+            *err = "stokes: lattice group mismatch";
+            return false;
+          }
+          inlat[q - q0] = 1;
+        }
+        P.nblk = (cnt + kGNT / kGLR - 1) / (kGNT / kGLR);
+      }
+      for (int q = q0; q < q1; q++)
+        if (!inlat[q - q0]) lrec.push_back(rec[q]);
+    }
+    P.ng = (int)lrec.size() - P.g0;
+  }
+  return true;
+}
+
 // Lanes of the one-workgroup sweep: group slot k of a phase goes to wave
 // k / kWG, its two rows to consecutive runs of kWLR lanes, and entry e of a
 // row to lane e % kWLR, register e / kWLR.  Levels whose residual, x and
@@ -1610,15 +1787,20 @@ hipError_t build_level(Stokes* S, int l, bool finest, std::string* err) {
     SCHK(up(S, &L.g_val, gval));
     SCHK(up(S, &L.g_linv, glv));
     SCHK(up(S, &L.g_ninv, gni));
+    auto f2 = [](const std::vector<double2>& v) {
+      std::vector<float2> o(v.size());
+      for (size_t t = 0; t < v.size(); t++) o[t] = make_float2((float)v[t].x, (float)v[t].y);
+      return o;
+    };
     if (S->fp32) {
-      auto f2 = [](const std::vector<double2>& v) {
-        std::vector<float2> o(v.size());
-        for (size_t t = 0; t < v.size(); t++) o[t] = make_float2((float)v[t].x, (float)v[t].y);
-        return o;
-      };
       SCHK(up(S, &L.g_val32, f2(gval)));
       SCHK(up(S, &L.g_ninv32, f2(gni)));
       SCHK(up(S, &L.g_linv32, to32(glv)));
+    }
+    if (S->lattice && (S->smoother == MG_LSGS || S->smoother == MG_SLSGS)) {
+      std::vector<int4> lrec;
+      if (!build_lattice(L.geo, rec, L.gph, L.lph, lrec, err)) return hipErrorInvalidValue;
+      SCHK(up(S, &L.l_rec, lrec));
     }
   }
   if (S->wg_sweep && (S->smoother == MG_LSGS || S->smoother == MG_SLSGS)) SCHK(build_wg_phases(S, L, A, grp));
@@ -1783,6 +1965,13 @@ hipError_t s_smooth(Stokes* S, StokesLevel& L, T* x, T* r, int steps, hipStream_
             const int ph = sw == 0 ? k : nph - 1 - k;
             const int g0 = L.gph[ph], ng = L.gph[ph + 1] - g0;
             if (ng == 0) continue;  // a colour without nodes on a small level
+            if (!L.lph.empty()) {
+              const LatPhase& P = L.lph[ph];
+              const int nb = P.nblk + (P.ng + kGNT / kGLR - 1) / (kGNT / kGLR);
+              hipLaunchKernelGGL((ks_lsgs_lat<T>), dim3(nb), dim3(kGNT), 0, s, P, (const int4*)L.l_rec,
+                                 (const int*)L.g_ent, SV<T>::G(L), SV<T>::GL(L), SV<T>::GN(L), L.geo, x, r);
+              continue;
+            }
             hipLaunchKernelGGL((ks_lsgs_grp<T>), dim3(blocks_for(ng, kGNT / kGLR)), dim3(kGNT), 0, s, g0, ng,
                                (const int4*)L.mgroups, (const int*)L.g_ent, SV<T>::G(L), SV<T>::GL(L), SV<T>::GN(L),
                                L.geo, x, r);
@@ -1875,6 +2064,7 @@ static int stokes_create_body(Stokes* S, int level, int k0, double alpha, const 
   S->tau = o.tau;
   S->fp32 = o.precision == MG_FP32_IR;
   S->wg_sweep = std::getenv("MGKKT_NO_WG_SWEEP") == nullptr;
+  S->lattice = std::getenv("MGKKT_NO_STOKES_LATTICE") == nullptr;
   S->lv.resize(level - k0 + 1);
   for (int l = k0; l <= level; l++) {
     const hipError_t e = build_level(S, l, l == level, err);

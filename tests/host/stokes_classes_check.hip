@@ -6,7 +6,11 @@
 //  - patch classes: every patch's unknowns, LU factors and pivots (computed
 //    here from the CSR entries) and its coefficient block over the union of
 //    its rows' columns come back exactly, and the patches of a colour share
-//    no union column.
+//    no union column;
+//  - the lattice path of the LSGS phases: with the smoother's own L^-1 and
+//    N^-1, each phase's interior groups (their records formed from the
+//    index as the kernel does) and its remaining records cover the phase's
+//    groups exactly once, and each formed record equals the group's own.
 // Prints one line per size and exits non-zero on any mismatch.
 #include "../../paper_1502_03917_amd/csrc/stokes.hip"
 #include <cstdio>
@@ -139,6 +143,78 @@ static long check_patches(int n, const HCsr& A, const SGeo& g) {
   return bad;
 }
 
+static long check_lattice(int n, double alpha, const Blocks& B, const HCsr& A, const SGeo& g, const ClassA& C,
+                          double* frac) {
+  // L^-1 and N^-1 as the solver sets them up
+  const int nv = g.nv, np = g.np, ndof = 4 * nv + 2 * np;
+  std::vector<double> Ld(ndof), W(nv);
+  for (int a = 0; a < nv; a++) W[a] = entry(B.Ms, a, a) + std::sqrt(alpha) * entry(B.Ks, a, a);
+  const int op = 2 * nv, ol = 2 * nv + np, om = 4 * nv + np;
+  for (int a = 0; a < nv; a++) {
+    Ld[a] = Ld[nv + a] = W[a];
+    Ld[ol + a] = Ld[ol + nv + a] = W[a] / alpha;
+  }
+  for (int q = 0; q < np; q++) {
+    double s = 0.0;
+    for (int c = 0; c < 2; c++)
+      for (int k = B.D[c].rp[q]; k < B.D[c].rp[q + 1]; k++) s += B.D[c].val[k] * B.D[c].val[k] / W[B.D[c].col[k]];
+    Ld[op + q] = alpha * s;
+    Ld[om + q] = s;
+  }
+  std::vector<double> Linv(ndof), Ninv(ndof);
+  for (int i = 0; i < ndof; i++) Linv[i] = 1.0 / Ld[i];
+  for (int i = 0; i < ndof; i++) {
+    double s = 0.0;
+    for (int k = A.rp[i]; k < A.rp[i + 1]; k++) s += A.val[k] * A.val[k] * Linv[A.col[k]];
+    Ninv[i] = 1.0 / s;
+  }
+  std::vector<int2> grp;
+  std::vector<int> ph;
+  colour_groups(n, grp, ph);
+  std::vector<int4> rec;
+  std::vector<int> ent;
+  std::vector<double2> val, nvv;
+  std::vector<double> lv;
+  std::string err;
+  if (!build_group_classes(C, g, grp, Linv, Ninv, rec, ent, val, lv, nvv, &err)) { printf("%s\n", err.c_str()); return 1; }
+  std::vector<LatPhase> lph;
+  std::vector<int4> lrec;
+  if (!build_lattice(g, rec, ph, lph, lrec, &err)) { printf("%s\n", err.c_str()); return 1; }
+  if (lph.size() + 1 != ph.size()) return 1;
+  long bad = 0, nlat = 0;
+  for (size_t p = 0; p + 1 < ph.size(); p++) {
+    const LatPhase& P = lph[p];
+    std::map<std::pair<int, int>, int> own;  // (i, j) -> its record
+    for (int t = ph[p]; t < ph[p + 1]; t++) own[{rec[t].x, rec[t].y}] = t;
+    std::map<std::pair<int, int>, int> seen;  // (i, j) -> times covered
+    if (P.nblk != (P.nx * P.ny + kGNT / kGLR - 1) / (kGNT / kGLR)) bad++;
+    for (int gi = 0; gi < P.nx * P.ny; gi++) {
+      // the record as the kernel forms it
+      const int hx = P.hx0 + P.step * (gi % P.nx), hy = P.hy0 + P.step * (gi / P.nx);
+      const int t = (hx & 1) + 2 * (hy & 1);
+      const int b = P.p1 ? (hy >> 1) * (n + 1) + (hx >> 1) : (hy - 1) * g.m + (hx - 1);
+      const int4 u = make_int4(P.bi + b, P.bj + b, P.ent[t], P.ent[t] + P.len[t]);
+      seen[{u.x, u.y}]++;
+      nlat++;
+      auto it = own.find({u.x, u.y});
+      if (it == own.end()) { bad++; continue; }
+      const int4 v = rec[it->second];
+      if (v.z != u.z || v.w != u.w) bad++;
+      int vx, vy;
+      spos(g, v.x, vx, vy);
+      if (vx != hx || vy != hy) bad++;
+    }
+    for (int t = P.g0; t < P.g0 + P.ng; t++) seen[{lrec[t].x, lrec[t].y}]++;
+    if ((int)seen.size() != ph[p + 1] - ph[p]) bad++;
+    for (int t = ph[p]; t < ph[p + 1]; t++) {
+      auto it = seen.find({rec[t].x, rec[t].y});
+      if (it == seen.end() || it->second != 1) bad++;
+    }
+  }
+  *frac = rec.empty() ? 0.0 : (double)nlat / rec.size();
+  return bad;
+}
+
 int main() {
   for (int n : {2, 4, 8, 16, 64}) {
     Blocks B;
@@ -151,8 +227,11 @@ int main() {
       std::string err;
       if (!build_classes(A, g, C, &err)) { printf("n=%d: %s\n", n, err.c_str()); return 1; }
       const long br = check_rows(A, g, C), bg = check_groups(n, A, g, C), bp = check_patches(n, A, g);
-      printf("n=%d alpha=%g rows=%d bad rows=%ld groups=%ld patches=%ld\n", n, alpha, A.nrows, br, bg, bp);
-      if (br || bg || bp) return 1;
+      double frac = 0.0;
+      const long bl = check_lattice(n, alpha, B, A, g, C, &frac);
+      printf("n=%d alpha=%g rows=%d bad rows=%ld groups=%ld patches=%ld lattice=%ld (%.3f of the groups)\n", n, alpha,
+             A.nrows, br, bg, bp, bl, frac);
+      if (br || bg || bp || bl) return 1;
     }
   }
   printf("ok\n");

@@ -134,6 +134,40 @@ def test_stokes_wg_sweep_matches_phase_launches(torch_cuda, monkeypatch):
     assert _rel(out[1][1], out[0][1]) < 1e-13
 
 
+@pytest.mark.parametrize("level,smoother,precision", [(5, "lsgs", "fp64"), (7, "slsgs", "fp64"), (8, "lsgs", "fp64"),
+                                                     (7, "lsgs", "fp32_ir")])
+def test_stokes_lattice_phases_match_records(torch_cuda, monkeypatch, level, smoother, precision):
+    """The lattice path of the LSGS colour phases (the records of the interior
+    groups formed from their index) against the record path of every group
+    (MGKKT_NO_STOKES_LATTICE=1): three smoothing steps on the same input, and
+    three FP32-refinement iterates, per field."""
+    torch = torch_cuda
+    monkeypatch.setenv("MGKKT_NO_STOKES_LATTICE", "1")
+    s_rec = _solver(level, 1e-2, smoother=smoother, precision=precision, max_cycles=3)
+    monkeypatch.delenv("MGKKT_NO_STOKES_LATTICE")
+    s_lat = _solver(level, 1e-2, smoother=smoother, precision=precision, max_cycles=3)
+    n = s_lat.vec_len()
+    x0 = workloads.uniform(n, 95)
+    r0 = workloads.uniform(n, 96)
+    out = []
+    for s in (s_rec, s_lat):
+        xg, rg = _dev(torch, x0), _dev(torch, r0)
+        s.smooth(xg, rg, steps=3)
+        out.append((_host(xg), _host(rg)))
+    assert_fields(out[1][0], out[0][0], 1e-13, problem="stokes", level=level, what="x after 3 steps")
+    assert_fields(out[1][1], out[0][1], 1e-12, problem="stokes", level=level, what="r after 3 steps")
+    if precision == "fp32_ir":
+        f = workloads.uniform(n, 97)
+        sol = []
+        for s in (s_rec, s_lat):
+            xg = torch.zeros(n, dtype=torch.float64, device="cuda")
+            s.solve(_dev(torch, f), xg, tol=1e-12, raise_on_error=False)
+            sol.append(_host(xg))
+        assert_fields(sol[1], sol[0], 1e-5, problem="stokes", level=level, what="3 FP32-refinement iterates")
+    s_rec.close()
+    s_lat.close()
+
+
 STOKES_CYCLES = [
     (3, 1e-2, "lsgs", 1),
     (3, 1.0, "ne", 1),
