@@ -266,18 +266,70 @@ __device__ __forceinline__ void lsgs_tile_body(const Lev& L, int ntx, int nty, i
   }
   if constexpr (IO == kIoProlong) {
     // (1) x + P x_c on every cell of the region and of the ring around it
-    // (the guard positions), zero outside the square: a coarse vertex takes
-    // the coarse value, a vertex on a coarse edge (horizontal, vertical or
-    // the (I,J)-(I+1,J+1) diagonal) the mean of its two endpoints (for a
-    // coarse vertex both endpoints are the vertex itself, and the mean is
-    // its value exactly).  The loads of a batch of cells are all issued
-    // before any of them is used.
+    // (the guard positions), zero outside the square.  A thread takes the
+    // 2 x 2 fine cells (2I + a, 2J + b), a, b in {0, 1}: P x_c there is the
+    // mean of the coarse values at (I, J) and (I + a, J + b) (a coarse vertex,
+    // or the two ends of the horizontal, vertical or (I,J)-(I+1,J+1) diagonal
+    // coarse edge the fine vertex halves; for a coarse vertex the mean is its
+    // value exactly).  The loads of a batch of blocks are all issued before
+    // any of them is used; f is loaded after the batches, in flight through
+    // the barrier.
     const Lev& Lc = io->Lc;
     const __amdgpu_buffer_rsrc_t Rxc = make_rsrc(io->xc, (size_t)2 * Lc.V * sizeof(T));
     const unsigned foc = (unsigned)(Lc.V * sizeof(T));
     const __amdgpu_buffer_rsrc_t Rf = make_rsrc(io->f, vbytes);
+    constexpr int RA = G::RMAX + 2;               // rows and columns of region + ring in s2
+    constexpr int BN = RA / 2 + 1;                // 2 x 2 blocks per row that cover them
+    constexpr int NB = (BN * BN + NT - 1) / NT;  // blocks per thread
+    constexpr int BB = 1;                         // blocks per batch
+    const int fa = ci0 - 1, fb = rj0 - 1;         // fine cell of s2[0] (>= -1)
+    const int I0 = (fa + 2) / 2 - 1, J0 = (fb + 2) / 2 - 1;  // floor(fa / 2), floor(fb / 2)
+    const int nc = Lc.n;
 #pragma unroll
-    for (int q = 0; q < NR; q++) {  // f of the region, in flight through (1)
+    for (int q0 = 0; q0 < NB; q0 += BB) {
+      T cv[BB][8], xv[BB][8];
+#pragma unroll
+      for (int u = 0; u < BB; u++) {
+        const int e = tid + (q0 + u) * NT;
+        const bool live = q0 + u < NB && e < BN * BN;
+        const int bj = e / BN, bi = e - bj * BN;
+#pragma unroll
+        for (int k = 0; k < 4; k++) {  // coarse vertex (I + (k & 1), J + (k >> 1)); fine cell (2I + (k & 1), 2J + (k >> 1))
+          const int I = I0 + bi + (k & 1), J = J0 + bj + (k >> 1);
+          const bool okc = live && I >= 0 && I <= nc && J >= 0 && J <= nc;
+          const unsigned oc = okc ? (unsigned)((J * Lc.ld + I) * sizeof(T)) : kOff;
+          cv[u][2 * k] = bload(Rxc, oc, (T*)nullptr);
+          cv[u][2 * k + 1] = bload(Rxc, okc ? oc + foc : kOff, (T*)nullptr);
+          const int gi = 2 * (I0 + bi) + (k & 1), gj = 2 * (J0 + bj) + (k >> 1);
+          const int wx = gi - fa, wy = gj - fb;
+          const bool okx = live && wx < RA && wy < RA && wx <= RW + 1 && wy <= RH + 1 && gi >= 0 && gi <= n &&
+                           gj >= 0 && gj <= n;
+          const unsigned ox = okx ? (unsigned)((gj * ld + gi) * sizeof(T)) : kOff;
+          xv[u][2 * k] = bload(Rxi, ox, (T*)nullptr);
+          xv[u][2 * k + 1] = bload(Rxi, okx ? ox + fo : kOff, (T*)nullptr);
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < BB; u++) {
+        const int e = tid + (q0 + u) * NT;
+        if (q0 + u < NB && e < BN * BN) {
+          const int bj = e / BN, bi = e - bj * BN;
+#pragma unroll
+          for (int k = 0; k < 4; k++) {
+            const int gi = 2 * (I0 + bi) + (k & 1), gj = 2 * (J0 + bj) + (k >> 1);
+            const int wx = gi - fa, wy = gj - fb;
+            if (wx >= 0 && wx < RA && wy >= 0 && wy < RA) {
+              // loads outside the square or past region + ring returned zeros
+              const bool in = wx <= RW + 1 && wy <= RH + 1 && gi >= 0 && gi <= n && gj >= 0 && gj <= n;
+              const T vy = (T)0.5 * (cv[u][0] + cv[u][2 * k]), vl = (T)0.5 * (cv[u][1] + cv[u][2 * k + 1]);
+              s2[wy * G::RP + wx] = in ? (T2){xv[u][2 * k] + vy, xv[u][2 * k + 1] + vl} : (T2){(T)0, (T)0};
+            }
+          }
+        }
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < NR; q++) {  // f of the region
       const int e = tid + q * NT;
       const int lr = e / G::RMAX, li = e - lr * G::RMAX;
       const bool ok = e < G::RMAX * G::RMAX && li < RW && lr < RH;
@@ -285,43 +337,9 @@ __device__ __forceinline__ void lsgs_tile_body(const Lev& L, int ntx, int nty, i
       ry[q] = bload(Rf, o, (T*)nullptr);
       rl[q] = bload(Rf, ok ? o + fo : kOff, (T*)nullptr);
     }
-    constexpr int RA = G::RMAX + 2;
-    constexpr int NA = (RA * RA + NT - 1) / NT;  // cells per thread
-    constexpr int BA = 3;                        // cells per batch
-#pragma unroll
-    for (int q0 = 0; q0 < NA; q0 += BA) {
-      T xv[BA], xw[BA], a0[BA], b0[BA], a1[BA], b1[BA];
-#pragma unroll
-      for (int u = 0; u < BA; u++) {
-        const int e = tid + (q0 + u) * NT;
-        const int lr = e / RA - 1, li = e - (lr + 1) * RA - 1;
-        const int gi = ci0 + li, gj = rj0 + lr;
-        const bool ok = q0 + u < NA && e < RA * RA && li <= RW && lr <= RH && gi >= 0 && gi <= n && gj >= 0 &&
-                        gj <= n;
-        const unsigned o = ok ? (unsigned)((gj * ld + gi) * sizeof(T)) : kOff;
-        const unsigned c0 = ok ? (unsigned)(((gj >> 1) * Lc.ld + (gi >> 1)) * sizeof(T)) : kOff;
-        const unsigned c1 = ok ? (unsigned)((((gj + 1) >> 1) * Lc.ld + ((gi + 1) >> 1)) * sizeof(T)) : kOff;
-        xv[u] = bload(Rxi, o, (T*)nullptr);
-        xw[u] = bload(Rxi, ok ? o + fo : kOff, (T*)nullptr);
-        a0[u] = bload(Rxc, c0, (T*)nullptr);
-        b0[u] = bload(Rxc, ok ? c0 + foc : kOff, (T*)nullptr);
-        a1[u] = bload(Rxc, c1, (T*)nullptr);
-        b1[u] = bload(Rxc, ok ? c1 + foc : kOff, (T*)nullptr);
-      }
-#pragma unroll
-      for (int u = 0; u < BA; u++) {
-        const int e = tid + (q0 + u) * NT;
-        if (q0 + u < NA && e < RA * RA) {
-          // masked loads returned zeros outside the square
-          const T vy = (T)0.5 * (a0[u] + a1[u]), vl = (T)0.5 * (b0[u] + b1[u]);
-          s2[e / RA * G::RP + e % RA] = (T2){xv[u] + vy, xw[u] + vl};
-        }
-      }
-    }
     lds_barrier();
-    // (2) r = f - A (x + P x_c) on the region, into registers (f loaded
-    // before (1)); the corrected iterate of the owned vertices for the x
-    // stores
+    // (2) r = f - A (x + P x_c) on the region, into registers; the corrected
+    // iterate of the owned vertices for the x stores
     const T ai = (T)L.ainv;
 #pragma unroll
     for (int q = 0; q < NR; q++) {
