@@ -1056,19 +1056,39 @@ __global__ __launch_bounds__(kGNT) void ks_lsgs_lat(LatPhase P, const int4* __re
     grp_wave<T>((blk - P.nblk) * WPB + wave, P.g0, P.ng, grp, gent, gval, glinv, gninv, geo, x, r);
     return;
   }
+  // the classes of the four node types in LDS, read by every group of the
+  // workgroup (type t's entries at [t * kMaxGroupEntries, + len), its N^-1
+  // pair at the first), so that the phase's global accesses are the
+  // residual's gathers and scatters
+  using T2 = typename T2of<T>::type;
+  constexpr int ME = kMaxGroupEntries;
+  __shared__ int s_ent[4 * ME];
+  __shared__ T2 s_val[4 * ME], s_ninv[4 * ME];
+  __shared__ T s_linv[4 * ME];
+  for (int q = (int)threadIdx.x; q < 4 * ME; q += kGNT) {
+    const int t = q / ME, k = q - t * ME;
+    // selects: no indexing of the argument by a thread value
+    const int e0 = t == 0 ? P.ent[0] : t == 1 ? P.ent[1] : t == 2 ? P.ent[2] : P.ent[3];
+    const int l0 = t == 0 ? P.len[0] : t == 1 ? P.len[1] : t == 2 ? P.len[2] : P.len[3];
+    if (k < l0) {
+      s_ent[q] = gent[e0 + k];
+      s_val[q] = gval[e0 + k];
+      s_linv[q] = glinv[e0 + k];
+      if (k == 0) s_ninv[q] = gninv[e0];
+    }
+  }
+  __syncthreads();
   auto rec = [&](int g, int& hx, int& hy) {
     const int gl = g >= 0 ? g : 0;
     const int gy = gl / P.nx, gx = gl - gy * P.nx;
     hx = P.hx0 + P.step * gx;
     hy = P.hy0 + P.step * gy;
     const int t = (hx & 1) + 2 * (hy & 1);
-    // the node type's class (selects: no indexing of the argument by a lane value)
-    const int e0 = t == 0 ? P.ent[0] : t == 1 ? P.ent[1] : t == 2 ? P.ent[2] : P.ent[3];
     const int l0 = t == 0 ? P.len[0] : t == 1 ? P.len[1] : t == 2 ? P.len[2] : P.len[3];
     const int b = P.p1 ? (hy >> 1) * (geo.n + 1) + (hx >> 1) : (hy - 1) * geo.m + (hx - 1);
-    return g >= 0 ? make_int4(P.bi + b, P.bj + b, e0, e0 + l0) : make_int4(0, 0, 0, 0);
+    return g >= 0 ? make_int4(P.bi + b, P.bj + b, t * ME, t * ME + l0) : make_int4(0, 0, 0, 0);
   };
-  grp_wave_of<T>(blk * WPB + wave, P.nx * P.ny, rec, gent, gval, glinv, gninv, geo, x, r);
+  grp_wave_of<T>(blk * WPB + wave, P.nx * P.ny, rec, s_ent, s_val, s_linv, s_ninv, geo, x, r);
 }
 
 // value of lane u (u uniform), read as scalars: independent of the exec mask
