@@ -1025,8 +1025,9 @@ __global__ __launch_bounds__(kWT) void ks_lsgs_wg(int ndof, int nph, int nseq, i
 // the parities of the node's position (a P2 vertex node, or the midpoint of
 // a horizontal, vertical or diagonal edge; one type for the vertex groups).
 // There the group's record (its two unknowns and its class's entry range) is
-// formed from its index, so a wave's chain of dependent loads starts at the
-// class entries rather than at the record.  Groups are taken in the record
+// formed from its index, and the classes of the four node types are staged in
+// LDS once per workgroup, so a wave's only global loads are the residual's
+// gathers (no record, no class entries).  Groups are taken in the record
 // path's order (row by row over the whole colour lattice, all node types
 // interleaved), which keeps the residual lines that neighbouring groups share
 // in cache; the groups near the boundary take the record path in the same
