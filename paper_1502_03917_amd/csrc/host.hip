@@ -987,7 +987,7 @@ bool sweep_norm(const mg_ctx* c) {
 int iterate(mg_ctx* c, const double* f, double* x, hipStream_t s) {
   if (c->st) {
     if (c->o.precision == MG_FP32_IR)
-      HIPCHK(c, mgk::stokes_ir_step(c->st, x, s, c->d_norm));
+      HIPCHK(c, mgk::stokes_ir_step(c->st, x, s, c->d_norm, c->o.inner_cycles));
     else
       HIPCHK(c, mgk::stokes_cycle(c->st, f, x, fine_r(c), true, s));
     return residual_norm(c, f, x, fine_r(c), 0, s);
@@ -1450,7 +1450,7 @@ static int impl_mg_cycle(mg_ctx* ctx, const double* f, double* x, void* stream) 
     if (ctx->o.precision == MG_FP32_IR) {
       int st = residual_norm(ctx, f, x, fine_r(ctx), 0, s);
       if (st != MG_OK) return st;
-      HIPCHK(ctx, mgk::stokes_ir_step(ctx->st, x, s, ctx->d_norm));
+      HIPCHK(ctx, mgk::stokes_ir_step(ctx->st, x, s, ctx->d_norm, ctx->o.inner_cycles));
       return MG_OK;
     }
     HIPCHK(ctx, mgk::stokes_cycle(ctx->st, f, x, fine_r(ctx), false, s));

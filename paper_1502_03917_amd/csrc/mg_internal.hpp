@@ -271,7 +271,7 @@ hipError_t stokes_coarse_solve(Stokes* S, const double* f, double* x, hipStream_
 hipError_t stokes_project(Stokes* S, int l, double* x, hipStream_t s);
 hipError_t stokes_cycle(Stokes* S, const double* f, double* x, double* r, bool current, hipStream_t s);
 double* stokes_fine_r(Stokes* S);
-hipError_t stokes_ir_step(Stokes* S, double* x, hipStream_t s, const double* nrm2);
+hipError_t stokes_ir_step(Stokes* S, double* x, hipStream_t s, const double* nrm2, int inner);
 
 // FP32-preconditioned iterative refinement glue
 // refinement scale s = sqrt(*nrm2) read on the device (1 if the norm is zero)

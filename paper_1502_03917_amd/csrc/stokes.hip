@@ -2211,12 +2211,13 @@ double* stokes_fine_r(Stokes* S) { return S->lv.back().r; }
 // one refinement step: FP32 cycle from zero on the scaled FP64 residual r
 // (||r||^2 in nrm2 on the device), x += s c in FP64, then the mean
 // projection of the FP64 iterate
-hipError_t stokes_ir_step(Stokes* S, double* x, hipStream_t s, const double* nrm2) {
+hipError_t stokes_ir_step(Stokes* S, double* x, hipStream_t s, const double* nrm2, int inner) {
   StokesLevel& L = S->lv.back();
   const size_t n = L.ndof;
   SCHK(launch_to_f32_scaled(L.r, n, nrm2, L.f32, L.r32, s));
   SCHK(launch_zero_f32(L.x32, n, s));
-  SCHK(s_cycle<float>(S, S->level, L.f32, L.x32, L.r32, true, s));
+  // inner_cycles FP32 cycles from zero; the residual is current for the first
+  for (int k = 0; k < inner; k++) SCHK(s_cycle<float>(S, S->level, L.f32, L.x32, L.r32, k == 0, s));
   SCHK(launch_axpy_f32(L.x32, n, nrm2, x, s));
   return s_project<double>(S, L, x, s);
 }

@@ -168,6 +168,24 @@ def test_stokes_lattice_phases_match_records(torch_cuda, monkeypatch, level, smo
     s_lat.close()
 
 
+def test_stokes_fp32_refinement_inner_cycles(torch_cuda):
+    """Two FP32 cycles per refinement step (inner_cycles = 2) on Stokes: the
+    solve reaches 1e-10 and agrees with the FP64 solve per field."""
+    torch = torch_cuda
+    level, alpha = 6, 1e-2
+    s64 = _solver(level, alpha)
+    s32 = _solver(level, alpha, precision="fp32_ir", inner_cycles=2)
+    vd = _dev(torch, workloads.desired_velocity(level, 7))
+    f = s64.rhs(vd)
+    x64, it64, rel64, st64 = s64.solve(f, tol=1e-10)
+    x32, it32, rel32, st32 = s32.solve(f, tol=1e-10)
+    assert st64 == 0 and st32 == 0 and rel32 <= 1e-10
+    assert it32 < it64  # two cycles per refinement iterate
+    assert_fields(_host(x32), _host(x64), 1e-8, problem="stokes", level=level, what="inner_cycles 2")
+    s64.close()
+    s32.close()
+
+
 STOKES_CYCLES = [
     (3, 1e-2, "lsgs", 1),
     (3, 1.0, "ne", 1),
