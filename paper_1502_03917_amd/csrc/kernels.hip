@@ -1140,12 +1140,17 @@ hipError_t launch_b_gather_norms(const double* const* d, int count, double* out,
 }
 
 // ---- dense coarse map: x = B r (accumulate 0) or x += B r (accumulate 1),
-// B row-major N x N with N even.  One wave per row and 8 rows per workgroup;
-// r is staged in LDS; a lane reads pairs of entries (one 16- or 8-byte load),
-// all of a row's loads in flight at once, and the wave sums its lanes in a
-// fixed order.
+// B row-major N x N with N even.  Four waves share a row (two rows per
+// 512-thread workgroup), so a wave keeps a quarter of the row's loads in
+// flight and twice as many waves stream the matrix as with one wave per row;
+// r is staged in LDS while those loads are in flight.  A lane reads pairs of
+// entries (one 16- or 8-byte load); wave k of a row takes the 64-pair chunks
+// k, k + 4, ...  Each wave sums its lanes in a fixed order, and the row's
+// four partial sums are added in wave order.
 namespace {
-constexpr int kDenseRows = 8;
+constexpr int kDenseWaves = 4;                                // waves per row
+constexpr int kDenseThreads = 512;                            // threads per workgroup
+constexpr int kDenseRows = kDenseThreads / 64 / kDenseWaves;  // rows per workgroup
 template <typename T>
 struct Pair2;
 template <>
@@ -1158,28 +1163,30 @@ struct Pair2<float> {
 };
 
 template <typename T>
-__global__ __launch_bounds__(64 * kDenseRows) void k_dense_map(const T* __restrict__ B, int N, const T* __restrict__ r,
+__global__ __launch_bounds__(kDenseThreads) void k_dense_map(const T* __restrict__ B, int N, const T* __restrict__ r,
                                                              T* __restrict__ x, int accumulate) {
   using T2 = typename Pair2<T>::type;
   __shared__ __align__(16) T rs[kDenseMapMaxN];
-  const int tid = threadIdx.x, lane = tid & 63;
-  const int row = blockIdx.x * kDenseRows + (tid >> 6);
+  __shared__ T part[kDenseThreads / 64];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int row = blockIdx.x * kDenseRows + wave / kDenseWaves;
+  const int wr = wave % kDenseWaves;
   const int np = N / 2;
-  // loads in issue order: this thread's share of r, then the whole row (in
-  // flight while r is staged in LDS: the wait for r does not wait for them)
-  constexpr int RU = (kDenseMapMaxN + 64 * kDenseRows - 1) / (64 * kDenseRows);
+  // loads in issue order: this thread's share of r, then its part of the row
+  // (in flight while r is staged in LDS: the wait for r does not wait for them)
+  constexpr int RU = (kDenseMapMaxN + kDenseThreads - 1) / kDenseThreads;
   T rv0[RU];
 #pragma unroll
   for (int u = 0; u < RU; u++) {
-    const int e = tid + u * 64 * kDenseRows;
+    const int e = tid + u * kDenseThreads;
     rv0[u] = r[e < N ? e : N - 1];  // unconditional loads keep the wait counts exact
   }
-  constexpr int U = (kDenseMapMaxN / 2 + 63) / 64;  // pairs per lane: the whole row in one batch
+  constexpr int U = (kDenseMapMaxN / 2 + 64 * kDenseWaves - 1) / (64 * kDenseWaves);  // pairs per lane
   T2 v[U];
   const T2* b2 = reinterpret_cast<const T2*>(B + (size_t)(row < N ? row : 0) * N);
 #pragma unroll
   for (int u = 0; u < U; u++) {
-    const int q = lane + 64 * u;
+    const int q = lane + 64 * (wr + kDenseWaves * u);
     // clamped index and a zero weight past the row's end: the load itself
     // stays unconditional (a guarded load would be moved under a branch)
     const T w = q < np ? (T)1 : (T)0;
@@ -1187,19 +1194,18 @@ __global__ __launch_bounds__(64 * kDenseRows) void k_dense_map(const T* __restri
   }
 #pragma unroll
   for (int u = 0; u < RU; u++) {
-    const int e = tid + u * 64 * kDenseRows;
+    const int e = tid + u * kDenseThreads;
     if (e < N) rs[e] = rv0[u];
   }
   // a barrier that orders the LDS stores only (the row's loads stay in flight)
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
   __builtin_amdgcn_s_barrier();
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
-  if (row >= N) return;
   const T2* r2 = reinterpret_cast<const T2*>(rs);
   T a0 = 0, a1 = 0;
 #pragma unroll
   for (int u = 0; u < U; u++) {
-    const int q = lane + 64 * u;
+    const int q = lane + 64 * (wr + kDenseWaves * u);
     const T2 rv = r2[q < np ? q : 0];
     a0 += v[u].x * rv.x;
     a1 += v[u].y * rv.y;
@@ -1207,14 +1213,21 @@ __global__ __launch_bounds__(64 * kDenseRows) void k_dense_map(const T* __restri
   T acc = a0 + a1;
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
-  if (lane == 0) x[row] = accumulate ? x[row] + acc : acc;
+  if (lane == 0) part[wave] = acc;
+  __syncthreads();  // every wave gets here: a row past N only skips the store
+  if (row < N && wr == 0 && lane == 0) {
+    T sum = part[wave];
+#pragma unroll
+    for (int k = 1; k < kDenseWaves; k++) sum += part[wave + k];
+    x[row] = accumulate ? x[row] + sum : sum;
+  }
 }
 }  // namespace
 
 template <typename T>
 hipError_t launch_dense_map(const T* B, int N, const T* r, T* x, int accumulate, hipStream_t s) {
   if (N <= 0 || N > kDenseMapMaxN || (N & 1)) return hipErrorInvalidValue;
-  hipLaunchKernelGGL((k_dense_map<T>), dim3((N + kDenseRows - 1) / kDenseRows), dim3(64 * kDenseRows), 0, s, B, N, r,
+  hipLaunchKernelGGL((k_dense_map<T>), dim3((N + kDenseRows - 1) / kDenseRows), dim3(kDenseThreads), 0, s, B, N, r,
                      x, accumulate);
   return hipGetLastError();
 }
