@@ -606,6 +606,13 @@ __device__ inline void block_store(double v, double* out) {
   }
 }
 
+// A read-only array seen through the constant address space: a load whose
+// index is the same on every lane of the wave becomes one scalar load.
+template <typename T>
+__device__ inline const __attribute__((address_space(4))) T* cptr(const T* p) {
+  return (const __attribute__((address_space(4))) T*)(p);
+}
+
 // Rows of a sparse operator: a CSR matrix (the transfers) or the stencil
 // classes of A.  row() gives the entry range and the row's lattice position
 // (classes) from which col_of() forms the column.
@@ -621,6 +628,10 @@ struct CsrRows {
   }
   __device__ int col_of(int k, int) const { return col[k]; }
   __device__ T val_of(int k) const { return val[k]; }
+  // the same for an entry index k common to the wave (loads from the
+  // constant address space, i.e. scalar loads)
+  __device__ int col_u(int k, int) const { return cptr(col)[k]; }
+  __device__ T val_u(int k) const { return cptr(val)[k]; }
 };
 template <typename T>
 struct ClassRows {
@@ -639,6 +650,8 @@ struct ClassRows {
   }
   __device__ int col_of(int k, int pos) const { return sent_col(g, ent[k], pos & 0xFFFF, pos >> 16); }
   __device__ T val_of(int k) const { return val[k]; }
+  __device__ int col_u(int k, int pos) const { return sent_col(g, cptr(ent)[k], pos & 0xFFFF, pos >> 16); }
+  __device__ T val_u(int k) const { return cptr(val)[k]; }
 };
 
 // Row kernels with 16 lanes per row (16 rows per 256-thread block), each
@@ -656,20 +669,56 @@ __device__ inline T row_sum(T v) {
 
 // r = f - A x, with per-block partial sums of ||r||_2^2 (MODE 1) or
 // r^T L^-1 r (MODE 2); f == nullptr gives r = A x.  One thread per row,
-// grid-stride: consecutive threads take consecutive rows of one field, i.e.
-// neighbouring lattice positions, which mostly share a stencil class, so the
-// class entries a wave reads are common to its lanes and the x of one entry
-// are contiguous.
+// grid-stride over chunks of 128 rows, a pair of waves per chunk: the first
+// wave takes the chunk's even rows, the second its odd rows.  Velocity nodes
+// alternate in type along a lattice row, so a wave's rows then share one
+// node type and, away from the boundary, one stencil class.  When every lane
+// of the wave has the same class, the class's entries and values are read
+// with scalar loads (one per entry for the whole wave) and only the x gathers
+// are vector loads; otherwise each lane walks its own class.  The entries go
+// in blocks of kResBlk, whose loads are issued together, and the products
+// are summed in entry order either way.
+constexpr int kResBlk = 8;
 template <typename T, int MODE, typename AT>
 __global__ __launch_bounds__(kSNT) void ks_resid(int n, AT A, const T* __restrict__ f, const T* __restrict__ x,
                                                  T* __restrict__ r, const double* __restrict__ Ldi,
                                                  double* __restrict__ part) {
+  static_assert(kSNT % 128 == 0, "whole chunks of 128 rows per block");
   double s2 = 0.0;
-  for (int i = blockIdx.x * kSNT + threadIdx.x; i < n; i += gridDim.x * kSNT) {
+  const int t = blockIdx.x * kSNT + threadIdx.x;
+  const int i0 = (t & ~127) + 2 * (t & 63) + ((t >> 6) & 1);
+  for (int i = i0; i < n; i += gridDim.x * kSNT) {
     int kb, ke, pos;
     A.row(i, kb, ke, pos);
     T s = 0;
-    for (int k = kb; k < ke; k++) s += A.val_of(k) * x[A.col_of(k, pos)];
+    const int kb0 = __builtin_amdgcn_readfirstlane(kb), ke0 = __builtin_amdgcn_readfirstlane(ke);
+    if (__builtin_amdgcn_ballot_w64(kb != kb0 || ke != ke0) == 0) {
+      int k = kb0;
+      for (; k + kResBlk <= ke0; k += kResBlk) {
+        T av[kResBlk], xv[kResBlk];
+#pragma unroll
+        for (int u = 0; u < kResBlk; u++) {
+          av[u] = A.val_u(k + u);
+          xv[u] = x[A.col_u(k + u, pos)];
+        }
+#pragma unroll
+        for (int u = 0; u < kResBlk; u++) s += av[u] * xv[u];
+      }
+      for (; k < ke0; k++) s += A.val_u(k) * x[A.col_u(k, pos)];
+    } else {
+      int k = kb;
+      for (; k + kResBlk <= ke; k += kResBlk) {
+        T av[kResBlk], xv[kResBlk];
+#pragma unroll
+        for (int u = 0; u < kResBlk; u++) {
+          av[u] = A.val_of(k + u);
+          xv[u] = x[A.col_of(k + u, pos)];
+        }
+#pragma unroll
+        for (int u = 0; u < kResBlk; u++) s += av[u] * xv[u];
+      }
+      for (; k < ke; k++) s += A.val_of(k) * x[A.col_of(k, pos)];
+    }
     const T ri = f ? f[i] - s : s;
     r[i] = ri;
     if (MODE == 1) s2 += (double)ri * (double)ri;
